@@ -1,0 +1,264 @@
+/*
+ * lc.h -- C ABI of the MI355X (gfx950) long-characteristics transport sweep.
+ *
+ * The library computes the high-order transport step of the multilevel
+ * quasidiffusion method with the method of long characteristics (Coale &
+ * Anistratov, "Multilevel method for thermal radiative transfer problems with
+ * method of long characteristics for the Boltzmann transport equation"):
+ *   - the characteristic grid over a 2D orthogonal material grid
+ *     (section "Method of Long Characteristics / Ray-Tracing Scheme":
+ *     characteristic coordinates, segments between cell-boundary crossings,
+ *     widths w_k, and the vertex-avoiding, width-halving construction given
+ *     after eq. (16));
+ *   - the backward-Euler sweep along every characteristic, eq. (10)-(13);
+ *   - the cell-average moments E, F and Eddington tensor, eq. (7), (14)-(15),
+ *     and boundary-face factors, eq. (16) and the "other linear-fractional
+ *     factors" of the method section.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * Material grid: nx x ny uniform cells on [0,lx] x [0,ly]; cell i = iy*nx+ix.
+ * Boundary faces (nb = 2(nx+ny)): [0,ny) x=0 (row iy), [ny,2ny) x=lx,
+ *   [2ny,2ny+nx) y=0 (column ix), [2ny+nx,nb) y=ly.
+ * Quadrature: n_az azimuths phi[a] (n_az even, phi[a+n_az/2] = phi[a] + pi),
+ *   n_pol polar cosines mu[p] (|mu| < 1), weights omega[m], direction
+ *   m = a*n_pol + p, Omega_m = (sqrt(1-mu^2) cos phi, sqrt(1-mu^2) sin phi, mu).
+ *   No azimuth may be parallel to a grid axis.
+ * Azimuth pairs: pair a < n_az/2 holds azimuth a (d = 0, forward) and
+ *   a + n_az/2 (d = 1, reverse); both share one family of characteristics.
+ * Characteristics of pair a are ordered by v = -x sin(phi_a) + y cos(phi_a)
+ *   ascending; global ray index k runs over pairs then rays; segments are
+ *   stored in forward order; global segment index j runs over pairs, rays,
+ *   segments.  Segment length l is the in-plane length; the path length in
+ *   direction m is l / sqrt(1 - mu_p^2).
+ * Groups: G >= 1; every [G][cells] array is group-major.
+ * Per-segment state (the previous step's segment-average intensities
+ *   I_bar^{n-1}): an opaque caller-owned device buffer of lc_state_bytes()
+ *   bytes; lc_state_export() gives it in the canonical order
+ *   [j][d][p][g] as float64.
+ * Exit intensities I_exit: float64 [n_rays][2][n_pol][G] (d = 0 leaves the
+ *   forward traversal's end, d = 1 the reverse traversal's end).
+ * Incoming boundary intensities I_in: float64 [nb][M][G]; only entries with
+ *   Omega_m . n_b < 0 are read.
+ *
+ * Memory and errors
+ * -----------------
+ * Unless stated otherwise, array pointers are DEVICE pointers owned by the
+ * caller; "stream" is a hipStream_t (NULL = default stream).  The library
+ * owns only its opaque handles (and their device geometry and workspaces),
+ * released by the matching *_free call.  lc_sweep, lc_moments and lc_step
+ * allocate nothing and never synchronise the stream, so a caller may capture
+ * them in a HIP graph.  Every entry point validates its arguments on the host
+ * before launching anything and returns a status; no exception or abort
+ * crosses the ABI.  lc_last_error() returns a thread-local description of the
+ * last failure.  A device fault surfaces as LC_ERR_HIP from a later call.
+ * Results are deterministic: no floating-point atomics are used.
+ */
+#ifndef LC_H
+#define LC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LC_OK = 0,
+    LC_ERR_ARG = 1,          /* invalid argument (null, size, range, layout) */
+    LC_ERR_ALLOC = 2,        /* device or host allocation failed */
+    LC_ERR_HIP = 3,          /* a HIP runtime call failed */
+    LC_ERR_STATE = 4,        /* invalid handle or inconsistent internal state */
+    LC_ERR_UNSUPPORTED = 5   /* valid request outside what this build supports */
+} lc_status;
+
+typedef enum { LC_RAYS_UNIFORM = 0, LC_RAYS_TUBES = 1 } lc_ray_mode;
+typedef enum { LC_F64 = 0, LC_F32 = 1 } lc_prec;
+
+typedef struct { int32_t nx, ny; double lx, ly; } lc_grid;
+
+/* Host arrays: phi[n_az], mu[n_pol], omega[n_az*n_pol]. */
+typedef struct {
+    int32_t n_az, n_pol;
+    const double* phi;
+    const double* mu;
+    const double* omega;
+} lc_quad;
+
+typedef struct {
+    int64_t n_rays;          /* characteristics over all azimuth pairs */
+    int64_t n_segments;      /* stored segments (each serves d = 0 and d = 1) */
+    int32_t n_pairs, n_az, n_pol, n_cells, n_faces;
+    int32_t max_seg_per_ray;
+    int32_t mode;            /* lc_ray_mode */
+    double h_moc;
+} lc_rays_info_t;
+
+typedef struct lc_rays_s* lc_rays_t;
+typedef struct lc_plan_s* lc_plan_t;
+typedef struct lc_batch_s* lc_batch_t;
+
+/* Library version (major*10000 + minor*100 + patch). */
+int32_t lc_version(void);
+
+/* Thread-local text describing the last non-OK status returned on this
+ * thread ("" if none).  Valid until the next failing call on the thread. */
+const char* lc_last_error(void);
+
+/*
+ * lc_build_rays -- characteristic grid for every azimuth pair.
+ * Paper: characteristic coordinates and segment lengths (section on the
+ * method of long characteristics), segment area eq. (14), the construction of
+ * the grid of characteristics after eq. (16), and the sets C(i,m) and F(f,m)
+ * of eq. (15)-(16).
+ *   mode LC_RAYS_UNIFORM: K = ceil(W/h_moc) characteristics of equal width
+ *     delta = W/K tiling the projected width W, centrelines at
+ *     v_min + (k+1/2) delta.
+ *   mode LC_RAYS_TUBES: the paper's construction -- the gaps between the
+ *     sorted projections of all grid vertices (no centreline crosses a
+ *     vertex), each halved until no width exceeds h_moc.
+ * Segments are cut at every grid-line crossing; crossings closer than
+ * 1e-12*min(hx,hy) are merged (no zero-length segments).  A characteristic
+ * entering or leaving through a domain corner belongs to the x = const face.
+ * The device geometry (segments, cell-major segment lists with area weights,
+ * boundary exit maps) lives in the returned handle; building synchronises
+ * `stream`.  Errors: LC_ERR_ARG for null pointers, nx/ny < 1, non-positive
+ * sizes or h_moc, odd n_az, unpaired azimuths, |mu| >= 1, axis-parallel
+ * azimuths, or a spacing so coarse that some cell is crossed by no
+ * characteristic of some direction; LC_ERR_ALLOC; LC_ERR_HIP.
+ */
+lc_status lc_build_rays(const lc_grid* grid, const lc_quad* quad, double h_moc,
+                        int32_t mode, void* stream, lc_rays_t* out);
+lc_status lc_rays_free(lc_rays_t rays);
+lc_status lc_rays_info(lc_rays_t rays, lc_rays_info_t* info);
+
+/*
+ * lc_rays_export -- copy the geometry to HOST arrays (any may be NULL):
+ * ray_off[n_pairs+1] (first global ray of each pair), seg_off[n_rays+1]
+ * (first global segment of each ray), cell[n_segments], len[n_segments],
+ * width[n_rays], face[n_rays][2] (entry and exit face of the forward
+ * traversal).  Synchronous.
+ */
+lc_status lc_rays_export(lc_rays_t rays, int32_t* ray_off, int32_t* seg_off,
+                         int32_t* cell, double* len, double* width, int32_t* face);
+
+/*
+ * lc_plan_create -- per-(geometry, G, precision) workspace: the cell
+ * coefficient table (modified opacity kappa_t = kappa + 1/(c dt), emission
+ * kappa B / kappa_t, and 1/(c dt kappa_t) of eq. (11)) and, for LC_F32, the
+ * per-group power-of-two scale of the stored intensities.  prec LC_F64 sweeps
+ * and stores in float64; LC_F32 sweeps and stores in float32 with
+ * compensated float32 moment sums and float64 division and boundary factors.
+ * The plan keeps a reference to `rays`, which must outlive it.
+ */
+lc_status lc_plan_create(lc_rays_t rays, int32_t G, int32_t prec, lc_plan_t* out);
+lc_status lc_plan_free(lc_plan_t plan);
+
+/* Bytes of one per-segment state buffer of `plan` (a 256-byte header, then
+ * n_segments*2*n_pol*G values of the plan's precision). */
+size_t lc_state_bytes(lc_plan_t plan);
+
+/*
+ * lc_state_fill -- initial condition of eq. (2) for the state: every segment
+ * and direction takes the value of the cell field it lies in,
+ * state[j][d][p][g] = field[g][cell(j)].  field: float64 [G][cells].
+ */
+lc_status lc_state_fill(lc_plan_t plan, const double* field, void* state, void* stream);
+
+/* lc_state_export -- state in canonical order, float64 [n_segments][2][n_pol][G]. */
+lc_status lc_state_export(lc_plan_t plan, const void* state, double* out, void* stream);
+
+/*
+ * lc_sweep -- one backward-Euler transport sweep, eq. (10)-(13), over every
+ * characteristic, direction and group:
+ *   kappa_t = kappa + 1/(c dt),  Q = kappa B + I_bar^{n-1}/(c dt),
+ *   tau = kappa_t l / sin(zeta),  I_out = I e^{-tau} + (Q/kappa_t)(1 - e^{-tau}),
+ *   alpha = 1/tau - e^{-tau}/(1 - e^{-tau}),  I_bar = alpha I + (1 - alpha) I_out.
+ * kappa, planck: float64 [G][cells] (kappa > 0 or 0, planck >= 0, finite);
+ * c_dt > 0; state_prev -> state_new (distinct buffers of lc_state_bytes);
+ * I_in: float64 [nb][M][G]; I_exit: float64 [n_rays][2][n_pol][G] or NULL.
+ * The intensity entering a characteristic is I_in of the face it enters
+ * through.  Errors: LC_ERR_ARG (null or aliased buffers, c_dt <= 0),
+ * LC_ERR_HIP.
+ */
+lc_status lc_sweep(lc_plan_t plan, const double* kappa, const double* planck, double c_dt,
+                   const void* state_prev, void* state_new, const double* I_in,
+                   double* I_exit, void* stream);
+
+/*
+ * lc_moments -- cell and boundary moments of a swept state, eq. (7),
+ * (14)-(16).  For each cell i and direction m the area-weighted mean
+ *   I_{i,m} = sum_{C(i,m)} A I_bar / sum_{C(i,m)} A,  A = l w,
+ * then Phi = sum_m omega_m I_{i,m}, E = Phi/c, F = sum_m omega_m Omega_m I_{i,m},
+ * f = sum_m omega_m Omega_m Omega_m I_{i,m} / Phi (f := 1/3 on the diagonal
+ * where Phi = 0).  Outputs (float64, any may be NULL):
+ *   E[G][cells], F[G][2][cells] (x, y), f[G][4][cells] (xx, xy, yy, zz),
+ *   bnd[G][nb][8] = Phi+, J+, Phi-, J-, C = J+/Phi+, f_xx, f_xy, f_yy of the
+ *   boundary face (outgoing: width-weighted mean exit intensity of the
+ *   characteristics leaving through the face, or of the one leaving nearest
+ *   its centre if none does; incoming: I_in).  bnd needs I_exit and I_in.
+ * c > 0 is the speed of light in the caller's units.
+ */
+lc_status lc_moments(lc_plan_t plan, const void* state, const double* I_exit,
+                     const double* I_in, double c, double* E, double* F, double* f,
+                     double* bnd, void* stream);
+
+/*
+ * lc_step -- n_steps backward-Euler time steps (sweep, then moments) with the
+ * state ping-ponging between state_a and state_b: step t reads the state
+ * written by step t-1 (step 0 reads state_a); after an odd number of steps
+ * the newest state is in state_b, after an even number in state_a.
+ * kappa/planck of step t start at kappa + t*material_stride (elements; 0
+ * means the same data every step).  The moments of the last step are written
+ * to E, F, f, bnd (as lc_moments; any may be NULL).  The step sequence is
+ * captured once in a HIP graph per argument set and replayed.
+ */
+lc_status lc_step(lc_plan_t plan, int32_t n_steps, const double* kappa, const double* planck,
+                  int64_t material_stride, double c_dt, double c, void* state_a, void* state_b,
+                  const double* I_in, double* I_exit, double* E, double* F, double* f,
+                  double* bnd, void* stream);
+
+/*
+ * Kernel timers (tracing).  lc_plan_profile(plan, 1) makes every following
+ * eager lc_sweep / lc_moments record HIP events around its main kernel on the
+ * caller's stream (not inside lc_step graphs); lc_plan_profile_read
+ * synchronises those events and returns, in out[4]: total milliseconds and
+ * launch count of the sweep kernel, then of the cell-moment kernel; it also
+ * clears the record.  lc_plan_profile(plan, 0) stops recording.
+ */
+lc_status lc_plan_profile(lc_plan_t plan, int32_t enable);
+lc_status lc_plan_profile_read(lc_plan_t plan, double* out);
+
+/*
+ * Batched form: many independent problems (each its own rays and plan) swept
+ * in one persistent launch per phase.  lc_batch_create copies the per-problem
+ * pointer sets (device arrays as for lc_step) into the handle and builds a
+ * work list ordered by decreasing cost; lc_batch_step then runs n_steps time
+ * steps of every problem (state ping-pong as lc_step) and writes each
+ * problem's last-step moments.
+ */
+typedef struct {
+    lc_plan_t plan;
+    const double* kappa;
+    const double* planck;
+    int64_t material_stride;
+    double c_dt;
+    void* state_a;
+    void* state_b;
+    const double* I_in;
+    double* I_exit;          /* required */
+    double* E;
+    double* F;
+    double* f;
+    double* bnd;
+} lc_problem_t;
+
+lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_batch_t* out);
+lc_status lc_batch_step(lc_batch_t batch, int32_t n_steps, double c, void* stream);
+lc_status lc_batch_free(lc_batch_t batch);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LC_H */

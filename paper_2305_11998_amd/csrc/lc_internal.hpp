@@ -1,0 +1,152 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/lc.h"
+
+namespace lc {
+
+void set_error(const char* fmt, ...);
+
+#define LC_HIP(expr)                                                          \
+    do {                                                                      \
+        hipError_t lc_e_ = (expr);                                            \
+        if (lc_e_ != hipSuccess) {                                            \
+            ::lc::set_error("%s failed: %s", #expr, hipGetErrorString(lc_e_)); \
+            return LC_ERR_HIP;                                                \
+        }                                                                     \
+    } while (0)
+
+#define LC_CHECK(cond, code, ...)          \
+    do {                                   \
+        if (!(cond)) {                     \
+            ::lc::set_error(__VA_ARGS__);  \
+            return (code);                 \
+        }                                  \
+    } while (0)
+
+#define LC_ARG(cond, ...) LC_CHECK(cond, LC_ERR_ARG, __VA_ARGS__)
+
+constexpr uint32_t kRaysMagic = 0x4c435259u;   // "LCRY"
+constexpr uint32_t kPlanMagic = 0x4c43504cu;   // "LCPL"
+constexpr uint32_t kBatchMagic = 0x4c434254u;  // "LCBT"
+constexpr int kMaxPol = 8;
+constexpr int kBlock = 256;                    // threads per block of the streaming kernels
+constexpr int kDirW = 10;                      // per-direction weight record, see dirw_index
+
+// Per (pair a, traversal d, polar p) record, float64:
+//   [0] omega, [1] omega Ox, [2] omega Oy, [3] omega Ox Ox, [4] omega Ox Oy,
+//   [5] omega Oy Oy, [6] omega Oz Oz, [7] Ox, [8] Oy, [9] 1/sin(zeta)
+inline size_t dirw_index(int a, int d, int p, int n_pol) {
+    return ((size_t)(a * 2 + d) * n_pol + p) * kDirW;
+}
+
+struct Rays {
+    uint32_t magic = 0;
+    int nx = 0, ny = 0;
+    double lx = 0, ly = 0, hx = 0, hy = 0;
+    int n_az = 0, n_pol = 0, n_pairs = 0, nb = 0, cells = 0, mode = 0;
+    double h_moc = 0;
+    int64_t n_rays = 0, n_seg = 0;
+    int max_seg = 0;
+    bool sym = false;                 // mu[p] == -mu[P-1-p] for every p
+    std::vector<double> phi, mu, omega, inv_sinz, cphi, sphi;
+    std::vector<int> ray_off;         // host copy [n_pairs + 1]
+    std::vector<double> dirw;         // host copy of d_dirw
+    // device geometry
+    int* d_ray_off = nullptr;         // [n_pairs + 1]
+    int* d_seg_off = nullptr;         // [n_rays + 1]
+    int* d_face = nullptr;            // [n_rays][2] entry, exit face of the forward traversal
+    double* d_v = nullptr;            // [n_rays] centreline offsets
+    double* d_width = nullptr;        // [n_rays]
+    double* d_pts = nullptr;          // [n_rays][4] entry x, y, exit x, y
+    int* d_cell = nullptr;            // [n_seg]
+    double* d_len = nullptr;          // [n_seg]
+    float* d_len32 = nullptr;         // [n_seg]
+    int* d_csr_off = nullptr;         // [cells * n_pairs + 1], index cell * n_pairs + a
+    int* d_csr_seg = nullptr;         // [n_seg] global segment j
+    double* d_csr_w = nullptr;        // [n_seg] A_j / sum of A over C(i, m)
+    float* d_csr_w32 = nullptr;
+    int* d_bmap = nullptr;            // [nb][n_pairs][2][2] first, end global ray leaving through b; -1 = incoming
+    double* d_dirw = nullptr;         // [n_pairs][2][n_pol][kDirW]
+    std::vector<void*> owned;         // every device allocation above
+};
+
+struct Plan;
+
+struct GraphEntry {
+    std::vector<uintptr_t> key;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct Plan {
+    uint32_t magic = 0;
+    Rays* rays = nullptr;
+    int G = 0;
+    int prec = 0;
+    size_t hdr_bytes = 0;             // state header (per-group scale exponents)
+    size_t value_bytes = 0;
+    void* d_coef = nullptr;           // [cells][G] {kappa_t, emission/kappa_t, 1/(c dt kappa_t), 0}
+    int64_t sweep_blocks = 0;         // blocks of one sweep launch
+    std::vector<int> blk_off;         // [2 n_pairs + 1] first logical block of (a, d)
+    int* d_blk_off = nullptr;
+    std::vector<GraphEntry> graphs;   // captured lc_step sequences
+    hipStream_t capture = nullptr;    // stream used only to record graphs
+    bool profile = false;             // record events around the main kernels
+    bool capturing = false;           // inside lc_step capture: never record events
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_mom;
+};
+
+// Event pair around one kernel launch when the plan records timings.
+lc_status prof_begin(Plan* pl, std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, hipStream_t st);
+lc_status prof_end(Plan* pl, std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, hipStream_t st);
+
+inline Rays* as_rays(lc_rays_t r) {
+    Rays* p = reinterpret_cast<Rays*>(r);
+    return (p && p->magic == kRaysMagic) ? p : nullptr;
+}
+inline Plan* as_plan(lc_plan_t r) {
+    Plan* p = reinterpret_cast<Plan*>(r);
+    return (p && p->magic == kPlanMagic) ? p : nullptr;
+}
+
+// device allocation owned by a vector of pointers (freed together)
+template <typename T>
+lc_status dalloc(std::vector<void*>& owned, T** out, size_t n) {
+    void* p = nullptr;
+    size_t bytes = n ? n * sizeof(T) : sizeof(T);
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+        (void)hipGetLastError();
+        return LC_ERR_ALLOC;
+    }
+    owned.push_back(p);
+    *out = static_cast<T*>(p);
+    return LC_OK;
+}
+
+// Internal launchers (stream-ordered, no allocation, no synchronisation).
+lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, double c_dt,
+                       const void* state_prev, void* state_new, const double* I_in,
+                       double* I_exit, hipStream_t st);
+lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, const double* I_in,
+                         double c, double* E, double* F, double* f, double* bnd, hipStream_t st);
+lc_status launch_state_fill(Plan* pl, const double* field, void* state, hipStream_t st);
+lc_status launch_state_export(Plan* pl, const void* state, double* out, hipStream_t st);
+lc_status build_geometry(Rays* r, hipStream_t st);
+lc_status plan_init_sweep(Plan* pl);
+
+// Device pointers to the values of a state buffer (after its header).
+inline const void* state_values(const Plan* pl, const void* s) {
+    return static_cast<const char*>(s) + pl->hdr_bytes;
+}
+inline void* state_values(const Plan* pl, void* s) { return static_cast<char*>(s) + pl->hdr_bytes; }
+
+}  // namespace lc

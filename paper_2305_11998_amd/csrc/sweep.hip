@@ -1,0 +1,327 @@
+// The transport sweep, eq. (10)-(13), on gfx950.
+//
+// Work decomposition: for each azimuth pair a and traversal d, the lanes of a
+// launch enumerate (characteristic k, group g) with g fastest, so a 64-wide
+// wavefront covers consecutive groups of one or a few neighbouring
+// characteristics.  Each lane walks its characteristic segment by segment,
+// carrying the intensity of every polar angle p in registers; per segment it
+// reads one cell-coefficient record (coalesced over g), the stored
+// I_bar^{n-1} of every p (coalesced over g), and writes I_bar^n.  Polar
+// angles with equal sin(zeta) (the +mu/-mu pairs of a symmetric set) share
+// the exponential and the weight alpha.  Blocks are remapped so that each
+// XCD's L2 serves a contiguous band of characteristics.
+#include <cmath>
+
+#include "lc_internal.hpp"
+
+namespace lc {
+namespace {
+
+template <typename T> struct Coef;
+template <> struct Coef<double> { double kt, a, b, pad; };
+template <> struct Coef<float> { float kt, a, b, pad; };
+
+struct SweepArgs {
+    const int* blk_off;      // [n_pd + 1] first logical block of each (a, d)
+    int n_pd;
+    int64_t n_blocks;
+    const int* ray_off;
+    const int* seg_off;
+    const int* face;
+    const int* cell;
+    const void* len;         // double or float [n_seg]
+    const void* coef;        // Coef<T> [cells][G]
+    const void* prev;        // state values
+    void* next;
+    const double* I_in;      // [nb][M][G]
+    double* I_exit;          // [n_rays][2][P][G] or null
+    const int* e_new;        // per-group exponent of the new state (float32 only)
+    int G, n_az, M;
+    double inv_sinz[kMaxPol];
+};
+
+// Hardware hands workgroups to the 8 XCDs round-robin; give each XCD a
+// contiguous range of logical blocks (a band of neighbouring characteristics)
+// so the cell coefficients they share stay in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t hw, int64_t n) {
+    const int64_t q = n >> 3, r = n & 7;
+    const int64_t x = hw & 7, i = hw >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
+__device__ __forceinline__ int find_block(const int* __restrict__ off, int n, int64_t lb) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= lb) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <typename T> struct Att { T E, D, al, be; };
+
+// e^{-tau}, 1 - e^{-tau} and alpha of eq. (13) in float32: series below the
+// thresholds where the closed forms cancel, convex forms everywhere.
+__device__ __forceinline__ Att<float> attenuate(float tau) {
+    const float E = __expf(-tau);
+    const float Ds = tau * (1.f - tau * (0.5f - tau * (1.f / 6.f - tau * (1.f / 24.f - tau * (1.f / 120.f - tau * (1.f / 720.f - tau * (1.f / 5040.f)))))));
+    const float D = tau < 0.25f ? Ds : 1.f - E;
+    const float t2 = tau * tau;
+    const float as = 0.5f - tau * (1.f / 12.f - t2 * (1.f / 720.f - t2 * (1.f / 30240.f - t2 * (1.f / 1209600.f - t2 * (1.f / 47900160.f)))));
+    const float ac = __fdividef(D - tau * E, tau * D);
+    const float al = tau < 1.f ? as : ac;
+    return {E, D, al, 1.f - al};
+}
+
+// Same in float64 (series below tau = 0.1).
+__device__ __forceinline__ Att<double> attenuate(double tau) {
+    const double E = exp(-tau);
+    const double Ds = tau * (1.0 - tau * (1.0 / 2 - tau * (1.0 / 6 - tau * (1.0 / 24 - tau * (1.0 / 120 - tau * (1.0 / 720 - tau * (1.0 / 5040 - tau * (1.0 / 40320 - tau * (1.0 / 362880 - tau * (1.0 / 3628800))))))))));
+    const bool small = tau < 0.1;
+    const double D = small ? Ds : 1.0 - E;
+    const double t2 = tau * tau;
+    const double as = 0.5 - tau * (1.0 / 12 - t2 * (1.0 / 720 - t2 * (1.0 / 30240 - t2 * (1.0 / 1209600))));
+    double al;
+    if (small) al = as;
+    else al = (D - tau * E) / (tau * D);
+    return {E, D, al, 1.0 - al};
+}
+
+template <typename T>
+__device__ __forceinline__ T ldg_stream(const T* p) { return __builtin_nontemporal_load(p); }
+template <typename T>
+__device__ __forceinline__ void stg_stream(T* p, T v) { __builtin_nontemporal_store(v, p); }
+
+constexpr int kUnroll = 4;   // segments whose loads are issued together
+
+template <typename T, int P, bool SYM>
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
+    const int64_t lb = xcd_logical_block(blockIdx.x, A.n_blocks);
+    const int pd = find_block(A.blk_off, A.n_pd, lb);
+    const int a = pd >> 1, d = pd & 1;
+    const int G = A.G;
+    const int64_t f = (lb - A.blk_off[pd]) * kBlock + threadIdx.x;
+    const int r0 = A.ray_off[a];
+    const int Ka = A.ray_off[a + 1] - r0;
+    const int kl = (int)(f / G);
+    const int g = (int)(f - (int64_t)kl * G);
+    if (kl >= Ka) return;
+    const int k = r0 + kl;
+    const int s0 = A.seg_off[k], s1 = A.seg_off[k + 1];
+    const int n = s1 - s0;
+    const int face_in = A.face[2 * k + d];
+    const int az = a + d * (A.n_az >> 1);
+    const T* __restrict__ len = static_cast<const T*>(A.len);
+    const Coef<T>* __restrict__ coef = static_cast<const Coef<T>*>(A.coef);
+    const T* __restrict__ prev = static_cast<const T*>(A.prev);
+    T* __restrict__ next = static_cast<T*>(A.next);
+
+    double sc_in = 1.0, sc_out = 1.0;
+    if (sizeof(T) == 4) {
+        const int e = A.e_new[g];
+        sc_in = ldexp(1.0, -e);
+        sc_out = ldexp(1.0, e);
+    }
+    T isz[P];
+    T I[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        isz[p] = (T)A.inv_sinz[p];
+        I[p] = (T)(A.I_in[((size_t)face_in * A.M + (size_t)az * P + p) * G + g] * sc_in);
+    }
+    const int step = d == 0 ? 1 : -1;
+    const int jfirst = d == 0 ? s0 : s1 - 1;
+    const size_t seg_stride = (size_t)2 * P * G;
+    const size_t lane_off = (size_t)d * P * G + g;
+
+    for (int t0 = 0; t0 < n; t0 += kUnroll) {
+        int ci[kUnroll];
+        T l[kUnroll];
+        Coef<T> cf[kUnroll];
+        T x[kUnroll][P];
+        size_t base[kUnroll];
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            const int t = min(t0 + u, n - 1);
+            const int j = jfirst + step * t;
+            ci[u] = A.cell[j];
+            l[u] = len[j];
+            base[u] = (size_t)j * seg_stride + lane_off;
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            cf[u] = coef[(size_t)ci[u] * G + g];
+#pragma unroll
+            for (int p = 0; p < P; ++p) x[u][p] = ldg_stream(prev + base[u] + (size_t)p * G);
+        }
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+            if (t0 + u < n) {
+                const T ktl = cf[u].kt * l[u];
+                Att<T> at[P];
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const int q = (SYM && p >= (P + 1) / 2) ? (P - 1 - p) : p;
+                    if (q == p) at[p] = attenuate(ktl * isz[p]);
+                    else at[p] = at[q];
+                }
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const T S = cf[u].a + cf[u].b * x[u][p];          // Q / kappa_t
+                    const T Io = at[p].E * I[p] + at[p].D * S;         // eq. (12)
+                    const T Ib = at[p].al * I[p] + at[p].be * Io;      // segment average
+                    stg_stream(next + base[u] + (size_t)p * G, Ib);
+                    I[p] = Io;
+                }
+            }
+        }
+    }
+    if (A.I_exit) {
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            A.I_exit[((size_t)(2 * k + d) * P + p) * G + g] = (double)I[p] * sc_out;
+    }
+}
+
+// Coefficients of eq. (11) per (cell, g): kappa_t, kappa B / kappa_t and
+// 1/(c dt kappa_t), so that Q / kappa_t = a + b I_bar^{n-1}.  float32 tables
+// carry the per-group power-of-two scales of the old and new state.
+template <typename T>
+__global__ void k_coef(const double* __restrict__ kappa, const double* __restrict__ planck,
+                       double c_dt, int cells, int G, const int* __restrict__ e_prev,
+                       const int* __restrict__ e_new, Coef<T>* coef) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)cells * G) return;
+    const int g = (int)(i / cells);
+    const int c = (int)(i - (int64_t)g * cells);
+    const double kap = kappa[i];
+    const double inv = 1.0 / c_dt;
+    const double kt = kap + inv;
+    double a = kap * planck[i] / kt;
+    double b = inv / kt;
+    if (sizeof(T) == 4) {
+        a = ldexp(a, -e_new[g]);
+        b = ldexp(b, e_prev[g] - e_new[g]);
+    }
+    Coef<T> r;
+    r.kt = (T)kt;
+    r.a = (T)a;
+    r.b = (T)b;
+    r.pad = (T)0;
+    coef[(size_t)c * G + g] = r;
+}
+
+// Per-group scale of the new float32 state: the stored values never exceed
+// max(I_in, B, previous state) (each step's segment average is a convex
+// combination of those), so the exponent is raised to cover the new sources
+// and never lowered.
+__global__ void k_scale(const double* __restrict__ planck, const double* __restrict__ I_in, int cells,
+                        int G, int64_t n_in, const int* __restrict__ e_prev, int* e_new) {
+    __shared__ double sh[kBlock];
+    const int g = blockIdx.x;
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < cells; i += kBlock) m = fmax(m, fabs(planck[(int64_t)g * cells + i]));
+    for (int64_t i = threadIdx.x; i < n_in; i += kBlock) m = fmax(m, fabs(I_in[i * G + g]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int e = e_prev[g];
+        if (sh[0] > 0.0 && isfinite(sh[0])) e = max(e, ilogb(sh[0]) + 1);
+        e_new[g] = e;
+    }
+}
+
+template <typename T, int P>
+lc_status launch_sweep_t(Plan* pl, const SweepArgs& A, bool sym, hipStream_t st) {
+    dim3 grid((unsigned)pl->sweep_blocks), block(kBlock);
+    lc_status rc = prof_begin(pl, pl->ev_sweep, st);
+    if (rc) return rc;
+    if (sym) hipLaunchKernelGGL((k_sweep<T, P, true>), grid, block, 0, st, A);
+    else hipLaunchKernelGGL((k_sweep<T, P, false>), grid, block, 0, st, A);
+    LC_HIP(hipGetLastError());
+    return prof_end(pl, pl->ev_sweep, st);
+}
+
+template <typename T>
+lc_status launch_sweep_p(Plan* pl, const SweepArgs& A, bool sym, hipStream_t st) {
+    switch (pl->rays->n_pol) {
+        case 1: return launch_sweep_t<T, 1>(pl, A, sym, st);
+        case 2: return launch_sweep_t<T, 2>(pl, A, sym, st);
+        case 3: return launch_sweep_t<T, 3>(pl, A, sym, st);
+        case 4: return launch_sweep_t<T, 4>(pl, A, sym, st);
+        case 5: return launch_sweep_t<T, 5>(pl, A, sym, st);
+        case 6: return launch_sweep_t<T, 6>(pl, A, sym, st);
+        case 7: return launch_sweep_t<T, 7>(pl, A, sym, st);
+        case 8: return launch_sweep_t<T, 8>(pl, A, sym, st);
+    }
+    set_error("n_pol = %d not supported (1..8)", pl->rays->n_pol);
+    return LC_ERR_UNSUPPORTED;
+}
+
+inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+lc_status plan_init_sweep(Plan* pl) {
+    Rays* r = pl->rays;
+    pl->blk_off.assign(2 * r->n_pairs + 1, 0);
+    for (int a = 0; a < r->n_pairs; ++a) {
+        const int64_t lanes = (int64_t)(r->ray_off[a + 1] - r->ray_off[a]) * pl->G;
+        const int64_t blocks = (lanes + kBlock - 1) / kBlock;
+        for (int d = 0; d < 2; ++d) {
+            const int pd = 2 * a + d;
+            LC_CHECK(pl->blk_off[pd] + blocks < INT32_MAX, LC_ERR_UNSUPPORTED, "sweep grid too large");
+            pl->blk_off[pd + 1] = pl->blk_off[pd] + (int)blocks;
+        }
+    }
+    pl->sweep_blocks = pl->blk_off.back();
+    return LC_OK;
+}
+
+lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, double c_dt,
+                       const void* state_prev, void* state_new, const double* I_in, double* I_exit,
+                       hipStream_t st) {
+    Rays* r = pl->rays;
+    const int G = pl->G;
+    const bool f32 = pl->prec == LC_F32;
+    const int* e_prev = static_cast<const int*>(state_prev);   // header: per-group exponents
+    int* e_new = static_cast<int*>(state_new);
+    if (f32) {
+        hipLaunchKernelGGL(k_scale, dim3(G), dim3(kBlock), 0, st, planck, I_in, r->cells, G,
+                           (int64_t)r->nb * r->n_az * r->n_pol, e_prev, e_new);
+        hipLaunchKernelGGL(k_coef<float>, dim3(nblk((int64_t)r->cells * G)), dim3(kBlock), 0, st,
+                           kappa, planck, c_dt, r->cells, G, e_prev, e_new,
+                           static_cast<Coef<float>*>(pl->d_coef));
+    } else {
+        hipLaunchKernelGGL(k_coef<double>, dim3(nblk((int64_t)r->cells * G)), dim3(kBlock), 0, st,
+                           kappa, planck, c_dt, r->cells, G, nullptr, nullptr,
+                           static_cast<Coef<double>*>(pl->d_coef));
+    }
+    LC_HIP(hipGetLastError());
+    SweepArgs A{};
+    A.blk_off = pl->d_blk_off;
+    A.n_pd = 2 * r->n_pairs;
+    A.n_blocks = pl->sweep_blocks;
+    A.ray_off = r->d_ray_off;
+    A.seg_off = r->d_seg_off;
+    A.face = r->d_face;
+    A.cell = r->d_cell;
+    A.len = f32 ? static_cast<const void*>(r->d_len32) : static_cast<const void*>(r->d_len);
+    A.coef = pl->d_coef;
+    A.prev = state_values(pl, state_prev);
+    A.next = state_values(pl, state_new);
+    A.I_in = I_in;
+    A.I_exit = I_exit;
+    A.e_new = e_new;
+    A.G = G;
+    A.n_az = r->n_az;
+    A.M = r->n_az * r->n_pol;
+    for (int p = 0; p < r->n_pol; ++p) A.inv_sinz[p] = r->inv_sinz[p];
+    return f32 ? launch_sweep_p<float>(pl, A, r->sym, st) : launch_sweep_p<double>(pl, A, r->sym, st);
+}
+
+}  // namespace lc

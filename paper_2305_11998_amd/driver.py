@@ -1,0 +1,108 @@
+"""Run whole transport problems through the C ABI with PyTorch device memory.
+
+``Solver`` uploads a problem's inputs once (opacities, Planck sources and
+boundary intensities for every step), builds the characteristic grid and a
+plan, and advances the per-segment state with ``lc_step`` (graph-captured) or
+with explicit ``lc_sweep`` / ``lc_moments`` calls.  All arithmetic of the
+method happens in the HIP library.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import lc
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+class Solver:
+    def __init__(self, prob, prec=lc.LC_F64, mode=lc.LC_RAYS_UNIFORM, c=None, rays=None):
+        from workloads import C_LIGHT
+        self.prob = prob
+        self.c = C_LIGHT if c is None else float(c)
+        self.prec = prec
+        self.rays = rays if rays is not None else lc.lc_build_rays(
+            prob.nx, prob.ny, prob.lx, prob.ly, prob.phi, prob.mu, prob.omega, prob.h_moc, mode)
+        self.plan = lc.Plan(self.rays, prob.G, prec)
+        G, cells = prob.G, prob.cells
+        self.kappa = _dev(np.stack(prob.kappa))          # [steps][G][cells]
+        self.planck = _dev(np.stack(prob.planck))
+        self.stride = G * cells if prob.steps > 1 else 0
+        self.I_in = _dev(prob.I_in)
+        self.state0 = _dev(prob.state0)
+        self.state = [self.plan.new_state(), self.plan.new_state()]
+        r = self.rays
+        self.I_exit = torch.zeros(r.n_rays * 2 * r.n_pol * G, dtype=torch.float64, device="cuda")
+        self.E = torch.zeros(G * cells, dtype=torch.float64, device="cuda")
+        self.F = torch.zeros(2 * G * cells, dtype=torch.float64, device="cuda")
+        self.f = torch.zeros(4 * G * cells, dtype=torch.float64, device="cuda")
+        self.bnd = torch.zeros(G * r.nb * 8, dtype=torch.float64, device="cuda")
+        self.cur = 0
+        self.t = 0
+
+    def reset(self):
+        lc.lc_state_fill(self.plan, self.state0, self.state[0])
+        self.cur = 0
+        self.t = 0
+
+    def step(self, n=1, graph=True):
+        """Advance n steps from the current state (material data of steps
+        t .. t+n-1) and leave the last step's moments in E, F, f, bnd."""
+        p = self.prob
+        t0 = self.t
+        if t0 + n > p.steps:
+            raise ValueError("not enough material steps")
+        off = t0 * self.stride
+        kap = self.kappa.view(-1)[off:]
+        pla = self.planck.view(-1)[off:]
+        if graph:
+            lc.lc_step(self.plan, n, kap, pla, p.c_dt, self.c, self.state[self.cur],
+                       self.state[1 - self.cur], self.I_in, self.I_exit, self.E, self.F, self.f,
+                       self.bnd, material_stride=self.stride)
+        else:
+            for t in range(n):
+                o = t * self.stride
+                lc.lc_sweep(self.plan, kap[o:], pla[o:], p.c_dt, self.state[(self.cur + t) % 2],
+                            self.state[(self.cur + t + 1) % 2], self.I_in, self.I_exit)
+            lc.lc_moments(self.plan, self.state[(self.cur + n) % 2], self.c, self.E, self.F, self.f,
+                          self.bnd, self.I_exit, self.I_in)
+        self.cur = (self.cur + n) % 2
+        self.t += n
+
+    def bench_step(self):
+        """One step with the first step's material data (for timing): eager
+        sweep then moments, state ping-pong."""
+        p = self.prob
+        nxt = 1 - self.cur
+        lc.lc_sweep(self.plan, self.kappa, self.planck, p.c_dt, self.state[self.cur], self.state[nxt],
+                    self.I_in, self.I_exit)
+        lc.lc_moments(self.plan, self.state[nxt], self.c, self.E, self.F, self.f, self.bnd,
+                      self.I_exit, self.I_in)
+        self.cur = nxt
+
+    def moments(self):
+        p = self.prob
+        G, cells = p.G, p.cells
+        return dict(E=self.E.cpu().numpy().reshape(G, cells),
+                    F=self.F.cpu().numpy().reshape(G, 2, cells),
+                    f=self.f.cpu().numpy().reshape(G, 4, cells),
+                    bnd=self.bnd.cpu().numpy().reshape(G, self.rays.nb, 8))
+
+    def state_canonical(self):
+        out = torch.empty(self.plan.n_state, dtype=torch.float64, device="cuda")
+        lc.lc_state_export(self.plan, self.state[self.cur], out)
+        r = self.rays
+        return out.cpu().numpy().reshape(r.n_segments, 2, r.n_pol, self.prob.G)
+
+    def exits(self):
+        r = self.rays
+        return self.I_exit.cpu().numpy().reshape(r.n_rays, 2, r.n_pol, self.prob.G)
+
+    def updates_per_step(self):
+        """Segment updates of one sweep: stored segments x 2 traversals x
+        polar angles x groups."""
+        r = self.rays
+        return r.n_segments * 2 * r.n_pol * self.prob.G

@@ -1,0 +1,280 @@
+"""Python binding of the ``liblc`` C ABI (argument marshalling only).
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of the method: it checks tensor devices, dtypes and sizes (so the
+kernels never see a buffer smaller than they assume), passes raw device
+pointers and the current HIP stream, and turns non-OK status codes into
+exceptions.  Device memory comes from PyTorch.  If the HIP library has not
+been built this module raises at import: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "liblc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; g.build()'`")
+_lib = C.CDLL(LIB_PATH)
+
+LC_OK, LC_ERR_ARG, LC_ERR_ALLOC, LC_ERR_HIP, LC_ERR_STATE, LC_ERR_UNSUPPORTED = range(6)
+LC_RAYS_UNIFORM, LC_RAYS_TUBES = 0, 1
+LC_F64, LC_F32 = 0, 1
+_STATUS = {1: "LC_ERR_ARG", 2: "LC_ERR_ALLOC", 3: "LC_ERR_HIP", 4: "LC_ERR_STATE", 5: "LC_ERR_UNSUPPORTED"}
+
+
+class LcError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class lc_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("lx", C.c_double), ("ly", C.c_double)]
+
+
+class lc_quad(C.Structure):
+    _fields_ = [("n_az", C.c_int32), ("n_pol", C.c_int32), ("phi", C.POINTER(C.c_double)),
+                ("mu", C.POINTER(C.c_double)), ("omega", C.POINTER(C.c_double))]
+
+
+class lc_rays_info_t(C.Structure):
+    _fields_ = [("n_rays", C.c_int64), ("n_segments", C.c_int64), ("n_pairs", C.c_int32),
+                ("n_az", C.c_int32), ("n_pol", C.c_int32), ("n_cells", C.c_int32),
+                ("n_faces", C.c_int32), ("max_seg_per_ray", C.c_int32), ("mode", C.c_int32),
+                ("h_moc", C.c_double)]
+
+
+class lc_problem_t(C.Structure):
+    _fields_ = [("plan", C.c_void_p), ("kappa", C.c_void_p), ("planck", C.c_void_p),
+                ("material_stride", C.c_int64), ("c_dt", C.c_double), ("state_a", C.c_void_p),
+                ("state_b", C.c_void_p), ("I_in", C.c_void_p), ("I_exit", C.c_void_p),
+                ("E", C.c_void_p), ("F", C.c_void_p), ("f", C.c_void_p), ("bnd", C.c_void_p)]
+
+
+_vp, _i32, _i64, _d = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+_SIGS = {
+    "lc_version": ([], C.c_int32),
+    "lc_last_error": ([], C.c_char_p),
+    "lc_build_rays": ([C.POINTER(lc_grid), C.POINTER(lc_quad), _d, _i32, _vp, C.POINTER(_vp)], C.c_int),
+    "lc_rays_free": ([_vp], C.c_int),
+    "lc_rays_info": ([_vp, C.POINTER(lc_rays_info_t)], C.c_int),
+    "lc_rays_export": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "lc_plan_create": ([_vp, _i32, _i32, C.POINTER(_vp)], C.c_int),
+    "lc_plan_free": ([_vp], C.c_int),
+    "lc_state_bytes": ([_vp], C.c_size_t),
+    "lc_state_fill": ([_vp, _vp, _vp, _vp], C.c_int),
+    "lc_state_export": ([_vp, _vp, _vp, _vp], C.c_int),
+    "lc_sweep": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "lc_moments": ([_vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "lc_step": ([_vp, _i32, _vp, _vp, _i64, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "lc_plan_profile": ([_vp, _i32], C.c_int),
+    "lc_plan_profile_read": ([_vp, _vp], C.c_int),
+    "lc_batch_create": ([_i32, C.POINTER(lc_problem_t), C.POINTER(_vp)], C.c_int),
+    "lc_batch_step": ([_vp, _i32, _d, _vp], C.c_int),
+    "lc_batch_free": ([_vp], C.c_int),
+}
+EXPORTED = tuple(_SIGS)
+for _name, (_args, _res) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+
+def _check(status):
+    if status != LC_OK:
+        raise LcError(status, _lib.lc_last_error().decode(errors="replace"))
+
+
+def lc_version() -> int:
+    return _lib.lc_version()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, n, dtype_name="float64", name="tensor", optional=False):
+    """Raw device pointer of a contiguous CUDA tensor holding >= n elements."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a device tensor")
+    if str(t.dtype) != f"torch.{dtype_name}":
+        raise TypeError(f"{name} must be {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < n:
+        raise ValueError(f"{name} holds {t.numel()} elements, needs {n}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _bytes(t, nbytes, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous device tensor")
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{name} holds {t.numel() * t.element_size()} bytes, needs {nbytes}")
+    return C.c_void_p(t.data_ptr())
+
+
+class Rays:
+    """Owning wrapper of an ``lc_rays_t`` handle."""
+
+    def __init__(self, handle, nx, ny, n_az, n_pol):
+        self.handle = handle
+        info = lc_rays_info_t()
+        _check(_lib.lc_rays_info(handle, C.byref(info)))
+        self.info = info
+        self.nx, self.ny, self.n_az, self.n_pol = nx, ny, n_az, n_pol
+        self.n_rays = info.n_rays
+        self.n_segments = info.n_segments
+        self.n_pairs = info.n_pairs
+        self.cells = info.n_cells
+        self.nb = info.n_faces
+        self.M = n_az * n_pol
+
+    def free(self):
+        if self.handle:
+            _check(_lib.lc_rays_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def lc_build_rays(nx, ny, lx, ly, phi, mu, omega, h_moc, mode=LC_RAYS_UNIFORM, stream=None) -> Rays:
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    omega = np.ascontiguousarray(omega, dtype=np.float64)
+    if omega.size != phi.size * mu.size:
+        raise ValueError("omega must have n_az * n_pol entries")
+    g = lc_grid(int(nx), int(ny), float(lx), float(ly))
+    dp = C.POINTER(C.c_double)
+    q = lc_quad(phi.size, mu.size, phi.ctypes.data_as(dp), mu.ctypes.data_as(dp), omega.ctypes.data_as(dp))
+    h = C.c_void_p()
+    _check(_lib.lc_build_rays(C.byref(g), C.byref(q), float(h_moc), int(mode), _stream(stream), C.byref(h)))
+    return Rays(h, int(nx), int(ny), phi.size, mu.size)
+
+
+def lc_rays_export(rays: Rays):
+    """Host copies: (ray_off, seg_off, cell, len, width, face)."""
+    ro = np.zeros(rays.n_pairs + 1, np.int32)
+    so = np.zeros(rays.n_rays + 1, np.int32)
+    ce = np.zeros(rays.n_segments, np.int32)
+    ln = np.zeros(rays.n_segments, np.float64)
+    wd = np.zeros(rays.n_rays, np.float64)
+    fc = np.zeros((rays.n_rays, 2), np.int32)
+    _check(_lib.lc_rays_export(rays.handle, ro.ctypes.data, so.ctypes.data, ce.ctypes.data,
+                               ln.ctypes.data, wd.ctypes.data, fc.ctypes.data))
+    return ro, so, ce, ln, wd, fc
+
+
+class Plan:
+    """Owning wrapper of an ``lc_plan_t`` handle (keeps its rays alive)."""
+
+    def __init__(self, rays: Rays, G: int, prec: int):
+        h = C.c_void_p()
+        _check(_lib.lc_plan_create(rays.handle, int(G), int(prec), C.byref(h)))
+        self.handle = h
+        self.rays = rays
+        self.G = int(G)
+        self.prec = int(prec)
+        self.state_bytes = int(_lib.lc_state_bytes(h))
+        r = rays
+        self.n_state = r.n_segments * 2 * r.n_pol * self.G
+        self.n_field = r.cells * self.G
+        self.n_in = r.nb * r.M * self.G
+        self.n_exit = r.n_rays * 2 * r.n_pol * self.G
+
+    def free(self):
+        if self.handle:
+            _check(_lib.lc_plan_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    def new_state(self):
+        import torch
+        return torch.empty(self.state_bytes, dtype=torch.uint8, device="cuda")
+
+
+def lc_plan_create(rays: Rays, G: int, prec: int) -> Plan:
+    return Plan(rays, G, prec)
+
+
+def lc_state_fill(plan: Plan, field, state, stream=None):
+    _check(_lib.lc_state_fill(plan.handle, _dev(field, plan.n_field, name="field"),
+                              _bytes(state, plan.state_bytes, "state"), _stream(stream)))
+
+
+def lc_state_export(plan: Plan, state, out, stream=None):
+    _check(_lib.lc_state_export(plan.handle, _bytes(state, plan.state_bytes, "state"),
+                                _dev(out, plan.n_state, name="out"), _stream(stream)))
+
+
+def lc_sweep(plan: Plan, kappa, planck, c_dt, state_prev, state_new, I_in, I_exit=None, stream=None):
+    _check(_lib.lc_sweep(plan.handle, _dev(kappa, plan.n_field, name="kappa"),
+                         _dev(planck, plan.n_field, name="planck"), float(c_dt),
+                         _bytes(state_prev, plan.state_bytes, "state_prev"),
+                         _bytes(state_new, plan.state_bytes, "state_new"),
+                         _dev(I_in, plan.n_in, name="I_in"),
+                         _dev(I_exit, plan.n_exit, name="I_exit", optional=True), _stream(stream)))
+
+
+def lc_moments(plan: Plan, state, c, E=None, F=None, f=None, bnd=None, I_exit=None, I_in=None,
+               stream=None):
+    r = plan.rays
+    _check(_lib.lc_moments(plan.handle, _bytes(state, plan.state_bytes, "state"),
+                           _dev(I_exit, plan.n_exit, name="I_exit", optional=True),
+                           _dev(I_in, plan.n_in, name="I_in", optional=True), float(c),
+                           _dev(E, plan.n_field, name="E", optional=True),
+                           _dev(F, 2 * plan.n_field, name="F", optional=True),
+                           _dev(f, 4 * plan.n_field, name="f", optional=True),
+                           _dev(bnd, plan.G * r.nb * 8, name="bnd", optional=True), _stream(stream)))
+
+
+def lc_plan_profile(plan: Plan, enable: bool):
+    _check(_lib.lc_plan_profile(plan.handle, int(bool(enable))))
+
+
+def lc_plan_profile_read(plan: Plan):
+    """(sweep_ms_total, sweep_launches, moments_ms_total, moments_launches)."""
+    out = (C.c_double * 4)()
+    _check(_lib.lc_plan_profile_read(plan.handle, out))
+    return tuple(out)
+
+
+def lc_step(plan: Plan, n_steps, kappa, planck, c_dt, c, state_a, state_b, I_in, I_exit=None,
+            E=None, F=None, f=None, bnd=None, material_stride=0, stream=None):
+    r = plan.rays
+    n_mat = plan.n_field + (int(n_steps) - 1) * int(material_stride)
+    _check(_lib.lc_step(plan.handle, int(n_steps), _dev(kappa, n_mat, name="kappa"),
+                        _dev(planck, n_mat, name="planck"), int(material_stride), float(c_dt), float(c),
+                        _bytes(state_a, plan.state_bytes, "state_a"),
+                        _bytes(state_b, plan.state_bytes, "state_b"),
+                        _dev(I_in, plan.n_in, name="I_in"),
+                        _dev(I_exit, plan.n_exit, name="I_exit", optional=True),
+                        _dev(E, plan.n_field, name="E", optional=True),
+                        _dev(F, 2 * plan.n_field, name="F", optional=True),
+                        _dev(f, 4 * plan.n_field, name="f", optional=True),
+                        _dev(bnd, plan.G * r.nb * 8, name="bnd", optional=True), _stream(stream)))
