@@ -49,7 +49,9 @@ void free_plan(Plan* pl) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (pl->capture) (void)hipStreamDestroy(pl->capture);
     if (pl->d_coef) (void)hipFree(pl->d_coef);
-    if (pl->d_blk_off) (void)hipFree(pl->d_blk_off);
+    if (pl->d_bun_off) (void)hipFree(pl->d_bun_off);
+    if (pl->d_bun_len) (void)hipFree(pl->d_bun_len);
+    if (pl->d_bun_base) (void)hipFree(pl->d_bun_base);
     pl->magic = 0;
     delete pl;
 }
@@ -249,15 +251,22 @@ lc_status lc_plan_create(lc_rays_t rays, int32_t G, int32_t prec, lc_plan_t* out
     pl->G = G;
     pl->prec = prec;
     pl->hdr_bytes = ((size_t)G * sizeof(int32_t) + 255) / 256 * 256;
-    pl->value_bytes = (size_t)r->n_seg * 2 * r->n_pol * G * (prec == LC_F32 ? 4 : 8);
     lc_status rc = plan_init_sweep(pl);
+    pl->value_bytes = (size_t)pl->half_elems * 2 * (prec == LC_F32 ? 4 : 8);
     hipError_t e = hipSuccess;
     if (rc == LC_OK) {
         const size_t coef_bytes = (size_t)r->cells * G * (prec == LC_F32 ? 16 : 32);
+        const size_t nbun = (size_t)pl->n_bun;
         e = hipMalloc(&pl->d_coef, coef_bytes);
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_blk_off), pl->blk_off.size() * sizeof(int));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_off), pl->bun_off.size() * sizeof(int));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_len), std::max<size_t>(nbun, 1) * sizeof(int));
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_base), std::max<size_t>(nbun, 1) * sizeof(int64_t));
         if (e == hipSuccess)
-            e = hipMemcpy(pl->d_blk_off, pl->blk_off.data(), pl->blk_off.size() * sizeof(int), hipMemcpyHostToDevice);
+            e = hipMemcpy(pl->d_bun_off, pl->bun_off.data(), pl->bun_off.size() * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(pl->d_bun_len, pl->bun_len_h.data(), nbun * sizeof(int), hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(pl->d_bun_base, pl->bun_base_h.data(), nbun * sizeof(int64_t), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->capture, hipStreamNonBlocking);
         if (e != hipSuccess) {
             set_error("plan allocation failed: %s", hipGetErrorString(e));

@@ -216,7 +216,7 @@ __global__ void k_csr_fill(const int* __restrict__ ray_off, int n_pairs, int n_r
                            const int* __restrict__ seg_off, const int* __restrict__ cell,
                            const double* __restrict__ len, const double* __restrict__ width,
                            const int* __restrict__ csr_off, const int* __restrict__ kfirst,
-                           int* csr_seg, double* csr_A, int* err) {
+                           int* csr_ray, int2* csr_t, double* csr_A, int* err) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_rays) return;
     int a = find_pair(ray_off, n_pairs, k);
@@ -228,7 +228,9 @@ __global__ void k_csr_fill(const int* __restrict__ ray_off, int n_pairs, int n_r
             atomicOr(err, 1);
             continue;
         }
-        csr_seg[pos] = j;
+        const int sp = j - seg_off[k];
+        csr_ray[pos] = k;
+        csr_t[pos] = make_int2(sp, seg_off[k + 1] - seg_off[k] - 1 - sp);   // position in d = 0, 1 order
         csr_A[pos] = len[j] * width[k];
     }
 }
@@ -412,6 +414,7 @@ lc_status build_geometry(Rays* r, hipStream_t st) {
             }
         }
         r->max_seg = mx;
+        r->seg_off = so;
     }
     r->n_seg = total;
     const int64_t ns = total;
@@ -430,7 +433,8 @@ lc_status build_geometry(Rays* r, hipStream_t st) {
     LC_STEP(dalloc(tmp, &d_cnt, n_keys));
     LC_STEP(dalloc(tmp, &d_kfirst, n_keys));
     LC_STEP(dalloc(r->owned, &r->d_csr_off, n_keys + 1));
-    LC_STEP(dalloc(r->owned, &r->d_csr_seg, ns));
+    LC_STEP(dalloc(r->owned, &r->d_csr_ray, ns));
+    LC_STEP(dalloc(r->owned, &r->d_csr_t, ns));
     LC_STEP(dalloc(r->owned, &r->d_csr_w, ns));
     LC_STEP(dalloc(r->owned, &r->d_csr_w32, ns));
     hipLaunchKernelGGL(k_fill_int, dim3(nblk(n_keys)), dim3(kBlock), 0, st, d_cnt, n_keys, 0);
@@ -441,7 +445,7 @@ lc_status build_geometry(Rays* r, hipStream_t st) {
     LC_STEP(scan_counts(d_cnt, r->d_csr_off, n_keys, tmp, st));
     hipLaunchKernelGGL(k_csr_fill, dim3(nblk(nr)), dim3(kBlock), 0, st, r->d_ray_off, P, nr,
                        r->d_seg_off, r->d_cell, r->d_len, r->d_width, r->d_csr_off, d_kfirst,
-                       r->d_csr_seg, r->d_csr_w, d_err);
+                       r->d_csr_ray, r->d_csr_t, r->d_csr_w, d_err);
     hipLaunchKernelGGL(k_csr_norm, dim3(nblk(n_keys)), dim3(kBlock), 0, st, r->d_csr_off, n_keys,
                        r->d_csr_w, r->d_csr_w32, d_err);
     LC_HIPC(hipGetLastError());

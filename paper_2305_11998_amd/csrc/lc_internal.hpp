@@ -38,6 +38,7 @@ constexpr uint32_t kPlanMagic = 0x4c43504cu;   // "LCPL"
 constexpr uint32_t kBatchMagic = 0x4c434254u;  // "LCBT"
 constexpr int kMaxPol = 8;
 constexpr int kBlock = 256;                    // threads per block of the streaming kernels
+constexpr int kWave = 64;                      // lanes per wavefront (gfx9)
 constexpr int kDirW = 10;                      // per-direction weight record, see dirw_index
 
 // Per (pair a, traversal d, polar p) record, float64:
@@ -58,6 +59,7 @@ struct Rays {
     bool sym = false;                 // mu[p] == -mu[P-1-p] for every p
     std::vector<double> phi, mu, omega, inv_sinz, cphi, sphi;
     std::vector<int> ray_off;         // host copy [n_pairs + 1]
+    std::vector<int> seg_off;         // host copy [n_rays + 1]
     std::vector<double> dirw;         // host copy of d_dirw
     // device geometry
     int* d_ray_off = nullptr;         // [n_pairs + 1]
@@ -70,7 +72,8 @@ struct Rays {
     double* d_len = nullptr;          // [n_seg]
     float* d_len32 = nullptr;         // [n_seg]
     int* d_csr_off = nullptr;         // [cells * n_pairs + 1], index cell * n_pairs + a
-    int* d_csr_seg = nullptr;         // [n_seg] global segment j
+    int* d_csr_ray = nullptr;         // [n_seg] global ray k of the entry
+    int2* d_csr_t = nullptr;          // [n_seg] position of the segment in the d = 0 and d = 1 traversal
     double* d_csr_w = nullptr;        // [n_seg] A_j / sum of A over C(i, m)
     float* d_csr_w32 = nullptr;
     int* d_bmap = nullptr;            // [nb][n_pairs][2][2] first, end global ray leaving through b; -1 = incoming
@@ -93,9 +96,20 @@ struct Plan {
     size_t hdr_bytes = 0;             // state header (per-group scale exponents)
     size_t value_bytes = 0;
     void* d_coef = nullptr;           // [cells][G] {kappa_t, emission/kappa_t, 1/(c dt kappa_t), 0}
+    // State layout: the lanes (k, g) of pair a, g fastest, are cut into
+    // bundles of 64 (one wavefront each).  For traversal d and bundle B the
+    // values [t][p][lane] (t = step along the traversal, padded to the
+    // longest characteristic of the bundle) are contiguous at
+    // d * half_elems + bun_base[B].
+    int64_t n_bun = 0;                // bundles over all pairs
+    std::vector<int> bun_off;         // [n_pairs + 1] first bundle of each pair
+    std::vector<int> bun_len_h;       // [n_bun] steps of each bundle
+    std::vector<int64_t> bun_base_h;  // [n_bun] element offset within one traversal half
+    int64_t half_elems = 0;
+    int* d_bun_off = nullptr;
+    int* d_bun_len = nullptr;
+    int64_t* d_bun_base = nullptr;
     int64_t sweep_blocks = 0;         // blocks of one sweep launch
-    std::vector<int> blk_off;         // [2 n_pairs + 1] first logical block of (a, d)
-    int* d_blk_off = nullptr;
     std::vector<GraphEntry> graphs;   // captured lc_step sequences
     hipStream_t capture = nullptr;    // stream used only to record graphs
     bool profile = false;             // record events around the main kernels

@@ -13,8 +13,13 @@ namespace {
 
 struct MomArgs {
     const int* csr_off;
-    const int* csr_seg;
+    const int* csr_ray;     // ray of each entry
+    const int2* csr_t;      // its step in the d = 0 and d = 1 traversal
     const void* csr_w;      // double or float
+    const int* ray_off;
+    const int* bun_off;
+    const int64_t* bun_base;
+    int64_t half;
     const double* dirw;     // [n_pairs][2][P][kDirW]
     const void* state;      // values
     const int* e;           // per-group exponents of the state (float32 only)
@@ -51,20 +56,29 @@ __global__ __launch_bounds__(kBlock) void k_cell_moments(MomArgs A) {
     const int g = (int)(lane - (int64_t)cell * G);
     const T* __restrict__ st = static_cast<const T*>(A.state);
     const T* __restrict__ cw = static_cast<const T*>(A.csr_w);
-    const size_t seg_stride = (size_t)2 * P * G;
     Acc<T> acc[7];
     for (int a = 0; a < A.n_pairs; ++a) {
         const int e0 = A.csr_off[(size_t)cell * A.n_pairs + a];
         const int e1 = A.csr_off[(size_t)cell * A.n_pairs + a + 1];
+        const int r0 = A.ray_off[a];
+        const int b0 = A.bun_off[a];
         T Iim[2 * P];
 #pragma unroll
         for (int q = 0; q < 2 * P; ++q) Iim[q] = (T)0;
         for (int e = e0; e < e1; ++e) {
-            const int j = A.csr_seg[e];
+            const int k = A.csr_ray[e];
+            const int2 tt = A.csr_t[e];
             const T w = cw[e];
-            const T* row = st + (size_t)j * seg_stride + g;
+            // bundle-major state: lane f = (k - r0) G + g of bundle b0 + f / 64
+            const int f = (k - r0) * G + g;
+            const T* row = st + (size_t)A.bun_base[b0 + f / kWave] + (f & (kWave - 1));
+            const T* r0p = row + (size_t)tt.x * P * kWave;
+            const T* r1p = row + (size_t)A.half + (size_t)tt.y * P * kWave;
 #pragma unroll
-            for (int q = 0; q < 2 * P; ++q) Iim[q] += w * __builtin_nontemporal_load(row + (size_t)q * G);
+            for (int p = 0; p < P; ++p) {
+                Iim[p] += w * __builtin_nontemporal_load(r0p + p * kWave);
+                Iim[P + p] += w * __builtin_nontemporal_load(r1p + p * kWave);
+            }
         }
 #pragma unroll
         for (int q = 0; q < 2 * P; ++q) {
@@ -195,7 +209,12 @@ lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, cons
     if (E || F || f) {
         MomArgs A{};
         A.csr_off = r->d_csr_off;
-        A.csr_seg = r->d_csr_seg;
+        A.csr_ray = r->d_csr_ray;
+        A.csr_t = r->d_csr_t;
+        A.ray_off = r->d_ray_off;
+        A.bun_off = pl->d_bun_off;
+        A.bun_base = pl->d_bun_base;
+        A.half = pl->half_elems;
         A.csr_w = f32 ? static_cast<const void*>(r->d_csr_w32) : static_cast<const void*>(r->d_csr_w);
         A.dirw = r->d_dirw;
         A.state = state_values(pl, state);

@@ -23,26 +23,76 @@ __global__ void k_field_scale(const double* __restrict__ field, int cells, int* 
     if (threadIdx.x == 0) e[g] = (sh[0] > 0.0 && isfinite(sh[0])) ? ilogb(sh[0]) + 1 : 0;
 }
 
-template <typename T>
-__global__ void k_fill(const double* __restrict__ field, const int* __restrict__ cell, int cells,
-                       int64_t n, int PG2, int G, const int* __restrict__ e, T* out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int64_t j = i / PG2;
-    const int g = (int)(i % G);
-    double v = field[(int64_t)g * cells + cell[j]];
-    if (sizeof(T) == 4) v = ldexp(v, -e[g]);
-    out[i] = (T)v;
+struct SlotArgs {
+    const int* bun_off;
+    const int* bun_len;
+    const int64_t* bun_base;
+    const int* ray_off;
+    const int* seg_off;
+    const int* cell;
+    int n_pairs, G, P, cells;
+    int64_t n_bun, half;
+};
+
+__device__ __forceinline__ int find_pair(const int* __restrict__ off, int n, int64_t v) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (off[mid] <= v) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Visit every slot of the bundle (d, B) = block; fn(slot, j, g, p) with
+// j = -1 for padding slots.
+template <typename Fn>
+__device__ void for_slots(const SlotArgs& A, Fn fn) {
+    const int64_t w = blockIdx.x;
+    const int d = w >= A.n_bun ? 1 : 0;
+    const int64_t B = w - (d ? A.n_bun : 0);
+    const int a = find_pair(A.bun_off, A.n_pairs, B);
+    const int r0 = A.ray_off[a], Ka = A.ray_off[a + 1] - r0;
+    const int64_t base = (int64_t)d * A.half + A.bun_base[B];
+    const int64_t n = (int64_t)A.bun_len[B] * A.P * kWave;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int lane = (int)(i & (kWave - 1));
+        const int64_t tp = i / kWave;
+        const int p = (int)(tp % A.P);
+        const int t = (int)(tp / A.P);
+        const int f = (int)(B - A.bun_off[a]) * kWave + lane;
+        const int kl = f / A.G, g = f - kl * A.G;
+        int j = -1;
+        if (kl < Ka) {
+            const int k = r0 + kl;
+            const int s0 = A.seg_off[k], nk = A.seg_off[k + 1] - s0;
+            if (t < nk) j = s0 + (d == 0 ? t : nk - 1 - t);
+        }
+        fn(base + i, j, d, g, p);
+    }
 }
 
 template <typename T>
-__global__ void k_export(const T* __restrict__ in, int64_t n, int G, const int* __restrict__ e,
-                         double* out) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double v = (double)in[i];
-    if (sizeof(T) == 4) v = ldexp(v, e[i % G]);
-    out[i] = v;
+__global__ void k_fill(SlotArgs A, const double* __restrict__ field, const int* __restrict__ e, T* out) {
+    for_slots(A, [&](int64_t slot, int j, int d, int g, int p) {
+        (void)d;
+        (void)p;
+        double v = 0.0;
+        if (j >= 0) {
+            v = field[(int64_t)g * A.cells + A.cell[j]];
+            if (sizeof(T) == 4) v = ldexp(v, -e[g]);
+        }
+        out[slot] = (T)v;
+    });
+}
+
+template <typename T>
+__global__ void k_export(SlotArgs A, const T* __restrict__ in, const int* __restrict__ e, double* out) {
+    for_slots(A, [&](int64_t slot, int j, int d, int g, int p) {
+        if (j < 0) return;
+        double v = (double)in[slot];
+        if (sizeof(T) == 4) v = ldexp(v, e[g]);
+        out[(((int64_t)j * 2 + d) * A.P + p) * A.G + g] = v;
+    });
 }
 
 __global__ void k_zero_int(int* p, int n) {
@@ -52,37 +102,55 @@ __global__ void k_zero_int(int* p, int n) {
 
 }  // namespace
 
+namespace {
+SlotArgs slot_args(Plan* pl) {
+    Rays* r = pl->rays;
+    SlotArgs A{};
+    A.bun_off = pl->d_bun_off;
+    A.bun_len = pl->d_bun_len;
+    A.bun_base = pl->d_bun_base;
+    A.ray_off = r->d_ray_off;
+    A.seg_off = r->d_seg_off;
+    A.cell = r->d_cell;
+    A.n_pairs = r->n_pairs;
+    A.G = pl->G;
+    A.P = r->n_pol;
+    A.cells = r->cells;
+    A.n_bun = pl->n_bun;
+    A.half = pl->half_elems;
+    return A;
+}
+}  // namespace
+
 lc_status launch_state_fill(Plan* pl, const double* field, void* state, hipStream_t st) {
     Rays* r = pl->rays;
     const int G = pl->G;
-    const int64_t n = r->n_seg * 2 * r->n_pol * G;
     int* e = static_cast<int*>(state);
-    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    const SlotArgs A = slot_args(pl);
+    const unsigned nb = (unsigned)(2 * pl->n_bun);
     if (pl->prec == LC_F32) {
         hipLaunchKernelGGL(k_field_scale, dim3(G), dim3(kBlock), 0, st, field, r->cells, e);
-        hipLaunchKernelGGL(k_fill<float>, dim3(nb), dim3(kBlock), 0, st, field, r->d_cell, r->cells, n,
-                           2 * r->n_pol * G, G, e, static_cast<float*>(state_values(pl, state)));
+        hipLaunchKernelGGL(k_fill<float>, dim3(nb), dim3(kBlock), 0, st, A, field, e,
+                           static_cast<float*>(state_values(pl, state)));
     } else {
         hipLaunchKernelGGL(k_zero_int, dim3((G + kBlock - 1) / kBlock), dim3(kBlock), 0, st, e, G);
-        hipLaunchKernelGGL(k_fill<double>, dim3(nb), dim3(kBlock), 0, st, field, r->d_cell, r->cells, n,
-                           2 * r->n_pol * G, G, e, static_cast<double*>(state_values(pl, state)));
+        hipLaunchKernelGGL(k_fill<double>, dim3(nb), dim3(kBlock), 0, st, A, field, e,
+                           static_cast<double*>(state_values(pl, state)));
     }
     LC_HIP(hipGetLastError());
     return LC_OK;
 }
 
 lc_status launch_state_export(Plan* pl, const void* state, double* out, hipStream_t st) {
-    Rays* r = pl->rays;
-    const int G = pl->G;
-    const int64_t n = r->n_seg * 2 * r->n_pol * G;
     const int* e = static_cast<const int*>(state);
-    const unsigned nb = (unsigned)((n + kBlock - 1) / kBlock);
+    const SlotArgs A = slot_args(pl);
+    const unsigned nb = (unsigned)(2 * pl->n_bun);
     if (pl->prec == LC_F32)
-        hipLaunchKernelGGL(k_export<float>, dim3(nb), dim3(kBlock), 0, st,
-                           static_cast<const float*>(state_values(pl, state)), n, G, e, out);
+        hipLaunchKernelGGL(k_export<float>, dim3(nb), dim3(kBlock), 0, st, A,
+                           static_cast<const float*>(state_values(pl, state)), e, out);
     else
-        hipLaunchKernelGGL(k_export<double>, dim3(nb), dim3(kBlock), 0, st,
-                           static_cast<const double*>(state_values(pl, state)), n, G, e, out);
+        hipLaunchKernelGGL(k_export<double>, dim3(nb), dim3(kBlock), 0, st, A,
+                           static_cast<const double*>(state_values(pl, state)), e, out);
     LC_HIP(hipGetLastError());
     return LC_OK;
 }

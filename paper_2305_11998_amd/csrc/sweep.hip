@@ -1,15 +1,17 @@
 // The transport sweep, eq. (10)-(13), on gfx950.
 //
-// Work decomposition: for each azimuth pair a and traversal d, the lanes of a
-// launch enumerate (characteristic k, group g) with g fastest, so a 64-wide
-// wavefront covers consecutive groups of one or a few neighbouring
-// characteristics.  Each lane walks its characteristic segment by segment,
-// carrying the intensity of every polar angle p in registers; per segment it
-// reads one cell-coefficient record (coalesced over g), the stored
-// I_bar^{n-1} of every p (coalesced over g), and writes I_bar^n.  Polar
+// Work decomposition: the lanes (characteristic k, group g) of an azimuth
+// pair, g fastest, are cut into bundles of 64 -- one wavefront per bundle and
+// traversal.  Each lane walks its characteristic segment by segment, carrying
+// the intensity of every polar angle p in registers; per segment it reads one
+// cell-coefficient record (coalesced over g), the stored I_bar^{n-1} of every
+// p, and writes I_bar^n.  The state is laid out bundle-major, step-minor, so
+// every wavefront streams its own contiguous, aligned 64-lane runs.  Polar
 // angles with equal sin(zeta) (the +mu/-mu pairs of a symmetric set) share
 // the exponential and the weight alpha.  Blocks are remapped so that each
 // XCD's L2 serves a contiguous band of characteristics.
+#include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "lc_internal.hpp"
@@ -22,8 +24,12 @@ template <> struct Coef<double> { double kt, a, b, pad; };
 template <> struct Coef<float> { float kt, a, b, pad; };
 
 struct SweepArgs {
-    const int* blk_off;      // [n_pd + 1] first logical block of each (a, d)
-    int n_pd;
+    const int* bun_off;      // [n_pairs + 1] first bundle of each pair
+    const int* bun_len;      // [n_bun] steps of each bundle
+    const int64_t* bun_base; // [n_bun] element offset of each bundle within a traversal half
+    int n_pairs;
+    int64_t n_bun;
+    int64_t half;            // elements of one traversal half of the state
     int64_t n_blocks;
     const int* ray_off;
     const int* seg_off;
@@ -49,11 +55,11 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t hw, int64_t n) {
     return x * q + (x < r ? x : r) + i;
 }
 
-__device__ __forceinline__ int find_block(const int* __restrict__ off, int n, int64_t lb) {
-    int lo = 0, hi = n;
+__device__ __forceinline__ int find_pair(const int* __restrict__ off, int n, int64_t v) {
+    int lo = 0, hi = n;                // off[lo] <= v < off[hi]
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
-        if (off[mid] <= lb) lo = mid; else hi = mid;
+        if (off[mid] <= v) lo = mid; else hi = mid;
     }
     return lo;
 }
@@ -68,7 +74,7 @@ __device__ __forceinline__ Att<float> attenuate(float tau) {
     const float D = tau < 0.25f ? Ds : 1.f - E;
     const float t2 = tau * tau;
     const float as = 0.5f - tau * (1.f / 12.f - t2 * (1.f / 720.f - t2 * (1.f / 30240.f - t2 * (1.f / 1209600.f - t2 * (1.f / 47900160.f)))));
-    const float ac = __fdividef(D - tau * E, tau * D);
+    const float ac = (D - tau * E) * __builtin_amdgcn_rcpf(tau * D);
     const float al = tau < 1.f ? as : ac;
     return {E, D, al, 1.f - al};
 }
@@ -92,29 +98,42 @@ __device__ __forceinline__ T ldg_stream(const T* p) { return __builtin_nontempor
 template <typename T>
 __device__ __forceinline__ void stg_stream(T* p, T v) { __builtin_nontemporal_store(v, p); }
 
-constexpr int kUnroll = 4;   // segments whose loads are issued together
-
-template <typename T, int P, bool SYM>
+// One wavefront per (traversal d, bundle B).  Lane (k, g) walks its
+// characteristic; step t reads the P stored values of the lane at
+// [t][p][lane] of the bundle (one 64-lane contiguous run per p) and writes the
+// new ones at the same place.  Loads run one chunk of U steps ahead of the
+// arithmetic: the geometry two chunks ahead, the cell coefficients (which
+// depend on it) and the stored values one chunk ahead.
+template <typename T, int P, bool SYM, int U>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
     const int64_t lb = xcd_logical_block(blockIdx.x, A.n_blocks);
-    const int pd = find_block(A.blk_off, A.n_pd, lb);
-    const int a = pd >> 1, d = pd & 1;
+    const int64_t w = lb * (kBlock / kWave) + (threadIdx.x / kWave);
+    const int lane = threadIdx.x & (kWave - 1);
+    if (w >= 2 * A.n_bun) return;
+    const int d = w >= A.n_bun ? 1 : 0;
+    const int64_t B = w - (d ? A.n_bun : 0);
+    const int a = find_pair(A.bun_off, A.n_pairs, B);
     const int G = A.G;
-    const int64_t f = (lb - A.blk_off[pd]) * kBlock + threadIdx.x;
     const int r0 = A.ray_off[a];
     const int Ka = A.ray_off[a + 1] - r0;
-    const int kl = (int)(f / G);
-    const int g = (int)(f - (int64_t)kl * G);
-    if (kl >= Ka) return;
+    const int f = (int)(B - A.bun_off[a]) * kWave + lane;
+    int kl = f / G;
+    const int g = f - kl * G;
+    const bool active = kl < Ka;
+    if (!active) kl = Ka - 1;                  // keep addresses valid; nothing is stored
     const int k = r0 + kl;
-    const int s0 = A.seg_off[k], s1 = A.seg_off[k + 1];
-    const int n = s1 - s0;
-    const int face_in = A.face[2 * k + d];
+    const int s0 = A.seg_off[k];
+    const int nk = A.seg_off[k + 1] - s0;
+    const int n = active ? nk : 0;
+    const int L = A.bun_len[B];
     const int az = a + d * (A.n_az >> 1);
     const T* __restrict__ len = static_cast<const T*>(A.len);
+    const int* __restrict__ cellv = A.cell;
     const Coef<T>* __restrict__ coef = static_cast<const Coef<T>*>(A.coef);
-    const T* __restrict__ prev = static_cast<const T*>(A.prev);
-    T* __restrict__ next = static_cast<T*>(A.next);
+    const size_t boff = (size_t)d * A.half + (size_t)A.bun_base[B] + lane;
+    const T* __restrict__ xin = static_cast<const T*>(A.prev) + boff;
+    T* __restrict__ xout = static_cast<T*>(A.next) + boff;
+    constexpr int SP = P * kWave;              // elements per step of a bundle
 
     double sc_in = 1.0, sc_out = 1.0;
     if (sizeof(T) == 4) {
@@ -124,59 +143,82 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
     }
     T isz[P];
     T I[P];
+    const int face_in = A.face[2 * k + d];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         isz[p] = (T)A.inv_sinz[p];
         I[p] = (T)(A.I_in[((size_t)face_in * A.M + (size_t)az * P + p) * G + g] * sc_in);
     }
-    const int step = d == 0 ? 1 : -1;
-    const int jfirst = d == 0 ? s0 : s1 - 1;
-    const size_t seg_stride = (size_t)2 * P * G;
-    const size_t lane_off = (size_t)d * P * G + g;
+    // segment index of step t (clamped into the characteristic)
+    auto seg = [&](int t) -> int {
+        const int tt = t < nk ? t : nk - 1;
+        return d == 0 ? s0 + tt : s0 + nk - 1 - tt;
+    };
+    auto srow = [&](int t) -> const T* { return xin + (size_t)(t < L ? t : L - 1) * SP; };
 
-    for (int t0 = 0; t0 < n; t0 += kUnroll) {
-        int ci[kUnroll];
-        T l[kUnroll];
-        Coef<T> cf[kUnroll];
-        T x[kUnroll][P];
-        size_t base[kUnroll];
+    int ci1[U];
+    T l0[U], l1[U];
+    Coef<T> c0[U];
+    T x0[U][P];
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            const int t = min(t0 + u, n - 1);
-            const int j = jfirst + step * t;
-            ci[u] = A.cell[j];
-            l[u] = len[j];
-            base[u] = (size_t)j * seg_stride + lane_off;
+    for (int u = 0; u < U; ++u) {
+        const int j0 = seg(u), j1 = seg(U + u);
+        l0[u] = len[j0];
+        c0[u] = coef[(size_t)cellv[j0] * G + g];
+        ci1[u] = cellv[j1];
+        l1[u] = len[j1];
+        const T* r = srow(u);
+#pragma unroll
+        for (int p = 0; p < P; ++p) x0[u][p] = ldg_stream(r + p * kWave);
+    }
+    for (int t0 = 0; t0 < L; t0 += U) {
+        Coef<T> c1[U];
+        T x1[U][P];
+        int ci2[U];
+        T l2[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c1[u] = coef[(size_t)ci1[u] * G + g];
+            const T* r = srow(t0 + U + u);
+#pragma unroll
+            for (int p = 0; p < P; ++p) x1[u][p] = ldg_stream(r + p * kWave);
+            const int j2 = seg(t0 + 2 * U + u);
+            ci2[u] = cellv[j2];
+            l2[u] = len[j2];
         }
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            cf[u] = coef[(size_t)ci[u] * G + g];
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u;
+            const bool live = t < n;
+            const T ktl = c0[u].kt * l0[u];
+            Att<T> at[P];
 #pragma unroll
-            for (int p = 0; p < P; ++p) x[u][p] = ldg_stream(prev + base[u] + (size_t)p * G);
-        }
+            for (int p = 0; p < P; ++p) {
+                const int q = (SYM && p >= (P + 1) / 2) ? (P - 1 - p) : p;
+                if (q == p) at[p] = attenuate(ktl * isz[p]);
+                else at[p] = at[q];
+            }
+            T* o = xout + (size_t)t * SP;
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) {
-            if (t0 + u < n) {
-                const T ktl = cf[u].kt * l[u];
-                Att<T> at[P];
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const int q = (SYM && p >= (P + 1) / 2) ? (P - 1 - p) : p;
-                    if (q == p) at[p] = attenuate(ktl * isz[p]);
-                    else at[p] = at[q];
-                }
-#pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    const T S = cf[u].a + cf[u].b * x[u][p];          // Q / kappa_t
-                    const T Io = at[p].E * I[p] + at[p].D * S;         // eq. (12)
-                    const T Ib = at[p].al * I[p] + at[p].be * Io;      // segment average
-                    stg_stream(next + base[u] + (size_t)p * G, Ib);
-                    I[p] = Io;
-                }
+            for (int p = 0; p < P; ++p) {
+                const T S = c0[u].a + c0[u].b * x0[u][p];             // Q / kappa_t
+                const T Io = at[p].E * I[p] + at[p].D * S;            // eq. (12)
+                const T Ib = at[p].al * I[p] + at[p].be * Io;         // segment average
+                if (live) stg_stream(o + p * kWave, Ib);
+                I[p] = live ? Io : I[p];
             }
         }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            c0[u] = c1[u];
+            l0[u] = l1[u];
+            l1[u] = l2[u];
+            ci1[u] = ci2[u];
+#pragma unroll
+            for (int p = 0; p < P; ++p) x0[u][p] = x1[u][p];
+        }
     }
-    if (A.I_exit) {
+    if (A.I_exit && active) {
 #pragma unroll
         for (int p = 0; p < P; ++p)
             A.I_exit[((size_t)(2 * k + d) * P + p) * G + g] = (double)I[p] * sc_out;
@@ -240,8 +282,9 @@ lc_status launch_sweep_t(Plan* pl, const SweepArgs& A, bool sym, hipStream_t st)
     dim3 grid((unsigned)pl->sweep_blocks), block(kBlock);
     lc_status rc = prof_begin(pl, pl->ev_sweep, st);
     if (rc) return rc;
-    if (sym) hipLaunchKernelGGL((k_sweep<T, P, true>), grid, block, 0, st, A);
-    else hipLaunchKernelGGL((k_sweep<T, P, false>), grid, block, 0, st, A);
+    constexpr int U = sizeof(T) == 4 ? 4 : 2;
+    if (sym) hipLaunchKernelGGL((k_sweep<T, P, true, U>), grid, block, 0, st, A);
+    else hipLaunchKernelGGL((k_sweep<T, P, false, U>), grid, block, 0, st, A);
     LC_HIP(hipGetLastError());
     return prof_end(pl, pl->ev_sweep, st);
 }
@@ -268,17 +311,32 @@ inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); 
 
 lc_status plan_init_sweep(Plan* pl) {
     Rays* r = pl->rays;
-    pl->blk_off.assign(2 * r->n_pairs + 1, 0);
+    const int G = pl->G, P = r->n_pol;
+    pl->bun_off.assign(r->n_pairs + 1, 0);
+    pl->bun_len_h.clear();
+    pl->bun_base_h.clear();
+    int64_t base = 0;
     for (int a = 0; a < r->n_pairs; ++a) {
-        const int64_t lanes = (int64_t)(r->ray_off[a + 1] - r->ray_off[a]) * pl->G;
-        const int64_t blocks = (lanes + kBlock - 1) / kBlock;
-        for (int d = 0; d < 2; ++d) {
-            const int pd = 2 * a + d;
-            LC_CHECK(pl->blk_off[pd] + blocks < INT32_MAX, LC_ERR_UNSUPPORTED, "sweep grid too large");
-            pl->blk_off[pd + 1] = pl->blk_off[pd] + (int)blocks;
+        const int r0 = r->ray_off[a], Ka = r->ray_off[a + 1] - r0;
+        const int64_t lanes = (int64_t)Ka * G;
+        const int64_t nb = (lanes + kWave - 1) / kWave;
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t f0 = b * kWave, f1 = std::min(lanes, f0 + kWave) - 1;
+            int L = 0;
+            for (int64_t kl = f0 / G; kl <= f1 / G; ++kl)
+                L = std::max(L, r->seg_off[r0 + kl + 1] - r->seg_off[r0 + kl]);
+            pl->bun_len_h.push_back(L);
+            pl->bun_base_h.push_back(base);
+            base += (int64_t)L * P * kWave;
         }
+        LC_CHECK((int64_t)pl->bun_len_h.size() < INT32_MAX, LC_ERR_UNSUPPORTED, "too many bundles");
+        pl->bun_off[a + 1] = (int)pl->bun_len_h.size();
     }
-    pl->sweep_blocks = pl->blk_off.back();
+    pl->n_bun = (int64_t)pl->bun_len_h.size();
+    pl->half_elems = base;
+    const int64_t waves = 2 * pl->n_bun;
+    pl->sweep_blocks = (waves + kBlock / kWave - 1) / (kBlock / kWave);
+    LC_CHECK(pl->sweep_blocks < INT32_MAX, LC_ERR_UNSUPPORTED, "sweep grid too large");
     return LC_OK;
 }
 
@@ -303,8 +361,12 @@ lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, doub
     }
     LC_HIP(hipGetLastError());
     SweepArgs A{};
-    A.blk_off = pl->d_blk_off;
-    A.n_pd = 2 * r->n_pairs;
+    A.bun_off = pl->d_bun_off;
+    A.bun_len = pl->d_bun_len;
+    A.bun_base = pl->d_bun_base;
+    A.n_pairs = r->n_pairs;
+    A.n_bun = pl->n_bun;
+    A.half = pl->half_elems;
     A.n_blocks = pl->sweep_blocks;
     A.ray_off = r->d_ray_off;
     A.seg_off = r->d_seg_off;
