@@ -37,16 +37,20 @@ def sweep_algorithmic_bytes(solver, elem):
     upd = solver.updates_per_step()
     state = 2 * upd * elem
     geom = 2 * r.n_segments * (4 + elem)
-    coef = r.cells * G * (4 * elem)
+    coef = r.cells * G * (2 * elem)
     io = 2 * r.n_rays * 2 * r.n_pol * G * 8
     return state + geom + coef + io
 
 
 def run_gpu(prob, prec, steps, warmup):
     import torch
-    from paper_2305_11998_amd import driver, lc
+    from paper_2305_11998_amd import driver, lc, tune
     s = driver.Solver(prob, prec=prec)
     s.reset()
+    tuned = tune.tune(s, cache=None, verbose=True)
+    _say(f"tuning: unroll {tuned['sweep_unroll']}, entries {tuned['moments_entries']}")
+    s.reset()
+    s.tuning = tuned
     lc.lc_plan_profile(s.plan, False)
     for _ in range(warmup):
         s.bench_step()
@@ -127,6 +131,7 @@ def main():
     s32, ms32, sw32, mo32 = run_gpu(prob, lc.LC_F32, args.steps, args.warmup)
     _say(f"f32: {ms32 / args.steps:.3f} ms/step, sweep kernel {sw32:.3f} ms, moments {mo32:.3f} ms")
     m32 = s32.moments()
+    tun32 = {k: s32.tuning[k] for k in ("sweep_unroll", "moments_entries")}
     upd = s32.updates_per_step()
     alg32 = sweep_algorithmic_bytes(s32, 4)
     del s32
@@ -159,13 +164,13 @@ def main():
         "data": "synthetic (seeded Fleck-Cummings-type sharp-front temperature field)",
         "config": {"workload": "single problem, 256x256 cells on 6x6 cm, G=51 groups 0.001-30 keV, "
                                "128 directions (32 azimuths x 4 polar), spacing h/2, FP32 sweep with "
-                               "Kahan moments", "updates_per_step": upd},
+                               "Kahan moments", "updates_per_step": upd, "tuning": tun32},
         "fp64": {"value": value64, "ms_per_step": ms64 / args.steps, "sweep_kernel_ms": sw64,
                  "moments_kernel_ms": mo64},
         "fp32_vs_fp64_max_err": errs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweep<float,4,sym>", "kernel_ms": sw32,
+                     "kernel": "k_sweep<float,P=4,sym>", "kernel_ms": sw32,
                      "algorithmic_bytes_per_launch": alg32},
     }
     if not args.no_cpu_baseline:

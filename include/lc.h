@@ -220,6 +220,20 @@ lc_status lc_step(lc_plan_t plan, int32_t n_steps, const double* kappa, const do
                   double* bnd, void* stream);
 
 /*
+ * Launch tuning of a plan (chosen by the project's autotuner; any value works,
+ * results are bit-identical across settings of moments_entries and
+ * sweep_unroll).  sweep_unroll: segments of a characteristic whose loads are
+ * issued together, 1, 2 or 4; moments_entries: cell-list entries gathered
+ * together, 1, 2 or 4.  Setting the tuning drops the plan's captured graphs.
+ */
+typedef struct {
+    int32_t sweep_unroll;
+    int32_t moments_entries;
+} lc_tuning_t;
+lc_status lc_plan_set_tuning(lc_plan_t plan, const lc_tuning_t* tuning);
+lc_status lc_plan_get_tuning(lc_plan_t plan, lc_tuning_t* tuning);
+
+/*
  * Kernel timers (tracing).  lc_plan_profile(plan, 1) makes every following
  * eager lc_sweep / lc_moments record HIP events around its main kernel on the
  * caller's stream (not inside lc_step graphs); lc_plan_profile_read

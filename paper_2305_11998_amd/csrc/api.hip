@@ -52,6 +52,7 @@ void free_plan(Plan* pl) {
     if (pl->d_bun_off) (void)hipFree(pl->d_bun_off);
     if (pl->d_bun_len) (void)hipFree(pl->d_bun_len);
     if (pl->d_bun_base) (void)hipFree(pl->d_bun_base);
+    if (pl->d_ent_off) (void)hipFree(pl->d_ent_off);
     pl->magic = 0;
     delete pl;
 }
@@ -182,9 +183,11 @@ lc_status lc_build_rays(const lc_grid* grid, const lc_quad* quad, double h_moc, 
             }
     lc_status rc = build_geometry(r, st);
     if (rc == LC_OK) rc = dalloc(r->owned, &r->d_dirw, r->dirw.size());
+
     if (rc == LC_OK) {
         hipError_t e = hipMemcpy(r->d_dirw, r->dirw.data(), r->dirw.size() * sizeof(double),
                                  hipMemcpyHostToDevice);
+
         if (e != hipSuccess) {
             set_error("hipMemcpy failed: %s", hipGetErrorString(e));
             rc = LC_ERR_HIP;
@@ -251,11 +254,13 @@ lc_status lc_plan_create(lc_rays_t rays, int32_t G, int32_t prec, lc_plan_t* out
     pl->G = G;
     pl->prec = prec;
     pl->hdr_bytes = ((size_t)G * sizeof(int32_t) + 255) / 256 * 256;
+    pl->sweep_unroll = prec == LC_F32 ? 4 : 2;
+    pl->moments_entries = 2;
     lc_status rc = plan_init_sweep(pl);
     pl->value_bytes = (size_t)pl->half_elems * 2 * (prec == LC_F32 ? 4 : 8);
     hipError_t e = hipSuccess;
     if (rc == LC_OK) {
-        const size_t coef_bytes = (size_t)r->cells * G * (prec == LC_F32 ? 16 : 32);
+        const size_t coef_bytes = (size_t)r->cells * G * (prec == LC_F32 ? 8 : 16);
         const size_t nbun = (size_t)pl->n_bun;
         e = hipMalloc(&pl->d_coef, coef_bytes);
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_off), pl->bun_off.size() * sizeof(int));
@@ -274,6 +279,7 @@ lc_status lc_plan_create(lc_rays_t rays, int32_t G, int32_t prec, lc_plan_t* out
             rc = LC_ERR_ALLOC;
         }
     }
+    if (rc == LC_OK) rc = plan_init_moments(pl);
     if (rc != LC_OK) {
         free_plan(pl);
         return rc;
@@ -390,6 +396,29 @@ lc_status lc_step(lc_plan_t plan, int32_t n_steps, const double* kappa, const do
         pl->graphs.push_back({key, exec});
     }
     LC_HIP(hipGraphLaunch(exec, st));
+    return LC_OK;
+}
+
+lc_status lc_plan_set_tuning(lc_plan_t plan, const lc_tuning_t* t) {
+    Plan* pl = as_plan(plan);
+    LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
+    LC_ARG(t, "tuning is NULL");
+    auto ok = [](int v) { return v == 1 || v == 2 || v == 4; };
+    LC_ARG(ok(t->sweep_unroll) && ok(t->moments_entries), "tuning values must be 1, 2 or 4");
+    pl->sweep_unroll = t->sweep_unroll;
+    pl->moments_entries = t->moments_entries;
+    for (auto& g : pl->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    pl->graphs.clear();
+    return LC_OK;
+}
+
+lc_status lc_plan_get_tuning(lc_plan_t plan, lc_tuning_t* t) {
+    Plan* pl = as_plan(plan);
+    LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
+    LC_ARG(t, "tuning is NULL");
+    t->sweep_unroll = pl->sweep_unroll;
+    t->moments_entries = pl->moments_entries;
     return LC_OK;
 }
 

@@ -76,6 +76,9 @@ struct Rays {
     int2* d_csr_t = nullptr;          // [n_seg] position of the segment in the d = 0 and d = 1 traversal
     double* d_csr_w = nullptr;        // [n_seg] A_j / sum of A over C(i, m)
     float* d_csr_w32 = nullptr;
+    int2* d_gi = nullptr;             // [n_seg] {cell, position in the cell-major lists} (sweep record)
+    double2* d_gf64 = nullptr;        // [n_seg] {length, area weight} (sweep record)
+    float2* d_gf32 = nullptr;
     int* d_bmap = nullptr;            // [nb][n_pairs][2][2] first, end global ray leaving through b; -1 = incoming
     double* d_dirw = nullptr;         // [n_pairs][2][n_pol][kDirW]
     std::vector<void*> owned;         // every device allocation above
@@ -95,7 +98,9 @@ struct Plan {
     int prec = 0;
     size_t hdr_bytes = 0;             // state header (per-group scale exponents)
     size_t value_bytes = 0;
-    void* d_coef = nullptr;           // [cells][G] {kappa_t, emission/kappa_t, 1/(c dt kappa_t), 0}
+    void* d_coef = nullptr;           // [cells][G] {kappa_t, kappa B / kappa_t}
+    int sweep_unroll = 0;             // steps whose loads are issued together (1, 2, 4)
+    int moments_entries = 0;          // C(i, m) entries gathered together (1, 2, 4)
     // State layout: the lanes (k, g) of pair a, g fastest, are cut into
     // bundles of 64 (one wavefront each).  For traversal d and bundle B the
     // values [t][p][lane] (t = step along the traversal, padded to the
@@ -109,6 +114,8 @@ struct Plan {
     int* d_bun_off = nullptr;
     int* d_bun_len = nullptr;
     int64_t* d_bun_base = nullptr;
+    long long* d_ent_off = nullptr;   // [n_seg][4] state offsets of each C(i, m) entry
+    int tile = 1;                     // cell-tile side of the moments kernel
     int64_t sweep_blocks = 0;         // blocks of one sweep launch
     std::vector<GraphEntry> graphs;   // captured lc_step sequences
     hipStream_t capture = nullptr;    // stream used only to record graphs
@@ -156,11 +163,13 @@ lc_status launch_state_fill(Plan* pl, const double* field, void* state, hipStrea
 lc_status launch_state_export(Plan* pl, const void* state, double* out, hipStream_t st);
 lc_status build_geometry(Rays* r, hipStream_t st);
 lc_status plan_init_sweep(Plan* pl);
+lc_status plan_init_moments(Plan* pl);
 
 // Device pointers to the values of a state buffer (after its header).
 inline const void* state_values(const Plan* pl, const void* s) {
     return static_cast<const char*>(s) + pl->hdr_bytes;
 }
 inline void* state_values(const Plan* pl, void* s) { return static_cast<char*>(s) + pl->hdr_bytes; }
+
 
 }  // namespace lc

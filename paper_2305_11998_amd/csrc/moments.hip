@@ -4,6 +4,7 @@
 // the characteristic grid), so the sums are deterministic and need no atomics.
 // The float32 form accumulates with compensated (Kahan) sums and divides in
 // float64.
+#include <algorithm>
 #include <cmath>
 
 #include "lc_internal.hpp"
@@ -12,18 +13,14 @@ namespace lc {
 namespace {
 
 struct MomArgs {
-    const int* csr_off;
-    const int* csr_ray;     // ray of each entry
-    const int2* csr_t;      // its step in the d = 0 and d = 1 traversal
-    const void* csr_w;      // double or float
-    const int* ray_off;
-    const int* bun_off;
-    const int64_t* bun_base;
-    int64_t half;
-    const double* dirw;     // [n_pairs][2][P][kDirW]
-    const void* state;      // values
-    const int* e;           // per-group exponents of the state (float32 only)
-    int cells, G, n_pairs;
+    const int* csr_off;       // [cells * n_pairs + 1] cell-major lists C(i, m)
+    const long long* ent_off; // [n_seg][4] state offsets of each entry: d0 first/second bundle, d1 first/second
+    const void* csr_w;        // area weights A / sum A, double or float
+    const double* dirw;       // [n_pairs][2][P][kDirW]
+    const void* state;        // values
+    const int* e;             // per-group exponents of the state (float32 only)
+    int nx, ny, G, n_pairs, ts, tiles_x;
+    int64_t n_tiles;
     double inv_c;
     double* E;
     double* F;
@@ -47,62 +44,131 @@ template <> struct Acc<float> {
     __device__ double value() const { return (double)s - (double)c; }
 };
 
-template <typename T, int P>
-__global__ __launch_bounds__(kBlock) void k_cell_moments(MomArgs A) {
-    const int64_t lane = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Hardware hands workgroups to the 8 XCDs round-robin; give each XCD a
+// contiguous range of tiles so that neighbouring tiles share an L2.
+__device__ __forceinline__ int64_t xcd_logical_block(int64_t hw, int64_t n) {
+    const int64_t q = n >> 3, r = n & 7;
+    const int64_t x = hw & 7, i = hw >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// One workgroup per ts x ts tile of cells; lane (cell, g).  For each azimuth
+// pair the lane gathers the segment averages of the characteristics crossing
+// its cell (the C(i, m) list, in (k, s) order) with the area weights, giving
+// I_{i,m} for both traversals and every polar angle, then adds that pair's
+// contribution to the seven angular moments (compensated float32 or plain
+// float64 sums, fixed order).  A characteristic crosses several cells of a
+// tile in consecutive steps, whose state rows are adjacent in memory, so the
+// tile's lanes share the cache lines they fetch.
+template <typename T, int P, int kEnt>
+__global__ __launch_bounds__(1024) void k_cell_moments(MomArgs A) {
+    const int64_t tile = xcd_logical_block(blockIdx.x, A.n_tiles);
     const int G = A.G;
-    if (lane >= (int64_t)A.cells * G) return;
-    const int cell = (int)(lane / G);
-    const int g = (int)(lane - (int64_t)cell * G);
+    const int cl = threadIdx.x / G;
+    const int g = threadIdx.x - cl * G;
+    const int ts = A.ts;
+    if (cl >= ts * ts) return;
+    const int cx = (int)(tile % A.tiles_x) * ts + cl % ts;
+    const int cy = (int)(tile / A.tiles_x) * ts + cl / ts;
+    if (cx >= A.nx || cy >= A.ny) return;
+    const int cell = cy * A.nx + cx;
+    const int cells = A.nx * A.ny;
     const T* __restrict__ st = static_cast<const T*>(A.state);
     const T* __restrict__ cw = static_cast<const T*>(A.csr_w);
+    const long long* __restrict__ eo = A.ent_off;
     Acc<T> acc[7];
     for (int a = 0; a < A.n_pairs; ++a) {
         const int e0 = A.csr_off[(size_t)cell * A.n_pairs + a];
         const int e1 = A.csr_off[(size_t)cell * A.n_pairs + a + 1];
-        const int r0 = A.ray_off[a];
-        const int b0 = A.bun_off[a];
         T Iim[2 * P];
 #pragma unroll
         for (int q = 0; q < 2 * P; ++q) Iim[q] = (T)0;
-        for (int e = e0; e < e1; ++e) {
-            const int k = A.csr_ray[e];
-            const int2 tt = A.csr_t[e];
-            const T w = cw[e];
-            // bundle-major state: lane f = (k - r0) G + g of bundle b0 + f / 64
-            const int f = (k - r0) * G + g;
-            const T* row = st + (size_t)A.bun_base[b0 + f / kWave] + (f & (kWave - 1));
-            const T* r0p = row + (size_t)tt.x * P * kWave;
-            const T* r1p = row + (size_t)A.half + (size_t)tt.y * P * kWave;
+        for (int eb = e0; eb < e1; eb += kEnt) {
+            T w[kEnt];
+            size_t o[kEnt][2];
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                Iim[p] += w * __builtin_nontemporal_load(r0p + p * kWave);
-                Iim[P + p] += w * __builtin_nontemporal_load(r1p + p * kWave);
+            for (int u = 0; u < kEnt; ++u) {
+                const bool ok = eb + u < e1;
+                const int e = ok ? eb + u : e0;
+                w[u] = ok ? cw[e] : (T)0;
+                const long long* r = eo + (size_t)e * 4;
+                const long long oa = r[0];
+                const bool first = g < kWave - (int)(oa & (kWave - 1));
+                o[u][0] = (size_t)(first ? oa : r[1]) + g;
+                o[u][1] = (size_t)(first ? r[2] : r[3]) + g;
             }
+            T x[kEnt][2 * P];
+#pragma unroll
+            for (int u = 0; u < kEnt; ++u)
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    x[u][p] = st[o[u][0] + p * kWave];
+                    x[u][P + p] = st[o[u][1] + p * kWave];
+                }
+#pragma unroll
+            for (int u = 0; u < kEnt; ++u)
+#pragma unroll
+                for (int q = 0; q < 2 * P; ++q) Iim[q] += w[u] * x[u][q];
         }
+        T part[7];
+#pragma unroll
+        for (int c = 0; c < 7; ++c) part[c] = (T)0;
 #pragma unroll
         for (int q = 0; q < 2 * P; ++q) {
             const double* dw = A.dirw + ((size_t)a * 2 * P + q) * kDirW;   // q = d * P + p
 #pragma unroll
-            for (int c = 0; c < 7; ++c) acc[c].add((T)dw[c] * Iim[q]);
+            for (int c = 0; c < 7; ++c) part[c] += (T)dw[c] * Iim[q];
         }
+#pragma unroll
+        for (int c = 0; c < 7; ++c) acc[c].add(part[c]);
     }
     double sc = 1.0;
     if (sizeof(T) == 4) sc = ldexp(1.0, A.e[g]);
     const double Phi = acc[0].value() * sc;
-    const size_t o = (size_t)g * A.cells + cell;
+    const size_t o = (size_t)g * cells + cell;
     if (A.E) A.E[o] = Phi * A.inv_c;
     if (A.F) {
-        A.F[((size_t)g * 2 + 0) * A.cells + cell] = acc[1].value() * sc;
-        A.F[((size_t)g * 2 + 1) * A.cells + cell] = acc[2].value() * sc;
+        A.F[((size_t)g * 2 + 0) * cells + cell] = acc[1].value() * sc;
+        A.F[((size_t)g * 2 + 1) * cells + cell] = acc[2].value() * sc;
     }
     if (A.f) {
         const bool z = Phi == 0.0;
         const double inv = z ? 0.0 : 1.0 / Phi;
-        A.f[((size_t)g * 4 + 0) * A.cells + cell] = z ? 1.0 / 3 : acc[3].value() * sc * inv;
-        A.f[((size_t)g * 4 + 1) * A.cells + cell] = z ? 0.0 : acc[4].value() * sc * inv;
-        A.f[((size_t)g * 4 + 2) * A.cells + cell] = z ? 1.0 / 3 : acc[5].value() * sc * inv;
-        A.f[((size_t)g * 4 + 3) * A.cells + cell] = z ? 1.0 / 3 : acc[6].value() * sc * inv;
+        A.f[((size_t)g * 4 + 0) * cells + cell] = z ? 1.0 / 3 : acc[3].value() * sc * inv;
+        A.f[((size_t)g * 4 + 1) * cells + cell] = z ? 0.0 : acc[4].value() * sc * inv;
+        A.f[((size_t)g * 4 + 2) * cells + cell] = z ? 1.0 / 3 : acc[5].value() * sc * inv;
+        A.f[((size_t)g * 4 + 3) * cells + cell] = z ? 1.0 / 3 : acc[6].value() * sc * inv;
+    }
+}
+
+// Offsets of every C(i, m) entry into the bundle-major state of a plan:
+// lanes g < 64 - (first & 63) lie in the bundle of the ray's group 0, the rest
+// in the next bundle.
+__global__ void k_entry_offsets(const int* __restrict__ csr_off, const int* __restrict__ csr_ray,
+                                const int2* __restrict__ csr_t, const int* __restrict__ ray_off,
+                                const int* __restrict__ bun_off, const int64_t* __restrict__ bun_base,
+                                int64_t n_keys, int n_pairs, int G, int P, int64_t half, long long* out) {
+    const int64_t key = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (key >= n_keys) return;
+    const int a = (int)(key % n_pairs);
+    for (int e = csr_off[key]; e < csr_off[key + 1]; ++e) {
+        const int k = csr_ray[e];
+        const int2 t = csr_t[e];
+        const int f0 = (k - ray_off[a]) * G;
+        const int B0 = bun_off[a] + f0 / kWave;
+        const int lane0 = f0 & (kWave - 1);
+        const int64_t step = (int64_t)P * kWave;
+        long long* o = out + (size_t)e * 4;
+        o[0] = bun_base[B0] + t.x * step + lane0;
+        o[2] = half + bun_base[B0] + t.y * step + lane0;
+        if (lane0 + G > kWave) {
+            const int split = kWave - lane0;
+            o[1] = bun_base[B0 + 1] + t.x * step - split;
+            o[3] = half + bun_base[B0 + 1] + t.y * step - split;
+        } else {
+            o[1] = o[0];
+            o[3] = o[2];
+        }
     }
 }
 
@@ -179,19 +245,28 @@ __global__ __launch_bounds__(kBlock) void k_boundary(BndArgs A) {
     out[7] = z ? 1.0 / 3 : Syy / S;
 }
 
+template <typename T, int P>
+void launch_cell_moments_e(int ent, const MomArgs& A, hipStream_t st) {
+    const int threads = (A.ts * A.ts * A.G + kWave - 1) / kWave * kWave;
+    dim3 grid((unsigned)A.n_tiles), block(threads);
+    switch (ent) {
+        case 1: hipLaunchKernelGGL((k_cell_moments<T, P, 1>), grid, block, 0, st, A); break;
+        case 4: hipLaunchKernelGGL((k_cell_moments<T, P, 4>), grid, block, 0, st, A); break;
+        default: hipLaunchKernelGGL((k_cell_moments<T, P, 2>), grid, block, 0, st, A); break;
+    }
+}
+
 template <typename T>
-lc_status launch_cell_moments_p(int P, const MomArgs& A, hipStream_t st) {
-    const int64_t lanes = (int64_t)A.cells * A.G;
-    dim3 grid((unsigned)((lanes + kBlock - 1) / kBlock)), block(kBlock);
+lc_status launch_cell_moments_p(int P, int ent, const MomArgs& A, hipStream_t st) {
     switch (P) {
-        case 1: hipLaunchKernelGGL((k_cell_moments<T, 1>), grid, block, 0, st, A); break;
-        case 2: hipLaunchKernelGGL((k_cell_moments<T, 2>), grid, block, 0, st, A); break;
-        case 3: hipLaunchKernelGGL((k_cell_moments<T, 3>), grid, block, 0, st, A); break;
-        case 4: hipLaunchKernelGGL((k_cell_moments<T, 4>), grid, block, 0, st, A); break;
-        case 5: hipLaunchKernelGGL((k_cell_moments<T, 5>), grid, block, 0, st, A); break;
-        case 6: hipLaunchKernelGGL((k_cell_moments<T, 6>), grid, block, 0, st, A); break;
-        case 7: hipLaunchKernelGGL((k_cell_moments<T, 7>), grid, block, 0, st, A); break;
-        case 8: hipLaunchKernelGGL((k_cell_moments<T, 8>), grid, block, 0, st, A); break;
+        case 1: launch_cell_moments_e<T, 1>(ent, A, st); break;
+        case 2: launch_cell_moments_e<T, 2>(ent, A, st); break;
+        case 3: launch_cell_moments_e<T, 3>(ent, A, st); break;
+        case 4: launch_cell_moments_e<T, 4>(ent, A, st); break;
+        case 5: launch_cell_moments_e<T, 5>(ent, A, st); break;
+        case 6: launch_cell_moments_e<T, 6>(ent, A, st); break;
+        case 7: launch_cell_moments_e<T, 7>(ent, A, st); break;
+        case 8: launch_cell_moments_e<T, 8>(ent, A, st); break;
         default:
             set_error("n_pol = %d not supported (1..8)", P);
             return LC_ERR_UNSUPPORTED;
@@ -202,6 +277,28 @@ lc_status launch_cell_moments_p(int P, const MomArgs& A, hipStream_t st) {
 
 }  // namespace
 
+lc_status plan_init_moments(Plan* pl) {
+    Rays* r = pl->rays;
+    const int64_t n_keys = (int64_t)r->cells * r->n_pairs;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&pl->d_ent_off),
+                             std::max<size_t>((size_t)r->n_seg, 1) * 4 * sizeof(long long));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc of the moment offsets failed: %s", hipGetErrorString(e));
+        return LC_ERR_ALLOC;
+    }
+    hipLaunchKernelGGL(k_entry_offsets, dim3((unsigned)((n_keys + kBlock - 1) / kBlock)), dim3(kBlock), 0, 0,
+                       r->d_csr_off, r->d_csr_ray, r->d_csr_t, r->d_ray_off, pl->d_bun_off, pl->d_bun_base,
+                       n_keys, r->n_pairs, pl->G, r->n_pol, pl->half_elems, pl->d_ent_off);
+    LC_HIP(hipGetLastError());
+    LC_HIP(hipDeviceSynchronize());
+    // tile side: the largest power of two whose tile of cells x groups fits a workgroup
+    int ts = 1;
+    while ((int64_t)(2 * ts) * (2 * ts) * pl->G <= 1024) ts *= 2;
+    pl->tile = ts;
+    return LC_OK;
+}
+
 lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, const double* I_in,
                          double c, double* E, double* F, double* f, double* bnd, hipStream_t st) {
     Rays* r = pl->rays;
@@ -209,17 +306,16 @@ lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, cons
     if (E || F || f) {
         MomArgs A{};
         A.csr_off = r->d_csr_off;
-        A.csr_ray = r->d_csr_ray;
-        A.csr_t = r->d_csr_t;
-        A.ray_off = r->d_ray_off;
-        A.bun_off = pl->d_bun_off;
-        A.bun_base = pl->d_bun_base;
-        A.half = pl->half_elems;
+        A.ent_off = pl->d_ent_off;
         A.csr_w = f32 ? static_cast<const void*>(r->d_csr_w32) : static_cast<const void*>(r->d_csr_w);
         A.dirw = r->d_dirw;
         A.state = state_values(pl, state);
         A.e = static_cast<const int*>(state);
-        A.cells = r->cells;
+        A.nx = r->nx;
+        A.ny = r->ny;
+        A.ts = pl->tile;
+        A.tiles_x = (r->nx + pl->tile - 1) / pl->tile;
+        A.n_tiles = (int64_t)A.tiles_x * ((r->ny + pl->tile - 1) / pl->tile);
         A.G = pl->G;
         A.n_pairs = r->n_pairs;
         A.inv_c = 1.0 / c;
@@ -228,8 +324,8 @@ lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, cons
         A.f = f;
         lc_status rc = prof_begin(pl, pl->ev_mom, st);
         if (rc) return rc;
-        rc = f32 ? launch_cell_moments_p<float>(r->n_pol, A, st)
-                 : launch_cell_moments_p<double>(r->n_pol, A, st);
+        rc = f32 ? launch_cell_moments_p<float>(r->n_pol, pl->moments_entries, A, st)
+                 : launch_cell_moments_p<double>(r->n_pol, pl->moments_entries, A, st);
         if (rc) return rc;
         rc = prof_end(pl, pl->ev_mom, st);
         if (rc) return rc;

@@ -129,13 +129,13 @@ lc_status launch_state_fill(Plan* pl, const double* field, void* state, hipStrea
     const SlotArgs A = slot_args(pl);
     const unsigned nb = (unsigned)(2 * pl->n_bun);
     if (pl->prec == LC_F32) {
+        float* v = static_cast<float*>(state_values(pl, state));
         hipLaunchKernelGGL(k_field_scale, dim3(G), dim3(kBlock), 0, st, field, r->cells, e);
-        hipLaunchKernelGGL(k_fill<float>, dim3(nb), dim3(kBlock), 0, st, A, field, e,
-                           static_cast<float*>(state_values(pl, state)));
+        hipLaunchKernelGGL(k_fill<float>, dim3(nb), dim3(kBlock), 0, st, A, field, e, v);
     } else {
+        double* v = static_cast<double*>(state_values(pl, state));
         hipLaunchKernelGGL(k_zero_int, dim3((G + kBlock - 1) / kBlock), dim3(kBlock), 0, st, e, G);
-        hipLaunchKernelGGL(k_fill<double>, dim3(nb), dim3(kBlock), 0, st, A, field, e,
-                           static_cast<double*>(state_values(pl, state)));
+        hipLaunchKernelGGL(k_fill<double>, dim3(nb), dim3(kBlock), 0, st, A, field, e, v);
     }
     LC_HIP(hipGetLastError());
     return LC_OK;

@@ -19,9 +19,9 @@
 namespace lc {
 namespace {
 
-template <typename T> struct Coef;
-template <> struct Coef<double> { double kt, a, b, pad; };
-template <> struct Coef<float> { float kt, a, b, pad; };
+// Cell record of eq. (11): kappa_t and the emission kappa B / kappa_t; the
+// remaining coefficient 1/(c dt kappa_t) is formed in the sweep.
+template <typename T> struct alignas(2 * sizeof(T)) Coef { T kt, a; };
 
 struct SweepArgs {
     const int* bun_off;      // [n_pairs + 1] first bundle of each pair
@@ -34,14 +34,16 @@ struct SweepArgs {
     const int* ray_off;
     const int* seg_off;
     const int* face;
-    const int* cell;
-    const void* len;         // double or float [n_seg]
+    const int2* gi;          // [n_seg] {cell, position in the cell-major lists}
+    const void* gf;          // [n_seg] {length, area weight} as double2 or float2
     const void* coef;        // Coef<T> [cells][G]
     const void* prev;        // state values
     void* next;
     const double* I_in;      // [nb][M][G]
     double* I_exit;          // [n_rays][2][P][G] or null
+    const int* e_prev;       // per-group exponent of the old state (float32 only)
     const int* e_new;        // per-group exponent of the new state (float32 only)
+    double inv_cdt;          // 1 / (c dt)
     int G, n_az, M;
     double inv_sinz[kMaxPol];
 };
@@ -93,6 +95,13 @@ __device__ __forceinline__ Att<double> attenuate(double tau) {
     return {E, D, al, 1.0 - al};
 }
 
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { using type = float2; };
+template <> struct Vec2<double> { using type = double2; };
+
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+
 template <typename T>
 __device__ __forceinline__ T ldg_stream(const T* p) { return __builtin_nontemporal_load(p); }
 template <typename T>
@@ -127,20 +136,23 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
     const int n = active ? nk : 0;
     const int L = A.bun_len[B];
     const int az = a + d * (A.n_az >> 1);
-    const T* __restrict__ len = static_cast<const T*>(A.len);
-    const int* __restrict__ cellv = A.cell;
+    using T2 = typename Vec2<T>::type;
+    const int2* __restrict__ gi = A.gi;
+    const T2* __restrict__ gf = static_cast<const T2*>(A.gf);
     const Coef<T>* __restrict__ coef = static_cast<const Coef<T>*>(A.coef);
     const size_t boff = (size_t)d * A.half + (size_t)A.bun_base[B] + lane;
     const T* __restrict__ xin = static_cast<const T*>(A.prev) + boff;
     T* __restrict__ xout = static_cast<T*>(A.next) + boff;
     constexpr int SP = P * kWave;              // elements per step of a bundle
 
-    double sc_in = 1.0, sc_out = 1.0;
+    double sc_in = 1.0, sc_out = 1.0, cb = A.inv_cdt;
     if (sizeof(T) == 4) {
         const int e = A.e_new[g];
         sc_in = ldexp(1.0, -e);
         sc_out = ldexp(1.0, e);
+        cb = ldexp(A.inv_cdt, A.e_prev[g] - e);   // old-state scale folded into 1/(c dt)
     }
+    const T cbt = (T)cb;
     T isz[P];
     T I[P];
     const int face_in = A.face[2 * k + d];
@@ -156,17 +168,18 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
     };
     auto srow = [&](int t) -> const T* { return xin + (size_t)(t < L ? t : L - 1) * SP; };
 
-    int ci1[U];
-    T l0[U], l1[U];
+    int2 gi1[U];
+    T2 gf0[U], gf1[U];
     Coef<T> c0[U];
     T x0[U][P];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int j0 = seg(u), j1 = seg(U + u);
-        l0[u] = len[j0];
-        c0[u] = coef[(size_t)cellv[j0] * G + g];
-        ci1[u] = cellv[j1];
-        l1[u] = len[j1];
+        const int2 g0 = gi[j0];
+        gf0[u] = gf[j0];
+        c0[u] = coef[(size_t)g0.x * G + g];
+        gi1[u] = gi[j1];
+        gf1[u] = gf[j1];
         const T* r = srow(u);
 #pragma unroll
         for (int p = 0; p < P; ++p) x0[u][p] = ldg_stream(r + p * kWave);
@@ -174,23 +187,24 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
     for (int t0 = 0; t0 < L; t0 += U) {
         Coef<T> c1[U];
         T x1[U][P];
-        int ci2[U];
-        T l2[U];
+        int2 gi2[U];
+        T2 gf2[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            c1[u] = coef[(size_t)ci1[u] * G + g];
+            c1[u] = coef[(size_t)gi1[u].x * G + g];
             const T* r = srow(t0 + U + u);
 #pragma unroll
             for (int p = 0; p < P; ++p) x1[u][p] = ldg_stream(r + p * kWave);
             const int j2 = seg(t0 + 2 * U + u);
-            ci2[u] = cellv[j2];
-            l2[u] = len[j2];
+            gi2[u] = gi[j2];
+            gf2[u] = gf[j2];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + u;
             const bool live = t < n;
-            const T ktl = c0[u].kt * l0[u];
+            const T ktl = c0[u].kt * gf0[u].x;
+            const T b = cbt * recip(c0[u].kt);                      // 1/(c dt kappa_t)
             Att<T> at[P];
 #pragma unroll
             for (int p = 0; p < P; ++p) {
@@ -201,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
             T* o = xout + (size_t)t * SP;
 #pragma unroll
             for (int p = 0; p < P; ++p) {
-                const T S = c0[u].a + c0[u].b * x0[u][p];             // Q / kappa_t
+                const T S = c0[u].a + b * x0[u][p];                   // Q / kappa_t
                 const T Io = at[p].E * I[p] + at[p].D * S;            // eq. (12)
                 const T Ib = at[p].al * I[p] + at[p].be * Io;         // segment average
                 if (live) stg_stream(o + p * kWave, Ib);
@@ -211,9 +225,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             c0[u] = c1[u];
-            l0[u] = l1[u];
-            l1[u] = l2[u];
-            ci1[u] = ci2[u];
+            gf0[u] = gf1[u];
+            gi1[u] = gi2[u];
+            gf1[u] = gf2[u];
 #pragma unroll
             for (int p = 0; p < P; ++p) x0[u][p] = x1[u][p];
         }
@@ -225,31 +239,23 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
     }
 }
 
-// Coefficients of eq. (11) per (cell, g): kappa_t, kappa B / kappa_t and
-// 1/(c dt kappa_t), so that Q / kappa_t = a + b I_bar^{n-1}.  float32 tables
-// carry the per-group power-of-two scales of the old and new state.
+// Coefficients of eq. (11) per (cell, g): kappa_t = kappa + 1/(c dt) and
+// a = kappa B / kappa_t, so that Q / kappa_t = a + I_bar^{n-1} / (c dt kappa_t).
+// float32 tables carry the per-group power-of-two scale of the new state.
 template <typename T>
 __global__ void k_coef(const double* __restrict__ kappa, const double* __restrict__ planck,
-                       double c_dt, int cells, int G, const int* __restrict__ e_prev,
-                       const int* __restrict__ e_new, Coef<T>* coef) {
+                       double c_dt, int cells, int G, const int* __restrict__ e_new, Coef<T>* coef) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)cells * G) return;
     const int g = (int)(i / cells);
     const int c = (int)(i - (int64_t)g * cells);
     const double kap = kappa[i];
-    const double inv = 1.0 / c_dt;
-    const double kt = kap + inv;
+    const double kt = kap + 1.0 / c_dt;
     double a = kap * planck[i] / kt;
-    double b = inv / kt;
-    if (sizeof(T) == 4) {
-        a = ldexp(a, -e_new[g]);
-        b = ldexp(b, e_prev[g] - e_new[g]);
-    }
+    if (sizeof(T) == 4) a = ldexp(a, -e_new[g]);
     Coef<T> r;
     r.kt = (T)kt;
     r.a = (T)a;
-    r.b = (T)b;
-    r.pad = (T)0;
     coef[(size_t)c * G + g] = r;
 }
 
@@ -277,14 +283,22 @@ __global__ void k_scale(const double* __restrict__ planck, const double* __restr
     }
 }
 
-template <typename T, int P>
-lc_status launch_sweep_t(Plan* pl, const SweepArgs& A, bool sym, hipStream_t st) {
+template <typename T, int P, int U>
+void launch_sweep_u(const Plan* pl, const SweepArgs& A, bool sym, hipStream_t st) {
     dim3 grid((unsigned)pl->sweep_blocks), block(kBlock);
-    lc_status rc = prof_begin(pl, pl->ev_sweep, st);
-    if (rc) return rc;
-    constexpr int U = sizeof(T) == 4 ? 4 : 2;
     if (sym) hipLaunchKernelGGL((k_sweep<T, P, true, U>), grid, block, 0, st, A);
     else hipLaunchKernelGGL((k_sweep<T, P, false, U>), grid, block, 0, st, A);
+}
+
+template <typename T, int P>
+lc_status launch_sweep_t(Plan* pl, const SweepArgs& A, bool sym, hipStream_t st) {
+    lc_status rc = prof_begin(pl, pl->ev_sweep, st);
+    if (rc) return rc;
+    switch (pl->sweep_unroll) {
+        case 1: launch_sweep_u<T, P, 1>(pl, A, sym, st); break;
+        case 2: launch_sweep_u<T, P, 2>(pl, A, sym, st); break;
+        default: launch_sweep_u<T, P, 4>(pl, A, sym, st); break;
+    }
     LC_HIP(hipGetLastError());
     return prof_end(pl, pl->ev_sweep, st);
 }
@@ -352,11 +366,11 @@ lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, doub
         hipLaunchKernelGGL(k_scale, dim3(G), dim3(kBlock), 0, st, planck, I_in, r->cells, G,
                            (int64_t)r->nb * r->n_az * r->n_pol, e_prev, e_new);
         hipLaunchKernelGGL(k_coef<float>, dim3(nblk((int64_t)r->cells * G)), dim3(kBlock), 0, st,
-                           kappa, planck, c_dt, r->cells, G, e_prev, e_new,
+                           kappa, planck, c_dt, r->cells, G, e_new,
                            static_cast<Coef<float>*>(pl->d_coef));
     } else {
         hipLaunchKernelGGL(k_coef<double>, dim3(nblk((int64_t)r->cells * G)), dim3(kBlock), 0, st,
-                           kappa, planck, c_dt, r->cells, G, nullptr, nullptr,
+                           kappa, planck, c_dt, r->cells, G, nullptr,
                            static_cast<Coef<double>*>(pl->d_coef));
     }
     LC_HIP(hipGetLastError());
@@ -371,14 +385,17 @@ lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, doub
     A.ray_off = r->d_ray_off;
     A.seg_off = r->d_seg_off;
     A.face = r->d_face;
-    A.cell = r->d_cell;
-    A.len = f32 ? static_cast<const void*>(r->d_len32) : static_cast<const void*>(r->d_len);
+    A.gi = r->d_gi;
+    A.gf = f32 ? static_cast<const void*>(r->d_gf32) : static_cast<const void*>(r->d_gf64);
     A.coef = pl->d_coef;
     A.prev = state_values(pl, state_prev);
     A.next = state_values(pl, state_new);
+
     A.I_in = I_in;
     A.I_exit = I_exit;
+    A.e_prev = e_prev;
     A.e_new = e_new;
+    A.inv_cdt = 1.0 / c_dt;
     A.G = G;
     A.n_az = r->n_az;
     A.M = r->n_az * r->n_pol;

@@ -49,6 +49,10 @@ class lc_rays_info_t(C.Structure):
                 ("h_moc", C.c_double)]
 
 
+class lc_tuning_t(C.Structure):
+    _fields_ = [("sweep_unroll", C.c_int32), ("moments_entries", C.c_int32)]
+
+
 class lc_problem_t(C.Structure):
     _fields_ = [("plan", C.c_void_p), ("kappa", C.c_void_p), ("planck", C.c_void_p),
                 ("material_stride", C.c_int64), ("c_dt", C.c_double), ("state_a", C.c_void_p),
@@ -72,6 +76,8 @@ _SIGS = {
     "lc_sweep": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_moments": ([_vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_step": ([_vp, _i32, _vp, _vp, _i64, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "lc_plan_set_tuning": ([_vp, C.POINTER(lc_tuning_t)], C.c_int),
+    "lc_plan_get_tuning": ([_vp, C.POINTER(lc_tuning_t)], C.c_int),
     "lc_plan_profile": ([_vp, _i32], C.c_int),
     "lc_plan_profile_read": ([_vp, _vp], C.c_int),
     "lc_batch_create": ([_i32, C.POINTER(lc_problem_t), C.POINTER(_vp)], C.c_int),
@@ -251,6 +257,17 @@ def lc_moments(plan: Plan, state, c, E=None, F=None, f=None, bnd=None, I_exit=No
                            _dev(F, 2 * plan.n_field, name="F", optional=True),
                            _dev(f, 4 * plan.n_field, name="f", optional=True),
                            _dev(bnd, plan.G * r.nb * 8, name="bnd", optional=True), _stream(stream)))
+
+
+def lc_plan_set_tuning(plan: Plan, sweep_unroll: int, moments_entries: int):
+    t = lc_tuning_t(int(sweep_unroll), int(moments_entries))
+    _check(_lib.lc_plan_set_tuning(plan.handle, C.byref(t)))
+
+
+def lc_plan_get_tuning(plan: Plan):
+    t = lc_tuning_t()
+    _check(_lib.lc_plan_get_tuning(plan.handle, C.byref(t)))
+    return dict(sweep_unroll=t.sweep_unroll, moments_entries=t.moments_entries)
 
 
 def lc_plan_profile(plan: Plan, enable: bool):

@@ -1,0 +1,90 @@
+"""Autotuner for the launch parameters of a plan.
+
+For a plan and its buffers it times every candidate of each tunable launch
+parameter with the library's own kernel timers (HIP events around the sweep
+and the cell-moment kernels) and keeps the fastest.  The sweep parameter and
+the moments parameter are independent, so each is searched on its own.
+Results are cached in a JSON file keyed by the shape class of the problem
+(precision, groups, polar angles, azimuth pairs, and the cell and segment
+counts rounded to powers of two), so a second problem of the same class
+reuses them without timing.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+from . import lc
+
+CANDIDATES = (1, 2, 4)
+DEFAULT_CACHE = os.environ.get(
+    "LC_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "lc_tuning.json"))
+
+
+def shape_key(plan) -> str:
+    r = plan.rays
+    b = lambda x: int(round(math.log2(max(int(x), 1))))
+    return (f"prec{plan.prec}-G{plan.G}-P{r.n_pol}-A{r.n_pairs}-"
+            f"c{b(r.cells)}-s{b(r.n_segments)}")
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(path, data):
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass
+
+
+def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool = False):
+    """Pick (sweep_unroll, moments_entries) for ``solver.plan`` by timing
+    ``reps`` eager steps per candidate.  Leaves the chosen tuning set on the
+    plan and returns it with the measured times (ms per launch)."""
+    import torch
+    plan = solver.plan
+    key = shape_key(plan)
+    db = _load(cache) if cache else {}
+    if key in db:
+        t = db[key]
+        lc.lc_plan_set_tuning(plan, t["sweep_unroll"], t["moments_entries"])
+        return dict(t, cached=True, key=key)
+    times = {}
+    # the two parameters act on different kernels: vary one with the other at 2
+    combos = sorted({(u, 2) for u in CANDIDATES} | {(2, e) for e in CANDIDATES})
+    for u, e in combos:
+        lc.lc_plan_set_tuning(plan, u, e)
+        solver.bench_step()                       # warm
+        torch.cuda.synchronize()
+        lc.lc_plan_profile_read(plan)
+        lc.lc_plan_profile(plan, True)
+        for _ in range(reps):
+            solver.bench_step()
+        torch.cuda.synchronize()
+        sw, nsw, mo, nmo = lc.lc_plan_profile_read(plan)
+        lc.lc_plan_profile(plan, False)
+        times[(u, e)] = (sw / max(nsw, 1), mo / max(nmo, 1))
+        if verbose:
+            print(f"  tune {key}: unroll {u} entries {e}: sweep {times[(u, e)][0]:.3f} ms, "
+                  f"moments {times[(u, e)][1]:.3f} ms", flush=True)
+    best_u = min(CANDIDATES, key=lambda u: times[(u, 2)][0])
+    best_e = min(CANDIDATES, key=lambda e: times[(2, e)][1])
+    lc.lc_plan_set_tuning(plan, best_u, best_e)
+    res = dict(sweep_unroll=best_u, moments_entries=best_e,
+               sweep_ms={str(k): v[0] for k, v in times.items()},
+               moments_ms={str(k): v[1] for k, v in times.items()})
+    if cache:
+        db[key] = res
+        _save(cache, db)
+    return dict(res, cached=False, key=key)
