@@ -1,29 +1,250 @@
-// Batched form: many independent problems in one persistent launch per phase.
+// Batched form: many independent problems advanced together.  Each phase of a
+// time step is one launch over all problems: the coefficient prologue, one
+// persistent sweep kernel whose wavefronts pull (problem, wavefront) items
+// from an integer counter, one persistent cell-moment kernel pulling
+// (problem, tile) items, and the boundary factors.  Items are ordered by
+// problem cost, largest first, so the small problems fill the tail.  The step
+// sequence is captured in a HIP graph per step count and replayed.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
 #include "lc_internal.hpp"
+
+namespace lc {
+namespace {
+
+struct Batch {
+    uint32_t magic = 0;
+    int n = 0, prec = 0, pm = 1, unroll = 4, ent = 2;
+    double c = 0.0;
+    std::vector<lc_problem_t> probs;
+    std::vector<Plan*> plans;
+    std::vector<char> h_mom;            // host copy of the moment records [2][n]
+    void* d_sweep_args = nullptr;       // [2][n] sweep records (parity of the step)
+    void* d_coef_args = nullptr;        // [n]
+    void* d_mom_args = nullptr;         // [2][n]
+    void* d_bnd_args = nullptr;         // [n]
+    int2* d_sweep_items = nullptr;
+    int2* d_mom_items = nullptr;
+    int64_t n_sweep_items = 0, n_mom_items = 0;
+    int* d_counters = nullptr;          // [2]
+    int64_t coef_lanes = 0, scale_blocks = 0, bnd_lanes = 0;
+    std::vector<GraphEntry> graphs;
+    hipStream_t capture = nullptr;
+};
+
+Batch* as_batch(lc_batch_t b) {
+    Batch* p = reinterpret_cast<Batch*>(b);
+    return (p && p->magic == kBatchMagic) ? p : nullptr;
+}
+
+void free_batch(Batch* b) {
+    if (!b) return;
+    for (auto& g : b->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    for (void* p : {b->d_sweep_args, b->d_coef_args, b->d_mom_args, b->d_bnd_args,
+                    static_cast<void*>(b->d_sweep_items), static_cast<void*>(b->d_mom_items),
+                    static_cast<void*>(b->d_counters)})
+        if (p) (void)hipFree(p);
+    b->magic = 0;
+    delete b;
+}
+
+lc_status upload(void** dst, const void* src, size_t bytes) {
+    hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 1));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+        return LC_ERR_ALLOC;
+    }
+    LC_HIP(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+    return LC_OK;
+}
+
+// Moment records for the current speed of light.
+lc_status build_moment_args(Batch* b, double c) {
+    const size_t mb = mom_args_bytes(), bb = bnd_args_bytes();
+    b->h_mom.assign(2 * b->n * mb, 0);
+    std::vector<char> hb(b->n * bb);
+    int64_t lane_off = 0;
+    for (int q = 0; q < b->n; ++q) {
+        const lc_problem_t& P = b->probs[q];
+        Plan* pl = b->plans[q];
+        for (int parity = 0; parity < 2; ++parity) {
+            const void* st = parity ? P.state_a : P.state_b;      // the state the step writes
+            std::vector<char> tmp(bb);
+            make_moment_args(pl, st, P.I_exit, P.I_in, c, P.E, P.F, P.f, P.bnd, lane_off,
+                             b->h_mom.data() + (parity * b->n + q) * mb, tmp.data());
+            if (parity == 0) std::memcpy(hb.data() + q * bb, tmp.data(), bb);
+        }
+        if (P.bnd) lane_off += (int64_t)pl->rays->nb * pl->G;
+    }
+    b->bnd_lanes = lane_off;
+    if (!b->d_mom_args) {
+        lc_status rc = upload(&b->d_mom_args, b->h_mom.data(), b->h_mom.size());
+        if (rc) return rc;
+        rc = upload(&b->d_bnd_args, hb.data(), hb.size());
+        if (rc) return rc;
+    } else {
+        LC_HIP(hipMemcpy(b->d_mom_args, b->h_mom.data(), b->h_mom.size(), hipMemcpyHostToDevice));
+        LC_HIP(hipMemcpy(b->d_bnd_args, hb.data(), hb.size(), hipMemcpyHostToDevice));
+    }
+    b->c = c;
+    return LC_OK;
+}
+
+}  // namespace
+}  // namespace lc
 
 using namespace lc;
 
 extern "C" {
 
 lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_batch_t* out) {
-    (void)n_problems;
-    (void)problems;
-    if (out) *out = nullptr;
-    set_error("batched form not available in this build");
-    return LC_ERR_UNSUPPORTED;
+    LC_ARG(out, "out is NULL");
+    *out = nullptr;
+    LC_ARG(n_problems >= 1 && problems, "need at least one problem");
+    int prec = -1, pm = 1;
+    for (int q = 0; q < n_problems; ++q) {
+        const lc_problem_t& P = problems[q];
+        Plan* pl = as_plan(P.plan);
+        LC_CHECK(pl, LC_ERR_STATE, "problem %d: invalid plan handle", q);
+        LC_ARG(P.kappa && P.planck && P.state_a && P.state_b && P.I_in && P.I_exit,
+               "problem %d: kappa, planck, states, I_in and I_exit are required", q);
+        LC_ARG(P.state_a != P.state_b, "problem %d: state_a and state_b must be distinct", q);
+        LC_ARG(std::isfinite(P.c_dt) && P.c_dt > 0.0, "problem %d: c_dt must be finite and > 0", q);
+        LC_ARG(P.material_stride >= 0, "problem %d: material_stride must be >= 0", q);
+        if (prec < 0) prec = pl->prec;
+        LC_ARG(pl->prec == prec, "all problems of a batch must use one precision");
+        while (pm < pl->rays->n_pol) pm *= 2;
+    }
+    Batch* b = new (std::nothrow) Batch();
+    LC_CHECK(b, LC_ERR_ALLOC, "host allocation failed");
+    b->magic = kBatchMagic;
+    b->n = n_problems;
+    b->prec = prec;
+    b->pm = pm;
+    b->probs.assign(problems, problems + n_problems);
+    for (int q = 0; q < n_problems; ++q) b->plans.push_back(as_plan(problems[q].plan));
+    b->unroll = b->plans[0]->sweep_unroll;
+    b->ent = b->plans[0]->moments_entries;
+    lc_status rc = LC_OK;
+    // argument records
+    const size_t sb = sweep_args_bytes(), cb = coef_args_bytes();
+    std::vector<char> hs(2 * n_problems * sb), hc(n_problems * cb);
+    int64_t lane_off = 0, blk_off = 0;
+    for (int q = 0; q < n_problems; ++q) {
+        const lc_problem_t& P = problems[q];
+        Plan* pl = b->plans[q];
+        std::vector<char> two(2 * sb);
+        make_batch_args(pl, P.c_dt, P.kappa, P.planck, P.material_stride, P.state_a, P.state_b, P.I_in,
+                        P.I_exit, lane_off, blk_off, two.data(), hc.data() + q * cb);
+        std::memcpy(hs.data() + q * sb, two.data(), sb);
+        std::memcpy(hs.data() + (n_problems + q) * sb, two.data() + sb, sb);
+        lane_off += (int64_t)pl->rays->cells * pl->G;
+        blk_off += pl->G;
+    }
+    b->coef_lanes = lane_off;
+    b->scale_blocks = blk_off;
+    // work items, problems in decreasing cost
+    std::vector<int> order(n_problems);
+    std::iota(order.begin(), order.end(), 0);
+    auto cost = [&](int q) { return (double)b->plans[q]->half_elems; };
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+    std::vector<int2> si, mi;
+    for (int q : order) {
+        const Plan* pl = b->plans[q];
+        for (int64_t w = 0; w < 2 * pl->n_bun; ++w) si.push_back(make_int2(q, (int)w));
+        for (int64_t t = 0; t < moment_tiles(pl); ++t) mi.push_back(make_int2(q, (int)t));
+    }
+    b->n_sweep_items = (int64_t)si.size();
+    b->n_mom_items = (int64_t)mi.size();
+    if (rc == LC_OK) rc = upload(&b->d_sweep_args, hs.data(), hs.size());
+    if (rc == LC_OK) rc = upload(&b->d_coef_args, hc.data(), hc.size());
+    if (rc == LC_OK) rc = upload(reinterpret_cast<void**>(&b->d_sweep_items), si.data(), si.size() * sizeof(int2));
+    if (rc == LC_OK) rc = upload(reinterpret_cast<void**>(&b->d_mom_items), mi.data(), mi.size() * sizeof(int2));
+    if (rc == LC_OK) {
+        int zero[2] = {0, 0};
+        rc = upload(reinterpret_cast<void**>(&b->d_counters), zero, sizeof(zero));
+    }
+    if (rc == LC_OK) rc = build_moment_args(b, 1.0);
+    if (rc == LC_OK) {
+        hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            set_error("hipStreamCreate failed: %s", hipGetErrorString(e));
+            rc = LC_ERR_HIP;
+        }
+    }
+    if (rc != LC_OK) {
+        free_batch(b);
+        return rc;
+    }
+    *out = reinterpret_cast<lc_batch_t>(b);
+    return LC_OK;
 }
 
 lc_status lc_batch_step(lc_batch_t batch, int32_t n_steps, double c, void* stream) {
-    (void)batch;
-    (void)n_steps;
-    (void)c;
-    (void)stream;
-    set_error("batched form not available in this build");
-    return LC_ERR_UNSUPPORTED;
+    Batch* b = as_batch(batch);
+    LC_CHECK(b, LC_ERR_STATE, "invalid batch handle");
+    LC_ARG(n_steps >= 1, "n_steps must be >= 1");
+    LC_ARG(std::isfinite(c) && c > 0.0, "c must be finite and > 0");
+    for (int q = 0; q < b->n; ++q) LC_CHECK(as_plan(b->probs[q].plan), LC_ERR_STATE, "problem %d: plan freed", q);
+    if (c != b->c) {
+        lc_status rc = build_moment_args(b, c);
+        if (rc) return rc;
+        for (auto& g : b->graphs)
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        b->graphs.clear();
+    }
+    hipGraphExec_t exec = nullptr;
+    for (auto& g : b->graphs)
+        if (g.key.size() == 1 && g.key[0] == (uintptr_t)n_steps) exec = g.exec;
+    if (!exec) {
+        LC_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+        lc_status rc = LC_OK;
+        const size_t sb = sweep_args_bytes(), mb = mom_args_bytes();
+        for (int t = 0; t < n_steps && rc == LC_OK; ++t) {
+            const int parity = t & 1;
+            rc = launch_zero_counters(b->d_counters, 2, b->capture);
+            if (rc == LC_OK)
+                rc = launch_prologue_batch(b->prec, b->d_coef_args, b->n, b->coef_lanes, b->scale_blocks, t,
+                                           b->capture);
+            if (rc == LC_OK)
+                rc = launch_sweep_batch(b->prec, b->pm, b->unroll,
+                                        static_cast<char*>(b->d_sweep_args) + parity * b->n * sb,
+                                        b->d_sweep_items, b->n_sweep_items, b->d_counters, b->capture);
+            if (rc == LC_OK && t == n_steps - 1) {
+                rc = launch_moments_batch(b->prec, b->pm, b->ent,
+                                          static_cast<char*>(b->d_mom_args) + parity * b->n * mb,
+                                          b->d_mom_items, b->n_mom_items, b->d_counters + 1, b->capture);
+                if (rc == LC_OK && b->bnd_lanes > 0)
+                    rc = launch_boundary_batch(b->d_bnd_args, b->n, b->bnd_lanes, b->capture);
+            }
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(b->capture, &graph);
+        if (rc != LC_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        LC_CHECK(e == hipSuccess && graph, LC_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        LC_CHECK(e == hipSuccess, LC_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+        b->graphs.push_back({{(uintptr_t)n_steps}, exec});
+    }
+    LC_HIP(hipGraphLaunch(exec, static_cast<hipStream_t>(stream)));
+    return LC_OK;
 }
 
 lc_status lc_batch_free(lc_batch_t batch) {
-    (void)batch;
+    if (!batch) return LC_OK;
+    Batch* b = as_batch(batch);
+    LC_CHECK(b, LC_ERR_STATE, "invalid batch handle");
+    free_batch(b);
     return LC_OK;
 }
 

@@ -165,6 +165,28 @@ lc_status build_geometry(Rays* r, hipStream_t st);
 lc_status plan_init_sweep(Plan* pl);
 lc_status plan_init_moments(Plan* pl);
 
+// Batched form: argument records (built on the host, copied to the device)
+// and launchers of the persistent kernels.
+size_t sweep_args_bytes();
+size_t coef_args_bytes();
+size_t mom_args_bytes();
+size_t bnd_args_bytes();
+void make_batch_args(Plan* pl, double c_dt, const double* kappa, const double* planck, int64_t stride,
+                     void* state_a, void* state_b, const double* I_in, double* I_exit, int64_t lane_off,
+                     int64_t blk_off, void* sweep_out2, void* coef_out);
+void make_moment_args(Plan* pl, const void* state, const double* I_exit, const double* I_in, double c,
+                      double* E, double* F, double* f, double* bnd, int64_t bnd_lane_off, void* mom_out,
+                      void* bnd_out);
+int64_t moment_tiles(const Plan* pl);
+lc_status launch_prologue_batch(int prec, const void* coef_args, int n, int64_t lanes, int64_t scale_blocks,
+                                int t, hipStream_t st);
+lc_status launch_zero_counters(int* c, int n, hipStream_t st);
+lc_status launch_sweep_batch(int prec, int pm, int unroll, const void* args, const int2* items, int64_t n_items,
+                             int* counter, hipStream_t st);
+lc_status launch_moments_batch(int prec, int pm, int ent, const void* args, const int2* items, int64_t n_items,
+                               int* counter, hipStream_t st);
+lc_status launch_boundary_batch(const void* args, int n, int64_t lanes, hipStream_t st);
+
 // Device pointers to the values of a state buffer (after its header).
 inline const void* state_values(const Plan* pl, const void* s) {
     return static_cast<const char*>(s) + pl->hdr_bytes;

@@ -6,6 +6,7 @@
 // float64.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "lc_internal.hpp"
 
@@ -19,7 +20,7 @@ struct MomArgs {
     const double* dirw;       // [n_pairs][2][P][kDirW]
     const void* state;        // values
     const int* e;             // per-group exponents of the state (float32 only)
-    int nx, ny, G, n_pairs, ts, tiles_x;
+    int nx, ny, G, P, n_pairs, ts, tiles_x;
     int64_t n_tiles;
     double inv_c;
     double* E;
@@ -59,13 +60,13 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t hw, int64_t n) {
 // contribution to the seven angular moments (compensated float32 or plain
 // float64 sums, fixed order).  A characteristic crosses several cells of a
 // tile in consecutive steps, whose state rows are adjacent in memory, so the
-// tile's lanes share the cache lines they fetch.
-template <typename T, int P, int kEnt>
-__global__ __launch_bounds__(1024) void k_cell_moments(MomArgs A) {
-    const int64_t tile = xcd_logical_block(blockIdx.x, A.n_tiles);
+// tile's lanes share the cache lines they fetch.  PM bounds the polar count.
+template <typename T, int PM, int kEnt>
+__device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int tid) {
     const int G = A.G;
-    const int cl = threadIdx.x / G;
-    const int g = threadIdx.x - cl * G;
+    const int P = A.P;
+    const int cl = tid / G;
+    const int g = tid - cl * G;
     const int ts = A.ts;
     if (cl >= ts * ts) return;
     const int cx = (int)(tile % A.tiles_x) * ts + cl % ts;
@@ -80,9 +81,11 @@ __global__ __launch_bounds__(1024) void k_cell_moments(MomArgs A) {
     for (int a = 0; a < A.n_pairs; ++a) {
         const int e0 = A.csr_off[(size_t)cell * A.n_pairs + a];
         const int e1 = A.csr_off[(size_t)cell * A.n_pairs + a + 1];
-        T Iim[2 * P];
+        T Iim[2][PM];
 #pragma unroll
-        for (int q = 0; q < 2 * P; ++q) Iim[q] = (T)0;
+        for (int d = 0; d < 2; ++d)
+#pragma unroll
+            for (int p = 0; p < PM; ++p) Iim[d][p] = (T)0;
         for (int eb = e0; eb < e1; eb += kEnt) {
             T w[kEnt];
             size_t o[kEnt][2];
@@ -97,28 +100,32 @@ __global__ __launch_bounds__(1024) void k_cell_moments(MomArgs A) {
                 o[u][0] = (size_t)(first ? oa : r[1]) + g;
                 o[u][1] = (size_t)(first ? r[2] : r[3]) + g;
             }
-            T x[kEnt][2 * P];
+            T x[kEnt][2][PM];
 #pragma unroll
             for (int u = 0; u < kEnt; ++u)
 #pragma unroll
-                for (int p = 0; p < P; ++p) {
-                    x[u][p] = st[o[u][0] + p * kWave];
-                    x[u][P + p] = st[o[u][1] + p * kWave];
-                }
+                for (int d = 0; d < 2; ++d)
+#pragma unroll
+                    for (int p = 0; p < PM; ++p) x[u][d][p] = p < P ? st[o[u][d] + p * kWave] : (T)0;
 #pragma unroll
             for (int u = 0; u < kEnt; ++u)
 #pragma unroll
-                for (int q = 0; q < 2 * P; ++q) Iim[q] += w[u] * x[u][q];
+                for (int d = 0; d < 2; ++d)
+#pragma unroll
+                    for (int p = 0; p < PM; ++p) Iim[d][p] += w[u] * x[u][d][p];
         }
         T part[7];
 #pragma unroll
         for (int c = 0; c < 7; ++c) part[c] = (T)0;
 #pragma unroll
-        for (int q = 0; q < 2 * P; ++q) {
-            const double* dw = A.dirw + ((size_t)a * 2 * P + q) * kDirW;   // q = d * P + p
+        for (int d = 0; d < 2; ++d)
 #pragma unroll
-            for (int c = 0; c < 7; ++c) part[c] += (T)dw[c] * Iim[q];
-        }
+            for (int p = 0; p < PM; ++p) {
+                if (p >= P) continue;
+                const double* dw = A.dirw + (((size_t)a * 2 + d) * P + p) * kDirW;
+#pragma unroll
+                for (int c = 0; c < 7; ++c) part[c] += (T)dw[c] * Iim[d][p];
+            }
 #pragma unroll
         for (int c = 0; c < 7; ++c) acc[c].add(part[c]);
     }
@@ -138,6 +145,29 @@ __global__ __launch_bounds__(1024) void k_cell_moments(MomArgs A) {
         A.f[((size_t)g * 4 + 1) * cells + cell] = z ? 0.0 : acc[4].value() * sc * inv;
         A.f[((size_t)g * 4 + 2) * cells + cell] = z ? 1.0 / 3 : acc[5].value() * sc * inv;
         A.f[((size_t)g * 4 + 3) * cells + cell] = z ? 1.0 / 3 : acc[6].value() * sc * inv;
+    }
+}
+
+template <typename T, int PM, int kEnt>
+__global__ __launch_bounds__(1024) void k_cell_moments(MomArgs A) {
+    moments_tile<T, PM, kEnt>(A, xcd_logical_block(blockIdx.x, A.n_tiles), threadIdx.x);
+}
+
+// Batched form: persistent workgroups take (problem, tile) items from an
+// integer counter in item-list order.
+template <typename T, int PM, int kEnt>
+__global__ __launch_bounds__(1024) void k_cell_moments_batch(const MomArgs* __restrict__ probs,
+                                                             const int2* __restrict__ items, int64_t n_items,
+                                                             int* counter) {
+    __shared__ int s_it;
+    for (;;) {
+        if (threadIdx.x == 0) s_it = atomicAdd(counter, 1);
+        __syncthreads();
+        const int it = s_it;
+        __syncthreads();
+        if (it >= n_items) break;
+        const int2 item = items[it];
+        moments_tile<T, PM, kEnt>(probs[item.x], item.y, threadIdx.x);
     }
 }
 
@@ -180,13 +210,13 @@ struct BndArgs {
     const double* I_in;     // [nb][M][G]
     int nx, ny, nb, G, n_pairs, n_az, P;
     double* bnd;            // [G][nb][8]
+    int64_t lane_off;       // first flat lane of this problem in a batched launch
 };
 
 // Boundary factors per (face b, group g): the outgoing intensity of a
 // direction is the width-weighted mean exit intensity of the characteristics
 // leaving through b; incoming directions take I_in.
-__global__ __launch_bounds__(kBlock) void k_boundary(BndArgs A) {
-    const int lane = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void boundary_lane(const BndArgs& A, int lane) {
     const int G = A.G;
     if (lane >= A.nb * G) return;
     const int b = lane / G;
@@ -245,6 +275,21 @@ __global__ __launch_bounds__(kBlock) void k_boundary(BndArgs A) {
     out[7] = z ? 1.0 / 3 : Syy / S;
 }
 
+__global__ __launch_bounds__(kBlock) void k_boundary(BndArgs A) {
+    boundary_lane(A, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_boundary_batch(const BndArgs* __restrict__ P, int n, int64_t lanes) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= lanes) return;
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (P[mid].lane_off <= i) lo = mid; else hi = mid;
+    }
+    boundary_lane(P[lo], (int)(i - P[lo].lane_off));
+}
+
 template <typename T, int P>
 void launch_cell_moments_e(int ent, const MomArgs& A, hipStream_t st) {
     const int threads = (A.ts * A.ts * A.G + kWave - 1) / kWave * kWave;
@@ -292,9 +337,9 @@ lc_status plan_init_moments(Plan* pl) {
                        n_keys, r->n_pairs, pl->G, r->n_pol, pl->half_elems, pl->d_ent_off);
     LC_HIP(hipGetLastError());
     LC_HIP(hipDeviceSynchronize());
-    // tile side: the largest power of two whose tile of cells x groups fits a workgroup
+    // tile side: the largest square tile of cells x groups that fits a workgroup
     int ts = 1;
-    while ((int64_t)(2 * ts) * (2 * ts) * pl->G <= 1024) ts *= 2;
+    while ((int64_t)(ts + 1) * (ts + 1) * pl->G <= 1024) ++ts;
     pl->tile = ts;
     return LC_OK;
 }
@@ -313,6 +358,7 @@ lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, cons
         A.e = static_cast<const int*>(state);
         A.nx = r->nx;
         A.ny = r->ny;
+        A.P = r->n_pol;
         A.ts = pl->tile;
         A.tiles_x = (r->nx + pl->tile - 1) / pl->tile;
         A.n_tiles = (int64_t)A.tiles_x * ((r->ny + pl->tile - 1) / pl->tile);
@@ -349,6 +395,115 @@ lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, cons
         hipLaunchKernelGGL(k_boundary, dim3((lanes + kBlock - 1) / kBlock), dim3(kBlock), 0, st, B);
         LC_HIP(hipGetLastError());
     }
+    return LC_OK;
+}
+
+namespace {
+
+template <typename T, int PM, int kEnt>
+lc_status launch_moments_batch_e(const void* args, const int2* items, int64_t n_items, int* counter,
+                                 hipStream_t st) {
+    static int grid = 0;
+    if (!grid) {
+        int dev = 0, cus = 0, per_cu = 0;
+        LC_HIP(hipGetDevice(&dev));
+        LC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        LC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(&k_cell_moments_batch<T, PM, kEnt>), 1024, 0));
+        grid = std::max(1, cus * std::max(per_cu, 1));
+    }
+    hipLaunchKernelGGL((k_cell_moments_batch<T, PM, kEnt>), dim3(grid), dim3(1024), 0, st,
+                       static_cast<const MomArgs*>(args), items, n_items, counter);
+    LC_HIP(hipGetLastError());
+    return LC_OK;
+}
+
+template <typename T, int PM>
+lc_status launch_moments_batch_p(int ent, const void* args, const int2* items, int64_t n, int* counter,
+                                 hipStream_t st) {
+    switch (ent) {
+        case 1: return launch_moments_batch_e<T, PM, 1>(args, items, n, counter, st);
+        case 4: return launch_moments_batch_e<T, PM, 4>(args, items, n, counter, st);
+        default: return launch_moments_batch_e<T, PM, 2>(args, items, n, counter, st);
+    }
+}
+
+}  // namespace
+
+size_t mom_args_bytes() { return sizeof(MomArgs); }
+size_t bnd_args_bytes() { return sizeof(BndArgs); }
+
+// Host copies of the moment and boundary records of one problem of a batch;
+// the moments read `state`.
+void make_moment_args(Plan* pl, const void* state, const double* I_exit, const double* I_in, double c,
+                      double* E, double* F, double* f, double* bnd, int64_t bnd_lane_off, void* mom_out,
+                      void* bnd_out) {
+    Rays* r = pl->rays;
+    const bool f32 = pl->prec == LC_F32;
+    MomArgs A{};
+    A.csr_off = r->d_csr_off;
+    A.ent_off = pl->d_ent_off;
+    A.csr_w = f32 ? static_cast<const void*>(r->d_csr_w32) : static_cast<const void*>(r->d_csr_w);
+    A.dirw = r->d_dirw;
+    A.state = state_values(pl, state);
+    A.e = static_cast<const int*>(state);
+    A.nx = r->nx;
+    A.ny = r->ny;
+    A.P = r->n_pol;
+    A.ts = pl->tile;
+    A.tiles_x = (r->nx + pl->tile - 1) / pl->tile;
+    A.n_tiles = (int64_t)A.tiles_x * ((r->ny + pl->tile - 1) / pl->tile);
+    A.G = pl->G;
+    A.n_pairs = r->n_pairs;
+    A.inv_c = 1.0 / c;
+    A.E = E;
+    A.F = F;
+    A.f = f;
+    std::memcpy(mom_out, &A, sizeof(A));
+    BndArgs B{};
+    B.bmap = r->d_bmap;
+    B.width = r->d_width;
+    B.dirw = r->d_dirw;
+    B.I_exit = I_exit;
+    B.I_in = I_in;
+    B.nx = r->nx;
+    B.ny = r->ny;
+    B.nb = r->nb;
+    B.G = pl->G;
+    B.n_pairs = r->n_pairs;
+    B.n_az = r->n_az;
+    B.P = r->n_pol;
+    B.bnd = bnd;
+    B.lane_off = bnd_lane_off;
+    std::memcpy(bnd_out, &B, sizeof(B));
+}
+
+int64_t moment_tiles(const Plan* pl) {
+    const Rays* r = pl->rays;
+    return (int64_t)((r->nx + pl->tile - 1) / pl->tile) * ((r->ny + pl->tile - 1) / pl->tile);
+}
+
+lc_status launch_moments_batch(int prec, int pm, int ent, const void* args, const int2* items, int64_t n_items,
+                               int* counter, hipStream_t st) {
+    const bool f32 = prec == LC_F32;
+    switch (pm) {
+        case 1: return f32 ? launch_moments_batch_p<float, 1>(ent, args, items, n_items, counter, st)
+                           : launch_moments_batch_p<double, 1>(ent, args, items, n_items, counter, st);
+        case 2: return f32 ? launch_moments_batch_p<float, 2>(ent, args, items, n_items, counter, st)
+                           : launch_moments_batch_p<double, 2>(ent, args, items, n_items, counter, st);
+        case 4: return f32 ? launch_moments_batch_p<float, 4>(ent, args, items, n_items, counter, st)
+                           : launch_moments_batch_p<double, 4>(ent, args, items, n_items, counter, st);
+        case 8: return f32 ? launch_moments_batch_p<float, 8>(ent, args, items, n_items, counter, st)
+                           : launch_moments_batch_p<double, 8>(ent, args, items, n_items, counter, st);
+    }
+    set_error("batched moments: polar bound %d not supported", pm);
+    return LC_ERR_UNSUPPORTED;
+}
+
+lc_status launch_boundary_batch(const void* args, int n, int64_t lanes, hipStream_t st) {
+    hipLaunchKernelGGL(k_boundary_batch, dim3((unsigned)((lanes + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       static_cast<const BndArgs*>(args), n, lanes);
+    LC_HIP(hipGetLastError());
     return LC_OK;
 }
 

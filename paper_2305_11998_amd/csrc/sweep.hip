@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstring>
 
 #include "lc_internal.hpp"
 
@@ -41,6 +42,8 @@ struct SweepArgs {
     void* next;
     const double* I_in;      // [nb][M][G]
     double* I_exit;          // [n_rays][2][P][G] or null
+    int P;                   // polar angles
+    int sym;                 // polar set mirror-symmetric
     const int* e_prev;       // per-group exponent of the old state (float32 only)
     const int* e_new;        // per-group exponent of the new state (float32 only)
     double inv_cdt;          // 1 / (c dt)
@@ -107,22 +110,25 @@ __device__ __forceinline__ T ldg_stream(const T* p) { return __builtin_nontempor
 template <typename T>
 __device__ __forceinline__ void stg_stream(T* p, T v) { __builtin_nontemporal_store(v, p); }
 
-// One wavefront per (traversal d, bundle B).  Lane (k, g) walks its
-// characteristic; step t reads the P stored values of the lane at
+// One wavefront per (traversal d, bundle B) of a problem.  Lane (k, g) walks
+// its characteristic; step t reads the P stored values of the lane at
 // [t][p][lane] of the bundle (one 64-lane contiguous run per p) and writes the
 // new ones at the same place.  Loads run one chunk of U steps ahead of the
 // arithmetic: the geometry two chunks ahead, the cell coefficients (which
 // depend on it) and the stored values one chunk ahead.
-template <typename T, int P, bool SYM, int U>
-__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
-    const int64_t lb = xcd_logical_block(blockIdx.x, A.n_blocks);
-    const int64_t w = lb * (kBlock / kWave) + (threadIdx.x / kWave);
-    const int lane = threadIdx.x & (kWave - 1);
-    if (w >= 2 * A.n_bun) return;
+//
+// Polar angles sit in PM register slots (PM >= P): lower slot i holds polar
+// p = i, upper slot i holds p = P - 1 - i, so that with a mirror-symmetric
+// polar set (mu_p = -mu_{P-1-p}, equal sin(zeta)) an upper slot reuses the
+// exponential and alpha of the lower slot with the same index.
+template <typename T, int PM, int U>
+__device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int lane) {
+    constexpr int NL = (PM + 1) / 2, NU = PM / 2, NS = NL + NU;
     const int d = w >= A.n_bun ? 1 : 0;
     const int64_t B = w - (d ? A.n_bun : 0);
     const int a = find_pair(A.bun_off, A.n_pairs, B);
     const int G = A.G;
+    const int P = A.P;
     const int r0 = A.ray_off[a];
     const int Ka = A.ray_off[a + 1] - r0;
     const int f = (int)(B - A.bun_off[a]) * kWave + lane;
@@ -143,7 +149,21 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
     const size_t boff = (size_t)d * A.half + (size_t)A.bun_base[B] + lane;
     const T* __restrict__ xin = static_cast<const T*>(A.prev) + boff;
     T* __restrict__ xout = static_cast<T*>(A.next) + boff;
-    constexpr int SP = P * kWave;              // elements per step of a bundle
+    const size_t SP = (size_t)P * kWave;       // elements per step of a bundle
+
+    int pol[NS];
+    bool val[NS];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        pol[i] = i;
+        val[i] = i < (P + 1) / 2;
+    }
+#pragma unroll
+    for (int i = 0; i < NU; ++i) {
+        pol[NL + i] = P - 1 - i;
+        val[NL + i] = i < P / 2;
+    }
+    const bool sym = A.sym;
 
     double sc_in = 1.0, sc_out = 1.0, cb = A.inv_cdt;
     if (sizeof(T) == 4) {
@@ -153,13 +173,13 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
         cb = ldexp(A.inv_cdt, A.e_prev[g] - e);   // old-state scale folded into 1/(c dt)
     }
     const T cbt = (T)cb;
-    T isz[P];
-    T I[P];
+    T isz[NS];
+    T I[NS];
     const int face_in = A.face[2 * k + d];
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-        isz[p] = (T)A.inv_sinz[p];
-        I[p] = (T)(A.I_in[((size_t)face_in * A.M + (size_t)az * P + p) * G + g] * sc_in);
+    for (int r = 0; r < NS; ++r) {
+        isz[r] = val[r] ? (T)A.inv_sinz[pol[r]] : (T)1;
+        I[r] = val[r] ? (T)(A.I_in[((size_t)face_in * A.M + (size_t)az * P + pol[r]) * G + g] * sc_in) : (T)0;
     }
     // segment index of step t (clamped into the characteristic)
     auto seg = [&](int t) -> int {
@@ -171,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
     int2 gi1[U];
     T2 gf0[U], gf1[U];
     Coef<T> c0[U];
-    T x0[U][P];
+    T x0[U][NS];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int j0 = seg(u), j1 = seg(U + u);
@@ -182,11 +202,11 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
         gf1[u] = gf[j1];
         const T* r = srow(u);
 #pragma unroll
-        for (int p = 0; p < P; ++p) x0[u][p] = ldg_stream(r + p * kWave);
+        for (int q = 0; q < NS; ++q) x0[u][q] = val[q] ? ldg_stream(r + pol[q] * kWave) : (T)0;
     }
     for (int t0 = 0; t0 < L; t0 += U) {
         Coef<T> c1[U];
-        T x1[U][P];
+        T x1[U][NS];
         int2 gi2[U];
         T2 gf2[U];
 #pragma unroll
@@ -194,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
             c1[u] = coef[(size_t)gi1[u].x * G + g];
             const T* r = srow(t0 + U + u);
 #pragma unroll
-            for (int p = 0; p < P; ++p) x1[u][p] = ldg_stream(r + p * kWave);
+            for (int q = 0; q < NS; ++q) x1[u][q] = val[q] ? ldg_stream(r + pol[q] * kWave) : (T)0;
             const int j2 = seg(t0 + 2 * U + u);
             gi2[u] = gi[j2];
             gf2[u] = gf[j2];
@@ -205,21 +225,22 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
             const bool live = t < n;
             const T ktl = c0[u].kt * gf0[u].x;
             const T b = cbt * recip(c0[u].kt);                      // 1/(c dt kappa_t)
-            Att<T> at[P];
+            Att<T> at[NS];
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const int q = (SYM && p >= (P + 1) / 2) ? (P - 1 - p) : p;
-                if (q == p) at[p] = attenuate(ktl * isz[p]);
-                else at[p] = at[q];
-            }
+            for (int i = 0; i < NL; ++i)
+                if (val[i]) at[i] = attenuate(ktl * isz[i]);
+#pragma unroll
+            for (int i = 0; i < NU; ++i)
+                if (val[NL + i]) at[NL + i] = sym ? at[i] : attenuate(ktl * isz[NL + i]);
             T* o = xout + (size_t)t * SP;
 #pragma unroll
-            for (int p = 0; p < P; ++p) {
-                const T S = c0[u].a + b * x0[u][p];                   // Q / kappa_t
-                const T Io = at[p].E * I[p] + at[p].D * S;            // eq. (12)
-                const T Ib = at[p].al * I[p] + at[p].be * Io;         // segment average
-                if (live) stg_stream(o + p * kWave, Ib);
-                I[p] = live ? Io : I[p];
+            for (int q = 0; q < NS; ++q) {
+                if (!val[q]) continue;
+                const T S = c0[u].a + b * x0[u][q];                   // Q / kappa_t
+                const T Io = at[q].E * I[q] + at[q].D * S;            // eq. (12)
+                const T Ib = at[q].al * I[q] + at[q].be * Io;         // segment average
+                if (live) stg_stream(o + pol[q] * kWave, Ib);
+                I[q] = live ? Io : I[q];
             }
         }
 #pragma unroll
@@ -229,13 +250,39 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
             gi1[u] = gi2[u];
             gf1[u] = gf2[u];
 #pragma unroll
-            for (int p = 0; p < P; ++p) x0[u][p] = x1[u][p];
+            for (int q = 0; q < NS; ++q) x0[u][q] = x1[u][q];
         }
     }
     if (A.I_exit && active) {
 #pragma unroll
-        for (int p = 0; p < P; ++p)
-            A.I_exit[((size_t)(2 * k + d) * P + p) * G + g] = (double)I[p] * sc_out;
+        for (int q = 0; q < NS; ++q)
+            if (val[q]) A.I_exit[((size_t)(2 * k + d) * P + pol[q]) * G + g] = (double)I[q] * sc_out;
+    }
+}
+
+template <typename T, int PM, int U>
+__global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
+    const int64_t lb = xcd_logical_block(blockIdx.x, A.n_blocks);
+    const int64_t w = lb * (kBlock / kWave) + (threadIdx.x / kWave);
+    if (w >= 2 * A.n_bun) return;
+    sweep_wave<T, PM, U>(A, w, threadIdx.x & (kWave - 1));
+}
+
+// Batched form: a persistent grid whose wavefronts take work items
+// (problem, wavefront of that problem) from an integer counter, in the order
+// of the item list (longest first).
+template <typename T, int PM, int U>
+__global__ __launch_bounds__(kBlock) void k_sweep_batch(const SweepArgs* __restrict__ probs,
+                                                        const int2* __restrict__ items, int64_t n_items,
+                                                        int* counter) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (;;) {
+        int it = 0;
+        if (lane == 0) it = atomicAdd(counter, 1);
+        it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
+        if (it >= n_items) break;
+        const int2 item = items[it];
+        sweep_wave<T, PM, U>(probs[item.x], item.y, lane);
     }
 }
 
@@ -283,37 +330,103 @@ __global__ void k_scale(const double* __restrict__ planck, const double* __restr
     }
 }
 
-template <typename T, int P, int U>
-void launch_sweep_u(const Plan* pl, const SweepArgs& A, bool sym, hipStream_t st) {
-    dim3 grid((unsigned)pl->sweep_blocks), block(kBlock);
-    if (sym) hipLaunchKernelGGL((k_sweep<T, P, true, U>), grid, block, 0, st, A);
-    else hipLaunchKernelGGL((k_sweep<T, P, false, U>), grid, block, 0, st, A);
+// ---- batched prologue -----------------------------------------------------------
+struct CoefArgs {
+    const double* kappa;     // step t at kappa + t * stride
+    const double* planck;
+    int64_t stride;
+    double c_dt;
+    int cells, G;
+    int64_t n_in;            // nb * M
+    const double* I_in;
+    const int* e_state[2];   // headers of state_a, state_b
+    void* coef;
+    int64_t lane_off;        // first flat lane of this problem (cells * G lanes)
+    int64_t blk_off;         // first block of this problem in the scale launch (G blocks)
+};
+
+__device__ __forceinline__ int find_prob(const CoefArgs* __restrict__ P, int n, int64_t v, bool blocks) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if ((blocks ? P[mid].blk_off : P[mid].lane_off) <= v) lo = mid; else hi = mid;
+    }
+    return lo;
 }
 
-template <typename T, int P>
-lc_status launch_sweep_t(Plan* pl, const SweepArgs& A, bool sym, hipStream_t st) {
+// Step t reads state (t % 2 == 0 ? a : b) and writes the other one.
+__global__ void k_scale_batch(const CoefArgs* __restrict__ P, int n, int t) {
+    __shared__ double sh[kBlock];
+    const int q = find_prob(P, n, blockIdx.x, true);
+    const CoefArgs& A = P[q];
+    const int g = (int)(blockIdx.x - A.blk_off);
+    const double* planck = A.planck + (int64_t)t * A.stride;
+    double m = 0.0;
+    for (int64_t i = threadIdx.x; i < A.cells; i += kBlock) m = fmax(m, fabs(planck[(int64_t)g * A.cells + i]));
+    for (int64_t i = threadIdx.x; i < A.n_in; i += kBlock) m = fmax(m, fabs(A.I_in[i * A.G + g]));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int* e_prev = A.e_state[t & 1];
+        int* e_new = const_cast<int*>(A.e_state[(t + 1) & 1]);
+        int e = e_prev[g];
+        if (sh[0] > 0.0 && isfinite(sh[0])) e = max(e, ilogb(sh[0]) + 1);
+        e_new[g] = e;
+    }
+}
+
+template <typename T>
+__global__ void k_coef_batch(const CoefArgs* __restrict__ P, int n, int64_t lanes, int t) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= lanes) return;
+    const int q = find_prob(P, n, i, false);
+    const CoefArgs& A = P[q];
+    const int64_t li = i - A.lane_off;
+    const int g = (int)(li / A.cells);
+    const int c = (int)(li - (int64_t)g * A.cells);
+    const double kap = A.kappa[(int64_t)t * A.stride + li];
+    const double kt = kap + 1.0 / A.c_dt;
+    double a = kap * A.planck[(int64_t)t * A.stride + li] / kt;
+    if (sizeof(T) == 4) a = ldexp(a, -A.e_state[(t + 1) & 1][g]);
+    Coef<T> r;
+    r.kt = (T)kt;
+    r.a = (T)a;
+    static_cast<Coef<T>*>(A.coef)[(size_t)c * A.G + g] = r;
+}
+
+__global__ void k_zero_counter(int* c, int n) {
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
+
+template <typename T, int PM>
+lc_status launch_sweep_t(Plan* pl, const SweepArgs& A, hipStream_t st) {
     lc_status rc = prof_begin(pl, pl->ev_sweep, st);
     if (rc) return rc;
+    dim3 grid((unsigned)pl->sweep_blocks), block(kBlock);
     switch (pl->sweep_unroll) {
-        case 1: launch_sweep_u<T, P, 1>(pl, A, sym, st); break;
-        case 2: launch_sweep_u<T, P, 2>(pl, A, sym, st); break;
-        default: launch_sweep_u<T, P, 4>(pl, A, sym, st); break;
+        case 1: hipLaunchKernelGGL((k_sweep<T, PM, 1>), grid, block, 0, st, A); break;
+        case 2: hipLaunchKernelGGL((k_sweep<T, PM, 2>), grid, block, 0, st, A); break;
+        default: hipLaunchKernelGGL((k_sweep<T, PM, 4>), grid, block, 0, st, A); break;
     }
     LC_HIP(hipGetLastError());
     return prof_end(pl, pl->ev_sweep, st);
 }
 
 template <typename T>
-lc_status launch_sweep_p(Plan* pl, const SweepArgs& A, bool sym, hipStream_t st) {
+lc_status launch_sweep_p(Plan* pl, const SweepArgs& A, hipStream_t st) {
     switch (pl->rays->n_pol) {
-        case 1: return launch_sweep_t<T, 1>(pl, A, sym, st);
-        case 2: return launch_sweep_t<T, 2>(pl, A, sym, st);
-        case 3: return launch_sweep_t<T, 3>(pl, A, sym, st);
-        case 4: return launch_sweep_t<T, 4>(pl, A, sym, st);
-        case 5: return launch_sweep_t<T, 5>(pl, A, sym, st);
-        case 6: return launch_sweep_t<T, 6>(pl, A, sym, st);
-        case 7: return launch_sweep_t<T, 7>(pl, A, sym, st);
-        case 8: return launch_sweep_t<T, 8>(pl, A, sym, st);
+        case 1: return launch_sweep_t<T, 1>(pl, A, st);
+        case 2: return launch_sweep_t<T, 2>(pl, A, st);
+        case 3: return launch_sweep_t<T, 3>(pl, A, st);
+        case 4: return launch_sweep_t<T, 4>(pl, A, st);
+        case 5: return launch_sweep_t<T, 5>(pl, A, st);
+        case 6: return launch_sweep_t<T, 6>(pl, A, st);
+        case 7: return launch_sweep_t<T, 7>(pl, A, st);
+        case 8: return launch_sweep_t<T, 8>(pl, A, st);
     }
     set_error("n_pol = %d not supported (1..8)", pl->rays->n_pol);
     return LC_ERR_UNSUPPORTED;
@@ -321,7 +434,129 @@ lc_status launch_sweep_p(Plan* pl, const SweepArgs& A, bool sym, hipStream_t st)
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+template <typename T, int PM, int U>
+lc_status launch_sweep_batch_u(const void* args, const int2* items, int64_t n_items, int* counter,
+                               hipStream_t st) {
+    static int grid = 0;
+    if (!grid) {
+        int dev = 0, cus = 0, per_cu = 0;
+        LC_HIP(hipGetDevice(&dev));
+        LC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        LC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_sweep_batch<T, PM, U>), kBlock, 0));
+        grid = std::max(1, cus * std::max(per_cu, 1));
+    }
+    hipLaunchKernelGGL((k_sweep_batch<T, PM, U>), dim3(grid), dim3(kBlock), 0, st,
+                       static_cast<const SweepArgs*>(args), items, n_items, counter);
+    LC_HIP(hipGetLastError());
+    return LC_OK;
+}
+
+template <typename T, int PM>
+lc_status launch_sweep_batch_p(int unroll, const void* args, const int2* items, int64_t n_items, int* counter,
+                               hipStream_t st) {
+    switch (unroll) {
+        case 1: return launch_sweep_batch_u<T, PM, 1>(args, items, n_items, counter, st);
+        case 2: return launch_sweep_batch_u<T, PM, 2>(args, items, n_items, counter, st);
+        default: return launch_sweep_batch_u<T, PM, 4>(args, items, n_items, counter, st);
+    }
+}
+
 }  // namespace
+
+size_t sweep_args_bytes() { return sizeof(SweepArgs); }
+size_t coef_args_bytes() { return sizeof(CoefArgs); }
+
+// Host copies of the argument records of one problem of a batch.
+void make_batch_args(Plan* pl, double c_dt, const double* kappa, const double* planck, int64_t stride,
+                     void* state_a, void* state_b, const double* I_in, double* I_exit, int64_t lane_off,
+                     int64_t blk_off, void* sweep_out2, void* coef_out) {
+    Rays* r = pl->rays;
+    const bool f32 = pl->prec == LC_F32;
+    for (int parity = 0; parity < 2; ++parity) {
+        void* prev = parity ? state_b : state_a;
+        void* next = parity ? state_a : state_b;
+        SweepArgs A{};
+        A.bun_off = pl->d_bun_off;
+        A.bun_len = pl->d_bun_len;
+        A.bun_base = pl->d_bun_base;
+        A.n_pairs = r->n_pairs;
+        A.n_bun = pl->n_bun;
+        A.half = pl->half_elems;
+        A.n_blocks = pl->sweep_blocks;
+        A.ray_off = r->d_ray_off;
+        A.seg_off = r->d_seg_off;
+        A.face = r->d_face;
+        A.gi = r->d_gi;
+        A.gf = f32 ? static_cast<const void*>(r->d_gf32) : static_cast<const void*>(r->d_gf64);
+        A.coef = pl->d_coef;
+        A.prev = state_values(pl, prev);
+        A.next = state_values(pl, next);
+        A.I_in = I_in;
+        A.I_exit = I_exit;
+        A.P = r->n_pol;
+        A.sym = r->sym ? 1 : 0;
+        A.e_prev = static_cast<const int*>(prev);
+        A.e_new = static_cast<const int*>(next);
+        A.inv_cdt = 1.0 / c_dt;
+        A.G = pl->G;
+        A.n_az = r->n_az;
+        A.M = r->n_az * r->n_pol;
+        for (int p = 0; p < r->n_pol; ++p) A.inv_sinz[p] = r->inv_sinz[p];
+        std::memcpy(static_cast<char*>(sweep_out2) + parity * sizeof(SweepArgs), &A, sizeof(A));
+    }
+    CoefArgs C{};
+    C.kappa = kappa;
+    C.planck = planck;
+    C.stride = stride;
+    C.c_dt = c_dt;
+    C.cells = r->cells;
+    C.G = pl->G;
+    C.n_in = (int64_t)r->nb * r->n_az * r->n_pol;
+    C.I_in = I_in;
+    C.e_state[0] = static_cast<const int*>(state_a);
+    C.e_state[1] = static_cast<const int*>(state_b);
+    C.coef = pl->d_coef;
+    C.lane_off = lane_off;
+    C.blk_off = blk_off;
+    std::memcpy(coef_out, &C, sizeof(C));
+}
+
+// Prologue of step t of a batch: per-group scales (float32) and coefficients.
+lc_status launch_prologue_batch(int prec, const void* coef_args, int n, int64_t lanes, int64_t scale_blocks,
+                                int t, hipStream_t st) {
+    const CoefArgs* P = static_cast<const CoefArgs*>(coef_args);
+    if (prec == LC_F32) {
+        hipLaunchKernelGGL(k_scale_batch, dim3((unsigned)scale_blocks), dim3(kBlock), 0, st, P, n, t);
+        hipLaunchKernelGGL(k_coef_batch<float>, dim3(nblk(lanes)), dim3(kBlock), 0, st, P, n, lanes, t);
+    } else {
+        hipLaunchKernelGGL(k_coef_batch<double>, dim3(nblk(lanes)), dim3(kBlock), 0, st, P, n, lanes, t);
+    }
+    LC_HIP(hipGetLastError());
+    return LC_OK;
+}
+
+lc_status launch_zero_counters(int* c, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, st, c, n);
+    LC_HIP(hipGetLastError());
+    return LC_OK;
+}
+
+lc_status launch_sweep_batch(int prec, int pm, int unroll, const void* args, const int2* items, int64_t n_items,
+                             int* counter, hipStream_t st) {
+    const bool f32 = prec == LC_F32;
+    switch (pm) {
+        case 1: return f32 ? launch_sweep_batch_p<float, 1>(unroll, args, items, n_items, counter, st)
+                           : launch_sweep_batch_p<double, 1>(unroll, args, items, n_items, counter, st);
+        case 2: return f32 ? launch_sweep_batch_p<float, 2>(unroll, args, items, n_items, counter, st)
+                           : launch_sweep_batch_p<double, 2>(unroll, args, items, n_items, counter, st);
+        case 4: return f32 ? launch_sweep_batch_p<float, 4>(unroll, args, items, n_items, counter, st)
+                           : launch_sweep_batch_p<double, 4>(unroll, args, items, n_items, counter, st);
+        case 8: return f32 ? launch_sweep_batch_p<float, 8>(unroll, args, items, n_items, counter, st)
+                           : launch_sweep_batch_p<double, 8>(unroll, args, items, n_items, counter, st);
+    }
+    set_error("batched sweep: polar bound %d not supported", pm);
+    return LC_ERR_UNSUPPORTED;
+}
 
 lc_status plan_init_sweep(Plan* pl) {
     Rays* r = pl->rays;
@@ -399,8 +634,10 @@ lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, doub
     A.G = G;
     A.n_az = r->n_az;
     A.M = r->n_az * r->n_pol;
+    A.P = r->n_pol;
+    A.sym = r->sym ? 1 : 0;
     for (int p = 0; p < r->n_pol; ++p) A.inv_sinz[p] = r->inv_sinz[p];
-    return f32 ? launch_sweep_p<float>(pl, A, r->sym, st) : launch_sweep_p<double>(pl, A, r->sym, st);
+    return f32 ? launch_sweep_p<float>(pl, A, st) : launch_sweep_p<double>(pl, A, st);
 }
 
 }  // namespace lc

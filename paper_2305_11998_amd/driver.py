@@ -106,3 +106,42 @@ class Solver:
         polar angles x groups."""
         r = self.rays
         return r.n_segments * 2 * r.n_pol * self.prob.G
+
+
+class BatchSolver:
+    """Many problems advanced together through the batched C entry points.
+    Each member keeps its own Solver (buffers, rays, plan); the batch handle
+    refers to their device buffers."""
+
+    def __init__(self, probs, prec=lc.LC_F32, c=None, tuning=None, static_material=False):
+        """static_material: every step uses the first step's material data
+        (then any number of steps may be taken)."""
+        self.solvers = [Solver(p, prec=prec, c=c) for p in probs]
+        if tuning is not None:
+            for s in self.solvers:
+                lc.lc_plan_set_tuning(s.plan, *tuning)
+        self.c = self.solvers[0].c
+        self.static = static_material
+        self.max_steps = None if static_material else min(s.prob.steps for s in self.solvers)
+        self.batch = lc.lc_batch_create([dict(
+            plan=s.plan, kappa=s.kappa, planck=s.planck, c_dt=s.prob.c_dt,
+            material_stride=0 if static_material else s.stride,
+            state_a=s.state[0], state_b=s.state[1], I_in=s.I_in, I_exit=s.I_exit, E=s.E, F=s.F,
+            f=s.f, bnd=s.bnd, n_steps_max=s.prob.steps) for s in self.solvers])
+
+    def reset(self):
+        for s in self.solvers:
+            s.reset()
+
+    def step(self, n):
+        """n steps from the states in state[0] (material steps 0 .. n-1)."""
+        if self.max_steps is not None and n > self.max_steps:
+            raise ValueError(f"only {self.max_steps} material steps are available")
+        lc.lc_batch_step(self.batch, n, self.c)
+        for s in self.solvers:
+            s.cur = n % 2
+            s.t = n
+
+    def updates_per_step(self):
+        return sum(s.updates_per_step() for s in self.solvers)
+

@@ -295,3 +295,55 @@ def lc_step(plan: Plan, n_steps, kappa, planck, c_dt, c, state_a, state_b, I_in,
                         _dev(F, 2 * plan.n_field, name="F", optional=True),
                         _dev(f, 4 * plan.n_field, name="f", optional=True),
                         _dev(bnd, plan.G * r.nb * 8, name="bnd", optional=True), _stream(stream)))
+
+
+class Batch:
+    """Owning wrapper of an ``lc_batch_t`` handle; keeps the problems' plans
+    and buffers alive."""
+
+    def __init__(self, handle, keep):
+        self.handle = handle
+        self._keep = keep
+
+    def free(self):
+        if self.handle:
+            _check(_lib.lc_batch_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def lc_batch_create(problems) -> Batch:
+    """problems: list of dicts with keys plan, kappa, planck, material_stride,
+    c_dt, state_a, state_b, I_in, I_exit and optionally E, F, f, bnd (device
+    tensors sized as for lc_step)."""
+    arr = (lc_problem_t * len(problems))()
+    keep = []
+    for i, p in enumerate(problems):
+        plan = p["plan"]
+        r = plan.rays
+        n_steps = int(p.get("n_steps_max", 1))
+        stride = int(p.get("material_stride", 0))
+        n_mat = plan.n_field + (n_steps - 1) * stride
+        arr[i] = lc_problem_t(
+            plan.handle, _dev(p["kappa"], n_mat, name="kappa"), _dev(p["planck"], n_mat, name="planck"),
+            stride, float(p["c_dt"]), _bytes(p["state_a"], plan.state_bytes, "state_a"),
+            _bytes(p["state_b"], plan.state_bytes, "state_b"), _dev(p["I_in"], plan.n_in, name="I_in"),
+            _dev(p["I_exit"], plan.n_exit, name="I_exit"),
+            _dev(p.get("E"), plan.n_field, name="E", optional=True),
+            _dev(p.get("F"), 2 * plan.n_field, name="F", optional=True),
+            _dev(p.get("f"), 4 * plan.n_field, name="f", optional=True),
+            _dev(p.get("bnd"), plan.G * r.nb * 8, name="bnd", optional=True))
+        keep.append(p)
+    h = C.c_void_p()
+    _check(_lib.lc_batch_create(len(problems), arr, C.byref(h)))
+    return Batch(h, keep)
+
+
+def lc_batch_step(batch: Batch, n_steps: int, c: float, stream=None):
+    _check(_lib.lc_batch_step(batch.handle, int(n_steps), float(c), _stream(stream)))
+
