@@ -1,13 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the long-characteristics transport step on one MI355X.
 
-A "step" is one backward-Euler transport step of the whole workload: the
-sweep (eq. (10)-(13)) over every characteristic, direction and group, then
-the cell moments and boundary factors (eq. (7), (14)-(16)).  Inputs are
-resident in HBM before the timed region.  Prints one JSON line.
+Default workload (the batched form): 64 independent problems of uneven size
+-- meshes from {32^2, 64^2, 128^2, 256^2} cells on 6x6 cm, G from {8, 17, 51}
+groups, 16/64/128 directions, characteristic spacing h/2, seeded smooth
+temperature fields -- advanced together in float32 (one persistent launch per
+phase, graph-captured steps).  Beside it the same 64 problems are run with the
+plain float64 sweep, problem by problem, and the float32 moments are compared
+with the float64 ones.
 
-Throughput is in segment-updates/s: one update is one evaluation of the
-segment propagation for one (segment, traversal, polar angle, group).
+A "step" is one backward-Euler transport step of the whole workload: the
+sweep (eq. (10)-(13)) over every characteristic, direction and group of every
+problem, then the cell moments and boundary factors (eq. (7), (14)-(16)).
+Inputs are resident in HBM before the timed region.  Throughput is in
+segment-updates/s: one update is one evaluation of the segment propagation for
+one (segment, traversal, polar angle, group).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -28,7 +35,7 @@ def _say(*a):
 
 
 def sweep_algorithmic_bytes(solver, elem):
-    """Bytes one sweep launch must move at minimum: the stored segment
+    """Bytes one sweep of a problem must move at minimum: the stored segment
     intensities read and written once, each segment's geometry (cell index
     and length) once per traversal, the cell-coefficient table once, the
     entering intensities and the exit intensities."""
@@ -42,39 +49,81 @@ def sweep_algorithmic_bytes(solver, elem):
     return state + geom + coef + io
 
 
-def run_gpu(prob, prec, steps, warmup):
+def moment_errors(got, ref):
+    from tests.parity_util import err_E, err_F, err_f
+    import workloads as W
+    return dict(E=err_E(got["E"], ref["E"]), F=err_F(got["F"], ref["F"], ref["E"], W.C_LIGHT),
+                f=err_f(got["f"], ref["f"], ref["E"]))
+
+
+def run_batched_f32(probs, steps, warmup):
     import torch
     from paper_2305_11998_amd import driver, lc, tune
-    s = driver.Solver(prob, prec=prec)
-    s.reset()
-    tuned = tune.tune(s, cache=None, verbose=True)
-    _say(f"tuning: unroll {tuned['sweep_unroll']}, entries {tuned['moments_entries']}")
-    s.reset()
-    s.tuning = tuned
-    lc.lc_plan_profile(s.plan, False)
-    for _ in range(warmup):
-        s.bench_step()
+    bs = driver.BatchSolver(probs, prec=lc.LC_F32, static_material=True)
+    tuned = tune.tune_batch(bs, verbose=True)
+    _say(f"batch tuning: unroll {tuned['sweep_unroll']}, entries {tuned['moments_entries']}")
+    bs.reset()
+    bs.step(warmup)                                   # graph of `warmup` steps
     torch.cuda.synchronize()
-    lc.lc_plan_profile_read(s.plan)
-    lc.lc_plan_profile(s.plan, True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    # timed: eager steps with the library's kernel timers around each phase
+    lc.lc_batch_profile(bs.batch, True)
+    lc.lc_batch_profile_read(bs.batch)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
-    for _ in range(steps):
-        s.bench_step()
+    bs.step(steps)
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
-    sw_ms, sw_n, mo_ms, mo_n = lc.lc_plan_profile_read(s.plan)
-    lc.lc_plan_profile(s.plan, False)
-    return s, ms, sw_ms / max(sw_n, 1), mo_ms / max(mo_n, 1)
+    pro, npro, sw, nsw, mo, nmo = lc.lc_batch_profile_read(bs.batch)
+    lc.lc_batch_profile(bs.batch, False)
+    # the same steps replayed from the captured graph
+    bs.step(steps)
+    torch.cuda.synchronize()
+    e0.record()
+    bs.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1)
+    # accuracy: one step from the initial state
+    bs.reset()
+    bs.step(1)
+    torch.cuda.synchronize()
+    mom = [s.moments() for s in bs.solvers]
+    return dict(bs=bs, ms=ms, ms_graph=ms_graph, sweep_ms=sw / max(nsw, 1), moments_ms=mo / max(nmo, 1),
+                prologue_ms=pro / max(npro, 1), tuning=tuned, moments=mom)
+
+
+def run_plain_f64(probs, steps):
+    """The plain float64 sweep, problem by problem (eager sweep + moments)."""
+    import torch
+    from paper_2305_11998_amd import driver, lc
+    tot_ms, upd, mom = 0.0, 0, []
+    for p in probs:
+        s = driver.Solver(p, prec=lc.LC_F64)
+        s.reset()
+        s.bench_step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            s.bench_step()
+        e1.record()
+        torch.cuda.synchronize()
+        tot_ms += e0.elapsed_time(e1) / steps
+        upd += s.updates_per_step()
+        s.reset()
+        s.step(1)
+        mom.append(s.moments())
+        del s
+    torch.cuda.empty_cache()
+    return dict(ms_per_step=tot_ms, updates=upd, moments=mom)
 
 
 def cpu_baseline(prob, budget_s=12.0):
-    """The oracle's sweep (unchanged) on a bounded sample of the same
-    workload: characteristics of the first azimuth pair, both traversals, all
-    polar angles and groups, as many characteristics as fit the budget."""
+    """The oracle's sweep (unchanged) on a bounded sample of the workload:
+    characteristics of the first azimuth pair of one member problem, both
+    traversals, all polar angles and groups, repeated until the budget."""
     import numpy as np
     from oracle import rays as orays, sweep as osweep
     P, G = prob.n_pol, prob.G
@@ -83,13 +132,12 @@ def cpu_baseline(prob, budget_s=12.0):
     pr = g.pairs[0]
     cols = list(range(P)) + list(range(half * P, half * P + P))
     I_in = prob.I_in[:, cols, :]
-    order = np.argsort(-pr.nseg)              # typical lengths: start from the middle
-    ks = np.sort(order[len(order) // 4:])
+    order = np.argsort(-pr.nseg)
+    ks = np.sort(order[len(order) // 4:])     # skip the shortest (corner) characteristics
     done_upd, t_used, n_rays = 0, 0.0, 0
-    chunk = 16
-    q = 0
+    chunk, q = 16, 0
     while t_used < budget_s:
-        if q >= len(ks):                      # all sampled characteristics done: sweep them again
+        if q >= len(ks):
             q = 0
         sel = ks[q:q + chunk]
         q += chunk
@@ -102,53 +150,59 @@ def cpu_baseline(prob, budget_s=12.0):
         done_upd += int(pr.nseg[sel].sum()) * 2 * P * G
         n_rays += len(sel)
     return dict(value=done_upd / t_used, unit="segment-updates/s", cores=1, kind="oracle",
-                sample=f"oracle FP64 sweep of {n_rays} characteristics of azimuth pair 0 "
-                       f"(both traversals, {P} polar angles, {G} groups, {done_upd} updates, "
-                       f"{t_used:.1f} s, numpy on one host thread)")
+                sample=f"oracle FP64 sweep of {n_rays} characteristics of azimuth pair 0 of member "
+                       f"{prob.name} ({prob.nx}x{prob.ny}, G={G}, {prob.M} directions; both traversals; "
+                       f"{done_upd} updates in {t_used:.1f} s; numpy on one host thread)")
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--f64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
               "is a design described in DESIGN.md, not a measured path", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     import workloads as W
-    from paper_2305_11998_amd import lc
-    from tests.parity_util import err_E, err_F, err_f
 
     torch.cuda.init()
-    prob = W.config(2)
-    _say("workload ready: 256x256, G=51, 32x4 directions, spacing h/2")
-    s32, ms32, sw32, mo32 = run_gpu(prob, lc.LC_F32, args.steps, args.warmup)
-    _say(f"f32: {ms32 / args.steps:.3f} ms/step, sweep kernel {sw32:.3f} ms, moments {mo32:.3f} ms")
-    m32 = s32.moments()
-    tun32 = {k: s32.tuning[k] for k in ("sweep_unroll", "moments_entries")}
-    upd = s32.updates_per_step()
-    alg32 = sweep_algorithmic_bytes(s32, 4)
-    del s32
+    t0 = time.time()
+    probs = W.batch_problems(steps=1)
+    _say(f"64 problems generated in {time.time() - t0:.0f} s")
+    r32 = run_batched_f32(probs, args.steps, args.warmup)
+    bs = r32.pop("bs")
+    upd = bs.updates_per_step()
+    alg = sum(sweep_algorithmic_bytes(s, 4) for s in bs.solvers)
+    ms32 = r32["ms"] / args.steps
+    _say(f"f32 batched: {ms32:.3f} ms/step (graph {r32['ms_graph'] / args.steps:.3f}), "
+         f"sweep {r32['sweep_ms']:.3f} ms, moments {r32['moments_ms']:.3f} ms, "
+         f"prologue {r32['prologue_ms']:.3f} ms, {upd} updates/step")
+    mom32 = r32["moments"]
+    del bs
     torch.cuda.empty_cache()
-    s64, ms64, sw64, mo64 = run_gpu(prob, lc.LC_F64, args.steps, args.warmup)
-    _say(f"f64: {ms64 / args.steps:.3f} ms/step, sweep kernel {sw64:.3f} ms, moments {mo64:.3f} ms")
-    m64 = s64.moments()
-    del s64
-    torch.cuda.empty_cache()
-    c = W.C_LIGHT
-    errs = dict(E=err_E(m32["E"], m64["E"]), F=err_F(m32["F"], m64["F"], m64["E"], c),
-                f=err_f(m32["f"], m64["f"], m64["E"]))
-    _say(f"f32 vs f64 GPU: {errs}")
 
-    value = upd * args.steps / (ms32 / 1e3)
-    value64 = upd * args.steps / (ms64 / 1e3)
-    achieved = alg32 / (sw32 / 1e3) / 1e9
+    out_f64, errs = None, None
+    if not args.no_f64:
+        r64 = run_plain_f64(probs, args.f64_steps)
+        errs = {k: 0.0 for k in ("E", "F", "f")}
+        for a, b in zip(mom32, r64["moments"]):
+            e = moment_errors(a, b)
+            for k in errs:
+                errs[k] = max(errs[k], e[k])
+        v64 = r64["updates"] / (r64["ms_per_step"] / 1e3)
+        out_f64 = {"value": v64, "unit": "segment-updates/s", "ms_per_step": r64["ms_per_step"],
+                   "form": "plain float64 sweep + moments, problem by problem"}
+        _say(f"f64 plain: {r64['ms_per_step']:.3f} ms/step; f32 vs f64 max errors {errs}")
+
+    value = upd / (ms32 / 1e3)
+    achieved = alg / (r32["sweep_ms"] / 1e3) / 1e9
     out = {
         "metric": "segment-updates/s, FP32 batched vs FP64 sweep at <=1e-5 rel error",
         "value": value,
@@ -156,26 +210,29 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms32 / args.steps,
+        "ms_per_step": ms32,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded Fleck-Cummings-type sharp-front temperature field)",
-        "config": {"workload": "single problem, 256x256 cells on 6x6 cm, G=51 groups 0.001-30 keV, "
-                               "128 directions (32 azimuths x 4 polar), spacing h/2, FP32 sweep with "
-                               "Kahan moments", "updates_per_step": upd, "tuning": tun32},
-        "fp64": {"value": value64, "ms_per_step": ms64 / args.steps, "sweep_kernel_ms": sw64,
-                 "moments_kernel_ms": mo64},
+        "data": "synthetic (seeded Fleck-Cummings-type problems, smooth temperature fields)",
+        "config": {"workload": "batched form: 64 independent problems, meshes {32,64,128,256}^2 on 6x6 cm, "
+                               "G in {8,17,51}, 16/64/128 directions, spacing h/2, float32 sweep with "
+                               "Kahan moments, one persistent launch per phase",
+                   "updates_per_step": upd, "graph_ms_per_step": r32["ms_graph"] / args.steps,
+                   "tuning": {k: r32["tuning"][k] for k in ("sweep_unroll", "moments_entries")}},
+        "fp64_plain": out_f64,
+        "speedup_vs_fp64": (value / out_f64["value"]) if out_f64 else None,
         "fp32_vs_fp64_max_err": errs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweep<float,P=4,sym>", "kernel_ms": sw32,
-                     "algorithmic_bytes_per_launch": alg32},
+                     "kernel": "k_sweep_batch<float,4,U>", "kernel_ms": r32["sweep_ms"],
+                     "moments_kernel_ms": r32["moments_ms"], "algorithmic_bytes_per_launch": alg},
     }
     if not args.no_cpu_baseline:
         _say("cpu baseline (oracle sample)")
-        out["cpu_baseline"] = cpu_baseline(prob)
+        big = max(probs, key=lambda p: p.cells * p.G * p.M)
+        out["cpu_baseline"] = cpu_baseline(big)
     print(json.dumps(out), flush=True)
 
 

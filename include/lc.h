@@ -210,9 +210,10 @@ lc_status lc_moments(lc_plan_t plan, const void* state, const double* I_exit,
  * written by step t-1 (step 0 reads state_a); after an odd number of steps
  * the newest state is in state_b, after an even number in state_a.
  * kappa/planck of step t start at kappa + t*material_stride (elements; 0
- * means the same data every step).  The moments of the last step are written
- * to E, F, f, bnd (as lc_moments; any may be NULL).  The step sequence is
- * captured once in a HIP graph per argument set and replayed.
+ * means the same data every step).  Every step forms its moments (as
+ * lc_moments; any output may be NULL); E, F, f, bnd hold those of the last
+ * step.  The step sequence is captured once in a HIP graph per argument set
+ * and replayed.
  */
 lc_status lc_step(lc_plan_t plan, int32_t n_steps, const double* kappa, const double* planck,
                   int64_t material_stride, double c_dt, double c, void* state_a, void* state_b,
@@ -249,8 +250,11 @@ lc_status lc_plan_profile_read(lc_plan_t plan, double* out);
  * in one persistent launch per phase.  lc_batch_create copies the per-problem
  * pointer sets (device arrays as for lc_step) into the handle and builds a
  * work list ordered by decreasing cost; lc_batch_step then runs n_steps time
- * steps of every problem (state ping-pong as lc_step) and writes each
- * problem's last-step moments.
+ * steps of every problem (state ping-pong as lc_step; step t reads material
+ * data at kappa + t * material_stride, so with a non-zero stride n_steps must
+ * not exceed the steps the caller provides); every step forms each problem's
+ * moments, and the outputs hold those of the last step.  All problems must share one precision; the launch
+ * tuning is that of the first problem's plan.  I_exit is required.
  */
 typedef struct {
     lc_plan_t plan;
@@ -271,6 +275,14 @@ typedef struct {
 lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_batch_t* out);
 lc_status lc_batch_step(lc_batch_t batch, int32_t n_steps, double c, void* stream);
 lc_status lc_batch_free(lc_batch_t batch);
+
+/* Kernel timers of a batch: with lc_batch_profile(batch, 1), lc_batch_step runs
+ * its steps without a graph and records HIP events around the prologue, the
+ * persistent sweep and the persistent moments launches; lc_batch_profile_read
+ * synchronises them and returns out[6] = total ms and launch count of each, in
+ * that order, clearing the record. */
+lc_status lc_batch_profile(lc_batch_t batch, int32_t enable);
+lc_status lc_batch_profile_read(lc_batch_t batch, double* out);
 
 #ifdef __cplusplus
 }

@@ -375,7 +375,7 @@ lc_status lc_step(lc_plan_t plan, int32_t n_steps, const double* kappa, const do
             void* next = (t % 2 == 0) ? state_b : state_a;
             rc = launch_sweep(pl, kappa + t * material_stride, planck + t * material_stride, c_dt, prev,
                               next, I_in, I_exit, pl->capture);
-            if (rc == LC_OK && t == n_steps - 1)
+            if (rc == LC_OK)                          // every step forms its moments
                 rc = launch_moments(pl, next, I_exit, I_in, c, E, F, f, bnd, pl->capture);
         }
         hipGraph_t graph = nullptr;

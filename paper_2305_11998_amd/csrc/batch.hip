@@ -33,7 +33,70 @@ struct Batch {
     int64_t coef_lanes = 0, scale_blocks = 0, bnd_lanes = 0;
     std::vector<GraphEntry> graphs;
     hipStream_t capture = nullptr;
+    bool profile = false;               // eager steps with events around each phase
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];   // prologue, sweep, moments
 };
+
+void clear_events(Batch* b) {
+    for (auto& v : b->ev) {
+        for (auto& e : v) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+        v.clear();
+    }
+}
+
+lc_status ev_begin(Batch* b, int k, hipStream_t st) {
+    if (!b->profile) return LC_OK;
+    hipEvent_t x = nullptr, y = nullptr;
+    LC_HIP(hipEventCreate(&x));
+    hipError_t e = hipEventCreate(&y);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(x);
+        set_error("hipEventCreate failed: %s", hipGetErrorString(e));
+        return LC_ERR_HIP;
+    }
+    b->ev[k].push_back({x, y});
+    LC_HIP(hipEventRecord(x, st));
+    return LC_OK;
+}
+
+lc_status ev_end(Batch* b, int k, hipStream_t st) {
+    if (!b->profile) return LC_OK;
+    LC_HIP(hipEventRecord(b->ev[k].back().second, st));
+    return LC_OK;
+}
+
+// Enqueue n_steps time steps of every problem on st.
+lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
+    const size_t sb = sweep_args_bytes(), mb = mom_args_bytes();
+    lc_status rc = LC_OK;
+    for (int t = 0; t < n_steps && rc == LC_OK; ++t) {
+        const int parity = t & 1;
+        rc = launch_zero_counters(b->d_counters, 2, st);
+        if (rc == LC_OK) rc = ev_begin(b, 0, st);
+        if (rc == LC_OK)
+            rc = launch_prologue_batch(b->prec, b->d_coef_args, b->n, b->coef_lanes, b->scale_blocks, t, st);
+        if (rc == LC_OK) rc = ev_end(b, 0, st);
+        if (rc == LC_OK) rc = ev_begin(b, 1, st);
+        if (rc == LC_OK)
+            rc = launch_sweep_batch(b->prec, b->pm, b->unroll,
+                                    static_cast<char*>(b->d_sweep_args) + parity * b->n * sb, b->d_sweep_items,
+                                    b->n_sweep_items, b->d_counters, st);
+        if (rc == LC_OK) rc = ev_end(b, 1, st);
+        if (rc == LC_OK) {                            // every step forms its moments
+            rc = ev_begin(b, 2, st);
+            if (rc == LC_OK)
+                rc = launch_moments_batch(b->prec, b->pm, b->ent,
+                                          static_cast<char*>(b->d_mom_args) + parity * b->n * mb,
+                                          b->d_mom_items, b->n_mom_items, b->d_counters + 1, st);
+            if (rc == LC_OK) rc = ev_end(b, 2, st);
+            if (rc == LC_OK && b->bnd_lanes > 0) rc = launch_boundary_batch(b->d_bnd_args, b->n, b->bnd_lanes, st);
+        }
+    }
+    return rc;
+}
 
 Batch* as_batch(lc_batch_t b) {
     Batch* p = reinterpret_cast<Batch*>(b);
@@ -42,6 +105,7 @@ Batch* as_batch(lc_batch_t b) {
 
 void free_batch(Batch* b) {
     if (!b) return;
+    clear_events(b);
     for (auto& g : b->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (b->capture) (void)hipStreamDestroy(b->capture);
@@ -199,31 +263,13 @@ lc_status lc_batch_step(lc_batch_t batch, int32_t n_steps, double c, void* strea
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
         b->graphs.clear();
     }
+    if (b->profile) return enqueue_steps(b, n_steps, static_cast<hipStream_t>(stream));
     hipGraphExec_t exec = nullptr;
     for (auto& g : b->graphs)
         if (g.key.size() == 1 && g.key[0] == (uintptr_t)n_steps) exec = g.exec;
     if (!exec) {
         LC_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-        lc_status rc = LC_OK;
-        const size_t sb = sweep_args_bytes(), mb = mom_args_bytes();
-        for (int t = 0; t < n_steps && rc == LC_OK; ++t) {
-            const int parity = t & 1;
-            rc = launch_zero_counters(b->d_counters, 2, b->capture);
-            if (rc == LC_OK)
-                rc = launch_prologue_batch(b->prec, b->d_coef_args, b->n, b->coef_lanes, b->scale_blocks, t,
-                                           b->capture);
-            if (rc == LC_OK)
-                rc = launch_sweep_batch(b->prec, b->pm, b->unroll,
-                                        static_cast<char*>(b->d_sweep_args) + parity * b->n * sb,
-                                        b->d_sweep_items, b->n_sweep_items, b->d_counters, b->capture);
-            if (rc == LC_OK && t == n_steps - 1) {
-                rc = launch_moments_batch(b->prec, b->pm, b->ent,
-                                          static_cast<char*>(b->d_mom_args) + parity * b->n * mb,
-                                          b->d_mom_items, b->n_mom_items, b->d_counters + 1, b->capture);
-                if (rc == LC_OK && b->bnd_lanes > 0)
-                    rc = launch_boundary_batch(b->d_bnd_args, b->n, b->bnd_lanes, b->capture);
-            }
-        }
+        lc_status rc = enqueue_steps(b, n_steps, b->capture);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(b->capture, &graph);
         if (rc != LC_OK) {
@@ -237,6 +283,32 @@ lc_status lc_batch_step(lc_batch_t batch, int32_t n_steps, double c, void* strea
         b->graphs.push_back({{(uintptr_t)n_steps}, exec});
     }
     LC_HIP(hipGraphLaunch(exec, static_cast<hipStream_t>(stream)));
+    return LC_OK;
+}
+
+lc_status lc_batch_profile(lc_batch_t batch, int32_t enable) {
+    Batch* b = as_batch(batch);
+    LC_CHECK(b, LC_ERR_STATE, "invalid batch handle");
+    b->profile = enable != 0;
+    return LC_OK;
+}
+
+lc_status lc_batch_profile_read(lc_batch_t batch, double* out) {
+    Batch* b = as_batch(batch);
+    LC_CHECK(b, LC_ERR_STATE, "invalid batch handle");
+    LC_ARG(out, "out is NULL");
+    for (int k = 0; k < 3; ++k) {
+        double ms_tot = 0.0;
+        for (auto& e : b->ev[k]) {
+            LC_HIP(hipEventSynchronize(e.second));
+            float ms = 0.f;
+            LC_HIP(hipEventElapsedTime(&ms, e.first, e.second));
+            ms_tot += ms;
+        }
+        out[2 * k] = ms_tot;
+        out[2 * k + 1] = (double)b->ev[k].size();
+    }
+    clear_events(b);
     return LC_OK;
 }
 

@@ -123,6 +123,18 @@ class BatchSolver:
         self.c = self.solvers[0].c
         self.static = static_material
         self.max_steps = None if static_material else min(s.prob.steps for s in self.solvers)
+        self.batch = None
+        self.rebuild()
+
+    def rebuild(self, tuning=None):
+        """(Re)create the batch handle, optionally with a new launch tuning
+        (sweep_unroll, moments_entries) set on every member's plan."""
+        if tuning is not None:
+            for s in self.solvers:
+                lc.lc_plan_set_tuning(s.plan, *tuning)
+        if self.batch is not None:
+            self.batch.free()
+        static_material = self.static
         self.batch = lc.lc_batch_create([dict(
             plan=s.plan, kappa=s.kappa, planck=s.planck, c_dt=s.prob.c_dt,
             material_stride=0 if static_material else s.stride,

@@ -83,6 +83,8 @@ _SIGS = {
     "lc_batch_create": ([_i32, C.POINTER(lc_problem_t), C.POINTER(_vp)], C.c_int),
     "lc_batch_step": ([_vp, _i32, _d, _vp], C.c_int),
     "lc_batch_free": ([_vp], C.c_int),
+    "lc_batch_profile": ([_vp, _i32], C.c_int),
+    "lc_batch_profile_read": ([_vp, _vp], C.c_int),
 }
 EXPORTED = tuple(_SIGS)
 for _name, (_args, _res) in _SIGS.items():
@@ -346,4 +348,15 @@ def lc_batch_create(problems) -> Batch:
 
 def lc_batch_step(batch: Batch, n_steps: int, c: float, stream=None):
     _check(_lib.lc_batch_step(batch.handle, int(n_steps), float(c), _stream(stream)))
+
+
+def lc_batch_profile(batch: Batch, enable: bool):
+    _check(_lib.lc_batch_profile(batch.handle, int(bool(enable))))
+
+
+def lc_batch_profile_read(batch: Batch):
+    """(prologue_ms, n, sweep_ms, n, moments_ms, n) totals since the last read."""
+    out = (C.c_double * 6)()
+    _check(_lib.lc_batch_profile_read(batch.handle, out))
+    return tuple(out)
 

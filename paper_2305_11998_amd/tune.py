@@ -88,3 +88,31 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
         db[key] = res
         _save(cache, db)
     return dict(res, cached=False, key=key)
+
+
+def tune_batch(bs, steps: int = 2, verbose: bool = False):
+    """Pick (sweep_unroll, moments_entries) for a BatchSolver by timing its
+    persistent launches (lc_batch_profile) for each candidate; the batch is
+    left rebuilt with the choice."""
+    import torch
+    times = {}
+    combos = sorted({(u, 2) for u in CANDIDATES} | {(2, e) for e in CANDIDATES})
+    for u, e in combos:
+        bs.rebuild((u, e))
+        lc.lc_batch_profile(bs.batch, True)
+        bs.reset()
+        bs.step(steps)
+        torch.cuda.synchronize()
+        pro, npro, sw, nsw, mo, nmo = lc.lc_batch_profile_read(bs.batch)
+        lc.lc_batch_profile(bs.batch, False)
+        times[(u, e)] = (sw / max(nsw, 1), mo / max(nmo, 1))
+        if verbose:
+            print(f"  tune batch: unroll {u} entries {e}: sweep {times[(u, e)][0]:.3f} ms, "
+                  f"moments {times[(u, e)][1]:.3f} ms", flush=True)
+    best_u = min(CANDIDATES, key=lambda u: times[(u, 2)][0])
+    best_e = min(CANDIDATES, key=lambda e: times[(2, e)][1])
+    bs.rebuild((best_u, best_e))
+    return dict(sweep_unroll=best_u, moments_entries=best_e,
+                sweep_ms={str(k): v[0] for k, v in times.items()},
+                moments_ms={str(k): v[1] for k, v in times.items()})
+
