@@ -12,6 +12,7 @@ reuses them without timing.
 from __future__ import annotations
 
 import json
+import sys
 import math
 import os
 
@@ -77,7 +78,7 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
         times[(u, e)] = (sw / max(nsw, 1), mo / max(nmo, 1))
         if verbose:
             print(f"  tune {key}: unroll {u} entries {e}: sweep {times[(u, e)][0]:.3f} ms, "
-                  f"moments {times[(u, e)][1]:.3f} ms", flush=True)
+                  f"moments {times[(u, e)][1]:.3f} ms", file=sys.stderr, flush=True)
     best_u = min(CANDIDATES, key=lambda u: times[(u, 2)][0])
     best_e = min(CANDIDATES, key=lambda e: times[(2, e)][1])
     lc.lc_plan_set_tuning(plan, best_u, best_e)
@@ -108,7 +109,7 @@ def tune_batch(bs, steps: int = 2, verbose: bool = False):
         times[(u, e)] = (sw / max(nsw, 1), mo / max(nmo, 1))
         if verbose:
             print(f"  tune batch: unroll {u} entries {e}: sweep {times[(u, e)][0]:.3f} ms, "
-                  f"moments {times[(u, e)][1]:.3f} ms", flush=True)
+                  f"moments {times[(u, e)][1]:.3f} ms", file=sys.stderr, flush=True)
     best_u = min(CANDIDATES, key=lambda u: times[(u, 2)][0])
     best_e = min(CANDIDATES, key=lambda e: times[(2, e)][1])
     bs.rebuild((best_u, best_e))
