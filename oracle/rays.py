@@ -205,8 +205,23 @@ def tube_offsets(nx, ny, lx, ly, c, s, h_moc):
     return np.array(v), np.array(w)
 
 
-def build(nx, ny, lx, ly, phi, h_moc, mode=UNIFORM) -> CharGrid:
-    """Characteristic grid for every azimuth pair of the quadrature."""
+def _crossing(v, nx, ny, lx, ly, c, s, cells):
+    """Offsets v (sorted) of the characteristics that cross any of the given
+    cells: a line v = const crosses a convex cell iff v lies strictly inside
+    the cell's projected extent."""
+    hx, hy = lx / nx, ly / ny
+    keep = np.zeros(len(v), dtype=bool)
+    for cell in cells:
+        ix, iy = int(cell) % nx, int(cell) // nx
+        cv = [-(x * hx) * s + (y * hy) * c for x in (ix, ix + 1) for y in (iy, iy + 1)]
+        keep |= (v > min(cv)) & (v < max(cv))
+    return keep
+
+
+def build(nx, ny, lx, ly, phi, h_moc, mode=UNIFORM, only_cells=None) -> CharGrid:
+    """Characteristic grid for every azimuth pair of the quadrature.  With
+    ``only_cells``, only the characteristics crossing those cells are traced
+    (enough for their cell moments, which involve no other characteristic)."""
     n_az = len(phi)
     if n_az % 2:
         raise ValueError("azimuths must come in opposite pairs")
@@ -223,6 +238,9 @@ def build(nx, ny, lx, ly, phi, h_moc, mode=UNIFORM) -> CharGrid:
             v, w = uniform_offsets(lx, ly, c, s, h_moc)
         else:
             v, w = tube_offsets(nx, ny, lx, ly, c, s, h_moc)
+        if only_cells is not None:
+            keep = _crossing(v, nx, ny, lx, ly, c, s, only_cells)
+            v, w = v[keep], w[keep]
         cells, lens, fi, fo, pi, po, vk, wk = [], [], [], [], [], [], [], []
         for vv, ww in zip(v, w):
             r = trace_characteristic(nx, ny, lx, ly, c, s, vv)

@@ -317,6 +317,76 @@ __global__ void k_bnd_final(const int* __restrict__ ray_off, const PairGeo* __re
     bmap[2 * key + 1] = best + 1;
 }
 
+// ---- the paper's construction: vertex-avoiding tubes, halved to h_moc -----------
+// Projections v = -x sin(phi) + y cos(phi) of all grid vertices, padded with +inf
+// to a power of two for the bitonic sort.
+__global__ void k_vertex_proj(int nx, int ny, double hx, double hy, double c, double s, int64_t n_vert,
+                              int64_t n_pad, double* proj) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_pad) return;
+    if (idx >= n_vert) {
+        proj[idx] = INFINITY;
+        return;
+    }
+    const int i = (int)(idx / (ny + 1)), j = (int)(idx % (ny + 1));
+    proj[idx] = -((double)i * hx) * s + ((double)j * hy) * c;
+}
+
+__global__ void k_bitonic_step(double* v, int64_t n, int64_t j, int64_t k) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t l = i ^ j;
+    if (l <= i) return;
+    const double a = v[i], b = v[l];
+    const bool up = (i & k) == 0;
+    if ((up && a > b) || (!up && a < b)) {
+        v[i] = b;
+        v[l] = a;
+    }
+}
+
+// flag[i] = 1 where sorted projection i starts a new distinct value
+// (differs from its predecessor by more than 1e-12 of the projected width).
+__global__ void k_distinct_flags(const double* __restrict__ proj, int64_t n, int* flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double tol = 1e-12 * (proj[n - 1] - proj[0]);
+    flag[i] = (i == 0 || proj[i] - proj[i - 1] > tol) ? 1 : 0;
+}
+
+__global__ void k_distinct_compact(const double* __restrict__ proj, int64_t n, const int* __restrict__ flag,
+                                   const int* __restrict__ pos, double* distinct) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    // the last distinct value is the maximum projection
+    if (flag[i]) distinct[pos[i]] = (pos[i] == pos[n] - 1) ? proj[n - 1] : proj[i];
+}
+
+// Each gap between distinct projections is one tube, split into the least
+// power of two of equal parts no wider than h_moc.
+__global__ void k_tube_parts(const double* __restrict__ distinct, int64_t m, double h_moc, int* parts) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m - 1) return;
+    const double width = distinct[t + 1] - distinct[t];
+    int q = 1;
+    while (width / q > h_moc && q < (1 << 28)) q *= 2;
+    parts[t] = q;
+}
+
+__global__ void k_tube_fill(const double* __restrict__ distinct, int64_t m, const int* __restrict__ parts,
+                            const int* __restrict__ roff, double* v, double* w) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= m - 1) return;
+    const double lo = distinct[t];
+    const double width = distinct[t + 1] - lo;
+    const int q = parts[t];
+    const double sub = width / q;
+    for (int u = 0; u < q; ++u) {
+        v[roff[t] + u] = lo + ((double)u + 0.5) * sub;
+        w[roff[t] + u] = sub;
+    }
+}
+
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 lc_status scan_counts(const int* in, int* out, int64_t n, std::vector<void*>& tmp, hipStream_t st) {
@@ -349,6 +419,14 @@ lc_status build_geometry(Rays* r, hipStream_t st) {
         rc = (x);                \
         if (rc) { cleanup(); return rc; } \
     } while (0)
+#define LC_CHECKC(cond, code, ...)  \
+    do {                            \
+        if (!(cond)) {              \
+            set_error(__VA_ARGS__); \
+            cleanup();              \
+            return (code);          \
+        }                           \
+    } while (0)
 #define LC_HIPC(x)                                                          \
     do {                                                                    \
         hipError_t e_ = (x);                                                \
@@ -376,12 +454,54 @@ lc_status build_geometry(Rays* r, hipStream_t st) {
         geo[a] = {c, s, vmin, W / (double)K};
         r->ray_off[a + 1] = r->ray_off[a] + (int)K;
     }
-    if (r->mode != LC_RAYS_UNIFORM) {
-        set_error("the vertex-avoiding construction is not available on the GPU in this build");
-        return LC_ERR_UNSUPPORTED;
+    // the paper's construction: per pair, tubes between sorted vertex projections
+    std::vector<double*> t_dist(P, nullptr);
+    std::vector<int*> t_parts(P, nullptr), t_roff(P, nullptr);
+    std::vector<int64_t> t_m(P, 0);
+    if (r->mode == LC_RAYS_TUBES) {
+        const int64_t n_vert = (int64_t)(r->nx + 1) * (r->ny + 1);
+        int64_t n_pad = 1;
+        while (n_pad < n_vert) n_pad *= 2;
+        double* proj = nullptr;
+        int *flag = nullptr, *pos = nullptr;
+        LC_STEP(dalloc(tmp, &proj, n_pad));
+        LC_STEP(dalloc(tmp, &flag, n_vert));
+        LC_STEP(dalloc(tmp, &pos, n_vert + 1));
+        for (int a = 0; a < P; ++a) {
+            hipLaunchKernelGGL(k_vertex_proj, dim3(nblk(n_pad)), dim3(kBlock), 0, st, r->nx, r->ny, r->hx, r->hy,
+                               r->cphi[a], r->sphi[a], n_vert, n_pad, proj);
+            for (int64_t k = 2; k <= n_pad; k *= 2)
+                for (int64_t j = k / 2; j > 0; j /= 2)
+                    hipLaunchKernelGGL(k_bitonic_step, dim3(nblk(n_pad)), dim3(kBlock), 0, st, proj, n_pad, j, k);
+            hipLaunchKernelGGL(k_distinct_flags, dim3(nblk(n_vert)), dim3(kBlock), 0, st, proj, n_vert, flag);
+            LC_HIPC(hipGetLastError());
+            LC_STEP(scan_counts(flag, pos, n_vert, tmp, st));
+            int m = 0;
+            LC_HIPC(hipMemcpyAsync(&m, pos + n_vert, sizeof(int), hipMemcpyDeviceToHost, st));
+            LC_HIPC(hipStreamSynchronize(st));
+            LC_CHECKC(m >= 2, LC_ERR_STATE, "pair %d: fewer than two distinct vertex projections", a);
+            t_m[a] = m;
+            LC_STEP(dalloc(tmp, &t_dist[a], m));
+            LC_STEP(dalloc(tmp, &t_parts[a], m));
+            LC_STEP(dalloc(tmp, &t_roff[a], m));
+            hipLaunchKernelGGL(k_distinct_compact, dim3(nblk(n_vert)), dim3(kBlock), 0, st, proj, n_vert, flag,
+                               pos, t_dist[a]);
+            hipLaunchKernelGGL(k_tube_parts, dim3(nblk(m)), dim3(kBlock), 0, st, t_dist[a], (int64_t)m, r->h_moc,
+                               t_parts[a]);
+            LC_HIPC(hipGetLastError());
+            LC_STEP(scan_counts(t_parts[a], t_roff[a], m - 1, tmp, st));
+            int K = 0;
+            LC_HIPC(hipMemcpyAsync(&K, t_roff[a] + (m - 1), sizeof(int), hipMemcpyDeviceToHost, st));
+            LC_HIPC(hipStreamSynchronize(st));
+            LC_CHECKC(K >= 1 && K < (1 << 26), LC_ERR_ARG, "pair %d: %d characteristics", a, K);
+            r->ray_off[a + 1] = r->ray_off[a] + K;
+            LC_CHECKC(r->ray_off[a + 1] < (1 << 30), LC_ERR_ARG, "too many characteristics");
+        }
     }
     r->n_rays = r->ray_off[P];
     const int nr = (int)r->n_rays;
+    LC_CHECKC((double)nr * (r->nx + r->ny) < 2.0e9, LC_ERR_ARG,
+              "characteristic grid too large for 32-bit segment indices (%d characteristics)", nr);
     PairGeo* d_geo = nullptr;
     int* d_count = nullptr;
     int* d_err = nullptr;
@@ -398,8 +518,14 @@ lc_status build_geometry(Rays* r, hipStream_t st) {
     LC_HIPC(hipMemcpyAsync(r->d_ray_off, r->ray_off.data(), (P + 1) * sizeof(int),
                            hipMemcpyHostToDevice, st));
     LC_HIPC(hipMemsetAsync(d_err, 0, sizeof(int), st));
-    hipLaunchKernelGGL(k_uniform_offsets, dim3(nblk(nr)), dim3(kBlock), 0, st, r->d_ray_off, d_geo, P,
-                       nr, r->d_v, r->d_width);
+    if (r->mode == LC_RAYS_TUBES) {
+        for (int a = 0; a < P; ++a)
+            hipLaunchKernelGGL(k_tube_fill, dim3(nblk(t_m[a])), dim3(kBlock), 0, st, t_dist[a], t_m[a], t_parts[a],
+                               t_roff[a], r->d_v + r->ray_off[a], r->d_width + r->ray_off[a]);
+    } else {
+        hipLaunchKernelGGL(k_uniform_offsets, dim3(nblk(nr)), dim3(kBlock), 0, st, r->d_ray_off, d_geo, P,
+                           nr, r->d_v, r->d_width);
+    }
     hipLaunchKernelGGL(k_trace<false>, dim3(nblk(nr)), dim3(kBlock), 0, st, r->d_ray_off, d_geo, P, nr,
                        r->nx, r->ny, r->lx, r->ly, r->hx, r->hy, r->d_v, d_count, r->d_face, r->d_pts,
                        nullptr, nullptr, nullptr, nullptr);
@@ -494,6 +620,7 @@ lc_status build_geometry(Rays* r, hipStream_t st) {
     return LC_OK;
 #undef LC_STEP
 #undef LC_HIPC
+#undef LC_CHECKC
 }
 
 }  // namespace lc

@@ -104,7 +104,7 @@ def test_full_batched_workload_sampled(lcmod):
         got = s.moments()
         cells = np.concatenate([rng.choice(p.cells, 4, replace=False), [0, p.cells - 1]])
         _say(f"  member {q}: {p.nx}^2 G={p.G} M={p.M}")
-        g = orays.build(p.nx, p.ny, p.lx, p.ly, p.phi, p.h_moc)
+        g = orays.build(p.nx, p.ny, p.lx, p.ly, p.phi, p.h_moc, only_cells=cells)
         ref = osolve.run_sampled(p, g, cells)["steps"][-1]
         c = W.C_LIGHT
         eE = err_E(got["E"][:, cells], ref["E"])

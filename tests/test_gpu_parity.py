@@ -50,14 +50,14 @@ def _custom_problem(nx=32, ny=24, lx=3.2, ly=2.4, n_az=12, mu=None, w=None, G=5,
     return W.Problem(nx, ny, lx, ly, phi, mu, om, edges, h_moc, 1.7, kap, B, I_in, s0, Ts, "custom")
 
 
-def _oracle_full(prob, steps=None):
-    return osolve.run(prob, steps=steps)
+def _oracle_full(prob, steps=None, mode=0):
+    return osolve.run(prob, steps=steps, mode=mode)
 
 
-def _compare_full(lc, driver, prob, prec, tol, graph=True, check_state=True):
-    _say(f"case {prob.name}: {prob.nx}x{prob.ny} G={prob.G} M={prob.M} prec={prec} steps={prob.steps}")
-    ref = _oracle_full(prob)
-    s = driver.Solver(prob, prec=prec)
+def _compare_full(lc, driver, prob, prec, tol, graph=True, check_state=True, mode=0):
+    _say(f"case {prob.name}: {prob.nx}x{prob.ny} G={prob.G} M={prob.M} prec={prec} steps={prob.steps} mode={mode}")
+    ref = _oracle_full(prob, mode=mode)
+    s = driver.Solver(prob, prec=prec, mode=mode)
     s.reset()
     s.step(prob.steps, graph=graph)
     got = s.moments()
@@ -97,6 +97,39 @@ def test_geometry_matches_oracle(lcmod):
         assert np.allclose(wd, w, rtol=1e-15)
         faces = np.concatenate([np.stack([p.entry_face, p.exit_face], 1) for p in g.pairs])
         assert np.array_equal(fc, faces)
+
+
+@pytest.mark.parametrize("shape", [(16, 16, 6.0, 6.0, 0.05), (20, 12, 2.0, 1.2, 0.02), (5, 9, 1.0, 1.8, 0.07)])
+def test_geometry_tube_mode_matches_oracle(lcmod, shape):
+    """The paper's vertex-avoiding, width-halving construction built on the
+    GPU (sorted vertex projections) against the oracle's."""
+    lc, driver = lcmod
+    nx, ny, lx, ly, h = shape
+    phi, mu, om = W.product_quadrature(16, 2)
+    _say(f"tube geometry {nx}x{ny} h_moc={h}")
+    g = orays.build(nx, ny, lx, ly, phi, h, orays.TUBES)
+    r = lc.lc_build_rays(nx, ny, lx, ly, phi, mu, om, h, lc.LC_RAYS_TUBES)
+    ro, so, ce, ln, wd, fc = lc.lc_rays_export(r)
+    ray_off, seg_off, cell, length, w = g.flat()
+    assert np.array_equal(ro, ray_off)
+    assert np.array_equal(so, seg_off)
+    assert np.array_equal(ce, cell)
+    assert np.allclose(ln, length, rtol=1e-12, atol=1e-14 * lx)
+    assert np.allclose(wd, w, rtol=1e-13, atol=0)
+    # traced area per cell and direction equals the cell area (exact construction)
+    area = (lx / nx) * (ly / ny)
+    for a in range(len(ro) - 1):
+        traced = np.zeros(nx * ny)
+        for k in range(ro[a], ro[a + 1]):
+            np.add.at(traced, ce[so[k]:so[k + 1]], ln[so[k]:so[k + 1]] * wd[k])
+        assert np.allclose(traced, area, rtol=1e-11)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tube_mode_full_parity(lcmod, prec):
+    lc, driver = lcmod
+    prob = _custom_problem(nx=12, ny=10, lx=1.2, ly=1.0, n_az=8, G=3, h_moc=0.04, steps=2)
+    _compare_full(lc, driver, prob, prec, TOL64 if prec == 0 else TOL32, mode=lc.LC_RAYS_TUBES)
 
 
 def test_config0_fp64(lcmod):
@@ -172,7 +205,7 @@ def test_full_size_sampled_cells(lcmod, cfg, prec):
     got = s.moments()
     cells = _sampled_cells(prob, 8, cfg)
     _say("  oracle on sampled cells")
-    g = orays.build(prob.nx, prob.ny, prob.lx, prob.ly, prob.phi, prob.h_moc)
+    g = orays.build(prob.nx, prob.ny, prob.lx, prob.ly, prob.phi, prob.h_moc, only_cells=cells)
     ref = osolve.run_sampled(prob, g, cells)["steps"][-1]
     c = W.C_LIGHT
     eE = err_E(got["E"][:, cells], ref["E"])

@@ -167,3 +167,17 @@ def test_global_segment_numbering():
         for k in range(pr.K):
             assert np.array_equal(cell[j:j + len(pr.cells[k])], pr.cells[k])
             j += len(pr.cells[k])
+
+
+def test_subset_build_traces_exactly_the_crossing_characteristics():
+    p = W.config(0)
+    g = rays.build(p.nx, p.ny, p.lx, p.ly, p.phi, p.h_moc)
+    cells = [0, 37, 200, 255]
+    sub = rays.build(p.nx, p.ny, p.lx, p.ly, p.phi, p.h_moc, only_cells=cells)
+    for full, part in zip(g.pairs, sub.pairs):
+        want = [k for k in range(full.K) if set(cells) & set(full.cells[k].tolist())]
+        assert np.array_equal(part.v, full.v[want])
+        for q, k in enumerate(want):
+            assert np.array_equal(part.cells[q], full.cells[k])
+            assert np.array_equal(part.lens[q], full.lens[k])
+

@@ -279,8 +279,12 @@ def make_problem(nx, ny, lx, ly, n_az, n_pol, G, nu_lo, nu_hi, h_moc, c_dt,
     phi, mu, omega = product_quadrature(n_az, n_pol)
     edges = group_edges(G, nu_lo, nu_hi)
     numid = group_midpoints(edges)
-    kap = [fc_opacity(numid, T) for T in T_steps]
-    B = [group_planck(edges, T) for T in T_steps]
+    kap, B = [], []
+    for T in T_steps:
+        # evaluate on the distinct temperatures only (fronts have two)
+        Tu, inv = np.unique(np.asarray(T, dtype=np.float64), return_inverse=True)
+        kap.append(fc_opacity(numid, Tu)[:, inv])
+        B.append(group_planck(edges, Tu)[:, inv])
     I_in = inflow_left_planck(nx, ny, phi, mu, edges, T_in)
     s0 = np.repeat(group_planck(edges, np.array([T0])), nx * ny, axis=1)
     return Problem(nx, ny, lx, ly, phi, mu, omega, edges, h_moc, c_dt,
