@@ -49,6 +49,7 @@ void free_plan(Plan* pl) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (pl->capture) (void)hipStreamDestroy(pl->capture);
     if (pl->d_coef) (void)hipFree(pl->d_coef);
+    if (pl->d_gmax) (void)hipFree(pl->d_gmax);
     if (pl->d_bun_off) (void)hipFree(pl->d_bun_off);
     if (pl->d_bun_len) (void)hipFree(pl->d_bun_len);
     if (pl->d_bun_base) (void)hipFree(pl->d_bun_base);
@@ -88,7 +89,7 @@ using namespace lc;
 
 extern "C" {
 
-int32_t lc_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+int32_t lc_version(void) { return 1 * 10000 + 1 * 100 + 0; }
 
 const char* lc_last_error(void) { return g_err; }
 
@@ -255,7 +256,7 @@ lc_status lc_plan_create(lc_rays_t rays, int32_t G, int32_t prec, lc_plan_t* out
     pl->prec = prec;
     pl->hdr_bytes = ((size_t)G * sizeof(int32_t) + 255) / 256 * 256;
     pl->sweep_unroll = prec == LC_F32 ? 4 : 2;
-    pl->moments_entries = 2;
+    pl->moments_entries = 3;
     lc_status rc = plan_init_sweep(pl);
     pl->value_bytes = (size_t)pl->half_elems * 2 * (prec == LC_F32 ? 4 : 8);
     hipError_t e = hipSuccess;
@@ -263,6 +264,7 @@ lc_status lc_plan_create(lc_rays_t rays, int32_t G, int32_t prec, lc_plan_t* out
         const size_t coef_bytes = (size_t)r->cells * G * (prec == LC_F32 ? 8 : 16);
         const size_t nbun = (size_t)pl->n_bun;
         e = hipMalloc(&pl->d_coef, coef_bytes);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_gmax), (size_t)G * sizeof(unsigned long long));
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_off), pl->bun_off.size() * sizeof(int));
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_len), std::max<size_t>(nbun, 1) * sizeof(int));
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_base), std::max<size_t>(nbun, 1) * sizeof(int64_t));
@@ -403,8 +405,8 @@ lc_status lc_plan_set_tuning(lc_plan_t plan, const lc_tuning_t* t) {
     Plan* pl = as_plan(plan);
     LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
     LC_ARG(t, "tuning is NULL");
-    auto ok = [](int v) { return v == 1 || v == 2 || v == 4; };
-    LC_ARG(ok(t->sweep_unroll) && ok(t->moments_entries), "tuning values must be 1, 2 or 4");
+    LC_ARG(t->sweep_unroll == 1 || t->sweep_unroll == 2 || t->sweep_unroll == 4, "sweep_unroll must be 1, 2 or 4");
+    LC_ARG(t->moments_entries >= 1 && t->moments_entries <= 4, "moments_entries must be 1, 2, 3 or 4");
     pl->sweep_unroll = t->sweep_unroll;
     pl->moments_entries = t->moments_entries;
     for (auto& g : pl->graphs)

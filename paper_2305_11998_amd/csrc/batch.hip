@@ -6,6 +6,7 @@
 // problem cost, largest first, so the small problems fill the tail.  The step
 // sequence is captured in a HIP graph per step count and replayed.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -30,7 +31,9 @@ struct Batch {
     int2* d_mom_items = nullptr;
     int64_t n_sweep_items = 0, n_mom_items = 0;
     int* d_counters = nullptr;          // [2]
-    int64_t coef_lanes = 0, scale_blocks = 0, bnd_lanes = 0;
+    unsigned long long* d_gmax = nullptr;   // per-group source maxima of every problem
+    int64_t n_gmax = 0, max_blocks = 0, coef_blocks = 0, bnd_lanes = 0;
+    int max_G = 1;
     std::vector<GraphEntry> graphs;
     hipStream_t capture = nullptr;
     bool profile = false;               // eager steps with events around each phase
@@ -77,7 +80,8 @@ lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
         rc = launch_zero_counters(b->d_counters, 2, st);
         if (rc == LC_OK) rc = ev_begin(b, 0, st);
         if (rc == LC_OK)
-            rc = launch_prologue_batch(b->prec, b->d_coef_args, b->n, b->coef_lanes, b->scale_blocks, t, st);
+            rc = launch_prologue_batch(b->prec, b->d_coef_args, b->n, b->max_blocks, b->coef_blocks, b->max_G,
+                                       b->d_gmax, b->n_gmax, t, st);
         if (rc == LC_OK) rc = ev_end(b, 0, st);
         if (rc == LC_OK) rc = ev_begin(b, 1, st);
         if (rc == LC_OK)
@@ -111,7 +115,7 @@ void free_batch(Batch* b) {
     if (b->capture) (void)hipStreamDestroy(b->capture);
     for (void* p : {b->d_sweep_args, b->d_coef_args, b->d_mom_args, b->d_bnd_args,
                     static_cast<void*>(b->d_sweep_items), static_cast<void*>(b->d_mom_items),
-                    static_cast<void*>(b->d_counters)})
+                    static_cast<void*>(b->d_counters), static_cast<void*>(b->d_gmax)})
         if (p) (void)hipFree(p);
     b->magic = 0;
     delete b;
@@ -199,20 +203,39 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
     // argument records
     const size_t sb = sweep_args_bytes(), cb = coef_args_bytes();
     std::vector<char> hs(2 * n_problems * sb), hc(n_problems * cb);
-    int64_t lane_off = 0, blk_off = 0;
+    for (int q = 0; q < n_problems; ++q) {
+        b->n_gmax += b->plans[q]->G;
+        b->max_G = std::max(b->max_G, b->plans[q]->G);
+    }
+    {
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&b->d_gmax), (size_t)b->n_gmax * sizeof(unsigned long long));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("hipMalloc of the batch maxima failed: %s", hipGetErrorString(e));
+            free_batch(b);
+            return LC_ERR_ALLOC;
+        }
+    }
+    int64_t g_off = 0;
     for (int q = 0; q < n_problems; ++q) {
         const lc_problem_t& P = problems[q];
         Plan* pl = b->plans[q];
         std::vector<char> two(2 * sb);
-        make_batch_args(pl, P.c_dt, P.kappa, P.planck, P.material_stride, P.state_a, P.state_b, P.I_in,
-                        P.I_exit, lane_off, blk_off, two.data(), hc.data() + q * cb);
+        make_batch_args(pl, P.c_dt, P.state_a, P.state_b, P.I_in, P.I_exit, two.data());
         std::memcpy(hs.data() + q * sb, two.data(), sb);
         std::memcpy(hs.data() + (n_problems + q) * sb, two.data() + sb, sb);
-        lane_off += (int64_t)pl->rays->cells * pl->G;
-        blk_off += pl->G;
+        int64_t nmb = 0, ncb = 0;
+        make_coef_args(pl, P.c_dt, P.kappa, P.planck, P.material_stride, P.state_a, P.state_b, P.I_in, b->d_gmax,
+                       b->max_blocks, b->coef_blocks, g_off, hc.data() + q * cb, &nmb, &ncb);
+        b->max_blocks += nmb;
+        b->coef_blocks += ncb;
+        g_off += pl->G;
     }
-    b->coef_lanes = lane_off;
-    b->scale_blocks = blk_off;
+    if (b->max_blocks >= INT32_MAX || b->coef_blocks >= INT32_MAX) {
+        set_error("batched prologue grid too large");
+        free_batch(b);
+        return LC_ERR_UNSUPPORTED;
+    }
     // work items, problems in decreasing cost
     std::vector<int> order(n_problems);
     std::iota(order.begin(), order.end(), 0);

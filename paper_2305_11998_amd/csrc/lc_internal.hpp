@@ -86,6 +86,10 @@ struct Rays {
 
 struct Plan;
 
+// Cell record of eq. (11): kappa_t and the emission kappa B / kappa_t; the
+// remaining coefficient 1/(c dt kappa_t) is formed in the sweep.
+template <typename T> struct alignas(2 * sizeof(T)) Coef { T kt, a; };
+
 struct GraphEntry {
     std::vector<uintptr_t> key;
     hipGraphExec_t exec = nullptr;
@@ -99,8 +103,9 @@ struct Plan {
     size_t hdr_bytes = 0;             // state header (per-group scale exponents)
     size_t value_bytes = 0;
     void* d_coef = nullptr;           // [cells][G] {kappa_t, kappa B / kappa_t}
+    unsigned long long* d_gmax = nullptr;  // [G] per-group source maxima of a step (float32 scale)
     int sweep_unroll = 0;             // steps whose loads are issued together (1, 2, 4)
-    int moments_entries = 0;          // C(i, m) entries gathered together (1, 2, 4)
+    int moments_entries = 0;          // C(i, m) entries per list in the moment pipeline (1..4)
     // State layout: the lanes (k, g) of pair a, g fastest, are cut into
     // bundles of 64 (one wavefront each).  For traversal d and bundle B the
     // values [t][p][lane] (t = step along the traversal, padded to the
@@ -171,15 +176,20 @@ size_t sweep_args_bytes();
 size_t coef_args_bytes();
 size_t mom_args_bytes();
 size_t bnd_args_bytes();
-void make_batch_args(Plan* pl, double c_dt, const double* kappa, const double* planck, int64_t stride,
-                     void* state_a, void* state_b, const double* I_in, double* I_exit, int64_t lane_off,
-                     int64_t blk_off, void* sweep_out2, void* coef_out);
+void make_batch_args(Plan* pl, double c_dt, void* state_a, void* state_b, const double* I_in, double* I_exit,
+                     void* sweep_out2);
+void make_coef_args(Plan* pl, double c_dt, const double* kappa, const double* planck, int64_t stride,
+                    void* state_a, void* state_b, const double* I_in, unsigned long long* gmax, int64_t max_blk_off,
+                    int64_t coef_blk_off, int64_t g_off, void* out, int64_t* n_max_blocks, int64_t* n_coef_blocks);
+lc_status launch_prologue(Plan* pl, const double* kappa, const double* planck, double c_dt,
+                          const void* state_prev, void* state_new, const double* I_in, hipStream_t st);
 void make_moment_args(Plan* pl, const void* state, const double* I_exit, const double* I_in, double c,
                       double* E, double* F, double* f, double* bnd, int64_t bnd_lane_off, void* mom_out,
                       void* bnd_out);
 int64_t moment_tiles(const Plan* pl);
-lc_status launch_prologue_batch(int prec, const void* coef_args, int n, int64_t lanes, int64_t scale_blocks,
-                                int t, hipStream_t st);
+lc_status launch_prologue_batch(int prec, const void* coef_args, int n, int64_t max_blocks_all,
+                                int64_t coef_blocks_all, int max_G, unsigned long long* gmax, int64_t n_gmax, int t,
+                                hipStream_t st);
 lc_status launch_zero_counters(int* c, int n, hipStream_t st);
 lc_status launch_sweep_batch(int prec, int pm, int unroll, const void* args, const int2* items, int64_t n_items,
                              int* counter, hipStream_t st);

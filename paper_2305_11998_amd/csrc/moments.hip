@@ -53,6 +53,30 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t hw, int64_t n) {
     return x * q + (x < r ? x : r) + i;
 }
 
+// State offsets and area weight of one C(i, m) entry as seen by lane g.
+// A slot past the end of its list reads entry 0 (which always exists) with
+// weight 0 and ok = false, so no load of a slot ever leaves the arrays.
+template <typename T> struct Slot {
+    size_t o0, o1;   // offsets of this lane's value in the two traversals
+    T w;
+    bool ok;
+};
+
+template <typename T>
+__device__ __forceinline__ Slot<T> load_slot(const long long* __restrict__ eo, const T* __restrict__ cw, int e,
+                                             bool ok, int g) {
+    Slot<T> s;
+    const int ee = ok ? e : 0;
+    s.ok = ok;
+    s.w = ok ? cw[ee] : (T)0;
+    const long long* r = eo + (size_t)ee * 4;
+    const long long oa = r[0];
+    const bool first = g < kWave - (int)(oa & (kWave - 1));
+    s.o0 = (size_t)(first ? oa : r[1]) + g;
+    s.o1 = (size_t)(first ? r[2] : r[3]) + g;
+    return s;
+}
+
 // One workgroup per ts x ts tile of cells; lane (cell, g).  For each azimuth
 // pair the lane gathers the segment averages of the characteristics crossing
 // its cell (the C(i, m) list, in (k, s) order) with the area weights, giving
@@ -60,8 +84,14 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t hw, int64_t n) {
 // contribution to the seven angular moments (compensated float32 or plain
 // float64 sums, fixed order).  A characteristic crosses several cells of a
 // tile in consecutive steps, whose state rows are adjacent in memory, so the
-// tile's lanes share the cache lines they fetch.  PM bounds the polar count.
-template <typename T, int PM, int kEnt>
+// tile's lanes share the cache lines they fetch.
+//
+// The loads are pipelined over pairs: while the state values of pair a are
+// in flight, the entry offsets of pair a+1 and the list end of pair a+2 are
+// fetched, so a pair costs about one memory round trip.  The first K entries
+// of a list go through the pipeline; longer lists finish in a plain loop.
+// The sums run in list order whatever K is.  PM bounds the polar count.
+template <typename T, int PM, int K>
 __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int tid) {
     const int G = A.G;
     const int P = A.P;
@@ -74,47 +104,54 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
     if (cx >= A.nx || cy >= A.ny) return;
     const int cell = cy * A.nx + cx;
     const int cells = A.nx * A.ny;
+    const int np = A.n_pairs;
     const T* __restrict__ st = static_cast<const T*>(A.state);
     const T* __restrict__ cw = static_cast<const T*>(A.csr_w);
     const long long* __restrict__ eo = A.ent_off;
+    const int* __restrict__ co = A.csr_off + (size_t)cell * np;
     Acc<T> acc[7];
-    for (int a = 0; a < A.n_pairs; ++a) {
-        const int e0 = A.csr_off[(size_t)cell * A.n_pairs + a];
-        const int e1 = A.csr_off[(size_t)cell * A.n_pairs + a + 1];
+    // list bounds: pair a is [b0, b1), pair a+1 is [b1, b2)
+    int b0 = co[0], b1 = co[1];
+    int b2 = np > 1 ? co[2] : b1;
+    Slot<T> cur[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) cur[u] = load_slot(eo, cw, b0 + u, b0 + u < b1, g);
+    for (int a = 0; a < np; ++a) {
+        T x[K][2][PM];
+#pragma unroll
+        for (int u = 0; u < K; ++u)
+#pragma unroll
+            for (int p = 0; p < PM; ++p) {
+                const bool ld = cur[u].ok && p < P;
+                x[u][0][p] = ld ? st[cur[u].o0 + p * kWave] : (T)0;
+                x[u][1][p] = ld ? st[cur[u].o1 + p * kWave] : (T)0;
+            }
+        const bool more = a + 1 < np;
+        Slot<T> nxt[K];
+#pragma unroll
+        for (int u = 0; u < K; ++u) nxt[u] = load_slot(eo, cw, b1 + u, more && b1 + u < b2, g);
+        const int b3 = a + 3 <= np ? co[a + 3] : b2;
         T Iim[2][PM];
 #pragma unroll
         for (int d = 0; d < 2; ++d)
 #pragma unroll
             for (int p = 0; p < PM; ++p) Iim[d][p] = (T)0;
-        for (int eb = e0; eb < e1; eb += kEnt) {
-            T w[kEnt];
-            size_t o[kEnt][2];
 #pragma unroll
-            for (int u = 0; u < kEnt; ++u) {
-                const bool ok = eb + u < e1;
-                const int e = ok ? eb + u : e0;
-                w[u] = ok ? cw[e] : (T)0;
-                const long long* r = eo + (size_t)e * 4;
-                const long long oa = r[0];
-                const bool first = g < kWave - (int)(oa & (kWave - 1));
-                o[u][0] = (size_t)(first ? oa : r[1]) + g;
-                o[u][1] = (size_t)(first ? r[2] : r[3]) + g;
+        for (int u = 0; u < K; ++u)
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+#pragma unroll
+                for (int p = 0; p < PM; ++p) Iim[d][p] += cur[u].w * x[u][d][p];
+        for (int e = b0 + K; e < b1; ++e) {
+            const Slot<T> t = load_slot(eo, cw, e, true, g);
+#pragma unroll
+            for (int p = 0; p < PM; ++p) {
+                if (p >= P) continue;
+                Iim[0][p] += t.w * st[t.o0 + p * kWave];
+                Iim[1][p] += t.w * st[t.o1 + p * kWave];
             }
-            T x[kEnt][2][PM];
-#pragma unroll
-            for (int u = 0; u < kEnt; ++u)
-#pragma unroll
-                for (int d = 0; d < 2; ++d)
-#pragma unroll
-                    for (int p = 0; p < PM; ++p) x[u][d][p] = p < P ? st[o[u][d] + p * kWave] : (T)0;
-#pragma unroll
-            for (int u = 0; u < kEnt; ++u)
-#pragma unroll
-                for (int d = 0; d < 2; ++d)
-#pragma unroll
-                    for (int p = 0; p < PM; ++p) Iim[d][p] += w[u] * x[u][d][p];
         }
-        T part[7];
+    T part[7];
 #pragma unroll
         for (int c = 0; c < 7; ++c) part[c] = (T)0;
 #pragma unroll
@@ -128,6 +165,11 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
             }
 #pragma unroll
         for (int c = 0; c < 7; ++c) acc[c].add(part[c]);
+#pragma unroll
+        for (int u = 0; u < K; ++u) cur[u] = nxt[u];
+        b0 = b1;
+        b1 = b2;
+        b2 = b3;
     }
     double sc = 1.0;
     if (sizeof(T) == 4) sc = ldexp(1.0, A.e[g]);
@@ -148,14 +190,14 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
     }
 }
 
-template <typename T, int PM, int kEnt>
+template <typename T, int PM, int K>
 __global__ __launch_bounds__(1024) void k_cell_moments(MomArgs A) {
-    moments_tile<T, PM, kEnt>(A, xcd_logical_block(blockIdx.x, A.n_tiles), threadIdx.x);
+    moments_tile<T, PM, K>(A, xcd_logical_block(blockIdx.x, A.n_tiles), threadIdx.x);
 }
 
 // Batched form: persistent workgroups take (problem, tile) items from an
 // integer counter in item-list order.
-template <typename T, int PM, int kEnt>
+template <typename T, int PM, int K>
 __global__ __launch_bounds__(1024) void k_cell_moments_batch(const MomArgs* __restrict__ probs,
                                                              const int2* __restrict__ items, int64_t n_items,
                                                              int* counter) {
@@ -163,11 +205,12 @@ __global__ __launch_bounds__(1024) void k_cell_moments_batch(const MomArgs* __re
     for (;;) {
         if (threadIdx.x == 0) s_it = atomicAdd(counter, 1);
         __syncthreads();
-        const int it = s_it;
+        const int it = __builtin_amdgcn_readfirstlane(s_it);
         __syncthreads();
         if (it >= n_items) break;
-        const int2 item = items[it];
-        moments_tile<T, PM, kEnt>(probs[item.x], item.y, threadIdx.x);
+        const int pr = __builtin_amdgcn_readfirstlane(items[it].x);
+        const int tl = __builtin_amdgcn_readfirstlane(items[it].y);
+        moments_tile<T, PM, K>(probs[pr], tl, threadIdx.x);
     }
 }
 
@@ -296,8 +339,9 @@ void launch_cell_moments_e(int ent, const MomArgs& A, hipStream_t st) {
     dim3 grid((unsigned)A.n_tiles), block(threads);
     switch (ent) {
         case 1: hipLaunchKernelGGL((k_cell_moments<T, P, 1>), grid, block, 0, st, A); break;
+        case 2: hipLaunchKernelGGL((k_cell_moments<T, P, 2>), grid, block, 0, st, A); break;
         case 4: hipLaunchKernelGGL((k_cell_moments<T, P, 4>), grid, block, 0, st, A); break;
-        default: hipLaunchKernelGGL((k_cell_moments<T, P, 2>), grid, block, 0, st, A); break;
+        default: hipLaunchKernelGGL((k_cell_moments<T, P, 3>), grid, block, 0, st, A); break;
     }
 }
 
@@ -400,7 +444,7 @@ lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, cons
 
 namespace {
 
-template <typename T, int PM, int kEnt>
+template <typename T, int PM, int K>
 lc_status launch_moments_batch_e(const void* args, const int2* items, int64_t n_items, int* counter,
                                  hipStream_t st) {
     static int grid = 0;
@@ -409,10 +453,10 @@ lc_status launch_moments_batch_e(const void* args, const int2* items, int64_t n_
         LC_HIP(hipGetDevice(&dev));
         LC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         LC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(&k_cell_moments_batch<T, PM, kEnt>), 1024, 0));
+            &per_cu, reinterpret_cast<const void*>(&k_cell_moments_batch<T, PM, K>), 1024, 0));
         grid = std::max(1, cus * std::max(per_cu, 1));
     }
-    hipLaunchKernelGGL((k_cell_moments_batch<T, PM, kEnt>), dim3(grid), dim3(1024), 0, st,
+    hipLaunchKernelGGL((k_cell_moments_batch<T, PM, K>), dim3(grid), dim3(1024), 0, st,
                        static_cast<const MomArgs*>(args), items, n_items, counter);
     LC_HIP(hipGetLastError());
     return LC_OK;
@@ -423,8 +467,9 @@ lc_status launch_moments_batch_p(int ent, const void* args, const int2* items, i
                                  hipStream_t st) {
     switch (ent) {
         case 1: return launch_moments_batch_e<T, PM, 1>(args, items, n, counter, st);
+        case 2: return launch_moments_batch_e<T, PM, 2>(args, items, n, counter, st);
         case 4: return launch_moments_batch_e<T, PM, 4>(args, items, n, counter, st);
-        default: return launch_moments_batch_e<T, PM, 2>(args, items, n, counter, st);
+        default: return launch_moments_batch_e<T, PM, 3>(args, items, n, counter, st);
     }
 }
 

@@ -20,10 +20,6 @@
 namespace lc {
 namespace {
 
-// Cell record of eq. (11): kappa_t and the emission kappa B / kappa_t; the
-// remaining coefficient 1/(c dt kappa_t) is formed in the sweep.
-template <typename T> struct alignas(2 * sizeof(T)) Coef { T kt, a; };
-
 struct SweepArgs {
     const int* bun_off;      // [n_pairs + 1] first bundle of each pair
     const int* bun_len;      // [n_bun] steps of each bundle
@@ -286,118 +282,6 @@ __global__ __launch_bounds__(kBlock) void k_sweep_batch(const SweepArgs* __restr
     }
 }
 
-// Coefficients of eq. (11) per (cell, g): kappa_t = kappa + 1/(c dt) and
-// a = kappa B / kappa_t, so that Q / kappa_t = a + I_bar^{n-1} / (c dt kappa_t).
-// float32 tables carry the per-group power-of-two scale of the new state.
-template <typename T>
-__global__ void k_coef(const double* __restrict__ kappa, const double* __restrict__ planck,
-                       double c_dt, int cells, int G, const int* __restrict__ e_new, Coef<T>* coef) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= (int64_t)cells * G) return;
-    const int g = (int)(i / cells);
-    const int c = (int)(i - (int64_t)g * cells);
-    const double kap = kappa[i];
-    const double kt = kap + 1.0 / c_dt;
-    double a = kap * planck[i] / kt;
-    if (sizeof(T) == 4) a = ldexp(a, -e_new[g]);
-    Coef<T> r;
-    r.kt = (T)kt;
-    r.a = (T)a;
-    coef[(size_t)c * G + g] = r;
-}
-
-// Per-group scale of the new float32 state: the stored values never exceed
-// max(I_in, B, previous state) (each step's segment average is a convex
-// combination of those), so the exponent is raised to cover the new sources
-// and never lowered.
-__global__ void k_scale(const double* __restrict__ planck, const double* __restrict__ I_in, int cells,
-                        int G, int64_t n_in, const int* __restrict__ e_prev, int* e_new) {
-    __shared__ double sh[kBlock];
-    const int g = blockIdx.x;
-    double m = 0.0;
-    for (int64_t i = threadIdx.x; i < cells; i += kBlock) m = fmax(m, fabs(planck[(int64_t)g * cells + i]));
-    for (int64_t i = threadIdx.x; i < n_in; i += kBlock) m = fmax(m, fabs(I_in[i * G + g]));
-    sh[threadIdx.x] = m;
-    __syncthreads();
-    for (int o = kBlock / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        int e = e_prev[g];
-        if (sh[0] > 0.0 && isfinite(sh[0])) e = max(e, ilogb(sh[0]) + 1);
-        e_new[g] = e;
-    }
-}
-
-// ---- batched prologue -----------------------------------------------------------
-struct CoefArgs {
-    const double* kappa;     // step t at kappa + t * stride
-    const double* planck;
-    int64_t stride;
-    double c_dt;
-    int cells, G;
-    int64_t n_in;            // nb * M
-    const double* I_in;
-    const int* e_state[2];   // headers of state_a, state_b
-    void* coef;
-    int64_t lane_off;        // first flat lane of this problem (cells * G lanes)
-    int64_t blk_off;         // first block of this problem in the scale launch (G blocks)
-};
-
-__device__ __forceinline__ int find_prob(const CoefArgs* __restrict__ P, int n, int64_t v, bool blocks) {
-    int lo = 0, hi = n;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if ((blocks ? P[mid].blk_off : P[mid].lane_off) <= v) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-// Step t reads state (t % 2 == 0 ? a : b) and writes the other one.
-__global__ void k_scale_batch(const CoefArgs* __restrict__ P, int n, int t) {
-    __shared__ double sh[kBlock];
-    const int q = find_prob(P, n, blockIdx.x, true);
-    const CoefArgs& A = P[q];
-    const int g = (int)(blockIdx.x - A.blk_off);
-    const double* planck = A.planck + (int64_t)t * A.stride;
-    double m = 0.0;
-    for (int64_t i = threadIdx.x; i < A.cells; i += kBlock) m = fmax(m, fabs(planck[(int64_t)g * A.cells + i]));
-    for (int64_t i = threadIdx.x; i < A.n_in; i += kBlock) m = fmax(m, fabs(A.I_in[i * A.G + g]));
-    sh[threadIdx.x] = m;
-    __syncthreads();
-    for (int o = kBlock / 2; o > 0; o >>= 1) {
-        if (threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const int* e_prev = A.e_state[t & 1];
-        int* e_new = const_cast<int*>(A.e_state[(t + 1) & 1]);
-        int e = e_prev[g];
-        if (sh[0] > 0.0 && isfinite(sh[0])) e = max(e, ilogb(sh[0]) + 1);
-        e_new[g] = e;
-    }
-}
-
-template <typename T>
-__global__ void k_coef_batch(const CoefArgs* __restrict__ P, int n, int64_t lanes, int t) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= lanes) return;
-    const int q = find_prob(P, n, i, false);
-    const CoefArgs& A = P[q];
-    const int64_t li = i - A.lane_off;
-    const int g = (int)(li / A.cells);
-    const int c = (int)(li - (int64_t)g * A.cells);
-    const double kap = A.kappa[(int64_t)t * A.stride + li];
-    const double kt = kap + 1.0 / A.c_dt;
-    double a = kap * A.planck[(int64_t)t * A.stride + li] / kt;
-    if (sizeof(T) == 4) a = ldexp(a, -A.e_state[(t + 1) & 1][g]);
-    Coef<T> r;
-    r.kt = (T)kt;
-    r.a = (T)a;
-    static_cast<Coef<T>*>(A.coef)[(size_t)c * A.G + g] = r;
-}
-
 __global__ void k_zero_counter(int* c, int n) {
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
 }
@@ -464,12 +348,10 @@ lc_status launch_sweep_batch_p(int unroll, const void* args, const int2* items, 
 }  // namespace
 
 size_t sweep_args_bytes() { return sizeof(SweepArgs); }
-size_t coef_args_bytes() { return sizeof(CoefArgs); }
 
-// Host copies of the argument records of one problem of a batch.
-void make_batch_args(Plan* pl, double c_dt, const double* kappa, const double* planck, int64_t stride,
-                     void* state_a, void* state_b, const double* I_in, double* I_exit, int64_t lane_off,
-                     int64_t blk_off, void* sweep_out2, void* coef_out) {
+// Host copies of the sweep records of one problem of a batch (one per step parity).
+void make_batch_args(Plan* pl, double c_dt, void* state_a, void* state_b, const double* I_in, double* I_exit,
+                     void* sweep_out2) {
     Rays* r = pl->rays;
     const bool f32 = pl->prec == LC_F32;
     for (int parity = 0; parity < 2; ++parity) {
@@ -504,35 +386,6 @@ void make_batch_args(Plan* pl, double c_dt, const double* kappa, const double* p
         for (int p = 0; p < r->n_pol; ++p) A.inv_sinz[p] = r->inv_sinz[p];
         std::memcpy(static_cast<char*>(sweep_out2) + parity * sizeof(SweepArgs), &A, sizeof(A));
     }
-    CoefArgs C{};
-    C.kappa = kappa;
-    C.planck = planck;
-    C.stride = stride;
-    C.c_dt = c_dt;
-    C.cells = r->cells;
-    C.G = pl->G;
-    C.n_in = (int64_t)r->nb * r->n_az * r->n_pol;
-    C.I_in = I_in;
-    C.e_state[0] = static_cast<const int*>(state_a);
-    C.e_state[1] = static_cast<const int*>(state_b);
-    C.coef = pl->d_coef;
-    C.lane_off = lane_off;
-    C.blk_off = blk_off;
-    std::memcpy(coef_out, &C, sizeof(C));
-}
-
-// Prologue of step t of a batch: per-group scales (float32) and coefficients.
-lc_status launch_prologue_batch(int prec, const void* coef_args, int n, int64_t lanes, int64_t scale_blocks,
-                                int t, hipStream_t st) {
-    const CoefArgs* P = static_cast<const CoefArgs*>(coef_args);
-    if (prec == LC_F32) {
-        hipLaunchKernelGGL(k_scale_batch, dim3((unsigned)scale_blocks), dim3(kBlock), 0, st, P, n, t);
-        hipLaunchKernelGGL(k_coef_batch<float>, dim3(nblk(lanes)), dim3(kBlock), 0, st, P, n, lanes, t);
-    } else {
-        hipLaunchKernelGGL(k_coef_batch<double>, dim3(nblk(lanes)), dim3(kBlock), 0, st, P, n, lanes, t);
-    }
-    LC_HIP(hipGetLastError());
-    return LC_OK;
 }
 
 lc_status launch_zero_counters(int* c, int n, hipStream_t st) {
@@ -597,18 +450,8 @@ lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, doub
     const bool f32 = pl->prec == LC_F32;
     const int* e_prev = static_cast<const int*>(state_prev);   // header: per-group exponents
     int* e_new = static_cast<int*>(state_new);
-    if (f32) {
-        hipLaunchKernelGGL(k_scale, dim3(G), dim3(kBlock), 0, st, planck, I_in, r->cells, G,
-                           (int64_t)r->nb * r->n_az * r->n_pol, e_prev, e_new);
-        hipLaunchKernelGGL(k_coef<float>, dim3(nblk((int64_t)r->cells * G)), dim3(kBlock), 0, st,
-                           kappa, planck, c_dt, r->cells, G, e_new,
-                           static_cast<Coef<float>*>(pl->d_coef));
-    } else {
-        hipLaunchKernelGGL(k_coef<double>, dim3(nblk((int64_t)r->cells * G)), dim3(kBlock), 0, st,
-                           kappa, planck, c_dt, r->cells, G, nullptr,
-                           static_cast<Coef<double>*>(pl->d_coef));
-    }
-    LC_HIP(hipGetLastError());
+    lc_status rc = launch_prologue(pl, kappa, planck, c_dt, state_prev, state_new, I_in, st);
+    if (rc) return rc;
     SweepArgs A{};
     A.bun_off = pl->d_bun_off;
     A.bun_len = pl->d_bun_len;

@@ -18,7 +18,9 @@ import os
 
 from . import lc
 
-CANDIDATES = (1, 2, 4)
+SWEEP_CANDIDATES = (1, 2, 4)
+MOMENT_CANDIDATES = (1, 2, 3, 4)
+BASE = (2, 3)             # the setting the other parameter is held at while one is searched
 DEFAULT_CACHE = os.environ.get(
     "LC_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "lc_tuning.json"))
 
@@ -26,7 +28,7 @@ DEFAULT_CACHE = os.environ.get(
 def shape_key(plan) -> str:
     r = plan.rays
     b = lambda x: int(round(math.log2(max(int(x), 1))))
-    return (f"prec{plan.prec}-G{plan.G}-P{r.n_pol}-A{r.n_pairs}-"
+    return (f"v{lc.lc_version()}-prec{plan.prec}-G{plan.G}-P{r.n_pol}-A{r.n_pairs}-"
             f"c{b(r.cells)}-s{b(r.n_segments)}")
 
 
@@ -62,8 +64,8 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
         lc.lc_plan_set_tuning(plan, t["sweep_unroll"], t["moments_entries"])
         return dict(t, cached=True, key=key)
     times = {}
-    # the two parameters act on different kernels: vary one with the other at 2
-    combos = sorted({(u, 2) for u in CANDIDATES} | {(2, e) for e in CANDIDATES})
+    # the two parameters act on different kernels: vary one with the other fixed
+    combos = sorted({(u, BASE[1]) for u in SWEEP_CANDIDATES} | {(BASE[0], e) for e in MOMENT_CANDIDATES})
     for u, e in combos:
         lc.lc_plan_set_tuning(plan, u, e)
         solver.bench_step()                       # warm
@@ -79,8 +81,8 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
         if verbose:
             print(f"  tune {key}: unroll {u} entries {e}: sweep {times[(u, e)][0]:.3f} ms, "
                   f"moments {times[(u, e)][1]:.3f} ms", file=sys.stderr, flush=True)
-    best_u = min(CANDIDATES, key=lambda u: times[(u, 2)][0])
-    best_e = min(CANDIDATES, key=lambda e: times[(2, e)][1])
+    best_u = min(SWEEP_CANDIDATES, key=lambda u: times[(u, BASE[1])][0])
+    best_e = min(MOMENT_CANDIDATES, key=lambda e: times[(BASE[0], e)][1])
     lc.lc_plan_set_tuning(plan, best_u, best_e)
     res = dict(sweep_unroll=best_u, moments_entries=best_e,
                sweep_ms={str(k): v[0] for k, v in times.items()},
@@ -97,7 +99,7 @@ def tune_batch(bs, steps: int = 2, verbose: bool = False):
     left rebuilt with the choice."""
     import torch
     times = {}
-    combos = sorted({(u, 2) for u in CANDIDATES} | {(2, e) for e in CANDIDATES})
+    combos = sorted({(u, BASE[1]) for u in SWEEP_CANDIDATES} | {(BASE[0], e) for e in MOMENT_CANDIDATES})
     for u, e in combos:
         bs.rebuild((u, e))
         lc.lc_batch_profile(bs.batch, True)
@@ -110,8 +112,8 @@ def tune_batch(bs, steps: int = 2, verbose: bool = False):
         if verbose:
             print(f"  tune batch: unroll {u} entries {e}: sweep {times[(u, e)][0]:.3f} ms, "
                   f"moments {times[(u, e)][1]:.3f} ms", file=sys.stderr, flush=True)
-    best_u = min(CANDIDATES, key=lambda u: times[(u, 2)][0])
-    best_e = min(CANDIDATES, key=lambda e: times[(2, e)][1])
+    best_u = min(SWEEP_CANDIDATES, key=lambda u: times[(u, BASE[1])][0])
+    best_e = min(MOMENT_CANDIDATES, key=lambda e: times[(BASE[0], e)][1])
     bs.rebuild((best_u, best_e))
     return dict(sweep_unroll=best_u, moments_entries=best_e,
                 sweep_ms={str(k): v[0] for k, v in times.items()},

@@ -184,6 +184,32 @@ def test_graph_equals_eager_and_is_deterministic(lcmod):
         assert np.array_equal(st, out[0][1])
 
 
+@pytest.mark.parametrize("prec,mode,h_moc", [(1, 0, 0.04), (1, 1, 0.04), (0, 0, 0.015)])
+def test_tuning_settings_give_identical_results(lcmod, prec, mode, h_moc):
+    """Every launch tuning gives bit-identical moments, boundary factors and
+    state.  Tube grids and fine spacing make (cell, pair) lists longer than the
+    moment kernel's pipelined slots, so its tail loop is covered too."""
+    lc, driver = lcmod
+    prob = _custom_problem(h_moc=h_moc, steps=2)
+    s = driver.Solver(prob, prec=prec, mode=mode)
+    ro, so, ce, _, _, _ = lc.lc_rays_export(s.rays)
+    longest = max(int(np.bincount(ce[so[ro[a]]:so[ro[a + 1]]]).max()) for a in range(len(ro) - 1))
+    _say(f"  longest (cell, pair) list: {longest}")
+    if mode == 1 or h_moc < 0.02:
+        assert longest > 4                      # the tail loop runs
+    out = []
+    for u, e in [(2, 3), (1, 1), (4, 2), (2, 4), (1, 3)]:
+        _say(f"case tuning prec={prec} mode={mode} h_moc={h_moc}: unroll {u} entries {e}")
+        lc.lc_plan_set_tuning(s.plan, u, e)
+        s.reset()
+        s.step(2, graph=False)
+        out.append((s.moments(), s.state_canonical()))
+    for m, st in out[1:]:
+        for k in ("E", "F", "f", "bnd"):
+            assert np.array_equal(m[k], out[0][0][k])
+        assert np.array_equal(st, out[0][1])
+
+
 def _sampled_cells(prob, n, seed):
     rng = np.random.default_rng(seed)
     cells = list(rng.choice(prob.cells, n - 2, replace=False))
