@@ -1,8 +1,8 @@
 // Batched form: many independent problems advanced together.  Each phase of a
 // time step is one launch over all problems: the coefficient prologue, one
 // persistent sweep kernel whose wavefronts pull (problem, wavefront) items
-// from an integer counter, one persistent cell-moment kernel pulling
-// (problem, tile) items, and the boundary factors.  Items are ordered by
+// from an integer counter, one cell-moment launch over the (problem, tile
+// wavefront) items of every problem, and the boundary factors.  Items are ordered by
 // problem cost, largest first, so the small problems fill the tail.  The step
 // sequence is captured in a HIP graph per step count and replayed.
 #include <algorithm>
@@ -16,6 +16,8 @@
 namespace lc {
 namespace {
 
+constexpr int kCounters = 1;
+
 struct Batch {
     uint32_t magic = 0;
     int n = 0, prec = 0, pm = 1, unroll = 4, ent = 2;
@@ -28,9 +30,9 @@ struct Batch {
     void* d_mom_args = nullptr;         // [2][n]
     void* d_bnd_args = nullptr;         // [n]
     int2* d_sweep_items = nullptr;
-    int2* d_mom_items = nullptr;
+    int2* d_mom_items = nullptr;        // {problem, wavefront of a tile}
     int64_t n_sweep_items = 0, n_mom_items = 0;
-    int* d_counters = nullptr;          // [2]
+    int* d_counters = nullptr;          // [kCounters]: the sweep's item counter
     unsigned long long* d_gmax = nullptr;   // per-group source maxima of every problem
     int64_t n_gmax = 0, max_blocks = 0, coef_blocks = 0, bnd_lanes = 0;
     int max_G = 1;
@@ -77,7 +79,7 @@ lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
     lc_status rc = LC_OK;
     for (int t = 0; t < n_steps && rc == LC_OK; ++t) {
         const int parity = t & 1;
-        rc = launch_zero_counters(b->d_counters, 2, st);
+        rc = launch_zero_counters(b->d_counters, kCounters, st);
         if (rc == LC_OK) rc = ev_begin(b, 0, st);
         if (rc == LC_OK)
             rc = launch_prologue_batch(b->prec, b->d_coef_args, b->n, b->max_blocks, b->coef_blocks, b->max_G,
@@ -94,7 +96,7 @@ lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
             if (rc == LC_OK)
                 rc = launch_moments_batch(b->prec, b->pm, b->ent,
                                           static_cast<char*>(b->d_mom_args) + parity * b->n * mb,
-                                          b->d_mom_items, b->n_mom_items, b->d_counters + 1, st);
+                                          b->d_mom_items, b->n_mom_items, st);
             if (rc == LC_OK) rc = ev_end(b, 2, st);
             if (rc == LC_OK && b->bnd_lanes > 0) rc = launch_boundary_batch(b->d_bnd_args, b->n, b->bnd_lanes, st);
         }
@@ -245,16 +247,24 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
     for (int q : order) {
         const Plan* pl = b->plans[q];
         for (int64_t w = 0; w < 2 * pl->n_bun; ++w) si.push_back(make_int2(q, (int)w));
-        for (int64_t t = 0; t < moment_tiles(pl); ++t) mi.push_back(make_int2(q, (int)t));
+        const int64_t mw = moment_tiles(pl) * moment_tile_waves(pl);
+        if (mw >= INT32_MAX) rc = LC_ERR_UNSUPPORTED;
+        for (int64_t w = 0; w < mw && rc == LC_OK; ++w) mi.push_back(make_int2(q, (int)w));
+    }
+    if (rc != LC_OK) set_error("batched moments: too many work items in one problem");
+    if (rc == LC_OK && (int64_t)mi.size() / 4 >= INT32_MAX / 2) {
+        rc = LC_ERR_UNSUPPORTED;
+        set_error("batched moments: grid too large");
     }
     b->n_sweep_items = (int64_t)si.size();
     b->n_mom_items = (int64_t)mi.size();
+
     if (rc == LC_OK) rc = upload(&b->d_sweep_args, hs.data(), hs.size());
     if (rc == LC_OK) rc = upload(&b->d_coef_args, hc.data(), hc.size());
     if (rc == LC_OK) rc = upload(reinterpret_cast<void**>(&b->d_sweep_items), si.data(), si.size() * sizeof(int2));
     if (rc == LC_OK) rc = upload(reinterpret_cast<void**>(&b->d_mom_items), mi.data(), mi.size() * sizeof(int2));
     if (rc == LC_OK) {
-        int zero[2] = {0, 0};
+        int zero[kCounters] = {};
         rc = upload(reinterpret_cast<void**>(&b->d_counters), zero, sizeof(zero));
     }
     if (rc == LC_OK) rc = build_moment_args(b, 1.0);

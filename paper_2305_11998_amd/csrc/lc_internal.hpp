@@ -187,6 +187,7 @@ void make_moment_args(Plan* pl, const void* state, const double* I_exit, const d
                       double* E, double* F, double* f, double* bnd, int64_t bnd_lane_off, void* mom_out,
                       void* bnd_out);
 int64_t moment_tiles(const Plan* pl);
+int moment_tile_waves(const Plan* pl);
 lc_status launch_prologue_batch(int prec, const void* coef_args, int n, int64_t max_blocks_all,
                                 int64_t coef_blocks_all, int max_G, unsigned long long* gmax, int64_t n_gmax, int t,
                                 hipStream_t st);
@@ -194,7 +195,7 @@ lc_status launch_zero_counters(int* c, int n, hipStream_t st);
 lc_status launch_sweep_batch(int prec, int pm, int unroll, const void* args, const int2* items, int64_t n_items,
                              int* counter, hipStream_t st);
 lc_status launch_moments_batch(int prec, int pm, int ent, const void* args, const int2* items, int64_t n_items,
-                               int* counter, hipStream_t st);
+                               hipStream_t st);
 lc_status launch_boundary_batch(const void* args, int n, int64_t lanes, hipStream_t st);
 
 // Device pointers to the values of a state buffer (after its header).

@@ -21,6 +21,7 @@ struct MomArgs {
     const void* state;        // values
     const int* e;             // per-group exponents of the state (float32 only)
     int nx, ny, G, P, n_pairs, ts, tiles_x;
+    int wpt;                  // wavefronts per tile (ts * ts * G lanes)
     int64_t n_tiles;
     double inv_c;
     double* E;
@@ -45,6 +46,9 @@ template <> struct Acc<float> {
     __device__ double value() const { return (double)s - (double)c; }
 };
 
+constexpr int kMomWaves = 4;   // wavefronts per block of the moment kernels
+constexpr int kXcdRun = 16;    // consecutive blocks per XCD in the batched moment launch
+
 // Hardware hands workgroups to the 8 XCDs round-robin; give each XCD a
 // contiguous range of tiles so that neighbouring tiles share an L2.
 __device__ __forceinline__ int64_t xcd_logical_block(int64_t hw, int64_t n) {
@@ -53,27 +57,31 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t hw, int64_t n) {
     return x * q + (x < r ? x : r) + i;
 }
 
+// Loads of the moment kernels go through global (address space 1) pointers,
+// so the compiler emits global rather than flat loads even where the
+// pointers come from an argument record in memory.
+template <typename T> using gptr = const __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<T> as_global(const T* p) { return (gptr<T>)p; }
+
 // State offsets and area weight of one C(i, m) entry as seen by lane g.
-// A slot past the end of its list reads entry 0 (which always exists) with
-// weight 0 and ok = false, so no load of a slot ever leaves the arrays.
+// A slot past the end of its list reads entry 0 (which always exists) and
+// gets weight 0, so every load is unconditional and stays inside the arrays.
 template <typename T> struct Slot {
     size_t o0, o1;   // offsets of this lane's value in the two traversals
     T w;
-    bool ok;
 };
 
 template <typename T>
-__device__ __forceinline__ Slot<T> load_slot(const long long* __restrict__ eo, const T* __restrict__ cw, int e,
-                                             bool ok, int g) {
+__device__ __forceinline__ Slot<T> load_slot(gptr<long long> eo, gptr<T> cw, int e, bool ok, int g) {
     Slot<T> s;
     const int ee = ok ? e : 0;
-    s.ok = ok;
-    s.w = ok ? cw[ee] : (T)0;
-    const long long* r = eo + (size_t)ee * 4;
-    const long long oa = r[0];
-    const bool first = g < kWave - (int)(oa & (kWave - 1));
-    s.o0 = (size_t)(first ? oa : r[1]) + g;
-    s.o1 = (size_t)(first ? r[2] : r[3]) + g;
+    const T w = cw[ee];
+    const long long r0 = eo[(size_t)ee * 4 + 0], r1 = eo[(size_t)ee * 4 + 1];
+    const long long r2 = eo[(size_t)ee * 4 + 2], r3 = eo[(size_t)ee * 4 + 3];
+    const bool first = g < kWave - (int)(r0 & (kWave - 1));
+    s.w = ok ? w : (T)0;
+    s.o0 = (size_t)(first ? r0 : r1) + g;
+    s.o1 = (size_t)(first ? r2 : r3) + g;
     return s;
 }
 
@@ -105,14 +113,14 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
     const int cell = cy * A.nx + cx;
     const int cells = A.nx * A.ny;
     const int np = A.n_pairs;
-    const T* __restrict__ st = static_cast<const T*>(A.state);
-    const T* __restrict__ cw = static_cast<const T*>(A.csr_w);
-    const long long* __restrict__ eo = A.ent_off;
-    const int* __restrict__ co = A.csr_off + (size_t)cell * np;
+    const gptr<T> st = as_global(static_cast<const T*>(A.state));
+    const gptr<T> cw = as_global(static_cast<const T*>(A.csr_w));
+    const gptr<long long> eo = as_global(A.ent_off);
+    const gptr<int> co = as_global(A.csr_off + (size_t)cell * np);
     Acc<T> acc[7];
     // list bounds: pair a is [b0, b1), pair a+1 is [b1, b2)
     int b0 = co[0], b1 = co[1];
-    int b2 = np > 1 ? co[2] : b1;
+    int b2 = co[min(2, np)];
     Slot<T> cur[K];
 #pragma unroll
     for (int u = 0; u < K; ++u) cur[u] = load_slot(eo, cw, b0 + u, b0 + u < b1, g);
@@ -122,15 +130,14 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
         for (int u = 0; u < K; ++u)
 #pragma unroll
             for (int p = 0; p < PM; ++p) {
-                const bool ld = cur[u].ok && p < P;
-                x[u][0][p] = ld ? st[cur[u].o0 + p * kWave] : (T)0;
-                x[u][1][p] = ld ? st[cur[u].o1 + p * kWave] : (T)0;
+                x[u][0][p] = p < P ? st[cur[u].o0 + p * kWave] : (T)0;
+                x[u][1][p] = p < P ? st[cur[u].o1 + p * kWave] : (T)0;
             }
         const bool more = a + 1 < np;
         Slot<T> nxt[K];
 #pragma unroll
         for (int u = 0; u < K; ++u) nxt[u] = load_slot(eo, cw, b1 + u, more && b1 + u < b2, g);
-        const int b3 = a + 3 <= np ? co[a + 3] : b2;
+        const int b3 = co[min(a + 3, np)];
         T Iim[2][PM];
 #pragma unroll
         for (int d = 0; d < 2; ++d)
@@ -159,7 +166,7 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
 #pragma unroll
             for (int p = 0; p < PM; ++p) {
                 if (p >= P) continue;
-                const double* dw = A.dirw + (((size_t)a * 2 + d) * P + p) * kDirW;
+                const gptr<double> dw = as_global(A.dirw + (((size_t)a * 2 + d) * P + p) * kDirW);
 #pragma unroll
                 for (int c = 0; c < 7; ++c) part[c] += (T)dw[c] * Iim[d][p];
             }
@@ -172,46 +179,62 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
         b2 = b3;
     }
     double sc = 1.0;
-    if (sizeof(T) == 4) sc = ldexp(1.0, A.e[g]);
+    if (sizeof(T) == 4) sc = ldexp(1.0, as_global(A.e)[g]);
     const double Phi = acc[0].value() * sc;
     const size_t o = (size_t)g * cells + cell;
-    if (A.E) A.E[o] = Phi * A.inv_c;
+    using gout = __attribute__((address_space(1))) double*;
+    if (A.E) ((gout)A.E)[o] = Phi * A.inv_c;
     if (A.F) {
-        A.F[((size_t)g * 2 + 0) * cells + cell] = acc[1].value() * sc;
-        A.F[((size_t)g * 2 + 1) * cells + cell] = acc[2].value() * sc;
+        gout F = (gout)A.F;
+        F[((size_t)g * 2 + 0) * cells + cell] = acc[1].value() * sc;
+        F[((size_t)g * 2 + 1) * cells + cell] = acc[2].value() * sc;
     }
     if (A.f) {
+        gout f = (gout)A.f;
         const bool z = Phi == 0.0;
         const double inv = z ? 0.0 : 1.0 / Phi;
-        A.f[((size_t)g * 4 + 0) * cells + cell] = z ? 1.0 / 3 : acc[3].value() * sc * inv;
-        A.f[((size_t)g * 4 + 1) * cells + cell] = z ? 0.0 : acc[4].value() * sc * inv;
-        A.f[((size_t)g * 4 + 2) * cells + cell] = z ? 1.0 / 3 : acc[5].value() * sc * inv;
-        A.f[((size_t)g * 4 + 3) * cells + cell] = z ? 1.0 / 3 : acc[6].value() * sc * inv;
+        f[((size_t)g * 4 + 0) * cells + cell] = z ? 1.0 / 3 : acc[3].value() * sc * inv;
+        f[((size_t)g * 4 + 1) * cells + cell] = z ? 0.0 : acc[4].value() * sc * inv;
+        f[((size_t)g * 4 + 2) * cells + cell] = z ? 1.0 / 3 : acc[5].value() * sc * inv;
+        f[((size_t)g * 4 + 3) * cells + cell] = z ? 1.0 / 3 : acc[6].value() * sc * inv;
     }
 }
 
+// Work unit: one wavefront of a tile, i.e. 64 consecutive (cell, g) lanes of
+// the tile's cell-major lane order.  Wavefronts need no barrier, so
+// occupancy follows from registers alone.  Blocks of kMomWaves wavefronts
+// are remapped so that each XCD takes a contiguous run of tiles.
 template <typename T, int PM, int K>
-__global__ __launch_bounds__(1024) void k_cell_moments(MomArgs A) {
-    moments_tile<T, PM, K>(A, xcd_logical_block(blockIdx.x, A.n_tiles), threadIdx.x);
+__global__ __launch_bounds__(kMomWaves * kWave) void k_cell_moments(MomArgs A) {
+    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t wi = lb * kMomWaves + (threadIdx.x >> 6);
+    if (wi >= A.n_tiles * A.wpt) return;
+    const int64_t tile = wi / A.wpt;
+    const int w = (int)(wi - tile * A.wpt);
+    moments_tile<T, PM, K>(A, tile, w * kWave + (threadIdx.x & (kWave - 1)));
 }
 
-// Batched form: persistent workgroups take (problem, tile) items from an
-// integer counter in item-list order.
+// Batched form: one launch over the wavefront items of every problem
+// ({problem, wavefront of a tile}, problems in decreasing cost).  Blocks are
+// remapped in groups of 8 * kXcdRun: within a group, XCD x takes kXcdRun
+// consecutive blocks, so neighbouring tiles share one L2 while all XCDs move
+// through the item list together and finish together.
 template <typename T, int PM, int K>
-__global__ __launch_bounds__(1024) void k_cell_moments_batch(const MomArgs* __restrict__ probs,
-                                                             const int2* __restrict__ items, int64_t n_items,
-                                                             int* counter) {
-    __shared__ int s_it;
-    for (;;) {
-        if (threadIdx.x == 0) s_it = atomicAdd(counter, 1);
-        __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane(s_it);
-        __syncthreads();
-        if (it >= n_items) break;
-        const int pr = __builtin_amdgcn_readfirstlane(items[it].x);
-        const int tl = __builtin_amdgcn_readfirstlane(items[it].y);
-        moments_tile<T, PM, K>(probs[pr], tl, threadIdx.x);
-    }
+__global__ __launch_bounds__(kMomWaves * kWave) void k_cell_moments_batch(const MomArgs* __restrict__ probs,
+                                                                         const int2* __restrict__ items,
+                                                                         int64_t n_items) {
+    const int64_t hw = blockIdx.x;
+    const int64_t grp = hw / (8 * kXcdRun);
+    const int64_t in = hw - grp * (8 * kXcdRun);
+    const int64_t lb = grp * (8 * kXcdRun) + (in & 7) * kXcdRun + (in >> 3);
+    const int64_t gi = lb * kMomWaves + (threadIdx.x >> 6);
+    if (gi >= n_items) return;
+    const int pr = __builtin_amdgcn_readfirstlane(items[gi].x);
+    const int lw = __builtin_amdgcn_readfirstlane(items[gi].y);
+    const MomArgs& A = probs[pr];
+    const int tile = lw / A.wpt;
+    const int w = lw - tile * A.wpt;
+    moments_tile<T, PM, K>(A, tile, w * kWave + (threadIdx.x & (kWave - 1)));
 }
 
 // Offsets of every C(i, m) entry into the bundle-major state of a plan:
@@ -335,8 +358,8 @@ __global__ __launch_bounds__(kBlock) void k_boundary_batch(const BndArgs* __rest
 
 template <typename T, int P>
 void launch_cell_moments_e(int ent, const MomArgs& A, hipStream_t st) {
-    const int threads = (A.ts * A.ts * A.G + kWave - 1) / kWave * kWave;
-    dim3 grid((unsigned)A.n_tiles), block(threads);
+    const int64_t waves = A.n_tiles * A.wpt;
+    dim3 grid((unsigned)((waves + kMomWaves - 1) / kMomWaves)), block(kMomWaves * kWave);
     switch (ent) {
         case 1: hipLaunchKernelGGL((k_cell_moments<T, P, 1>), grid, block, 0, st, A); break;
         case 2: hipLaunchKernelGGL((k_cell_moments<T, P, 2>), grid, block, 0, st, A); break;
@@ -406,6 +429,7 @@ lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, cons
         A.ts = pl->tile;
         A.tiles_x = (r->nx + pl->tile - 1) / pl->tile;
         A.n_tiles = (int64_t)A.tiles_x * ((r->ny + pl->tile - 1) / pl->tile);
+        A.wpt = moment_tile_waves(pl);
         A.G = pl->G;
         A.n_pairs = r->n_pairs;
         A.inv_c = 1.0 / c;
@@ -445,31 +469,22 @@ lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, cons
 namespace {
 
 template <typename T, int PM, int K>
-lc_status launch_moments_batch_e(const void* args, const int2* items, int64_t n_items, int* counter,
-                                 hipStream_t st) {
-    static int grid = 0;
-    if (!grid) {
-        int dev = 0, cus = 0, per_cu = 0;
-        LC_HIP(hipGetDevice(&dev));
-        LC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        LC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &per_cu, reinterpret_cast<const void*>(&k_cell_moments_batch<T, PM, K>), 1024, 0));
-        grid = std::max(1, cus * std::max(per_cu, 1));
-    }
-    hipLaunchKernelGGL((k_cell_moments_batch<T, PM, K>), dim3(grid), dim3(1024), 0, st,
-                       static_cast<const MomArgs*>(args), items, n_items, counter);
+lc_status launch_moments_batch_e(const void* args, const int2* items, int64_t n_items, hipStream_t st) {
+    const int64_t blocks = (n_items + kMomWaves - 1) / kMomWaves;
+    const int64_t grid = (blocks + 8 * kXcdRun - 1) / (8 * kXcdRun) * (8 * kXcdRun);
+    hipLaunchKernelGGL((k_cell_moments_batch<T, PM, K>), dim3((unsigned)grid), dim3(kMomWaves * kWave), 0, st,
+                       static_cast<const MomArgs*>(args), items, n_items);
     LC_HIP(hipGetLastError());
     return LC_OK;
 }
 
 template <typename T, int PM>
-lc_status launch_moments_batch_p(int ent, const void* args, const int2* items, int64_t n, int* counter,
-                                 hipStream_t st) {
+lc_status launch_moments_batch_p(int ent, const void* args, const int2* items, int64_t n_items, hipStream_t st) {
     switch (ent) {
-        case 1: return launch_moments_batch_e<T, PM, 1>(args, items, n, counter, st);
-        case 2: return launch_moments_batch_e<T, PM, 2>(args, items, n, counter, st);
-        case 4: return launch_moments_batch_e<T, PM, 4>(args, items, n, counter, st);
-        default: return launch_moments_batch_e<T, PM, 3>(args, items, n, counter, st);
+        case 1: return launch_moments_batch_e<T, PM, 1>(args, items, n_items, st);
+        case 2: return launch_moments_batch_e<T, PM, 2>(args, items, n_items, st);
+        case 4: return launch_moments_batch_e<T, PM, 4>(args, items, n_items, st);
+        default: return launch_moments_batch_e<T, PM, 3>(args, items, n_items, st);
     }
 }
 
@@ -498,6 +513,7 @@ void make_moment_args(Plan* pl, const void* state, const double* I_exit, const d
     A.ts = pl->tile;
     A.tiles_x = (r->nx + pl->tile - 1) / pl->tile;
     A.n_tiles = (int64_t)A.tiles_x * ((r->ny + pl->tile - 1) / pl->tile);
+    A.wpt = moment_tile_waves(pl);
     A.G = pl->G;
     A.n_pairs = r->n_pairs;
     A.inv_c = 1.0 / c;
@@ -528,18 +544,20 @@ int64_t moment_tiles(const Plan* pl) {
     return (int64_t)((r->nx + pl->tile - 1) / pl->tile) * ((r->ny + pl->tile - 1) / pl->tile);
 }
 
+int moment_tile_waves(const Plan* pl) { return (pl->tile * pl->tile * pl->G + kWave - 1) / kWave; }
+
 lc_status launch_moments_batch(int prec, int pm, int ent, const void* args, const int2* items, int64_t n_items,
-                               int* counter, hipStream_t st) {
+                               hipStream_t st) {
     const bool f32 = prec == LC_F32;
     switch (pm) {
-        case 1: return f32 ? launch_moments_batch_p<float, 1>(ent, args, items, n_items, counter, st)
-                           : launch_moments_batch_p<double, 1>(ent, args, items, n_items, counter, st);
-        case 2: return f32 ? launch_moments_batch_p<float, 2>(ent, args, items, n_items, counter, st)
-                           : launch_moments_batch_p<double, 2>(ent, args, items, n_items, counter, st);
-        case 4: return f32 ? launch_moments_batch_p<float, 4>(ent, args, items, n_items, counter, st)
-                           : launch_moments_batch_p<double, 4>(ent, args, items, n_items, counter, st);
-        case 8: return f32 ? launch_moments_batch_p<float, 8>(ent, args, items, n_items, counter, st)
-                           : launch_moments_batch_p<double, 8>(ent, args, items, n_items, counter, st);
+        case 1: return f32 ? launch_moments_batch_p<float, 1>(ent, args, items, n_items, st)
+                           : launch_moments_batch_p<double, 1>(ent, args, items, n_items, st);
+        case 2: return f32 ? launch_moments_batch_p<float, 2>(ent, args, items, n_items, st)
+                           : launch_moments_batch_p<double, 2>(ent, args, items, n_items, st);
+        case 4: return f32 ? launch_moments_batch_p<float, 4>(ent, args, items, n_items, st)
+                           : launch_moments_batch_p<double, 4>(ent, args, items, n_items, st);
+        case 8: return f32 ? launch_moments_batch_p<float, 8>(ent, args, items, n_items, st)
+                           : launch_moments_batch_p<double, 8>(ent, args, items, n_items, st);
     }
     set_error("batched moments: polar bound %d not supported", pm);
     return LC_ERR_UNSUPPORTED;
