@@ -1,9 +1,9 @@
 // Batched form: many independent problems advanced together.  Each phase of a
 // time step is one launch over all problems: the coefficient prologue, one
-// persistent sweep kernel whose wavefronts pull (problem, wavefront) items
-// from an integer counter, one cell-moment launch over the (problem, tile
-// wavefront) items of every problem, and the boundary factors.  Items are ordered by
-// problem cost, largest first, so the small problems fill the tail.  The step
+// persistent sweep kernel whose wavefronts pull (problem, bundle traversal)
+// items from an integer counter, one cell-moment launch over the (problem,
+// tile wavefront) items, and the boundary factors.  Items are ordered by problem cost, largest first, so the
+// small problems fill the tail.  The step
 // sequence is captured in a HIP graph per step count and replayed.
 #include <algorithm>
 #include <climits>
@@ -15,8 +15,6 @@
 
 namespace lc {
 namespace {
-
-constexpr int kCounters = 1;
 
 struct Batch {
     uint32_t magic = 0;
@@ -32,7 +30,7 @@ struct Batch {
     int2* d_sweep_items = nullptr;
     int2* d_mom_items = nullptr;        // {problem, wavefront of a tile}
     int64_t n_sweep_items = 0, n_mom_items = 0;
-    int* d_counters = nullptr;          // [kCounters]: the sweep's item counter
+    int* d_counters = nullptr;          // [1] the sweep's item counter
     unsigned long long* d_gmax = nullptr;   // per-group source maxima of every problem
     int64_t n_gmax = 0, max_blocks = 0, coef_blocks = 0, bnd_lanes = 0;
     int max_G = 1;
@@ -79,7 +77,7 @@ lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
     lc_status rc = LC_OK;
     for (int t = 0; t < n_steps && rc == LC_OK; ++t) {
         const int parity = t & 1;
-        rc = launch_zero_counters(b->d_counters, kCounters, st);
+        rc = launch_zero_counters(b->d_counters, 1, st);
         if (rc == LC_OK) rc = ev_begin(b, 0, st);
         if (rc == LC_OK)
             rc = launch_prologue_batch(b->prec, b->d_coef_args, b->n, b->max_blocks, b->coef_blocks, b->max_G,
@@ -264,8 +262,8 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
     if (rc == LC_OK) rc = upload(reinterpret_cast<void**>(&b->d_sweep_items), si.data(), si.size() * sizeof(int2));
     if (rc == LC_OK) rc = upload(reinterpret_cast<void**>(&b->d_mom_items), mi.data(), mi.size() * sizeof(int2));
     if (rc == LC_OK) {
-        int zero[kCounters] = {};
-        rc = upload(reinterpret_cast<void**>(&b->d_counters), zero, sizeof(zero));
+        const int zero = 0;
+        rc = upload(reinterpret_cast<void**>(&b->d_counters), &zero, sizeof(zero));
     }
     if (rc == LC_OK) rc = build_moment_args(b, 1.0);
     if (rc == LC_OK) {

@@ -86,6 +86,13 @@ struct Rays {
 
 struct Plan;
 
+// Global (address space 1) pointers: device code loads through them so that
+// the compiler emits global rather than flat memory instructions even where a
+// pointer comes from an argument record in memory.
+template <typename T> using gptr = __attribute__((address_space(1))) T*;
+template <typename T> __device__ __forceinline__ gptr<const T> as_global(const T* p) { return (gptr<const T>)p; }
+template <typename T> __device__ __forceinline__ gptr<T> as_global_w(T* p) { return (gptr<T>)p; }
+
 // Cell record of eq. (11): kappa_t and the emission kappa B / kappa_t; the
 // remaining coefficient 1/(c dt kappa_t) is formed in the sweep.
 template <typename T> struct alignas(2 * sizeof(T)) Coef { T kt, a; };

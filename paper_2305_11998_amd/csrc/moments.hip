@@ -57,12 +57,6 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t hw, int64_t n) {
     return x * q + (x < r ? x : r) + i;
 }
 
-// Loads of the moment kernels go through global (address space 1) pointers,
-// so the compiler emits global rather than flat loads even where the
-// pointers come from an argument record in memory.
-template <typename T> using gptr = const __attribute__((address_space(1))) T*;
-template <typename T> __device__ __forceinline__ gptr<T> as_global(const T* p) { return (gptr<T>)p; }
-
 // State offsets and area weight of one C(i, m) entry as seen by lane g.
 // A slot past the end of its list reads entry 0 (which always exists) and
 // gets weight 0, so every load is unconditional and stays inside the arrays.
@@ -72,7 +66,7 @@ template <typename T> struct Slot {
 };
 
 template <typename T>
-__device__ __forceinline__ Slot<T> load_slot(gptr<long long> eo, gptr<T> cw, int e, bool ok, int g) {
+__device__ __forceinline__ Slot<T> load_slot(gptr<const long long> eo, gptr<const T> cw, int e, bool ok, int g) {
     Slot<T> s;
     const int ee = ok ? e : 0;
     const T w = cw[ee];
@@ -113,10 +107,10 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
     const int cell = cy * A.nx + cx;
     const int cells = A.nx * A.ny;
     const int np = A.n_pairs;
-    const gptr<T> st = as_global(static_cast<const T*>(A.state));
-    const gptr<T> cw = as_global(static_cast<const T*>(A.csr_w));
-    const gptr<long long> eo = as_global(A.ent_off);
-    const gptr<int> co = as_global(A.csr_off + (size_t)cell * np);
+    const gptr<const T> st = as_global(static_cast<const T*>(A.state));
+    const gptr<const T> cw = as_global(static_cast<const T*>(A.csr_w));
+    const gptr<const long long> eo = as_global(A.ent_off);
+    const gptr<const int> co = as_global(A.csr_off + (size_t)cell * np);
     Acc<T> acc[7];
     // list bounds: pair a is [b0, b1), pair a+1 is [b1, b2)
     int b0 = co[0], b1 = co[1];
@@ -166,7 +160,7 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
 #pragma unroll
             for (int p = 0; p < PM; ++p) {
                 if (p >= P) continue;
-                const gptr<double> dw = as_global(A.dirw + (((size_t)a * 2 + d) * P + p) * kDirW);
+                const gptr<const double> dw = as_global(A.dirw + (((size_t)a * 2 + d) * P + p) * kDirW);
 #pragma unroll
                 for (int c = 0; c < 7; ++c) part[c] += (T)dw[c] * Iim[d][p];
             }
@@ -182,15 +176,14 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
     if (sizeof(T) == 4) sc = ldexp(1.0, as_global(A.e)[g]);
     const double Phi = acc[0].value() * sc;
     const size_t o = (size_t)g * cells + cell;
-    using gout = __attribute__((address_space(1))) double*;
-    if (A.E) ((gout)A.E)[o] = Phi * A.inv_c;
+    if (A.E) as_global_w(A.E)[o] = Phi * A.inv_c;
     if (A.F) {
-        gout F = (gout)A.F;
+        const gptr<double> F = as_global_w(A.F);
         F[((size_t)g * 2 + 0) * cells + cell] = acc[1].value() * sc;
         F[((size_t)g * 2 + 1) * cells + cell] = acc[2].value() * sc;
     }
     if (A.f) {
-        gout f = (gout)A.f;
+        const gptr<double> f = as_global_w(A.f);
         const bool z = Phi == 0.0;
         const double inv = z ? 0.0 : 1.0 / Phi;
         f[((size_t)g * 4 + 0) * cells + cell] = z ? 1.0 / 3 : acc[3].value() * sc * inv;
@@ -295,22 +288,25 @@ __device__ __forceinline__ void boundary_lane(const BndArgs& A, int lane) {
     else if (b < 2 * A.ny + A.nx) nyv = -1;
     else nyv = 1;
     double Pp = 0, Jp = 0, Pm = 0, Jm = 0, S = 0, Sxx = 0, Sxy = 0, Syy = 0, wo = 0, wodn = 0;
+    const gptr<const double> width = as_global(A.width);
+    const gptr<const double> I_exit = as_global(A.I_exit);
+    const gptr<const double> I_in = as_global(A.I_in);
     for (int a = 0; a < A.n_pairs; ++a) {
         for (int d = 0; d < 2; ++d) {
-            const int* bm = A.bmap + ((size_t)(b * A.n_pairs + a) * 2 + d) * 2;
+            const gptr<const int> bm = as_global(A.bmap + ((size_t)(b * A.n_pairs + a) * 2 + d) * 2);
             const int k0 = bm[0], k1 = bm[1];
             double wsum = 0.0;
             if (k0 >= 0)
-                for (int k = k0; k < k1; ++k) wsum += A.width[k];
+                for (int k = k0; k < k1; ++k) wsum += width[k];
             for (int p = 0; p < P; ++p) {
-                const double* dw = A.dirw + ((size_t)(a * 2 + d) * P + p) * kDirW;
+                const gptr<const double> dw = as_global(A.dirw + ((size_t)(a * 2 + d) * P + p) * kDirW);
                 const double om = dw[0];
                 const double odn = dw[7] * nxv + dw[8] * nyv;
                 double I;
                 if (k0 >= 0) {
                     double acc = 0.0;
                     for (int k = k0; k < k1; ++k)
-                        acc += A.width[k] * A.I_exit[((size_t)(2 * k + d) * P + p) * G + g];
+                        acc += width[k] * I_exit[((size_t)(2 * k + d) * P + p) * G + g];
                     I = acc / wsum;
                     Pp += om * I;
                     Jp += om * odn * I;
@@ -318,7 +314,7 @@ __device__ __forceinline__ void boundary_lane(const BndArgs& A, int lane) {
                     wodn += om * odn;
                 } else {
                     const int m = (a + d * (A.n_az >> 1)) * P + p;
-                    I = A.I_in[((size_t)b * M + m) * G + g];
+                    I = I_in[((size_t)b * M + m) * G + g];
                     Pm += om * I;
                     Jm += om * fabs(odn) * I;
                 }
@@ -329,7 +325,7 @@ __device__ __forceinline__ void boundary_lane(const BndArgs& A, int lane) {
             }
         }
     }
-    double* out = A.bnd + ((size_t)g * A.nb + b) * 8;
+    const gptr<double> out = as_global_w(A.bnd + ((size_t)g * A.nb + b) * 8);
     out[0] = Pp;
     out[1] = Jp;
     out[2] = Pm;

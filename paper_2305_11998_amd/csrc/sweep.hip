@@ -56,7 +56,7 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t hw, int64_t n) {
     return x * q + (x < r ? x : r) + i;
 }
 
-__device__ __forceinline__ int find_pair(const int* __restrict__ off, int n, int64_t v) {
+__device__ __forceinline__ int find_pair(gptr<const int> off, int n, int64_t v) {
     int lo = 0, hi = n;                // off[lo] <= v < off[hi]
     while (hi - lo > 1) {
         int mid = (lo + hi) >> 1;
@@ -101,10 +101,33 @@ template <> struct Vec2<double> { using type = double2; };
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 
+// Two-component records (int2, float2/double2, Coef<T>) loaded as native
+// clang vectors: the HIP class types cannot be copied out of address space 1.
+template <typename E> using vec2 = E __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ int2 ld2(gptr<const int2> p) {
+    const vec2<int> v = *(gptr<const vec2<int>>)p;
+    return make_int2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld2(gptr<const float2> p) {
+    const vec2<float> v = *(gptr<const vec2<float>>)p;
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ double2 ld2(gptr<const double2> p) {
+    const vec2<double> v = *(gptr<const vec2<double>>)p;
+    return make_double2(v.x, v.y);
+}
+template <typename T> __device__ __forceinline__ Coef<T> ld2(gptr<const Coef<T>> p) {
+    const vec2<T> v = *(gptr<const vec2<T>>)p;
+    Coef<T> c;
+    c.kt = v.x;
+    c.a = v.y;
+    return c;
+}
+
 template <typename T>
-__device__ __forceinline__ T ldg_stream(const T* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ T ldg_stream(gptr<const T> p) { return __builtin_nontemporal_load(p); }
 template <typename T>
-__device__ __forceinline__ void stg_stream(T* p, T v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void stg_stream(gptr<T> p, T v) { __builtin_nontemporal_store(v, p); }
 
 // One wavefront per (traversal d, bundle B) of a problem.  Lane (k, g) walks
 // its characteristic; step t reads the P stored values of the lane at
@@ -122,29 +145,32 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
     constexpr int NL = (PM + 1) / 2, NU = PM / 2, NS = NL + NU;
     const int d = w >= A.n_bun ? 1 : 0;
     const int64_t B = w - (d ? A.n_bun : 0);
-    const int a = find_pair(A.bun_off, A.n_pairs, B);
+    const gptr<const int> bun_off = as_global(A.bun_off);
+    const gptr<const int> ray_off = as_global(A.ray_off);
+    const gptr<const int> seg_off = as_global(A.seg_off);
+    const int a = find_pair(bun_off, A.n_pairs, B);
     const int G = A.G;
     const int P = A.P;
-    const int r0 = A.ray_off[a];
-    const int Ka = A.ray_off[a + 1] - r0;
-    const int f = (int)(B - A.bun_off[a]) * kWave + lane;
+    const int r0 = ray_off[a];
+    const int Ka = ray_off[a + 1] - r0;
+    const int f = (int)(B - bun_off[a]) * kWave + lane;
     int kl = f / G;
     const int g = f - kl * G;
     const bool active = kl < Ka;
     if (!active) kl = Ka - 1;                  // keep addresses valid; nothing is stored
     const int k = r0 + kl;
-    const int s0 = A.seg_off[k];
-    const int nk = A.seg_off[k + 1] - s0;
+    const int s0 = seg_off[k];
+    const int nk = seg_off[k + 1] - s0;
     const int n = active ? nk : 0;
-    const int L = A.bun_len[B];
+    const int L = as_global(A.bun_len)[B];
     const int az = a + d * (A.n_az >> 1);
     using T2 = typename Vec2<T>::type;
-    const int2* __restrict__ gi = A.gi;
-    const T2* __restrict__ gf = static_cast<const T2*>(A.gf);
-    const Coef<T>* __restrict__ coef = static_cast<const Coef<T>*>(A.coef);
-    const size_t boff = (size_t)d * A.half + (size_t)A.bun_base[B] + lane;
-    const T* __restrict__ xin = static_cast<const T*>(A.prev) + boff;
-    T* __restrict__ xout = static_cast<T*>(A.next) + boff;
+    const gptr<const int2> gi = as_global(A.gi);
+    const gptr<const T2> gf = as_global(static_cast<const T2*>(A.gf));
+    const gptr<const Coef<T>> coef = as_global(static_cast<const Coef<T>*>(A.coef));
+    const size_t boff = (size_t)d * A.half + (size_t)as_global(A.bun_base)[B] + lane;
+    const gptr<const T> xin = as_global(static_cast<const T*>(A.prev) + boff);
+    const gptr<T> xout = as_global_w(static_cast<T*>(A.next) + boff);
     const size_t SP = (size_t)P * kWave;       // elements per step of a bundle
 
     int pol[NS];
@@ -163,26 +189,27 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
 
     double sc_in = 1.0, sc_out = 1.0, cb = A.inv_cdt;
     if (sizeof(T) == 4) {
-        const int e = A.e_new[g];
+        const int e = as_global(A.e_new)[g];
         sc_in = ldexp(1.0, -e);
         sc_out = ldexp(1.0, e);
-        cb = ldexp(A.inv_cdt, A.e_prev[g] - e);   // old-state scale folded into 1/(c dt)
+        cb = ldexp(A.inv_cdt, as_global(A.e_prev)[g] - e);   // old-state scale folded into 1/(c dt)
     }
     const T cbt = (T)cb;
     T isz[NS];
     T I[NS];
-    const int face_in = A.face[2 * k + d];
+    const int face_in = as_global(A.face)[2 * k + d];
+    const gptr<const double> I_in = as_global(A.I_in);
 #pragma unroll
     for (int r = 0; r < NS; ++r) {
         isz[r] = val[r] ? (T)A.inv_sinz[pol[r]] : (T)1;
-        I[r] = val[r] ? (T)(A.I_in[((size_t)face_in * A.M + (size_t)az * P + pol[r]) * G + g] * sc_in) : (T)0;
+        I[r] = val[r] ? (T)(I_in[((size_t)face_in * A.M + (size_t)az * P + pol[r]) * G + g] * sc_in) : (T)0;
     }
     // segment index of step t (clamped into the characteristic)
     auto seg = [&](int t) -> int {
         const int tt = t < nk ? t : nk - 1;
         return d == 0 ? s0 + tt : s0 + nk - 1 - tt;
     };
-    auto srow = [&](int t) -> const T* { return xin + (size_t)(t < L ? t : L - 1) * SP; };
+    auto srow = [&](int t) -> gptr<const T> { return xin + (size_t)(t < L ? t : L - 1) * SP; };
 
     int2 gi1[U];
     T2 gf0[U], gf1[U];
@@ -191,12 +218,12 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int j0 = seg(u), j1 = seg(U + u);
-        const int2 g0 = gi[j0];
-        gf0[u] = gf[j0];
-        c0[u] = coef[(size_t)g0.x * G + g];
-        gi1[u] = gi[j1];
-        gf1[u] = gf[j1];
-        const T* r = srow(u);
+        const int2 g0 = ld2(gi + j0);
+        gf0[u] = ld2(gf + j0);
+        c0[u] = ld2(coef + ((size_t)g0.x * G + g));
+        gi1[u] = ld2(gi + j1);
+        gf1[u] = ld2(gf + j1);
+        const gptr<const T> r = srow(u);
 #pragma unroll
         for (int q = 0; q < NS; ++q) x0[u][q] = val[q] ? ldg_stream(r + pol[q] * kWave) : (T)0;
     }
@@ -207,13 +234,13 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
         T2 gf2[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            c1[u] = coef[(size_t)gi1[u].x * G + g];
-            const T* r = srow(t0 + U + u);
+            c1[u] = ld2(coef + ((size_t)gi1[u].x * G + g));
+            const gptr<const T> r = srow(t0 + U + u);
 #pragma unroll
             for (int q = 0; q < NS; ++q) x1[u][q] = val[q] ? ldg_stream(r + pol[q] * kWave) : (T)0;
             const int j2 = seg(t0 + 2 * U + u);
-            gi2[u] = gi[j2];
-            gf2[u] = gf[j2];
+            gi2[u] = ld2(gi + j2);
+            gf2[u] = ld2(gf + j2);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -228,7 +255,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
 #pragma unroll
             for (int i = 0; i < NU; ++i)
                 if (val[NL + i]) at[NL + i] = sym ? at[i] : attenuate(ktl * isz[NL + i]);
-            T* o = xout + (size_t)t * SP;
+            const gptr<T> o = xout + (size_t)t * SP;
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
                 if (!val[q]) continue;
@@ -250,9 +277,10 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
         }
     }
     if (A.I_exit && active) {
+        const gptr<double> I_exit = as_global_w(A.I_exit);
 #pragma unroll
         for (int q = 0; q < NS; ++q)
-            if (val[q]) A.I_exit[((size_t)(2 * k + d) * P + pol[q]) * G + g] = (double)I[q] * sc_out;
+            if (val[q]) I_exit[((size_t)(2 * k + d) * P + pol[q]) * G + g] = (double)I[q] * sc_out;
     }
 }
 
@@ -266,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
 
 // Batched form: a persistent grid whose wavefronts take work items
 // (problem, wavefront of that problem) from an integer counter, in the order
-// of the item list (longest first).
+// of the item list (problems in decreasing cost).
 template <typename T, int PM, int U>
 __global__ __launch_bounds__(kBlock) void k_sweep_batch(const SweepArgs* __restrict__ probs,
                                                         const int2* __restrict__ items, int64_t n_items,
@@ -277,8 +305,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep_batch(const SweepArgs* __restr
         if (lane == 0) it = atomicAdd(counter, 1);
         it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
         if (it >= n_items) break;
-        const int2 item = items[it];
-        sweep_wave<T, PM, U>(probs[item.x], item.y, lane);
+        const int pr = __builtin_amdgcn_readfirstlane(items[it].x);
+        const int w = __builtin_amdgcn_readfirstlane(items[it].y);
+        sweep_wave<T, PM, U>(probs[pr], w, lane);
     }
 }
 
