@@ -1,7 +1,7 @@
 // Batched form: many independent problems advanced together.  Each phase of a
 // time step is one launch over all problems: the coefficient prologue, one
 // persistent sweep kernel whose wavefronts pull (problem, bundle traversal)
-// items from an integer counter, one cell-moment launch over the (problem,
+// items from eight per-XCD queues, one cell-moment launch over the (problem,
 // tile wavefront) items, and the boundary factors.  Items are ordered by problem cost, largest first, so the
 // small problems fill the tail.  The step
 // sequence is captured in a HIP graph per step count and replayed.
@@ -30,7 +30,8 @@ struct Batch {
     int2* d_sweep_items = nullptr;
     int2* d_mom_items = nullptr;        // {problem, wavefront of a tile}
     int64_t n_sweep_items = 0, n_mom_items = 0;
-    int* d_counters = nullptr;          // [1] the sweep's item counter
+    int64_t* d_sweep_qb = nullptr;      // [9] bounds of the eight per-XCD sweep queues
+    int* d_counters = nullptr;          // [8] counters of the sweep queues
     unsigned long long* d_gmax = nullptr;   // per-group source maxima of every problem
     int64_t n_gmax = 0, max_blocks = 0, coef_blocks = 0, bnd_lanes = 0;
     int max_G = 1;
@@ -77,7 +78,7 @@ lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
     lc_status rc = LC_OK;
     for (int t = 0; t < n_steps && rc == LC_OK; ++t) {
         const int parity = t & 1;
-        rc = launch_zero_counters(b->d_counters, 1, st);
+        rc = launch_zero_counters(b->d_counters, 8, st);
         if (rc == LC_OK) rc = ev_begin(b, 0, st);
         if (rc == LC_OK)
             rc = launch_prologue_batch(b->prec, b->d_coef_args, b->n, b->max_blocks, b->coef_blocks, b->max_G,
@@ -87,7 +88,7 @@ lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
         if (rc == LC_OK)
             rc = launch_sweep_batch(b->prec, b->pm, b->unroll,
                                     static_cast<char*>(b->d_sweep_args) + parity * b->n * sb, b->d_sweep_items,
-                                    b->n_sweep_items, b->d_counters, st);
+                                    b->d_sweep_qb, b->d_counters, st);
         if (rc == LC_OK) rc = ev_end(b, 1, st);
         if (rc == LC_OK) {                            // every step forms its moments
             rc = ev_begin(b, 2, st);
@@ -115,7 +116,8 @@ void free_batch(Batch* b) {
     if (b->capture) (void)hipStreamDestroy(b->capture);
     for (void* p : {b->d_sweep_args, b->d_coef_args, b->d_mom_args, b->d_bnd_args,
                     static_cast<void*>(b->d_sweep_items), static_cast<void*>(b->d_mom_items),
-                    static_cast<void*>(b->d_counters), static_cast<void*>(b->d_gmax)})
+                    static_cast<void*>(b->d_counters), static_cast<void*>(b->d_gmax),
+                    static_cast<void*>(b->d_sweep_qb)})
         if (p) (void)hipFree(p);
     b->magic = 0;
     delete b;
@@ -242,9 +244,14 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
     auto cost = [&](int q) { return (double)b->plans[q]->half_elems; };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
     std::vector<int2> si, mi;
+    std::vector<double> scost;          // summed steps of the sweep items, for the queue split
     for (int q : order) {
         const Plan* pl = b->plans[q];
-        for (int64_t w = 0; w < 2 * pl->n_bun; ++w) si.push_back(make_int2(q, (int)w));
+        for (int64_t B = 0; B < pl->n_bun; ++B)
+            for (int d = 0; d < 2; ++d) {
+                si.push_back(make_int2(q, (int)(d * pl->n_bun + B)));
+                scost.push_back((double)pl->bun_len_h[B] * pl->rays->n_pol);
+            }
         const int64_t mw = moment_tiles(pl) * moment_tile_waves(pl);
         if (mw >= INT32_MAX) rc = LC_ERR_UNSUPPORTED;
         for (int64_t w = 0; w < mw && rc == LC_OK; ++w) mi.push_back(make_int2(q, (int)w));
@@ -255,15 +262,29 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
         set_error("batched moments: grid too large");
     }
     b->n_sweep_items = (int64_t)si.size();
+    int64_t sqb[9];
+    {
+        double tot = 0.0;
+        for (double c : scost) tot += c;
+        double acc = 0.0;
+        int x = 1;
+        sqb[0] = 0;
+        for (int64_t i = 0; i < (int64_t)scost.size() && x < 8; ++i) {
+            acc += scost[i];
+            while (x < 8 && acc >= tot * x / 8.0) sqb[x++] = i + 1;
+        }
+        while (x < 9) sqb[x++] = (int64_t)scost.size();
+    }
     b->n_mom_items = (int64_t)mi.size();
 
     if (rc == LC_OK) rc = upload(&b->d_sweep_args, hs.data(), hs.size());
     if (rc == LC_OK) rc = upload(&b->d_coef_args, hc.data(), hc.size());
     if (rc == LC_OK) rc = upload(reinterpret_cast<void**>(&b->d_sweep_items), si.data(), si.size() * sizeof(int2));
     if (rc == LC_OK) rc = upload(reinterpret_cast<void**>(&b->d_mom_items), mi.data(), mi.size() * sizeof(int2));
+    if (rc == LC_OK) rc = upload(reinterpret_cast<void**>(&b->d_sweep_qb), sqb, sizeof(sqb));
     if (rc == LC_OK) {
-        const int zero = 0;
-        rc = upload(reinterpret_cast<void**>(&b->d_counters), &zero, sizeof(zero));
+        const int zero[8] = {};
+        rc = upload(reinterpret_cast<void**>(&b->d_counters), zero, sizeof(zero));
     }
     if (rc == LC_OK) rc = build_moment_args(b, 1.0);
     if (rc == LC_OK) {

@@ -127,7 +127,7 @@ struct Plan {
     int* d_bun_len = nullptr;
     int64_t* d_bun_base = nullptr;
     long long* d_ent_off = nullptr;   // [n_seg][4] state offsets of each C(i, m) entry
-    int tile = 1;                     // cell-tile side of the moments kernel
+    int tile_w = 1, tile_h = 1;       // cell tile of the moments kernel
     int64_t sweep_blocks = 0;         // blocks of one sweep launch
     std::vector<GraphEntry> graphs;   // captured lc_step sequences
     hipStream_t capture = nullptr;    // stream used only to record graphs
@@ -199,8 +199,8 @@ lc_status launch_prologue_batch(int prec, const void* coef_args, int n, int64_t 
                                 int64_t coef_blocks_all, int max_G, unsigned long long* gmax, int64_t n_gmax, int t,
                                 hipStream_t st);
 lc_status launch_zero_counters(int* c, int n, hipStream_t st);
-lc_status launch_sweep_batch(int prec, int pm, int unroll, const void* args, const int2* items, int64_t n_items,
-                             int* counter, hipStream_t st);
+lc_status launch_sweep_batch(int prec, int pm, int unroll, const void* args, const int2* items, const int64_t* qb,
+                             int* counters, hipStream_t st);
 lc_status launch_moments_batch(int prec, int pm, int ent, const void* args, const int2* items, int64_t n_items,
                                hipStream_t st);
 lc_status launch_boundary_batch(const void* args, int n, int64_t lanes, hipStream_t st);

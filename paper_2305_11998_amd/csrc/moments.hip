@@ -20,8 +20,9 @@ struct MomArgs {
     const double* dirw;       // [n_pairs][2][P][kDirW]
     const void* state;        // values
     const int* e;             // per-group exponents of the state (float32 only)
-    int nx, ny, G, P, n_pairs, ts, tiles_x;
-    int wpt;                  // wavefronts per tile (ts * ts * G lanes)
+    int nx, ny, G, P, n_pairs;
+    int tw, th, tiles_x;      // tile of tw x th cells; tiles in row-major order
+    int wpt;                  // wavefronts per tile (tw * th * G lanes)
     int64_t n_tiles;
     double inv_c;
     double* E;
@@ -47,7 +48,8 @@ template <> struct Acc<float> {
 };
 
 constexpr int kMomWaves = 4;   // wavefronts per block of the moment kernels
-constexpr int kXcdRun = 16;    // consecutive blocks per XCD in the batched moment launch
+constexpr int kXcdRun = 64;    // consecutive blocks per XCD in the batched moment launch
+constexpr int kTileWaves = kMomWaves * kXcdRun;   // wavefronts of a tile at most: one XCD run
 
 // Hardware hands workgroups to the 8 XCDs round-robin; give each XCD a
 // contiguous range of tiles so that neighbouring tiles share an L2.
@@ -79,14 +81,15 @@ __device__ __forceinline__ Slot<T> load_slot(gptr<const long long> eo, gptr<cons
     return s;
 }
 
-// One workgroup per ts x ts tile of cells; lane (cell, g).  For each azimuth
+// Lane (cell, g) of a tile of tw x th cells.  For each azimuth
 // pair the lane gathers the segment averages of the characteristics crossing
 // its cell (the C(i, m) list, in (k, s) order) with the area weights, giving
 // I_{i,m} for both traversals and every polar angle, then adds that pair's
 // contribution to the seven angular moments (compensated float32 or plain
-// float64 sums, fixed order).  A characteristic crosses several cells of a
-// tile in consecutive steps, whose state rows are adjacent in memory, so the
-// tile's lanes share the cache lines they fetch.
+// float64 sums, fixed order).  A cache line of the state holds neighbouring
+// characteristics at the same step, which cross neighbouring cells, so the
+// wavefronts of a tile -- run together on one XCD -- share the lines they
+// fetch; a tile row of 16 cells fills whole 128-byte lines of the outputs.
 //
 // The loads are pipelined over pairs: while the state values of pair a are
 // in flight, the entry offsets of pair a+1 and the list end of pair a+2 are
@@ -99,10 +102,9 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
     const int P = A.P;
     const int cl = tid / G;
     const int g = tid - cl * G;
-    const int ts = A.ts;
-    if (cl >= ts * ts) return;
-    const int cx = (int)(tile % A.tiles_x) * ts + cl % ts;
-    const int cy = (int)(tile / A.tiles_x) * ts + cl / ts;
+    if (cl >= A.tw * A.th) return;
+    const int cx = (int)(tile % A.tiles_x) * A.tw + cl % A.tw;
+    const int cy = (int)(tile / A.tiles_x) * A.th + cl / A.tw;
     if (cx >= A.nx || cy >= A.ny) return;
     const int cell = cy * A.nx + cx;
     const int cells = A.nx * A.ny;
@@ -400,10 +402,11 @@ lc_status plan_init_moments(Plan* pl) {
                        n_keys, r->n_pairs, pl->G, r->n_pol, pl->half_elems, pl->d_ent_off);
     LC_HIP(hipGetLastError());
     LC_HIP(hipDeviceSynchronize());
-    // tile side: the largest square tile of cells x groups that fits a workgroup
-    int ts = 1;
-    while ((int64_t)(ts + 1) * (ts + 1) * pl->G <= 1024) ++ts;
-    pl->tile = ts;
+    // tile: 16 cells wide (a 128-byte line of each output row) and as tall
+    // as fits in kTileWaves wavefronts, at most 16; narrower for large G
+    const int cells_max = std::max(1, kTileWaves * kWave / pl->G);
+    pl->tile_w = std::max(1, std::min({16, cells_max, r->nx}));
+    pl->tile_h = std::max(1, std::min({16, cells_max / pl->tile_w, r->ny}));
     return LC_OK;
 }
 
@@ -422,9 +425,10 @@ lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, cons
         A.nx = r->nx;
         A.ny = r->ny;
         A.P = r->n_pol;
-        A.ts = pl->tile;
-        A.tiles_x = (r->nx + pl->tile - 1) / pl->tile;
-        A.n_tiles = (int64_t)A.tiles_x * ((r->ny + pl->tile - 1) / pl->tile);
+        A.tw = pl->tile_w;
+        A.th = pl->tile_h;
+        A.tiles_x = (r->nx + pl->tile_w - 1) / pl->tile_w;
+        A.n_tiles = moment_tiles(pl);
         A.wpt = moment_tile_waves(pl);
         A.G = pl->G;
         A.n_pairs = r->n_pairs;
@@ -506,9 +510,10 @@ void make_moment_args(Plan* pl, const void* state, const double* I_exit, const d
     A.nx = r->nx;
     A.ny = r->ny;
     A.P = r->n_pol;
-    A.ts = pl->tile;
-    A.tiles_x = (r->nx + pl->tile - 1) / pl->tile;
-    A.n_tiles = (int64_t)A.tiles_x * ((r->ny + pl->tile - 1) / pl->tile);
+    A.tw = pl->tile_w;
+    A.th = pl->tile_h;
+    A.tiles_x = (r->nx + pl->tile_w - 1) / pl->tile_w;
+    A.n_tiles = moment_tiles(pl);
     A.wpt = moment_tile_waves(pl);
     A.G = pl->G;
     A.n_pairs = r->n_pairs;
@@ -537,10 +542,10 @@ void make_moment_args(Plan* pl, const void* state, const double* I_exit, const d
 
 int64_t moment_tiles(const Plan* pl) {
     const Rays* r = pl->rays;
-    return (int64_t)((r->nx + pl->tile - 1) / pl->tile) * ((r->ny + pl->tile - 1) / pl->tile);
+    return (int64_t)((r->nx + pl->tile_w - 1) / pl->tile_w) * ((r->ny + pl->tile_h - 1) / pl->tile_h);
 }
 
-int moment_tile_waves(const Plan* pl) { return (pl->tile * pl->tile * pl->G + kWave - 1) / kWave; }
+int moment_tile_waves(const Plan* pl) { return (pl->tile_w * pl->tile_h * pl->G + kWave - 1) / kWave; }
 
 lc_status launch_moments_batch(int prec, int pm, int ent, const void* args, const int2* items, int64_t n_items,
                                hipStream_t st) {

@@ -293,20 +293,32 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
 }
 
 // Batched form: a persistent grid whose wavefronts take work items
-// (problem, wavefront of that problem) from an integer counter, in the order
-// of the item list (problems in decreasing cost).
+// (problem, wavefront of that problem) from eight queues, one per XCD --
+// block b is assumed to run on XCD b mod 8, the hardware's round-robin order.
+// Queue x holds a contiguous range of the item list (problems in decreasing
+// cost, the two traversals of a bundle side by side) of about one eighth of
+// the summed bundle lengths, so the characteristics crossing a cell are swept
+// on one XCD and share its L2 copy of the cell coefficients.  A wavefront
+// whose queue is empty moves on to the next one and stops after finding all
+// eight empty; counters only grow, so every wavefront exits.
 template <typename T, int PM, int U>
 __global__ __launch_bounds__(kBlock) void k_sweep_batch(const SweepArgs* __restrict__ probs,
-                                                        const int2* __restrict__ items, int64_t n_items,
-                                                        int* counter) {
+                                                        const int2* __restrict__ items,
+                                                        const int64_t* __restrict__ qb, int* counters) {
     const int lane = threadIdx.x & (kWave - 1);
-    for (;;) {
+    int q = blockIdx.x & 7;
+    for (int empty = 0; empty < 8;) {
         int it = 0;
-        if (lane == 0) it = atomicAdd(counter, 1);
+        if (lane == 0) it = atomicAdd(&counters[q], 1);
         it = __builtin_amdgcn_readfirstlane(__shfl(it, 0));
-        if (it >= n_items) break;
-        const int pr = __builtin_amdgcn_readfirstlane(items[it].x);
-        const int w = __builtin_amdgcn_readfirstlane(items[it].y);
+        const int64_t gi = qb[q] + it;
+        if (gi >= qb[q + 1]) {
+            ++empty;
+            q = (q + 1) & 7;
+            continue;
+        }
+        const int pr = __builtin_amdgcn_readfirstlane(items[gi].x);
+        const int w = __builtin_amdgcn_readfirstlane(items[gi].y);
         sweep_wave<T, PM, U>(probs[pr], w, lane);
     }
 }
@@ -348,7 +360,7 @@ lc_status launch_sweep_p(Plan* pl, const SweepArgs& A, hipStream_t st) {
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
 template <typename T, int PM, int U>
-lc_status launch_sweep_batch_u(const void* args, const int2* items, int64_t n_items, int* counter,
+lc_status launch_sweep_batch_u(const void* args, const int2* items, const int64_t* qb, int* counters,
                                hipStream_t st) {
     static int grid = 0;
     if (!grid) {
@@ -356,21 +368,21 @@ lc_status launch_sweep_batch_u(const void* args, const int2* items, int64_t n_it
         LC_HIP(hipGetDevice(&dev));
         LC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
         LC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_sweep_batch<T, PM, U>), kBlock, 0));
-        grid = std::max(1, cus * std::max(per_cu, 1));
+        grid = std::max(8, cus * std::max(per_cu, 1) / 8 * 8);
     }
     hipLaunchKernelGGL((k_sweep_batch<T, PM, U>), dim3(grid), dim3(kBlock), 0, st,
-                       static_cast<const SweepArgs*>(args), items, n_items, counter);
+                       static_cast<const SweepArgs*>(args), items, qb, counters);
     LC_HIP(hipGetLastError());
     return LC_OK;
 }
 
 template <typename T, int PM>
-lc_status launch_sweep_batch_p(int unroll, const void* args, const int2* items, int64_t n_items, int* counter,
+lc_status launch_sweep_batch_p(int unroll, const void* args, const int2* items, const int64_t* qb, int* counters,
                                hipStream_t st) {
     switch (unroll) {
-        case 1: return launch_sweep_batch_u<T, PM, 1>(args, items, n_items, counter, st);
-        case 2: return launch_sweep_batch_u<T, PM, 2>(args, items, n_items, counter, st);
-        default: return launch_sweep_batch_u<T, PM, 4>(args, items, n_items, counter, st);
+        case 1: return launch_sweep_batch_u<T, PM, 1>(args, items, qb, counters, st);
+        case 2: return launch_sweep_batch_u<T, PM, 2>(args, items, qb, counters, st);
+        default: return launch_sweep_batch_u<T, PM, 4>(args, items, qb, counters, st);
     }
 }
 
@@ -423,18 +435,18 @@ lc_status launch_zero_counters(int* c, int n, hipStream_t st) {
     return LC_OK;
 }
 
-lc_status launch_sweep_batch(int prec, int pm, int unroll, const void* args, const int2* items, int64_t n_items,
-                             int* counter, hipStream_t st) {
+lc_status launch_sweep_batch(int prec, int pm, int unroll, const void* args, const int2* items, const int64_t* qb,
+                             int* counters, hipStream_t st) {
     const bool f32 = prec == LC_F32;
     switch (pm) {
-        case 1: return f32 ? launch_sweep_batch_p<float, 1>(unroll, args, items, n_items, counter, st)
-                           : launch_sweep_batch_p<double, 1>(unroll, args, items, n_items, counter, st);
-        case 2: return f32 ? launch_sweep_batch_p<float, 2>(unroll, args, items, n_items, counter, st)
-                           : launch_sweep_batch_p<double, 2>(unroll, args, items, n_items, counter, st);
-        case 4: return f32 ? launch_sweep_batch_p<float, 4>(unroll, args, items, n_items, counter, st)
-                           : launch_sweep_batch_p<double, 4>(unroll, args, items, n_items, counter, st);
-        case 8: return f32 ? launch_sweep_batch_p<float, 8>(unroll, args, items, n_items, counter, st)
-                           : launch_sweep_batch_p<double, 8>(unroll, args, items, n_items, counter, st);
+        case 1: return f32 ? launch_sweep_batch_p<float, 1>(unroll, args, items, qb, counters, st)
+                           : launch_sweep_batch_p<double, 1>(unroll, args, items, qb, counters, st);
+        case 2: return f32 ? launch_sweep_batch_p<float, 2>(unroll, args, items, qb, counters, st)
+                           : launch_sweep_batch_p<double, 2>(unroll, args, items, qb, counters, st);
+        case 4: return f32 ? launch_sweep_batch_p<float, 4>(unroll, args, items, qb, counters, st)
+                           : launch_sweep_batch_p<double, 4>(unroll, args, items, qb, counters, st);
+        case 8: return f32 ? launch_sweep_batch_p<float, 8>(unroll, args, items, qb, counters, st)
+                           : launch_sweep_batch_p<double, 8>(unroll, args, items, qb, counters, st);
     }
     set_error("batched sweep: polar bound %d not supported", pm);
     return LC_ERR_UNSUPPORTED;
