@@ -61,7 +61,7 @@ def run_batched_f32(probs, steps, warmup):
     from paper_2305_11998_amd import driver, lc, tune
     bs = driver.BatchSolver(probs, prec=lc.LC_F32, static_material=True)
     tuned = tune.tune_batch(bs, verbose=True)
-    _say(f"batch tuning: unroll {tuned['sweep_unroll']}, entries {tuned['moments_entries']}")
+    _say(f"batch tuning per polar class: {tuned['per_class']}")
     bs.reset()
     bs.step(warmup)                                   # graph of `warmup` steps
     torch.cuda.synchronize()
@@ -220,7 +220,7 @@ def main():
                                "G in {8,17,51}, 16/64/128 directions, spacing h/2, float32 sweep with "
                                "Kahan moments, one persistent launch per phase",
                    "updates_per_step": upd, "graph_ms_per_step": r32["ms_graph"] / args.steps,
-                   "tuning": {k: r32["tuning"][k] for k in ("sweep_unroll", "moments_entries")}},
+                   "tuning": r32["tuning"]["per_class"]},
         "fp64_plain": out_f64,
         "speedup_vs_fp64": (value / out_f64["value"]) if out_f64 else None,
         "fp32_vs_fp64_max_err": errs,

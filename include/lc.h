@@ -247,15 +247,18 @@ lc_status lc_plan_profile(lc_plan_t plan, int32_t enable);
 lc_status lc_plan_profile_read(lc_plan_t plan, double* out);
 
 /*
- * Batched form: many independent problems (each its own rays and plan) swept
- * in one persistent launch per phase.  lc_batch_create copies the per-problem
- * pointer sets (device arrays as for lc_step) into the handle and builds a
- * work list ordered by decreasing cost; lc_batch_step then runs n_steps time
- * steps of every problem (state ping-pong as lc_step; step t reads material
- * data at kappa + t * material_stride, so with a non-zero stride n_steps must
- * not exceed the steps the caller provides); every step forms each problem's
- * moments, and the outputs hold those of the last step.  All problems must share one precision; the launch
- * tuning is that of the first problem's plan.  I_exit is required.
+ * Batched form: many independent problems (each its own rays and plan)
+ * advanced together.  Problems are grouped by polar bound (the power of two
+ * >= n_pol); per group, the sweep and the cell moments are one launch each
+ * over all members, with the launch tuning of the plan of the group's
+ * lowest-index member.  lc_batch_create copies the per-problem pointer sets
+ * (device arrays as for lc_step) into the handle and builds work lists
+ * ordered by decreasing cost; lc_batch_step then runs n_steps time steps of
+ * every problem (state ping-pong as lc_step; step t reads material data at
+ * kappa + t * material_stride, so with a non-zero stride n_steps must not
+ * exceed the steps the caller provides); every step forms each problem's
+ * moments, and the outputs hold those of the last step.  All problems must
+ * share one precision.  I_exit is required.
  */
 typedef struct {
     lc_plan_t plan;
@@ -279,7 +282,7 @@ lc_status lc_batch_free(lc_batch_t batch);
 
 /* Kernel timers of a batch: with lc_batch_profile(batch, 1), lc_batch_step runs
  * its steps without a graph and records HIP events around the prologue, the
- * persistent sweep and the persistent moments launches; lc_batch_profile_read
+ * sweep launches and the moment launches of each step; lc_batch_profile_read
  * synchronises them and returns out[6] = total ms and launch count of each, in
  * that order, clearing the record. */
 lc_status lc_batch_profile(lc_batch_t batch, int32_t enable);

@@ -16,9 +16,21 @@
 namespace lc {
 namespace {
 
+// Problems of one polar bound (the power of two >= their polar count): their
+// sweep and moment kernels are compiled for that bound, so a class of
+// two-angle problems does not carry the registers of a four-angle one.
+struct PolarClass {
+    int pm = 1;
+    int unroll = 2, ent = 3;            // launch tuning of the class's lowest-index member
+    int2* d_sweep_items = nullptr;      // {problem, bundle traversal}
+    int64_t* d_sweep_qb = nullptr;      // [9] bounds of the eight per-XCD sweep queues
+    int2* d_mom_items = nullptr;        // {problem, wavefront of a tile}
+    int64_t n_mom_items = 0;
+};
+
 struct Batch {
     uint32_t magic = 0;
-    int n = 0, prec = 0, pm = 1, unroll = 4, ent = 2;
+    int n = 0, prec = 0;
     double c = 0.0;
     std::vector<lc_problem_t> probs;
     std::vector<Plan*> plans;
@@ -27,11 +39,8 @@ struct Batch {
     void* d_coef_args = nullptr;        // [n]
     void* d_mom_args = nullptr;         // [2][n]
     void* d_bnd_args = nullptr;         // [n]
-    int2* d_sweep_items = nullptr;
-    int2* d_mom_items = nullptr;        // {problem, wavefront of a tile}
-    int64_t n_sweep_items = 0, n_mom_items = 0;
-    int64_t* d_sweep_qb = nullptr;      // [9] bounds of the eight per-XCD sweep queues
-    int* d_counters = nullptr;          // [8] counters of the sweep queues
+    std::vector<PolarClass> cls;
+    int* d_counters = nullptr;          // [8 * classes] counters of the sweep queues
     unsigned long long* d_gmax = nullptr;   // per-group source maxima of every problem
     int64_t n_gmax = 0, max_blocks = 0, coef_blocks = 0, bnd_lanes = 0;
     int max_G = 1;
@@ -78,24 +87,24 @@ lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
     lc_status rc = LC_OK;
     for (int t = 0; t < n_steps && rc == LC_OK; ++t) {
         const int parity = t & 1;
-        rc = launch_zero_counters(b->d_counters, 8, st);
+        rc = launch_zero_counters(b->d_counters, 8 * (int)b->cls.size(), st);
         if (rc == LC_OK) rc = ev_begin(b, 0, st);
         if (rc == LC_OK)
             rc = launch_prologue_batch(b->prec, b->d_coef_args, b->n, b->max_blocks, b->coef_blocks, b->max_G,
                                        b->d_gmax, b->n_gmax, t, st);
         if (rc == LC_OK) rc = ev_end(b, 0, st);
         if (rc == LC_OK) rc = ev_begin(b, 1, st);
-        if (rc == LC_OK)
-            rc = launch_sweep_batch(b->prec, b->pm, b->unroll,
-                                    static_cast<char*>(b->d_sweep_args) + parity * b->n * sb, b->d_sweep_items,
-                                    b->d_sweep_qb, b->d_counters, st);
+        for (size_t c = 0; c < b->cls.size() && rc == LC_OK; ++c)
+            rc = launch_sweep_batch(b->prec, b->cls[c].pm, b->cls[c].unroll,
+                                    static_cast<char*>(b->d_sweep_args) + parity * b->n * sb,
+                                    b->cls[c].d_sweep_items, b->cls[c].d_sweep_qb, b->d_counters + 8 * c, st);
         if (rc == LC_OK) rc = ev_end(b, 1, st);
         if (rc == LC_OK) {                            // every step forms its moments
             rc = ev_begin(b, 2, st);
-            if (rc == LC_OK)
-                rc = launch_moments_batch(b->prec, b->pm, b->ent,
+            for (size_t c = 0; c < b->cls.size() && rc == LC_OK; ++c)
+                rc = launch_moments_batch(b->prec, b->cls[c].pm, b->cls[c].ent,
                                           static_cast<char*>(b->d_mom_args) + parity * b->n * mb,
-                                          b->d_mom_items, b->n_mom_items, st);
+                                          b->cls[c].d_mom_items, b->cls[c].n_mom_items, st);
             if (rc == LC_OK) rc = ev_end(b, 2, st);
             if (rc == LC_OK && b->bnd_lanes > 0) rc = launch_boundary_batch(b->d_bnd_args, b->n, b->bnd_lanes, st);
         }
@@ -115,10 +124,12 @@ void free_batch(Batch* b) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (b->capture) (void)hipStreamDestroy(b->capture);
     for (void* p : {b->d_sweep_args, b->d_coef_args, b->d_mom_args, b->d_bnd_args,
-                    static_cast<void*>(b->d_sweep_items), static_cast<void*>(b->d_mom_items),
-                    static_cast<void*>(b->d_counters), static_cast<void*>(b->d_gmax),
-                    static_cast<void*>(b->d_sweep_qb)})
+                    static_cast<void*>(b->d_counters), static_cast<void*>(b->d_gmax)})
         if (p) (void)hipFree(p);
+    for (auto& c : b->cls)
+        for (void* p : {static_cast<void*>(c.d_sweep_items), static_cast<void*>(c.d_sweep_qb),
+                        static_cast<void*>(c.d_mom_items)})
+            if (p) (void)hipFree(p);
     b->magic = 0;
     delete b;
 }
@@ -177,7 +188,7 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
     LC_ARG(out, "out is NULL");
     *out = nullptr;
     LC_ARG(n_problems >= 1 && problems, "need at least one problem");
-    int prec = -1, pm = 1;
+    int prec = -1;
     for (int q = 0; q < n_problems; ++q) {
         const lc_problem_t& P = problems[q];
         Plan* pl = as_plan(P.plan);
@@ -189,18 +200,14 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
         LC_ARG(P.material_stride >= 0, "problem %d: material_stride must be >= 0", q);
         if (prec < 0) prec = pl->prec;
         LC_ARG(pl->prec == prec, "all problems of a batch must use one precision");
-        while (pm < pl->rays->n_pol) pm *= 2;
     }
     Batch* b = new (std::nothrow) Batch();
     LC_CHECK(b, LC_ERR_ALLOC, "host allocation failed");
     b->magic = kBatchMagic;
     b->n = n_problems;
     b->prec = prec;
-    b->pm = pm;
     b->probs.assign(problems, problems + n_problems);
     for (int q = 0; q < n_problems; ++q) b->plans.push_back(as_plan(problems[q].plan));
-    b->unroll = b->plans[0]->sweep_unroll;
-    b->ent = b->plans[0]->moments_entries;
     lc_status rc = LC_OK;
     // argument records
     const size_t sb = sweep_args_bytes(), cb = coef_args_bytes();
@@ -238,32 +245,43 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
         free_batch(b);
         return LC_ERR_UNSUPPORTED;
     }
-    // work items, problems in decreasing cost
+    // work items per polar class, problems in decreasing cost
     std::vector<int> order(n_problems);
     std::iota(order.begin(), order.end(), 0);
     auto cost = [&](int q) { return (double)b->plans[q]->half_elems; };
     std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
-    std::vector<int2> si, mi;
-    std::vector<double> scost;          // summed steps of the sweep items, for the queue split
-    for (int q : order) {
-        const Plan* pl = b->plans[q];
-        for (int64_t B = 0; B < pl->n_bun; ++B)
-            for (int d = 0; d < 2; ++d) {
-                si.push_back(make_int2(q, (int)(d * pl->n_bun + B)));
-                scost.push_back((double)pl->bun_len_h[B] * pl->rays->n_pol);
+    auto pm_of = [&](int q) {
+        int pm = 1;
+        while (pm < b->plans[q]->rays->n_pol) pm *= 2;
+        return pm;
+    };
+    if (rc == LC_OK) rc = upload(&b->d_sweep_args, hs.data(), hs.size());
+    if (rc == LC_OK) rc = upload(&b->d_coef_args, hc.data(), hc.size());
+    for (int pm = 1; pm <= kMaxPol && rc == LC_OK; pm *= 2) {
+        std::vector<int2> si, mi;
+        std::vector<double> scost;      // summed steps of the sweep items, for the queue split
+        for (int q : order) {
+            if (pm_of(q) != pm) continue;
+            const Plan* pl = b->plans[q];
+            for (int64_t B = 0; B < pl->n_bun; ++B)
+                for (int d = 0; d < 2; ++d) {
+                    si.push_back(make_int2(q, (int)(d * pl->n_bun + B)));
+                    scost.push_back((double)pl->bun_len_h[B] * pl->rays->n_pol);
+                }
+            const int64_t mw = moment_tiles(pl) * moment_tile_waves(pl);
+            if (mw >= INT32_MAX) {
+                rc = LC_ERR_UNSUPPORTED;
+                set_error("batched moments: too many work items in problem %d", q);
             }
-        const int64_t mw = moment_tiles(pl) * moment_tile_waves(pl);
-        if (mw >= INT32_MAX) rc = LC_ERR_UNSUPPORTED;
-        for (int64_t w = 0; w < mw && rc == LC_OK; ++w) mi.push_back(make_int2(q, (int)w));
-    }
-    if (rc != LC_OK) set_error("batched moments: too many work items in one problem");
-    if (rc == LC_OK && (int64_t)mi.size() / 4 >= INT32_MAX / 2) {
-        rc = LC_ERR_UNSUPPORTED;
-        set_error("batched moments: grid too large");
-    }
-    b->n_sweep_items = (int64_t)si.size();
-    int64_t sqb[9];
-    {
+            for (int64_t w = 0; w < mw && rc == LC_OK; ++w) mi.push_back(make_int2(q, (int)w));
+        }
+        if (si.empty() || rc != LC_OK) continue;
+        if ((int64_t)mi.size() / 4 >= INT32_MAX / 2) {
+            rc = LC_ERR_UNSUPPORTED;
+            set_error("batched moments: grid too large");
+            break;
+        }
+        int64_t sqb[9];
         double tot = 0.0;
         for (double c : scost) tot += c;
         double acc = 0.0;
@@ -274,17 +292,24 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
             while (x < 8 && acc >= tot * x / 8.0) sqb[x++] = i + 1;
         }
         while (x < 9) sqb[x++] = (int64_t)scost.size();
+        PolarClass c;
+        c.pm = pm;
+        for (int q = 0; q < n_problems; ++q)
+            if (pm_of(q) == pm) {
+                c.unroll = b->plans[q]->sweep_unroll;
+                c.ent = b->plans[q]->moments_entries;
+                break;
+            }
+        c.n_mom_items = (int64_t)mi.size();
+        b->cls.push_back(c);
+        PolarClass& cc = b->cls.back();
+        rc = upload(reinterpret_cast<void**>(&cc.d_sweep_items), si.data(), si.size() * sizeof(int2));
+        if (rc == LC_OK) rc = upload(reinterpret_cast<void**>(&cc.d_sweep_qb), sqb, sizeof(sqb));
+        if (rc == LC_OK) rc = upload(reinterpret_cast<void**>(&cc.d_mom_items), mi.data(), mi.size() * sizeof(int2));
     }
-    b->n_mom_items = (int64_t)mi.size();
-
-    if (rc == LC_OK) rc = upload(&b->d_sweep_args, hs.data(), hs.size());
-    if (rc == LC_OK) rc = upload(&b->d_coef_args, hc.data(), hc.size());
-    if (rc == LC_OK) rc = upload(reinterpret_cast<void**>(&b->d_sweep_items), si.data(), si.size() * sizeof(int2));
-    if (rc == LC_OK) rc = upload(reinterpret_cast<void**>(&b->d_mom_items), mi.data(), mi.size() * sizeof(int2));
-    if (rc == LC_OK) rc = upload(reinterpret_cast<void**>(&b->d_sweep_qb), sqb, sizeof(sqb));
     if (rc == LC_OK) {
-        const int zero[8] = {};
-        rc = upload(reinterpret_cast<void**>(&b->d_counters), zero, sizeof(zero));
+        const std::vector<int> zero(8 * b->cls.size(), 0);
+        rc = upload(reinterpret_cast<void**>(&b->d_counters), zero.data(), zero.size() * sizeof(int));
     }
     if (rc == LC_OK) rc = build_moment_args(b, 1.0);
     if (rc == LC_OK) {

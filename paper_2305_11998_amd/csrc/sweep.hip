@@ -211,18 +211,21 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
     };
     auto srow = [&](int t) -> gptr<const T> { return xin + (size_t)(t < L ? t : L - 1) * SP; };
 
-    int2 gi1[U];
-    T2 gf0[U], gf1[U];
+    // of each segment record the sweep needs the cell index and the length only
+    const gptr<const int> gcell = (gptr<const int>)gi;
+    const gptr<const T> glen = (gptr<const T>)gf;
+    int cell1[U];
+    T len0[U], len1[U];
     Coef<T> c0[U];
     T x0[U][NS];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int j0 = seg(u), j1 = seg(U + u);
-        const int2 g0 = ld2(gi + j0);
-        gf0[u] = ld2(gf + j0);
-        c0[u] = ld2(coef + ((size_t)g0.x * G + g));
-        gi1[u] = ld2(gi + j1);
-        gf1[u] = ld2(gf + j1);
+        const int cell0 = gcell[2 * (size_t)j0];
+        len0[u] = glen[2 * (size_t)j0];
+        c0[u] = ld2(coef + ((size_t)cell0 * G + g));
+        cell1[u] = gcell[2 * (size_t)j1];
+        len1[u] = glen[2 * (size_t)j1];
         const gptr<const T> r = srow(u);
 #pragma unroll
         for (int q = 0; q < NS; ++q) x0[u][q] = val[q] ? ldg_stream(r + pol[q] * kWave) : (T)0;
@@ -230,23 +233,23 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
     for (int t0 = 0; t0 < L; t0 += U) {
         Coef<T> c1[U];
         T x1[U][NS];
-        int2 gi2[U];
-        T2 gf2[U];
+        int cell2[U];
+        T len2[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            c1[u] = ld2(coef + ((size_t)gi1[u].x * G + g));
+            c1[u] = ld2(coef + ((size_t)cell1[u] * G + g));
             const gptr<const T> r = srow(t0 + U + u);
 #pragma unroll
             for (int q = 0; q < NS; ++q) x1[u][q] = val[q] ? ldg_stream(r + pol[q] * kWave) : (T)0;
             const int j2 = seg(t0 + 2 * U + u);
-            gi2[u] = ld2(gi + j2);
-            gf2[u] = ld2(gf + j2);
+            cell2[u] = gcell[2 * (size_t)j2];
+            len2[u] = glen[2 * (size_t)j2];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + u;
             const bool live = t < n;
-            const T ktl = c0[u].kt * gf0[u].x;
+            const T ktl = c0[u].kt * len0[u];
             const T b = cbt * recip(c0[u].kt);                      // 1/(c dt kappa_t)
             Att<T> at[NS];
 #pragma unroll
@@ -269,9 +272,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             c0[u] = c1[u];
-            gf0[u] = gf1[u];
-            gi1[u] = gi2[u];
-            gf1[u] = gf2[u];
+            len0[u] = len1[u];
+            cell1[u] = cell2[u];
+            len1[u] = len2[u];
 #pragma unroll
             for (int q = 0; q < NS; ++q) x0[u][q] = x1[u][q];
         }

@@ -126,12 +126,25 @@ class BatchSolver:
         self.batch = None
         self.rebuild()
 
+    def polar_class(self, s):
+        """Polar bound of a member: the power of two >= its polar count (the
+        library launches each class separately)."""
+        pm = 1
+        while pm < s.prob.n_pol:
+            pm *= 2
+        return pm
+
+    def classes(self):
+        return sorted({self.polar_class(s) for s in self.solvers})
+
     def rebuild(self, tuning=None):
         """(Re)create the batch handle, optionally with a new launch tuning
-        (sweep_unroll, moments_entries) set on every member's plan."""
+        (sweep_unroll, moments_entries) set on every member's plan: one pair
+        for all, or a dict {polar class: pair}."""
         if tuning is not None:
             for s in self.solvers:
-                lc.lc_plan_set_tuning(s.plan, *tuning)
+                t = tuning[self.polar_class(s)] if isinstance(tuning, dict) else tuning
+                lc.lc_plan_set_tuning(s.plan, *t)
         if self.batch is not None:
             self.batch.free()
         static_material = self.static

@@ -94,28 +94,39 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
 
 
 def tune_batch(bs, steps: int = 2, verbose: bool = False):
-    """Pick (sweep_unroll, moments_entries) for a BatchSolver by timing its
-    persistent launches (lc_batch_profile) for each candidate; the batch is
-    left rebuilt with the choice."""
+    """Pick (sweep_unroll, moments_entries) per polar class of a BatchSolver
+    (the library launches each class separately, with the tuning of its
+    members' plans).  Each class is searched in turn with the others held at
+    their current choice, timing the batch's launches (lc_batch_profile);
+    the batch is left rebuilt with the choice."""
     import torch
-    times = {}
-    combos = sorted({(u, BASE[1]) for u in SWEEP_CANDIDATES} | {(BASE[0], e) for e in MOMENT_CANDIDATES})
-    for u, e in combos:
-        bs.rebuild((u, e))
+    classes = bs.classes()
+    best = {pm: list(BASE) for pm in classes}
+
+    def run(cfg):
+        bs.rebuild({pm: tuple(v) for pm, v in cfg.items()})
         lc.lc_batch_profile(bs.batch, True)
         bs.reset()
         bs.step(steps)
         torch.cuda.synchronize()
         pro, npro, sw, nsw, mo, nmo = lc.lc_batch_profile_read(bs.batch)
         lc.lc_batch_profile(bs.batch, False)
-        times[(u, e)] = (sw / max(nsw, 1), mo / max(nmo, 1))
-        if verbose:
-            print(f"  tune batch: unroll {u} entries {e}: sweep {times[(u, e)][0]:.3f} ms, "
-                  f"moments {times[(u, e)][1]:.3f} ms", file=sys.stderr, flush=True)
-    best_u = min(SWEEP_CANDIDATES, key=lambda u: times[(u, BASE[1])][0])
-    best_e = min(MOMENT_CANDIDATES, key=lambda e: times[(BASE[0], e)][1])
-    bs.rebuild((best_u, best_e))
-    return dict(sweep_unroll=best_u, moments_entries=best_e,
-                sweep_ms={str(k): v[0] for k, v in times.items()},
-                moments_ms={str(k): v[1] for k, v in times.items()})
+        return sw / max(nsw, 1), mo / max(nmo, 1)
 
+    times = {}
+    for pm in classes:
+        for k, cands in ((0, SWEEP_CANDIDATES), (1, MOMENT_CANDIDATES)):
+            res = {}
+            for v in cands:
+                cfg = {c: list(x) for c, x in best.items()}
+                cfg[pm][k] = v
+                res[v] = run(cfg)[k]
+                times[(pm, k, v)] = res[v]
+                if verbose:
+                    what = "unroll" if k == 0 else "entries"
+                    print(f"  tune batch: polar class {pm} {what} {v}: "
+                          f"{'sweep' if k == 0 else 'moments'} {res[v]:.3f} ms", file=sys.stderr, flush=True)
+            best[pm][k] = min(res, key=res.get)
+    bs.rebuild({pm: tuple(v) for pm, v in best.items()})
+    return dict(per_class={str(pm): dict(sweep_unroll=v[0], moments_entries=v[1]) for pm, v in best.items()},
+                times={f"{pm}/{'unroll' if k == 0 else 'entries'}/{v}": t for (pm, k, v), t in times.items()})
