@@ -134,7 +134,9 @@ __device__ __forceinline__ void stg_stream(gptr<T> p, T v) { __builtin_nontempor
 // [t][p][lane] of the bundle (one 64-lane contiguous run per p) and writes the
 // new ones at the same place.  Loads run one chunk of U steps ahead of the
 // arithmetic: the geometry two chunks ahead, the cell coefficients (which
-// depend on it) and the stored values one chunk ahead.
+// depend on it) and the stored values one chunk ahead.  Each chunk's loads
+// are issued together, so a wavefront asks for U consecutive rows of its
+// bundle at once.
 //
 // Polar angles sit in PM register slots (PM >= P): lower slot i holds polar
 // p = i, upper slot i holds p = P - 1 - i, so that with a mirror-symmetric
@@ -338,7 +340,8 @@ lc_status launch_sweep_t(Plan* pl, const SweepArgs& A, hipStream_t st) {
     switch (pl->sweep_unroll) {
         case 1: hipLaunchKernelGGL((k_sweep<T, PM, 1>), grid, block, 0, st, A); break;
         case 2: hipLaunchKernelGGL((k_sweep<T, PM, 2>), grid, block, 0, st, A); break;
-        default: hipLaunchKernelGGL((k_sweep<T, PM, 4>), grid, block, 0, st, A); break;
+        case 4: hipLaunchKernelGGL((k_sweep<T, PM, 4>), grid, block, 0, st, A); break;
+        default: hipLaunchKernelGGL((k_sweep<T, PM, 8>), grid, block, 0, st, A); break;
     }
     LC_HIP(hipGetLastError());
     return prof_end(pl, pl->ev_sweep, st);
@@ -385,7 +388,8 @@ lc_status launch_sweep_batch_p(int unroll, const void* args, const int2* items, 
     switch (unroll) {
         case 1: return launch_sweep_batch_u<T, PM, 1>(args, items, qb, counters, st);
         case 2: return launch_sweep_batch_u<T, PM, 2>(args, items, qb, counters, st);
-        default: return launch_sweep_batch_u<T, PM, 4>(args, items, qb, counters, st);
+        case 4: return launch_sweep_batch_u<T, PM, 4>(args, items, qb, counters, st);
+        default: return launch_sweep_batch_u<T, PM, 8>(args, items, qb, counters, st);
     }
 }
 

@@ -18,9 +18,9 @@ import os
 
 from . import lc
 
-SWEEP_CANDIDATES = (1, 2, 4)
+SWEEP_CANDIDATES = (2, 4, 8)
 MOMENT_CANDIDATES = (1, 2, 3, 4)
-BASE = (2, 3)             # the setting the other parameter is held at while one is searched
+BASE = (4, 3)             # the setting the other parameter is held at while one is searched
 DEFAULT_CACHE = os.environ.get(
     "LC_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "lc_tuning.json"))
 
