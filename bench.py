@@ -49,6 +49,31 @@ def sweep_algorithmic_bytes(solver, elem):
     return state + geom + coef + io
 
 
+TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sweep_batch_traffic.txt")
+SWEEP_SOURCES = ("sweep.hip", "batch.hip", "lc_internal.hpp")
+
+
+def recorded_traffic(tuning):
+    """HBM bytes per sweep phase measured with rocprofv3 counters for this
+    workload, or None when the sweep sources or the tuning differ from those
+    the counters were taken with."""
+    import hashlib
+    try:
+        rec = dict(line.split(" ", 1) for line in open(TRAFFIC_RECORD).read().splitlines()
+                   if line and not line.startswith("#"))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in SWEEP_SOURCES:
+        with open(os.path.join(ROOT, "paper_2305_11998_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if rec.get("source_sha256", "").strip() != h.hexdigest():
+        return None
+    if json.loads(rec.get("tuning", "null")) != tuning:
+        return None
+    return float(rec["traffic_bytes"])
+
+
 def moment_errors(got, ref):
     from tests.parity_util import err_E, err_F, err_f
     import workloads as W
@@ -155,9 +180,76 @@ def cpu_baseline(prob, budget_s=12.0):
                        f"{done_upd} updates in {t_used:.1f} s; numpy on one host thread)")
 
 
+def run_single(k, steps, warmup):
+    """One problem of the named workloads (workloads.config(k)) on the plain
+    path, float32 and float64: eager steps timed with the library's kernel
+    timers, plus the float32-vs-float64 moment errors after one step."""
+    import torch
+    import workloads as W
+    from paper_2305_11998_amd import driver, lc, tune
+    prob = W.config(k, steps=1)
+    out = {}
+    for prec, name in ((lc.LC_F32, "f32"), (lc.LC_F64, "f64")):
+        s = driver.Solver(prob, prec=prec)
+        tuned = tune.tune(s, cache=None)
+        s.reset()
+        for _ in range(warmup):
+            s.bench_step()
+        torch.cuda.synchronize()
+        lc.lc_plan_profile_read(s.plan)
+        lc.lc_plan_profile(s.plan, True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            s.bench_step()
+        e1.record()
+        torch.cuda.synchronize()
+        sw, nsw, mo, nmo = lc.lc_plan_profile_read(s.plan)
+        lc.lc_plan_profile(s.plan, False)
+        s.reset()
+        s.step(1)
+        out[name] = dict(ms=e0.elapsed_time(e1) / steps, sweep_ms=sw / max(nsw, 1), moments_ms=mo / max(nmo, 1),
+                         upd=s.updates_per_step(), moments=s.moments(),
+                         alg=sweep_algorithmic_bytes(s, 4 if prec == lc.LC_F32 else 8),
+                         tuning={kk: tuned[kk] for kk in ("sweep_unroll", "moments_entries")})
+        _say(f"config {k} {name}: {out[name]['ms']:.3f} ms/step, sweep {out[name]['sweep_ms']:.3f} ms, "
+             f"moments {out[name]['moments_ms']:.3f} ms")
+        del s
+        torch.cuda.empty_cache()
+    return prob, out
+
+
+def main_single(args):
+    prob, out = run_single(args.config, args.steps, args.warmup)
+    f32, f64 = out["f32"], out["f64"]
+    errs = moment_errors(f32["moments"], f64["moments"])
+    value = f32["upd"] / (f32["ms"] / 1e3)
+    achieved = f32["alg"] / (f32["sweep_ms"] / 1e3) / 1e9
+    res = {
+        "metric": "segment-updates/s, FP32 vs FP64 sweep at <=1e-5 rel error (single problem)",
+        "value": value, "unit": "segment-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": f32["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"single problem {prob.name}: {prob.nx}x{prob.ny} cells, G={prob.G}, "
+                               f"{prob.M} directions, spacing {prob.h_moc:.4g} cm",
+                   "updates_per_step": f32["upd"], "tuning": f32["tuning"]},
+        "fp64_plain": {"value": f64["upd"] / (f64["ms"] / 1e3), "ms_per_step": f64["ms"],
+                       "sweep_ms": f64["sweep_ms"], "moments_ms": f64["moments_ms"], "tuning": f64["tuning"]},
+        "fp32_vs_fp64_max_err": errs,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sweep<float,P,U>",
+                     "kernel_ms": f32["sweep_ms"], "moments_kernel_ms": f32["moments_ms"],
+                     "algorithmic_bytes_per_launch": f32["alg"]},
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=("batch", "single"), default="batch",
+                    help="batch: the 64-problem batched form (default); single: one problem of --config")
+    ap.add_argument("--config", type=int, default=2, help="workload index for --workload single (0, 1, 2 or 4)")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--f64-steps", type=int, default=2)
@@ -173,6 +265,9 @@ def main():
     import workloads as W
 
     torch.cuda.init()
+    if args.workload == "single":
+        main_single(args)
+        return
     t0 = time.time()
     probs = W.batch_problems(steps=1)
     _say(f"64 problems generated in {time.time() - t0:.0f} s")
@@ -203,6 +298,7 @@ def main():
 
     value = upd / (ms32 / 1e3)
     achieved = alg / (r32["sweep_ms"] / 1e3) / 1e9
+    traffic = recorded_traffic(r32["tuning"]["per_class"])
     out = {
         "metric": "segment-updates/s, FP32 batched vs FP64 sweep at <=1e-5 rel error",
         "value": value,
@@ -218,15 +314,16 @@ def main():
         "data": "synthetic (seeded Fleck-Cummings-type problems, smooth temperature fields)",
         "config": {"workload": "batched form: 64 independent problems, meshes {32,64,128,256}^2 on 6x6 cm, "
                                "G in {8,17,51}, 16/64/128 directions, spacing h/2, float32 sweep with "
-                               "Kahan moments, one persistent launch per phase",
+                               "Kahan moments, one launch per phase and polar group",
                    "updates_per_step": upd, "graph_ms_per_step": r32["ms_graph"] / args.steps,
                    "tuning": r32["tuning"]["per_class"]},
         "fp64_plain": out_f64,
         "speedup_vs_fp64": (value / out_f64["value"]) if out_f64 else None,
         "fp32_vs_fp64_max_err": errs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweep_batch<float,4,U>", "kernel_ms": r32["sweep_ms"],
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_sweep_batch<float,PM,U> (one launch per polar group, summed)",
+                     "kernel_ms": r32["sweep_ms"],
                      "moments_kernel_ms": r32["moments_ms"], "algorithmic_bytes_per_launch": alg},
     }
     if not args.no_cpu_baseline:
