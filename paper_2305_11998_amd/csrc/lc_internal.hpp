@@ -115,7 +115,7 @@ struct Plan {
     int moments_entries = 0;          // C(i, m) entries per list in the moment pipeline (1..4)
     // State layout: the lanes (k, g) of pair a, g fastest, are cut into
     // bundles of 64 (one wavefront each).  For traversal d and bundle B the
-    // values [t][p][lane] (t = step along the traversal, padded to the
+    // values [t][lane][p] (t = step along the traversal, padded to the
     // longest characteristic of the bundle) are contiguous at
     // d * half_elems + bun_base[B].
     int64_t n_bun = 0;                // bundles over all pairs

@@ -48,6 +48,10 @@ template <> struct Acc<float> {
 };
 
 constexpr int kMomWaves = 4;   // wavefronts per block of the moment kernels
+// the first state offset of an entry carries the lane of the ray's group 0 in
+// its top bits (state offsets stay far below 2^56)
+constexpr int kLaneShift = 56;
+constexpr long long kOffMask = (1LL << kLaneShift) - 1;
 constexpr int kXcdRun = 64;    // consecutive blocks per XCD in the batched moment launch
 constexpr int kTileWaves = kMomWaves * kXcdRun;   // wavefronts of a tile at most: one XCD run
 
@@ -68,17 +72,36 @@ template <typename T> struct Slot {
 };
 
 template <typename T>
-__device__ __forceinline__ Slot<T> load_slot(gptr<const long long> eo, gptr<const T> cw, int e, bool ok, int g) {
+__device__ __forceinline__ Slot<T> load_slot(gptr<const long long> eo, gptr<const T> cw, int e, bool ok, int g,
+                                             int P) {
     Slot<T> s;
     const int ee = ok ? e : 0;
     const T w = cw[ee];
-    const long long r0 = eo[(size_t)ee * 4 + 0], r1 = eo[(size_t)ee * 4 + 1];
+    const long long q0 = eo[(size_t)ee * 4 + 0], r1 = eo[(size_t)ee * 4 + 1];
     const long long r2 = eo[(size_t)ee * 4 + 2], r3 = eo[(size_t)ee * 4 + 3];
-    const bool first = g < kWave - (int)(r0 & (kWave - 1));
+    const long long r0 = q0 & kOffMask;
+    const int lane0 = (int)(q0 >> kLaneShift);      // lane of the ray's group 0
+    const bool first = g < kWave - lane0;
     s.w = ok ? w : (T)0;
-    s.o0 = (size_t)(first ? r0 : r1) + g;
-    s.o1 = (size_t)(first ? r2 : r3) + g;
+    s.o0 = (size_t)(first ? r0 : r1) + (size_t)g * P;
+    s.o1 = (size_t)(first ? r2 : r3) + (size_t)g * P;
     return s;
+}
+
+// The P values of one entry for one traversal (contiguous, [lane][p]); with
+// P == PM (a power of two) one vector load.
+template <typename T, int PM>
+__device__ __forceinline__ void load_entry(gptr<const T> st, size_t o, int P, T (&x)[PM]) {
+    constexpr bool kVecOk = PM >= 2 && (PM & (PM - 1)) == 0;
+    if (kVecOk && P == PM) {
+        using V = T __attribute__((ext_vector_type(PM)));
+        const V v = *(gptr<const V>)(st + o);
+#pragma unroll
+        for (int p = 0; p < PM; ++p) x[p] = v[p];
+    } else {
+#pragma unroll
+        for (int p = 0; p < PM; ++p) x[p] = p < P ? st[o + p] : (T)0;
+    }
 }
 
 // Lane (cell, g) of a tile of tw x th cells.  For each azimuth
@@ -119,20 +142,18 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
     int b2 = co[min(2, np)];
     Slot<T> cur[K];
 #pragma unroll
-    for (int u = 0; u < K; ++u) cur[u] = load_slot(eo, cw, b0 + u, b0 + u < b1, g);
+    for (int u = 0; u < K; ++u) cur[u] = load_slot(eo, cw, b0 + u, b0 + u < b1, g, P);
     for (int a = 0; a < np; ++a) {
         T x[K][2][PM];
 #pragma unroll
-        for (int u = 0; u < K; ++u)
-#pragma unroll
-            for (int p = 0; p < PM; ++p) {
-                x[u][0][p] = p < P ? st[cur[u].o0 + p * kWave] : (T)0;
-                x[u][1][p] = p < P ? st[cur[u].o1 + p * kWave] : (T)0;
-            }
+        for (int u = 0; u < K; ++u) {
+            load_entry<T, PM>(st, cur[u].o0, P, x[u][0]);
+            load_entry<T, PM>(st, cur[u].o1, P, x[u][1]);
+        }
         const bool more = a + 1 < np;
         Slot<T> nxt[K];
 #pragma unroll
-        for (int u = 0; u < K; ++u) nxt[u] = load_slot(eo, cw, b1 + u, more && b1 + u < b2, g);
+        for (int u = 0; u < K; ++u) nxt[u] = load_slot(eo, cw, b1 + u, more && b1 + u < b2, g, P);
         const int b3 = co[min(a + 3, np)];
         T Iim[2][PM];
 #pragma unroll
@@ -146,13 +167,14 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
 #pragma unroll
                 for (int p = 0; p < PM; ++p) Iim[d][p] += cur[u].w * x[u][d][p];
         for (int e = b0 + K; e < b1; ++e) {
-            const Slot<T> t = load_slot(eo, cw, e, true, g);
+            const Slot<T> t = load_slot(eo, cw, e, true, g, P);
+            T y[2][PM];
+            load_entry<T, PM>(st, t.o0, P, y[0]);
+            load_entry<T, PM>(st, t.o1, P, y[1]);
 #pragma unroll
-            for (int p = 0; p < PM; ++p) {
-                if (p >= P) continue;
-                Iim[0][p] += t.w * st[t.o0 + p * kWave];
-                Iim[1][p] += t.w * st[t.o1 + p * kWave];
-            }
+            for (int d = 0; d < 2; ++d)
+#pragma unroll
+                for (int p = 0; p < PM; ++p) Iim[d][p] += t.w * y[d][p];
         }
     T part[7];
 #pragma unroll
@@ -232,9 +254,9 @@ __global__ __launch_bounds__(kMomWaves * kWave) void k_cell_moments_batch(const 
     moments_tile<T, PM, K>(A, tile, w * kWave + (threadIdx.x & (kWave - 1)));
 }
 
-// Offsets of every C(i, m) entry into the bundle-major state of a plan:
-// lanes g < 64 - (first & 63) lie in the bundle of the ray's group 0, the rest
-// in the next bundle.
+// Offsets of every C(i, m) entry into the bundle-major state of a plan
+// ([t][lane][p] per bundle): lanes g < 64 - lane0 lie in the bundle of the
+// ray's group 0, the rest in the next bundle.
 __global__ void k_entry_offsets(const int* __restrict__ csr_off, const int* __restrict__ csr_ray,
                                 const int2* __restrict__ csr_t, const int* __restrict__ ray_off,
                                 const int* __restrict__ bun_off, const int64_t* __restrict__ bun_base,
@@ -250,12 +272,12 @@ __global__ void k_entry_offsets(const int* __restrict__ csr_off, const int* __re
         const int lane0 = f0 & (kWave - 1);
         const int64_t step = (int64_t)P * kWave;
         long long* o = out + (size_t)e * 4;
-        o[0] = bun_base[B0] + t.x * step + lane0;
-        o[2] = half + bun_base[B0] + t.y * step + lane0;
+        o[0] = (bun_base[B0] + t.x * step + (int64_t)lane0 * P) | ((long long)lane0 << kLaneShift);
+        o[2] = half + bun_base[B0] + t.y * step + (int64_t)lane0 * P;
         if (lane0 + G > kWave) {
             const int split = kWave - lane0;
-            o[1] = bun_base[B0 + 1] + t.x * step - split;
-            o[3] = half + bun_base[B0 + 1] + t.y * step - split;
+            o[1] = bun_base[B0 + 1] + t.x * step - (int64_t)split * P;
+            o[3] = half + bun_base[B0 + 1] + t.y * step - (int64_t)split * P;
         } else {
             o[1] = o[0];
             o[3] = o[2];
@@ -389,6 +411,7 @@ lc_status launch_cell_moments_p(int P, int ent, const MomArgs& A, hipStream_t st
 
 lc_status plan_init_moments(Plan* pl) {
     Rays* r = pl->rays;
+    LC_CHECK(2 * pl->half_elems < (1LL << kLaneShift), LC_ERR_UNSUPPORTED, "state too large for the moment offsets");
     const int64_t n_keys = (int64_t)r->cells * r->n_pairs;
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&pl->d_ent_off),
                              std::max<size_t>((size_t)r->n_seg, 1) * 4 * sizeof(long long));

@@ -54,11 +54,11 @@ __device__ void for_slots(const SlotArgs& A, Fn fn) {
     const int r0 = A.ray_off[a], Ka = A.ray_off[a + 1] - r0;
     const int64_t base = (int64_t)d * A.half + A.bun_base[B];
     const int64_t n = (int64_t)A.bun_len[B] * A.P * kWave;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const int lane = (int)(i & (kWave - 1));
-        const int64_t tp = i / kWave;
-        const int p = (int)(tp % A.P);
-        const int t = (int)(tp / A.P);
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {      // i = (t * 64 + lane) * P + p
+        const int p = (int)(i % A.P);
+        const int64_t tl = i / A.P;
+        const int lane = (int)(tl & (kWave - 1));
+        const int t = (int)(tl / kWave);
         const int f = (int)(B - A.bun_off[a]) * kWave + lane;
         const int kl = f / A.G, g = f - kl * A.G;
         int j = -1;

@@ -131,8 +131,8 @@ __device__ __forceinline__ void stg_stream(gptr<T> p, T v) { __builtin_nontempor
 
 // One wavefront per (traversal d, bundle B) of a problem.  Lane (k, g) walks
 // its characteristic; step t reads the P stored values of the lane at
-// [t][p][lane] of the bundle (one 64-lane contiguous run per p) and writes the
-// new ones at the same place.  Loads run one chunk of U steps ahead of the
+// [t][lane][p] of the bundle (contiguous per lane, 64 * P contiguous values
+// per step) and writes the new ones at the same place.  Loads run one chunk of U steps ahead of the
 // arithmetic: the geometry two chunks ahead, the cell coefficients (which
 // depend on it) and the stored values one chunk ahead.  Each chunk's loads
 // are issued together, so a wavefront asks for U consecutive rows of its
@@ -170,10 +170,15 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
     const gptr<const int2> gi = as_global(A.gi);
     const gptr<const T2> gf = as_global(static_cast<const T2*>(A.gf));
     const gptr<const Coef<T>> coef = as_global(static_cast<const Coef<T>*>(A.coef));
-    const size_t boff = (size_t)d * A.half + (size_t)as_global(A.bun_base)[B] + lane;
+    const size_t boff = (size_t)d * A.half + (size_t)as_global(A.bun_base)[B] + (size_t)lane * P;
     const gptr<const T> xin = as_global(static_cast<const T*>(A.prev) + boff);
     const gptr<T> xout = as_global_w(static_cast<T*>(A.next) + boff);
-    const size_t SP = (size_t)P * kWave;       // elements per step of a bundle
+    const size_t SP = (size_t)P * kWave;       // elements per step of a bundle ([lane][p])
+    // a lane's P values of one step are contiguous: with P == PM (a power of
+    // two) they move as one vector load or store
+    constexpr bool kVecOk = PM >= 2 && (PM & (PM - 1)) == 0;
+    const bool vec = kVecOk && P == PM;
+    using V = T __attribute__((ext_vector_type(PM)));
 
     int pol[NS];
     bool val[NS];
@@ -212,6 +217,19 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
         return d == 0 ? s0 + tt : s0 + nk - 1 - tt;
     };
     auto srow = [&](int t) -> gptr<const T> { return xin + (size_t)(t < L ? t : L - 1) * SP; };
+    // the stored values of one step into the polar slots
+    auto load_row = [&](gptr<const T> r, T (&x)[NS]) {
+        if (vec) {
+            const V v = __builtin_nontemporal_load((gptr<const V>)r);
+#pragma unroll
+            for (int i = 0; i < NL; ++i) x[i] = v[i];
+#pragma unroll
+            for (int i = 0; i < NU; ++i) x[NL + i] = v[PM - 1 - i];
+        } else {
+#pragma unroll
+            for (int q = 0; q < NS; ++q) x[q] = val[q] ? ldg_stream(r + pol[q]) : (T)0;
+        }
+    };
 
     // of each segment record the sweep needs the cell index and the length only
     const gptr<const int> gcell = (gptr<const int>)gi;
@@ -228,9 +246,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
         c0[u] = ld2(coef + ((size_t)cell0 * G + g));
         cell1[u] = gcell[2 * (size_t)j1];
         len1[u] = glen[2 * (size_t)j1];
-        const gptr<const T> r = srow(u);
-#pragma unroll
-        for (int q = 0; q < NS; ++q) x0[u][q] = val[q] ? ldg_stream(r + pol[q] * kWave) : (T)0;
+        load_row(srow(u), x0[u]);
     }
     for (int t0 = 0; t0 < L; t0 += U) {
         Coef<T> c1[U];
@@ -240,9 +256,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             c1[u] = ld2(coef + ((size_t)cell1[u] * G + g));
-            const gptr<const T> r = srow(t0 + U + u);
-#pragma unroll
-            for (int q = 0; q < NS; ++q) x1[u][q] = val[q] ? ldg_stream(r + pol[q] * kWave) : (T)0;
+            load_row(srow(t0 + U + u), x1[u]);
             const int j2 = seg(t0 + 2 * U + u);
             cell2[u] = gcell[2 * (size_t)j2];
             len2[u] = glen[2 * (size_t)j2];
@@ -261,14 +275,29 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
             for (int i = 0; i < NU; ++i)
                 if (val[NL + i]) at[NL + i] = sym ? at[i] : attenuate(ktl * isz[NL + i]);
             const gptr<T> o = xout + (size_t)t * SP;
+            T ob[NS];
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
+                ob[q] = (T)0;
                 if (!val[q]) continue;
                 const T S = c0[u].a + b * x0[u][q];                   // Q / kappa_t
                 const T Io = at[q].E * I[q] + at[q].D * S;            // eq. (12)
-                const T Ib = at[q].al * I[q] + at[q].be * Io;         // segment average
-                if (live) stg_stream(o + pol[q] * kWave, Ib);
+                ob[q] = at[q].al * I[q] + at[q].be * Io;              // segment average
                 I[q] = live ? Io : I[q];
+            }
+            if (live) {
+                if (vec) {
+                    V v;
+#pragma unroll
+                    for (int i = 0; i < NL; ++i) v[i] = ob[i];
+#pragma unroll
+                    for (int i = 0; i < NU; ++i) v[PM - 1 - i] = ob[NL + i];
+                    __builtin_nontemporal_store(v, (gptr<V>)o);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < NS; ++q)
+                        if (val[q]) stg_stream(o + pol[q], ob[q]);
+                }
             }
         }
 #pragma unroll
