@@ -42,7 +42,7 @@ struct Batch {
     std::vector<PolarClass> cls;
     int* d_counters = nullptr;          // [8 * classes] counters of the sweep queues
     unsigned long long* d_gmax = nullptr;   // per-group source maxima of every problem
-    int64_t n_gmax = 0, max_blocks = 0, coef_blocks = 0, bnd_lanes = 0;
+    int64_t n_gmax = 0, max_blocks = 0, coef_blocks = 0, bnd_blocks = 0;
     int max_G = 1;
     std::vector<GraphEntry> graphs;
     hipStream_t capture = nullptr;
@@ -106,7 +106,7 @@ lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
                                           static_cast<char*>(b->d_mom_args) + parity * b->n * mb,
                                           b->cls[c].d_mom_items, b->cls[c].n_mom_items, st);
             if (rc == LC_OK) rc = ev_end(b, 2, st);
-            if (rc == LC_OK && b->bnd_lanes > 0) rc = launch_boundary_batch(b->d_bnd_args, b->n, b->bnd_lanes, st);
+            if (rc == LC_OK && b->bnd_blocks > 0) rc = launch_boundary_batch(b->d_bnd_args, b->n, b->bnd_blocks, st);
         }
     }
     return rc;
@@ -150,20 +150,20 @@ lc_status build_moment_args(Batch* b, double c) {
     const size_t mb = mom_args_bytes(), bb = bnd_args_bytes();
     b->h_mom.assign(2 * b->n * mb, 0);
     std::vector<char> hb(b->n * bb);
-    int64_t lane_off = 0;
+    int64_t blk_off = 0;
     for (int q = 0; q < b->n; ++q) {
         const lc_problem_t& P = b->probs[q];
         Plan* pl = b->plans[q];
         for (int parity = 0; parity < 2; ++parity) {
             const void* st = parity ? P.state_a : P.state_b;      // the state the step writes
             std::vector<char> tmp(bb);
-            make_moment_args(pl, st, P.I_exit, P.I_in, c, P.E, P.F, P.f, P.bnd, lane_off,
+            make_moment_args(pl, st, P.I_exit, P.I_in, c, P.E, P.F, P.f, P.bnd, blk_off,
                              b->h_mom.data() + (parity * b->n + q) * mb, tmp.data());
             if (parity == 0) std::memcpy(hb.data() + q * bb, tmp.data(), bb);
         }
-        if (P.bnd) lane_off += (int64_t)pl->rays->nb * pl->G;
+        if (P.bnd) blk_off += ((int64_t)pl->rays->nb * pl->G + kBlock - 1) / kBlock;
     }
-    b->bnd_lanes = lane_off;
+    b->bnd_blocks = blk_off;
     if (!b->d_mom_args) {
         lc_status rc = upload(&b->d_mom_args, b->h_mom.data(), b->h_mom.size());
         if (rc) return rc;

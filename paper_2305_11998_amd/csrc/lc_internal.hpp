@@ -191,7 +191,7 @@ void make_coef_args(Plan* pl, double c_dt, const double* kappa, const double* pl
 lc_status launch_prologue(Plan* pl, const double* kappa, const double* planck, double c_dt,
                           const void* state_prev, void* state_new, const double* I_in, hipStream_t st);
 void make_moment_args(Plan* pl, const void* state, const double* I_exit, const double* I_in, double c,
-                      double* E, double* F, double* f, double* bnd, int64_t bnd_lane_off, void* mom_out,
+                      double* E, double* F, double* f, double* bnd, int64_t bnd_blk_off, void* mom_out,
                       void* bnd_out);
 int64_t moment_tiles(const Plan* pl);
 int moment_tile_waves(const Plan* pl);
@@ -203,7 +203,7 @@ lc_status launch_sweep_batch(int prec, int pm, int unroll, const void* args, con
                              int* counters, hipStream_t st);
 lc_status launch_moments_batch(int prec, int pm, int ent, const void* args, const int2* items, int64_t n_items,
                                hipStream_t st);
-lc_status launch_boundary_batch(const void* args, int n, int64_t lanes, hipStream_t st);
+lc_status launch_boundary_batch(const void* args, int n, int64_t blocks, hipStream_t st);
 
 // Device pointers to the values of a state buffer (after its header).
 inline const void* state_values(const Plan* pl, const void* s) {

@@ -293,12 +293,13 @@ struct BndArgs {
     const double* I_in;     // [nb][M][G]
     int nx, ny, nb, G, n_pairs, n_az, P;
     double* bnd;            // [G][nb][8]
-    int64_t lane_off;       // first flat lane of this problem in a batched launch
+    int64_t blk_off;        // first block of this problem in a batched launch
 };
 
 // Boundary factors per (face b, group g): the outgoing intensity of a
 // direction is the width-weighted mean exit intensity of the characteristics
-// leaving through b; incoming directions take I_in.
+// leaving through b; incoming directions take I_in.  One pass over the exit
+// characteristics of each (pair, traversal) accumulates every polar angle.
 __device__ __forceinline__ void boundary_lane(const BndArgs& A, int lane) {
     const int G = A.G;
     if (lane >= A.nb * G) return;
@@ -320,18 +321,27 @@ __device__ __forceinline__ void boundary_lane(const BndArgs& A, int lane) {
             const gptr<const int> bm = as_global(A.bmap + ((size_t)(b * A.n_pairs + a) * 2 + d) * 2);
             const int k0 = bm[0], k1 = bm[1];
             double wsum = 0.0;
+            double acc[kMaxPol];
+#pragma unroll
+            for (int p = 0; p < kMaxPol; ++p) acc[p] = 0.0;
             if (k0 >= 0)
-                for (int k = k0; k < k1; ++k) wsum += width[k];
-            for (int p = 0; p < P; ++p) {
+                for (int k = k0; k < k1; ++k) {
+                    const double w = width[k];
+                    wsum += w;
+                    const gptr<const double> ie = I_exit + (size_t)(2 * k + d) * P * G + g;
+#pragma unroll
+                    for (int p = 0; p < kMaxPol; ++p)
+                        if (p < P) acc[p] += w * ie[(size_t)p * G];
+                }
+#pragma unroll
+            for (int p = 0; p < kMaxPol; ++p) {
+                if (p >= P) continue;
                 const gptr<const double> dw = as_global(A.dirw + ((size_t)(a * 2 + d) * P + p) * kDirW);
                 const double om = dw[0];
                 const double odn = dw[7] * nxv + dw[8] * nyv;
                 double I;
                 if (k0 >= 0) {
-                    double acc = 0.0;
-                    for (int k = k0; k < k1; ++k)
-                        acc += width[k] * I_exit[((size_t)(2 * k + d) * P + p) * G + g];
-                    I = acc / wsum;
+                    I = acc[p] / wsum;
                     Pp += om * I;
                     Jp += om * odn * I;
                     wo += om;
@@ -365,15 +375,16 @@ __global__ __launch_bounds__(kBlock) void k_boundary(BndArgs A) {
     boundary_lane(A, blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-__global__ __launch_bounds__(kBlock) void k_boundary_batch(const BndArgs* __restrict__ P, int n, int64_t lanes) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= lanes) return;
+// Batched form: each problem owns a contiguous range of blocks (blk_off), so
+// a block finds its problem with a block-uniform search.
+__global__ __launch_bounds__(kBlock) void k_boundary_batch(const BndArgs* __restrict__ P, int n) {
+    const int64_t blk = blockIdx.x;
     int lo = 0, hi = n;
     while (hi - lo > 1) {
         const int mid = (lo + hi) >> 1;
-        if (P[mid].lane_off <= i) lo = mid; else hi = mid;
+        if (P[mid].blk_off <= blk) lo = mid; else hi = mid;
     }
-    boundary_lane(P[lo], (int)(i - P[lo].lane_off));
+    boundary_lane(P[lo], (int)((blk - P[lo].blk_off) * kBlock + threadIdx.x));
 }
 
 template <typename T, int P>
@@ -519,7 +530,7 @@ size_t bnd_args_bytes() { return sizeof(BndArgs); }
 // Host copies of the moment and boundary records of one problem of a batch;
 // the moments read `state`.
 void make_moment_args(Plan* pl, const void* state, const double* I_exit, const double* I_in, double c,
-                      double* E, double* F, double* f, double* bnd, int64_t bnd_lane_off, void* mom_out,
+                      double* E, double* F, double* f, double* bnd, int64_t bnd_blk_off, void* mom_out,
                       void* bnd_out) {
     Rays* r = pl->rays;
     const bool f32 = pl->prec == LC_F32;
@@ -559,7 +570,7 @@ void make_moment_args(Plan* pl, const void* state, const double* I_exit, const d
     B.n_az = r->n_az;
     B.P = r->n_pol;
     B.bnd = bnd;
-    B.lane_off = bnd_lane_off;
+    B.blk_off = bnd_blk_off;
     std::memcpy(bnd_out, &B, sizeof(B));
 }
 
@@ -587,9 +598,9 @@ lc_status launch_moments_batch(int prec, int pm, int ent, const void* args, cons
     return LC_ERR_UNSUPPORTED;
 }
 
-lc_status launch_boundary_batch(const void* args, int n, int64_t lanes, hipStream_t st) {
-    hipLaunchKernelGGL(k_boundary_batch, dim3((unsigned)((lanes + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
-                       static_cast<const BndArgs*>(args), n, lanes);
+lc_status launch_boundary_batch(const void* args, int n, int64_t blocks, hipStream_t st) {
+    hipLaunchKernelGGL(k_boundary_batch, dim3((unsigned)blocks), dim3(kBlock), 0, st,
+                       static_cast<const BndArgs*>(args), n);
     LC_HIP(hipGetLastError());
     return LC_OK;
 }
