@@ -150,7 +150,11 @@ lc_status lc_rays_export(lc_rays_t rays, int32_t* ray_off, int32_t* seg_off,
  * per-group power-of-two scale of the stored intensities.  prec LC_F64 sweeps
  * and stores in float64; LC_F32 sweeps and stores in float32 with
  * compensated float32 moment sums and float64 division and boundary factors.
- * The plan keeps a reference to `rays`, which must outlive it.
+ * The plan keeps a reference to `rays`, which must outlive it.  Errors:
+ * LC_ERR_ARG for G outside 1..4096 or an unknown precision; LC_ERR_UNSUPPORTED
+ * when the state would hold 2^32 or more lane records (a lane record is the
+ * n_pol values of one (segment, traversal, group)), the limit of the moment
+ * gather's 32-bit offsets; LC_ERR_ALLOC; LC_ERR_HIP.
  */
 lc_status lc_plan_create(lc_rays_t rays, int32_t G, int32_t prec, lc_plan_t* out);
 lc_status lc_plan_free(lc_plan_t plan);

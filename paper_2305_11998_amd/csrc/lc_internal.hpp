@@ -126,7 +126,7 @@ struct Plan {
     int* d_bun_off = nullptr;
     int* d_bun_len = nullptr;
     int64_t* d_bun_base = nullptr;
-    long long* d_ent_off = nullptr;   // [n_seg][4] state offsets of each C(i, m) entry
+    unsigned* d_ent_off = nullptr;    // [n_seg][4] state lane records (P values each) of each C(i, m) entry
     int tile_w = 1, tile_h = 1;       // cell tile of the moments kernel
     int64_t sweep_blocks = 0;         // blocks of one sweep launch
     std::vector<GraphEntry> graphs;   // captured lc_step sequences

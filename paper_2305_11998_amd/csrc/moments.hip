@@ -15,7 +15,7 @@ namespace {
 
 struct MomArgs {
     const int* csr_off;       // [cells * n_pairs + 1] cell-major lists C(i, m)
-    const long long* ent_off; // [n_seg][4] state offsets of each entry: d0 first/second bundle, d1 first/second
+    const unsigned* ent_off;  // [n_seg][4] lane records of each entry: d0 first/second bundle, d1 first/second
     const void* csr_w;        // area weights A / sum A, double or float
     const double* dirw;       // [n_pairs][2][P][kDirW]
     const void* state;        // values
@@ -48,10 +48,6 @@ template <> struct Acc<float> {
 };
 
 constexpr int kMomWaves = 4;   // wavefronts per block of the moment kernels
-// the first state offset of an entry carries the lane of the ray's group 0 in
-// its top bits (state offsets stay far below 2^56)
-constexpr int kLaneShift = 56;
-constexpr long long kOffMask = (1LL << kLaneShift) - 1;
 constexpr int kXcdRun = 64;    // consecutive blocks per XCD in the batched moment launch
 constexpr int kTileWaves = kMomWaves * kXcdRun;   // wavefronts of a tile at most: one XCD run
 
@@ -63,28 +59,29 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t hw, int64_t n) {
     return x * q + (x < r ? x : r) + i;
 }
 
-// State offsets and area weight of one C(i, m) entry as seen by lane g.
-// A slot past the end of its list reads entry 0 (which always exists) and
-// gets weight 0, so every load is unconditional and stays inside the arrays.
+// Lane records of one C(i, m) entry as seen by lane g.  A lane record is the
+// P values of one lane at one step, so element offset = record * P; bundle
+// bases and step rows hold whole multiples of 64 records, so the lane of the
+// ray's group 0 is the first record mod 64.  A slot past the end of its list
+// reads entry 0 (which always exists) and gets weight 0, so every load is
+// unconditional and stays inside the arrays.
 template <typename T> struct Slot {
-    size_t o0, o1;   // offsets of this lane's value in the two traversals
+    unsigned r0, r1;   // this lane's record in the two traversals
     T w;
 };
 
 template <typename T>
-__device__ __forceinline__ Slot<T> load_slot(gptr<const long long> eo, gptr<const T> cw, int e, bool ok, int g,
-                                             int P) {
+__device__ __forceinline__ Slot<T> load_slot(gptr<const unsigned> eo, gptr<const T> cw, int e, bool ok, int g) {
     Slot<T> s;
     const int ee = ok ? e : 0;
     const T w = cw[ee];
-    const long long q0 = eo[(size_t)ee * 4 + 0], r1 = eo[(size_t)ee * 4 + 1];
-    const long long r2 = eo[(size_t)ee * 4 + 2], r3 = eo[(size_t)ee * 4 + 3];
-    const long long r0 = q0 & kOffMask;
-    const int lane0 = (int)(q0 >> kLaneShift);      // lane of the ray's group 0
+    using U4 = unsigned __attribute__((ext_vector_type(4)));
+    const U4 q = *(gptr<const U4>)(eo + (size_t)ee * 4);
+    const int lane0 = (int)(q.x & (kWave - 1));     // lane of the ray's group 0
     const bool first = g < kWave - lane0;
     s.w = ok ? w : (T)0;
-    s.o0 = (size_t)(first ? r0 : r1) + (size_t)g * P;
-    s.o1 = (size_t)(first ? r2 : r3) + (size_t)g * P;
+    s.r0 = (first ? q.x : q.y) + (unsigned)g;
+    s.r1 = (first ? q.z : q.w) + (unsigned)g;
     return s;
 }
 
@@ -134,7 +131,7 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
     const int np = A.n_pairs;
     const gptr<const T> st = as_global(static_cast<const T*>(A.state));
     const gptr<const T> cw = as_global(static_cast<const T*>(A.csr_w));
-    const gptr<const long long> eo = as_global(A.ent_off);
+    const gptr<const unsigned> eo = as_global(A.ent_off);
     const gptr<const int> co = as_global(A.csr_off + (size_t)cell * np);
     Acc<T> acc[7];
     // list bounds: pair a is [b0, b1), pair a+1 is [b1, b2)
@@ -142,18 +139,18 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
     int b2 = co[min(2, np)];
     Slot<T> cur[K];
 #pragma unroll
-    for (int u = 0; u < K; ++u) cur[u] = load_slot(eo, cw, b0 + u, b0 + u < b1, g, P);
+    for (int u = 0; u < K; ++u) cur[u] = load_slot(eo, cw, b0 + u, b0 + u < b1, g);
     for (int a = 0; a < np; ++a) {
         T x[K][2][PM];
 #pragma unroll
         for (int u = 0; u < K; ++u) {
-            load_entry<T, PM>(st, cur[u].o0, P, x[u][0]);
-            load_entry<T, PM>(st, cur[u].o1, P, x[u][1]);
+            load_entry<T, PM>(st, (size_t)cur[u].r0 * P, P, x[u][0]);
+            load_entry<T, PM>(st, (size_t)cur[u].r1 * P, P, x[u][1]);
         }
         const bool more = a + 1 < np;
         Slot<T> nxt[K];
 #pragma unroll
-        for (int u = 0; u < K; ++u) nxt[u] = load_slot(eo, cw, b1 + u, more && b1 + u < b2, g, P);
+        for (int u = 0; u < K; ++u) nxt[u] = load_slot(eo, cw, b1 + u, more && b1 + u < b2, g);
         const int b3 = co[min(a + 3, np)];
         T Iim[2][PM];
 #pragma unroll
@@ -167,10 +164,10 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
 #pragma unroll
                 for (int p = 0; p < PM; ++p) Iim[d][p] += cur[u].w * x[u][d][p];
         for (int e = b0 + K; e < b1; ++e) {
-            const Slot<T> t = load_slot(eo, cw, e, true, g, P);
+            const Slot<T> t = load_slot(eo, cw, e, true, g);
             T y[2][PM];
-            load_entry<T, PM>(st, t.o0, P, y[0]);
-            load_entry<T, PM>(st, t.o1, P, y[1]);
+            load_entry<T, PM>(st, (size_t)t.r0 * P, P, y[0]);
+            load_entry<T, PM>(st, (size_t)t.r1 * P, P, y[1]);
 #pragma unroll
             for (int d = 0; d < 2; ++d)
 #pragma unroll
@@ -260,7 +257,7 @@ __global__ __launch_bounds__(kMomWaves * kWave) void k_cell_moments_batch(const 
 __global__ void k_entry_offsets(const int* __restrict__ csr_off, const int* __restrict__ csr_ray,
                                 const int2* __restrict__ csr_t, const int* __restrict__ ray_off,
                                 const int* __restrict__ bun_off, const int64_t* __restrict__ bun_base,
-                                int64_t n_keys, int n_pairs, int G, int P, int64_t half, long long* out) {
+                                int64_t n_keys, int n_pairs, int G, int P, int64_t half, unsigned* out) {
     const int64_t key = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (key >= n_keys) return;
     const int a = (int)(key % n_pairs);
@@ -270,14 +267,16 @@ __global__ void k_entry_offsets(const int* __restrict__ csr_off, const int* __re
         const int f0 = (k - ray_off[a]) * G;
         const int B0 = bun_off[a] + f0 / kWave;
         const int lane0 = f0 & (kWave - 1);
-        const int64_t step = (int64_t)P * kWave;
-        long long* o = out + (size_t)e * 4;
-        o[0] = (bun_base[B0] + t.x * step + (int64_t)lane0 * P) | ((long long)lane0 << kLaneShift);
-        o[2] = half + bun_base[B0] + t.y * step + (int64_t)lane0 * P;
+        // lane records: bases and halves are whole multiples of 64 * P elements
+        const int64_t b0 = bun_base[B0] / P, hr = half / P;
+        unsigned* o = out + (size_t)e * 4;
+        o[0] = (unsigned)(b0 + (int64_t)t.x * kWave + lane0);
+        o[2] = (unsigned)(hr + b0 + (int64_t)t.y * kWave + lane0);
         if (lane0 + G > kWave) {
             const int split = kWave - lane0;
-            o[1] = bun_base[B0 + 1] + t.x * step - (int64_t)split * P;
-            o[3] = half + bun_base[B0 + 1] + t.y * step - (int64_t)split * P;
+            const int64_t b1 = bun_base[B0 + 1] / P;
+            o[1] = (unsigned)(b1 + (int64_t)t.x * kWave - split);
+            o[3] = (unsigned)(hr + b1 + (int64_t)t.y * kWave - split);
         } else {
             o[1] = o[0];
             o[3] = o[2];
@@ -422,10 +421,11 @@ lc_status launch_cell_moments_p(int P, int ent, const MomArgs& A, hipStream_t st
 
 lc_status plan_init_moments(Plan* pl) {
     Rays* r = pl->rays;
-    LC_CHECK(2 * pl->half_elems < (1LL << kLaneShift), LC_ERR_UNSUPPORTED, "state too large for the moment offsets");
+    LC_CHECK(2 * pl->half_elems / r->n_pol < (1LL << 32), LC_ERR_UNSUPPORTED,
+             "state too large for the 32-bit moment gather offsets (2^32 lane records)");
     const int64_t n_keys = (int64_t)r->cells * r->n_pairs;
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&pl->d_ent_off),
-                             std::max<size_t>((size_t)r->n_seg, 1) * 4 * sizeof(long long));
+                             std::max<size_t>((size_t)r->n_seg, 1) * 4 * sizeof(unsigned));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         set_error("hipMalloc of the moment offsets failed: %s", hipGetErrorString(e));
