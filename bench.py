@@ -94,7 +94,7 @@ def run_batched_f32(probs, steps, warmup):
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     # timed: `steps` steps replayed from the captured graph (the production
-    # path: polar groups on their own streams); captured once, untimed
+    # path); captured once, untimed
     bs.step(steps)
     torch.cuda.synchronize()
     e0.record()

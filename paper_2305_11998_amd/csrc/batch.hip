@@ -5,8 +5,7 @@
 // wavefront) items; the coefficient prologue and the boundary factors are one
 // launch over all problems.  Items are ordered by problem cost, largest
 // first, so the small problems fill the tail.  The step sequence is captured
-// in a HIP graph per step count and replayed; in the graph each group runs on
-// its own stream, so one group's kernels fill the other's tail.
+// in a HIP graph per step count and replayed.
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -48,11 +47,6 @@ struct Batch {
     int max_G = 1;
     std::vector<GraphEntry> graphs;
     hipStream_t capture = nullptr;
-    // graph mode runs the polar groups concurrently: one side stream per
-    // group (sweep, then moments) and one for the boundary factors
-    std::vector<hipStream_t> side;
-    hipEvent_t e_pro = nullptr, e_bnd = nullptr;
-    std::vector<hipEvent_t> e_sweep, e_mom;
     bool profile = false;               // eager steps with events around each phase
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];   // prologue, sweep, moments
 };
@@ -88,48 +82,10 @@ lc_status ev_end(Batch* b, int k, hipStream_t st) {
     return LC_OK;
 }
 
-// One step with the polar groups on their own streams (fork after the
-// prologue, join before the next step).  Used for graph capture; the kernels
-// and their per-problem order are those of enqueue_steps, so the results are
-// identical.
-lc_status enqueue_step_concurrent(Batch* b, int t, hipStream_t st) {
-    const size_t sb = sweep_args_bytes(), mb = mom_args_bytes();
-    const int parity = t & 1;
-    const size_t nc = b->cls.size();
-    lc_status rc = launch_zero_counters(b->d_counters, 8 * (int)nc, st);
-    if (rc == LC_OK)
-        rc = launch_prologue_batch(b->prec, b->d_coef_args, b->n, b->max_blocks, b->coef_blocks, b->max_G,
-                                   b->d_gmax, b->n_gmax, t, st);
-    if (rc) return rc;
-    LC_HIP(hipEventRecord(b->e_pro, st));
-    for (size_t c = 0; c < nc; ++c) {
-        hipStream_t sc = b->side[c];
-        LC_HIP(hipStreamWaitEvent(sc, b->e_pro, 0));
-        rc = launch_sweep_batch(b->prec, b->cls[c].pm, b->cls[c].unroll,
-                                static_cast<char*>(b->d_sweep_args) + parity * b->n * sb, b->cls[c].d_sweep_items,
-                                b->cls[c].d_sweep_qb, b->d_counters + 8 * c, sc);
-        if (rc) return rc;
-        LC_HIP(hipEventRecord(b->e_sweep[c], sc));
-        rc = launch_moments_batch(b->prec, b->cls[c].pm, b->cls[c].ent,
-                                  static_cast<char*>(b->d_mom_args) + parity * b->n * mb, b->cls[c].d_mom_items,
-                                  b->cls[c].n_mom_items, sc);
-        if (rc) return rc;
-        LC_HIP(hipEventRecord(b->e_mom[c], sc));
-    }
-    hipStream_t sbnd = b->side[nc];
-    for (size_t c = 0; c < nc; ++c) LC_HIP(hipStreamWaitEvent(sbnd, b->e_sweep[c], 0));
-    if (b->bnd_blocks > 0) {
-        rc = launch_boundary_batch(b->d_bnd_args, b->n, b->bnd_blocks, sbnd);
-        if (rc) return rc;
-    }
-    LC_HIP(hipEventRecord(b->e_bnd, sbnd));
-    for (size_t c = 0; c < nc; ++c) LC_HIP(hipStreamWaitEvent(st, b->e_mom[c], 0));
-    LC_HIP(hipStreamWaitEvent(st, b->e_bnd, 0));
-    return LC_OK;
-}
-
 // Enqueue n_steps time steps of every problem on st, one phase after the
-// other (with the phase timers when profiling).
+// other (with the phase timers when profiling).  Running the polar groups
+// on streams of their own was measured slower: their kernels contend for the
+// same caches and bandwidth rather than filling each other's tails.
 lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
     const size_t sb = sweep_args_bytes(), mb = mom_args_bytes();
     lc_status rc = LC_OK;
@@ -171,14 +127,6 @@ void free_batch(Batch* b) {
     for (auto& g : b->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (b->capture) (void)hipStreamDestroy(b->capture);
-    for (hipStream_t x : b->side)
-        if (x) (void)hipStreamDestroy(x);
-    for (hipEvent_t x : b->e_sweep)
-        if (x) (void)hipEventDestroy(x);
-    for (hipEvent_t x : b->e_mom)
-        if (x) (void)hipEventDestroy(x);
-    if (b->e_pro) (void)hipEventDestroy(b->e_pro);
-    if (b->e_bnd) (void)hipEventDestroy(b->e_bnd);
     for (void* p : {b->d_sweep_args, b->d_coef_args, b->d_mom_args, b->d_bnd_args,
                     static_cast<void*>(b->d_counters), static_cast<void*>(b->d_gmax)})
         if (p) (void)hipFree(p);
@@ -370,17 +318,6 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
     if (rc == LC_OK) rc = build_moment_args(b, 1.0);
     if (rc == LC_OK) {
         hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
-        const size_t nc = b->cls.size();
-        b->side.assign(nc + 1, nullptr);
-        b->e_sweep.assign(nc, nullptr);
-        b->e_mom.assign(nc, nullptr);
-        for (size_t c = 0; c <= nc && e == hipSuccess; ++c) e = hipStreamCreateWithFlags(&b->side[c], hipStreamNonBlocking);
-        for (size_t c = 0; c < nc && e == hipSuccess; ++c) {
-            e = hipEventCreateWithFlags(&b->e_sweep[c], hipEventDisableTiming);
-            if (e == hipSuccess) e = hipEventCreateWithFlags(&b->e_mom[c], hipEventDisableTiming);
-        }
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->e_pro, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->e_bnd, hipEventDisableTiming);
         if (e != hipSuccess) {
             set_error("hipStreamCreate failed: %s", hipGetErrorString(e));
             rc = LC_ERR_HIP;
@@ -413,8 +350,7 @@ lc_status lc_batch_step(lc_batch_t batch, int32_t n_steps, double c, void* strea
         if (g.key.size() == 1 && g.key[0] == (uintptr_t)n_steps) exec = g.exec;
     if (!exec) {
         LC_HIP(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-        lc_status rc = LC_OK;
-        for (int t = 0; t < n_steps && rc == LC_OK; ++t) rc = enqueue_step_concurrent(b, t, b->capture);
+        lc_status rc = enqueue_steps(b, n_steps, b->capture);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(b->capture, &graph);
         if (rc != LC_OK) {

@@ -115,10 +115,9 @@ def test_full_batched_workload_sampled(lcmod):
 
 
 def test_batch_graph_replays_equal_eager_phases(lcmod):
-    """The captured graph runs the polar groups on their own streams; the
-    profiled eager path runs the phases one after the other.  Every replay of
-    the graph, with eager work (state resets) between replays, gives the
-    eager result bit for bit."""
+    """Every replay of the captured step graph, with eager work (state
+    resets) between replays, gives the result of the eager, profiled path
+    bit for bit."""
     import torch
     lc, driver = lcmod
     probs = _mixed_problems(steps=1)
