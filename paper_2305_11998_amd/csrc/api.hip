@@ -54,6 +54,7 @@ void free_plan(Plan* pl) {
     if (pl->d_bun_len) (void)hipFree(pl->d_bun_len);
     if (pl->d_bun_base) (void)hipFree(pl->d_bun_base);
     if (pl->d_ent_off) (void)hipFree(pl->d_ent_off);
+    if (pl->d_bun_rec) (void)hipFree(pl->d_bun_rec);
     pl->magic = 0;
     delete pl;
 }

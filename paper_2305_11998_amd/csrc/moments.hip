@@ -15,7 +15,11 @@ namespace {
 
 struct MomArgs {
     const int* csr_off;       // [cells * n_pairs + 1] cell-major lists C(i, m)
-    const unsigned* ent_off;  // [n_seg][4] lane records of each entry: d0 first/second bundle, d1 first/second
+    const unsigned* ent_off;  // [n_seg][4] per entry: lane records {d0 first/second bundle, d1 first/second};
+                              // with multi: {first bundle, step d0, step d1, lane of group 0}
+    const unsigned* bun_rec;  // [n_bun] first lane record of each bundle (multi only)
+    unsigned half_rec;        // lane records of one traversal half
+    int multi;                // G > 64: a characteristic's groups may span three or more bundles
     const void* csr_w;        // area weights A / sum A, double or float
     const double* dirw;       // [n_pairs][2][P][kDirW]
     const void* state;        // values
@@ -70,18 +74,28 @@ template <typename T> struct Slot {
     T w;
 };
 
+// With G > 64 (`multi`) an entry holds its first bundle and steps instead,
+// and each lane reads the first record of its own bundle from bun_rec.
 template <typename T>
-__device__ __forceinline__ Slot<T> load_slot(gptr<const unsigned> eo, gptr<const T> cw, int e, bool ok, int g) {
+__device__ __forceinline__ Slot<T> load_slot(gptr<const unsigned> eo, gptr<const T> cw, int e, bool ok, int g,
+                                             const MomArgs& A) {
     Slot<T> s;
     const int ee = ok ? e : 0;
     const T w = cw[ee];
     using U4 = unsigned __attribute__((ext_vector_type(4)));
     const U4 q = *(gptr<const U4>)(eo + (size_t)ee * 4);
-    const int lane0 = (int)(q.x & (kWave - 1));     // lane of the ray's group 0
-    const bool first = g < kWave - lane0;
     s.w = ok ? w : (T)0;
-    s.r0 = (first ? q.x : q.y) + (unsigned)g;
-    s.r1 = (first ? q.z : q.w) + (unsigned)g;
+    if (A.multi) {
+        const unsigned f = q.w + (unsigned)g;        // lane within the bundles from the first
+        const unsigned base = as_global(A.bun_rec)[q.x + (f >> 6)];
+        s.r0 = base + q.y * kWave + (f & (kWave - 1));
+        s.r1 = A.half_rec + base + q.z * kWave + (f & (kWave - 1));
+    } else {
+        const int lane0 = (int)(q.x & (kWave - 1));  // lane of the ray's group 0
+        const bool first = g < kWave - lane0;
+        s.r0 = (first ? q.x : q.y) + (unsigned)g;
+        s.r1 = (first ? q.z : q.w) + (unsigned)g;
+    }
     return s;
 }
 
@@ -139,7 +153,7 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
     int b2 = co[min(2, np)];
     Slot<T> cur[K];
 #pragma unroll
-    for (int u = 0; u < K; ++u) cur[u] = load_slot(eo, cw, b0 + u, b0 + u < b1, g);
+    for (int u = 0; u < K; ++u) cur[u] = load_slot(eo, cw, b0 + u, b0 + u < b1, g, A);
     for (int a = 0; a < np; ++a) {
         T x[K][2][PM];
 #pragma unroll
@@ -150,7 +164,7 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
         const bool more = a + 1 < np;
         Slot<T> nxt[K];
 #pragma unroll
-        for (int u = 0; u < K; ++u) nxt[u] = load_slot(eo, cw, b1 + u, more && b1 + u < b2, g);
+        for (int u = 0; u < K; ++u) nxt[u] = load_slot(eo, cw, b1 + u, more && b1 + u < b2, g, A);
         const int b3 = co[min(a + 3, np)];
         T Iim[2][PM];
 #pragma unroll
@@ -164,7 +178,7 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
 #pragma unroll
                 for (int p = 0; p < PM; ++p) Iim[d][p] += cur[u].w * x[u][d][p];
         for (int e = b0 + K; e < b1; ++e) {
-            const Slot<T> t = load_slot(eo, cw, e, true, g);
+            const Slot<T> t = load_slot(eo, cw, e, true, g, A);
             T y[2][PM];
             load_entry<T, PM>(st, (size_t)t.r0 * P, P, y[0]);
             load_entry<T, PM>(st, (size_t)t.r1 * P, P, y[1]);
@@ -267,9 +281,16 @@ __global__ void k_entry_offsets(const int* __restrict__ csr_off, const int* __re
         const int f0 = (k - ray_off[a]) * G;
         const int B0 = bun_off[a] + f0 / kWave;
         const int lane0 = f0 & (kWave - 1);
+        unsigned* o = out + (size_t)e * 4;
+        if (G > kWave) {                            // groups may span three or more bundles
+            o[0] = (unsigned)B0;
+            o[1] = (unsigned)t.x;
+            o[2] = (unsigned)t.y;
+            o[3] = (unsigned)lane0;
+            continue;
+        }
         // lane records: bases and halves are whole multiples of 64 * P elements
         const int64_t b0 = bun_base[B0] / P, hr = half / P;
-        unsigned* o = out + (size_t)e * 4;
         o[0] = (unsigned)(b0 + (int64_t)t.x * kWave + lane0);
         o[2] = (unsigned)(hr + b0 + (int64_t)t.y * kWave + lane0);
         if (lane0 + G > kWave) {
@@ -424,6 +445,17 @@ lc_status plan_init_moments(Plan* pl) {
     LC_CHECK(2 * pl->half_elems / r->n_pol < (1LL << 32), LC_ERR_UNSUPPORTED,
              "state too large for the 32-bit moment gather offsets (2^32 lane records)");
     const int64_t n_keys = (int64_t)r->cells * r->n_pairs;
+    {
+        std::vector<unsigned> rec(std::max<size_t>((size_t)pl->n_bun, 1), 0u);
+        for (int64_t B = 0; B < pl->n_bun; ++B) rec[B] = (unsigned)(pl->bun_base_h[B] / r->n_pol);
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_rec), rec.size() * sizeof(unsigned));
+        if (e == hipSuccess) e = hipMemcpy(pl->d_bun_rec, rec.data(), rec.size() * sizeof(unsigned), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("allocation of the bundle record table failed: %s", hipGetErrorString(e));
+            return LC_ERR_ALLOC;
+        }
+    }
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&pl->d_ent_off),
                              std::max<size_t>((size_t)r->n_seg, 1) * 4 * sizeof(unsigned));
     if (e != hipSuccess) {
@@ -452,6 +484,9 @@ lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, cons
         MomArgs A{};
         A.csr_off = r->d_csr_off;
         A.ent_off = pl->d_ent_off;
+        A.bun_rec = pl->d_bun_rec;
+        A.half_rec = (unsigned)(pl->half_elems / r->n_pol);
+        A.multi = pl->G > kWave ? 1 : 0;
         A.csr_w = f32 ? static_cast<const void*>(r->d_csr_w32) : static_cast<const void*>(r->d_csr_w);
         A.dirw = r->d_dirw;
         A.state = state_values(pl, state);
@@ -537,6 +572,9 @@ void make_moment_args(Plan* pl, const void* state, const double* I_exit, const d
     MomArgs A{};
     A.csr_off = r->d_csr_off;
     A.ent_off = pl->d_ent_off;
+    A.bun_rec = pl->d_bun_rec;
+    A.half_rec = (unsigned)(pl->half_elems / r->n_pol);
+    A.multi = pl->G > kWave ? 1 : 0;
     A.csr_w = f32 ? static_cast<const void*>(r->d_csr_w32) : static_cast<const void*>(r->d_csr_w);
     A.dirw = r->d_dirw;
     A.state = state_values(pl, state);

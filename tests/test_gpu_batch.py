@@ -139,3 +139,27 @@ def test_batch_graph_replays_equal_eager_phases(lcmod):
             for k in ("E", "F", "f", "bnd"):
                 assert np.array_equal(m[k], m0[k])
             assert np.array_equal(s.state_canonical(), st0)
+
+
+def test_batch_with_more_than_64_groups(lcmod):
+    """A member with G > 64 beside small-G members: batch equals the
+    single-problem runs bit for bit."""
+    lc, driver = lcmod
+    specs = [(9, 7, 8, 2, 70), (12, 10, 8, 2, 5)]
+    probs = []
+    for j, (nx, ny, n_az, n_pol, G) in enumerate(specs):
+        rng = np.random.default_rng(300 + j)
+        Ts = [rng.uniform(0.01, 1.0, nx * ny) for _ in range(2)]
+        probs.append(W.make_problem(nx, ny, nx * 0.1, ny * 0.1, n_az, n_pol, G, 0.001, 20.0, 0.03, 2.0, Ts,
+                                    name=f"g{j}"))
+    for prec in (0, 1):
+        bs = driver.BatchSolver(probs, prec=prec)
+        bs.reset()
+        bs.step(2)
+        for p, sb in zip(probs, bs.solvers):
+            s = driver.Solver(p, prec=prec)
+            s.reset()
+            s.step(2)
+            mb, ms = sb.moments(), s.moments()
+            for k in ("E", "F", "f", "bnd"):
+                assert np.array_equal(mb[k], ms[k]), (p.name, k)

@@ -210,6 +210,15 @@ def test_tuning_settings_give_identical_results(lcmod, prec, mode, h_moc):
         assert np.array_equal(st, out[0][1])
 
 
+@pytest.mark.parametrize("G,prec", [(66, 0), (100, 0), (100, 1)])
+def test_many_groups_span_three_bundles(lcmod, G, prec):
+    """G > 64: a characteristic's groups can span three 64-lane bundles (the
+    moment gather then looks up each lane's bundle)."""
+    lc, driver = lcmod
+    prob = _custom_problem(nx=9, ny=7, lx=0.9, ly=0.7, n_az=8, G=G, h_moc=0.04, steps=1)
+    _compare_full(lc, driver, prob, prec, TOL64 if prec == 0 else TOL32)
+
+
 def _sampled_cells(prob, n, seed):
     rng = np.random.default_rng(seed)
     cells = list(rng.choice(prob.cells, n - 2, replace=False))
