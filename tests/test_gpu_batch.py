@@ -163,3 +163,27 @@ def test_batch_with_more_than_64_groups(lcmod):
             mb, ms = sb.moments(), s.moments()
             for k in ("E", "F", "f", "bnd"):
                 assert np.array_equal(mb[k], ms[k]), (p.name, k)
+
+
+def test_batch_polar_bound_eight(lcmod):
+    """Members with 8 and 5 polar angles share the polar-bound-8 launches;
+    batch equals the single-problem runs bit for bit."""
+    lc, driver = lcmod
+    probs = []
+    for j, (nx, ny, n_pol, G) in enumerate([(10, 8, 8, 6), (8, 9, 5, 3), (12, 6, 2, 4)]):
+        rng = np.random.default_rng(400 + j)
+        Ts = [rng.uniform(0.01, 1.0, nx * ny) for _ in range(2)]
+        probs.append(W.make_problem(nx, ny, nx * 0.1, ny * 0.1, 8, n_pol, G, 0.001, 20.0, 0.03, 2.0, Ts,
+                                    name=f"p{j}"))
+    for prec in (0, 1):
+        bs = driver.BatchSolver(probs, prec=prec)
+        bs.reset()
+        bs.step(2)
+        for p, sb in zip(probs, bs.solvers):
+            s = driver.Solver(p, prec=prec)
+            s.reset()
+            s.step(2)
+            mb, ms = sb.moments(), s.moments()
+            for k in ("E", "F", "f", "bnd"):
+                assert np.array_equal(mb[k], ms[k]), (p.name, k)
+            assert np.array_equal(sb.state_canonical(), s.state_canonical())

@@ -219,6 +219,16 @@ def test_many_groups_span_three_bundles(lcmod, G, prec):
     _compare_full(lc, driver, prob, prec, TOL64 if prec == 0 else TOL32)
 
 
+@pytest.mark.parametrize("n_pol,prec", [(8, 0), (8, 1), (5, 1)])
+def test_polar_counts_above_four(lcmod, n_pol, prec):
+    """P = 8 (whole-vector state accesses of 8 values) and P = 5 (element
+    accesses) against the oracle."""
+    lc, driver = lcmod
+    mu, w = np.polynomial.legendre.leggauss(n_pol)
+    prob = _custom_problem(nx=10, ny=8, lx=1.0, ly=0.8, n_az=8, mu=mu, w=w, G=6, h_moc=0.04, steps=2)
+    _compare_full(lc, driver, prob, prec, TOL64 if prec == 0 else TOL32)
+
+
 def _sampled_cells(prob, n, seed):
     rng = np.random.default_rng(seed)
     cells = list(rng.choice(prob.cells, n - 2, replace=False))
