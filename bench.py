@@ -57,8 +57,8 @@ SWEEP_SOURCES = ("sweep.hip", "batch.hip", "lc_internal.hpp")
 
 def recorded_traffic(tuning):
     """HBM bytes per sweep phase measured with rocprofv3 counters for this
-    workload, or None when the sweep sources or the tuning differ from those
-    the counters were taken with."""
+    workload, or None when the sweep sources or the sweep tuning differ from
+    those the counters were taken with."""
     import hashlib
     try:
         rec = dict(line.split(" ", 1) for line in open(TRAFFIC_RECORD).read().splitlines()
@@ -71,7 +71,8 @@ def recorded_traffic(tuning):
             h.update(fh.read())
     if rec.get("source_sha256", "").strip() != h.hexdigest():
         return None
-    if json.loads(rec.get("tuning", "null")) != tuning:
+    sweep_tuning = {k: v["sweep_unroll"] for k, v in tuning.items()}
+    if json.loads(rec.get("sweep_unroll", "null")) != sweep_tuning:
         return None
     return float(rec["traffic_bytes"])
 
