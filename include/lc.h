@@ -31,7 +31,8 @@
  *   stored in forward order; global segment index j runs over pairs, rays,
  *   segments.  Segment length l is the in-plane length; the path length in
  *   direction m is l / sqrt(1 - mu_p^2).
- * Groups: G >= 1; every [G][cells] array is group-major.
+ * Groups: G >= 1; every [G][cells] input array is group-major; the moment
+ *   outputs of lc_moments and lc_step are cell-major (group fastest).
  * Per-segment state (the previous step's segment-average intensities
  *   I_bar^{n-1}): an opaque caller-owned device buffer of lc_state_bytes()
  *   bytes; lc_state_export() gives it in the canonical order
@@ -197,7 +198,7 @@ lc_status lc_sweep(lc_plan_t plan, const double* kappa, const double* planck, do
  * then Phi = sum_m omega_m I_{i,m}, E = Phi/c, F = sum_m omega_m Omega_m I_{i,m},
  * f = sum_m omega_m Omega_m Omega_m I_{i,m} / Phi (f := 1/3 on the diagonal
  * where Phi = 0).  Outputs (float64, any may be NULL):
- *   E[G][cells], F[G][2][cells] (x, y), f[G][4][cells] (xx, xy, yy, zz),
+ *   E[cells][G], F[cells][2][G] (x, y), f[cells][4][G] (xx, xy, yy, zz),
  *   bnd[G][nb][8] = Phi+, J+, Phi-, J-, C = J+/Phi+, f_xx, f_xy, f_yy of the
  *   boundary face (outgoing: width-weighted mean exit intensity of the
  *   characteristics leaving through the face, or of the one leaving nearest

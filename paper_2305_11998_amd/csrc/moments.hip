@@ -210,21 +210,21 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
     double sc = 1.0;
     if (sizeof(T) == 4) sc = ldexp(1.0, as_global(A.e)[g]);
     const double Phi = acc[0].value() * sc;
-    const size_t o = (size_t)g * cells + cell;
+    const size_t o = (size_t)cell * G + g;
     if (A.E) as_global_w(A.E)[o] = Phi * A.inv_c;
     if (A.F) {
         const gptr<double> F = as_global_w(A.F);
-        F[((size_t)g * 2 + 0) * cells + cell] = acc[1].value() * sc;
-        F[((size_t)g * 2 + 1) * cells + cell] = acc[2].value() * sc;
+        F[((size_t)cell * 2 + 0) * G + g] = acc[1].value() * sc;
+        F[((size_t)cell * 2 + 1) * G + g] = acc[2].value() * sc;
     }
     if (A.f) {
         const gptr<double> f = as_global_w(A.f);
         const bool z = Phi == 0.0;
         const double inv = z ? 0.0 : 1.0 / Phi;
-        f[((size_t)g * 4 + 0) * cells + cell] = z ? 1.0 / 3 : acc[3].value() * sc * inv;
-        f[((size_t)g * 4 + 1) * cells + cell] = z ? 0.0 : acc[4].value() * sc * inv;
-        f[((size_t)g * 4 + 2) * cells + cell] = z ? 1.0 / 3 : acc[5].value() * sc * inv;
-        f[((size_t)g * 4 + 3) * cells + cell] = z ? 1.0 / 3 : acc[6].value() * sc * inv;
+        f[((size_t)cell * 4 + 0) * G + g] = z ? 1.0 / 3 : acc[3].value() * sc * inv;
+        f[((size_t)cell * 4 + 1) * G + g] = z ? 0.0 : acc[4].value() * sc * inv;
+        f[((size_t)cell * 4 + 2) * G + g] = z ? 1.0 / 3 : acc[5].value() * sc * inv;
+        f[((size_t)cell * 4 + 3) * G + g] = z ? 1.0 / 3 : acc[6].value() * sc * inv;
     }
 }
 
@@ -468,8 +468,9 @@ lc_status plan_init_moments(Plan* pl) {
                        n_keys, r->n_pairs, pl->G, r->n_pol, pl->half_elems, pl->d_ent_off);
     LC_HIP(hipGetLastError());
     LC_HIP(hipDeviceSynchronize());
-    // tile: 16 cells wide (a 128-byte line of each output row) and as tall
-    // as fits in kTileWaves wavefronts, at most 16; narrower for large G
+    // tile: up to 16 x 16 cells, as many as fit in kTileWaves wavefronts
+    // (narrower for large G); neighbouring cells are crossed by the same
+    // characteristics, so the waves of a tile read overlapping state lines
     const int cells_max = std::max(1, kTileWaves * kWave / pl->G);
     pl->tile_w = std::max(1, std::min({16, cells_max, r->nx}));
     pl->tile_h = std::max(1, std::min({16, cells_max / pl->tile_w, r->ny}));

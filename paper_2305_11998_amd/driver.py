@@ -86,10 +86,18 @@ class Solver:
     def moments(self):
         p = self.prob
         G, cells = p.G, p.cells
-        return dict(E=self.E.cpu().numpy().reshape(G, cells),
-                    F=self.F.cpu().numpy().reshape(G, 2, cells),
-                    f=self.f.cpu().numpy().reshape(G, 4, cells),
+        # The library writes cell-major arrays; hand out [G][...][cells] views.
+        return dict(E=self.E.cpu().numpy().reshape(cells, G).T,
+                    F=self.F.cpu().numpy().reshape(cells, 2, G).transpose(2, 1, 0),
+                    f=self.f.cpu().numpy().reshape(cells, 4, G).transpose(2, 1, 0),
                     bnd=self.bnd.cpu().numpy().reshape(G, self.rays.nb, 8))
+
+    def moment_views(self):
+        """Device views of E, F, f indexed [g][component][cell] (E has one
+        component); no copy."""
+        G, cells = self.prob.G, self.prob.cells
+        return {k: getattr(self, k).view(cells, n, G).permute(2, 1, 0)
+                for k, n in (("E", 1), ("F", 2), ("f", 4))}
 
     def state_canonical(self):
         out = torch.empty(self.plan.n_state, dtype=torch.float64, device="cuda")

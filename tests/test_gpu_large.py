@@ -20,10 +20,9 @@ def _say(msg):
     sys.stdout.flush()
 
 
-def _sampled(t, G, cells, idx, comps=1):
-    """Moments at sampled cells, gathered on the device."""
-    v = t.view(G, comps, cells)
-    return v[:, :, idx].cpu().numpy()
+def _sampled(solver, idx):
+    """Moments [g][component][sampled cell], gathered on the device."""
+    return {k: v[:, :, idx].cpu().numpy() for k, v in solver.moment_views().items()}
 
 
 def test_largest_problem_fp32_with_per_step_fp64_check():
@@ -49,8 +48,8 @@ def test_largest_problem_fp32_with_per_step_fp64_check():
         s32.step(1)
         s64.step(1)
         torch.cuda.synchronize()
-        a = {k: _sampled(getattr(s32, k), G, cells, idx, n) for k, n in (("E", 1), ("F", 2), ("f", 4))}
-        b = {k: _sampled(getattr(s64, k), G, cells, idx, n) for k, n in (("E", 1), ("F", 2), ("f", 4))}
+        a = _sampled(s32, idx)
+        b = _sampled(s64, idx)
         e = dict(E=err_E(a["E"][:, 0], b["E"][:, 0]), F=err_F(a["F"], b["F"], b["E"][:, 0], c),
                  f=err_f(a["f"], b["f"], b["E"][:, 0]))
         _say(f"  step {t}: f32 vs f64 on {len(idx_np)} cells: E {e['E']:.2e} F {e['F']:.2e} f {e['f']:.2e}")
@@ -59,8 +58,7 @@ def test_largest_problem_fp32_with_per_step_fp64_check():
     assert worst["E"] <= 1e-5 and worst["F"] <= 1e-5 and worst["f"] <= 1e-5, worst
     # the float64 run against the oracle on a few cells after the last step
     few = np.concatenate([rng.choice(cells, 3, replace=False), [0, cells - 1]])
-    m64 = {k: _sampled(getattr(s64, k), G, cells, torch.from_numpy(few).cuda(), n)
-           for k, n in (("E", 1), ("F", 2), ("f", 4))}
+    m64 = _sampled(s64, torch.from_numpy(few).cuda())
     del s32, s64
     torch.cuda.empty_cache()
     _say("  oracle on 5 cells, 10 steps")

@@ -61,6 +61,9 @@ def _compare_full(lc, driver, prob, prec, tol, graph=True, check_state=True, mod
     s.reset()
     s.step(prob.steps, graph=graph)
     got = s.moments()
+    v = s.moment_views()
+    assert np.array_equal(v["E"][:, 0].cpu().numpy(), got["E"])
+    assert np.array_equal(v["F"].cpu().numpy(), got["F"]) and np.array_equal(v["f"].cpu().numpy(), got["f"])
     r = ref["steps"][-1]
     c = W.C_LIGHT
     eE = err_E(got["E"], r["E"])
