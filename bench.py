@@ -260,6 +260,8 @@ def main():
     ap.add_argument("--f64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy a 4 GiB buffer three times (scales the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
@@ -270,6 +272,15 @@ def main():
     import workloads as W
 
     torch.cuda.init()
+    if args.copy_calibration:
+        n = 1 << 30                                      # 2^30 float32 = 4 GiB
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        _say(f"copied 3 x {n * 4} bytes")
+        return
     if args.workload == "single":
         main_single(args)
         return
