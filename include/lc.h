@@ -203,7 +203,9 @@ lc_status lc_sweep(lc_plan_t plan, const double* kappa, const double* planck, do
  *   boundary face (outgoing: width-weighted mean exit intensity of the
  *   characteristics leaving through the face, or of the one leaving nearest
  *   its centre if none does; incoming: I_in).  bnd needs I_exit and I_in.
- * c > 0 is the speed of light in the caller's units.
+ * c > 0 is the speed of light in the caller's units.  Errors: LC_ERR_ARG
+ * (null state, c not finite or <= 0, bnd without I_exit and I_in),
+ * LC_ERR_HIP.
  */
 lc_status lc_moments(lc_plan_t plan, const void* state, const double* I_exit,
                      const double* I_in, double c, double* E, double* F, double* f,
@@ -218,7 +220,9 @@ lc_status lc_moments(lc_plan_t plan, const void* state, const double* I_exit,
  * means the same data every step).  Every step forms its moments (as
  * lc_moments; any output may be NULL); E, F, f, bnd hold those of the last
  * step.  The step sequence is captured once in a HIP graph per argument set
- * and replayed.
+ * and replayed.  Errors: LC_ERR_ARG (n_steps < 1; null kappa, planck, states
+ * or I_in; state_a == state_b; material_stride < 0; c_dt or c not finite or
+ * <= 0; bnd without I_exit), LC_ERR_ALLOC, LC_ERR_HIP.
  */
 lc_status lc_step(lc_plan_t plan, int32_t n_steps, const double* kappa, const double* planck,
                   int64_t material_stride, double c_dt, double c, void* state_a, void* state_b,
@@ -232,6 +236,8 @@ lc_status lc_step(lc_plan_t plan, int32_t n_steps, const double* kappa, const do
  * in flight ahead of the arithmetic, 1, 2, 4 or 8; moments_entries: entries of each (cell,
  * azimuth pair) list whose loads go through the moment kernel's pipeline, 1 to
  * 4 (longer lists finish in a plain loop).  Setting the tuning drops the plan's captured graphs.
+ * Errors: LC_ERR_ARG for a null tuning or a value outside those sets (the
+ * plan keeps its previous tuning).
  */
 typedef struct {
     int32_t sweep_unroll;
@@ -263,7 +269,13 @@ lc_status lc_plan_profile_read(lc_plan_t plan, double* out);
  * kappa + t * material_stride, so with a non-zero stride n_steps must not
  * exceed the steps the caller provides); every step forms each problem's
  * moments, and the outputs hold those of the last step.  All problems must
- * share one precision.  I_exit is required.
+ * share one precision.  I_exit is required.  Errors of lc_batch_create:
+ * LC_ERR_ARG (no problems; a problem without kappa, planck, states, I_in or
+ * I_exit; state_a == state_b; c_dt not finite or <= 0; material_stride < 0;
+ * mixed precisions), LC_ERR_STATE (an invalid plan), LC_ERR_UNSUPPORTED
+ * (work lists beyond 32-bit indexing), LC_ERR_ALLOC, LC_ERR_HIP.  Errors of
+ * lc_batch_step: LC_ERR_ARG (n_steps < 1, c not finite or <= 0),
+ * LC_ERR_STATE (a member's plan freed), LC_ERR_HIP.
  */
 typedef struct {
     lc_plan_t plan;
