@@ -256,7 +256,7 @@ def main():
                     help="batch: the 64-problem batched form (default); single: one problem of --config")
     ap.add_argument("--config", type=int, default=2, help="workload index for --workload single (0, 1, 2 or 4)")
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--f64-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true")

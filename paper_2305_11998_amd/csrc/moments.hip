@@ -123,7 +123,8 @@ __device__ __forceinline__ void load_entry(gptr<const T> st, size_t o, int P, T 
 // float64 sums, fixed order).  A cache line of the state holds neighbouring
 // characteristics at the same step, which cross neighbouring cells, so the
 // wavefronts of a tile -- run together on one XCD -- share the lines they
-// fetch; a tile row of 16 cells fills whole 128-byte lines of the outputs.
+// fetch.  The outputs are cell-major, so a wavefront's 64 (cell, g) lanes
+// store contiguous doubles.
 //
 // The loads are pipelined over pairs: while the state values of pair a are
 // in flight, the entry offsets of pair a+1 and the list end of pair a+2 are
@@ -187,7 +188,7 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
 #pragma unroll
                 for (int p = 0; p < PM; ++p) Iim[d][p] += t.w * y[d][p];
         }
-    T part[7];
+        T part[7];
 #pragma unroll
         for (int c = 0; c < 7; ++c) part[c] = (T)0;
 #pragma unroll
