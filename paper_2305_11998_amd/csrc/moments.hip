@@ -337,47 +337,67 @@ __device__ __forceinline__ void boundary_lane(const BndArgs& A, int lane) {
     const gptr<const double> width = as_global(A.width);
     const gptr<const double> I_exit = as_global(A.I_exit);
     const gptr<const double> I_in = as_global(A.I_in);
-    for (int a = 0; a < A.n_pairs; ++a) {
-        for (int d = 0; d < 2; ++d) {
-            const gptr<const int> bm = as_global(A.bmap + ((size_t)(b * A.n_pairs + a) * 2 + d) * 2);
-            const int k0 = bm[0], k1 = bm[1];
-            double wsum = 0.0;
-            double acc[kMaxPol];
+    // exit ranges of face b, one int2 per (pair, traversal); the next one is
+    // loaded while the current one is summed
+    const int nad = 2 * A.n_pairs;
+    using I2 = int __attribute__((ext_vector_type(2)));
+    const gptr<const I2> bmv = (gptr<const I2>)as_global(A.bmap + (size_t)b * nad * 2);
+    I2 nxt = bmv[0];
+    for (int ad = 0; ad < nad; ++ad) {
+        const int a = ad >> 1, d = ad & 1;
+        const int k0 = nxt.x, k1 = nxt.y;
+        if (ad + 1 < nad) nxt = bmv[ad + 1];
+        double wsum = 0.0;
+        double acc[kMaxPol];
 #pragma unroll
-            for (int p = 0; p < kMaxPol; ++p) acc[p] = 0.0;
-            if (k0 >= 0)
-                for (int k = k0; k < k1; ++k) {
-                    const double w = width[k];
-                    wsum += w;
-                    const gptr<const double> ie = I_exit + (size_t)(2 * k + d) * P * G + g;
+        for (int p = 0; p < kMaxPol; ++p) acc[p] = 0.0;
+        if (k0 >= 0)
+            for (int k = k0; k < k1; k += 2) {        // two characteristics' loads in flight
+                const bool two = k + 1 < k1;
+                const double w0 = width[k];
+                const double w1 = two ? width[k + 1] : 0.0;
+                const gptr<const double> ie0 = I_exit + (size_t)(2 * k + d) * P * G + g;
+                const gptr<const double> ie1 = ie0 + (size_t)2 * P * G;
+                double x0[kMaxPol], x1[kMaxPol];
+#pragma unroll
+                for (int p = 0; p < kMaxPol; ++p) {
+                    x0[p] = p < P ? ie0[(size_t)p * G] : 0.0;
+                    x1[p] = p < P && two ? ie1[(size_t)p * G] : 0.0;
+                }
+                wsum += w0;
+#pragma unroll
+                for (int p = 0; p < kMaxPol; ++p)
+                    if (p < P) acc[p] += w0 * x0[p];
+                if (two) {
+                    wsum += w1;
 #pragma unroll
                     for (int p = 0; p < kMaxPol; ++p)
-                        if (p < P) acc[p] += w * ie[(size_t)p * G];
+                        if (p < P) acc[p] += w1 * x1[p];
                 }
-#pragma unroll
-            for (int p = 0; p < kMaxPol; ++p) {
-                if (p >= P) continue;
-                const gptr<const double> dw = as_global(A.dirw + ((size_t)(a * 2 + d) * P + p) * kDirW);
-                const double om = dw[0];
-                const double odn = dw[7] * nxv + dw[8] * nyv;
-                double I;
-                if (k0 >= 0) {
-                    I = acc[p] / wsum;
-                    Pp += om * I;
-                    Jp += om * odn * I;
-                    wo += om;
-                    wodn += om * odn;
-                } else {
-                    const int m = (a + d * (A.n_az >> 1)) * P + p;
-                    I = I_in[((size_t)b * M + m) * G + g];
-                    Pm += om * I;
-                    Jm += om * fabs(odn) * I;
-                }
-                S += om * I;
-                Sxx += dw[3] * I;
-                Sxy += dw[4] * I;
-                Syy += dw[5] * I;
             }
+#pragma unroll
+        for (int p = 0; p < kMaxPol; ++p) {
+            if (p >= P) continue;
+            const gptr<const double> dw = as_global(A.dirw + ((size_t)(a * 2 + d) * P + p) * kDirW);
+            const double om = dw[0];
+            const double odn = dw[7] * nxv + dw[8] * nyv;
+            double I;
+            if (k0 >= 0) {
+                I = acc[p] / wsum;
+                Pp += om * I;
+                Jp += om * odn * I;
+                wo += om;
+                wodn += om * odn;
+            } else {
+                const int m = (a + d * (A.n_az >> 1)) * P + p;
+                I = I_in[((size_t)b * M + m) * G + g];
+                Pm += om * I;
+                Jm += om * fabs(odn) * I;
+            }
+            S += om * I;
+            Sxx += dw[3] * I;
+            Sxy += dw[4] * I;
+            Syy += dw[5] * I;
         }
     }
     const gptr<double> out = as_global_w(A.bnd + ((size_t)g * A.nb + b) * 8);

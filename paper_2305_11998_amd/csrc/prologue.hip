@@ -18,7 +18,7 @@
 namespace lc {
 namespace {
 
-constexpr int kMaxChunk = 2048;   // elements per block of k_group_max
+constexpr int kMaxChunk = 8192;   // elements per block of k_group_max
 constexpr int kCoefTile = 1024;   // cells x groups per block of k_coef
 
 struct CoefArgs {
@@ -39,13 +39,18 @@ struct CoefArgs {
     int64_t g_off;           // first entry of this problem in a batch's maxima
 };
 
+// I_in rows per block of k_group_max: about kMaxChunk values, whole rows.
+__host__ __device__ __forceinline__ int64_t in_rows_per_block(int G) { return G >= kMaxChunk ? 1 : kMaxChunk / G; }
+
 __device__ __forceinline__ unsigned long long bits_of(double v) {
     return (unsigned long long)__double_as_longlong(v);
 }
 
 // Block b of the maxima of one problem at step `step`.  Blocks below
-// pl_blocks take a run of one group's B row; the others take a run of the flat
-// [nb*M][G] I_in array.  Values that are not finite are skipped.
+// pl_blocks take a run of one group's B row; the others take whole rows of the
+// [nb*M][G] I_in array, each thread reducing one group in registers (G up to
+// the block size) before one LDS merge per thread.  Values that are not
+// finite are skipped.
 __device__ __forceinline__ void group_max_block(const CoefArgs& A, int64_t b, int step, int t,
                                                 unsigned long long* smax) {
     const int G = A.G;
@@ -55,10 +60,18 @@ __device__ __forceinline__ void group_max_block(const CoefArgs& A, int64_t b, in
         const int64_t i0 = (b - (int64_t)g * per_g) * kMaxChunk;
         const int64_t i1 = min((int64_t)A.cells, i0 + kMaxChunk);
         const double* row = A.planck + (int64_t)step * A.stride + (int64_t)g * A.cells;
+        // eight independent loads in flight per thread
         double m = 0.0;
-        for (int64_t i = i0 + t; i < i1; i += kBlock) {
-            const double v = fabs(row[i]);
-            if (isfinite(v)) m = fmax(m, v);
+        for (int64_t ib = i0 + t; ib < i1; ib += 8 * kBlock) {
+            double v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t i = ib + (int64_t)j * kBlock;
+                v[j] = i < i1 ? fabs(row[i]) : 0.0;
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (isfinite(v[j])) m = fmax(m, v[j]);
         }
         for (int o = kWave / 2; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o));
         if ((t & (kWave - 1)) == 0 && m > 0.0) atomicMax(&A.gmax[g], bits_of(m));
@@ -66,16 +79,35 @@ __device__ __forceinline__ void group_max_block(const CoefArgs& A, int64_t b, in
     }
     for (int g = t; g < G; g += kBlock) smax[g] = 0ull;
     __syncthreads();
-    const int64_t n = A.n_in * G;
-    const int64_t i0 = (b - A.pl_blocks) * kMaxChunk;
-    const int64_t i1 = min(n, i0 + kMaxChunk);
-    int g = (int)((i0 + t) % G);
-    const int gstep = kBlock % G;
-    for (int64_t i = i0 + t; i < i1; i += kBlock) {
-        const double v = fabs(A.I_in[i]);
-        if (isfinite(v) && v > 0.0) atomicMax(&smax[g], bits_of(v));
-        g += gstep;
-        if (g >= G) g -= G;
+    // rows [r0, r1) of the [nb*M][G] I_in array
+    const int64_t rpb = in_rows_per_block(G);
+    const int64_t r0 = (b - A.pl_blocks) * rpb;
+    const int64_t r1 = min(A.n_in, r0 + rpb);
+    if (G <= kBlock) {
+        // thread t keeps the maximum of group t % G over every R-th row
+        const int R = kBlock / G;
+        if (t < R * G) {
+            const int g = t % G;
+            double m = 0.0;
+            for (int64_t rb = r0 + t / G; rb < r1; rb += 8 * (int64_t)R) {
+                double v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int64_t r = rb + (int64_t)j * R;
+                    v[j] = r < r1 ? fabs(A.I_in[r * G + g]) : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    if (isfinite(v[j])) m = fmax(m, v[j]);
+            }
+            if (m > 0.0) atomicMax(&smax[g], bits_of(m));
+        }
+    } else {
+        for (int64_t r = r0; r < r1; ++r)
+            for (int g = t; g < G; g += kBlock) {
+                const double v = fabs(A.I_in[r * G + g]);
+                if (isfinite(v) && v > 0.0) atomicMax(&smax[g], bits_of(v));
+            }
     }
     __syncthreads();
     for (int q = t; q < G; q += kBlock)
@@ -196,7 +228,10 @@ CoefArgs coef_args(const Plan* pl, double c_dt, const double* kappa, const doubl
     return C;
 }
 
-int64_t max_blocks(const CoefArgs& C) { return C.pl_blocks + (C.n_in * C.G + kMaxChunk - 1) / kMaxChunk; }
+int64_t max_blocks(const CoefArgs& C) {
+    const int64_t rpb = in_rows_per_block(C.G);
+    return C.pl_blocks + (C.n_in + rpb - 1) / rpb;
+}
 int64_t coef_blocks(const CoefArgs& C) {
     return ((int64_t)C.cells + C.ct - 1) / C.ct * ((C.G + C.gt - 1) / C.gt);
 }

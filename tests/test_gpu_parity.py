@@ -213,10 +213,11 @@ def test_tuning_settings_give_identical_results(lcmod, prec, mode, h_moc):
         assert np.array_equal(st, out[0][1])
 
 
-@pytest.mark.parametrize("G,prec", [(66, 0), (100, 0), (100, 1)])
+@pytest.mark.parametrize("G,prec", [(66, 0), (100, 0), (100, 1), (260, 1)])
 def test_many_groups_span_three_bundles(lcmod, G, prec):
     """G > 64: a characteristic's groups can span three 64-lane bundles (the
-    moment gather then looks up each lane's bundle)."""
+    moment gather then looks up each lane's bundle).  G = 260 also exceeds
+    the block size of the float32 prologue's group maxima."""
     lc, driver = lcmod
     prob = _custom_problem(nx=9, ny=7, lx=0.9, ly=0.7, n_az=8, G=G, h_moc=0.04, steps=1)
     _compare_full(lc, driver, prob, prec, TOL64 if prec == 0 else TOL32)
