@@ -23,6 +23,7 @@ namespace {
 struct PolarClass {
     int pm = 1;
     int unroll = 2, ent = 3;            // launch tuning of the class's lowest-index member
+    int sweep_grid = 0;                 // resident blocks of the persistent sweep on this device
     int2* d_sweep_items = nullptr;      // {problem, bundle traversal}
     int64_t* d_sweep_qb = nullptr;      // [9] bounds of the eight per-XCD sweep queues
     int2* d_mom_items = nullptr;        // {problem, wavefront of a tile}
@@ -99,7 +100,7 @@ lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
         if (rc == LC_OK) rc = ev_end(b, 0, st);
         if (rc == LC_OK) rc = ev_begin(b, 1, st);
         for (size_t c = 0; c < b->cls.size() && rc == LC_OK; ++c)
-            rc = launch_sweep_batch(b->prec, b->cls[c].pm, b->cls[c].unroll,
+            rc = launch_sweep_batch(b->prec, b->cls[c].pm, b->cls[c].unroll, b->cls[c].sweep_grid,
                                     static_cast<char*>(b->d_sweep_args) + parity * b->n * sb,
                                     b->cls[c].d_sweep_items, b->cls[c].d_sweep_qb, b->d_counters + 8 * c, st);
         if (rc == LC_OK) rc = ev_end(b, 1, st);
@@ -305,6 +306,8 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
                 break;
             }
         c.n_mom_items = (int64_t)mi.size();
+        rc = sweep_batch_grid(b->prec, pm, c.unroll, &c.sweep_grid);
+        if (rc != LC_OK) break;
         b->cls.push_back(c);
         PolarClass& cc = b->cls.back();
         rc = upload(reinterpret_cast<void**>(&cc.d_sweep_items), si.data(), si.size() * sizeof(int2));

@@ -200,8 +200,9 @@ lc_status launch_prologue_batch(int prec, const void* coef_args, int n, int64_t 
                                 int64_t coef_blocks_all, int max_G, unsigned long long* gmax, int64_t n_gmax, int t,
                                 hipStream_t st);
 lc_status launch_zero_counters(int* c, int n, hipStream_t st);
-lc_status launch_sweep_batch(int prec, int pm, int unroll, const void* args, const int2* items, const int64_t* qb,
-                             int* counters, hipStream_t st);
+lc_status sweep_batch_grid(int prec, int pm, int unroll, int* grid);
+lc_status launch_sweep_batch(int prec, int pm, int unroll, int grid, const void* args, const int2* items,
+                             const int64_t* qb, int* counters, hipStream_t st);
 lc_status launch_moments_batch(int prec, int pm, int ent, const void* args, const int2* items, int64_t n_items,
                                hipStream_t st);
 lc_status launch_boundary_batch(const void* args, int n, int64_t blocks, hipStream_t st);

@@ -394,17 +394,32 @@ lc_status launch_sweep_p(Plan* pl, const SweepArgs& A, hipStream_t st) {
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// The persistent grid of the batched sweep: as many blocks as the current
+// device keeps resident (a multiple of 8, so every XCD gets the same count).
 template <typename T, int PM, int U>
-lc_status launch_sweep_batch_u(const void* args, const int2* items, const int64_t* qb, int* counters,
-                               hipStream_t st) {
-    static int grid = 0;
-    if (!grid) {
-        int dev = 0, cus = 0, per_cu = 0;
-        LC_HIP(hipGetDevice(&dev));
-        LC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-        LC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_sweep_batch<T, PM, U>), kBlock, 0));
-        grid = std::max(8, cus * std::max(per_cu, 1) / 8 * 8);
+lc_status sweep_batch_grid_u(int* grid) {
+    int dev = 0, cus = 0, per_cu = 0;
+    LC_HIP(hipGetDevice(&dev));
+    LC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    LC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_sweep_batch<T, PM, U>),
+                                                        kBlock, 0));
+    *grid = std::max(8, cus * std::max(per_cu, 1) / 8 * 8);
+    return LC_OK;
+}
+
+template <typename T, int PM>
+lc_status sweep_batch_grid_p(int unroll, int* grid) {
+    switch (unroll) {
+        case 1: return sweep_batch_grid_u<T, PM, 1>(grid);
+        case 2: return sweep_batch_grid_u<T, PM, 2>(grid);
+        case 4: return sweep_batch_grid_u<T, PM, 4>(grid);
+        default: return sweep_batch_grid_u<T, PM, 8>(grid);
     }
+}
+
+template <typename T, int PM, int U>
+lc_status launch_sweep_batch_u(int grid, const void* args, const int2* items, const int64_t* qb, int* counters,
+                               hipStream_t st) {
     hipLaunchKernelGGL((k_sweep_batch<T, PM, U>), dim3(grid), dim3(kBlock), 0, st,
                        static_cast<const SweepArgs*>(args), items, qb, counters);
     LC_HIP(hipGetLastError());
@@ -412,13 +427,13 @@ lc_status launch_sweep_batch_u(const void* args, const int2* items, const int64_
 }
 
 template <typename T, int PM>
-lc_status launch_sweep_batch_p(int unroll, const void* args, const int2* items, const int64_t* qb, int* counters,
-                               hipStream_t st) {
+lc_status launch_sweep_batch_p(int unroll, int grid, const void* args, const int2* items, const int64_t* qb,
+                               int* counters, hipStream_t st) {
     switch (unroll) {
-        case 1: return launch_sweep_batch_u<T, PM, 1>(args, items, qb, counters, st);
-        case 2: return launch_sweep_batch_u<T, PM, 2>(args, items, qb, counters, st);
-        case 4: return launch_sweep_batch_u<T, PM, 4>(args, items, qb, counters, st);
-        default: return launch_sweep_batch_u<T, PM, 8>(args, items, qb, counters, st);
+        case 1: return launch_sweep_batch_u<T, PM, 1>(grid, args, items, qb, counters, st);
+        case 2: return launch_sweep_batch_u<T, PM, 2>(grid, args, items, qb, counters, st);
+        case 4: return launch_sweep_batch_u<T, PM, 4>(grid, args, items, qb, counters, st);
+        default: return launch_sweep_batch_u<T, PM, 8>(grid, args, items, qb, counters, st);
     }
 }
 
@@ -471,18 +486,30 @@ lc_status launch_zero_counters(int* c, int n, hipStream_t st) {
     return LC_OK;
 }
 
-lc_status launch_sweep_batch(int prec, int pm, int unroll, const void* args, const int2* items, const int64_t* qb,
-                             int* counters, hipStream_t st) {
+lc_status sweep_batch_grid(int prec, int pm, int unroll, int* grid) {
     const bool f32 = prec == LC_F32;
     switch (pm) {
-        case 1: return f32 ? launch_sweep_batch_p<float, 1>(unroll, args, items, qb, counters, st)
-                           : launch_sweep_batch_p<double, 1>(unroll, args, items, qb, counters, st);
-        case 2: return f32 ? launch_sweep_batch_p<float, 2>(unroll, args, items, qb, counters, st)
-                           : launch_sweep_batch_p<double, 2>(unroll, args, items, qb, counters, st);
-        case 4: return f32 ? launch_sweep_batch_p<float, 4>(unroll, args, items, qb, counters, st)
-                           : launch_sweep_batch_p<double, 4>(unroll, args, items, qb, counters, st);
-        case 8: return f32 ? launch_sweep_batch_p<float, 8>(unroll, args, items, qb, counters, st)
-                           : launch_sweep_batch_p<double, 8>(unroll, args, items, qb, counters, st);
+        case 1: return f32 ? sweep_batch_grid_p<float, 1>(unroll, grid) : sweep_batch_grid_p<double, 1>(unroll, grid);
+        case 2: return f32 ? sweep_batch_grid_p<float, 2>(unroll, grid) : sweep_batch_grid_p<double, 2>(unroll, grid);
+        case 4: return f32 ? sweep_batch_grid_p<float, 4>(unroll, grid) : sweep_batch_grid_p<double, 4>(unroll, grid);
+        case 8: return f32 ? sweep_batch_grid_p<float, 8>(unroll, grid) : sweep_batch_grid_p<double, 8>(unroll, grid);
+    }
+    set_error("batched sweep: polar bound %d not supported", pm);
+    return LC_ERR_UNSUPPORTED;
+}
+
+lc_status launch_sweep_batch(int prec, int pm, int unroll, int grid, const void* args, const int2* items,
+                             const int64_t* qb, int* counters, hipStream_t st) {
+    const bool f32 = prec == LC_F32;
+    switch (pm) {
+        case 1: return f32 ? launch_sweep_batch_p<float, 1>(unroll, grid, args, items, qb, counters, st)
+                           : launch_sweep_batch_p<double, 1>(unroll, grid, args, items, qb, counters, st);
+        case 2: return f32 ? launch_sweep_batch_p<float, 2>(unroll, grid, args, items, qb, counters, st)
+                           : launch_sweep_batch_p<double, 2>(unroll, grid, args, items, qb, counters, st);
+        case 4: return f32 ? launch_sweep_batch_p<float, 4>(unroll, grid, args, items, qb, counters, st)
+                           : launch_sweep_batch_p<double, 4>(unroll, grid, args, items, qb, counters, st);
+        case 8: return f32 ? launch_sweep_batch_p<float, 8>(unroll, grid, args, items, qb, counters, st)
+                           : launch_sweep_batch_p<double, 8>(unroll, grid, args, items, qb, counters, st);
     }
     set_error("batched sweep: polar bound %d not supported", pm);
     return LC_ERR_UNSUPPORTED;
