@@ -260,7 +260,10 @@ lc_status lc_plan_profile_read(lc_plan_t plan, double* out);
 /*
  * Batched form: many independent problems (each its own rays and plan)
  * advanced together.  Problems are grouped by polar bound (the power of two
- * >= n_pol); per group, the sweep and the cell moments are one launch each
+ * >= n_pol) and by sweep form (mirror-symmetric polar sets of power-of-two
+ * size run a sweep without per-angle branches, as in their single-problem
+ * runs, so batched results equal those runs bit for bit); per group, the
+ * sweep and the cell moments are one launch each
  * over all members, with the launch tuning of the plan of the group's
  * lowest-index member.  lc_batch_create copies the per-problem pointer sets
  * (device arrays as for lc_step) into the handle and builds work lists

@@ -1,5 +1,6 @@
 // Batched form: many independent problems advanced together.  Problems are
-// grouped by polar bound; per step and group there is one persistent sweep
+// grouped by polar bound and sweep form; per step and group there is one
+// persistent sweep
 // kernel whose wavefronts pull (problem, bundle traversal) items from eight
 // per-XCD queues and one cell-moment launch over the (problem, tile
 // wavefront) items; the coefficient prologue and the boundary factors are one
@@ -17,12 +18,16 @@
 namespace lc {
 namespace {
 
-// Problems of one polar bound (the power of two >= their polar count): their
-// sweep and moment kernels are compiled for that bound, so a class of
-// two-angle problems does not carry the registers of a four-angle one.
+// Problems of one polar bound (the power of two >= their polar count) and
+// one sweep form: their sweep and moment kernels are compiled for that bound,
+// so a class of two-angle problems does not carry the registers of a
+// four-angle one, and each member runs the sweep code of its single-problem
+// run.
 struct PolarClass {
     int pm = 1;
     int unroll = 2, ent = 3;            // launch tuning of the class's lowest-index member
+    bool full = false;                  // members run the FULL sweep (sweep_full)
+    size_t sweep_lds = 0;               // LDS reserved per sweep block
     int sweep_grid = 0;                 // resident blocks of the persistent sweep on this device
     int2* d_sweep_items = nullptr;      // {problem, bundle traversal}
     int64_t* d_sweep_qb = nullptr;      // [9] bounds of the eight per-XCD sweep queues
@@ -100,8 +105,8 @@ lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
         if (rc == LC_OK) rc = ev_end(b, 0, st);
         if (rc == LC_OK) rc = ev_begin(b, 1, st);
         for (size_t c = 0; c < b->cls.size() && rc == LC_OK; ++c)
-            rc = launch_sweep_batch(b->prec, b->cls[c].pm, b->cls[c].unroll, b->cls[c].sweep_grid,
-                                    static_cast<char*>(b->d_sweep_args) + parity * b->n * sb,
+            rc = launch_sweep_batch(b->prec, b->cls[c].pm, b->cls[c].unroll, b->cls[c].full, b->cls[c].sweep_lds,
+                                    b->cls[c].sweep_grid, static_cast<char*>(b->d_sweep_args) + parity * b->n * sb,
                                     b->cls[c].d_sweep_items, b->cls[c].d_sweep_qb, b->d_counters + 8 * c, st);
         if (rc == LC_OK) rc = ev_end(b, 1, st);
         if (rc == LC_OK) {                            // every step forms its moments
@@ -262,11 +267,16 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
     };
     if (rc == LC_OK) rc = upload(&b->d_sweep_args, hs.data(), hs.size());
     if (rc == LC_OK) rc = upload(&b->d_coef_args, hc.data(), hc.size());
-    for (int pm = 1; pm <= kMaxPol && rc == LC_OK; pm *= 2) {
+    // one class per polar bound and sweep form, so that every member runs
+    // the sweep code of its single-problem run (bit-identical results)
+    for (int key = 0; key < 2 * 4 && rc == LC_OK; ++key) {
+        const int pm = 1 << (key >> 1);
+        const bool full = (key & 1) == 0;
+        auto member = [&](int q) { return pm_of(q) == pm && sweep_full(b->plans[q]->rays) == full; };
         std::vector<int2> si, mi;
         std::vector<double> scost;      // summed steps of the sweep items, for the queue split
         for (int q : order) {
-            if (pm_of(q) != pm) continue;
+            if (!member(q)) continue;
             const Plan* pl = b->plans[q];
             for (int64_t B = 0; B < pl->n_bun; ++B)
                 for (int d = 0; d < 2; ++d) {
@@ -299,14 +309,16 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
         while (x < 9) sqb[x++] = (int64_t)scost.size();
         PolarClass c;
         c.pm = pm;
+        c.full = full;
         for (int q = 0; q < n_problems; ++q)
-            if (pm_of(q) == pm) {
+            if (member(q)) {
                 c.unroll = b->plans[q]->sweep_unroll;
                 c.ent = b->plans[q]->moments_entries;
                 break;
             }
         c.n_mom_items = (int64_t)mi.size();
-        rc = sweep_batch_grid(b->prec, pm, c.unroll, &c.sweep_grid);
+        rc = sweep_lds_bytes(&c.sweep_lds);
+        if (rc == LC_OK) rc = sweep_batch_grid(b->prec, pm, c.unroll, c.full, c.sweep_lds, &c.sweep_grid);
         if (rc != LC_OK) break;
         b->cls.push_back(c);
         PolarClass& cc = b->cls.back();

@@ -130,6 +130,7 @@ struct Plan {
     unsigned* d_bun_rec = nullptr;    // [n_bun] first lane record of each bundle
     int tile_w = 1, tile_h = 1;       // cell tile of the moments kernel
     int64_t sweep_blocks = 0;         // blocks of one sweep launch
+    size_t sweep_lds = 0;             // LDS reserved per sweep block (caps the blocks per CU)
     std::vector<GraphEntry> graphs;   // captured lc_step sequences
     hipStream_t capture = nullptr;    // stream used only to record graphs
     bool profile = false;             // record events around the main kernels
@@ -200,9 +201,13 @@ lc_status launch_prologue_batch(int prec, const void* coef_args, int n, int64_t 
                                 int64_t coef_blocks_all, int max_G, unsigned long long* gmax, int64_t n_gmax, int t,
                                 hipStream_t st);
 lc_status launch_zero_counters(int* c, int n, hipStream_t st);
-lc_status sweep_batch_grid(int prec, int pm, int unroll, int* grid);
-lc_status launch_sweep_batch(int prec, int pm, int unroll, int grid, const void* args, const int2* items,
-                             const int64_t* qb, int* counters, hipStream_t st);
+// The sweep form without per-polar-slot branches: a mirror-symmetric polar
+// set whose size is a power of two (so it fills its polar bound exactly).
+inline bool sweep_full(const Rays* r) { return r->sym && (r->n_pol & (r->n_pol - 1)) == 0; }
+lc_status sweep_lds_bytes(size_t* lds);
+lc_status sweep_batch_grid(int prec, int pm, int unroll, bool full, size_t lds, int* grid);
+lc_status launch_sweep_batch(int prec, int pm, int unroll, bool full, size_t lds, int grid, const void* args,
+                             const int2* items, const int64_t* qb, int* counters, hipStream_t st);
 lc_status launch_moments_batch(int prec, int pm, int ent, const void* args, const int2* items, int64_t n_items,
                                hipStream_t st);
 lc_status launch_boundary_batch(const void* args, int n, int64_t blocks, hipStream_t st);

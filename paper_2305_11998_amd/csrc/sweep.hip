@@ -65,6 +65,12 @@ __device__ __forceinline__ int find_pair(gptr<const int> off, int n, int64_t v) 
     return lo;
 }
 
+// Blocks of a sweep launch resident on one CU at most (two wavefronts per
+// SIMD), enforced by the LDS each block reserves: more resident wavefronts
+// were measured to make the sweep slower (the caches serve fewer streams
+// better).
+constexpr int kSweepBlocksPerCU = 2;
+
 template <typename T> struct Att { T E, D, al, be; };
 
 // e^{-tau}, 1 - e^{-tau} and alpha of eq. (13) in float32: series below the
@@ -142,7 +148,13 @@ __device__ __forceinline__ void stg_stream(gptr<T> p, T v) { __builtin_nontempor
 // p = i, upper slot i holds p = P - 1 - i, so that with a mirror-symmetric
 // polar set (mu_p = -mu_{P-1-p}, equal sin(zeta)) an upper slot reuses the
 // exponential and alpha of the lower slot with the same index.
-template <typename T, int PM, int U>
+//
+// FULL: P == PM and the polar set is mirror-symmetric, known at compile
+// time, so a step has no per-slot branches (used for power-of-two P, whose
+// batched launches share the polar bound P).  A FULL wavefront also stores
+// every row of its bundle: the rows past the end of a lane's characteristic
+// are that lane's padding, which nothing reads.
+template <typename T, int PM, int U, bool FULL>
 __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int lane) {
     constexpr int NL = (PM + 1) / 2, NU = PM / 2, NS = NL + NU;
     const int d = w >= A.n_bun ? 1 : 0;
@@ -177,7 +189,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
     // a lane's P values of one step are contiguous: with P == PM (a power of
     // two) they move as one vector load or store
     constexpr bool kVecOk = PM >= 2 && (PM & (PM - 1)) == 0;
-    const bool vec = kVecOk && P == PM;
+    const bool vec = kVecOk && (FULL || P == PM);
     using V = T __attribute__((ext_vector_type(PM)));
 
     int pol[NS];
@@ -185,14 +197,14 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
 #pragma unroll
     for (int i = 0; i < NL; ++i) {
         pol[i] = i;
-        val[i] = i < (P + 1) / 2;
+        val[i] = FULL || i < (P + 1) / 2;
     }
 #pragma unroll
     for (int i = 0; i < NU; ++i) {
         pol[NL + i] = P - 1 - i;
-        val[NL + i] = i < P / 2;
+        val[NL + i] = FULL || i < P / 2;
     }
-    const bool sym = A.sym;
+    const bool sym = FULL || A.sym;
 
     double sc_in = 1.0, sc_out = 1.0, cb = A.inv_cdt;
     if (sizeof(T) == 4) {
@@ -285,7 +297,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
                 ob[q] = at[q].al * I[q] + at[q].be * Io;              // segment average
                 I[q] = live ? Io : I[q];
             }
-            if (live) {
+            if (FULL ? t < L : live) {
                 if (vec) {
                     V v;
 #pragma unroll
@@ -318,12 +330,12 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
     }
 }
 
-template <typename T, int PM, int U>
+template <typename T, int PM, int U, bool FULL>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
     const int64_t lb = xcd_logical_block(blockIdx.x, A.n_blocks);
     const int64_t w = lb * (kBlock / kWave) + (threadIdx.x / kWave);
     if (w >= 2 * A.n_bun) return;
-    sweep_wave<T, PM, U>(A, w, threadIdx.x & (kWave - 1));
+    sweep_wave<T, PM, U, FULL>(A, w, threadIdx.x & (kWave - 1));
 }
 
 // Batched form: a persistent grid whose wavefronts take work items
@@ -334,8 +346,9 @@ __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
 // the summed bundle lengths, so the characteristics crossing a cell are swept
 // on one XCD and share its L2 copy of the cell coefficients.  A wavefront
 // whose queue is empty moves on to the next one and stops after finding all
-// eight empty; counters only grow, so every wavefront exits.
-template <typename T, int PM, int U>
+// eight empty; counters only grow, so every wavefront exits.  FULL holds for
+// every problem of the launch.
+template <typename T, int PM, int U, bool FULL>
 __global__ __launch_bounds__(kBlock) void k_sweep_batch(const SweepArgs* __restrict__ probs,
                                                         const int2* __restrict__ items,
                                                         const int64_t* __restrict__ qb, int* counters) {
@@ -353,7 +366,7 @@ __global__ __launch_bounds__(kBlock) void k_sweep_batch(const SweepArgs* __restr
         }
         const int pr = __builtin_amdgcn_readfirstlane(items[gi].x);
         const int w = __builtin_amdgcn_readfirstlane(items[gi].y);
-        sweep_wave<T, PM, U>(probs[pr], w, lane);
+        sweep_wave<T, PM, U, FULL>(probs[pr], w, lane);
     }
 }
 
@@ -361,81 +374,93 @@ __global__ void k_zero_counter(int* c, int n) {
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
-template <typename T, int PM>
-lc_status launch_sweep_t(Plan* pl, const SweepArgs& A, hipStream_t st) {
-    lc_status rc = prof_begin(pl, pl->ev_sweep, st);
-    if (rc) return rc;
-    dim3 grid((unsigned)pl->sweep_blocks), block(kBlock);
-    switch (pl->sweep_unroll) {
-        case 1: hipLaunchKernelGGL((k_sweep<T, PM, 1>), grid, block, 0, st, A); break;
-        case 2: hipLaunchKernelGGL((k_sweep<T, PM, 2>), grid, block, 0, st, A); break;
-        case 4: hipLaunchKernelGGL((k_sweep<T, PM, 4>), grid, block, 0, st, A); break;
-        default: hipLaunchKernelGGL((k_sweep<T, PM, 8>), grid, block, 0, st, A); break;
+// One sweep launch: a single problem (args1, blocks) or a batch (args,
+// items, qb, counters, grid), or, with grid_out, the query of the batch's
+// persistent grid.  lds is the dynamic LDS each block reserves to cap the
+// blocks resident on a CU.
+struct SweepCall {
+    int unroll = 8;
+    bool full = false;
+    size_t lds = 0;
+    hipStream_t st = nullptr;
+    const SweepArgs* args1 = nullptr;
+    unsigned blocks = 0;
+    const void* args = nullptr;
+    const int2* items = nullptr;
+    const int64_t* qb = nullptr;
+    int* counters = nullptr;
+    int grid = 0;
+    int* grid_out = nullptr;
+};
+
+template <bool BATCH, typename T, int PM, int U, bool FULL>
+lc_status sweep_call(const SweepCall& c) {
+    if constexpr (!BATCH) {
+        hipLaunchKernelGGL((k_sweep<T, PM, U, FULL>), dim3(c.blocks), dim3(kBlock), c.lds, c.st, *c.args1);
+    } else if (c.grid_out) {
+        // as many blocks as the device keeps resident, a multiple of 8 so
+        // that every XCD gets the same count
+        int dev = 0, cus = 0, per_cu = 0;
+        LC_HIP(hipGetDevice(&dev));
+        LC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        LC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void*>(&k_sweep_batch<T, PM, U, FULL>), kBlock, c.lds));
+        *c.grid_out = std::max(8, cus * std::max(per_cu, 1) / 8 * 8);
+        return LC_OK;
+    } else {
+        hipLaunchKernelGGL((k_sweep_batch<T, PM, U, FULL>), dim3(c.grid), dim3(kBlock), c.lds, c.st,
+                           static_cast<const SweepArgs*>(c.args), c.items, c.qb, c.counters);
     }
     LC_HIP(hipGetLastError());
-    return prof_end(pl, pl->ev_sweep, st);
+    return LC_OK;
 }
 
-template <typename T>
-lc_status launch_sweep_p(Plan* pl, const SweepArgs& A, hipStream_t st) {
-    switch (pl->rays->n_pol) {
-        case 1: return launch_sweep_t<T, 1>(pl, A, st);
-        case 2: return launch_sweep_t<T, 2>(pl, A, st);
-        case 3: return launch_sweep_t<T, 3>(pl, A, st);
-        case 4: return launch_sweep_t<T, 4>(pl, A, st);
-        case 5: return launch_sweep_t<T, 5>(pl, A, st);
-        case 6: return launch_sweep_t<T, 6>(pl, A, st);
-        case 7: return launch_sweep_t<T, 7>(pl, A, st);
-        case 8: return launch_sweep_t<T, 8>(pl, A, st);
+template <bool BATCH, typename T, int PM, bool FULL>
+lc_status sweep_call_u(const SweepCall& c) {
+    switch (c.unroll) {
+        case 1: return sweep_call<BATCH, T, PM, 1, FULL>(c);
+        case 2: return sweep_call<BATCH, T, PM, 2, FULL>(c);
+        case 4: return sweep_call<BATCH, T, PM, 4, FULL>(c);
+        default: return sweep_call<BATCH, T, PM, 8, FULL>(c);
     }
-    set_error("n_pol = %d not supported (1..8)", pl->rays->n_pol);
+}
+
+template <bool BATCH, typename T, int PM>
+lc_status sweep_call_f(const SweepCall& c) {
+    return c.full ? sweep_call_u<BATCH, T, PM, true>(c) : sweep_call_u<BATCH, T, PM, false>(c);
+}
+
+// Single problems: PM = n_pol exactly.
+template <typename T>
+lc_status sweep_call_single(int n_pol, const SweepCall& c) {
+    switch (n_pol) {
+        case 1: return sweep_call_f<false, T, 1>(c);
+        case 2: return sweep_call_f<false, T, 2>(c);
+        case 3: return sweep_call_f<false, T, 3>(c);
+        case 4: return sweep_call_f<false, T, 4>(c);
+        case 5: return sweep_call_f<false, T, 5>(c);
+        case 6: return sweep_call_f<false, T, 6>(c);
+        case 7: return sweep_call_f<false, T, 7>(c);
+        case 8: return sweep_call_f<false, T, 8>(c);
+    }
+    set_error("n_pol = %d not supported (1..8)", n_pol);
+    return LC_ERR_UNSUPPORTED;
+}
+
+// Batches: PM = the polar bound of a group of problems, a power of two.
+lc_status sweep_call_batch(int prec, int pm, const SweepCall& c) {
+    const bool f32 = prec == LC_F32;
+    switch (pm) {
+        case 1: return f32 ? sweep_call_f<true, float, 1>(c) : sweep_call_f<true, double, 1>(c);
+        case 2: return f32 ? sweep_call_f<true, float, 2>(c) : sweep_call_f<true, double, 2>(c);
+        case 4: return f32 ? sweep_call_f<true, float, 4>(c) : sweep_call_f<true, double, 4>(c);
+        case 8: return f32 ? sweep_call_f<true, float, 8>(c) : sweep_call_f<true, double, 8>(c);
+    }
+    set_error("batched sweep: polar bound %d not supported", pm);
     return LC_ERR_UNSUPPORTED;
 }
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
-
-// The persistent grid of the batched sweep: as many blocks as the current
-// device keeps resident (a multiple of 8, so every XCD gets the same count).
-template <typename T, int PM, int U>
-lc_status sweep_batch_grid_u(int* grid) {
-    int dev = 0, cus = 0, per_cu = 0;
-    LC_HIP(hipGetDevice(&dev));
-    LC_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    LC_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_sweep_batch<T, PM, U>),
-                                                        kBlock, 0));
-    *grid = std::max(8, cus * std::max(per_cu, 1) / 8 * 8);
-    return LC_OK;
-}
-
-template <typename T, int PM>
-lc_status sweep_batch_grid_p(int unroll, int* grid) {
-    switch (unroll) {
-        case 1: return sweep_batch_grid_u<T, PM, 1>(grid);
-        case 2: return sweep_batch_grid_u<T, PM, 2>(grid);
-        case 4: return sweep_batch_grid_u<T, PM, 4>(grid);
-        default: return sweep_batch_grid_u<T, PM, 8>(grid);
-    }
-}
-
-template <typename T, int PM, int U>
-lc_status launch_sweep_batch_u(int grid, const void* args, const int2* items, const int64_t* qb, int* counters,
-                               hipStream_t st) {
-    hipLaunchKernelGGL((k_sweep_batch<T, PM, U>), dim3(grid), dim3(kBlock), 0, st,
-                       static_cast<const SweepArgs*>(args), items, qb, counters);
-    LC_HIP(hipGetLastError());
-    return LC_OK;
-}
-
-template <typename T, int PM>
-lc_status launch_sweep_batch_p(int unroll, int grid, const void* args, const int2* items, const int64_t* qb,
-                               int* counters, hipStream_t st) {
-    switch (unroll) {
-        case 1: return launch_sweep_batch_u<T, PM, 1>(grid, args, items, qb, counters, st);
-        case 2: return launch_sweep_batch_u<T, PM, 2>(grid, args, items, qb, counters, st);
-        case 4: return launch_sweep_batch_u<T, PM, 4>(grid, args, items, qb, counters, st);
-        default: return launch_sweep_batch_u<T, PM, 8>(grid, args, items, qb, counters, st);
-    }
-}
 
 }  // namespace
 
@@ -486,33 +511,39 @@ lc_status launch_zero_counters(int* c, int n, hipStream_t st) {
     return LC_OK;
 }
 
-lc_status sweep_batch_grid(int prec, int pm, int unroll, int* grid) {
-    const bool f32 = prec == LC_F32;
-    switch (pm) {
-        case 1: return f32 ? sweep_batch_grid_p<float, 1>(unroll, grid) : sweep_batch_grid_p<double, 1>(unroll, grid);
-        case 2: return f32 ? sweep_batch_grid_p<float, 2>(unroll, grid) : sweep_batch_grid_p<double, 2>(unroll, grid);
-        case 4: return f32 ? sweep_batch_grid_p<float, 4>(unroll, grid) : sweep_batch_grid_p<double, 4>(unroll, grid);
-        case 8: return f32 ? sweep_batch_grid_p<float, 8>(unroll, grid) : sweep_batch_grid_p<double, 8>(unroll, grid);
-    }
-    set_error("batched sweep: polar bound %d not supported", pm);
-    return LC_ERR_UNSUPPORTED;
+lc_status sweep_lds_bytes(size_t* lds) {
+    *lds = 0;
+    int dev = 0, per_cu = 0;
+    LC_HIP(hipGetDevice(&dev));
+    if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+        per_cu <= 0)
+        return LC_OK;                 // no cap
+    *lds = (size_t)per_cu / (kSweepBlocksPerCU + 1) + 1;
+    return LC_OK;
 }
 
-lc_status launch_sweep_batch(int prec, int pm, int unroll, int grid, const void* args, const int2* items,
-                             const int64_t* qb, int* counters, hipStream_t st) {
-    const bool f32 = prec == LC_F32;
-    switch (pm) {
-        case 1: return f32 ? launch_sweep_batch_p<float, 1>(unroll, grid, args, items, qb, counters, st)
-                           : launch_sweep_batch_p<double, 1>(unroll, grid, args, items, qb, counters, st);
-        case 2: return f32 ? launch_sweep_batch_p<float, 2>(unroll, grid, args, items, qb, counters, st)
-                           : launch_sweep_batch_p<double, 2>(unroll, grid, args, items, qb, counters, st);
-        case 4: return f32 ? launch_sweep_batch_p<float, 4>(unroll, grid, args, items, qb, counters, st)
-                           : launch_sweep_batch_p<double, 4>(unroll, grid, args, items, qb, counters, st);
-        case 8: return f32 ? launch_sweep_batch_p<float, 8>(unroll, grid, args, items, qb, counters, st)
-                           : launch_sweep_batch_p<double, 8>(unroll, grid, args, items, qb, counters, st);
-    }
-    set_error("batched sweep: polar bound %d not supported", pm);
-    return LC_ERR_UNSUPPORTED;
+lc_status sweep_batch_grid(int prec, int pm, int unroll, bool full, size_t lds, int* grid) {
+    SweepCall c;
+    c.unroll = unroll;
+    c.full = full;
+    c.lds = lds;
+    c.grid_out = grid;
+    return sweep_call_batch(prec, pm, c);
+}
+
+lc_status launch_sweep_batch(int prec, int pm, int unroll, bool full, size_t lds, int grid, const void* args,
+                             const int2* items, const int64_t* qb, int* counters, hipStream_t st) {
+    SweepCall c;
+    c.unroll = unroll;
+    c.full = full;
+    c.lds = lds;
+    c.st = st;
+    c.args = args;
+    c.items = items;
+    c.qb = qb;
+    c.counters = counters;
+    c.grid = grid;
+    return sweep_call_batch(prec, pm, c);
 }
 
 lc_status plan_init_sweep(Plan* pl) {
@@ -543,7 +574,7 @@ lc_status plan_init_sweep(Plan* pl) {
     const int64_t waves = 2 * pl->n_bun;
     pl->sweep_blocks = (waves + kBlock / kWave - 1) / (kBlock / kWave);
     LC_CHECK(pl->sweep_blocks < INT32_MAX, LC_ERR_UNSUPPORTED, "sweep grid too large");
-    return LC_OK;
+    return sweep_lds_bytes(&pl->sweep_lds);
 }
 
 lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, double c_dt,
@@ -584,7 +615,18 @@ lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, doub
     A.P = r->n_pol;
     A.sym = r->sym ? 1 : 0;
     for (int p = 0; p < r->n_pol; ++p) A.inv_sinz[p] = r->inv_sinz[p];
-    return f32 ? launch_sweep_p<float>(pl, A, st) : launch_sweep_p<double>(pl, A, st);
+    rc = prof_begin(pl, pl->ev_sweep, st);
+    if (rc) return rc;
+    SweepCall c;
+    c.unroll = pl->sweep_unroll;
+    c.full = sweep_full(r);
+    c.lds = pl->sweep_lds;
+    c.st = st;
+    c.args1 = &A;
+    c.blocks = (unsigned)pl->sweep_blocks;
+    rc = f32 ? sweep_call_single<float>(r->n_pol, c) : sweep_call_single<double>(r->n_pol, c);
+    if (rc) return rc;
+    return prof_end(pl, pl->ev_sweep, st);
 }
 
 }  // namespace lc
