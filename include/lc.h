@@ -233,7 +233,8 @@ lc_status lc_step(lc_plan_t plan, int32_t n_steps, const double* kappa, const do
  * Launch tuning of a plan (chosen by the project's autotuner; any value works,
  * results are bit-identical across settings of moments_entries and
  * sweep_unroll).  sweep_unroll: steps of a characteristic whose loads are
- * in flight ahead of the arithmetic, 1, 2, 4 or 8; moments_entries: entries of each (cell,
+ * in flight ahead of the arithmetic, 1, 2, 4, 8 or 16 (16: LC_F32 plans with
+ * n_pol <= 4 only); moments_entries: entries of each (cell,
  * azimuth pair) list whose loads go through the moment kernel's pipeline, 1 to
  * 4 (longer lists finish in a plain loop).  Setting the tuning drops the plan's captured graphs.
  * Errors: LC_ERR_ARG for a null tuning or a value outside those sets (the

@@ -24,7 +24,7 @@ ARCH = os.environ.get("LC_OFFLOAD_ARCH", "gfx950")
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
-PER_FILE = {"geometry.hip": ["-ffp-contract=off"]}
+PER_FILE = {"geometry.hip": ["-ffp-contract=off"], "sweep.hip": ["-ffp-contract=off"]}
 
 
 def hipcc() -> str:

@@ -90,7 +90,7 @@ using namespace lc;
 
 extern "C" {
 
-int32_t lc_version(void) { return 1 * 10000 + 1 * 100 + 0; }
+int32_t lc_version(void) { return 1 * 10000 + 2 * 100 + 0; }
 
 const char* lc_last_error(void) { return g_err; }
 
@@ -406,8 +406,11 @@ lc_status lc_plan_set_tuning(lc_plan_t plan, const lc_tuning_t* t) {
     Plan* pl = as_plan(plan);
     LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
     LC_ARG(t, "tuning is NULL");
-    LC_ARG(t->sweep_unroll == 1 || t->sweep_unroll == 2 || t->sweep_unroll == 4 || t->sweep_unroll == 8,
-           "sweep_unroll must be 1, 2, 4 or 8");
+    LC_ARG(t->sweep_unroll == 1 || t->sweep_unroll == 2 || t->sweep_unroll == 4 || t->sweep_unroll == 8 ||
+               t->sweep_unroll == 16,
+           "sweep_unroll must be 1, 2, 4, 8 or 16");
+    LC_ARG(t->sweep_unroll != 16 || (pl->prec == LC_F32 && pl->rays->n_pol <= kMaxPolUnroll16),
+           "sweep_unroll 16 needs LC_F32 and n_pol <= %d", kMaxPolUnroll16);
     LC_ARG(t->moments_entries >= 1 && t->moments_entries <= 4, "moments_entries must be 1, 2, 3 or 4");
     pl->sweep_unroll = t->sweep_unroll;
     pl->moments_entries = t->moments_entries;

@@ -37,6 +37,7 @@ constexpr uint32_t kRaysMagic = 0x4c435259u;   // "LCRY"
 constexpr uint32_t kPlanMagic = 0x4c43504cu;   // "LCPL"
 constexpr uint32_t kBatchMagic = 0x4c434254u;  // "LCBT"
 constexpr int kMaxPol = 8;
+constexpr int kMaxPolUnroll16 = 4;               // sweep_unroll 16: float32 plans with n_pol up to this
 constexpr int kBlock = 256;                    // threads per block of the streaming kernels
 constexpr int kWave = 64;                      // lanes per wavefront (gfx9)
 constexpr int kDirW = 10;                      // per-direction weight record, see dirw_index

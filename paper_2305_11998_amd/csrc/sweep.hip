@@ -73,15 +73,31 @@ constexpr int kSweepBlocksPerCU = 2;
 
 template <typename T> struct Att { T E, D, al, be; };
 
+// This file is compiled without floating-point contraction: every fused
+// multiply-add is written out, so each instantiation (polar bound, chunk
+// length, branch-free or not, single or batched) rounds identically and the
+// results do not depend on the launch tuning.
+__device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // e^{-tau}, 1 - e^{-tau} and alpha of eq. (13) in float32: series below the
 // thresholds where the closed forms cancel, convex forms everywhere.
 __device__ __forceinline__ Att<float> attenuate(float tau) {
     const float E = __expf(-tau);
-    const float Ds = tau * (1.f - tau * (0.5f - tau * (1.f / 6.f - tau * (1.f / 24.f - tau * (1.f / 120.f - tau * (1.f / 720.f - tau * (1.f / 5040.f)))))));
-    const float D = tau < 0.25f ? Ds : 1.f - E;
+    float p = fma_(-tau, 1.f / 5040.f, 1.f / 720.f);          // (1 - e^{-tau}) / tau, Horner in -tau
+    p = fma_(-tau, p, 1.f / 120.f);
+    p = fma_(-tau, p, 1.f / 24.f);
+    p = fma_(-tau, p, 1.f / 6.f);
+    p = fma_(-tau, p, 0.5f);
+    p = fma_(-tau, p, 1.f);
+    const float D = tau < 0.25f ? tau * p : 1.f - E;
     const float t2 = tau * tau;
-    const float as = 0.5f - tau * (1.f / 12.f - t2 * (1.f / 720.f - t2 * (1.f / 30240.f - t2 * (1.f / 1209600.f - t2 * (1.f / 47900160.f)))));
-    const float ac = (D - tau * E) * __builtin_amdgcn_rcpf(tau * D);
+    float q = fma_(-t2, 1.f / 47900160.f, 1.f / 1209600.f);  // alpha = 1/2 - tau/12 + tau^3/720 - ...
+    q = fma_(-t2, q, 1.f / 30240.f);
+    q = fma_(-t2, q, 1.f / 720.f);
+    q = fma_(-t2, q, 1.f / 12.f);
+    const float as = fma_(-tau, q, 0.5f);
+    const float ac = fma_(-tau, E, D) * __builtin_amdgcn_rcpf(tau * D);
     const float al = tau < 1.f ? as : ac;
     return {E, D, al, 1.f - al};
 }
@@ -89,14 +105,25 @@ __device__ __forceinline__ Att<float> attenuate(float tau) {
 // Same in float64 (series below tau = 0.1).
 __device__ __forceinline__ Att<double> attenuate(double tau) {
     const double E = exp(-tau);
-    const double Ds = tau * (1.0 - tau * (1.0 / 2 - tau * (1.0 / 6 - tau * (1.0 / 24 - tau * (1.0 / 120 - tau * (1.0 / 720 - tau * (1.0 / 5040 - tau * (1.0 / 40320 - tau * (1.0 / 362880 - tau * (1.0 / 3628800))))))))));
+    double p = fma_(-tau, 1.0 / 3628800, 1.0 / 362880);
+    p = fma_(-tau, p, 1.0 / 40320);
+    p = fma_(-tau, p, 1.0 / 5040);
+    p = fma_(-tau, p, 1.0 / 720);
+    p = fma_(-tau, p, 1.0 / 120);
+    p = fma_(-tau, p, 1.0 / 24);
+    p = fma_(-tau, p, 1.0 / 6);
+    p = fma_(-tau, p, 1.0 / 2);
+    p = fma_(-tau, p, 1.0);
     const bool small = tau < 0.1;
-    const double D = small ? Ds : 1.0 - E;
+    const double D = small ? tau * p : 1.0 - E;
     const double t2 = tau * tau;
-    const double as = 0.5 - tau * (1.0 / 12 - t2 * (1.0 / 720 - t2 * (1.0 / 30240 - t2 * (1.0 / 1209600))));
+    double q = fma_(-t2, 1.0 / 1209600, 1.0 / 30240);
+    q = fma_(-t2, q, 1.0 / 720);
+    q = fma_(-t2, q, 1.0 / 12);
+    const double as = fma_(-tau, q, 0.5);
     double al;
     if (small) al = as;
-    else al = (D - tau * E) / (tau * D);
+    else al = fma_(-tau, E, D) / (tau * D);
     return {E, D, al, 1.0 - al};
 }
 
@@ -292,9 +319,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
             for (int q = 0; q < NS; ++q) {
                 ob[q] = (T)0;
                 if (!val[q]) continue;
-                const T S = c0[u].a + b * x0[u][q];                   // Q / kappa_t
-                const T Io = at[q].E * I[q] + at[q].D * S;            // eq. (12)
-                ob[q] = at[q].al * I[q] + at[q].be * Io;              // segment average
+                const T S = fma_(b, x0[u][q], c0[u].a);               // Q / kappa_t
+                const T Io = fma_(at[q].E, I[q], at[q].D * S);        // eq. (12)
+                ob[q] = fma_(at[q].al, I[q], at[q].be * Io);          // segment average
                 I[q] = live ? Io : I[q];
             }
             if (FULL ? t < L : live) {
@@ -421,6 +448,12 @@ lc_status sweep_call_u(const SweepCall& c) {
         case 1: return sweep_call<BATCH, T, PM, 1, FULL>(c);
         case 2: return sweep_call<BATCH, T, PM, 2, FULL>(c);
         case 4: return sweep_call<BATCH, T, PM, 4, FULL>(c);
+        case 16:
+            // 16-step chunks fit the registers of two wavefronts per SIMD in
+            // float32 with up to four polar angles only
+            if constexpr (sizeof(T) == 4 && PM <= kMaxPolUnroll16) return sweep_call<BATCH, T, PM, 16, FULL>(c);
+            set_error("sweep_unroll 16 needs float32 and n_pol <= %d", kMaxPolUnroll16);
+            return LC_ERR_UNSUPPORTED;
         default: return sweep_call<BATCH, T, PM, 8, FULL>(c);
     }
 }

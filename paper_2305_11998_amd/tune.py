@@ -19,6 +19,8 @@ import os
 from . import lc
 
 SWEEP_CANDIDATES = (2, 4, 8)
+SWEEP_CANDIDATES_F32 = (2, 4, 8, 16)   # 16: float32 with at most MAX_POL_UNROLL16 polar angles
+MAX_POL_UNROLL16 = 4
 MOMENT_CANDIDATES = (1, 2, 3, 4)
 BASE = (4, 3)             # the setting the other parameter is held at while one is searched
 DEFAULT_CACHE = os.environ.get(
@@ -51,6 +53,12 @@ def _save(path, data):
         pass
 
 
+def sweep_candidates(prec: int, n_pol: int):
+    """The sweep_unroll values the library accepts for this precision and
+    polar count, in search order."""
+    return SWEEP_CANDIDATES_F32 if prec == lc.LC_F32 and n_pol <= MAX_POL_UNROLL16 else SWEEP_CANDIDATES
+
+
 def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool = False):
     """Pick (sweep_unroll, moments_entries) for ``solver.plan`` by timing
     ``reps`` eager steps per candidate.  Leaves the chosen tuning set on the
@@ -65,7 +73,8 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
         return dict(t, cached=True, key=key)
     times = {}
     # the two parameters act on different kernels: vary one with the other fixed
-    combos = sorted({(u, BASE[1]) for u in SWEEP_CANDIDATES} | {(BASE[0], e) for e in MOMENT_CANDIDATES})
+    ucands = sweep_candidates(plan.prec, plan.rays.n_pol)
+    combos = sorted({(u, BASE[1]) for u in ucands} | {(BASE[0], e) for e in MOMENT_CANDIDATES})
     for u, e in combos:
         lc.lc_plan_set_tuning(plan, u, e)
         solver.bench_step()                       # warm
@@ -81,7 +90,7 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
         if verbose:
             print(f"  tune {key}: unroll {u} entries {e}: sweep {times[(u, e)][0]:.3f} ms, "
                   f"moments {times[(u, e)][1]:.3f} ms", file=sys.stderr, flush=True)
-    best_u = min(SWEEP_CANDIDATES, key=lambda u: times[(u, BASE[1])][0])
+    best_u = min(ucands, key=lambda u: times[(u, BASE[1])][0])
     best_e = min(MOMENT_CANDIDATES, key=lambda e: times[(BASE[0], e)][1])
     lc.lc_plan_set_tuning(plan, best_u, best_e)
     res = dict(sweep_unroll=best_u, moments_entries=best_e,
@@ -115,7 +124,8 @@ def tune_batch(bs, steps: int = 2, verbose: bool = False):
 
     times = {}
     for pm in classes:
-        for k, cands in ((0, SWEEP_CANDIDATES), (1, MOMENT_CANDIDATES)):
+        ucands = sweep_candidates(bs.solvers[0].plan.prec, pm)
+        for k, cands in ((0, ucands), (1, MOMENT_CANDIDATES)):
             res = {}
             for v in cands:
                 cfg = {c: list(x) for c, x in best.items()}

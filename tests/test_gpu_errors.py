@@ -54,13 +54,19 @@ def test_plan_create_rejects_group_count_and_precision(env):
 def test_tuning_rejects_out_of_range_values_and_keeps_the_old_setting(env):
     lc, driver, s = env
     lc.lc_plan_set_tuning(s.plan, 4, 2)
-    for u, e, needle in [(3, 2, "sweep_unroll"), (16, 2, "sweep_unroll"), (0, 2, "sweep_unroll"),
+    for u, e, needle in [(3, 2, "sweep_unroll"), (32, 2, "sweep_unroll"), (0, 2, "sweep_unroll"),
                          (4, 0, "moments_entries"), (4, 5, "moments_entries")]:
         _say(f"set_tuning {u} {e}")
         t = lc.lc_tuning_t(u, e)
         _expect(lc, lc._lib.lc_plan_set_tuning(s.plan.handle, C.byref(t)), lc.LC_ERR_ARG, needle)
         assert lc.lc_plan_get_tuning(s.plan) == dict(sweep_unroll=4, moments_entries=2)
     _expect(lc, lc._lib.lc_plan_set_tuning(s.plan.handle, None), lc.LC_ERR_ARG, "tuning")
+    # 16-step chunks: float32 only
+    p64 = lc.Plan(s.rays, 3, lc.LC_F64)
+    t = lc.lc_tuning_t(16, 2)
+    _expect(lc, lc._lib.lc_plan_set_tuning(p64.handle, C.byref(t)), lc.LC_ERR_ARG, "sweep_unroll 16")
+    lc.lc_plan_set_tuning(s.plan, 16, 2)
+    assert lc.lc_plan_get_tuning(s.plan) == dict(sweep_unroll=16, moments_entries=2)
 
 
 def test_sweep_moments_and_step_reject_bad_arguments(env):

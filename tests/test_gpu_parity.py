@@ -187,13 +187,20 @@ def test_graph_equals_eager_and_is_deterministic(lcmod):
         assert np.array_equal(st, out[0][1])
 
 
-@pytest.mark.parametrize("prec,mode,h_moc", [(1, 0, 0.04), (1, 1, 0.04), (0, 0, 0.015)])
-def test_tuning_settings_give_identical_results(lcmod, prec, mode, h_moc):
+@pytest.mark.parametrize("prec,mode,h_moc,n_pol", [(1, 0, 0.04, 3), (1, 1, 0.04, 3), (0, 0, 0.015, 3),
+                                                  (1, 0, 0.04, 4), (0, 0, 0.04, 2)])
+def test_tuning_settings_give_identical_results(lcmod, prec, mode, h_moc, n_pol):
     """Every launch tuning gives bit-identical moments, boundary factors and
     state.  Tube grids and fine spacing make (cell, pair) lists longer than the
-    moment kernel's pipelined slots, so its tail loop is covered too."""
+    moment kernel's pipelined slots, so its tail loop is covered too.  Three
+    polar angles run the sweep with per-angle branches, 2 and 4 (symmetric
+    Gauss-Legendre sets) the branch-free form; 16-step chunks exist in
+    float32 only."""
     lc, driver = lcmod
-    prob = _custom_problem(h_moc=h_moc, steps=2)
+    mu = w = None
+    if n_pol != 3:
+        mu, w = np.polynomial.legendre.leggauss(n_pol)
+    prob = _custom_problem(h_moc=h_moc, steps=2, mu=mu, w=w)
     s = driver.Solver(prob, prec=prec, mode=mode)
     ro, so, ce, _, _, _ = lc.lc_rays_export(s.rays)
     longest = max(int(np.bincount(ce[so[ro[a]]:so[ro[a + 1]]]).max()) for a in range(len(ro) - 1))
@@ -201,7 +208,8 @@ def test_tuning_settings_give_identical_results(lcmod, prec, mode, h_moc):
     if mode == 1 or h_moc < 0.02:
         assert longest > 4                      # the tail loop runs
     out = []
-    for u, e in [(2, 3), (1, 1), (4, 2), (2, 4), (1, 3)]:
+    settings = [(2, 3), (1, 1), (4, 2), (2, 4), (1, 3), (8, 2)] + ([(16, 1), (16, 3)] if prec == 1 else [])
+    for u, e in settings:
         _say(f"case tuning prec={prec} mode={mode} h_moc={h_moc}: unroll {u} entries {e}")
         lc.lc_plan_set_tuning(s.plan, u, e)
         s.reset()
