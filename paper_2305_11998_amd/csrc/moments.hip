@@ -142,7 +142,6 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
     const int cy = (int)(tile / A.tiles_x) * A.th + cl / A.tw;
     if (cx >= A.nx || cy >= A.ny) return;
     const int cell = cy * A.nx + cx;
-    const int cells = A.nx * A.ny;
     const int np = A.n_pairs;
     const gptr<const T> st = as_global(static_cast<const T*>(A.state));
     const gptr<const T> cw = as_global(static_cast<const T*>(A.csr_w));
