@@ -185,6 +185,37 @@ def cpu_baseline(prob, budget_s=12.0):
                        f"{done_upd} updates in {t_used:.1f} s; numpy on one host thread)")
 
 
+def time_grey_closures(s, reps=20):
+    """lc_grey_closures on the solver's last moments: mean launch time
+    (events on the stream it runs on), its algorithmic bytes (7 moment and 2
+    material values per (cell, group) read, 13 fields per cell written) and
+    the oracle's time on the same inputs (one host thread)."""
+    import torch
+    from oracle import closures as oc
+    from paper_2305_11998_amd import lc
+    p = s.prob
+    G, cells = p.G, p.cells
+    kap, pla = s.kappa.view(-1)[:G * cells], s.planck.view(-1)[:G * cells]
+    out = torch.empty(lc.N_GREY * cells, dtype=torch.float64, device="cuda")
+    lc.lc_grey_closures(s.plan, s.E, s.F, s.f, kap, pla, out)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        lc.lc_grey_closures(s.plan, s.E, s.F, s.f, kap, pla, out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nbytes = (9 * G + lc.N_GREY) * cells * 8
+    m = s.moments()
+    t0 = time.perf_counter()
+    oc.grey_closures(m["E"], m["F"], m["f"], p.kappa[0], p.planck[0])
+    cpu_ms = (time.perf_counter() - t0) * 1e3
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"kernel": "k_grey_closures", "ms": ms, "algorithmic_bytes": nbytes, "achieved": gbs,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "cpu_oracle_ms": cpu_ms}
+
+
 def run_single(k, steps, warmup):
     """One problem of the named workloads (workloads.config(k)) on the plain
     path, float32 and float64: eager steps timed with the library's kernel
@@ -213,7 +244,9 @@ def run_single(k, steps, warmup):
         lc.lc_plan_profile(s.plan, False)
         s.reset()
         s.step(1)
+        grey = time_grey_closures(s) if prec == lc.LC_F32 else None
         out[name] = dict(ms=e0.elapsed_time(e1) / steps, sweep_ms=sw / max(nsw, 1), moments_ms=mo / max(nmo, 1),
+                         grey=grey,
                          upd=s.updates_per_step(), moments=s.moments(),
                          alg=sweep_algorithmic_bytes(s, 4 if prec == lc.LC_F32 else 8),
                          tuning={kk: tuned[kk] for kk in ("sweep_unroll", "moments_entries")})
@@ -245,6 +278,7 @@ def main_single(args):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_sweep<float,P,U>",
                      "kernel_ms": f32["sweep_ms"], "moments_kernel_ms": f32["moments_ms"],
                      "algorithmic_bytes_per_launch": f32["alg"]},
+        "grey_closures": f32["grey"],
     }
     print(json.dumps(res), flush=True)
 

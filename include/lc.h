@@ -212,6 +212,29 @@ lc_status lc_moments(lc_plan_t plan, const void* state, const double* I_exit,
                      double* bnd, void* stream);
 
 /*
+ * lc_grey_closures -- cell-local closures of the effective grey problem,
+ * eq. (8)-(9), from the multigroup cell moments of this plan (as written by
+ * lc_moments or lc_step) and the opacity and Planck source of the step:
+ *   out[13][cells] = E, F_x, F_y (sums over the groups), <kappa>_E,
+ *   <kappa>_B, K_R,xx = <kappa>_|F_x|, K_R,yy = <kappa>_|F_y|, eta_x, eta_y,
+ *   <f>_E (xx, xy, yy, zz), where
+ *   <u>_E = sum_g u_g E_g / sum_g E_g,  <u>_B = sum_g u_g B_g / sum_g B_g
+ *   (the mean that closes the emission term of eq. (5a) when a_R T^4 is read
+ *   as (4 pi / c) sum_g B_g), <u>_|F_a| = sum_g u_g |F_a,g| / sum_g |F_a,g|,
+ *   eta_a = sum_g (kappa_g - K_R,aa) F_a,g / sum_g E_g, <f>_E =
+ *   sum_g f_g E_g / sum_g E_g; the group sums are deterministic (a fixed
+ *   order over the groups, the same in every call).
+ *   A zero denominator takes a fallback: <kappa>_E -> <kappa>_B -> the mean
+ *   of kappa_g over the groups; <kappa>_B and <kappa>_|F_a| -> <kappa>_E;
+ *   with sum E = 0, eta = 0 and <f>_E = 1/3 on the diagonal.
+ * E, F, f: float64 in the cell-major layout of lc_moments; kappa, planck:
+ * float64 [G][cells]; out: float64, caller-owned.  Allocates nothing.
+ * Errors: LC_ERR_ARG (null pointer), LC_ERR_HIP.
+ */
+lc_status lc_grey_closures(lc_plan_t plan, const double* E, const double* F, const double* f,
+                           const double* kappa, const double* planck, double* out, void* stream);
+
+/*
  * lc_step -- n_steps backward-Euler time steps (sweep, then moments) with the
  * state ping-ponging between state_a and state_b: step t reads the state
  * written by step t-1 (step 0 reads state_a); after an odd number of steps

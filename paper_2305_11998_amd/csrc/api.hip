@@ -345,6 +345,14 @@ lc_status lc_moments(lc_plan_t plan, const void* state, const double* I_exit, co
     return launch_moments(pl, state, I_exit, I_in, c, E, F, f, bnd, static_cast<hipStream_t>(stream));
 }
 
+lc_status lc_grey_closures(lc_plan_t plan, const double* E, const double* F, const double* f,
+                           const double* kappa, const double* planck, double* out, void* stream) {
+    Plan* pl = as_plan(plan);
+    LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
+    LC_ARG(E && F && f && kappa && planck && out, "E, F, f, kappa, planck and out must not be NULL");
+    return launch_grey_closures(pl, E, F, f, kappa, planck, out, static_cast<hipStream_t>(stream));
+}
+
 lc_status lc_step(lc_plan_t plan, int32_t n_steps, const double* kappa, const double* planck,
                   int64_t material_stride, double c_dt, double c, void* state_a, void* state_b,
                   const double* I_in, double* I_exit, double* E, double* F, double* f, double* bnd,

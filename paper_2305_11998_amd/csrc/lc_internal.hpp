@@ -212,6 +212,8 @@ lc_status launch_sweep_batch(int prec, int pm, int unroll, bool full, size_t lds
 lc_status launch_moments_batch(int prec, int pm, int ent, const void* args, const int2* items, int64_t n_items,
                                hipStream_t st);
 lc_status launch_boundary_batch(const void* args, int n, int64_t blocks, hipStream_t st);
+lc_status launch_grey_closures(const Plan* pl, const double* E, const double* F, const double* f,
+                               const double* kappa, const double* planck, double* out, hipStream_t st);
 
 // Device pointers to the values of a state buffer (after its header).
 inline const void* state_values(const Plan* pl, const void* s) {

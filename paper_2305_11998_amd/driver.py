@@ -99,6 +99,18 @@ class Solver:
         return {k: getattr(self, k).view(cells, n, G).permute(2, 1, 0)
                 for k, n in (("E", 1), ("F", 2), ("f", 4))}
 
+    def grey_closures(self):
+        """Grey closures (lc_grey_closures) of the moments left by the last
+        step, with that step's opacity and Planck source: [13][cells]."""
+        p = self.prob
+        G, cells = p.G, p.cells
+        t = max(self.t - 1, 0)
+        off = t * self.stride
+        out = torch.empty(lc.N_GREY * cells, dtype=torch.float64, device="cuda")
+        lc.lc_grey_closures(self.plan, self.E, self.F, self.f, self.kappa.view(-1)[off:off + G * cells],
+                            self.planck.view(-1)[off:off + G * cells], out)
+        return out.cpu().numpy().reshape(lc.N_GREY, cells)
+
     def state_canonical(self):
         out = torch.empty(self.plan.n_state, dtype=torch.float64, device="cuda")
         lc.lc_state_export(self.plan, self.state[self.cur], out)

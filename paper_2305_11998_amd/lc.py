@@ -76,6 +76,7 @@ _SIGS = {
     "lc_sweep": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_moments": ([_vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_step": ([_vp, _i32, _vp, _vp, _i64, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "lc_grey_closures": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_plan_set_tuning": ([_vp, C.POINTER(lc_tuning_t)], C.c_int),
     "lc_plan_get_tuning": ([_vp, C.POINTER(lc_tuning_t)], C.c_int),
     "lc_plan_profile": ([_vp, _i32], C.c_int),
@@ -259,6 +260,19 @@ def lc_moments(plan: Plan, state, c, E=None, F=None, f=None, bnd=None, I_exit=No
                            _dev(F, 2 * plan.n_field, name="F", optional=True),
                            _dev(f, 4 * plan.n_field, name="f", optional=True),
                            _dev(bnd, plan.G * r.nb * 8, name="bnd", optional=True), _stream(stream)))
+
+
+N_GREY = 13     # fields of lc_grey_closures, [N_GREY][cells]
+
+
+def lc_grey_closures(plan: Plan, E, F, f, kappa, planck, out, stream=None):
+    """Grey closures of every cell from the plan's cell moments (cell-major
+    E, F, f as written by lc_moments) and [G][cells] kappa, planck."""
+    n = plan.n_field
+    _check(_lib.lc_grey_closures(plan.handle, _dev(E, n, name="E"), _dev(F, 2 * n, name="F"),
+                                 _dev(f, 4 * n, name="f"), _dev(kappa, n, name="kappa"),
+                                 _dev(planck, n, name="planck"), _dev(out, N_GREY * plan.rays.cells, name="out"),
+                                 _stream(stream)))
 
 
 def lc_plan_set_tuning(plan: Plan, sweep_unroll: int, moments_entries: int):
