@@ -53,6 +53,8 @@ struct Batch {
     int max_G = 1;
     std::vector<GraphEntry> graphs;
     hipStream_t capture = nullptr;
+    hipStream_t side = nullptr;         // captured side branch (boundary factors, next prologue)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool profile = false;               // eager steps with events around each phase
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];   // prologue, sweep, moments
 };
@@ -92,23 +94,43 @@ lc_status ev_end(Batch* b, int k, hipStream_t st) {
 // other (with the phase timers when profiling).  Running the polar groups
 // on streams of their own was measured slower: their kernels contend for the
 // same caches and bandwidth rather than filling each other's tails.
+//
+// In a captured graph (no profiling) the work that does not feed the moments
+// runs on a side branch beside them, joined before the next step's sweep:
+// the boundary factors of step t (they need only the exit intensities) and
+// the prologue of step t + 1 (queue counters, source maxima, coefficient
+// table and the scale of the state that step t consumed -- nothing the
+// moments of step t read).
 lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
     const size_t sb = sweep_args_bytes(), mb = mom_args_bytes();
+    const bool branch = !b->profile;
+    auto prologue = [&](int t, hipStream_t s) {
+        lc_status rc = launch_zero_counters(b->d_counters, 8 * (int)b->cls.size(), s);
+        if (rc == LC_OK) rc = ev_begin(b, 0, s);
+        if (rc == LC_OK)
+            rc = launch_prologue_batch(b->prec, b->d_coef_args, b->n, b->max_blocks, b->coef_blocks, b->max_G,
+                                       b->d_gmax, b->n_gmax, t, s);
+        if (rc == LC_OK) rc = ev_end(b, 0, s);
+        return rc;
+    };
     lc_status rc = LC_OK;
     for (int t = 0; t < n_steps && rc == LC_OK; ++t) {
         const int parity = t & 1;
-        rc = launch_zero_counters(b->d_counters, 8 * (int)b->cls.size(), st);
-        if (rc == LC_OK) rc = ev_begin(b, 0, st);
-        if (rc == LC_OK)
-            rc = launch_prologue_batch(b->prec, b->d_coef_args, b->n, b->max_blocks, b->coef_blocks, b->max_G,
-                                       b->d_gmax, b->n_gmax, t, st);
-        if (rc == LC_OK) rc = ev_end(b, 0, st);
+        if (t == 0 || !branch) rc = prologue(t, st);  // later steps: on the previous step's branch
         if (rc == LC_OK) rc = ev_begin(b, 1, st);
         for (size_t c = 0; c < b->cls.size() && rc == LC_OK; ++c)
             rc = launch_sweep_batch(b->prec, b->cls[c].pm, b->cls[c].unroll, b->cls[c].full, b->cls[c].sweep_lds,
                                     b->cls[c].sweep_grid, static_cast<char*>(b->d_sweep_args) + parity * b->n * sb,
                                     b->cls[c].d_sweep_items, b->cls[c].d_sweep_qb, b->d_counters + 8 * c, st);
         if (rc == LC_OK) rc = ev_end(b, 1, st);
+        const bool side = branch && (b->bnd_blocks > 0 || t + 1 < n_steps);
+        if (rc == LC_OK && side) {
+            if (hipEventRecord(b->ev_fork, st) != hipSuccess || hipStreamWaitEvent(b->side, b->ev_fork, 0) != hipSuccess)
+                rc = LC_ERR_HIP;
+            if (rc == LC_OK && b->bnd_blocks > 0) rc = launch_boundary_batch(b->d_bnd_args, b->n, b->bnd_blocks, b->side);
+            if (rc == LC_OK && t + 1 < n_steps) rc = prologue(t + 1, b->side);
+            if (rc == LC_OK && hipEventRecord(b->ev_join, b->side) != hipSuccess) rc = LC_ERR_HIP;
+        }
         if (rc == LC_OK) {                            // every step forms its moments
             rc = ev_begin(b, 2, st);
             for (size_t c = 0; c < b->cls.size() && rc == LC_OK; ++c)
@@ -116,7 +138,9 @@ lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
                                           static_cast<char*>(b->d_mom_args) + parity * b->n * mb,
                                           b->cls[c].d_mom_items, b->cls[c].n_mom_items, st);
             if (rc == LC_OK) rc = ev_end(b, 2, st);
-            if (rc == LC_OK && b->bnd_blocks > 0) rc = launch_boundary_batch(b->d_bnd_args, b->n, b->bnd_blocks, st);
+            if (rc == LC_OK && !branch && b->bnd_blocks > 0)
+                rc = launch_boundary_batch(b->d_bnd_args, b->n, b->bnd_blocks, st);
+            if (rc == LC_OK && side && hipStreamWaitEvent(st, b->ev_join, 0) != hipSuccess) rc = LC_ERR_HIP;
         }
     }
     return rc;
@@ -133,6 +157,9 @@ void free_batch(Batch* b) {
     for (auto& g : b->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (b->capture) (void)hipStreamDestroy(b->capture);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     for (void* p : {b->d_sweep_args, b->d_coef_args, b->d_mom_args, b->d_bnd_args,
                     static_cast<void*>(b->d_counters), static_cast<void*>(b->d_gmax)})
         if (p) (void)hipFree(p);
@@ -333,6 +360,9 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
     if (rc == LC_OK) rc = build_moment_args(b, 1.0);
     if (rc == LC_OK) {
         hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
         if (e != hipSuccess) {
             set_error("hipStreamCreate failed: %s", hipGetErrorString(e));
             rc = LC_ERR_HIP;

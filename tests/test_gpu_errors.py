@@ -97,6 +97,8 @@ def test_sweep_moments_and_step_reject_bad_arguments(env):
     _expect(lc, step(stride=-1), lc.LC_ERR_ARG, "material_stride")
     _expect(lc, step(c=0.0), lc.LC_ERR_ARG, "c_dt and c")
     _expect(lc, step(iex=None), lc.LC_ERR_ARG, "I_exit")
+    _say("grey closures: null output")
+    _expect(lc, L.lc_grey_closures(pl, E, F, f, k, B, None, None), lc.LC_ERR_ARG, "out")
 
 
 def test_plan_still_works_after_rejected_calls(env):
