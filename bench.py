@@ -283,10 +283,64 @@ def main_single(args):
     print(json.dumps(res), flush=True)
 
 
+def main_refinement(args):
+    """Characteristic-grid refinement at fixed material grid, transport only:
+    the paper's vertex-avoiding, width-halving grid with h_moc = h_mat / r,
+    r = 8, 16, ..., on a Fleck-Cummings-like slab (6 x 6 cm, 1 keV Planckian
+    entering at x = 0, opacity 27/nu^3 (1 - e^{-nu/T}), 17 groups, 36 x 4
+    directions), one backward-Euler step (c dt = 0.6 cm, the paper's 0.02 ns)
+    through a prescribed temperature profile T(x) = 1 keV e^{-x / 1 cm} + 1 eV.
+    Reports ||Delta E|| = || E_{h_moc} - E_{h_moc / 2} || (grey E, area-weighted
+    L2 over the cells) and rho = ||Delta E_{h}|| / ||Delta E_{h/2}||, with the
+    characteristic counts and step times."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2305_11998_amd import driver, lc
+    L = 6.0
+    rows = []
+    for n, ratios in ((10, (8, 16, 32, 64, 128, 256, 512)), (40, (8, 16, 32, 64, 128))):
+        h = L / n
+        x = (np.arange(n) + 0.5) * h
+        T = np.tile(1.0 * np.exp(-x / 1.0) + 0.001, n)          # cell i = iy * n + ix
+        prev = None
+        for r in ratios:
+            prob = W.make_problem(n, n, L, L, 36, 4, 17, 0.001, 30.0, h / r, 0.6, [T], name=f"fc{n}")
+            s = driver.Solver(prob, prec=lc.LC_F64, mode=lc.LC_RAYS_TUBES)
+            s.reset()
+            s.step(1, graph=False)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.reset()
+            e0.record()
+            s.step(1, graph=False)
+            e1.record()
+            torch.cuda.synchronize()
+            E = s.moments()["E"].sum(axis=0)                        # grey E per cell
+            row = {"h_mat": h, "ratio": r, "h_moc": h / r, "characteristics": int(s.rays.n_rays),
+                   "segments": int(s.rays.n_segments), "step_ms": e0.elapsed_time(e1),
+                   "norm_E": float(np.sqrt(np.sum(E ** 2) * h * h))}
+            if prev is not None:
+                d = float(np.sqrt(np.sum((E - prev) ** 2) * h * h))
+                row["dE"] = d
+                row["dE_rel"] = d / row["norm_E"]
+                if "dE" in rows[-1]:
+                    row["rho"] = rows[-1]["dE"] / d if d > 0 else None
+            rows.append(row)
+            prev = E
+            _say(f"h_mat {h:.3f} ratio {r}: {row['characteristics']} characteristics, "
+                 f"{row['segments']} segments, {row['step_ms']:.2f} ms, dE {row.get('dE', float('nan')):.3e}, "
+                 f"rho {row.get('rho') or float('nan'):.2f}")
+            del s
+            torch.cuda.empty_cache()
+    print(json.dumps({"workload": "characteristic-grid refinement (tube mode), transport only", "rows": rows}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("batch", "single"), default="batch",
+    ap.add_argument("--workload", choices=("batch", "single", "refinement"), default="batch",
                     help="batch: the 64-problem batched form (default); single: one problem of --config")
     ap.add_argument("--config", type=int, default=2, help="workload index for --workload single (0, 1, 2 or 4)")
     ap.add_argument("--steps", type=int, default=10)
@@ -314,6 +368,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         _say(f"copied 3 x {n * 4} bytes")
+        return
+    if args.workload == "refinement":
+        main_refinement(args)
         return
     if args.workload == "single":
         main_single(args)
