@@ -63,7 +63,7 @@ def direction_index(a, d, p, n_az, n_pol):
 
 
 def sweep_pair(grid, a, mu, kappa, planck, c_dt, state_prev, I_in, rays=None,
-               local_state=False):
+               local_state=False, points=None):
     """Sweep both directions of azimuth pair a, all polar angles and groups.
 
     kappa, planck: [G][cells]; state_prev: canonical [n_seg][2][P][G] (only
@@ -71,7 +71,10 @@ def sweep_pair(grid, a, mu, kappa, planck, c_dt, state_prev, I_in, rays=None,
     optionally limits the sweep to a subset of characteristics (for sampled
     checks); with ``local_state`` the state rows are indexed like the
     returned rows (only the chosen rays' segments, in their order) instead of
-    by global segment index.  Returns (j [n], rows [n][2][P][G],
+    by global segment index.  ``points`` ([n_seg][2][P][G], optional)
+    receives the intensity entering each segment in each traversal (the
+    value at its upwind face, I_{k,s} of eq. (12) and (16)).  Returns
+    (j [n], rows [n][2][P][G],
     I_exit [2][K'][P][G], ray ids) where j are the global indices of the
     swept segments.
     """
@@ -108,6 +111,8 @@ def sweep_pair(grid, a, mu, kappa, planck, c_dt, state_prev, I_in, rays=None,
             kt = kap_t[:, cell].T[:, None, :]               # [k][1][G]
             row_prev = (local[kk] + s) if local_state else (first[kk] + s)
             Q = emis[:, cell].T[:, None, :] + state_prev[row_prev, d] / c_dt
+            if points is not None:
+                points[first[kk] + s, d] = I[kk]
             I_out, I_bar = segment_step(I[kk], kt, Q, ln[:, None, None],
                                         sin_zeta[None, :, None])
             rows[local[kk] + s, d] = I_bar
@@ -116,14 +121,15 @@ def sweep_pair(grid, a, mu, kappa, planck, c_dt, state_prev, I_in, rays=None,
     return jglob, rows, I_exit, ks
 
 
-def sweep(grid, mu, kappa, planck, c_dt, state_prev, I_in):
+def sweep(grid, mu, kappa, planck, c_dt, state_prev, I_in, points=None):
     """Full sweep: every pair, both directions, all polar angles and groups.
-    Returns (state_new [n_seg][2][P][G], I_exit list per pair [2][K][P][G])."""
+    Returns (state_new [n_seg][2][P][G], I_exit list per pair [2][K][P][G]);
+    ``points`` as for sweep_pair."""
     state_new = np.zeros_like(state_prev)
     exits = []
     for a in range(len(grid.pairs)):
         j, rows, I_exit, _ = sweep_pair(grid, a, mu, kappa, planck, c_dt,
-                                        state_prev, I_in)
+                                        state_prev, I_in, points=points)
         state_new[j] = rows
         exits.append(I_exit)
     return state_new, exits
