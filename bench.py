@@ -216,6 +216,40 @@ def time_grey_closures(s, reps=20):
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS, "cpu_oracle_ms": cpu_ms}
 
 
+def time_faces(s, reps=5):
+    """Interior-face moments of eq. (16) on the solver's problem: the sweep
+    that also stores the upwind-face intensities and the face gather
+    (lc_face_moments), mean times over `reps` launches.  The gather's
+    algorithmic bytes: the stored intensities read once (one value per
+    segment update) plus its outputs (7 doubles per face and group)."""
+    import torch
+    from paper_2305_11998_amd import lc
+    p = s.prob
+    s.enable_faces()
+    s.reset()
+    kap, pla = s.kappa.view(-1), s.planck.view(-1)
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    lc.lc_sweep_points(s.plan, kap, pla, p.c_dt, s.state[0], s.state[1], s.I_in, s.points, s.I_exit)
+    torch.cuda.synchronize()
+    e[0].record()
+    for _ in range(reps):
+        lc.lc_sweep_points(s.plan, kap, pla, p.c_dt, s.state[0], s.state[1], s.I_in, s.points, s.I_exit)
+    e[1].record()
+    for _ in range(reps):
+        lc.lc_face_moments(s.plan, s.points, s.state[1], s.c, s.Ef, s.Ff, s.ff)
+    e[2].record()
+    torch.cuda.synchronize()
+    sweep_ms = e[0].elapsed_time(e[1]) / reps
+    face_ms = e[1].elapsed_time(e[2]) / reps
+    nf = lc.n_interior_faces(s.rays)
+    elem = 4 if s.prec == lc.LC_F32 else 8
+    nbytes = s.updates_per_step() * elem + 7 * nf * p.G * 8
+    gbs = nbytes / (face_ms * 1e-3) / 1e9
+    return {"kernel": "k_cell_moments over the interior-face lists", "sweep_with_points_ms": sweep_ms,
+            "face_moments_ms": face_ms, "faces": nf, "algorithmic_bytes": nbytes, "achieved": gbs,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+
+
 def run_single(k, steps, warmup):
     """One problem of the named workloads (workloads.config(k)) on the plain
     path, float32 and float64: eager steps timed with the library's kernel
@@ -250,6 +284,7 @@ def run_single(k, steps, warmup):
                          upd=s.updates_per_step(), moments=s.moments(),
                          alg=sweep_algorithmic_bytes(s, 4 if prec == lc.LC_F32 else 8),
                          tuning={kk: tuned[kk] for kk in ("sweep_unroll", "moments_entries")})
+        out[name]["faces"] = time_faces(s) if prec == lc.LC_F32 else None     # after the moments above
         _say(f"config {k} {name}: {out[name]['ms']:.3f} ms/step, sweep {out[name]['sweep_ms']:.3f} ms, "
              f"moments {out[name]['moments_ms']:.3f} ms")
         del s
@@ -279,6 +314,7 @@ def main_single(args):
                      "kernel_ms": f32["sweep_ms"], "moments_kernel_ms": f32["moments_ms"],
                      "algorithmic_bytes_per_launch": f32["alg"]},
         "grey_closures": f32["grey"],
+        "interior_faces": f32["faces"],
     }
     print(json.dumps(res), flush=True)
 

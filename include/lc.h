@@ -212,6 +212,47 @@ lc_status lc_moments(lc_plan_t plan, const void* state, const double* I_exit,
                      double* bnd, void* stream);
 
 /*
+ * Interior faces, eq. (16): the face-average moments on every interior face
+ * of the material grid, from the intensities at the faces' crossings with
+ * the characteristics (I_{k,s} at the upwind face of each segment).
+ *
+ * lc_plan_enable_faces -- build the interior-face crossing lists F(f, m)
+ * (kept with the characteristic grid, shared by its plans) and this plan's
+ * records of them.  Allocates; synchronises `stream`.  A crossing is where
+ * two consecutive segments lie in cells that share a face; a passage
+ * through a vertex (diagonal neighbours) crosses no face interior and is
+ * left out.  Faces: x-faces (x = ix hx, 1 <= ix < nx) of row iy are numbered
+ * iy (nx - 1) + ix - 1, then y-faces (y = iy hy, 1 <= iy < ny) of column ix
+ * follow at (nx - 1) ny + (iy - 1) nx + ix.  Errors: LC_ERR_ALLOC,
+ * LC_ERR_STATE (crossings that do not form contiguous runs), LC_ERR_HIP.
+ *
+ * lc_sweep_points -- lc_sweep that also stores, in `points` (a buffer of
+ * lc_state_bytes, same layout as the state), the intensity entering every
+ * segment in each traversal.  Same results in state_new and I_exit as
+ * lc_sweep.  Errors as lc_sweep, and LC_ERR_ARG for a NULL or aliased
+ * points buffer.
+ *
+ * lc_face_moments -- per interior face f and group: the width-weighted mean
+ * of the crossing intensities of each direction, I_{f,m} = sum w_k I / sum
+ * w_k over F(f, m) (read per direction, as for the boundary faces; a
+ * direction with no crossing contributes nothing), then E_f = sum_m omega_m
+ * I_{f,m} / c, F_f = sum_m omega_m Omega_m I_{f,m}, f_f = sum_m omega_m
+ * Omega_m Omega_m I_{f,m} / (c E_f) (1/3 on the diagonal where E_f = 0).
+ * points: as written by lc_sweep_points; state: the state_new of that sweep
+ * (its header holds the scale of the stored values).  Outputs (float64, any
+ * may be NULL), face-major like lc_moments: E[faces][G], F[faces][2][G],
+ * f[faces][4][G], faces = (nx - 1) ny + nx (ny - 1).  Needs
+ * lc_plan_enable_faces (LC_ERR_STATE otherwise); LC_ERR_ARG for NULL
+ * points/state or c <= 0.
+ */
+lc_status lc_plan_enable_faces(lc_plan_t plan, void* stream);
+lc_status lc_sweep_points(lc_plan_t plan, const double* kappa, const double* planck, double c_dt,
+                          const void* state_prev, void* state_new, const double* I_in, double* I_exit,
+                          void* points, void* stream);
+lc_status lc_face_moments(lc_plan_t plan, const void* points, const void* state, double c, double* E, double* F,
+                          double* f, void* stream);
+
+/*
  * lc_grey_closures -- cell-local closures of the effective grey problem,
  * eq. (8)-(9), from the multigroup cell moments of this plan (as written by
  * lc_moments or lc_step) and the opacity and Planck source of the step:

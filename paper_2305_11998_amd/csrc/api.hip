@@ -54,6 +54,7 @@ void free_plan(Plan* pl) {
     if (pl->d_bun_len) (void)hipFree(pl->d_bun_len);
     if (pl->d_bun_base) (void)hipFree(pl->d_bun_base);
     if (pl->d_ent_off) (void)hipFree(pl->d_ent_off);
+    if (pl->d_fent_off) (void)hipFree(pl->d_fent_off);
     if (pl->d_bun_rec) (void)hipFree(pl->d_bun_rec);
     pl->magic = 0;
     delete pl;
@@ -90,7 +91,7 @@ using namespace lc;
 
 extern "C" {
 
-int32_t lc_version(void) { return 1 * 10000 + 2 * 100 + 0; }
+int32_t lc_version(void) { return 1 * 10000 + 3 * 100 + 0; }
 
 const char* lc_last_error(void) { return g_err; }
 
@@ -343,6 +344,35 @@ lc_status lc_moments(lc_plan_t plan, const void* state, const double* I_exit, co
     LC_ARG(finite_pos(c), "c must be finite and > 0");
     LC_ARG(!bnd || (I_exit && I_in), "boundary factors need I_exit and I_in");
     return launch_moments(pl, state, I_exit, I_in, c, E, F, f, bnd, static_cast<hipStream_t>(stream));
+}
+
+lc_status lc_plan_enable_faces(lc_plan_t plan, void* stream) {
+    Plan* pl = as_plan(plan);
+    LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
+    return plan_enable_faces(pl, static_cast<hipStream_t>(stream));
+}
+
+lc_status lc_sweep_points(lc_plan_t plan, const double* kappa, const double* planck, double c_dt,
+                          const void* state_prev, void* state_new, const double* I_in, double* I_exit,
+                          void* points, void* stream) {
+    Plan* pl = as_plan(plan);
+    LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
+    LC_ARG(kappa && planck && state_prev && state_new && I_in && points,
+           "kappa, planck, states, I_in and points must not be NULL");
+    LC_ARG(state_prev != state_new && points != state_prev && points != state_new,
+           "state_prev, state_new and points must be distinct buffers");
+    LC_ARG(finite_pos(c_dt), "c_dt must be finite and > 0");
+    return launch_sweep(pl, kappa, planck, c_dt, state_prev, state_new, I_in, I_exit,
+                        static_cast<hipStream_t>(stream), points);
+}
+
+lc_status lc_face_moments(lc_plan_t plan, const void* points, const void* state, double c, double* E, double* F,
+                          double* f, void* stream) {
+    Plan* pl = as_plan(plan);
+    LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
+    LC_ARG(points && state, "points and state must not be NULL");
+    LC_ARG(finite_pos(c), "c must be finite and > 0");
+    return launch_face_moments(pl, points, state, c, E, F, f, static_cast<hipStream_t>(stream));
 }
 
 lc_status lc_grey_closures(lc_plan_t plan, const double* E, const double* F, const double* f,

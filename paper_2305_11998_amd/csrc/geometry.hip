@@ -389,6 +389,80 @@ __global__ void k_tube_fill(const double* __restrict__ distinct, int64_t m, cons
 
 inline unsigned nblk(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
+// ---- interior-face crossing lists F(f, m) ---------------------------------------
+// The face shared by the cells of two consecutive segments, or -1 when they
+// are diagonal neighbours (a passage through a vertex crosses no face).
+__device__ __forceinline__ int face_of_step(int nx, int ny, int c0, int c1) {
+    const int iy0 = c0 / nx, ix0 = c0 - iy0 * nx;
+    const int iy1 = c1 / nx, ix1 = c1 - iy1 * nx;
+    if (iy0 == iy1 && (ix1 - ix0 == 1 || ix0 - ix1 == 1)) return iy0 * (nx - 1) + min(ix0, ix1);
+    if (ix0 == ix1 && (iy1 - iy0 == 1 || iy0 - iy1 == 1)) return (nx - 1) * ny + min(iy0, iy1) * nx + ix0;
+    return -1;
+}
+
+__global__ void k_fcsr_count(const int* __restrict__ ray_off, int n_pairs, int n_rays,
+                             const int* __restrict__ seg_off, const int* __restrict__ cell, int nx, int ny,
+                             int* cnt, int* kfirst) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_rays) return;
+    int a = find_pair(ray_off, n_pairs, k);
+    int kl = k - ray_off[a];
+    for (int j = seg_off[k] + 1; j < seg_off[k + 1]; ++j) {
+        const int f = face_of_step(nx, ny, cell[j - 1], cell[j]);
+        if (f < 0) continue;
+        const int64_t key = (int64_t)f * n_pairs + a;
+        atomicAdd(&cnt[key], 1);
+        atomicMin(&kfirst[key], kl);
+    }
+}
+
+// Characteristics of one direction crossing a face form a contiguous run of
+// k; the position of ray k in the face's list is k - kfirst.
+__global__ void k_fcsr_fill(const int* __restrict__ ray_off, int n_pairs, int n_rays,
+                            const int* __restrict__ seg_off, const int* __restrict__ cell, int nx, int ny,
+                            const double* __restrict__ width, const int* __restrict__ off,
+                            const int* __restrict__ kfirst, int* ray, int2* t, double* w, int* err) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_rays) return;
+    int a = find_pair(ray_off, n_pairs, k);
+    int kl = k - ray_off[a];
+    const int nk = seg_off[k + 1] - seg_off[k];
+    for (int j = seg_off[k] + 1; j < seg_off[k + 1]; ++j) {
+        const int f = face_of_step(nx, ny, cell[j - 1], cell[j]);
+        if (f < 0) continue;
+        const int64_t key = (int64_t)f * n_pairs + a;
+        const int pos = off[key] + (kl - kfirst[key]);
+        if (pos >= off[key + 1]) {
+            atomicOr(err, 4);
+            continue;
+        }
+        const int s = j - seg_off[k];
+        ray[pos] = k;
+        t[pos] = make_int2(s, nk - s);
+        w[pos] = width[k];
+    }
+}
+
+// Normalise each (face, pair) list's widths; a list entry left unfilled
+// (a gap in the run of characteristics) is an error.
+__global__ void k_fcsr_norm(const int* __restrict__ off, int64_t n_keys, const int* __restrict__ ray, double* w,
+                            float* w32, int* err) {
+    int64_t key = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (key >= n_keys) return;
+    const int b = off[key], e = off[key + 1];
+    double sum = 0.0;
+    for (int q = b; q < e; ++q) {
+        if (ray[q] < 0) atomicOr(err, 8);
+        sum += w[q];
+    }
+    for (int q = b; q < e; ++q) {
+        const double v = sum > 0.0 ? w[q] / sum : 0.0;
+        w[q] = v;
+        w32[q] = (float)v;
+    }
+}
+
+
 lc_status scan_counts(const int* in, int* out, int64_t n, std::vector<void*>& tmp, hipStream_t st) {
     int64_t tiles = (n + kScanTile - 1) / kScanTile;
     if (tiles == 0) tiles = 1;
@@ -621,6 +695,105 @@ lc_status build_geometry(Rays* r, hipStream_t st) {
 #undef LC_STEP
 #undef LC_HIPC
 #undef LC_CHECKC
+}
+
+lc_status build_face_lists(Rays* r, hipStream_t st) {
+    std::vector<void*> tmp;
+    auto cleanup = [&]() {
+        for (void* p : tmp) (void)hipFree(p);
+        tmp.clear();
+    };
+    lc_status rc = LC_OK;
+#define LC_STEP(x)               \
+    do {                         \
+        rc = (x);                \
+        if (rc) { cleanup(); return rc; } \
+    } while (0)
+#define LC_HIPC(x)                                                          \
+    do {                                                                    \
+        hipError_t e_ = (x);                                                \
+        if (e_ != hipSuccess) {                                             \
+            set_error("%s failed: %s", #x, hipGetErrorString(e_));          \
+            cleanup();                                                      \
+            return LC_ERR_HIP;                                              \
+        }                                                                   \
+    } while (0)
+    const int P = r->n_pairs;
+    const int nr = (int)r->n_rays;
+    const int64_t n_keys = std::max<int64_t>(n_interior_faces(r) * P, 1);
+    int *d_cnt = nullptr, *d_kfirst = nullptr, *d_err = nullptr, *d_off = nullptr;
+    LC_STEP(dalloc(tmp, &d_cnt, n_keys));
+    LC_STEP(dalloc(tmp, &d_kfirst, n_keys));
+    LC_STEP(dalloc(tmp, &d_err, 1));
+    LC_STEP(dalloc(tmp, &d_off, n_keys + 1));
+    hipLaunchKernelGGL(k_fill_int, dim3(nblk(n_keys)), dim3(kBlock), 0, st, d_cnt, n_keys, 0);
+    hipLaunchKernelGGL(k_fill_int, dim3(nblk(n_keys)), dim3(kBlock), 0, st, d_kfirst, n_keys, INT_MAX);
+    hipLaunchKernelGGL(k_fill_int, dim3(1), dim3(kBlock), 0, st, d_err, 1, 0);
+    hipLaunchKernelGGL(k_fcsr_count, dim3(nblk(nr)), dim3(kBlock), 0, st, r->d_ray_off, P, nr, r->d_seg_off,
+                       r->d_cell, r->nx, r->ny, d_cnt, d_kfirst);
+    LC_HIPC(hipGetLastError());
+    LC_STEP(scan_counts(d_cnt, d_off, n_keys, tmp, st));
+    int total = 0;
+    LC_HIPC(hipMemcpyAsync(&total, d_off + n_keys, sizeof(int), hipMemcpyDeviceToHost, st));
+    LC_HIPC(hipStreamSynchronize(st));
+    const int64_t ne = std::max(total, 1);
+    std::vector<void*> fresh;
+    auto drop = [&]() {
+        for (void* p : fresh) (void)hipFree(p);
+        fresh.clear();
+    };
+    int* off = nullptr;
+    int* ray = nullptr;
+    int2* tt = nullptr;
+    double* w = nullptr;
+    float* w32 = nullptr;
+    rc = dalloc(fresh, &off, n_keys + 1);
+    if (rc == LC_OK) rc = dalloc(fresh, &ray, ne);
+    if (rc == LC_OK) rc = dalloc(fresh, &tt, ne);
+    if (rc == LC_OK) rc = dalloc(fresh, &w, ne);
+    if (rc == LC_OK) rc = dalloc(fresh, &w32, ne);
+    if (rc) {
+        drop();
+        cleanup();
+        return rc;
+    }
+    auto fail = [&](lc_status code) {
+        drop();
+        cleanup();
+        return code;
+    };
+    if (hipMemcpyAsync(off, d_off, (n_keys + 1) * sizeof(int), hipMemcpyDeviceToDevice, st) != hipSuccess)
+        return fail(LC_ERR_HIP);
+    hipLaunchKernelGGL(k_fill_int, dim3(nblk(ne)), dim3(kBlock), 0, st, ray, ne, -1);
+    hipLaunchKernelGGL(k_fcsr_fill, dim3(nblk(nr)), dim3(kBlock), 0, st, r->d_ray_off, P, nr, r->d_seg_off,
+                       r->d_cell, r->nx, r->ny, r->d_width, off, d_kfirst, ray, tt, w, d_err);
+    hipLaunchKernelGGL(k_fcsr_norm, dim3(nblk(n_keys)), dim3(kBlock), 0, st, off, n_keys, ray, w, w32, d_err);
+    if (hipGetLastError() != hipSuccess) {
+        set_error("face list kernels failed to launch");
+        return fail(LC_ERR_HIP);
+    }
+    int err = 0;
+    if (hipMemcpyAsync(&err, d_err, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        set_error("face list build failed");
+        return fail(LC_ERR_HIP);
+    }
+    if (err) {
+        set_error("interior-face crossings do not form contiguous runs (flags %d)", err);
+        return fail(LC_ERR_STATE);
+    }
+    for (void* p : fresh) r->owned.push_back(p);
+    fresh.clear();
+    r->n_fent = total;
+    r->d_fcsr_off = off;
+    r->d_fcsr_ray = ray;
+    r->d_fcsr_t = tt;
+    r->d_fcsr_w = w;
+    r->d_fcsr_w32 = w32;
+    cleanup();
+    return LC_OK;
+#undef LC_STEP
+#undef LC_HIPC
 }
 
 }  // namespace lc

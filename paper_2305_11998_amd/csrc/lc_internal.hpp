@@ -82,6 +82,14 @@ struct Rays {
     float2* d_gf32 = nullptr;
     int* d_bmap = nullptr;            // [nb][n_pairs][2][2] first, end global ray leaving through b; -1 = incoming
     double* d_dirw = nullptr;         // [n_pairs][2][n_pol][kDirW]
+    // interior-face crossing lists, built on request (lc_plan_enable_faces):
+    // x-faces first ((nx-1) * ny, row-major), then y-faces (nx * (ny-1))
+    int64_t n_fent = 0;               // crossings over all pairs
+    int* d_fcsr_off = nullptr;        // [n_ifaces * n_pairs + 1], index face * n_pairs + a
+    int* d_fcsr_ray = nullptr;        // [n_fent] global ray k
+    int2* d_fcsr_t = nullptr;         // [n_fent] {s, nk - s}: steps of the segments entered there (d = 0, 1)
+    double* d_fcsr_w = nullptr;       // [n_fent] w_k / sum of w over the (face, pair) list
+    float* d_fcsr_w32 = nullptr;
     std::vector<void*> owned;         // every device allocation above
 };
 
@@ -128,6 +136,7 @@ struct Plan {
     int* d_bun_len = nullptr;
     int64_t* d_bun_base = nullptr;
     unsigned* d_ent_off = nullptr;    // [n_seg][4] state lane records (P values each) of each C(i, m) entry
+    unsigned* d_fent_off = nullptr;   // [n_fent][4] the same for the interior-face crossings (on request)
     unsigned* d_bun_rec = nullptr;    // [n_bun] first lane record of each bundle
     int tile_w = 1, tile_h = 1;       // cell tile of the moments kernel
     int64_t sweep_blocks = 0;         // blocks of one sweep launch
@@ -171,7 +180,7 @@ lc_status dalloc(std::vector<void*>& owned, T** out, size_t n) {
 // Internal launchers (stream-ordered, no allocation, no synchronisation).
 lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, double c_dt,
                        const void* state_prev, void* state_new, const double* I_in,
-                       double* I_exit, hipStream_t st);
+                       double* I_exit, hipStream_t st, void* point = nullptr);
 lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, const double* I_in,
                          double c, double* E, double* F, double* f, double* bnd, hipStream_t st);
 lc_status launch_state_fill(Plan* pl, const double* field, void* state, hipStream_t st);
@@ -179,6 +188,9 @@ lc_status launch_state_export(Plan* pl, const void* state, double* out, hipStrea
 lc_status build_geometry(Rays* r, hipStream_t st);
 lc_status plan_init_sweep(Plan* pl);
 lc_status plan_init_moments(Plan* pl);
+lc_status plan_enable_faces(Plan* pl, hipStream_t st);
+lc_status launch_face_moments(Plan* pl, const void* point, const void* state, double c, double* E, double* F,
+                              double* f, hipStream_t st);
 
 // Batched form: argument records (built on the host, copied to the device)
 // and launchers of the persistent kernels.
@@ -212,6 +224,8 @@ lc_status launch_sweep_batch(int prec, int pm, int unroll, bool full, size_t lds
 lc_status launch_moments_batch(int prec, int pm, int ent, const void* args, const int2* items, int64_t n_items,
                                hipStream_t st);
 lc_status launch_boundary_batch(const void* args, int n, int64_t blocks, hipStream_t st);
+lc_status build_face_lists(Rays* r, hipStream_t st);
+inline int64_t n_interior_faces(const Rays* r) { return (int64_t)(r->nx - 1) * r->ny + (int64_t)r->nx * (r->ny - 1); }
 lc_status launch_grey_closures(const Plan* pl, const double* E, const double* F, const double* f,
                                const double* kappa, const double* planck, double* out, hipStream_t st);
 

@@ -497,6 +497,81 @@ lc_status plan_init_moments(Plan* pl) {
     return LC_OK;
 }
 
+// Interior-face crossing lists of a plan: the geometry's lists (built once
+// per characteristic grid) and their state lane records for this plan.
+lc_status plan_enable_faces(Plan* pl, hipStream_t st) {
+    Rays* r = pl->rays;
+    if (!r->d_fcsr_off) {
+        lc_status rc = build_face_lists(r, st);
+        if (rc) return rc;
+    }
+    if (pl->d_fent_off) return LC_OK;
+    const int64_t n_keys = n_interior_faces(r) * r->n_pairs;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&pl->d_fent_off),
+                             std::max<size_t>((size_t)r->n_fent, 1) * 4 * sizeof(unsigned));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        pl->d_fent_off = nullptr;
+        set_error("hipMalloc of the face offsets failed: %s", hipGetErrorString(e));
+        return LC_ERR_ALLOC;
+    }
+    if (n_keys > 0) {
+        hipLaunchKernelGGL(k_entry_offsets, dim3((unsigned)((n_keys + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                           r->d_fcsr_off, r->d_fcsr_ray, r->d_fcsr_t, r->d_ray_off, pl->d_bun_off, pl->d_bun_base,
+                           n_keys, r->n_pairs, pl->G, r->n_pol, pl->half_elems, pl->d_fent_off);
+        LC_HIP(hipGetLastError());
+    }
+    LC_HIP(hipStreamSynchronize(st));
+    return LC_OK;
+}
+
+// Face averages of eq. (16) on the interior faces: the cell-moment gather run
+// over the face crossing lists, on the stored upwind-face intensities.  The
+// x-faces ((nx-1) x ny) and the y-faces (nx x (ny-1)) are two grids of their
+// own.
+lc_status launch_face_moments(Plan* pl, const void* point, const void* state, double c, double* E, double* F,
+                              double* f, hipStream_t st) {
+    Rays* r = pl->rays;
+    LC_CHECK(pl->d_fent_off, LC_ERR_STATE, "interior faces are not enabled on this plan (lc_plan_enable_faces)");
+    const bool f32 = pl->prec == LC_F32;
+    const int G = pl->G;
+    for (int part = 0; part < 2; ++part) {
+        const int fnx = part == 0 ? r->nx - 1 : r->nx;
+        const int fny = part == 0 ? r->ny : r->ny - 1;
+        if (fnx < 1 || fny < 1) continue;
+        const int64_t face0 = part == 0 ? 0 : (int64_t)(r->nx - 1) * r->ny;
+        MomArgs A{};
+        A.csr_off = r->d_fcsr_off + face0 * r->n_pairs;
+        A.ent_off = pl->d_fent_off;
+        A.bun_rec = pl->d_bun_rec;
+        A.half_rec = (unsigned)(pl->half_elems / r->n_pol);
+        A.multi = G > kWave ? 1 : 0;
+        A.csr_w = f32 ? static_cast<const void*>(r->d_fcsr_w32) : static_cast<const void*>(r->d_fcsr_w);
+        A.dirw = r->d_dirw;
+        A.state = state_values(pl, point);
+        A.e = static_cast<const int*>(state);        // the scale of the values the sweep stored
+        A.nx = fnx;
+        A.ny = fny;
+        A.P = r->n_pol;
+        const int cells_max = std::max(1, kTileWaves * kWave / G);
+        A.tw = std::max(1, std::min({16, cells_max, fnx}));
+        A.th = std::max(1, std::min({16, cells_max / A.tw, fny}));
+        A.tiles_x = (fnx + A.tw - 1) / A.tw;
+        A.n_tiles = (int64_t)A.tiles_x * ((fny + A.th - 1) / A.th);
+        A.wpt = (A.tw * A.th * G + kWave - 1) / kWave;
+        A.G = G;
+        A.n_pairs = r->n_pairs;
+        A.inv_c = 1.0 / c;
+        A.E = E ? E + face0 * G : nullptr;
+        A.F = F ? F + face0 * 2 * G : nullptr;
+        A.f = f ? f + face0 * 4 * G : nullptr;
+        lc_status rc = f32 ? launch_cell_moments_p<float>(r->n_pol, pl->moments_entries, A, st)
+                           : launch_cell_moments_p<double>(r->n_pol, pl->moments_entries, A, st);
+        if (rc) return rc;
+    }
+    return LC_OK;
+}
+
 lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, const double* I_in,
                          double c, double* E, double* F, double* f, double* bnd, hipStream_t st) {
     Rays* r = pl->rays;

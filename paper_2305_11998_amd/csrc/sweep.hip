@@ -36,6 +36,7 @@ struct SweepArgs {
     const void* coef;        // Coef<T> [cells][G]
     const void* prev;        // state values
     void* next;
+    void* point;             // values entering each segment, state layout, or null
     const double* I_in;      // [nb][M][G]
     double* I_exit;          // [n_rays][2][P][G] or null
     int P;                   // polar angles
@@ -70,6 +71,7 @@ __device__ __forceinline__ int find_pair(gptr<const int> off, int n, int64_t v) 
 // were measured to make the sweep slower (the caches serve fewer streams
 // better).
 constexpr int kSweepBlocksPerCU = 2;
+constexpr int kPointUnroll = 4;       // chunk length of the sweep that also stores upwind intensities
 
 template <typename T> struct Att { T E, D, al, be; };
 
@@ -181,7 +183,10 @@ __device__ __forceinline__ void stg_stream(gptr<T> p, T v) { __builtin_nontempor
 // batched launches share the polar bound P).  A FULL wavefront also stores
 // every row of its bundle: the rows past the end of a lane's characteristic
 // are that lane's padding, which nothing reads.
-template <typename T, int PM, int U, bool FULL>
+//
+// POINT: also store the intensity entering each segment (the value at its
+// upwind face) into A.point, in the state layout.
+template <typename T, int PM, int U, bool FULL, bool POINT = false>
 __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int lane) {
     constexpr int NL = (PM + 1) / 2, NU = PM / 2, NS = NL + NU;
     const int d = w >= A.n_bun ? 1 : 0;
@@ -212,6 +217,8 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
     const size_t boff = (size_t)d * A.half + (size_t)as_global(A.bun_base)[B] + (size_t)lane * P;
     const gptr<const T> xin = as_global(static_cast<const T*>(A.prev) + boff);
     const gptr<T> xout = as_global_w(static_cast<T*>(A.next) + boff);
+    // optional: the intensity entering each segment (its upwind-face value)
+    const gptr<T> pout = as_global_w(static_cast<T*>(POINT ? A.point : A.next) + boff);
     const size_t SP = (size_t)P * kWave;       // elements per step of a bundle ([lane][p])
     // a lane's P values of one step are contiguous: with P == PM (a power of
     // two) they move as one vector load or store
@@ -270,6 +277,22 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
         }
     };
 
+    // the values of one step from the polar slots
+    auto store_row = [&](gptr<T> o, const T (&x)[NS]) {
+        if (vec) {
+            V v;
+#pragma unroll
+            for (int i = 0; i < NL; ++i) v[i] = x[i];
+#pragma unroll
+            for (int i = 0; i < NU; ++i) v[PM - 1 - i] = x[NL + i];
+            __builtin_nontemporal_store(v, (gptr<V>)o);
+        } else {
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                if (val[q]) stg_stream(o + pol[q], x[q]);
+        }
+    };
+
     // of each segment record the sweep needs the cell index and the length only
     const gptr<const int> gcell = (gptr<const int>)gi;
     const gptr<const T> glen = (gptr<const T>)gf;
@@ -313,11 +336,11 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
 #pragma unroll
             for (int i = 0; i < NU; ++i)
                 if (val[NL + i]) at[NL + i] = sym ? at[i] : attenuate(ktl * isz[NL + i]);
-            const gptr<T> o = xout + (size_t)t * SP;
-            T ob[NS];
+            T ob[NS], ib[NS];
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
                 ob[q] = (T)0;
+                ib[q] = I[q];
                 if (!val[q]) continue;
                 const T S = fma_(b, x0[u][q], c0[u].a);               // Q / kappa_t
                 const T Io = fma_(at[q].E, I[q], at[q].D * S);        // eq. (12)
@@ -325,18 +348,8 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
                 I[q] = live ? Io : I[q];
             }
             if (FULL ? t < L : live) {
-                if (vec) {
-                    V v;
-#pragma unroll
-                    for (int i = 0; i < NL; ++i) v[i] = ob[i];
-#pragma unroll
-                    for (int i = 0; i < NU; ++i) v[PM - 1 - i] = ob[NL + i];
-                    __builtin_nontemporal_store(v, (gptr<V>)o);
-                } else {
-#pragma unroll
-                    for (int q = 0; q < NS; ++q)
-                        if (val[q]) stg_stream(o + pol[q], ob[q]);
-                }
+                store_row(xout + (size_t)t * SP, ob);
+                if (POINT) store_row(pout + (size_t)t * SP, ib);
             }
         }
 #pragma unroll
@@ -357,12 +370,12 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
     }
 }
 
-template <typename T, int PM, int U, bool FULL>
+template <typename T, int PM, int U, bool FULL, bool POINT>
 __global__ __launch_bounds__(kBlock) void k_sweep(SweepArgs A) {
     const int64_t lb = xcd_logical_block(blockIdx.x, A.n_blocks);
     const int64_t w = lb * (kBlock / kWave) + (threadIdx.x / kWave);
     if (w >= 2 * A.n_bun) return;
-    sweep_wave<T, PM, U, FULL>(A, w, threadIdx.x & (kWave - 1));
+    sweep_wave<T, PM, U, FULL, POINT>(A, w, threadIdx.x & (kWave - 1));
 }
 
 // Batched form: a persistent grid whose wavefronts take work items
@@ -408,6 +421,7 @@ __global__ void k_zero_counter(int* c, int n) {
 struct SweepCall {
     int unroll = 8;
     bool full = false;
+    bool point = false;       // single problems: store the upwind intensities too
     size_t lds = 0;
     hipStream_t st = nullptr;
     const SweepArgs* args1 = nullptr;
@@ -420,10 +434,10 @@ struct SweepCall {
     int* grid_out = nullptr;
 };
 
-template <bool BATCH, typename T, int PM, int U, bool FULL>
+template <bool BATCH, typename T, int PM, int U, bool FULL, bool POINT = false>
 lc_status sweep_call(const SweepCall& c) {
     if constexpr (!BATCH) {
-        hipLaunchKernelGGL((k_sweep<T, PM, U, FULL>), dim3(c.blocks), dim3(kBlock), c.lds, c.st, *c.args1);
+        hipLaunchKernelGGL((k_sweep<T, PM, U, FULL, POINT>), dim3(c.blocks), dim3(kBlock), c.lds, c.st, *c.args1);
     } else if (c.grid_out) {
         // as many blocks as the device keeps resident, a multiple of 8 so
         // that every XCD gets the same count
@@ -444,6 +458,9 @@ lc_status sweep_call(const SweepCall& c) {
 
 template <bool BATCH, typename T, int PM, bool FULL>
 lc_status sweep_call_u(const SweepCall& c) {
+    // the upwind-intensity form has one chunk length (results do not depend on it)
+    if constexpr (!BATCH)
+        if (c.point) return sweep_call<BATCH, T, PM, kPointUnroll, FULL, true>(c);
     switch (c.unroll) {
         case 1: return sweep_call<BATCH, T, PM, 1, FULL>(c);
         case 2: return sweep_call<BATCH, T, PM, 2, FULL>(c);
@@ -612,7 +629,7 @@ lc_status plan_init_sweep(Plan* pl) {
 
 lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, double c_dt,
                        const void* state_prev, void* state_new, const double* I_in, double* I_exit,
-                       hipStream_t st) {
+                       hipStream_t st, void* point) {
     Rays* r = pl->rays;
     const int G = pl->G;
     const bool f32 = pl->prec == LC_F32;
@@ -636,6 +653,7 @@ lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, doub
     A.coef = pl->d_coef;
     A.prev = state_values(pl, state_prev);
     A.next = state_values(pl, state_new);
+    A.point = point ? state_values(pl, point) : nullptr;
 
     A.I_in = I_in;
     A.I_exit = I_exit;
@@ -653,6 +671,7 @@ lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, doub
     SweepCall c;
     c.unroll = pl->sweep_unroll;
     c.full = sweep_full(r);
+    c.point = point != nullptr;
     c.lds = pl->sweep_lds;
     c.st = st;
     c.args1 = &A;

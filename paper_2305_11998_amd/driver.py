@@ -72,6 +72,45 @@ class Solver:
         self.cur = (self.cur + n) % 2
         self.t += n
 
+    def enable_faces(self):
+        """Interior-face lists on the plan, a buffer for the upwind-face
+        intensities and the face outputs."""
+        lc.lc_plan_enable_faces(self.plan)
+        G = self.prob.G
+        nf = lc.n_interior_faces(self.rays)
+        self.points = self.plan.new_state()
+        self.Ef = torch.zeros(nf * G, dtype=torch.float64, device="cuda")
+        self.Ff = torch.zeros(2 * nf * G, dtype=torch.float64, device="cuda")
+        self.ff = torch.zeros(4 * nf * G, dtype=torch.float64, device="cuda")
+
+    def step_faces(self, n=1):
+        """Like step(n, graph=False), storing the upwind-face intensities of
+        every sweep; leaves the last step's cell and interior-face moments."""
+        p = self.prob
+        t0 = self.t
+        if t0 + n > p.steps:
+            raise ValueError("not enough material steps")
+        off = t0 * self.stride
+        kap = self.kappa.view(-1)[off:]
+        pla = self.planck.view(-1)[off:]
+        for t in range(n):
+            o = t * self.stride
+            lc.lc_sweep_points(self.plan, kap[o:], pla[o:], p.c_dt, self.state[(self.cur + t) % 2],
+                               self.state[(self.cur + t + 1) % 2], self.I_in, self.points, self.I_exit)
+        new = self.state[(self.cur + n) % 2]
+        lc.lc_moments(self.plan, new, self.c, self.E, self.F, self.f, self.bnd, self.I_exit, self.I_in)
+        lc.lc_face_moments(self.plan, self.points, new, self.c, self.Ef, self.Ff, self.ff)
+        self.cur = (self.cur + n) % 2
+        self.t += n
+
+    def face_moments(self):
+        """Interior-face E [G][faces], F [G][2][faces], f [G][4][faces]."""
+        G = self.prob.G
+        nf = lc.n_interior_faces(self.rays)
+        return dict(E=self.Ef.cpu().numpy().reshape(nf, G).T,
+                    F=self.Ff.cpu().numpy().reshape(nf, 2, G).transpose(2, 1, 0),
+                    f=self.ff.cpu().numpy().reshape(nf, 4, G).transpose(2, 1, 0))
+
     def bench_step(self):
         """One step with the first step's material data (for timing): eager
         sweep then moments, state ping-pong."""

@@ -77,6 +77,9 @@ _SIGS = {
     "lc_moments": ([_vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_step": ([_vp, _i32, _vp, _vp, _i64, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_grey_closures": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "lc_plan_enable_faces": ([_vp, _vp], C.c_int),
+    "lc_sweep_points": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "lc_face_moments": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp], C.c_int),
     "lc_plan_set_tuning": ([_vp, C.POINTER(lc_tuning_t)], C.c_int),
     "lc_plan_get_tuning": ([_vp, C.POINTER(lc_tuning_t)], C.c_int),
     "lc_plan_profile": ([_vp, _i32], C.c_int),
@@ -260,6 +263,31 @@ def lc_moments(plan: Plan, state, c, E=None, F=None, f=None, bnd=None, I_exit=No
                            _dev(F, 2 * plan.n_field, name="F", optional=True),
                            _dev(f, 4 * plan.n_field, name="f", optional=True),
                            _dev(bnd, plan.G * r.nb * 8, name="bnd", optional=True), _stream(stream)))
+
+
+def n_interior_faces(rays) -> int:
+    return (rays.nx - 1) * rays.ny + rays.nx * (rays.ny - 1)
+
+
+def lc_plan_enable_faces(plan: Plan, stream=None):
+    _check(_lib.lc_plan_enable_faces(plan.handle, _stream(stream)))
+
+
+def lc_sweep_points(plan: Plan, kappa, planck, c_dt, state_prev, state_new, I_in, points, I_exit=None, stream=None):
+    _check(_lib.lc_sweep_points(plan.handle, _dev(kappa, plan.n_field, name="kappa"),
+                                _dev(planck, plan.n_field, name="planck"), float(c_dt),
+                                _bytes(state_prev, plan.state_bytes, "state_prev"),
+                                _bytes(state_new, plan.state_bytes, "state_new"), _dev(I_in, plan.n_in, name="I_in"),
+                                _dev(I_exit, plan.n_exit, name="I_exit", optional=True),
+                                _bytes(points, plan.state_bytes, "points"), _stream(stream)))
+
+
+def lc_face_moments(plan: Plan, points, state, c, E=None, F=None, f=None, stream=None):
+    n = n_interior_faces(plan.rays) * plan.G
+    _check(_lib.lc_face_moments(plan.handle, _bytes(points, plan.state_bytes, "points"),
+                                _bytes(state, plan.state_bytes, "state"), float(c),
+                                _dev(E, n, name="E", optional=True), _dev(F, 2 * n, name="F", optional=True),
+                                _dev(f, 4 * n, name="f", optional=True), _stream(stream)))
 
 
 N_GREY = 13     # fields of lc_grey_closures, [N_GREY][cells]
