@@ -274,6 +274,12 @@ lc_status lc_face_moments(lc_plan_t plan, const void* points, const void* state,
  */
 lc_status lc_grey_closures(lc_plan_t plan, const double* E, const double* F, const double* f,
                            const double* kappa, const double* planck, double* out, void* stream);
+/* The same with explicit sizes, for moments gathered from several plans (for
+ * instance groups swept on characteristic grids of their own): E, F, f in the
+ * cell-major layout of lc_moments over all G groups.  LC_ERR_ARG for cells or
+ * G < 1 or a NULL pointer. */
+lc_status lc_grey_closures_dims(int32_t cells, int32_t G, const double* E, const double* F, const double* f,
+                                const double* kappa, const double* planck, double* out, void* stream);
 
 /*
  * lc_step -- n_steps backward-Euler time steps (sweep, then moments) with the

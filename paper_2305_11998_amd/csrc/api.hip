@@ -383,6 +383,13 @@ lc_status lc_grey_closures(lc_plan_t plan, const double* E, const double* F, con
     return launch_grey_closures(pl, E, F, f, kappa, planck, out, static_cast<hipStream_t>(stream));
 }
 
+lc_status lc_grey_closures_dims(int32_t cells, int32_t G, const double* E, const double* F, const double* f,
+                                const double* kappa, const double* planck, double* out, void* stream) {
+    LC_ARG(cells >= 1 && G >= 1, "cells and G must be >= 1 (got %d, %d)", cells, G);
+    LC_ARG(E && F && f && kappa && planck && out, "E, F, f, kappa, planck and out must not be NULL");
+    return launch_grey_closures_dims(cells, G, E, F, f, kappa, planck, out, static_cast<hipStream_t>(stream));
+}
+
 lc_status lc_step(lc_plan_t plan, int32_t n_steps, const double* kappa, const double* planck,
                   int64_t material_stride, double c_dt, double c, void* state_a, void* state_b,
                   const double* I_in, double* I_exit, double* E, double* F, double* f, double* bnd,

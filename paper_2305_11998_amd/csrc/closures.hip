@@ -111,9 +111,14 @@ __global__ __launch_bounds__(kBlock) void k_grey_closures(GreyArgs A) {
 
 lc_status launch_grey_closures(const Plan* pl, const double* E, const double* F, const double* f,
                                const double* kappa, const double* planck, double* out, hipStream_t st) {
+    return launch_grey_closures_dims(pl->rays->cells, pl->G, E, F, f, kappa, planck, out, st);
+}
+
+lc_status launch_grey_closures_dims(int cells, int G, const double* E, const double* F, const double* f,
+                                    const double* kappa, const double* planck, double* out, hipStream_t st) {
     GreyArgs A;
-    A.cells = pl->rays->cells;
-    A.G = pl->G;
+    A.cells = cells;
+    A.G = G;
     A.E = E;
     A.F = F;
     A.f = f;

@@ -226,6 +226,8 @@ lc_status launch_moments_batch(int prec, int pm, int ent, const void* args, cons
 lc_status launch_boundary_batch(const void* args, int n, int64_t blocks, hipStream_t st);
 lc_status build_face_lists(Rays* r, hipStream_t st);
 inline int64_t n_interior_faces(const Rays* r) { return (int64_t)(r->nx - 1) * r->ny + (int64_t)r->nx * (r->ny - 1); }
+lc_status launch_grey_closures_dims(int cells, int G, const double* E, const double* F, const double* f,
+                                    const double* kappa, const double* planck, double* out, hipStream_t st);
 lc_status launch_grey_closures(const Plan* pl, const double* E, const double* F, const double* f,
                                const double* kappa, const double* planck, double* out, hipStream_t st);
 

@@ -167,6 +167,50 @@ class Solver:
         return r.n_segments * 2 * r.n_pol * self.prob.G
 
 
+class GroupSplitSolver:
+    """Group-dependent characteristic grids: the groups of one problem are
+    split into ranges, each swept on a grid of characteristics with its own
+    spacing (and, optionally, construction); the ranges advance together as
+    one batch.  Moments and grey closures are those of the whole problem."""
+
+    def __init__(self, prob, parts, prec=lc.LC_F64, static_material=False):
+        """parts: list of (g0, g1, h_moc) covering the groups in order."""
+        import workloads as W
+        assert parts[0][0] == 0 and parts[-1][1] == prob.G
+        assert all(a[1] == b[0] for a, b in zip(parts, parts[1:]))
+        self.prob = prob
+        self.parts = parts
+        self.subs = [W.group_subset(prob, g0, g1, h) for g0, g1, h in parts]
+        self.batch = BatchSolver(self.subs, prec=prec, static_material=static_material)
+        self.kappa = _dev(np.stack(prob.kappa))          # [steps][G][cells], for the closures
+        self.planck = _dev(np.stack(prob.planck))
+
+    def reset(self):
+        self.batch.reset()
+
+    def step(self, n=1):
+        self.batch.step(n)
+
+    def moments(self):
+        """E [G][cells], F [G][2][cells], f [G][4][cells], bnd [G][nb][8]."""
+        ms = [s.moments() for s in self.batch.solvers]
+        return {k: np.concatenate([m[k] for m in ms], axis=0) for k in ("E", "F", "f", "bnd")}
+
+    def grey_closures(self, step):
+        """Grey closures of the whole problem with the material data of
+        `step` (lc_grey_closures_dims on the ranges' moments): [13][cells]."""
+        p = self.prob
+        cells, G = p.cells, p.G
+        sv = self.batch.solvers
+        E = torch.cat([s.E.view(cells, s.prob.G) for s in sv], dim=1).contiguous()
+        F = torch.cat([s.F.view(cells, 2, s.prob.G) for s in sv], dim=2).contiguous()
+        f = torch.cat([s.f.view(cells, 4, s.prob.G) for s in sv], dim=2).contiguous()
+        out = torch.empty(lc.N_GREY * cells, dtype=torch.float64, device="cuda")
+        lc.lc_grey_closures_dims(cells, G, E.view(-1), F.view(-1), f.view(-1), self.kappa[step].reshape(-1),
+                                 self.planck[step].reshape(-1), out)
+        return out.cpu().numpy().reshape(lc.N_GREY, cells)
+
+
 class BatchSolver:
     """Many problems advanced together through the batched C entry points.
     Each member keeps its own Solver (buffers, rays, plan); the batch handle

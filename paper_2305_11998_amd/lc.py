@@ -77,6 +77,7 @@ _SIGS = {
     "lc_moments": ([_vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_step": ([_vp, _i32, _vp, _vp, _i64, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_grey_closures": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "lc_grey_closures_dims": ([_i32, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_plan_enable_faces": ([_vp, _vp], C.c_int),
     "lc_sweep_points": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_face_moments": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp], C.c_int),
@@ -301,6 +302,16 @@ def lc_grey_closures(plan: Plan, E, F, f, kappa, planck, out, stream=None):
                                  _dev(f, 4 * n, name="f"), _dev(kappa, n, name="kappa"),
                                  _dev(planck, n, name="planck"), _dev(out, N_GREY * plan.rays.cells, name="out"),
                                  _stream(stream)))
+
+
+def lc_grey_closures_dims(cells: int, G: int, E, F, f, kappa, planck, out, stream=None):
+    """lc_grey_closures for moments of `cells` cells and G groups gathered
+    from several plans (cell-major E, F, f; [G][cells] kappa, planck)."""
+    n = int(cells) * int(G)
+    _check(_lib.lc_grey_closures_dims(int(cells), int(G), _dev(E, n, name="E"), _dev(F, 2 * n, name="F"),
+                                      _dev(f, 4 * n, name="f"), _dev(kappa, n, name="kappa"),
+                                      _dev(planck, n, name="planck"), _dev(out, N_GREY * int(cells), name="out"),
+                                      _stream(stream)))
 
 
 def lc_plan_set_tuning(plan: Plan, sweep_unroll: int, moments_entries: int):

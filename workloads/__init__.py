@@ -291,6 +291,17 @@ def make_problem(nx, ny, lx, ly, n_az, n_pol, G, nu_lo, nu_hi, h_moc, c_dt,
                    kap, B, I_in, s0, list(T_steps), name)
 
 
+def group_subset(prob: Problem, g0: int, g1: int, h_moc: float | None = None, name: str = "") -> Problem:
+    """Groups [g0, g1) of a problem as a problem of their own, optionally
+    with another characteristic spacing (every input sliced, nothing else)."""
+    return Problem(prob.nx, prob.ny, prob.lx, prob.ly, prob.phi, prob.mu, prob.omega, prob.edges[g0:g1 + 1].copy(),
+                   prob.h_moc if h_moc is None else h_moc, prob.c_dt,
+                   [np.ascontiguousarray(k[g0:g1]) for k in prob.kappa],
+                   [np.ascontiguousarray(b[g0:g1]) for b in prob.planck],
+                   np.ascontiguousarray(prob.I_in[:, :, g0:g1]), np.ascontiguousarray(prob.state0[g0:g1]),
+                   list(prob.T), name or f"{prob.name}[{g0}:{g1}]")
+
+
 def config(k: int, steps: int | None = None) -> Problem:
     """The five workloads, built from seed SEED0 + k:
 
