@@ -102,3 +102,12 @@ def test_out_pointer_required(lc):
     q = lc.lc_quad(len(phi), len(mu), phi.ctypes.data_as(dp), mu.ctypes.data_as(dp), om.ctypes.data_as(dp))
     assert lc._lib.lc_build_rays(C.byref(g), C.byref(q), 0.1, 0, None, None) == lc.LC_ERR_ARG
     assert b"out" in lc._lib.lc_last_error()
+
+
+def test_grey_closures_dims_rejects_bad_sizes(lc):
+    nul = (None,) * 7
+    assert lc._lib.lc_grey_closures_dims(0, 4, *nul) == lc.LC_ERR_ARG
+    assert b"cells and G" in lc._lib.lc_last_error()
+    assert lc._lib.lc_grey_closures_dims(5, 0, *nul) == lc.LC_ERR_ARG
+    assert lc._lib.lc_grey_closures_dims(5, 3, *nul) == lc.LC_ERR_ARG
+    assert b"NULL" in lc._lib.lc_last_error()
