@@ -159,10 +159,14 @@ template <typename T> __device__ __forceinline__ Coef<T> ld2(gptr<const Coef<T>>
     return c;
 }
 
+// Element-wise state accesses (a polar count that is not a power of two):
+// a lane's P values share cache lines with its neighbours', so they go
+// through the caches -- non-temporal element accesses fetched the same lines
+// once per polar slot (measured 2.7x slower at 512^2 with 6 polar angles).
 template <typename T>
-__device__ __forceinline__ T ldg_stream(gptr<const T> p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ T ldg_elem(gptr<const T> p) { return *p; }
 template <typename T>
-__device__ __forceinline__ void stg_stream(gptr<T> p, T v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void stg_elem(gptr<T> p, T v) { *p = v; }
 
 // One wavefront per (traversal d, bundle B) of a problem.  Lane (k, g) walks
 // its characteristic; step t reads the P stored values of the lane at
@@ -224,6 +228,11 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
     // two) they move as one vector load or store
     constexpr bool kVecOk = PM >= 2 && (PM & (PM - 1)) == 0;
     const bool vec = kVecOk && (FULL || P == PM);
+    // an even polar count that is not a power of two (6): pairs of values,
+    // through the caches (the pairs of neighbouring lanes share lines)
+    constexpr bool kPairsOk = !kVecOk && PM % 2 == 0;
+    const bool pairs = kPairsOk && (FULL || P == PM);
+    using V2 = T __attribute__((ext_vector_type(2)));
     using V = T __attribute__((ext_vector_type(PM)));
 
     int pol[NS];
@@ -271,9 +280,21 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
             for (int i = 0; i < NL; ++i) x[i] = v[i];
 #pragma unroll
             for (int i = 0; i < NU; ++i) x[NL + i] = v[PM - 1 - i];
+        } else if (pairs) {
+            T y[PM];
+#pragma unroll
+            for (int h = 0; h < PM / 2; ++h) {
+                const V2 v = *(gptr<const V2>)(r + 2 * h);
+                y[2 * h] = v.x;
+                y[2 * h + 1] = v.y;
+            }
+#pragma unroll
+            for (int i = 0; i < NL; ++i) x[i] = y[i];
+#pragma unroll
+            for (int i = 0; i < NU; ++i) x[NL + i] = y[PM - 1 - i];
         } else {
 #pragma unroll
-            for (int q = 0; q < NS; ++q) x[q] = val[q] ? ldg_stream(r + pol[q]) : (T)0;
+            for (int q = 0; q < NS; ++q) x[q] = val[q] ? ldg_elem(r + pol[q]) : (T)0;
         }
     };
 
@@ -286,10 +307,23 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
 #pragma unroll
             for (int i = 0; i < NU; ++i) v[PM - 1 - i] = x[NL + i];
             __builtin_nontemporal_store(v, (gptr<V>)o);
+        } else if (pairs) {
+            T y[PM];
+#pragma unroll
+            for (int i = 0; i < NL; ++i) y[i] = x[i];
+#pragma unroll
+            for (int i = 0; i < NU; ++i) y[PM - 1 - i] = x[NL + i];
+#pragma unroll
+            for (int h = 0; h < PM / 2; ++h) {
+                V2 v;
+                v.x = y[2 * h];
+                v.y = y[2 * h + 1];
+                *(gptr<V2>)(o + 2 * h) = v;
+            }
         } else {
 #pragma unroll
             for (int q = 0; q < NS; ++q)
-                if (val[q]) stg_stream(o + pol[q], x[q]);
+                if (val[q]) stg_elem(o + pol[q], x[q]);
         }
     };
 
