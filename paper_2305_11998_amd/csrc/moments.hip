@@ -100,15 +100,24 @@ __device__ __forceinline__ Slot<T> load_slot(gptr<const unsigned> eo, gptr<const
 }
 
 // The P values of one entry for one traversal (contiguous, [lane][p]); with
-// P == PM (a power of two) one vector load.
+// P == PM one vector load (a power of two) or pairs (an even count).
 template <typename T, int PM>
 __device__ __forceinline__ void load_entry(gptr<const T> st, size_t o, int P, T (&x)[PM]) {
     constexpr bool kVecOk = PM >= 2 && (PM & (PM - 1)) == 0;
+    constexpr bool kPairsOk = !kVecOk && PM % 2 == 0;    // 6 values: three pairs
     if (kVecOk && P == PM) {
         using V = T __attribute__((ext_vector_type(PM)));
         const V v = *(gptr<const V>)(st + o);
 #pragma unroll
         for (int p = 0; p < PM; ++p) x[p] = v[p];
+    } else if (kPairsOk && P == PM) {
+        using V2 = T __attribute__((ext_vector_type(2)));
+#pragma unroll
+        for (int h = 0; h < PM / 2; ++h) {
+            const V2 v = *(gptr<const V2>)(st + o + 2 * h);
+            x[2 * h] = v.x;
+            x[2 * h + 1] = v.y;
+        }
     } else {
 #pragma unroll
         for (int p = 0; p < PM; ++p) x[p] = p < P ? st[o + p] : (T)0;
