@@ -318,6 +318,29 @@ lc_status lc_plan_set_tuning(lc_plan_t plan, const lc_tuning_t* tuning);
 lc_status lc_plan_get_tuning(lc_plan_t plan, lc_tuning_t* tuning);
 
 /*
+ * Split sweep (in-ray parallel scan), for problems with few lanes and long
+ * characteristics.  The step of eq. (12) is affine in the intensity entering
+ * a segment, so a traversal cut into chunks of chunk_steps steps maps the
+ * intensity entering each chunk onto the one leaving it as I -> A I + B.
+ * With chunk_steps > 0, every following lc_sweep and lc_step of the plan runs
+ * three launches: one wavefront per (traversal of a bundle, chunk) forms
+ * the chunk's map (the first chunk from the true boundary intensity), a scan
+ * composes the maps along each traversal, and one wavefront per chunk sweeps
+ * it from its entering intensity, writing the state rows and, at the last
+ * chunk, the exit intensities.  The first two chunks of a traversal round
+ * exactly as the whole-traversal sweep; later ones differ from it by
+ * rounding only.  The plan holds the work lists and a transfer buffer of
+ * (chunks - 1 per traversal) * n_pol * 64 value pairs of its precision.
+ * chunk_steps = 0 turns it off (the default).  lc_sweep_points and batched
+ * steps always sweep whole traversals.  Synchronises the device and drops
+ * the plan's captured graphs.  Errors: LC_ERR_ARG for a chunk_steps that is
+ * negative, not a multiple of 4 or above 2^24; LC_ERR_UNSUPPORTED for a work
+ * list beyond 2^31 blocks; LC_ERR_ALLOC (the plan is then left with the
+ * split turned off); LC_ERR_HIP.
+ */
+lc_status lc_plan_set_split(lc_plan_t plan, int32_t chunk_steps);
+
+/*
  * Kernel timers (tracing).  lc_plan_profile(plan, 1) makes every following
  * eager lc_sweep / lc_moments record HIP events around its main kernel on the
  * caller's stream (not inside lc_step graphs); lc_plan_profile_read

@@ -56,6 +56,7 @@ void free_plan(Plan* pl) {
     if (pl->d_ent_off) (void)hipFree(pl->d_ent_off);
     if (pl->d_fent_off) (void)hipFree(pl->d_fent_off);
     if (pl->d_bun_rec) (void)hipFree(pl->d_bun_rec);
+    plan_free_split(pl);
     pl->magic = 0;
     delete pl;
 }
@@ -91,7 +92,7 @@ using namespace lc;
 
 extern "C" {
 
-int32_t lc_version(void) { return 1 * 10000 + 3 * 100 + 0; }
+int32_t lc_version(void) { return 1 * 10000 + 4 * 100 + 0; }
 
 const char* lc_last_error(void) { return g_err; }
 
@@ -463,6 +464,18 @@ lc_status lc_plan_set_tuning(lc_plan_t plan, const lc_tuning_t* t) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     pl->graphs.clear();
     return LC_OK;
+}
+
+lc_status lc_plan_set_split(lc_plan_t plan, int32_t chunk_steps) {
+    Plan* pl = as_plan(plan);
+    LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
+    LC_ARG(chunk_steps >= 0 && chunk_steps % kSplitUnroll == 0 && chunk_steps <= (1 << 24),
+           "chunk_steps must be 0 or a positive multiple of %d up to 2^24", kSplitUnroll);
+    for (auto& g : pl->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    pl->graphs.clear();
+    LC_HIP(hipDeviceSynchronize());   // no sweep in flight still reads the old records
+    return plan_set_split(pl, chunk_steps);
 }
 
 lc_status lc_plan_get_tuning(lc_plan_t plan, lc_tuning_t* t) {

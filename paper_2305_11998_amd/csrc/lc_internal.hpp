@@ -38,6 +38,7 @@ constexpr uint32_t kPlanMagic = 0x4c43504cu;   // "LCPL"
 constexpr uint32_t kBatchMagic = 0x4c434254u;  // "LCBT"
 constexpr int kMaxPol = 8;
 constexpr int kMaxPolUnroll16 = 4;               // sweep_unroll 16: float32 plans with n_pol up to this
+constexpr int kSplitUnroll = 4;                  // load chunk of the split sweep; split lengths are multiples
 constexpr int kBlock = 256;                    // threads per block of the streaming kernels
 constexpr int kWave = 64;                      // lanes per wavefront (gfx9)
 constexpr int kDirW = 10;                      // per-direction weight record, see dirw_index
@@ -141,6 +142,14 @@ struct Plan {
     int tile_w = 1, tile_h = 1;       // cell tile of the moments kernel
     int64_t sweep_blocks = 0;         // blocks of one sweep launch
     size_t sweep_lds = 0;             // LDS reserved per sweep block (caps the blocks per CU)
+    // split sweep (lc_plan_set_split): traversals cut into chunks of
+    // split_len steps; items {wavefront, chunk} of the transfer pass (the
+    // first n_split1) then of the sweep pass; transfer records per wavefront
+    int split_len = 0;
+    int2* d_split_items = nullptr;
+    int64_t n_split1 = 0, n_split_items = 0;
+    int64_t* d_cbase = nullptr;       // [2 n_bun + 1] first transfer record of each wavefront
+    void* d_carry = nullptr;          // [records][n_pol][64] {A, B} pairs of the state type
     std::vector<GraphEntry> graphs;   // captured lc_step sequences
     hipStream_t capture = nullptr;    // stream used only to record graphs
     bool profile = false;             // record events around the main kernels
@@ -187,6 +196,8 @@ lc_status launch_state_fill(Plan* pl, const double* field, void* state, hipStrea
 lc_status launch_state_export(Plan* pl, const void* state, double* out, hipStream_t st);
 lc_status build_geometry(Rays* r, hipStream_t st);
 lc_status plan_init_sweep(Plan* pl);
+lc_status plan_set_split(Plan* pl, int len);
+void plan_free_split(Plan* pl);
 lc_status plan_init_moments(Plan* pl);
 lc_status plan_enable_faces(Plan* pl, hipStream_t st);
 lc_status launch_face_moments(Plan* pl, const void* point, const void* state, double c, double* E, double* F,

@@ -48,6 +48,14 @@ struct SweepArgs {
     double inv_sinz[kMaxPol];
 };
 
+// Split sweep (chunks of a traversal): the transfer records, the first
+// record of each wavefront (d * n_bun + B) and the chunk length in steps.
+struct SplitArgs {
+    void* carry;             // [record][slot][lane] of {A, B} pairs (T)
+    const int64_t* cbase;    // [2 n_bun + 1]
+    int len;
+};
+
 // Hardware hands workgroups to the 8 XCDs round-robin; give each XCD a
 // contiguous range of logical blocks (a band of neighbouring characteristics)
 // so the cell coefficients they share stay in that XCD's L2.
@@ -190,8 +198,19 @@ __device__ __forceinline__ void stg_elem(gptr<T> p, T v) { *p = v; }
 //
 // POINT: also store the intensity entering each segment (the value at its
 // upwind face) into A.point, in the state layout.
-template <typename T, int PM, int U, bool FULL, bool POINT = false>
-__device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int lane) {
+//
+// SPLIT (a traversal cut into chunks of A.split_len steps, chunk c of the
+// wavefront's traversal): the recurrence of eq. (12) maps the intensity
+// entering a chunk affinely onto the one leaving it, I -> A I + B, A the
+// product of the chunk's attenuation factors.  SPLIT == 1 computes that map
+// of chunk c (for c = 0 from the true boundary intensity, so A = 0 and B is
+// the exact exit of the chunk) into transfer record c of the wavefront, and
+// stores no state; SPLIT == 2 sweeps chunk c from the intensity the scan of
+// the records left in record c - 1 (chunk 0 from the boundary) and stores
+// its rows, and the exit intensities at the last chunk.
+template <typename T, int PM, int U, bool FULL, bool POINT = false, int SPLIT = 0>
+__device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int lane, int chunk = 0,
+                                           const SplitArgs& S = SplitArgs{}) {
     constexpr int NL = (PM + 1) / 2, NU = PM / 2, NS = NL + NU;
     const int d = w >= A.n_bun ? 1 : 0;
     const int64_t B = w - (d ? A.n_bun : 0);
@@ -213,6 +232,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
     const int nk = seg_off[k + 1] - s0;
     const int n = active ? nk : 0;
     const int L = as_global(A.bun_len)[B];
+    // steps [tb, te) of the traversal (all of it unless split)
+    const int tb = SPLIT ? chunk * S.len : 0;
+    const int te = SPLIT ? min(tb + S.len, L) : L;
     const int az = a + d * (A.n_az >> 1);
     using T2 = typename Vec2<T>::type;
     const gptr<const int2> gi = as_global(A.gi);
@@ -265,6 +287,20 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
     for (int r = 0; r < NS; ++r) {
         isz[r] = val[r] ? (T)A.inv_sinz[pol[r]] : (T)1;
         I[r] = val[r] ? (T)(I_in[((size_t)face_in * A.M + (size_t)az * P + pol[r]) * G + g] * sc_in) : (T)0;
+    }
+    // split: transfer records of this wavefront, [slot][lane] pairs each
+    using T2v = T __attribute__((ext_vector_type(2)));
+    const gptr<T2v> rec = as_global_w(static_cast<T2v*>(S.carry)) +
+                          (SPLIT ? (size_t)as_global(S.cbase)[w] * NS * kWave + lane : 0);
+    T Am[NS];                                      // SPLIT == 1: product of the attenuation factors
+#pragma unroll
+    for (int r = 0; r < NS; ++r) Am[r] = (T)1;
+    if (SPLIT && chunk > 0) {
+#pragma unroll
+        for (int r = 0; r < NS; ++r) {
+            if (SPLIT == 1) I[r] = (T)0;
+            else I[r] = val[r] ? rec[((size_t)(chunk - 1) * NS + r) * kWave].y : (T)0;
+        }
     }
     // segment index of step t (clamped into the characteristic)
     auto seg = [&](int t) -> int {
@@ -336,15 +372,15 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
     T x0[U][NS];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-        const int j0 = seg(u), j1 = seg(U + u);
+        const int j0 = seg(tb + u), j1 = seg(tb + U + u);
         const int cell0 = gcell[2 * (size_t)j0];
         len0[u] = glen[2 * (size_t)j0];
         c0[u] = ld2(coef + ((size_t)cell0 * G + g));
         cell1[u] = gcell[2 * (size_t)j1];
         len1[u] = glen[2 * (size_t)j1];
-        load_row(srow(u), x0[u]);
+        load_row(srow(tb + u), x0[u]);
     }
-    for (int t0 = 0; t0 < L; t0 += U) {
+    for (int t0 = tb; t0 < te; t0 += U) {
         Coef<T> c1[U];
         T x1[U][NS];
         int cell2[U];
@@ -380,8 +416,9 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
                 const T Io = fma_(at[q].E, I[q], at[q].D * S);        // eq. (12)
                 ob[q] = fma_(at[q].al, I[q], at[q].be * Io);          // segment average
                 I[q] = live ? Io : I[q];
+                if (SPLIT == 1) Am[q] = live ? Am[q] * at[q].E : Am[q];
             }
-            if (FULL ? t < L : live) {
+            if (SPLIT != 1 && (FULL ? t < te : live)) {
                 store_row(xout + (size_t)t * SP, ob);
                 if (POINT) store_row(pout + (size_t)t * SP, ib);
             }
@@ -396,7 +433,17 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
             for (int q = 0; q < NS; ++q) x0[u][q] = x1[u][q];
         }
     }
-    if (A.I_exit && active) {
+    if (SPLIT == 1) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            T2v v;
+            v.x = chunk > 0 ? Am[q] : (T)0;
+            v.y = I[q];
+            rec[((size_t)chunk * NS + q) * kWave] = v;
+        }
+        return;
+    }
+    if (A.I_exit && active && te == L) {
         const gptr<double> I_exit = as_global_w(A.I_exit);
 #pragma unroll
         for (int q = 0; q < NS; ++q)
@@ -441,6 +488,43 @@ __global__ __launch_bounds__(kBlock) void k_sweep_batch(const SweepArgs* __restr
         const int pr = __builtin_amdgcn_readfirstlane(items[gi].x);
         const int w = __builtin_amdgcn_readfirstlane(items[gi].y);
         sweep_wave<T, PM, U, FULL>(probs[pr], w, lane);
+    }
+}
+
+// Split sweep: one wavefront per item {wavefront of the plain sweep, chunk},
+// in either mode; blocks remapped per XCD as in the plain sweep.
+template <typename T, int PM, int MODE>
+__global__ __launch_bounds__(kBlock) void k_sweep_split(SweepArgs A, SplitArgs S, const int2* __restrict__ items,
+                                                        int64_t n_items, int64_t n_blocks) {
+    const int64_t lb = xcd_logical_block(blockIdx.x, n_blocks);
+    const int64_t i = lb * (kBlock / kWave) + (threadIdx.x / kWave);
+    if (i >= n_items) return;
+    const int2 it = ld2(as_global(items) + i);
+    const int w = __builtin_amdgcn_readfirstlane(it.x);
+    const int c = __builtin_amdgcn_readfirstlane(it.y);
+    sweep_wave<T, PM, kSplitUnroll, false, false, MODE>(A, w, threadIdx.x & (kWave - 1), c, S);
+}
+
+// Sequential composition of the transfer records of each wavefront: one
+// thread per (wavefront, slot, lane) walks the records of its chunks in
+// order, I <- A I + B from I = 0, and leaves in record c the intensity
+// entering chunk c + 1 (record 0 holds the exact exit of chunk 0, A = 0).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_split_scan(T* carry, const int64_t* __restrict__ cbase, int per,
+                                                       int64_t n_threads) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= n_threads) return;
+    const int64_t w = e / per, o = e - w * per;
+    const gptr<const int64_t> cb = as_global(cbase);
+    const int64_t r0 = cb[w], r1 = cb[w + 1];
+    using T2v = T __attribute__((ext_vector_type(2)));
+    const gptr<T2v> rec = as_global_w(reinterpret_cast<T2v*>(carry));
+    T I = (T)0;
+    for (int64_t r = r0; r < r1; ++r) {
+        T2v v = rec[r * per + o];
+        I = fma_(v.x, I, v.y);
+        v.y = I;
+        rec[r * per + o] = v;
     }
 }
 
@@ -541,6 +625,50 @@ lc_status sweep_call_batch(int prec, int pm, const SweepCall& c) {
         case 8: return f32 ? sweep_call_f<true, float, 8>(c) : sweep_call_f<true, double, 8>(c);
     }
     set_error("batched sweep: polar bound %d not supported", pm);
+    return LC_ERR_UNSUPPORTED;
+}
+
+// Split sweep of a single problem (PM = n_pol): mode 1 over the transfer
+// items, the scan, mode 2 over the sweep items.
+template <typename T, int PM>
+lc_status split_call(const Plan* pl, const SweepArgs& A, hipStream_t st) {
+    const int64_t per = (int64_t)PM * kWave;
+    SplitArgs S;
+    S.carry = pl->d_carry;
+    S.cbase = pl->d_cbase;
+    S.len = pl->split_len;
+    const int64_t n1 = pl->n_split1, n2 = pl->n_split_items - pl->n_split1;
+    const int wpb = kBlock / kWave;
+    if (n1 > 0) {
+        const int64_t nb = (n1 + wpb - 1) / wpb;
+        hipLaunchKernelGGL((k_sweep_split<T, PM, 1>), dim3((unsigned)nb), dim3(kBlock), pl->sweep_lds, st, A, S,
+                           pl->d_split_items, n1, nb);
+        LC_HIP(hipGetLastError());
+        const int64_t nt = 2 * pl->n_bun * per;
+        hipLaunchKernelGGL(k_split_scan<T>, dim3((unsigned)((nt + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                           static_cast<T*>(pl->d_carry), pl->d_cbase, (int)per, nt);
+        LC_HIP(hipGetLastError());
+    }
+    const int64_t nb = (n2 + wpb - 1) / wpb;
+    hipLaunchKernelGGL((k_sweep_split<T, PM, 2>), dim3((unsigned)nb), dim3(kBlock), pl->sweep_lds, st, A, S,
+                       pl->d_split_items + n1, n2, nb);
+    LC_HIP(hipGetLastError());
+    return LC_OK;
+}
+
+template <typename T>
+lc_status split_call_p(const Plan* pl, const SweepArgs& A, hipStream_t st) {
+    switch (pl->rays->n_pol) {
+        case 1: return split_call<T, 1>(pl, A, st);
+        case 2: return split_call<T, 2>(pl, A, st);
+        case 3: return split_call<T, 3>(pl, A, st);
+        case 4: return split_call<T, 4>(pl, A, st);
+        case 5: return split_call<T, 5>(pl, A, st);
+        case 6: return split_call<T, 6>(pl, A, st);
+        case 7: return split_call<T, 7>(pl, A, st);
+        case 8: return split_call<T, 8>(pl, A, st);
+    }
+    set_error("n_pol = %d not supported (1..8)", pl->rays->n_pol);
     return LC_ERR_UNSUPPORTED;
 }
 
@@ -661,6 +789,63 @@ lc_status plan_init_sweep(Plan* pl) {
     return sweep_lds_bytes(&pl->sweep_lds);
 }
 
+void plan_free_split(Plan* pl) {
+    for (void* q : {static_cast<void*>(pl->d_split_items), static_cast<void*>(pl->d_cbase), pl->d_carry})
+        if (q) (void)hipFree(q);
+    pl->d_split_items = nullptr;
+    pl->d_cbase = nullptr;
+    pl->d_carry = nullptr;
+    pl->n_split1 = pl->n_split_items = 0;
+    pl->split_len = 0;
+}
+
+lc_status plan_set_split(Plan* pl, int len) {
+    plan_free_split(pl);
+    if (len == 0) return LC_OK;
+    const int64_t nw = 2 * pl->n_bun;
+    std::vector<int64_t> cbase(nw + 1, 0);
+    std::vector<int2> items1, items2;
+    for (int64_t w = 0; w < nw; ++w) {
+        const int L = pl->bun_len_h[w % pl->n_bun];
+        const int nc = std::max(1, (L + len - 1) / len);
+        for (int c = 0; c + 1 < nc; ++c) items1.push_back(make_int2((int)w, c));
+        for (int c = 0; c < nc; ++c) items2.push_back(make_int2((int)w, c));
+        cbase[w + 1] = cbase[w] + (nc - 1);
+    }
+    const int64_t wpb = kBlock / kWave;
+    LC_CHECK(((int64_t)items2.size() + wpb - 1) / wpb < INT32_MAX, LC_ERR_UNSUPPORTED, "split sweep grid too large");
+    LC_CHECK((nw * pl->rays->n_pol * kWave + kBlock - 1) / kBlock < INT32_MAX, LC_ERR_UNSUPPORTED,
+             "split sweep scan grid too large");
+    const size_t elem = pl->prec == LC_F32 ? sizeof(float) : sizeof(double);
+    const size_t carry = (size_t)std::max<int64_t>(cbase[nw], 1) * pl->rays->n_pol * kWave * 2 * elem;
+    std::vector<int2> items(items1);
+    items.insert(items.end(), items2.begin(), items2.end());
+    lc_status rc = LC_OK;
+    auto put = [&](void** dst, const void* src, size_t bytes) {
+        if (rc != LC_OK) return;
+        if (hipMalloc(dst, bytes) != hipSuccess) {
+            set_error("hipMalloc of %zu bytes for the split sweep failed", bytes);
+            rc = LC_ERR_ALLOC;
+            return;
+        }
+        if (src && hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            set_error("copy of the split sweep items failed");
+            rc = LC_ERR_HIP;
+        }
+    };
+    put(reinterpret_cast<void**>(&pl->d_split_items), items.data(), items.size() * sizeof(int2));
+    put(reinterpret_cast<void**>(&pl->d_cbase), cbase.data(), cbase.size() * sizeof(int64_t));
+    put(&pl->d_carry, nullptr, carry);
+    if (rc != LC_OK) {
+        plan_free_split(pl);
+        return rc;
+    }
+    pl->n_split1 = (int64_t)items1.size();
+    pl->n_split_items = (int64_t)items.size();
+    pl->split_len = len;
+    return LC_OK;
+}
+
 lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, double c_dt,
                        const void* state_prev, void* state_new, const double* I_in, double* I_exit,
                        hipStream_t st, void* point) {
@@ -702,6 +887,11 @@ lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, doub
     for (int p = 0; p < r->n_pol; ++p) A.inv_sinz[p] = r->inv_sinz[p];
     rc = prof_begin(pl, pl->ev_sweep, st);
     if (rc) return rc;
+    if (pl->split_len > 0 && !point) {
+        rc = f32 ? split_call_p<float>(pl, A, st) : split_call_p<double>(pl, A, st);
+        if (rc) return rc;
+        return prof_end(pl, pl->ev_sweep, st);
+    }
     SweepCall c;
     c.unroll = pl->sweep_unroll;
     c.full = sweep_full(r);

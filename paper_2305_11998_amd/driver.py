@@ -19,7 +19,9 @@ def _dev(a):
 
 
 class Solver:
-    def __init__(self, prob, prec=lc.LC_F64, mode=lc.LC_RAYS_UNIFORM, c=None, rays=None):
+    def __init__(self, prob, prec=lc.LC_F64, mode=lc.LC_RAYS_UNIFORM, c=None, rays=None, split=0):
+        """split > 0: sweep traversals in chunks of that many steps
+        (lc_plan_set_split)."""
         from workloads import C_LIGHT
         self.prob = prob
         self.c = C_LIGHT if c is None else float(c)
@@ -27,6 +29,8 @@ class Solver:
         self.rays = rays if rays is not None else lc.lc_build_rays(
             prob.nx, prob.ny, prob.lx, prob.ly, prob.phi, prob.mu, prob.omega, prob.h_moc, mode)
         self.plan = lc.Plan(self.rays, prob.G, prec)
+        if split:
+            lc.lc_plan_set_split(self.plan, split)
         G, cells = prob.G, prob.cells
         self.kappa = _dev(np.stack(prob.kappa))          # [steps][G][cells]
         self.planck = _dev(np.stack(prob.planck))

@@ -54,10 +54,11 @@ def _oracle_full(prob, steps=None, mode=0):
     return osolve.run(prob, steps=steps, mode=mode)
 
 
-def _compare_full(lc, driver, prob, prec, tol, graph=True, check_state=True, mode=0):
-    _say(f"case {prob.name}: {prob.nx}x{prob.ny} G={prob.G} M={prob.M} prec={prec} steps={prob.steps} mode={mode}")
+def _compare_full(lc, driver, prob, prec, tol, graph=True, check_state=True, mode=0, split=0):
+    _say(f"case {prob.name}: {prob.nx}x{prob.ny} G={prob.G} M={prob.M} prec={prec} steps={prob.steps} mode={mode}"
+         f" split={split}")
     ref = _oracle_full(prob, mode=mode)
-    s = driver.Solver(prob, prec=prec, mode=mode)
+    s = driver.Solver(prob, prec=prec, mode=mode, split=split)
     s.reset()
     s.step(prob.steps, graph=graph)
     got = s.moments()
