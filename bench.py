@@ -283,7 +283,7 @@ def run_single(k, steps, warmup):
                          grey=grey,
                          upd=s.updates_per_step(), moments=s.moments(),
                          alg=sweep_algorithmic_bytes(s, 4 if prec == lc.LC_F32 else 8),
-                         tuning={kk: tuned[kk] for kk in ("sweep_unroll", "moments_entries")})
+                         tuning={kk: tuned.get(kk, 0) for kk in ("sweep_unroll", "moments_entries", "split")})
         out[name]["faces"] = time_faces(s) if prec == lc.LC_F32 else None     # after the moments above
         _say(f"config {k} {name}: {out[name]['ms']:.3f} ms/step, sweep {out[name]['sweep_ms']:.3f} ms, "
              f"moments {out[name]['moments_ms']:.3f} ms")
@@ -317,6 +317,70 @@ def main_single(args):
         "interior_faces": f32["faces"],
     }
     print(json.dumps(res), flush=True)
+
+
+def split_cases():
+    """Few-lane problems, where a traversal's steps are the critical path:
+    a 512^2 grid swept for one group with 8 x 2 directions (lanes = the
+    characteristics only), and the two lowest groups of the 256^2, G = 51,
+    32 x 4 problem on a characteristic grid four times finer (spacing h/8),
+    the kind of group range that group-dependent grids put on a fine grid;
+    with the 128^2, G = 17 problem for comparison."""
+    import numpy as np
+    import workloads as W
+    rng = np.random.default_rng(W.SEED0 + 7)
+    n, L = 512, 6.0
+    T = W.t_field_gaussians(rng, n, n, L, L)
+    grey = W.make_problem(n, n, L, L, 8, 2, 1, 0.001, 30.0, L / n / 2, 3.0, [T], name="512x512 G=1 8x2 dirs h/2")
+    c2 = W.config(2, steps=1)
+    low = W.group_subset(c2, 0, 2, h_moc=c2.lx / c2.nx / 8, name="256x256 groups 0-1 of 51, 32x4 dirs, h/8")
+    c1 = W.config(1, steps=1)
+    c1.name = "128x128 G=17 32x2 dirs h/4"
+    return [grey, low, c1]
+
+
+def main_split(args):
+    """Whole-traversal vs split sweep (lc_plan_set_split) on few-lane
+    problems: sweep milliseconds per chunk length, float32 and float64, and
+    the largest relative difference of E between the two forms."""
+    import numpy as np
+    import torch
+    from paper_2305_11998_amd import driver, lc, tune
+    rows = []
+    cases = split_cases()
+    for prob in (cases if args.case is None else [cases[args.case]]):
+        for prec, name in ((lc.LC_F32, "f32"), (lc.LC_F64, "f64")):
+            s = driver.Solver(prob, prec=prec)
+            tune.tune(s, cache=None)
+            times, E = {}, {}
+            for sp in (0, 16, 32, 64, 128, 256):
+                lc.lc_plan_set_split(s.plan, sp)
+                s.reset()
+                for _ in range(args.warmup):
+                    s.bench_step()
+                torch.cuda.synchronize()
+                lc.lc_plan_profile_read(s.plan)
+                lc.lc_plan_profile(s.plan, True)
+                for _ in range(args.steps):
+                    s.bench_step()
+                torch.cuda.synchronize()
+                sw, nsw, _, _ = lc.lc_plan_profile_read(s.plan)
+                lc.lc_plan_profile(s.plan, False)
+                times[sp] = sw / max(nsw, 1)
+                s.reset()
+                s.step(1, graph=False)
+                E[sp] = s.moments()["E"]
+            best = min(times, key=times.get)
+            dE = max(float(np.max(np.abs(E[sp] - E[0]) / np.maximum(np.abs(E[0]), 1e-300))) for sp in E)
+            row = dict(problem=prob.name, prec=name, updates=s.updates_per_step(), whole_ms=times[0],
+                       best_split=best, best_ms=times[best], speedup=times[0] / times[best],
+                       ms={str(k): v for k, v in times.items()}, max_rel_dE=dE)
+            _say(f"{prob.name} {name}: whole {times[0]:.4f} ms, split {best}: {times[best]:.4f} ms "
+                 f"({row['speedup']:.2f}x), max rel dE {dE:.1e}")
+            rows.append(row)
+            del s
+            torch.cuda.empty_cache()
+    print(json.dumps({"workload": "split sweep on few-lane problems", "rows": rows}), flush=True)
 
 
 def main_refinement(args):
@@ -376,9 +440,12 @@ def main_refinement(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("batch", "single", "refinement"), default="batch",
-                    help="batch: the 64-problem batched form (default); single: one problem of --config")
+    ap.add_argument("--workload", choices=("batch", "single", "refinement", "split"), default="batch",
+                    help="batch: the 64-problem batched form (default); single: one problem of --config; "
+                         "refinement: characteristic-grid refinement study; split: whole vs split sweep "
+                         "on few-lane problems")
     ap.add_argument("--config", type=int, default=2, help="workload index for --workload single (0, 1, 2 or 4)")
+    ap.add_argument("--case", type=int, default=None, help="--workload split: run only this case (0, 1 or 2)")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--f64-steps", type=int, default=2)
@@ -405,6 +472,8 @@ def main():
         torch.cuda.synchronize()
         _say(f"copied 3 x {n * 4} bytes")
         return
+    if args.workload == "split":
+        return main_split(args)
     if args.workload == "refinement":
         main_refinement(args)
         return

@@ -519,12 +519,22 @@ __global__ __launch_bounds__(kBlock) void k_split_scan(T* carry, const int64_t* 
     const int64_t r0 = cb[w], r1 = cb[w + 1];
     using T2v = T __attribute__((ext_vector_type(2)));
     const gptr<T2v> rec = as_global_w(reinterpret_cast<T2v*>(carry));
+    // records are read kScanBatch at a time (independent loads in flight
+    // together), then composed in order
+    constexpr int kScanBatch = 8;
     T I = (T)0;
-    for (int64_t r = r0; r < r1; ++r) {
-        T2v v = rec[r * per + o];
-        I = fma_(v.x, I, v.y);
-        v.y = I;
-        rec[r * per + o] = v;
+    for (int64_t r = r0; r < r1; r += kScanBatch) {
+        T2v v[kScanBatch];
+#pragma unroll
+        for (int j = 0; j < kScanBatch; ++j)
+            if (r + j < r1) v[j] = rec[(r + j) * per + o];
+#pragma unroll
+        for (int j = 0; j < kScanBatch; ++j)
+            if (r + j < r1) {
+                I = fma_(v[j].x, I, v[j].y);
+                v[j].y = I;
+                rec[(r + j) * per + o] = v[j];
+            }
     }
 }
 
@@ -629,7 +639,10 @@ lc_status sweep_call_batch(int prec, int pm, const SweepCall& c) {
 }
 
 // Split sweep of a single problem (PM = n_pol): mode 1 over the transfer
-// items, the scan, mode 2 over the sweep items.
+// items, the scan, mode 2 over the sweep items.  Its problems are the ones
+// with too few lanes to fill the device, whose time is the latency of a
+// chunk's steps: the blocks reserve no LDS, so as many wavefronts stay
+// resident as the registers allow.
 template <typename T, int PM>
 lc_status split_call(const Plan* pl, const SweepArgs& A, hipStream_t st) {
     const int64_t per = (int64_t)PM * kWave;
@@ -641,7 +654,7 @@ lc_status split_call(const Plan* pl, const SweepArgs& A, hipStream_t st) {
     const int wpb = kBlock / kWave;
     if (n1 > 0) {
         const int64_t nb = (n1 + wpb - 1) / wpb;
-        hipLaunchKernelGGL((k_sweep_split<T, PM, 1>), dim3((unsigned)nb), dim3(kBlock), pl->sweep_lds, st, A, S,
+        hipLaunchKernelGGL((k_sweep_split<T, PM, 1>), dim3((unsigned)nb), dim3(kBlock), 0, st, A, S,
                            pl->d_split_items, n1, nb);
         LC_HIP(hipGetLastError());
         const int64_t nt = 2 * pl->n_bun * per;
@@ -650,7 +663,7 @@ lc_status split_call(const Plan* pl, const SweepArgs& A, hipStream_t st) {
         LC_HIP(hipGetLastError());
     }
     const int64_t nb = (n2 + wpb - 1) / wpb;
-    hipLaunchKernelGGL((k_sweep_split<T, PM, 2>), dim3((unsigned)nb), dim3(kBlock), pl->sweep_lds, st, A, S,
+    hipLaunchKernelGGL((k_sweep_split<T, PM, 2>), dim3((unsigned)nb), dim3(kBlock), 0, st, A, S,
                        pl->d_split_items + n1, n2, nb);
     LC_HIP(hipGetLastError());
     return LC_OK;

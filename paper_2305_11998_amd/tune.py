@@ -22,6 +22,8 @@ SWEEP_CANDIDATES = (2, 4, 8)
 SWEEP_CANDIDATES_F32 = (2, 4, 8, 16)   # 16: float32 with at most MAX_POL_UNROLL16 polar angles
 MAX_POL_UNROLL16 = 4
 MOMENT_CANDIDATES = (1, 2, 3, 4)
+SPLIT_CANDIDATES = (0, 32, 64, 128, 256)   # chunk steps of the split sweep, 0 = whole traversals
+SPLIT_GAIN = 0.97          # a split form is kept only if at least 3% faster than whole traversals
 BASE = (4, 3)             # the setting the other parameter is held at while one is searched
 DEFAULT_CACHE = os.environ.get(
     "LC_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "lc_tuning.json"))
@@ -60,9 +62,10 @@ def sweep_candidates(prec: int, n_pol: int):
 
 
 def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool = False):
-    """Pick (sweep_unroll, moments_entries) for ``solver.plan`` by timing
-    ``reps`` eager steps per candidate.  Leaves the chosen tuning set on the
-    plan and returns it with the measured times (ms per launch)."""
+    """Pick (sweep_unroll, moments_entries), then the split sweep's chunk
+    length (0 = whole traversals), for ``solver.plan`` by timing ``reps``
+    eager steps per candidate.  Leaves the choice set on the plan and
+    returns it with the measured times (ms per launch)."""
     import torch
     plan = solver.plan
     key = shape_key(plan)
@@ -70,7 +73,9 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
     if key in db:
         t = db[key]
         lc.lc_plan_set_tuning(plan, t["sweep_unroll"], t["moments_entries"])
+        lc.lc_plan_set_split(plan, t.get("split", 0))
         return dict(t, cached=True, key=key)
+    lc.lc_plan_set_split(plan, 0)
     times = {}
     # the two parameters act on different kernels: vary one with the other fixed
     ucands = sweep_candidates(plan.prec, plan.rays.n_pol)
@@ -93,9 +98,31 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
     best_u = min(ucands, key=lambda u: times[(u, BASE[1])][0])
     best_e = min(MOMENT_CANDIDATES, key=lambda e: times[(BASE[0], e)][1])
     lc.lc_plan_set_tuning(plan, best_u, best_e)
-    res = dict(sweep_unroll=best_u, moments_entries=best_e,
+    # then the split sweep's chunk length (its own load chunk is fixed, so
+    # the unroll above does not act on it); few-lane problems gain from it
+    split_ms = {}
+    for sp in SPLIT_CANDIDATES:
+        lc.lc_plan_set_split(plan, sp)
+        solver.bench_step()
+        torch.cuda.synchronize()
+        lc.lc_plan_profile_read(plan)
+        lc.lc_plan_profile(plan, True)
+        for _ in range(reps):
+            solver.bench_step()
+        torch.cuda.synchronize()
+        sw, nsw, _, _ = lc.lc_plan_profile_read(plan)
+        lc.lc_plan_profile(plan, False)
+        split_ms[sp] = sw / max(nsw, 1)
+        if verbose:
+            print(f"  tune {key}: split {sp}: sweep {split_ms[sp]:.3f} ms", file=sys.stderr, flush=True)
+    best_s = min(split_ms, key=split_ms.get)
+    if split_ms[best_s] > SPLIT_GAIN * split_ms[0]:
+        best_s = 0
+    lc.lc_plan_set_split(plan, best_s)
+    res = dict(sweep_unroll=best_u, moments_entries=best_e, split=best_s,
                sweep_ms={str(k): v[0] for k, v in times.items()},
-               moments_ms={str(k): v[1] for k, v in times.items()})
+               moments_ms={str(k): v[1] for k, v in times.items()},
+               split_ms={str(k): v for k, v in split_ms.items()})
     if cache:
         db[key] = res
         _save(cache, db)
