@@ -455,8 +455,8 @@ def main():
                     help="only copy a 4 GiB buffer three times (scales the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
-              "is a design described in DESIGN.md, not a measured path", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); sharding the groups over "
+              "several GPUs is a design only, not a measured path", file=sys.stderr)
         sys.exit(2)
 
     import torch

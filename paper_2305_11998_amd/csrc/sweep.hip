@@ -662,6 +662,7 @@ lc_status split_call(const Plan* pl, const SweepArgs& A, hipStream_t st) {
                            static_cast<T*>(pl->d_carry), pl->d_cbase, (int)per, nt);
         LC_HIP(hipGetLastError());
     }
+    if (n2 == 0) return LC_OK;
     const int64_t nb = (n2 + wpb - 1) / wpb;
     hipLaunchKernelGGL((k_sweep_split<T, PM, 2>), dim3((unsigned)nb), dim3(kBlock), 0, st, A, S,
                        pl->d_split_items + n1, n2, nb);
