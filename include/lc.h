@@ -343,10 +343,11 @@ lc_status lc_plan_set_split(lc_plan_t plan, int32_t chunk_steps);
 /*
  * Kernel timers (tracing).  lc_plan_profile(plan, 1) makes every following
  * eager lc_sweep / lc_moments record HIP events around its main kernel on the
- * caller's stream (not inside lc_step graphs); lc_plan_profile_read
- * synchronises those events and returns, in out[4]: total milliseconds and
- * launch count of the sweep kernel, then of the cell-moment kernel; it also
- * clears the record.  lc_plan_profile(plan, 0) stops recording.
+ * caller's stream (not inside lc_step graphs; around all three launches of
+ * a split sweep); lc_plan_profile_read synchronises those events and
+ * returns, in out[4]: total milliseconds and count of the recorded sweeps,
+ * then of the cell-moment launches; it also clears the record.
+ * lc_plan_profile(plan, 0) stops recording.
  */
 lc_status lc_plan_profile(lc_plan_t plan, int32_t enable);
 lc_status lc_plan_profile_read(lc_plan_t plan, double* out);

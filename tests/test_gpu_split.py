@@ -125,3 +125,25 @@ def test_split_argument_errors(lcmod):
         assert e.value.status == lc.LC_ERR_ARG
     lc.lc_plan_set_split(s.plan, 1 << 24)
     lc.lc_plan_set_split(s.plan, 0)
+
+
+def test_tuner_choice_is_cached_with_the_split(lcmod, tmp_path):
+    """The tuner's choice (split chunk length included) is stored and
+    restored from its cache; results with the restored setting equal those
+    right after tuning."""
+    lc, driver = lcmod
+    from paper_2305_11998_amd import tune
+    prob = _custom_problem(nx=12, ny=10, lx=1.2, ly=1.0, n_az=8, G=2, h_moc=0.02, steps=1)
+    cache = str(tmp_path / "tune.json")
+    a = driver.Solver(prob, prec=lc.LC_F32)
+    ta = tune.tune(a, reps=1, cache=cache)
+    assert not ta["cached"] and ta["split"] in tune.SPLIT_CANDIDATES
+    assert set(ta["split_ms"]) == {str(c) for c in tune.SPLIT_CANDIDATES}
+    b = driver.Solver(prob, prec=lc.LC_F32)
+    tb = tune.tune(b, reps=1, cache=cache)
+    assert tb["cached"] and tb["split"] == ta["split"] and tb["sweep_unroll"] == ta["sweep_unroll"]
+    for s in (a, b):
+        s.reset()
+        s.step(1)
+    assert np.array_equal(a.state_canonical(), b.state_canonical())
+    assert np.array_equal(a.moments()["E"], b.moments()["E"])
