@@ -236,11 +236,12 @@ __global__ void k_csr_fill(const int* __restrict__ ray_off, int n_pairs, int n_r
 }
 
 // Normalise the areas of each (cell, pair) list into weights A / sum A and
-// give every segment its sweep record: cell, list position, length, weight.
+// give every segment its sweep record: cell and length, packed so that the
+// sweep reads both with one load.
 __global__ void k_csr_norm(const int* __restrict__ csr_off, int64_t n_keys, const int* __restrict__ csr_ray,
                            const int2* __restrict__ csr_t, const int* __restrict__ seg_off,
                            const int* __restrict__ cell, const double* __restrict__ len, double* csr_w,
-                           float* csr_w32, int2* gi, double2* gf64, float2* gf32, int* err) {
+                           float* csr_w32, int2* seg32, int4* seg64, int* err) {
     int64_t key = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (key >= n_keys) return;
     int b = csr_off[key], e = csr_off[key + 1];
@@ -255,9 +256,8 @@ __global__ void k_csr_norm(const int* __restrict__ csr_off, int64_t n_keys, cons
         csr_w[q] = w;
         csr_w32[q] = (float)w;
         const int j = seg_off[csr_ray[q]] + csr_t[q].x;
-        gi[j] = make_int2(cell[j], q);
-        gf64[j] = make_double2(len[j], w);
-        gf32[j] = make_float2((float)len[j], (float)w);
+        seg32[j] = make_int2(cell[j], __float_as_int((float)len[j]));
+        seg64[j] = make_int4(cell[j], 0, __double2loint(len[j]), __double2hiint(len[j]));
     }
 }
 
@@ -654,12 +654,11 @@ lc_status build_geometry(Rays* r, hipStream_t st) {
     hipLaunchKernelGGL(k_csr_fill, dim3(nblk(nr)), dim3(kBlock), 0, st, r->d_ray_off, P, nr,
                        r->d_seg_off, r->d_cell, r->d_len, r->d_width, r->d_csr_off, d_kfirst,
                        r->d_csr_ray, r->d_csr_t, r->d_csr_w, d_err);
-    LC_STEP(dalloc(r->owned, &r->d_gi, ns));
-    LC_STEP(dalloc(r->owned, &r->d_gf64, ns));
-    LC_STEP(dalloc(r->owned, &r->d_gf32, ns));
+    LC_STEP(dalloc(r->owned, &r->d_seg32, ns));
+    LC_STEP(dalloc(r->owned, &r->d_seg64, ns));
     hipLaunchKernelGGL(k_csr_norm, dim3(nblk(n_keys)), dim3(kBlock), 0, st, r->d_csr_off, n_keys,
                        r->d_csr_ray, r->d_csr_t, r->d_seg_off, r->d_cell, r->d_len, r->d_csr_w,
-                       r->d_csr_w32, r->d_gi, r->d_gf64, r->d_gf32, d_err);
+                       r->d_csr_w32, r->d_seg32, r->d_seg64, d_err);
     LC_HIPC(hipGetLastError());
 
     // F(f, m) on the boundary: rays leaving through each face, per traversal

@@ -78,9 +78,8 @@ struct Rays {
     int2* d_csr_t = nullptr;          // [n_seg] position of the segment in the d = 0 and d = 1 traversal
     double* d_csr_w = nullptr;        // [n_seg] A_j / sum of A over C(i, m)
     float* d_csr_w32 = nullptr;
-    int2* d_gi = nullptr;             // [n_seg] {cell, position in the cell-major lists} (sweep record)
-    double2* d_gf64 = nullptr;        // [n_seg] {length, area weight} (sweep record)
-    float2* d_gf32 = nullptr;
+    int2* d_seg32 = nullptr;          // [n_seg] sweep record {cell, bits of the float32 length}
+    int4* d_seg64 = nullptr;          // [n_seg] sweep record {cell, 0, low and high words of the float64 length}
     int* d_bmap = nullptr;            // [nb][n_pairs][2][2] first, end global ray leaving through b; -1 = incoming
     double* d_dirw = nullptr;         // [n_pairs][2][n_pol][kDirW]
     // interior-face crossing lists, built on request (lc_plan_enable_faces):

@@ -31,8 +31,7 @@ struct SweepArgs {
     const int* ray_off;
     const int* seg_off;
     const int* face;
-    const int2* gi;          // [n_seg] {cell, position in the cell-major lists}
-    const void* gf;          // [n_seg] {length, area weight} as double2 or float2
+    const void* seg;         // [n_seg] {cell, length}: int2 (float32 bits) or int4 (cell, 0, float64 words)
     const void* coef;        // Coef<T> [cells][G]
     const void* prev;        // state values
     void* next;
@@ -147,6 +146,7 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 // Two-component records (int2, float2/double2, Coef<T>) loaded as native
 // clang vectors: the HIP class types cannot be copied out of address space 1.
 template <typename E> using vec2 = E __attribute__((ext_vector_type(2)));
+template <typename E> using vec4 = E __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int2 ld2(gptr<const int2> p) {
     const vec2<int> v = *(gptr<const vec2<int>>)p;
     return make_int2(v.x, v.y);
@@ -236,9 +236,6 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
     const int tb = SPLIT ? chunk * S.len : 0;
     const int te = SPLIT ? min(tb + S.len, L) : L;
     const int az = a + d * (A.n_az >> 1);
-    using T2 = typename Vec2<T>::type;
-    const gptr<const int2> gi = as_global(A.gi);
-    const gptr<const T2> gf = as_global(static_cast<const T2*>(A.gf));
     const gptr<const Coef<T>> coef = as_global(static_cast<const Coef<T>*>(A.coef));
     const size_t boff = (size_t)d * A.half + (size_t)as_global(A.bun_base)[B] + (size_t)lane * P;
     const gptr<const T> xin = as_global(static_cast<const T*>(A.prev) + boff);
@@ -363,9 +360,19 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
         }
     };
 
-    // of each segment record the sweep needs the cell index and the length only
-    const gptr<const int> gcell = (gptr<const int>)gi;
-    const gptr<const T> glen = (gptr<const T>)gf;
+    // a segment's cell index and length arrive in one load
+    const gptr<const int> gseg = as_global(static_cast<const int*>(A.seg));
+    auto seg_rec = [&](int j, int& cell, T& len) {
+        if constexpr (sizeof(T) == 4) {
+            const vec2<int> v = *(gptr<const vec2<int>>)(gseg + 2 * (size_t)j);
+            cell = v.x;
+            len = __int_as_float(v.y);
+        } else {
+            const vec4<int> v = *(gptr<const vec4<int>>)(gseg + 4 * (size_t)j);
+            cell = v.x;
+            len = __hiloint2double(v.w, v.z);
+        }
+    };
     int cell1[U];
     T len0[U], len1[U];
     Coef<T> c0[U];
@@ -373,11 +380,10 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int j0 = seg(tb + u), j1 = seg(tb + U + u);
-        const int cell0 = gcell[2 * (size_t)j0];
-        len0[u] = glen[2 * (size_t)j0];
+        int cell0;
+        seg_rec(j0, cell0, len0[u]);
         c0[u] = ld2(coef + ((size_t)cell0 * G + g));
-        cell1[u] = gcell[2 * (size_t)j1];
-        len1[u] = glen[2 * (size_t)j1];
+        seg_rec(j1, cell1[u], len1[u]);
         load_row(srow(tb + u), x0[u]);
     }
     for (int t0 = tb; t0 < te; t0 += U) {
@@ -390,8 +396,7 @@ __device__ __forceinline__ void sweep_wave(const SweepArgs& A, int64_t w, int la
             c1[u] = ld2(coef + ((size_t)cell1[u] * G + g));
             load_row(srow(t0 + U + u), x1[u]);
             const int j2 = seg(t0 + 2 * U + u);
-            cell2[u] = gcell[2 * (size_t)j2];
-            len2[u] = glen[2 * (size_t)j2];
+            seg_rec(j2, cell2[u], len2[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -711,8 +716,7 @@ void make_batch_args(Plan* pl, double c_dt, void* state_a, void* state_b, const 
         A.ray_off = r->d_ray_off;
         A.seg_off = r->d_seg_off;
         A.face = r->d_face;
-        A.gi = r->d_gi;
-        A.gf = f32 ? static_cast<const void*>(r->d_gf32) : static_cast<const void*>(r->d_gf64);
+        A.seg = f32 ? static_cast<const void*>(r->d_seg32) : static_cast<const void*>(r->d_seg64);
         A.coef = pl->d_coef;
         A.prev = state_values(pl, prev);
         A.next = state_values(pl, next);
@@ -881,8 +885,7 @@ lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, doub
     A.ray_off = r->d_ray_off;
     A.seg_off = r->d_seg_off;
     A.face = r->d_face;
-    A.gi = r->d_gi;
-    A.gf = f32 ? static_cast<const void*>(r->d_gf32) : static_cast<const void*>(r->d_gf64);
+    A.seg = f32 ? static_cast<const void*>(r->d_seg32) : static_cast<const void*>(r->d_seg64);
     A.coef = pl->d_coef;
     A.prev = state_values(pl, state_prev);
     A.next = state_values(pl, state_new);
