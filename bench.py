@@ -57,8 +57,9 @@ SWEEP_SOURCES = ("sweep.hip", "batch.hip", "lc_internal.hpp")
 
 def recorded_traffic(tuning):
     """HBM bytes per sweep phase measured with rocprofv3 counters for this
-    workload, or None when the sweep sources or the sweep tuning differ from
-    those the counters were taken with."""
+    workload (the recorded bytes per launch of each polar group's sweep at
+    its chosen sweep_unroll, summed), or None when the sweep sources differ
+    from those the counters were taken with or a choice was not recorded."""
     import hashlib
     try:
         rec = dict(line.split(" ", 1) for line in open(TRAFFIC_RECORD).read().splitlines()
@@ -71,10 +72,14 @@ def recorded_traffic(tuning):
             h.update(fh.read())
     if rec.get("source_sha256", "").strip() != h.hexdigest():
         return None
-    sweep_tuning = {k: v["sweep_unroll"] for k, v in tuning.items()}
-    if json.loads(rec.get("sweep_unroll", "null")) != sweep_tuning:
-        return None
-    return float(rec["traffic_bytes"])
+    per = json.loads(rec.get("traffic_bytes_per_launch", "null")) or {}
+    total = 0.0
+    for pm, v in tuning.items():
+        b = per.get(str(pm), {}).get(str(v["sweep_unroll"]))
+        if b is None:
+            return None
+        total += b
+    return total
 
 
 def moment_errors(got, ref):
