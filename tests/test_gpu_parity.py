@@ -248,16 +248,18 @@ def _sampled_cells(prob, n, seed):
     return np.array(cells + [0, prob.cells - 1])          # include two corner cells
 
 
-@pytest.mark.parametrize("cfg,prec", [(1, 0), (2, 0), (2, 1)])
-def test_full_size_sampled_cells(lcmod, cfg, prec):
+@pytest.mark.parametrize("cfg,prec,split", [(1, 0, 0), (2, 0, 0), (2, 1, 0), (1, 1, 256), (1, 0, 32)])
+def test_full_size_sampled_cells(lcmod, cfg, prec, split):
     """Full-size workloads: every sampled cell's moments against the oracle,
     which sweeps only the characteristics crossing those cells (exact, since
-    characteristics evolve independently under prescribed material data)."""
+    characteristics evolve independently under prescribed material data).
+    The 128^2 problem also runs as the split sweep (chunks of 256 steps are
+    what the tuner picks for it in float32)."""
     lc, driver = lcmod
     prob = W.config(cfg)
     tol = TOL64 if prec == 0 else TOL32
-    _say(f"config {cfg} prec {prec}: GPU run")
-    s = driver.Solver(prob, prec=prec)
+    _say(f"config {cfg} prec {prec} split {split}: GPU run")
+    s = driver.Solver(prob, prec=prec, split=split)
     s.reset()
     s.step(prob.steps)
     got = s.moments()
