@@ -42,8 +42,7 @@ __device__ int face_of(int nx, int ny, double hx, double hy, double x, double y,
 // are merged.  Returns the number of segments; FILL writes them.
 template <bool FILL>
 __device__ int walk(int nx, int ny, double lx, double ly, double hx, double hy, double c, double s,
-                    double v, int* face2, double* pts4, int* cell_out, double* len_out,
-                    float* len32_out, int cap) {
+                    double v, int* face2, double* pts4, int* cell_out, double* len_out, int cap) {
     const double tol = 1e-12 * fmin(hx, hy);
     const double ux0 = (0.0 + v * s) / c, ux1 = (lx + v * s) / c;
     const double uy0 = (0.0 - v * c) / s, uy1 = (ly - v * c) / s;
@@ -83,7 +82,6 @@ __device__ int walk(int nx, int ny, double lx, double ly, double hx, double hy, 
             if (FILL && n < cap) {
                 cell_out[n] = iy * nx + ix;
                 len_out[n] = u_out - u_cur;
-                len32_out[n] = (float)(u_out - u_cur);
             }
             return n + 1;
         }
@@ -91,7 +89,6 @@ __device__ int walk(int nx, int ny, double lx, double ly, double hx, double hy, 
             if (FILL && n < cap) {
                 cell_out[n] = iy * nx + ix;
                 len_out[n] = un - u_cur;
-                len32_out[n] = (float)(un - u_cur);
             }
             ++n;
             u_cur = un;
@@ -115,17 +112,17 @@ template <bool FILL>
 __global__ void k_trace(const int* __restrict__ ray_off, const PairGeo* __restrict__ geo, int n_pairs,
                         int n_rays, int nx, int ny, double lx, double ly, double hx, double hy,
                         const double* __restrict__ v, int* count, int* face, double* pts,
-                        const int* __restrict__ seg_off, int* cell, double* len, float* len32) {
+                        const int* __restrict__ seg_off, int* cell, double* len) {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_rays) return;
     int a = find_pair(ray_off, n_pairs, k);
     if (FILL) {
         int o = seg_off[k];
         walk<true>(nx, ny, lx, ly, hx, hy, geo[a].c, geo[a].s, v[k], nullptr, nullptr, cell + o,
-                   len + o, len32 + o, seg_off[k + 1] - o);
+                   len + o, seg_off[k + 1] - o);
     } else {
         count[k] = walk<false>(nx, ny, lx, ly, hx, hy, geo[a].c, geo[a].s, v[k], face + 2 * k,
-                               pts + 4 * k, nullptr, nullptr, nullptr, 0);
+                               pts + 4 * k, nullptr, nullptr, 0);
     }
 }
 
@@ -602,7 +599,7 @@ lc_status build_geometry(Rays* r, hipStream_t st) {
     }
     hipLaunchKernelGGL(k_trace<false>, dim3(nblk(nr)), dim3(kBlock), 0, st, r->d_ray_off, d_geo, P, nr,
                        r->nx, r->ny, r->lx, r->ly, r->hx, r->hy, r->d_v, d_count, r->d_face, r->d_pts,
-                       nullptr, nullptr, nullptr, nullptr);
+                       nullptr, nullptr, nullptr);
     LC_HIPC(hipGetLastError());
     LC_STEP(scan_counts(d_count, r->d_seg_off, nr, tmp, st));
     int total = 0;
@@ -628,10 +625,9 @@ lc_status build_geometry(Rays* r, hipStream_t st) {
     const int64_t ns = total;
     LC_STEP(dalloc(r->owned, &r->d_cell, ns));
     LC_STEP(dalloc(r->owned, &r->d_len, ns));
-    LC_STEP(dalloc(r->owned, &r->d_len32, ns));
     hipLaunchKernelGGL(k_trace<true>, dim3(nblk(nr)), dim3(kBlock), 0, st, r->d_ray_off, d_geo, P, nr,
                        r->nx, r->ny, r->lx, r->ly, r->hx, r->hy, r->d_v, nullptr, nullptr, nullptr,
-                       r->d_seg_off, r->d_cell, r->d_len, r->d_len32);
+                       r->d_seg_off, r->d_cell, r->d_len);
     LC_HIPC(hipGetLastError());
 
     // C(i, m): cell-major lists per (cell, pair)

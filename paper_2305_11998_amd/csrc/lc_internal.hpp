@@ -72,7 +72,6 @@ struct Rays {
     double* d_pts = nullptr;          // [n_rays][4] entry x, y, exit x, y
     int* d_cell = nullptr;            // [n_seg]
     double* d_len = nullptr;          // [n_seg]
-    float* d_len32 = nullptr;         // [n_seg]
     int* d_csr_off = nullptr;         // [cells * n_pairs + 1], index cell * n_pairs + a
     int* d_csr_ray = nullptr;         // [n_seg] global ray k of the entry
     int2* d_csr_t = nullptr;          // [n_seg] position of the segment in the d = 0 and d = 1 traversal
@@ -120,7 +119,7 @@ struct Plan {
     size_t value_bytes = 0;
     void* d_coef = nullptr;           // [cells][G] {kappa_t, kappa B / kappa_t}
     unsigned long long* d_gmax = nullptr;  // [G] per-group source maxima of a step (float32 scale)
-    int sweep_unroll = 0;             // steps whose loads are issued together (1, 2, 4)
+    int sweep_unroll = 0;             // steps whose loads are issued together (1, 2, 4, 8 or 16)
     int moments_entries = 0;          // C(i, m) entries per list in the moment pipeline (1..4)
     // State layout: the lanes (k, g) of pair a, g fastest, are cut into
     // bundles of 64 (one wavefront each).  For traversal d and bundle B the

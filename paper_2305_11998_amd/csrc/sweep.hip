@@ -3,13 +3,16 @@
 // Work decomposition: the lanes (characteristic k, group g) of an azimuth
 // pair, g fastest, are cut into bundles of 64 -- one wavefront per bundle and
 // traversal.  Each lane walks its characteristic segment by segment, carrying
-// the intensity of every polar angle p in registers; per segment it reads one
-// cell-coefficient record (coalesced over g), the stored I_bar^{n-1} of every
-// p, and writes I_bar^n.  The state is laid out bundle-major, step-minor, so
+// the intensity of every polar angle p in registers; per segment it reads the
+// segment's packed {cell, length} record (one load), one cell-coefficient
+// record (coalesced over g) and the stored I_bar^{n-1} of every p, and writes
+// I_bar^n.  The state is laid out bundle-major, step-minor, so
 // every wavefront streams its own contiguous, aligned 64-lane runs.  Polar
 // angles with equal sin(zeta) (the +mu/-mu pairs of a symmetric set) share
 // the exponential and the weight alpha.  Blocks are remapped so that each
-// XCD's L2 serves a contiguous band of characteristics.
+// XCD's L2 serves a contiguous band of characteristics.  A split form cuts
+// each traversal into chunks whose affine transfer maps are composed by a
+// scan (for problems with too few lanes to fill the device).
 #include <algorithm>
 #include <climits>
 #include <cmath>
@@ -842,6 +845,8 @@ lc_status plan_set_split(Plan* pl, int len) {
     auto put = [&](void** dst, const void* src, size_t bytes) {
         if (rc != LC_OK) return;
         if (hipMalloc(dst, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            *dst = nullptr;
             set_error("hipMalloc of %zu bytes for the split sweep failed", bytes);
             rc = LC_ERR_ALLOC;
             return;
