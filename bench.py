@@ -288,7 +288,8 @@ def run_single(k, steps, warmup):
                          grey=grey,
                          upd=s.updates_per_step(), moments=s.moments(),
                          alg=sweep_algorithmic_bytes(s, 4 if prec == lc.LC_F32 else 8),
-                         tuning={kk: tuned.get(kk, 0) for kk in ("sweep_unroll", "moments_entries", "split")})
+                         tuning={kk: tuned.get(kk, 0) for kk in ("sweep_unroll", "moments_entries", "sweep_capped",
+                                                                 "split")})
         out[name]["faces"] = time_faces(s) if prec == lc.LC_F32 else None     # after the moments above
         _say(f"config {k} {name}: {out[name]['ms']:.3f} ms/step, sweep {out[name]['sweep_ms']:.3f} ms, "
              f"moments {out[name]['moments_ms']:.3f} ms")

@@ -318,6 +318,18 @@ lc_status lc_plan_set_tuning(lc_plan_t plan, const lc_tuning_t* tuning);
 lc_status lc_plan_get_tuning(lc_plan_t plan, lc_tuning_t* tuning);
 
 /*
+ * Residency of the whole-traversal sweep of a plan.  capped = 1 (the
+ * default): every sweep block reserves a third of a CU's LDS, so at most two
+ * blocks (two wavefronts per SIMD) stay resident -- the streams of large
+ * problems are served better by the caches that way; capped = 0: residency
+ * is set by the kernel's registers alone, which shortens the tail of small
+ * problems.  Results are bit-identical either way.  Batches keep the cap.
+ * Drops the plan's captured graphs.  Errors: LC_ERR_ARG for a value other
+ * than 0 or 1.
+ */
+lc_status lc_plan_set_sweep_residency(lc_plan_t plan, int32_t capped);
+
+/*
  * Split sweep (in-ray parallel scan), for problems with few lanes and long
  * characteristics.  The step of eq. (12) is affine in the intensity entering
  * a segment, so a traversal cut into chunks of chunk_steps steps maps the

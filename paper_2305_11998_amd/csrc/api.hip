@@ -466,6 +466,22 @@ lc_status lc_plan_set_tuning(lc_plan_t plan, const lc_tuning_t* t) {
     return LC_OK;
 }
 
+lc_status lc_plan_set_sweep_residency(lc_plan_t plan, int32_t capped) {
+    Plan* pl = as_plan(plan);
+    LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
+    LC_ARG(capped == 0 || capped == 1, "capped must be 0 or 1");
+    size_t lds = 0;
+    if (capped) {
+        lc_status rc = sweep_lds_bytes(&lds);
+        if (rc) return rc;
+    }
+    pl->sweep_lds = lds;
+    for (auto& g : pl->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    pl->graphs.clear();
+    return LC_OK;
+}
+
 lc_status lc_plan_set_split(lc_plan_t plan, int32_t chunk_steps) {
     Plan* pl = as_plan(plan);
     LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");

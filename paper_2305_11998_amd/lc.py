@@ -84,6 +84,7 @@ _SIGS = {
     "lc_plan_set_tuning": ([_vp, C.POINTER(lc_tuning_t)], C.c_int),
     "lc_plan_get_tuning": ([_vp, C.POINTER(lc_tuning_t)], C.c_int),
     "lc_plan_set_split": ([_vp, _i32], C.c_int),
+    "lc_plan_set_sweep_residency": ([_vp, _i32], C.c_int),
     "lc_plan_profile": ([_vp, _i32], C.c_int),
     "lc_plan_profile_read": ([_vp, _vp], C.c_int),
     "lc_batch_create": ([_i32, C.POINTER(lc_problem_t), C.POINTER(_vp)], C.c_int),
@@ -318,6 +319,10 @@ def lc_grey_closures_dims(cells: int, G: int, E, F, f, kappa, planck, out, strea
 def lc_plan_set_tuning(plan: Plan, sweep_unroll: int, moments_entries: int):
     t = lc_tuning_t(int(sweep_unroll), int(moments_entries))
     _check(_lib.lc_plan_set_tuning(plan.handle, C.byref(t)))
+
+
+def lc_plan_set_sweep_residency(plan: Plan, capped: bool):
+    _check(_lib.lc_plan_set_sweep_residency(plan.handle, int(bool(capped))))
 
 
 def lc_plan_set_split(plan: Plan, chunk_steps: int):

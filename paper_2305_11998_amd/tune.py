@@ -62,10 +62,11 @@ def sweep_candidates(prec: int, n_pol: int):
 
 
 def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool = False):
-    """Pick (sweep_unroll, moments_entries), then the split sweep's chunk
-    length (0 = whole traversals), for ``solver.plan`` by timing ``reps``
-    eager steps per candidate.  Leaves the choice set on the plan and
-    returns it with the measured times (ms per launch)."""
+    """Pick (sweep_unroll, moments_entries), then the residency cap of the
+    whole-traversal sweep, then the split sweep's chunk length (0 = whole
+    traversals), for ``solver.plan`` by timing ``reps`` eager steps per
+    candidate.  Leaves the choice set on the plan and returns it with the
+    measured times (ms per launch)."""
     import torch
     plan = solver.plan
     key = shape_key(plan)
@@ -73,9 +74,11 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
     if key in db:
         t = db[key]
         lc.lc_plan_set_tuning(plan, t["sweep_unroll"], t["moments_entries"])
+        lc.lc_plan_set_sweep_residency(plan, t.get("sweep_capped", 1))
         lc.lc_plan_set_split(plan, t.get("split", 0))
         return dict(t, cached=True, key=key)
     lc.lc_plan_set_split(plan, 0)
+    lc.lc_plan_set_sweep_residency(plan, 1)
     times = {}
     # the two parameters act on different kernels: vary one with the other fixed
     ucands = sweep_candidates(plan.prec, plan.rays.n_pol)
@@ -98,11 +101,8 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
     best_u = min(ucands, key=lambda u: times[(u, BASE[1])][0])
     best_e = min(MOMENT_CANDIDATES, key=lambda e: times[(BASE[0], e)][1])
     lc.lc_plan_set_tuning(plan, best_u, best_e)
-    # then the split sweep's chunk length (its own load chunk is fixed, so
-    # the unroll above does not act on it); few-lane problems gain from it
-    split_ms = {}
-    for sp in SPLIT_CANDIDATES:
-        lc.lc_plan_set_split(plan, sp)
+
+    def sweep_ms():
         solver.bench_step()
         torch.cuda.synchronize()
         lc.lc_plan_profile_read(plan)
@@ -112,16 +112,34 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
         torch.cuda.synchronize()
         sw, nsw, _, _ = lc.lc_plan_profile_read(plan)
         lc.lc_plan_profile(plan, False)
-        split_ms[sp] = sw / max(nsw, 1)
+        return sw / max(nsw, 1)
+
+    # the residency cap of the whole-traversal sweep (kept unless lifting it
+    # is at least 3% faster: small problems, where the tail dominates)
+    cap_ms = {1: sweep_ms()}
+    lc.lc_plan_set_sweep_residency(plan, 0)
+    cap_ms[0] = sweep_ms()
+    best_c = 0 if cap_ms[0] <= SPLIT_GAIN * cap_ms[1] else 1
+    lc.lc_plan_set_sweep_residency(plan, best_c)
+    if verbose:
+        print(f"  tune {key}: residency capped {cap_ms[1]:.3f} ms, uncapped {cap_ms[0]:.3f} ms",
+              file=sys.stderr, flush=True)
+    # then the split sweep's chunk length (its own load chunk is fixed, so
+    # the unroll above does not act on it); few-lane problems gain from it
+    split_ms = {}
+    for sp in SPLIT_CANDIDATES:
+        lc.lc_plan_set_split(plan, sp)
+        split_ms[sp] = sweep_ms()
         if verbose:
             print(f"  tune {key}: split {sp}: sweep {split_ms[sp]:.3f} ms", file=sys.stderr, flush=True)
     best_s = min(split_ms, key=split_ms.get)
     if split_ms[best_s] > SPLIT_GAIN * split_ms[0]:
         best_s = 0
     lc.lc_plan_set_split(plan, best_s)
-    res = dict(sweep_unroll=best_u, moments_entries=best_e, split=best_s,
+    res = dict(sweep_unroll=best_u, moments_entries=best_e, sweep_capped=best_c, split=best_s,
                sweep_ms={str(k): v[0] for k, v in times.items()},
                moments_ms={str(k): v[1] for k, v in times.items()},
+               capped_ms={str(k): v for k, v in cap_ms.items()},
                split_ms={str(k): v for k, v in split_ms.items()})
     if cache:
         db[key] = res

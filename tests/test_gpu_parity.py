@@ -222,6 +222,23 @@ def test_tuning_settings_give_identical_results(lcmod, prec, mode, h_moc, n_pol)
         assert np.array_equal(st, out[0][1])
 
 
+def test_sweep_residency_gives_identical_results(lcmod):
+    """The residency cap of the sweep changes occupancy only."""
+    lc, driver = lcmod
+    prob = _custom_problem(G=7, steps=2)
+    outs = []
+    for capped in (1, 0):
+        s = driver.Solver(prob, prec=lc.LC_F32)
+        lc.lc_plan_set_sweep_residency(s.plan, capped)
+        s.reset()
+        s.step(2)
+        m = s.moments()
+        outs.append((s.state_canonical(), s.exits(), m["E"], m["F"], m["f"], m["bnd"]))
+        assert lc._lib.lc_plan_set_sweep_residency(s.plan.handle, 2) == lc.LC_ERR_ARG
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
+
+
 @pytest.mark.parametrize("G,prec", [(66, 0), (100, 0), (100, 1), (260, 1)])
 def test_many_groups_span_three_bundles(lcmod, G, prec):
     """G > 64: a characteristic's groups can span three 64-lane bundles (the

@@ -142,6 +142,7 @@ def test_tuner_choice_is_cached_with_the_split(lcmod, tmp_path):
     b = driver.Solver(prob, prec=lc.LC_F32)
     tb = tune.tune(b, reps=1, cache=cache)
     assert tb["cached"] and tb["split"] == ta["split"] and tb["sweep_unroll"] == ta["sweep_unroll"]
+    assert tb["sweep_capped"] == ta["sweep_capped"] and ta["sweep_capped"] in (0, 1)
     for s in (a, b):
         s.reset()
         s.step(1)
