@@ -23,7 +23,7 @@ SWEEP_CANDIDATES_F32 = (2, 4, 8, 16)   # 16: float32 with at most MAX_POL_UNROLL
 MAX_POL_UNROLL16 = 4
 MOMENT_CANDIDATES = (1, 2, 3, 4)
 SPLIT_CANDIDATES = (0, 32, 64, 128, 256)   # chunk steps of the split sweep, 0 = whole traversals
-SPLIT_GAIN = 0.97          # a split form is kept only if at least 3% faster than whole traversals
+MIN_GAIN = 0.97            # an uncapped or split sweep is kept only if at least 3% faster than the default
 BASE = (4, 3)             # the setting the other parameter is held at while one is searched
 DEFAULT_CACHE = os.environ.get(
     "LC_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "lc_tuning.json"))
@@ -79,13 +79,9 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
         return dict(t, cached=True, key=key)
     lc.lc_plan_set_split(plan, 0)
     lc.lc_plan_set_sweep_residency(plan, 1)
-    times = {}
-    # the two parameters act on different kernels: vary one with the other fixed
-    ucands = sweep_candidates(plan.prec, plan.rays.n_pol)
-    combos = sorted({(u, BASE[1]) for u in ucands} | {(BASE[0], e) for e in MOMENT_CANDIDATES})
-    for u, e in combos:
-        lc.lc_plan_set_tuning(plan, u, e)
-        solver.bench_step()                       # warm
+    def timed():
+        """(sweep, moments) ms per launch over reps eager steps, after one warm step."""
+        solver.bench_step()
         torch.cuda.synchronize()
         lc.lc_plan_profile_read(plan)
         lc.lc_plan_profile(plan, True)
@@ -94,32 +90,27 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
         torch.cuda.synchronize()
         sw, nsw, mo, nmo = lc.lc_plan_profile_read(plan)
         lc.lc_plan_profile(plan, False)
-        times[(u, e)] = (sw / max(nsw, 1), mo / max(nmo, 1))
+        return sw / max(nsw, 1), mo / max(nmo, 1)
+
+    times = {}
+    # the two parameters act on different kernels: vary one with the other fixed
+    ucands = sweep_candidates(plan.prec, plan.rays.n_pol)
+    combos = sorted({(u, BASE[1]) for u in ucands} | {(BASE[0], e) for e in MOMENT_CANDIDATES})
+    for u, e in combos:
+        lc.lc_plan_set_tuning(plan, u, e)
+        times[(u, e)] = timed()
         if verbose:
             print(f"  tune {key}: unroll {u} entries {e}: sweep {times[(u, e)][0]:.3f} ms, "
                   f"moments {times[(u, e)][1]:.3f} ms", file=sys.stderr, flush=True)
     best_u = min(ucands, key=lambda u: times[(u, BASE[1])][0])
     best_e = min(MOMENT_CANDIDATES, key=lambda e: times[(BASE[0], e)][1])
     lc.lc_plan_set_tuning(plan, best_u, best_e)
-
-    def sweep_ms():
-        solver.bench_step()
-        torch.cuda.synchronize()
-        lc.lc_plan_profile_read(plan)
-        lc.lc_plan_profile(plan, True)
-        for _ in range(reps):
-            solver.bench_step()
-        torch.cuda.synchronize()
-        sw, nsw, _, _ = lc.lc_plan_profile_read(plan)
-        lc.lc_plan_profile(plan, False)
-        return sw / max(nsw, 1)
-
     # the residency cap of the whole-traversal sweep (kept unless lifting it
     # is at least 3% faster: small problems, where the tail dominates)
-    cap_ms = {1: sweep_ms()}
+    cap_ms = {1: timed()[0]}
     lc.lc_plan_set_sweep_residency(plan, 0)
-    cap_ms[0] = sweep_ms()
-    best_c = 0 if cap_ms[0] <= SPLIT_GAIN * cap_ms[1] else 1
+    cap_ms[0] = timed()[0]
+    best_c = 0 if cap_ms[0] <= MIN_GAIN * cap_ms[1] else 1
     lc.lc_plan_set_sweep_residency(plan, best_c)
     if verbose:
         print(f"  tune {key}: residency capped {cap_ms[1]:.3f} ms, uncapped {cap_ms[0]:.3f} ms",
@@ -129,11 +120,11 @@ def tune(solver, reps: int = 3, cache: str | None = DEFAULT_CACHE, verbose: bool
     split_ms = {}
     for sp in SPLIT_CANDIDATES:
         lc.lc_plan_set_split(plan, sp)
-        split_ms[sp] = sweep_ms()
+        split_ms[sp] = timed()[0]
         if verbose:
             print(f"  tune {key}: split {sp}: sweep {split_ms[sp]:.3f} ms", file=sys.stderr, flush=True)
     best_s = min(split_ms, key=split_ms.get)
-    if split_ms[best_s] > SPLIT_GAIN * split_ms[0]:
+    if split_ms[best_s] > MIN_GAIN * split_ms[0]:
         best_s = 0
     lc.lc_plan_set_split(plan, best_s)
     res = dict(sweep_unroll=best_u, moments_entries=best_e, sweep_capped=best_c, split=best_s,
