@@ -134,7 +134,7 @@ struct Plan {
     int* d_bun_off = nullptr;
     int* d_bun_len = nullptr;
     int64_t* d_bun_base = nullptr;
-    unsigned* d_ent_off = nullptr;    // [n_seg][4] state lane records (P values each) of each C(i, m) entry
+    unsigned* d_ent_off = nullptr;    // [n_seg][4] state lane records (P values each) and float32 weight of each C(i, m) entry
     unsigned* d_fent_off = nullptr;   // [n_fent][4] the same for the interior-face crossings (on request)
     unsigned* d_bun_rec = nullptr;    // [n_bun] first lane record of each bundle
     int tile_w = 1, tile_h = 1;       // cell tile of the moments kernel

@@ -15,12 +15,13 @@ namespace {
 
 struct MomArgs {
     const int* csr_off;       // [cells * n_pairs + 1] cell-major lists C(i, m)
-    const unsigned* ent_off;  // [n_seg][4] per entry: lane records {d0 first/second bundle, d1 first/second};
+    const unsigned* ent_off;  // [n_seg][4] per entry: {lane record in the first bundle for d0, the same for
+                              // d1, offset of the second bundle's records, bits of the float32 weight};
                               // with multi: {first bundle, step d0, step d1, lane of group 0}
     const unsigned* bun_rec;  // [n_bun] first lane record of each bundle (multi only)
     unsigned half_rec;        // lane records of one traversal half
     int multi;                // G > 64: a characteristic's groups may span three or more bundles
-    const void* csr_w;        // area weights A / sum A, double or float
+    const void* csr_w;        // area weights A / sum A, double or float (float32 without multi: unused)
     const double* dirw;       // [n_pairs][2][P][kDirW]
     const void* state;        // values
     const int* e;             // per-group exponents of the state (float32 only)
@@ -66,9 +67,12 @@ __device__ __forceinline__ int64_t xcd_logical_block(int64_t hw, int64_t n) {
 // Lane records of one C(i, m) entry as seen by lane g.  A lane record is the
 // P values of one lane at one step, so element offset = record * P; bundle
 // bases and step rows hold whole multiples of 64 records, so the lane of the
-// ray's group 0 is the first record mod 64.  A slot past the end of its list
-// reads entry 0 (which always exists) and gets weight 0, so every load is
-// unconditional and stays inside the arrays.
+// ray's group 0 is the first record mod 64.  The groups past the first
+// bundle's end sit at a fixed offset in the next bundle, the same for both
+// traversals.  In float32 the entry's weight travels in the same 16-byte
+// record, so an entry costs one load besides its state values.  A slot past
+// the end of its list reads entry 0 (which always exists) and gets weight 0,
+// so every load is unconditional and stays inside the arrays.
 template <typename T> struct Slot {
     unsigned r0, r1;   // this lane's record in the two traversals
     T w;
@@ -81,9 +85,11 @@ __device__ __forceinline__ Slot<T> load_slot(gptr<const unsigned> eo, gptr<const
                                              const MomArgs& A) {
     Slot<T> s;
     const int ee = ok ? e : 0;
-    const T w = cw[ee];
     using U4 = unsigned __attribute__((ext_vector_type(4)));
     const U4 q = *(gptr<const U4>)(eo + (size_t)ee * 4);
+    T w;
+    if (sizeof(T) == 4 && !A.multi) w = (T)__uint_as_float(q.w);
+    else w = cw[ee];
     s.w = ok ? w : (T)0;
     if (A.multi) {
         const unsigned f = q.w + (unsigned)g;        // lane within the bundles from the first
@@ -92,9 +98,9 @@ __device__ __forceinline__ Slot<T> load_slot(gptr<const unsigned> eo, gptr<const
         s.r1 = A.half_rec + base + q.z * kWave + (f & (kWave - 1));
     } else {
         const int lane0 = (int)(q.x & (kWave - 1));  // lane of the ray's group 0
-        const bool first = g < kWave - lane0;
-        s.r0 = (first ? q.x : q.y) + (unsigned)g;
-        s.r1 = (first ? q.z : q.w) + (unsigned)g;
+        const unsigned sh = g < kWave - lane0 ? 0u : q.z;
+        s.r0 = q.x + sh + (unsigned)g;
+        s.r1 = q.y + sh + (unsigned)g;
     }
     return s;
 }
@@ -276,11 +282,14 @@ __global__ __launch_bounds__(kMomWaves * kWave) void k_cell_moments_batch(const 
 
 // Offsets of every C(i, m) entry into the bundle-major state of a plan
 // ([t][lane][p] per bundle): lanes g < 64 - lane0 lie in the bundle of the
-// ray's group 0, the rest in the next bundle.
+// ray's group 0, the rest in the next bundle, whose records for the same
+// step sit 64 (L - 1) records further on (L the first bundle's length) in
+// either traversal.  The entry's float32 weight rides along.
 __global__ void k_entry_offsets(const int* __restrict__ csr_off, const int* __restrict__ csr_ray,
                                 const int2* __restrict__ csr_t, const int* __restrict__ ray_off,
                                 const int* __restrict__ bun_off, const int64_t* __restrict__ bun_base,
-                                int64_t n_keys, int n_pairs, int G, int P, int64_t half, unsigned* out) {
+                                const float* __restrict__ w32, int64_t n_keys, int n_pairs, int G, int P,
+                                int64_t half, unsigned* out) {
     const int64_t key = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (key >= n_keys) return;
     const int a = (int)(key % n_pairs);
@@ -301,16 +310,11 @@ __global__ void k_entry_offsets(const int* __restrict__ csr_off, const int* __re
         // lane records: bases and halves are whole multiples of 64 * P elements
         const int64_t b0 = bun_base[B0] / P, hr = half / P;
         o[0] = (unsigned)(b0 + (int64_t)t.x * kWave + lane0);
-        o[2] = (unsigned)(hr + b0 + (int64_t)t.y * kWave + lane0);
-        if (lane0 + G > kWave) {
-            const int split = kWave - lane0;
-            const int64_t b1 = bun_base[B0 + 1] / P;
-            o[1] = (unsigned)(b1 + (int64_t)t.x * kWave - split);
-            o[3] = (unsigned)(hr + b1 + (int64_t)t.y * kWave - split);
-        } else {
-            o[1] = o[0];
-            o[3] = o[2];
-        }
+        o[1] = (unsigned)(hr + b0 + (int64_t)t.y * kWave + lane0);
+        // group g >= 64 - lane0 sits at record b1 + t * 64 + (g - (64 - lane0))
+        // = (first-bundle record of g) + (b1 - b0) - 64, in both traversals
+        o[2] = lane0 + G > kWave ? (unsigned)(bun_base[B0 + 1] / P - b0 - kWave) : 0u;
+        o[3] = __float_as_uint(w32[e]);
     }
 }
 
@@ -494,7 +498,7 @@ lc_status plan_init_moments(Plan* pl) {
     }
     hipLaunchKernelGGL(k_entry_offsets, dim3((unsigned)((n_keys + kBlock - 1) / kBlock)), dim3(kBlock), 0, 0,
                        r->d_csr_off, r->d_csr_ray, r->d_csr_t, r->d_ray_off, pl->d_bun_off, pl->d_bun_base,
-                       n_keys, r->n_pairs, pl->G, r->n_pol, pl->half_elems, pl->d_ent_off);
+                       r->d_csr_w32, n_keys, r->n_pairs, pl->G, r->n_pol, pl->half_elems, pl->d_ent_off);
     LC_HIP(hipGetLastError());
     LC_HIP(hipDeviceSynchronize());
     // tile: up to 16 x 16 cells, as many as fit in kTileWaves wavefronts
@@ -527,7 +531,7 @@ lc_status plan_enable_faces(Plan* pl, hipStream_t st) {
     if (n_keys > 0) {
         hipLaunchKernelGGL(k_entry_offsets, dim3((unsigned)((n_keys + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
                            r->d_fcsr_off, r->d_fcsr_ray, r->d_fcsr_t, r->d_ray_off, pl->d_bun_off, pl->d_bun_base,
-                           n_keys, r->n_pairs, pl->G, r->n_pol, pl->half_elems, pl->d_fent_off);
+                           r->d_fcsr_w32, n_keys, r->n_pairs, pl->G, r->n_pol, pl->half_elems, pl->d_fent_off);
         LC_HIP(hipGetLastError());
     }
     LC_HIP(hipStreamSynchronize(st));
