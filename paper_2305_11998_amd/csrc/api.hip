@@ -267,7 +267,8 @@ lc_status lc_plan_create(lc_rays_t rays, int32_t G, int32_t prec, lc_plan_t* out
         const size_t coef_bytes = (size_t)r->cells * G * (prec == LC_F32 ? 8 : 16);
         const size_t nbun = (size_t)pl->n_bun;
         e = hipMalloc(&pl->d_coef, coef_bytes);
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_gmax), (size_t)G * sizeof(unsigned long long));
+        if (e == hipSuccess)
+            e = hipMalloc(reinterpret_cast<void**>(&pl->d_gmax), 2 * (size_t)G * sizeof(unsigned long long));
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_off), pl->bun_off.size() * sizeof(int));
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_len), std::max<size_t>(nbun, 1) * sizeof(int));
         if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_base), std::max<size_t>(nbun, 1) * sizeof(int64_t));

@@ -48,7 +48,7 @@ struct Batch {
     void* d_bnd_args = nullptr;         // [n]
     std::vector<PolarClass> cls;
     int* d_counters = nullptr;          // [8 * classes] counters of the sweep queues
-    unsigned long long* d_gmax = nullptr;   // per-group source maxima of every problem
+    unsigned long long* d_gmax = nullptr;   // [2][n_gmax] per-group maxima of |B|, then of |I_in|, of every problem
     int64_t n_gmax = 0, max_blocks = 0, coef_blocks = 0, bnd_blocks = 0;
     int max_G = 1;
     std::vector<GraphEntry> graphs;
@@ -254,7 +254,8 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
         b->max_G = std::max(b->max_G, b->plans[q]->G);
     }
     {
-        hipError_t e = hipMalloc(reinterpret_cast<void**>(&b->d_gmax), (size_t)b->n_gmax * sizeof(unsigned long long));
+        hipError_t e =
+            hipMalloc(reinterpret_cast<void**>(&b->d_gmax), 2 * (size_t)b->n_gmax * sizeof(unsigned long long));
         if (e != hipSuccess) {
             (void)hipGetLastError();
             set_error("hipMalloc of the batch maxima failed: %s", hipGetErrorString(e));
@@ -272,7 +273,7 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
         std::memcpy(hs.data() + (n_problems + q) * sb, two.data() + sb, sb);
         int64_t nmb = 0, ncb = 0;
         make_coef_args(pl, P.c_dt, P.kappa, P.planck, P.material_stride, P.state_a, P.state_b, P.I_in, b->d_gmax,
-                       b->max_blocks, b->coef_blocks, g_off, hc.data() + q * cb, &nmb, &ncb);
+                       b->d_gmax + b->n_gmax, b->max_blocks, b->coef_blocks, g_off, hc.data() + q * cb, &nmb, &ncb);
         b->max_blocks += nmb;
         b->coef_blocks += ncb;
         g_off += pl->G;

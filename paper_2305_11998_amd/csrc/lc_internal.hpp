@@ -118,7 +118,7 @@ struct Plan {
     size_t hdr_bytes = 0;             // state header (per-group scale exponents)
     size_t value_bytes = 0;
     void* d_coef = nullptr;           // [cells][G] {kappa_t, kappa B / kappa_t}
-    unsigned long long* d_gmax = nullptr;  // [G] per-group source maxima of a step (float32 scale)
+    unsigned long long* d_gmax = nullptr;  // [2][G] per-group maxima of |B| and of |I_in| (float32 scale)
     int sweep_unroll = 0;             // steps whose loads are issued together (1, 2, 4, 8 or 16)
     int moments_entries = 0;          // C(i, m) entries per list in the moment pipeline (1..4)
     // State layout: the lanes (k, g) of pair a, g fastest, are cut into
@@ -210,8 +210,9 @@ size_t bnd_args_bytes();
 void make_batch_args(Plan* pl, double c_dt, void* state_a, void* state_b, const double* I_in, double* I_exit,
                      void* sweep_out2);
 void make_coef_args(Plan* pl, double c_dt, const double* kappa, const double* planck, int64_t stride,
-                    void* state_a, void* state_b, const double* I_in, unsigned long long* gmax, int64_t max_blk_off,
-                    int64_t coef_blk_off, int64_t g_off, void* out, int64_t* n_max_blocks, int64_t* n_coef_blocks);
+                    void* state_a, void* state_b, const double* I_in, unsigned long long* gmax,
+                    unsigned long long* gmax_in, int64_t max_blk_off, int64_t coef_blk_off, int64_t g_off, void* out,
+                    int64_t* n_max_blocks, int64_t* n_coef_blocks);
 lc_status launch_prologue(Plan* pl, const double* kappa, const double* planck, double c_dt,
                           const void* state_prev, void* state_new, const double* I_in, hipStream_t st);
 void make_moment_args(Plan* pl, const void* state, const double* I_exit, const double* I_in, double c,

@@ -5,7 +5,9 @@
 //   * k_group_max: the largest |B| and |I_in| of every group, reduced in LDS
 //     and merged with integer atomics on the bit patterns of non-negative
 //     doubles (whose order is the order of the values), so the result is
-//     exact and independent of scheduling;
+//     exact and independent of scheduling.  The incoming intensities do not
+//     change within one call, so their maxima are taken at its first step
+//     only and kept apart for the later ones;
 //   * k_coef: per tile of cells x groups, reads kappa and B in their
 //     [G][cells] layout, forms (kappa_t, a) and writes the [cells][G] table
 //     through an LDS transpose; it also derives the new exponents.
@@ -31,7 +33,8 @@ struct CoefArgs {
     const double* I_in;
     const int* e_state[2];   // headers of state_a, state_b
     void* coef;              // Coef<T> [cells][G]
-    unsigned long long* gmax;// [G] maxima as bit patterns (zeroed before the step)
+    unsigned long long* gmax;// [G] maxima of |B| as bit patterns (zeroed before the step)
+    unsigned long long* gmax_in; // [G] maxima of |I_in| (zeroed before the first step of a call)
     int gt, ct;              // k_coef tile: gt groups x ct cells
     int64_t pl_blocks;       // k_group_max blocks over B (the rest cover I_in)
     int64_t max_blk_off;     // first block of this problem in a batched k_group_max
@@ -77,6 +80,7 @@ __device__ __forceinline__ void group_max_block(const CoefArgs& A, int64_t b, in
         if ((t & (kWave - 1)) == 0 && m > 0.0) atomicMax(&A.gmax[g], bits_of(m));
         return;
     }
+    if (step > 0) return;              // I_in maxima: taken at the first step of the call
     for (int g = t; g < G; g += kBlock) smax[g] = 0ull;
     __syncthreads();
     // rows [r0, r1) of the [nb*M][G] I_in array
@@ -111,7 +115,7 @@ __device__ __forceinline__ void group_max_block(const CoefArgs& A, int64_t b, in
     }
     __syncthreads();
     for (int q = t; q < G; q += kBlock)
-        if (smax[q]) atomicMax(&A.gmax[q], smax[q]);
+        if (smax[q]) atomicMax(&A.gmax_in[q], smax[q]);
 }
 
 // Block b of the coefficients of one problem: groups [g0, g0 + gt) of cells
@@ -132,7 +136,8 @@ __device__ __forceinline__ void coef_block(const CoefArgs& A, int64_t b, int ste
         int* e_new = const_cast<int*>(A.e_state[(step + 1) & 1]);
         for (int q = t; q < ng; q += kBlock) {
             int e = e_prev[g0 + q];
-            const double m = __longlong_as_double((long long)A.gmax[g0 + q]);
+            const unsigned long long mb = max(A.gmax[g0 + q], A.gmax_in[g0 + q]);
+            const double m = __longlong_as_double((long long)mb);
             if (m > 0.0 && isfinite(m)) e = max(e, ilogb(m) + 1);
             s_e[q] = e;
             if (c0 == 0) e_new[g0 + q] = e;
@@ -207,7 +212,8 @@ inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBl
 template <typename T> size_t coef_lds() { return (size_t)kCoefTile * sizeof(int) + (size_t)kCoefTile * sizeof(Coef<T>); }
 
 CoefArgs coef_args(const Plan* pl, double c_dt, const double* kappa, const double* planck, int64_t stride,
-                   const void* state_a, const void* state_b, const double* I_in, unsigned long long* gmax) {
+                   const void* state_a, const void* state_b, const double* I_in, unsigned long long* gmax,
+                   unsigned long long* gmax_in) {
     const Rays* r = pl->rays;
     CoefArgs C{};
     C.kappa = kappa;
@@ -222,6 +228,7 @@ CoefArgs coef_args(const Plan* pl, double c_dt, const double* kappa, const doubl
     C.e_state[1] = static_cast<const int*>(state_b);
     C.coef = pl->d_coef;
     C.gmax = gmax;
+    C.gmax_in = gmax_in;
     C.gt = std::min(pl->G, kCoefTile);
     C.ct = std::max(1, kCoefTile / C.gt);
     C.pl_blocks = (int64_t)pl->G * ((r->cells + kMaxChunk - 1) / kMaxChunk);
@@ -246,9 +253,12 @@ lc_status launch_prologue(Plan* pl, const double* kappa, const double* planck, d
                           const void* state_prev, void* state_new, const double* I_in, hipStream_t st) {
     const bool f32 = pl->prec == LC_F32;
     // the kernels index the state headers by step parity: step 0 reads e_state[0]
-    CoefArgs C = coef_args(pl, c_dt, kappa, planck, 0, state_prev, state_new, I_in, pl->d_gmax);
+    // d_gmax holds the |B| maxima, then the |I_in| maxima; a single step is
+    // the first of its call, so both are formed
+    CoefArgs C = coef_args(pl, c_dt, kappa, planck, 0, state_prev, state_new, I_in, pl->d_gmax, pl->d_gmax + pl->G);
     if (f32) {
-        hipLaunchKernelGGL(k_zero_u64, dim3(blocks_for(pl->G)), dim3(kBlock), 0, st, pl->d_gmax, (int64_t)pl->G);
+        hipLaunchKernelGGL(k_zero_u64, dim3(blocks_for(2 * (int64_t)pl->G)), dim3(kBlock), 0, st, pl->d_gmax,
+                           2 * (int64_t)pl->G);
         hipLaunchKernelGGL(k_group_max, dim3((unsigned)max_blocks(C)), dim3(kBlock),
                            (size_t)pl->G * sizeof(unsigned long long), st, C);
         hipLaunchKernelGGL(k_coef<float>, dim3((unsigned)coef_blocks(C)), dim3(kBlock), coef_lds<float>(), st, C, 0);
@@ -262,9 +272,10 @@ lc_status launch_prologue(Plan* pl, const double* kappa, const double* planck, d
 
 // Host record of one problem of a batch; returns its block counts.
 void make_coef_args(Plan* pl, double c_dt, const double* kappa, const double* planck, int64_t stride,
-                    void* state_a, void* state_b, const double* I_in, unsigned long long* gmax, int64_t max_blk_off,
-                    int64_t coef_blk_off, int64_t g_off, void* out, int64_t* n_max_blocks, int64_t* n_coef_blocks) {
-    CoefArgs C = coef_args(pl, c_dt, kappa, planck, stride, state_a, state_b, I_in, gmax + g_off);
+                    void* state_a, void* state_b, const double* I_in, unsigned long long* gmax,
+                    unsigned long long* gmax_in, int64_t max_blk_off, int64_t coef_blk_off, int64_t g_off, void* out,
+                    int64_t* n_max_blocks, int64_t* n_coef_blocks) {
+    CoefArgs C = coef_args(pl, c_dt, kappa, planck, stride, state_a, state_b, I_in, gmax + g_off, gmax_in + g_off);
     C.max_blk_off = max_blk_off;
     C.coef_blk_off = coef_blk_off;
     C.g_off = g_off;
@@ -273,13 +284,16 @@ void make_coef_args(Plan* pl, double c_dt, const double* kappa, const double* pl
     std::memcpy(out, &C, sizeof(C));
 }
 
-// Prologue of step t of a batch.
+// Prologue of step t of a batch.  gmax holds the |B| maxima of every
+// problem (n_gmax entries) followed by their |I_in| maxima, which are
+// cleared and formed at the first step of a call only.
 lc_status launch_prologue_batch(int prec, const void* coef_args, int n, int64_t max_blocks_all,
                                 int64_t coef_blocks_all, int max_G, unsigned long long* gmax, int64_t n_gmax, int t,
                                 hipStream_t st) {
     const CoefArgs* P = static_cast<const CoefArgs*>(coef_args);
     if (prec == LC_F32) {
-        hipLaunchKernelGGL(k_zero_u64, dim3(blocks_for(n_gmax)), dim3(kBlock), 0, st, gmax, n_gmax);
+        const int64_t nz = t == 0 ? 2 * n_gmax : n_gmax;
+        hipLaunchKernelGGL(k_zero_u64, dim3(blocks_for(nz)), dim3(kBlock), 0, st, gmax, nz);
         hipLaunchKernelGGL(k_group_max_batch, dim3((unsigned)max_blocks_all), dim3(kBlock),
                            (size_t)max_G * sizeof(unsigned long long), st, P, n, t);
         hipLaunchKernelGGL(k_coef_batch<float>, dim3((unsigned)coef_blocks_all), dim3(kBlock), coef_lds<float>(), st,
