@@ -378,8 +378,11 @@ lc_status lc_plan_profile_read(lc_plan_t plan, double* out);
  * every problem (state ping-pong as lc_step; step t reads material data at
  * kappa + t * material_stride, so with a non-zero stride n_steps must not
  * exceed the steps the caller provides); every step forms each problem's
- * moments, and the outputs hold those of the last step.  All problems must
- * share one precision.  I_exit is required.  Errors of lc_batch_create:
+ * moments, and the outputs hold those of the last step.  The incoming
+ * intensities I_in are the same for every step of a call (their float32
+ * scale maxima are taken at its first step); they may change between calls.
+ * All problems must share one precision.  I_exit is required.  Errors of
+ * lc_batch_create:
  * LC_ERR_ARG (no problems; a problem without kappa, planck, states, I_in or
  * I_exit; state_a == state_b; c_dt not finite or <= 0; material_stride < 0;
  * mixed precisions), LC_ERR_STATE (an invalid plan), LC_ERR_UNSUPPORTED
