@@ -1,0 +1,51 @@
+"""CPU: host logic of bench.py -- the counter-traffic record is summed over
+the polar groups at the chosen sweep_unroll, and refused when a choice was
+not recorded or the sweep sources changed."""
+import json
+import os
+
+import pytest
+
+import bench
+
+
+def _record():
+    rec = {}
+    for line in open(bench.TRAFFIC_RECORD).read().splitlines():
+        if line and not line.startswith("#"):
+            k, v = line.split(" ", 1)
+            rec[k] = v
+    return rec
+
+
+def test_traffic_is_the_sum_over_polar_groups():
+    per = json.loads(_record()["traffic_bytes_per_launch"])
+    tuning = {pm: {"sweep_unroll": int(sorted(v)[0])} for pm, v in per.items()}
+    want = sum(per[pm][str(t["sweep_unroll"])] for pm, t in tuning.items())
+    assert bench.recorded_traffic(tuning) == pytest.approx(want, rel=0, abs=0)
+    assert want > 0
+
+
+def test_traffic_refused_for_an_unrecorded_choice():
+    per = json.loads(_record()["traffic_bytes_per_launch"])
+    pm = sorted(per)[0]
+    assert bench.recorded_traffic({pm: {"sweep_unroll": 3}}) is None
+    assert bench.recorded_traffic({"64": {"sweep_unroll": 16}}) is None
+
+
+def test_traffic_refused_when_the_sources_change(tmp_path, monkeypatch):
+    rec = open(bench.TRAFFIC_RECORD).read().replace("source_sha256 ", "source_sha256 0")
+    p = tmp_path / "traffic.txt"
+    p.write_text(rec)
+    monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(p))
+    per = json.loads(_record()["traffic_bytes_per_launch"])
+    tuning = {pm: {"sweep_unroll": int(sorted(v)[0])} for pm, v in per.items()}
+    assert bench.recorded_traffic(tuning) is None
+
+
+def test_more_than_one_gpu_is_refused():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(os.path.dirname(bench.__file__), "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU only" in r.stderr
