@@ -35,6 +35,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
+from .rays import face_centres
 from .sweep import direction_index
 
 N_BND = 8   # Phi+, J+, Phi-, J-, C, fxx, fxy, fyy
@@ -51,11 +52,14 @@ def directions(phi, mu):
     return ox, oy, oz
 
 
-def cell_direction_averages(grid, n_pol, state):
-    """I_{i,m,g} for all cells, directions and groups: [cells][M][G]."""
-    cells = grid.nx * grid.ny
+def cell_direction_averages(grid, n_pol, state, cells=None):
+    """I_{i,m,g} for all cells (or only the listed ones, in their order),
+    directions and groups: [cells][M][G].  Every returned cell must be
+    crossed by a characteristic of every azimuth pair."""
+    n_cells = grid.nx * grid.ny
+    rows_out = np.arange(n_cells) if cells is None else np.asarray(cells, dtype=np.int64)
     G = state.shape[-1]
-    out = np.zeros((cells, grid.n_az * n_pol, G))
+    out = np.zeros((len(rows_out), grid.n_az * n_pol, G))
     for a, pr in enumerate(grid.pairs):
         js, cs, As = [], [], []
         j = pr.seg_base
@@ -64,14 +68,14 @@ def cell_direction_averages(grid, n_pol, state):
             js.append(np.arange(j, j + n)); cs.append(pr.cells[k])
             As.append(pr.lens[k] * pr.w[k])
             j += n
-        js = np.concatenate(js) - pr.seg_base
-        cs = np.concatenate(cs)
-        As = np.concatenate(As)
-        traced = np.bincount(cs, weights=As, minlength=cells)
-        if np.any(traced <= 0.0):
+        js = (np.concatenate(js) - pr.seg_base) if js else np.zeros(0, dtype=np.int64)
+        cs = np.concatenate(cs) if cs else np.zeros(0, dtype=np.int64)
+        As = np.concatenate(As) if As else np.zeros(0)
+        traced = np.bincount(cs, weights=As, minlength=n_cells)
+        if np.any(traced[rows_out] <= 0.0):
             raise ValueError(f"pair {a}: some cell is crossed by no characteristic")
-        Wm = sp.csr_matrix((As / traced[cs], (cs, js)),
-                           shape=(cells, int(pr.nseg.sum())))
+        Wm = sp.csr_matrix((As / np.where(traced > 0.0, traced, 1.0)[cs], (cs, js)),
+                           shape=(n_cells, int(pr.nseg.sum())))[rows_out]
         rows = state[pr.seg_base:pr.seg_base + int(pr.nseg.sum())]
         for d in (0, 1):
             for p in range(n_pol):
@@ -80,10 +84,11 @@ def cell_direction_averages(grid, n_pol, state):
     return out
 
 
-def cell_moments(grid, phi, mu, omega, state, c):
-    """E [G][cells], F [G][2][cells], f [G][4][cells] (xx, xy, yy, zz)."""
+def cell_moments(grid, phi, mu, omega, state, c, cells=None):
+    """E [G][cells], F [G][2][cells], f [G][4][cells] (xx, xy, yy, zz); with
+    ``cells``, only those cells, in their order."""
     n_pol = len(mu)
-    Iim = cell_direction_averages(grid, n_pol, state)      # [cells][M][G]
+    Iim = cell_direction_averages(grid, n_pol, state, cells)    # [cells][M][G]
     return _moments_from_averages(Iim, phi, mu, omega, c)
 
 
@@ -107,15 +112,6 @@ def _moments_from_averages(Iim, phi, mu, omega, c):
     return E, F, f
 
 
-def face_centres(nx, ny, lx, ly):
-    hx, hy = lx / nx, ly / ny
-    yc = (np.arange(ny) + 0.5) * hy
-    xc = (np.arange(nx) + 0.5) * hx
-    return np.concatenate([
-        np.stack([np.zeros(ny), yc], 1), np.stack([np.full(ny, lx), yc], 1),
-        np.stack([xc, np.zeros(nx)], 1), np.stack([xc, np.full(nx, ly)], 1)])
-
-
 def face_normals(nx, ny):
     n = np.zeros((2 * (nx + ny), 2))
     n[:ny] = (-1, 0); n[ny:2 * ny] = (1, 0)
@@ -123,9 +119,10 @@ def face_normals(nx, ny):
     return n
 
 
-def boundary_intensities(grid, mu, exits, I_in):
+def boundary_intensities(grid, mu, exits, I_in, faces=None):
     """I_{b,m,g}: [nb][M][G] (outgoing: width-weighted exit mean; incoming:
-    I_in) and the outgoing mask [nb][M]."""
+    I_in) and the outgoing mask [nb][M].  With ``faces``, only those faces'
+    outgoing entries are formed (the others keep I_in and a False mask)."""
     nx, ny = grid.nx, grid.ny
     nb = 2 * (nx + ny)
     n_pol = len(mu)
@@ -141,7 +138,7 @@ def boundary_intensities(grid, mu, exits, I_in):
             dirn = sign * np.array([pr.c, pr.s])
             fexit = pr.exit_face if d == 0 else pr.entry_face
             pexit = pr.exit_pt if d == 0 else pr.entry_pt
-            for b in range(nb):
+            for b in (range(nb) if faces is None else faces):
                 if normals[b] @ dirn <= 0.0:
                     continue
                 sel = np.nonzero(fexit == b)[0]
@@ -156,15 +153,17 @@ def boundary_intensities(grid, mu, exits, I_in):
     return Ib, out_mask
 
 
-def boundary_factors(grid, phi, mu, omega, exits, I_in):
-    """[G][nb][8]: Phi+, J+, Phi-, J-, C, fxx, fxy, fyy per boundary face."""
-    Ib, out_mask = boundary_intensities(grid, mu, exits, I_in)
+def boundary_factors(grid, phi, mu, omega, exits, I_in, faces=None):
+    """[G][nb][8]: Phi+, J+, Phi-, J-, C, fxx, fxy, fyy per boundary face;
+    with ``faces``, [G][len(faces)][8] for those faces only."""
+    Ib, out_mask = boundary_intensities(grid, mu, exits, I_in, faces)
     nb, M, G = Ib.shape
+    sel = np.arange(nb) if faces is None else np.asarray(faces, dtype=np.int64)
     ox, oy, oz = directions(phi, mu)
     w = np.asarray(omega)
     normals = face_normals(grid.nx, grid.ny)
-    res = np.zeros((G, nb, 8))
-    for b in range(nb):
+    res = np.zeros((G, len(sel), 8))
+    for q, b in enumerate(sel):
         odn = ox * normals[b, 0] + oy * normals[b, 1]           # Omega . n
         o = out_mask[b]
         i = ~o
@@ -180,9 +179,9 @@ def boundary_factors(grid, phi, mu, omega, exits, I_in):
         Syy = ((w * oy * oy)[:, None] * Ib[b]).sum(0)
         z = S == 0.0
         Ss = np.where(z, 1.0, S)
-        res[:, b, 0], res[:, b, 1], res[:, b, 2], res[:, b, 3] = Pp, Jp, Pm, Jm
-        res[:, b, 4] = C
-        res[:, b, 5] = np.where(z, 1 / 3, Sxx / Ss)
-        res[:, b, 6] = np.where(z, 0.0, Sxy / Ss)
-        res[:, b, 7] = np.where(z, 1 / 3, Syy / Ss)
+        res[:, q, 0], res[:, q, 1], res[:, q, 2], res[:, q, 3] = Pp, Jp, Pm, Jm
+        res[:, q, 4] = C
+        res[:, q, 5] = np.where(z, 1 / 3, Sxx / Ss)
+        res[:, q, 6] = np.where(z, 0.0, Sxy / Ss)
+        res[:, q, 7] = np.where(z, 1 / 3, Syy / Ss)
     return res

@@ -109,15 +109,11 @@ def _face_index(nx, ny, lx, ly, x, y, on_x_face, x_side_right):
     return (2 * ny + nx + ix) if x_side_right else (2 * ny + ix)
 
 
-def trace_characteristic(nx, ny, lx, ly, c, s, v):
-    """Cut the characteristic v = const of direction (c, s) into segments.
-
-    All crossings with the interior grid lines x = i hx and y = j hy are
-    collected, sorted and merged; each consecutive pair of points is one
-    segment whose cell is found from its midpoint.  Returns
-    (cells, lens, entry_face, exit_face, entry_pt, exit_pt) or None when the
-    line misses the domain.
-    """
+def endpoints(nx, ny, lx, ly, c, s, v):
+    """Where the characteristic v = const of direction (c, s) enters and
+    leaves the domain: (u_in, u_out, entry_face, exit_face, entry_pt,
+    exit_pt) of the forward (+u) traversal, or None when the line misses the
+    domain (or only grazes it)."""
     hx, hy = lx / nx, ly / ny
     tol = TOL_REL * min(hx, hy)
     # u-interval inside 0 <= x <= lx and 0 <= y <= ly
@@ -139,6 +135,24 @@ def trace_characteristic(nx, ny, lx, ly, c, s, v):
         f_out = _face_index(nx, ny, lx, ly, x_out, y_out, True, c > 0)
     else:
         f_out = _face_index(nx, ny, lx, ly, x_out, y_out, False, s > 0)
+    return u_in, u_out, f_in, f_out, (x_in, y_in), (x_out, y_out)
+
+
+def trace_characteristic(nx, ny, lx, ly, c, s, v):
+    """Cut the characteristic v = const of direction (c, s) into segments.
+
+    All crossings with the interior grid lines x = i hx and y = j hy are
+    collected, sorted and merged; each consecutive pair of points is one
+    segment whose cell is found from its midpoint.  Returns
+    (cells, lens, entry_face, exit_face, entry_pt, exit_pt) or None when the
+    line misses the domain.
+    """
+    hx, hy = lx / nx, ly / ny
+    tol = TOL_REL * min(hx, hy)
+    ends = endpoints(nx, ny, lx, ly, c, s, v)
+    if ends is None:
+        return None
+    u_in, u_out, f_in, f_out, (x_in, y_in), (x_out, y_out) = ends
 
     cross = [(i * hx + v * s) / c for i in range(1, nx)]
     cross += [(j * hy - v * c) / s for j in range(1, ny)]
@@ -218,10 +232,50 @@ def _crossing(v, nx, ny, lx, ly, c, s, cells):
     return keep
 
 
-def build(nx, ny, lx, ly, phi, h_moc, mode=UNIFORM, only_cells=None) -> CharGrid:
-    """Characteristic grid for every azimuth pair of the quadrature.  With
-    ``only_cells``, only the characteristics crossing those cells are traced
-    (enough for their cell moments, which involve no other characteristic)."""
+def face_centres(nx, ny, lx, ly):
+    """Centres [nb][2] of the boundary faces, numbered [0, ny) x = 0 (row iy),
+    [ny, 2ny) x = lx, [2ny, 2ny + nx) y = 0 (column ix), then y = ly."""
+    hx, hy = lx / nx, ly / ny
+    yc = (np.arange(ny) + 0.5) * hy
+    xc = (np.arange(nx) + 0.5) * hx
+    return np.concatenate([
+        np.stack([np.zeros(ny), yc], 1), np.stack([np.full(ny, lx), yc], 1),
+        np.stack([xc, np.zeros(nx)], 1), np.stack([xc, np.full(nx, ly)], 1)])
+
+
+def _leaving(v, nx, ny, lx, ly, c, s, faces):
+    """Offsets of the characteristics whose values on the given boundary
+    faces enter the boundary factors: those that enter or leave the domain
+    through one of the faces, and, per face and traversal, every one whose
+    exit point lies nearest the face's centre (the stand-in for a face that
+    no characteristic of the direction leaves through)."""
+    ends = [endpoints(nx, ny, lx, ly, c, s, vv) for vv in v]
+    inside = np.array([e is not None for e in ends])
+    keep = np.zeros(len(v), dtype=bool)
+    if not inside.any():
+        return keep
+    idx = np.nonzero(inside)[0]
+    f_in = np.array([ends[k][2] for k in idx])
+    f_out = np.array([ends[k][3] for k in idx])
+    p_in = np.array([ends[k][4] for k in idx])
+    p_out = np.array([ends[k][5] for k in idx])
+    centres = face_centres(nx, ny, lx, ly)
+    for b in faces:
+        keep[idx[(f_in == b) | (f_out == b)]] = True
+        for pts in (p_out, p_in):                 # exits of d = 0 and d = 1
+            dist = np.hypot(pts[:, 0] - centres[b, 0], pts[:, 1] - centres[b, 1])
+            keep[idx[dist == dist.min()]] = True
+    return keep
+
+
+def build(nx, ny, lx, ly, phi, h_moc, mode=UNIFORM, only_cells=None, only_faces=None) -> CharGrid:
+    """Characteristic grid for every azimuth pair of the quadrature.
+
+    With ``only_cells`` and/or ``only_faces`` only a subset of the
+    characteristics is traced: those crossing the given cells (enough for
+    their cell moments, which involve no other characteristic) and those
+    whose exit values enter the boundary factors of the given boundary faces.
+    Characteristics keep their order (v ascending) and widths."""
     n_az = len(phi)
     if n_az % 2:
         raise ValueError("azimuths must come in opposite pairs")
@@ -238,8 +292,12 @@ def build(nx, ny, lx, ly, phi, h_moc, mode=UNIFORM, only_cells=None) -> CharGrid
             v, w = uniform_offsets(lx, ly, c, s, h_moc)
         else:
             v, w = tube_offsets(nx, ny, lx, ly, c, s, h_moc)
-        if only_cells is not None:
-            keep = _crossing(v, nx, ny, lx, ly, c, s, only_cells)
+        if only_cells is not None or only_faces is not None:
+            keep = np.zeros(len(v), dtype=bool)
+            if only_cells is not None:
+                keep |= _crossing(v, nx, ny, lx, ly, c, s, only_cells)
+            if only_faces is not None:
+                keep |= _leaving(v, nx, ny, lx, ly, c, s, only_faces)
             v, w = v[keep], w[keep]
         cells, lens, fi, fo, pi, po, vk, wk = [], [], [], [], [], [], [], []
         for vv, ww in zip(v, w):
@@ -250,8 +308,8 @@ def build(nx, ny, lx, ly, phi, h_moc, mode=UNIFORM, only_cells=None) -> CharGrid
             fi.append(r[2]); fo.append(r[3]); pi.append(r[4]); po.append(r[5])
             vk.append(vv); wk.append(ww)
         pr = PairRays(ph, c, s, np.array(vk), np.array(wk), cells, lens,
-                      np.array(fi), np.array(fo), np.array(pi), np.array(po),
-                      base)
+                      np.array(fi, dtype=np.int64), np.array(fo, dtype=np.int64),
+                      np.array(pi).reshape(-1, 2), np.array(po).reshape(-1, 2), base)
         base += int(pr.nseg.sum())
         pairs.append(pr)
     return CharGrid(nx, ny, lx, ly, n_az, h_moc, mode, pairs)

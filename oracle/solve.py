@@ -37,64 +37,38 @@ def run(prob, grid=None, steps=None, c=None, mode=rays.UNIFORM):
     return dict(grid=grid, state=st, exits=exits, steps=hist)
 
 
-def rays_through_cells(grid, cells):
-    """Per pair, the characteristics that cross any of the given cells."""
-    cells = set(int(c) for c in cells)
-    out = []
-    for pr in grid.pairs:
-        out.append(np.array([k for k in range(pr.K)
-                             if cells.intersection(pr.cells[k].tolist())],
-                            dtype=np.int64))
-    return out
+def run_sampled(prob, grid, cells, steps=None, c=None, faces=None):
+    """Moments of a sample of cells (and boundary factors of a sample of
+    boundary faces) at any problem size.
 
+    ``grid`` is the characteristic grid restricted to the characteristics
+    that reach the samples (``rays.build(..., only_cells=cells,
+    only_faces=faces)``).  Under prescribed material data each
+    characteristic evolves independently of the others: its segment states
+    depend only on its own previous states, the material data and the
+    boundary intensity of the face it enters through.  So the plain time loop
+    of ``run`` over that subset gives, step by step, the same segment states
+    as over the whole grid, and the sampled cells' and faces' moments follow
+    from the characteristics reaching them.
 
-def run_sampled(prob, grid, cells, steps=None, c=None):
-    """Cell moments for a sample of cells only, at any problem size: each
-    characteristic evolves independently of the others (material data are
-    prescribed), so sweeping only the characteristics that cross the sampled
-    cells over all steps gives those cells' moments exactly.
-
-    Returns per step a dict {E, F, f} of arrays [G][n_sample] (and [G][2]/[4]
-    components) in the order of ``cells``, plus the swept rays per pair and
-    their final segment rows (for segment-level comparisons)."""
+    Returns per step a dict {E [G][n], F [G][2][n], f [G][4][n]} over the
+    sampled cells, in the order of ``cells``, and ``bnd`` [G][n_faces][8]
+    when ``faces`` is given; plus the grid, final state and exits (for
+    segment-level comparisons)."""
     from workloads import C_LIGHT
     c = C_LIGHT if c is None else c
     n = prob.steps if steps is None else steps
     cells = np.asarray(cells, dtype=np.int64)
-    sel = rays_through_cells(grid, cells)
-    n_pol = prob.n_pol
-    local = []
-    for a, pr in enumerate(grid.pairs):
-        ks = sel[a]
-        X = prob.state0
-        rows = []
-        for k in ks:
-            rows.append(np.broadcast_to(X[:, pr.cells[k]].T[:, None, None, :],
-                                        (len(pr.cells[k]), 2, n_pol, X.shape[0])))
-        local.append(np.concatenate(rows).copy() if rows else None)
+    st = sweep.initial_state(grid, prob.n_pol, prob.state0)
     hist = []
+    exits = None
     for t in range(n):
-        Iim = np.zeros((len(cells), prob.M, prob.G))
-        out_j = []
-        for a, pr in enumerate(grid.pairs):
-            ks = sel[a]
-            if len(ks) == 0:
-                raise ValueError("a sampled cell is crossed by no characteristic")
-            j, rows, _, _ = sweep.sweep_pair(grid, a, prob.mu, prob.kappa[t],
-                                             prob.planck[t], prob.c_dt, local[a],
-                                             prob.I_in, rays=ks, local_state=True)
-            local[a] = rows
-            out_j.append(j)
-            # area-weighted per-direction averages for the sampled cells
-            cs = np.concatenate([pr.cells[k] for k in ks])
-            As = np.concatenate([pr.lens[k] * pr.w[k] for k in ks])
-            for q, cell in enumerate(cells):
-                mask = cs == cell
-                A = As[mask]
-                for d in (0, 1):
-                    for p in range(n_pol):
-                        m = sweep.direction_index(a, d, p, grid.n_az, n_pol)
-                        Iim[q, m, :] = (A[:, None] * rows[mask, d, p, :]).sum(0) / A.sum()
-        E, F, f = moments._moments_from_averages(Iim, prob.phi, prob.mu, prob.omega, c)
-        hist.append(dict(E=E, F=F, f=f))
-    return dict(steps=hist, rays=sel, rows=local, j=out_j)
+        st, exits = sweep.sweep(grid, prob.mu, prob.kappa[t], prob.planck[t],
+                                prob.c_dt, st, prob.I_in)
+        E, F, f = moments.cell_moments(grid, prob.phi, prob.mu, prob.omega, st, c, cells=cells)
+        h = dict(E=E, F=F, f=f)
+        if faces is not None:
+            h["bnd"] = moments.boundary_factors(grid, prob.phi, prob.mu, prob.omega, exits,
+                                                prob.I_in, faces=faces)
+        hist.append(h)
+    return dict(grid=grid, state=st, exits=exits, steps=hist)
