@@ -18,7 +18,27 @@ def _record():
     return rec
 
 
-def test_traffic_is_the_sum_over_polar_groups():
+def _current_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in bench.SWEEP_SOURCES:
+        with open(os.path.join(bench.ROOT, "paper_2305_11998_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _current_record(tmp_path, monkeypatch):
+    """The committed record with the hash of the sources as they are (the
+    summing logic is tested whether or not the counters are current)."""
+    rec = _record()
+    lines = [f"{k} {v}" for k, v in rec.items() if k != "source_sha256"] + [f"source_sha256 {_current_hash()}"]
+    p = tmp_path / "traffic.txt"
+    p.write_text("\n".join(lines) + "\n")
+    monkeypatch.setattr(bench, "TRAFFIC_RECORD", str(p))
+
+
+def test_traffic_is_the_sum_over_polar_groups(tmp_path, monkeypatch):
+    _current_record(tmp_path, monkeypatch)
     per = json.loads(_record()["traffic_bytes_per_launch"])
     tuning = {pm: {"sweep_unroll": int(sorted(v)[0])} for pm, v in per.items()}
     want = sum(per[pm][str(t["sweep_unroll"])] for pm, t in tuning.items())
@@ -26,7 +46,8 @@ def test_traffic_is_the_sum_over_polar_groups():
     assert want > 0
 
 
-def test_traffic_refused_for_an_unrecorded_choice():
+def test_traffic_refused_for_an_unrecorded_choice(tmp_path, monkeypatch):
+    _current_record(tmp_path, monkeypatch)
     per = json.loads(_record()["traffic_bytes_per_launch"])
     pm = sorted(per)[0]
     assert bench.recorded_traffic({pm: {"sweep_unroll": 3}}) is None

@@ -2,7 +2,9 @@
 directions (48 azimuths x 6 polar), spacing h/2, a temperature front moving
 0.25 cm per step, 10 backward-Euler steps -- run as the float32 sweep, with a
 float64 run beside it checking the moments on 1% of the cells after every
-step, and the oracle checking a few cells after the last step."""
+step, and the oracle checking 64 cells (corners, domain edges, both sides of
+moment-tile edges, random ones) and 16 boundary faces after the last
+step."""
 import sys
 
 import numpy as np
@@ -10,7 +12,8 @@ import pytest
 
 import workloads as W
 from oracle import rays as orays, solve as osolve
-from tests.parity_util import err_E, err_F, err_f
+from tests import oracle_pool
+from tests.parity_util import bnd_errors, err_E, err_F, err_f, sample_cells, sample_faces
 
 pytestmark = pytest.mark.gpu
 
@@ -25,6 +28,7 @@ def _sampled(solver, idx):
     return {k: v[:, :, idx].cpu().numpy() for k, v in solver.moment_views().items()}
 
 
+@pytest.mark.timeout(900)
 def test_largest_problem_fp32_with_per_step_fp64_check():
     import torch
     if not torch.cuda.is_available():
@@ -56,16 +60,27 @@ def test_largest_problem_fp32_with_per_step_fp64_check():
         for k in worst:
             worst[k] = max(worst[k], e[k])
     assert worst["E"] <= 1e-5 and worst["F"] <= 1e-5 and worst["f"] <= 1e-5, worst
-    # the float64 run against the oracle on a few cells after the last step
-    few = np.concatenate([rng.choice(cells, 3, replace=False), [0, cells - 1]])
+    # the float64 run against the oracle on 64 cells and 16 boundary faces
+    # after the last step
+    few = sample_cells(prob.nx, prob.ny, 64, 4)
+    faces, _ = sample_faces(prob, 16, 4)
     m64 = _sampled(s64, torch.from_numpy(few).cuda())
+    b64 = s64.bnd.view(G, -1, 8)[:, torch.from_numpy(faces).cuda()].cpu().numpy()
     del s32, s64
     torch.cuda.empty_cache()
-    _say("  oracle on 5 cells, 10 steps")
-    g = orays.build(prob.nx, prob.ny, prob.lx, prob.ly, prob.phi, prob.h_moc, only_cells=few)
-    ref = osolve.run_sampled(prob, g, few)["steps"][-1]
+    nblk = 16
+    jobs = [(("config", 4, prob.steps), cb, fb)
+            for cb, fb in zip(oracle_pool.blocks(few, nblk), oracle_pool.blocks(faces, nblk))]
+    _say(f"  oracle on {len(few)} cells and {len(faces)} faces, {prob.steps} steps, "
+         f"{len(jobs)} blocks on {oracle_pool.workers()} processes")
+    res = oracle_pool.run_blocks(jobs)
+    last = [r[-1] for r in res]
+    ref = {k: np.concatenate([r[k] for r in last], axis=-1) for k in ("E", "F", "f")}
+    ref_b = np.concatenate([r["bnd"] for r in last], axis=1)
     eE = err_E(m64["E"][:, 0], ref["E"])
     eF = err_F(m64["F"], ref["F"], ref["E"], c)
     ef = err_f(m64["f"], ref["f"], ref["E"])
-    _say(f"  f64 vs oracle: E {eE:.2e} F {eF:.2e} f {ef:.2e}")
+    eb, ebc = bnd_errors(b64, ref_b, floor=0.0)
+    _say(f"  f64 vs oracle: E {eE:.2e} F {eF:.2e} f {ef:.2e} bnd {eb:.2e} / C,f_b {ebc:.2e}")
     assert eE <= 1e-12 and eF <= 1e-12 and ef <= 1e-12
+    assert eb <= 1e-12 and ebc <= 1e-12

@@ -272,3 +272,23 @@ def test_sampled_faces_include_the_stand_ins():
     sub = rays.build(p.nx, p.ny, p.lx, p.ly, p.phi, p.h_moc, only_faces=faces)
     got = solve.run_sampled(p, sub, np.zeros(0, dtype=np.int64), faces=faces)["steps"][0]["bnd"]
     assert np.array_equal(got, ref[:, faces])
+
+
+def test_worker_blocks_equal_the_whole_run():
+    """The block-parallel form used at the largest sizes (tests/oracle_pool):
+    blocks of samples in spawned workers, put side by side, equal the
+    whole-grid oracle on those samples."""
+    from tests import oracle_pool
+    from tests.parity_util import sample_cells, sample_faces
+    p = W.config(0, steps=2)
+    ref = solve.run(p)["steps"]
+    cells = sample_cells(p.nx, p.ny, 12, 0)
+    faces, _ = sample_faces(p, 6, 0)
+    jobs = [(("config", 0, 2), cb, fb) for cb, fb in zip(oracle_pool.blocks(cells, 3), oracle_pool.blocks(faces, 3))]
+    res = oracle_pool.run_blocks(jobs)
+    for t in range(2):
+        for k, sl in (("E", np.s_[:, cells]), ("F", np.s_[:, :, cells]), ("f", np.s_[:, :, cells])):
+            got = np.concatenate([r[t][k] for r in res], axis=-1)
+            assert np.allclose(got, ref[t][k][sl], rtol=1e-14, atol=0)
+        got_b = np.concatenate([r[t]["bnd"] for r in res], axis=1)
+        assert np.allclose(got_b, ref[t]["bnd"][:, faces], rtol=1e-14, atol=1e-300)
