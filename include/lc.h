@@ -192,6 +192,31 @@ lc_status lc_sweep(lc_plan_t plan, const double* kappa, const double* planck, do
                    double* I_exit, void* stream);
 
 /*
+ * lc_sweep_noalloc -- lc_sweep for callers that cannot allocate device memory
+ * while they sweep: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, results (bit for bit)
+ * and errors as lc_sweep, except that
+ *   - the sweep's scratch -- the cell coefficient table (cells x G records
+ *     of 8 bytes for LC_F32 or 16 for LC_F64, rounded up to 256 bytes) and
+ *     the float32 per-group maxima (2 G values of 8 bytes) -- lives in a
+ *     static device array of 64 MiB, which the library holds on every device
+ *     it runs on until the process ends, instead of the plan's workspace;
+ *   - it always sweeps whole traversals (a plan's split setting is not
+ *     used) and records no timing events;
+ *   - it calls no allocating routine (the first call on a device looks up
+ *     the array's address there).
+ * Every call on a device shares that device's array, and each call
+ * rewrites (and clears) what it reads, so calls ordered on one stream are
+ * safe; calls that overlap on one device (other streams, other threads)
+ * race and must not be made.  Errors: as lc_sweep, plus LC_ERR_ARG when the
+ * plan's scratch exceeds the array (256^2 cells x 51 groups fit in either
+ * precision, 512^2 x 51 does not), LC_ERR_HIP when the address lookup fails.
+ */
+lc_status lc_sweep_noalloc(lc_plan_t plan, const double* kappa, const double* planck, double c_dt,
+                           const void* state_prev, void* state_new, const double* I_in,
+                           double* I_exit, void* stream);
+
+/*
  * lc_moments -- cell and boundary moments of a swept state, eq. (7),
  * (14)-(16).  For each cell i and direction m the area-weighted mean
  *   I_{i,m} = sum_{C(i,m)} A I_bar / sum_{C(i,m)} A,  A = l w,

@@ -184,10 +184,19 @@ lc_status dalloc(std::vector<void*>& owned, T** out, size_t n) {
     return LC_OK;
 }
 
+// Scratch of one sweep given by the caller instead of the plan's: the
+// coefficient table [cells][G] and the float32 per-group maxima [2][G].
+// With it the sweep runs whole traversals and records no timing events.
+struct SweepScratch {
+    void* coef = nullptr;
+    unsigned long long* gmax = nullptr;
+};
+
 // Internal launchers (stream-ordered, no allocation, no synchronisation).
 lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, double c_dt,
                        const void* state_prev, void* state_new, const double* I_in,
-                       double* I_exit, hipStream_t st, void* point = nullptr);
+                       double* I_exit, hipStream_t st, void* point = nullptr,
+                       const SweepScratch* ws = nullptr);
 lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, const double* I_in,
                          double c, double* E, double* F, double* f, double* bnd, hipStream_t st);
 lc_status launch_state_fill(Plan* pl, const double* field, void* state, hipStream_t st);
@@ -214,7 +223,8 @@ void make_coef_args(Plan* pl, double c_dt, const double* kappa, const double* pl
                     unsigned long long* gmax_in, int64_t max_blk_off, int64_t coef_blk_off, int64_t g_off, void* out,
                     int64_t* n_max_blocks, int64_t* n_coef_blocks);
 lc_status launch_prologue(Plan* pl, const double* kappa, const double* planck, double c_dt,
-                          const void* state_prev, void* state_new, const double* I_in, hipStream_t st);
+                          const void* state_prev, void* state_new, const double* I_in, hipStream_t st,
+                          void* coef, unsigned long long* gmax);
 void make_moment_args(Plan* pl, const void* state, const double* I_exit, const double* I_in, double c,
                       double* E, double* F, double* f, double* bnd, int64_t bnd_blk_off, void* mom_out,
                       void* bnd_out);

@@ -250,14 +250,16 @@ size_t coef_args_bytes() { return sizeof(CoefArgs); }
 // Prologue of one problem (lc_sweep / lc_step): the float32 scale of the new
 // state in its header, then the coefficient table.
 lc_status launch_prologue(Plan* pl, const double* kappa, const double* planck, double c_dt,
-                          const void* state_prev, void* state_new, const double* I_in, hipStream_t st) {
+                          const void* state_prev, void* state_new, const double* I_in, hipStream_t st,
+                          void* coef, unsigned long long* gmax) {
     const bool f32 = pl->prec == LC_F32;
     // the kernels index the state headers by step parity: step 0 reads e_state[0]
-    // d_gmax holds the |B| maxima, then the |I_in| maxima; a single step is
+    // gmax holds the |B| maxima, then the |I_in| maxima; a single step is
     // the first of its call, so both are formed
-    CoefArgs C = coef_args(pl, c_dt, kappa, planck, 0, state_prev, state_new, I_in, pl->d_gmax, pl->d_gmax + pl->G);
+    CoefArgs C = coef_args(pl, c_dt, kappa, planck, 0, state_prev, state_new, I_in, gmax, gmax + pl->G);
+    C.coef = coef;
     if (f32) {
-        hipLaunchKernelGGL(k_zero_u64, dim3(blocks_for(2 * (int64_t)pl->G)), dim3(kBlock), 0, st, pl->d_gmax,
+        hipLaunchKernelGGL(k_zero_u64, dim3(blocks_for(2 * (int64_t)pl->G)), dim3(kBlock), 0, st, gmax,
                            2 * (int64_t)pl->G);
         hipLaunchKernelGGL(k_group_max, dim3((unsigned)max_blocks(C)), dim3(kBlock),
                            (size_t)pl->G * sizeof(unsigned long long), st, C);

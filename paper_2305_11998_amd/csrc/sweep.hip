@@ -871,13 +871,15 @@ lc_status plan_set_split(Plan* pl, int len) {
 
 lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, double c_dt,
                        const void* state_prev, void* state_new, const double* I_in, double* I_exit,
-                       hipStream_t st, void* point) {
+                       hipStream_t st, void* point, const SweepScratch* ws) {
     Rays* r = pl->rays;
     const int G = pl->G;
     const bool f32 = pl->prec == LC_F32;
     const int* e_prev = static_cast<const int*>(state_prev);   // header: per-group exponents
     int* e_new = static_cast<int*>(state_new);
-    lc_status rc = launch_prologue(pl, kappa, planck, c_dt, state_prev, state_new, I_in, st);
+    void* coef = ws ? ws->coef : pl->d_coef;
+    unsigned long long* gmax = ws ? ws->gmax : pl->d_gmax;
+    lc_status rc = launch_prologue(pl, kappa, planck, c_dt, state_prev, state_new, I_in, st, coef, gmax);
     if (rc) return rc;
     SweepArgs A{};
     A.bun_off = pl->d_bun_off;
@@ -891,7 +893,7 @@ lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, doub
     A.seg_off = r->d_seg_off;
     A.face = r->d_face;
     A.seg = f32 ? static_cast<const void*>(r->d_seg32) : static_cast<const void*>(r->d_seg64);
-    A.coef = pl->d_coef;
+    A.coef = coef;
     A.prev = state_values(pl, state_prev);
     A.next = state_values(pl, state_new);
     A.point = point ? state_values(pl, point) : nullptr;
@@ -907,9 +909,11 @@ lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, doub
     A.P = r->n_pol;
     A.sym = r->sym ? 1 : 0;
     for (int p = 0; p < r->n_pol; ++p) A.inv_sinz[p] = r->inv_sinz[p];
-    rc = prof_begin(pl, pl->ev_sweep, st);
-    if (rc) return rc;
-    if (pl->split_len > 0 && !point) {
+    if (!ws) {
+        rc = prof_begin(pl, pl->ev_sweep, st);
+        if (rc) return rc;
+    }
+    if (pl->split_len > 0 && !point && !ws) {
         rc = f32 ? split_call_p<float>(pl, A, st) : split_call_p<double>(pl, A, st);
         if (rc) return rc;
         return prof_end(pl, pl->ev_sweep, st);
@@ -924,7 +928,7 @@ lc_status launch_sweep(Plan* pl, const double* kappa, const double* planck, doub
     c.blocks = (unsigned)pl->sweep_blocks;
     rc = f32 ? sweep_call_single<float>(r->n_pol, c) : sweep_call_single<double>(r->n_pol, c);
     if (rc) return rc;
-    return prof_end(pl, pl->ev_sweep, st);
+    return ws ? LC_OK : prof_end(pl, pl->ev_sweep, st);
 }
 
 }  // namespace lc

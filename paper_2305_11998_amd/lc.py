@@ -74,6 +74,7 @@ _SIGS = {
     "lc_state_fill": ([_vp, _vp, _vp, _vp], C.c_int),
     "lc_state_export": ([_vp, _vp, _vp, _vp], C.c_int),
     "lc_sweep": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "lc_sweep_noalloc": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_moments": ([_vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_step": ([_vp, _i32, _vp, _vp, _i64, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_grey_closures": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
@@ -254,6 +255,15 @@ def lc_sweep(plan: Plan, kappa, planck, c_dt, state_prev, state_new, I_in, I_exi
                          _bytes(state_new, plan.state_bytes, "state_new"),
                          _dev(I_in, plan.n_in, name="I_in"),
                          _dev(I_exit, plan.n_exit, name="I_exit", optional=True), _stream(stream)))
+
+
+def lc_sweep_noalloc(plan: Plan, kappa, planck, c_dt, state_prev, state_new, I_in, I_exit=None, stream=None):
+    _check(_lib.lc_sweep_noalloc(plan.handle, _dev(kappa, plan.n_field, name="kappa"),
+                                 _dev(planck, plan.n_field, name="planck"), float(c_dt),
+                                 _bytes(state_prev, plan.state_bytes, "state_prev"),
+                                 _bytes(state_new, plan.state_bytes, "state_new"),
+                                 _dev(I_in, plan.n_in, name="I_in"),
+                                 _dev(I_exit, plan.n_exit, name="I_exit", optional=True), _stream(stream)))
 
 
 def lc_moments(plan: Plan, state, c, E=None, F=None, f=None, bnd=None, I_exit=None, I_in=None,
