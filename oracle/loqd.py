@@ -1,0 +1,211 @@
+"""Multigroup low-order quasidiffusion (LOQD) equations of the paper's
+multilevel method, eq. (4), for one backward-Euler time step on the material
+grid, closed by the Eddington tensors of the transport sweep (eq. (7), (15)
+for cells, (16) for faces) and the half-range boundary factor C.
+
+TEST INFRASTRUCTURE ONLY: plain Python + scipy's sparse direct solver; the
+HIP library never imports it.
+
+Time-discrete equations (backward Euler, kappa_t = kappa + 1/(c dt)):
+    c kappa_t E + div F = 4 pi kappa B + E^{n-1}/dt                   (4a)
+    kappa_t F + c div(f E) = F^{n-1}/(c dt)                          (4b)
+
+The paper discretises them with a second-order finite-volume scheme that it
+cites but does not print.  Reading (the scheme implemented here):
+
+* unknowns per group: the cell averages E_i and the face averages E_f on
+  every face (interior and boundary); the normal face fluxes F_f (the x
+  component on x-faces, y on y-faces) follow from them;
+* (4a) integrated over cell i of size hx x hy:
+    c kappa_t,i E_i + (F_R - F_L)/hx + (F_T - F_B)/hy = 4 pi kappa_i B_i + E^{n-1}_i/dt;
+* (4b), x component, integrated over each half of the cell next to an
+  x-face, with the half-cell average of kappa_t F_x taken as kappa_t,i times
+  the face value and f E taken as the cell tensor times E_i at the centre,
+  the face tensor times E_f on the face, and the y-face averages of the
+  cell on the half-cell's top and bottom:
+    kappa_t,i (hx/2) F_R = -c (f_xx,R E_R - f_xx,i E_i)
+                           - c hx/(2 hy) (f_xy,T E_T - f_xy,B E_B) + (hx/2) F^{n-1}_R/(c dt)
+    kappa_t,i (hx/2) F_L = -c (f_xx,i E_i - f_xx,L E_L)
+                           - c hx/(2 hy) (f_xy,T E_T - f_xy,B E_B) + (hx/2) F^{n-1}_L/(c dt)
+  and alike for the y component on y-faces (f_yy, and f_xy on the cell's
+  x-faces);
+* an interior face has one flux: the relations of its two cells give the
+  same F_f (one equation per interior face);
+* a boundary face with outward normal n closes with the exact QD boundary
+  condition n.F = C (c E_f - Phi^-) - J^-, where C = J^+/Phi^+ is the
+  half-range factor and Phi^-, J^- are the incoming half-range moments of
+  the boundary intensity (all three from the transport's boundary factors).
+
+Face numbering (shared with the library by this written convention only):
+interior x-faces (x = ix hx, 1 <= ix < nx) of row iy are iy (nx-1) + ix - 1;
+interior y-faces (y = iy hy, 1 <= iy < ny) of column ix follow at
+(nx-1) ny + (iy-1) nx + ix; then the boundary faces in their own order
+([0, ny) x = 0, [ny, 2ny) x = lx, [2ny, 2ny+nx) y = 0, then y = ly) offset
+by the interior count.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+
+def n_interior(nx, ny):
+    return (nx - 1) * ny + nx * (ny - 1)
+
+
+def n_faces(nx, ny):
+    return n_interior(nx, ny) + 2 * (nx + ny)
+
+
+def cell_faces(nx, ny):
+    """Faces (L, R, B, T) of every cell in the all-face numbering: [cells][4]."""
+    nint = n_interior(nx, ny)
+    out = np.zeros((nx * ny, 4), dtype=np.int64)
+    for iy in range(ny):
+        for ix in range(nx):
+            i = iy * nx + ix
+            L = iy * (nx - 1) + ix - 1 if ix > 0 else nint + iy
+            R = iy * (nx - 1) + ix if ix < nx - 1 else nint + ny + iy
+            B = (nx - 1) * ny + (iy - 1) * nx + ix if iy > 0 else nint + 2 * ny + ix
+            T = (nx - 1) * ny + iy * nx + ix if iy < ny - 1 else nint + 2 * ny + nx + ix
+            out[i] = (L, R, B, T)
+    return out
+
+
+def face_cells(nx, ny):
+    """For every face: (cell on the low side, cell on the high side) along its
+    normal axis, -1 outside the domain, and whether it is an x-face."""
+    nf = n_faces(nx, ny)
+    lo = np.full(nf, -1, dtype=np.int64)
+    hi = np.full(nf, -1, dtype=np.int64)
+    is_x = np.zeros(nf, dtype=bool)
+    cf = cell_faces(nx, ny)
+    for i in range(nx * ny):
+        L, R, B, T = cf[i]
+        hi[L] = i; lo[R] = i; hi[B] = i; lo[T] = i
+        is_x[L] = is_x[R] = True
+    return lo, hi, is_x
+
+
+class _Group:
+    """Per-group data of one solve (plain attribute bag)."""
+
+    def __init__(self, nx, ny, lx, ly, c, c_dt, kappa, F_prev, f_cell, f_face):
+        self.nx, self.ny = nx, ny
+        self.hx, self.hy = lx / nx, ly / ny
+        self.N = nx * ny
+        self.c, self.c_dt = c, c_dt
+        self.kt = kappa + 1.0 / c_dt
+        self.F_prev = F_prev
+        self.fxx, self.fxy, self.fyy = f_cell
+        self.gxx, self.gxy, self.gyy = f_face
+        self.cf = cell_faces(nx, ny)
+
+
+def half_cell_flux(q, i, face):
+    """The first-moment relation of cell i on the half of the cell next to one
+    of its faces, solved for that face's normal flux:
+    F_face = sum coef * x[col] + const, with columns 0..N-1 the cell
+    unknowns and N + f the face unknowns.  Returns ([(col, coef)], const)."""
+    c, N = q.c, q.N
+    L, R, B, T = q.cf[i]
+    if face in (L, R):
+        a = q.kt[i] * q.hx / 2.0
+        cross = [(N + T, -c * q.hx / (2 * q.hy) * q.gxy[T] / a), (N + B, c * q.hx / (2 * q.hy) * q.gxy[B] / a)]
+        if face == R:
+            terms = [(N + R, -c * q.gxx[R] / a), (i, c * q.fxx[i] / a)]
+        else:
+            terms = [(i, -c * q.fxx[i] / a), (N + L, c * q.gxx[L] / a)]
+        return terms + cross, (q.hx / 2.0) * q.F_prev[face] / q.c_dt / a
+    a = q.kt[i] * q.hy / 2.0
+    cross = [(N + R, -c * q.hy / (2 * q.hx) * q.gxy[R] / a), (N + L, c * q.hy / (2 * q.hx) * q.gxy[L] / a)]
+    if face == T:
+        terms = [(N + T, -c * q.gyy[T] / a), (i, c * q.fyy[i] / a)]
+    else:
+        terms = [(i, -c * q.fyy[i] / a), (N + B, c * q.gyy[B] / a)]
+    return terms + cross, (q.hy / 2.0) * q.F_prev[face] / q.c_dt / a
+
+
+def boundary_condition(C, Phi_in, J_in, c):
+    """n.F = C (c E_f - Phi^-) - J^- as (coefficient of E_f, constant)."""
+    return C * c, -C * Phi_in - J_in
+
+
+def solve_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc):
+    """One group.  kappa, planck, E_prev: [cells]; F_prev: [faces] normal
+    flux of the previous step (x component on x-faces, y on y-faces);
+    f_cell: [3][cells] and f_face: [3][faces] Eddington tensor entries
+    (xx, xy, yy); bc: [nb][3] = (C, Phi^-, J^-) per boundary face.
+    Returns (E_cell [cells], E_face [faces], F_face [faces])."""
+    q = _Group(nx, ny, lx, ly, c, c_dt, kappa, F_prev, f_cell, f_face)
+    N = q.N
+    nf = n_faces(nx, ny)
+    nint = n_interior(nx, ny)
+    lo, hi, _ = face_cells(nx, ny)
+    rows, cols, vals = [], [], []
+    rhs = np.zeros(N + nf)
+
+    def add(r, terms, scale):
+        for col, v in terms:
+            rows.append(r); cols.append(col); vals.append(scale * v)
+
+    # cell balances: c kappa_t E_i + (F_R - F_L)/hx + (F_T - F_B)/hy = source
+    for i in range(N):
+        L, R, B, T = q.cf[i]
+        add(i, [(i, c * q.kt[i])], 1.0)
+        rhs[i] = 4.0 * np.pi * kappa[i] * planck[i] + c * E_prev[i] / c_dt
+        for face, sgn, h in ((R, 1.0, q.hx), (L, -1.0, q.hx), (T, 1.0, q.hy), (B, -1.0, q.hy)):
+            terms, const = half_cell_flux(q, i, face)
+            add(i, terms, sgn / h)
+            rhs[i] -= sgn / h * const
+    # face equations
+    for f in range(nf):
+        r = N + f
+        if lo[f] >= 0 and hi[f] >= 0:               # one flux from both sides
+            t1, c1 = half_cell_flux(q, lo[f], f)
+            t2, c2 = half_cell_flux(q, hi[f], f)
+            add(r, t1, 1.0)
+            add(r, t2, -1.0)
+            rhs[r] = c2 - c1
+        else:                                      # n.F from the cell equals the boundary condition
+            C, Pm, Jm = bc[f - nint]
+            i = lo[f] if lo[f] >= 0 else hi[f]
+            sgn = 1.0 if lo[f] >= 0 else -1.0      # n = +axis when the cell lies below the face
+            t1, c1 = half_cell_flux(q, i, f)
+            ce, cc = boundary_condition(C, Pm, Jm, c)
+            add(r, t1, sgn)
+            add(r, [(N + f, -ce)], 1.0)
+            rhs[r] = cc - sgn * c1
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(N + nf, N + nf))
+    x = spla.spsolve(A.tocsc(), rhs)
+    E_cell, E_face = x[:N], x[N:]
+    F_face = np.zeros(nf)
+    for f in range(nf):
+        i = lo[f] if lo[f] >= 0 else hi[f]
+        terms, const = half_cell_flux(q, i, f)
+        F_face[f] = sum(v * x[col] for col, v in terms) + const
+    return E_cell, E_face, F_face
+
+
+def solve(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc):
+    """All groups: kappa, planck, E_prev [G][cells]; F_prev [G][faces];
+    f_cell [G][3][cells]; f_face [G][3][faces]; bc [G][nb][3].  Returns
+    E_cell [G][cells], E_face [G][faces], F_face [G][faces]."""
+    G = kappa.shape[0]
+    out = [solve_group(nx, ny, lx, ly, c, c_dt, kappa[g], planck[g], E_prev[g], F_prev[g], f_cell[g],
+                       f_face[g], bc[g]) for g in range(G)]
+    return tuple(np.stack([o[k] for o in out]) for k in range(3))
+
+
+def closures_from_transport(nx, ny, E_cellmajor_f, face_f, bnd):
+    """Arrange the transport's outputs as the solver's closures:
+    cell tensors from the cell moments f [G][4][cells] (xx, xy, yy, zz),
+    interior face tensors from the face moments f [G][4][interior faces],
+    boundary face tensors and (C, Phi^-, J^-) from the boundary factors
+    [G][nb][8] (Phi+, J+, Phi-, J-, C, fxx, fxy, fyy).  Returns
+    (f_cell [G][3][cells], f_face [G][3][faces], bc [G][nb][3])."""
+    f_cell = E_cellmajor_f[:, [0, 1, 2], :]
+    f_face = np.concatenate([face_f[:, [0, 1, 2], :], bnd[:, :, 5:8].transpose(0, 2, 1)], axis=2)
+    bc = bnd[:, :, [4, 2, 3]]
+    return f_cell, f_face, bc

@@ -1,0 +1,325 @@
+"""Pins of the LOQD oracle (oracle/loqd.py): the finite-volume reading of the
+multigroup low-order equations, eq. (4), for one backward-Euler step.
+
+* A linear energy density with constant coefficients (anisotropic Eddington
+  tensor with a cross term, a previous-step flux, unequal cell sides) is
+  reproduced exactly in the cells and on the faces, flux included.
+* A smooth manufactured solution with varying opacity and Eddington tensor
+  (sources derived symbolically) converges at second order in cells and
+  face fluxes.
+* Isotropic equilibrium with the quadrature's own boundary factors stays in
+  equilibrium: E = 4 pi B / c, F = 0.
+* Every cell balances with the returned fluxes, both cells next to a face
+  give it the same flux, and the sources equal the outflow over the
+  boundary (conservation).
+* Planted mistakes (cross-term sign, cell tensor on the face, previous-step
+  flux dropped, boundary-condition sign) fail the pins."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import loqd
+
+
+def _faces_geometry(nx, ny, lx, ly):
+    """Centre, normal axis (0 = x, 1 = y) and the two end points of every face
+    in the all-face numbering."""
+    hx, hy = lx / nx, ly / ny
+    nf = loqd.n_faces(nx, ny)
+    cen = np.zeros((nf, 2))
+    axis = np.zeros(nf, dtype=int)
+    cf = loqd.cell_faces(nx, ny)
+    for iy in range(ny):
+        for ix in range(nx):
+            L, R, B, T = cf[iy * nx + ix]
+            x0, x1, y0, y1 = ix * hx, (ix + 1) * hx, iy * hy, (iy + 1) * hy
+            cen[L] = (x0, (y0 + y1) / 2); cen[R] = (x1, (y0 + y1) / 2)
+            cen[B] = ((x0 + x1) / 2, y0); cen[T] = ((x0 + x1) / 2, y1)
+            axis[B] = axis[T] = 1
+    return cen, axis
+
+
+def _outward_sign(nx, ny):
+    """+1 where a boundary face's outward normal points along +axis."""
+    nb = 2 * (nx + ny)
+    s = np.ones(nb)
+    s[:ny] = -1.0                         # x = 0
+    s[2 * ny:2 * ny + nx] = -1.0          # y = 0
+    return s
+
+
+# ---------------------------------------------------------------------------
+# linear fields are exact
+# ---------------------------------------------------------------------------
+
+def _linear_case(nx=6, ny=4, lx=1.2, ly=1.0):
+    c, c_dt, kap = 3.0, 0.5, 2.0
+    kt = kap + 1.0 / c_dt
+    a0, bx, by = 2.0, 0.7, -0.4
+    T = np.array([[0.40, 0.12], [0.12, 0.35]])
+    Fp = np.array([0.3, -0.2])
+    gradE = np.array([bx, by])
+    F = (Fp / c_dt - c * T @ gradE) / kt                     # constant flux
+    N = nx * ny
+    hx, hy = lx / nx, ly / ny
+    xc = (np.arange(nx) + 0.5) * hx
+    yc = (np.arange(ny) + 0.5) * hy
+    X, Y = np.meshgrid(xc, yc)
+    Ec = (a0 + bx * X + by * Y).ravel()
+    S = c * kt * Ec                                          # div F = 0
+    E_prev = 0.5 * Ec
+    planck = (S - c * E_prev / c_dt) / (4 * math.pi * kap)
+    cen, axis = _faces_geometry(nx, ny, lx, ly)
+    nf = len(axis)
+    Ef = a0 + bx * cen[:, 0] + by * cen[:, 1]
+    F_face = F[axis]
+    F_prev = Fp[axis]
+    f_cell = np.array([np.full(N, T[0, 0]), np.full(N, T[0, 1]), np.full(N, T[1, 1])])
+    f_face = np.array([np.full(nf, T[0, 0]), np.full(nf, T[0, 1]), np.full(nf, T[1, 1])])
+    nint = loqd.n_interior(nx, ny)
+    sgn = _outward_sign(nx, ny)
+    nb = 2 * (nx + ny)
+    C = 0.45 + 0.05 * np.cos(np.arange(nb))
+    Pm = 0.3 + 0.1 * np.sin(np.arange(nb))
+    nF = sgn * F_face[nint:]
+    Jm = C * (c * Ef[nint:] - Pm) - nF                       # the boundary condition holds exactly
+    bc = np.stack([C, Pm, Jm], axis=1)
+    args = (nx, ny, lx, ly, c, c_dt, np.full(N, kap), planck, E_prev, F_prev, f_cell, f_face, bc)
+    return args, (Ec, Ef, F_face)
+
+
+def test_linear_field_is_reproduced_exactly():
+    args, (Ec, Ef, Ff) = _linear_case()
+    e, ef, ff = loqd.solve_group(*args)
+    assert np.allclose(e, Ec, rtol=1e-12, atol=0)
+    assert np.allclose(ef, Ef, rtol=1e-12, atol=0)
+    assert np.allclose(ff, Ff, rtol=1e-11, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# second-order convergence on a smooth manufactured solution
+# ---------------------------------------------------------------------------
+
+def _manufactured():
+    import sympy as S
+    x, y = S.symbols("x y")
+    c, c_dt = 2.0, 0.8
+    E = 1 + 0.5 * S.sin(2 * x + 0.3) * S.cos(1.5 * y) + 0.2 * x * y
+    kap = 1.5 + 0.8 * S.sin(x + 2 * y) ** 2
+    kt = kap + 1 / c_dt
+    fxx = S.Rational(1, 3) + 0.1 * S.cos(x) * S.sin(y)
+    fyy = S.Rational(1, 3) - 0.05 * S.sin(2 * x)
+    fxy = 0.08 * S.sin(x + y)
+    Fpx = 0.2 * S.cos(y) * x
+    Fpy = -0.1 * S.sin(x) + 0.05
+    Fx = (Fpx / c_dt - c * (S.diff(fxx * E, x) + S.diff(fxy * E, y))) / kt
+    Fy = (Fpy / c_dt - c * (S.diff(fxy * E, x) + S.diff(fyy * E, y))) / kt
+    src = c * kt * E + S.diff(Fx, x) + S.diff(Fy, y)
+    f = {k: S.lambdify((x, y), v, "numpy") for k, v in dict(E=E, kap=kap, fxx=fxx, fyy=fyy, fxy=fxy, Fpx=Fpx,
+                                                            Fpy=Fpy, Fx=Fx, Fy=Fy, src=src).items()}
+    return f, c, c_dt
+
+
+def _gl(n=4):
+    t, w = np.polynomial.legendre.leggauss(n)
+    return 0.5 * (t + 1.0), 0.5 * w
+
+
+def _cell_avg(fn, nx, ny, lx, ly):
+    hx, hy = lx / nx, ly / ny
+    t, w = _gl()
+    out = np.zeros(nx * ny)
+    for iy in range(ny):
+        for ix in range(nx):
+            X, Y = np.meshgrid(ix * hx + t * hx, iy * hy + t * hy)
+            out[iy * nx + ix] = np.sum(np.outer(w, w) * np.broadcast_to(fn(X, Y), X.shape))
+    return out
+
+
+def _face_avg(fn, nx, ny, lx, ly):
+    hx, hy = lx / nx, ly / ny
+    cen, axis = _faces_geometry(nx, ny, lx, ly)
+    t, w = _gl()
+    out = np.zeros(len(axis))
+    for f in range(len(axis)):
+        if axis[f] == 0:
+            xs, ys = np.full_like(t, cen[f, 0]), cen[f, 1] - hy / 2 + t * hy
+        else:
+            xs, ys = cen[f, 0] - hx / 2 + t * hx, np.full_like(t, cen[f, 1])
+        out[f] = np.sum(w * np.broadcast_to(fn(xs, ys), xs.shape))
+    return out
+
+
+def _manufactured_case(n, lx=1.0, ly=0.8):
+    f, c, c_dt = _manufactured()
+    nx = ny = n
+    avg = lambda k: _cell_avg(f[k], nx, ny, lx, ly)
+    favg = lambda k: _face_avg(f[k], nx, ny, lx, ly)
+    _, axis = _faces_geometry(nx, ny, lx, ly)
+    kap = avg("kap")
+    Ec = avg("E")
+    S = avg("src")
+    E_prev = S * c_dt / c                                   # the whole source through E^{n-1}
+    planck = np.zeros_like(Ec)
+    f_cell = np.array([avg("fxx"), avg("fxy"), avg("fyy")])
+    f_face = np.array([favg("fxx"), favg("fxy"), favg("fyy")])
+    F_prev = np.where(axis == 0, favg("Fpx"), favg("Fpy"))
+    F_face = np.where(axis == 0, favg("Fx"), favg("Fy"))
+    Ef = favg("E")
+    nint = loqd.n_interior(nx, ny)
+    sgn = _outward_sign(nx, ny)
+    C = np.full(2 * (nx + ny), 0.5)
+    Pm = np.zeros(2 * (nx + ny))
+    Jm = C * c * Ef[nint:] - sgn * F_face[nint:]
+    bc = np.stack([C, Pm, Jm], axis=1)
+    args = (nx, ny, lx, ly, c, c_dt, kap, planck, E_prev, F_prev, f_cell, f_face, bc)
+    return args, (Ec, Ef, F_face), lx * ly / (nx * ny)
+
+
+def _errors(n):
+    args, (Ec, Ef, Ff), area = _manufactured_case(n)
+    e, ef, ff = loqd.solve_group(*args)
+    return (math.sqrt(np.sum((e - Ec) ** 2) * area), float(np.max(np.abs(ff - Ff))))
+
+
+def test_second_order_convergence_on_a_manufactured_solution():
+    errs = [_errors(n) for n in (8, 16, 32)]
+    rates_E = [math.log2(a[0] / b[0]) for a, b in zip(errs, errs[1:])]
+    rates_F = [math.log2(a[1] / b[1]) for a, b in zip(errs, errs[1:])]
+    assert all(r > 1.8 for r in rates_E), (errs, rates_E)
+    assert rates_F[-1] > 1.5, (errs, rates_F)
+    assert errs[-1][0] < 1e-3
+
+
+# ---------------------------------------------------------------------------
+# isotropic equilibrium
+# ---------------------------------------------------------------------------
+
+def test_isotropic_equilibrium_is_kept():
+    nx, ny, lx, ly = 5, 3, 1.0, 0.6
+    c, c_dt = 299.792458, 3.0
+    phi, mu, om = W.product_quadrature(16, 2)
+    ox = (np.cos(phi)[:, None] * np.sqrt(1 - mu ** 2)[None, :]).ravel()
+    oy = (np.sin(phi)[:, None] * np.sqrt(1 - mu ** 2)[None, :]).ravel()
+    normals = W.boundary_faces(nx, ny)
+    Bv = 0.37
+    N = nx * ny
+    nf = loqd.n_faces(nx, ny)
+    bc = []
+    for n in normals:
+        dn = ox * n[0] + oy * n[1]
+        out, inn = dn > 0, dn < 0
+        C_iso = np.sum(om[out] * dn[out]) / np.sum(om[out])
+        bc.append((C_iso, np.sum(om[inn]) * Bv, np.sum(om[inn] * np.abs(dn[inn])) * Bv))
+    bc = np.array(bc)
+    third = np.full((3, N), 1 / 3); third[1] = 0.0
+    thirdf = np.full((3, nf), 1 / 3); thirdf[1] = 0.0
+    kap = np.linspace(0.5, 3.0, N)
+    e, ef, ff = loqd.solve_group(nx, ny, lx, ly, c, c_dt, kap, np.full(N, Bv), np.full(N, 4 * math.pi * Bv / c),
+                                 np.zeros(nf), third, thirdf, bc)
+    E0 = 4 * math.pi * Bv / c
+    assert np.allclose(e, E0, rtol=1e-13) and np.allclose(ef, E0, rtol=1e-13)
+    assert np.max(np.abs(ff)) < 1e-12 * c * E0
+
+
+# ---------------------------------------------------------------------------
+# conservation
+# ---------------------------------------------------------------------------
+
+def _random_case(nx=7, ny=5, lx=1.4, ly=0.7, seed=3):
+    rng = np.random.default_rng(seed)
+    N, nf = nx * ny, loqd.n_faces(nx, ny)
+    c, c_dt = 5.0, 0.7
+    kap = rng.uniform(0.1, 10.0, N)
+    planck = rng.uniform(0.0, 1.0, N)
+    E_prev = rng.uniform(0.0, 1.0, N)
+    F_prev = rng.uniform(-0.5, 0.5, nf)
+
+    def tensors(n):
+        a = rng.uniform(0.15, 0.6, n)
+        d = rng.uniform(0.15, 0.6, n)
+        b = rng.uniform(-0.5, 0.5, n) * np.sqrt(a * d)
+        return np.array([a, b, d])
+    bc = np.stack([rng.uniform(0.3, 0.7, 2 * (nx + ny)), rng.uniform(0, 1, 2 * (nx + ny)),
+                   rng.uniform(0, 0.5, 2 * (nx + ny))], axis=1)
+    return (nx, ny, lx, ly, c, c_dt, kap, planck, E_prev, F_prev, tensors(N), tensors(nf), bc)
+
+
+def test_discrete_conservation():
+    args = _random_case()
+    nx, ny, lx, ly, c, c_dt, kap, planck, E_prev, F_prev, f_cell, f_face, bc = args
+    e, ef, ff = loqd.solve_group(*args)
+    hx, hy = lx / nx, ly / ny
+    kt = kap + 1.0 / c_dt
+    src = 4 * math.pi * kap * planck + c * E_prev / c_dt
+    cf = loqd.cell_faces(nx, ny)
+    L, R, B, T = cf.T
+    div = (ff[R] - ff[L]) / hx + (ff[T] - ff[B]) / hy
+    assert np.allclose(c * kt * e + div, src, rtol=1e-11, atol=1e-12 * np.max(src))
+    # the other cell next to each interior face gives the same flux
+    q = loqd._Group(nx, ny, lx, ly, c, c_dt, kap, F_prev, f_cell, f_face)
+    x = np.concatenate([e, ef])
+    lo, hi, _ = loqd.face_cells(nx, ny)
+    for fidx in range(loqd.n_interior(nx, ny)):
+        terms, const = loqd.half_cell_flux(q, hi[fidx], fidx)
+        other = sum(v * x[col] for col, v in terms) + const
+        assert abs(other - ff[fidx]) <= 1e-10 * (1 + abs(ff[fidx]))
+    # sources = absorption + outflow through the boundary
+    nint = loqd.n_interior(nx, ny)
+    sgn = _outward_sign(nx, ny)
+    lens = np.concatenate([np.full(ny, hy), np.full(ny, hy), np.full(nx, hx), np.full(nx, hx)])
+    outflow = np.sum(sgn * ff[nint:] * lens)
+    assert math.isclose(np.sum((src - c * kt * e) * hx * hy), outflow, rel_tol=1e-10, abs_tol=1e-12)
+    # and the boundary condition holds
+    C, Pm, Jm = bc.T
+    assert np.allclose(sgn * ff[nint:], C * (c * ef[nint:] - Pm) - Jm, rtol=1e-10, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# planted mistakes
+# ---------------------------------------------------------------------------
+
+_orig_flux = loqd.half_cell_flux
+
+
+def _cross_sign_flipped(q, i, face):
+    terms, const = _orig_flux(q, i, face)
+    return terms[:2] + [(col, -v) for col, v in terms[2:]], const
+
+
+def _cell_tensor_on_face(q, i, face):
+    terms, const = _orig_flux(q, i, face)
+    L, R, B, T = q.cf[i]
+    out = []
+    for col, v in terms[:2]:
+        if col >= q.N and col - q.N in (L, R):
+            v = v * q.fxx[i] / q.gxx[col - q.N]
+        elif col >= q.N and col - q.N in (B, T) and face in (B, T):
+            v = v * q.fyy[i] / q.gyy[col - q.N]
+        out.append((col, v))
+    return out + terms[2:], const
+
+
+def _no_previous_flux(q, i, face):
+    terms, _ = _orig_flux(q, i, face)
+    return terms, 0.0
+
+
+@pytest.mark.parametrize("bad", [_cross_sign_flipped, _cell_tensor_on_face, _no_previous_flux])
+def test_planted_flux_mistakes_are_caught(monkeypatch, bad):
+    monkeypatch.setattr(loqd, "half_cell_flux", bad)
+    caught = 0
+    for pin in (test_linear_field_is_reproduced_exactly, test_second_order_convergence_on_a_manufactured_solution):
+        try:
+            pin()
+        except AssertionError:
+            caught += 1
+    assert caught >= 1
+
+
+def test_planted_boundary_mistake_is_caught(monkeypatch):
+    monkeypatch.setattr(loqd, "boundary_condition", lambda C, Pm, Jm, c: (C * c, -C * Pm + Jm))
+    with pytest.raises(AssertionError):
+        test_linear_field_is_reproduced_exactly()
