@@ -51,6 +51,17 @@ def sweep_algorithmic_bytes(solver, elem):
     return state + geom + coef + io
 
 
+def step_algorithmic_bytes(solver, elem):
+    """Bytes one whole transport step of a problem must move at minimum: the
+    sweep's (above) plus the moments every step writes -- E, F and the
+    Eddington tensor (7 float64 per cell and group) and the boundary factors
+    (8 float64 per boundary face and group).  Re-reading the stored
+    intensities to form the moments is not counted: it is the price of an
+    unfused reduction, not of the method."""
+    p, r = solver.prob, solver.rays
+    return sweep_algorithmic_bytes(solver, elem) + p.cells * p.G * 7 * 8 + p.G * r.nb * 8 * 8
+
+
 TRAFFIC_RECORD = os.path.join(ROOT, "profiles", "sweep_batch_traffic.txt")
 SWEEP_SOURCES = ("sweep.hip", "batch.hip", "lc_internal.hpp")
 
@@ -89,10 +100,15 @@ def moment_errors(got, ref):
                 f=err_f(got["f"], ref["f"], ref["E"]))
 
 
-def run_batched_f32(probs, steps, warmup):
+def run_batched(probs, steps, warmup, prec, snapshot_steps=0):
+    """The batched form in precision `prec`: tuned, then `steps` steps
+    replayed from the captured graph (timed with events around the replay),
+    then the same steps eager with the library's kernel timers per phase.
+    With snapshot_steps = T, the moments after 1, 2, ..., T steps from the
+    initial state are kept on the device (for the per-step accuracy check)."""
     import torch
     from paper_2305_11998_amd import driver, lc, tune
-    bs = driver.BatchSolver(probs, prec=lc.LC_F32, static_material=True)
+    bs = driver.BatchSolver(probs, prec=prec, static_material=True)
     tuned = tune.tune_batch(bs, verbose=True)
     _say(f"batch tuning per polar class: {tuned['per_class']}")
     bs.reset()
@@ -120,21 +136,48 @@ def run_batched_f32(probs, steps, warmup):
     ms = e0.elapsed_time(e1)
     pro, npro, sw, nsw, mo, nmo = lc.lc_batch_profile_read(bs.batch)
     lc.lc_batch_profile(bs.batch, False)
-    # accuracy: one step from the initial state
-    bs.reset()
-    bs.step(1)
-    torch.cuda.synchronize()
-    mom = [s.moments() for s in bs.solvers]
+    snaps = []
+    for n in range(1, snapshot_steps + 1):
+        bs.reset()
+        bs.step(n)
+        torch.cuda.synchronize()
+        snaps.append([{k: getattr(s, k).clone() for k in ("E", "F", "f")} for s in bs.solvers])
     return dict(bs=bs, ms=ms_graph, ms_eager=ms, sweep_ms=sw / max(nsw, 1), moments_ms=mo / max(nmo, 1),
-                prologue_ms=pro / max(npro, 1), tuning=tuned, moments=mom)
+                prologue_ms=pro / max(npro, 1), tuning=tuned, snapshots=snaps)
 
 
-def run_plain_f64(probs, steps):
-    """The plain float64 sweep, problem by problem (eager sweep + moments)."""
+def _dev_errors(a, b, G, cells, c):
+    """Error metrics of moments a against b (device tensors in the library's
+    cell-major layout) -- the metrics of tests/parity_util on the device:
+    relative E over cells whose E is above 1e-30 of the group's largest, F
+    relative to c E, f absolute."""
     import torch
+    Ea, Eb = a["E"].view(cells, G), b["E"].view(cells, G)
+    m = Eb > 1e-30 * Eb.max(dim=0, keepdim=True).values
+    if not bool(m.any()):
+        return dict(E=0.0, F=0.0, f=0.0)
+    eE = ((Ea - Eb).abs() / torch.where(m, Eb, torch.ones_like(Eb)))[m].max().item()
+    dF = (a["F"].view(cells, 2, G) - b["F"].view(cells, 2, G)).abs().amax(dim=1)
+    eF = (dF / torch.where(m, c * Eb, torch.ones_like(Eb)))[m].max().item()
+    df = (a["f"].view(cells, 4, G) - b["f"].view(cells, 4, G)).abs().amax(dim=1)
+    return dict(E=eE, F=eF, f=df[m].max().item())
+
+
+def run_plain_f64(probs, steps, snapshots=None):
+    """The plain float64 sweep, problem by problem (eager sweep + moments),
+    timed over `steps` steps per problem.  With float32 snapshots (moments
+    after 1..T steps, per problem), each problem is then advanced T steps
+    from the initial state and its moments after every step are compared
+    with the float32 ones; returns the worst error over steps and problems,
+    and per step."""
+    import torch
+    import workloads as W
     from paper_2305_11998_amd import driver, lc
-    tot_ms, upd, mom = 0.0, 0, []
-    for p in probs:
+    tot_ms, upd = 0.0, 0
+    T = len(snapshots) if snapshots else 0
+    worst = {k: 0.0 for k in ("E", "F", "f")}
+    per_step = [{k: 0.0 for k in ("E", "F", "f")} for _ in range(T)]
+    for q, p in enumerate(probs):
         s = driver.Solver(p, prec=lc.LC_F64)
         s.reset()
         s.bench_step()
@@ -147,28 +190,35 @@ def run_plain_f64(probs, steps):
         torch.cuda.synchronize()
         tot_ms += e0.elapsed_time(e1) / steps
         upd += s.updates_per_step()
-        s.reset()
-        s.step(1)
-        mom.append(s.moments())
+        if T:
+            s.reset()
+            for t in range(T):
+                s.bench_step()
+                e = _dev_errors(snapshots[t][q], dict(E=s.E, F=s.F, f=s.f), p.G, p.cells, W.C_LIGHT)
+                for k in worst:
+                    worst[k] = max(worst[k], e[k])
+                    per_step[t][k] = max(per_step[t][k], e[k])
         del s
     torch.cuda.empty_cache()
-    return dict(ms_per_step=tot_ms, updates=upd, moments=mom)
+    return dict(ms_per_step=tot_ms, updates=upd, worst=worst, per_step=per_step)
 
 
-def cpu_baseline(prob, budget_s=12.0):
-    """The oracle's sweep (unchanged) on a bounded sample of the workload:
-    characteristics of the first azimuth pair of one member problem, both
-    traversals, all polar angles and groups, repeated until the budget."""
+def _oracle_pair_sample(prob, a, budget_s):
+    """The oracle's sweep (unchanged) of azimuth pair a of a problem, both
+    traversals, all polar angles and groups, on batches of 16
+    characteristics (the shortest quarter, corner clips, left out), repeated
+    until `budget_s` seconds of sweeping.  Returns (updates, seconds,
+    characteristics)."""
     import numpy as np
     from oracle import rays as orays, sweep as osweep
     P, G = prob.n_pol, prob.G
     half = prob.n_az // 2
-    g = orays.build(prob.nx, prob.ny, prob.lx, prob.ly, prob.phi[[0, half]], prob.h_moc)
+    g = orays.build(prob.nx, prob.ny, prob.lx, prob.ly, prob.phi[[a, a + half]], prob.h_moc)
     pr = g.pairs[0]
-    cols = list(range(P)) + list(range(half * P, half * P + P))
+    cols = list(range(a * P, a * P + P)) + list(range((a + half) * P, (a + half) * P + P))
     I_in = prob.I_in[:, cols, :]
     order = np.argsort(-pr.nseg)
-    ks = np.sort(order[len(order) // 4:])     # skip the shortest (corner) characteristics
+    ks = np.sort(order[len(order) // 4:])
     done_upd, t_used, n_rays = 0, 0.0, 0
     chunk, q = 16, 0
     while t_used < budget_s:
@@ -184,10 +234,56 @@ def cpu_baseline(prob, budget_s=12.0):
         t_used += time.perf_counter() - t0
         done_upd += int(pr.nseg[sel].sum()) * 2 * P * G
         n_rays += len(sel)
-    return dict(value=done_upd / t_used, unit="segment-updates/s", cores=1, kind="oracle",
-                sample=f"oracle FP64 sweep of {n_rays} characteristics of azimuth pair 0 of member "
-                       f"{prob.name} ({prob.nx}x{prob.ny}, G={G}, {prob.M} directions; both traversals; "
-                       f"{done_upd} updates in {t_used:.1f} s; numpy on one host thread)")
+    return done_upd, t_used, n_rays
+
+
+def _oracle_pair_job(args):
+    member, a, budget_s = args
+    import workloads as W
+    prob = W.batch_problems(steps=1, only=[member])[0]
+    return _oracle_pair_sample(prob, a, budget_s)
+
+
+def _host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count()
+    return dict(model=model, nproc=os.cpu_count(), affinity=avail)
+
+
+def cpu_baseline(prob, member, budget_s=12.0):
+    """The oracle's sweep (unchanged) on a bounded sample of the workload's
+    largest member, timed on the host: one process per azimuth pair (up to
+    16, spawned), each sweeping characteristics of its pair for `budget_s`
+    seconds; the aggregate rate is the sum of the processes' rates.  The
+    single-process rate on pair 0 is reported beside it."""
+    import multiprocessing as mp
+    host = _host_cpu()
+    n_pairs = prob.n_az // 2
+    nproc = max(1, min(16, host["affinity"] or 1, n_pairs))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(nproc) as pool:
+        res = pool.map(_oracle_pair_job, [(member, a, budget_s) for a in range(nproc)], chunksize=1)
+    rate = sum(u / t for u, t, _ in res)
+    upd = sum(u for u, _, _ in res)
+    rays = sum(r for _, _, r in res)
+    u1, t1, r1 = _oracle_pair_sample(prob, 0, budget_s)
+    return dict(value=rate, unit="segment-updates/s", cores=nproc, kind="oracle",
+                sample=f"oracle FP64 sweep, one process per azimuth pair ({nproc} pairs) of member "
+                       f"{prob.name} ({prob.nx}x{prob.ny}, G={prob.G}, {prob.M} directions), both "
+                       f"traversals, {rays} characteristics, {upd} updates, about {budget_s:.0f} s per "
+                       f"process; host: {host['model']}, {host['nproc']} CPUs ({host['affinity']} usable)",
+                single_process=dict(value=u1 / t1, updates=u1, seconds=t1, characteristics=r1),
+                host=host)
 
 
 def time_grey_closures(s, reps=20):
@@ -455,6 +551,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--f64-steps", type=int, default=2)
+    ap.add_argument("--check-steps", type=int, default=5,
+                    help="steps over which the float32 moments are compared with float64 ones")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -467,6 +565,7 @@ def main():
 
     import torch
     import workloads as W
+    from paper_2305_11998_amd import lc
 
     torch.cuda.init()
     if args.copy_calibration:
@@ -489,33 +588,48 @@ def main():
     t0 = time.time()
     probs = W.batch_problems(steps=1)
     _say(f"64 problems generated in {time.time() - t0:.0f} s")
-    r32 = run_batched_f32(probs, args.steps, args.warmup)
+    r32 = run_batched(probs, args.steps, args.warmup, lc.LC_F32,
+                      snapshot_steps=0 if args.no_f64 else args.check_steps)
     bs = r32.pop("bs")
     upd = bs.updates_per_step()
     alg = sum(sweep_algorithmic_bytes(s, 4) for s in bs.solvers)
+    step_alg = sum(step_algorithmic_bytes(s, 4) for s in bs.solvers)
     ms32 = r32["ms"] / args.steps
     _say(f"f32 batched: {ms32:.3f} ms/step (eager, phase by phase {r32['ms_eager'] / args.steps:.3f}), "
          f"sweep {r32['sweep_ms']:.3f} ms, moments {r32['moments_ms']:.3f} ms, "
          f"prologue {r32['prologue_ms']:.3f} ms, {upd} updates/step")
-    mom32 = r32["moments"]
+    snaps = r32.pop("snapshots")
     del bs
     torch.cuda.empty_cache()
 
-    out_f64, errs = None, None
+    out_f64, out_f64b, errs = None, None, None
     if not args.no_f64:
-        r64 = run_plain_f64(probs, args.f64_steps)
-        errs = {k: 0.0 for k in ("E", "F", "f")}
-        for a, b in zip(mom32, r64["moments"]):
-            e = moment_errors(a, b)
-            for k in errs:
-                errs[k] = max(errs[k], e[k])
+        r64b = run_batched(probs, args.steps, args.warmup, lc.LC_F64)
+        bs64 = r64b.pop("bs")
+        alg64 = sum(sweep_algorithmic_bytes(s, 8) for s in bs64.solvers)
+        del bs64
+        torch.cuda.empty_cache()
+        ms64b = r64b["ms"] / args.steps
+        out_f64b = {"value": upd / (ms64b / 1e3), "unit": "segment-updates/s", "ms_per_step": ms64b,
+                    "sweep_ms": r64b["sweep_ms"], "moments_ms": r64b["moments_ms"],
+                    "sweep_achieved_GBs": alg64 / (r64b["sweep_ms"] / 1e3) / 1e9,
+                    "tuning": r64b["tuning"]["per_class"],
+                    "form": "float64 batched: the same launches and graph-captured steps as the float32 form"}
+        _say(f"f64 batched: {ms64b:.3f} ms/step, sweep {r64b['sweep_ms']:.3f} ms, "
+             f"moments {r64b['moments_ms']:.3f} ms")
+        r64 = run_plain_f64(probs, args.f64_steps, snaps)
+        errs = dict(r64["worst"], steps_checked=len(snaps), per_step=r64["per_step"])
         v64 = r64["updates"] / (r64["ms_per_step"] / 1e3)
         out_f64 = {"value": v64, "unit": "segment-updates/s", "ms_per_step": r64["ms_per_step"],
                    "form": "plain float64 sweep + moments, problem by problem"}
-        _say(f"f64 plain: {r64['ms_per_step']:.3f} ms/step; f32 vs f64 max errors {errs}")
+        _say(f"f64 plain: {r64['ms_per_step']:.3f} ms/step; f32 vs f64 max errors over "
+             f"{len(snaps)} steps {r64['worst']}")
+    del snaps
+    torch.cuda.empty_cache()
 
     value = upd / (ms32 / 1e3)
     achieved = alg / (r32["sweep_ms"] / 1e3) / 1e9
+    step_achieved = step_alg / (ms32 / 1e3) / 1e9
     traffic = recorded_traffic(r32["tuning"]["per_class"])
     out = {
         "metric": "segment-updates/s, FP32 batched vs FP64 sweep at <=1e-5 rel error",
@@ -536,18 +650,25 @@ def main():
                    "updates_per_step": upd, "eager_ms_per_step": r32["ms_eager"] / args.steps,
                    "tuning": r32["tuning"]["per_class"]},
         "fp64_plain": out_f64,
+        "fp64_batched": out_f64b,
         "speedup_vs_fp64": (value / out_f64["value"]) if out_f64 else None,
+        "speedup_vs_fp64_batched": (value / out_f64b["value"]) if out_f64b else None,
         "fp32_vs_fp64_max_err": errs,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_source": "recorded: rocprofv3 FETCH_SIZE + WRITE_SIZE of the same sweep sources "
+                                       "(profiles/sweep_batch_traffic.txt, source hash checked), scaled by a "
+                                       "plain copy's counts",
                      "kernel": "k_sweep_batch<float,PM,U> (one launch per polar group, summed)",
                      "kernel_ms": r32["sweep_ms"],
-                     "moments_kernel_ms": r32["moments_ms"], "algorithmic_bytes_per_launch": alg},
+                     "moments_kernel_ms": r32["moments_ms"], "algorithmic_bytes_per_launch": alg,
+                     "step_algorithmic_bytes": step_alg, "step_achieved": step_achieved,
+                     "step_frac": step_achieved / HBM_PEAK_GBS},
     }
     if not args.no_cpu_baseline:
         _say("cpu baseline (oracle sample)")
-        big = max(probs, key=lambda p: p.cells * p.G * p.M)
-        out["cpu_baseline"] = cpu_baseline(big)
+        big = max(range(len(probs)), key=lambda j: probs[j].cells * probs[j].G * probs[j].M)
+        out["cpu_baseline"] = cpu_baseline(probs[big], big)
     print(json.dumps(out), flush=True)
 
 
