@@ -3,8 +3,8 @@ multilevel method, eq. (4), for one backward-Euler time step on the material
 grid, closed by the Eddington tensors of the transport sweep (eq. (7), (15)
 for cells, (16) for faces) and the half-range boundary factor C.
 
-TEST INFRASTRUCTURE ONLY: plain Python + scipy's sparse direct solver; the
-HIP library never imports it.
+TEST INFRASTRUCTURE ONLY: plain Python + scipy's sparse direct solver (on
+the row-scaled system); the HIP library never imports it.
 
 Time-discrete equations (backward Euler, kappa_t = kappa + 1/(c dt)):
     c kappa_t E + div F = 4 pi kappa B + E^{n-1}/dt                   (4a)
@@ -132,12 +132,9 @@ def boundary_condition(C, Phi_in, J_in, c):
     return C * c, -C * Phi_in - J_in
 
 
-def solve_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc):
-    """One group.  kappa, planck, E_prev: [cells]; F_prev: [faces] normal
-    flux of the previous step (x component on x-faces, y on y-faces);
-    f_cell: [3][cells] and f_face: [3][faces] Eddington tensor entries
-    (xx, xy, yy); bc: [nb][3] = (C, Phi^-, J^-) per boundary face.
-    Returns (E_cell [cells], E_face [faces], F_face [faces])."""
+def assemble_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc):
+    """The linear system of one group: (A [n][n] sparse, rhs [n], per-group
+    data), n = cells + faces, cell unknowns first."""
     q = _Group(nx, ny, lx, ly, c, c_dt, kappa, F_prev, f_cell, f_face)
     N = q.N
     nf = n_faces(nx, ny)
@@ -178,7 +175,25 @@ def solve_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, 
             add(r, [(N + f, -ce)], 1.0)
             rhs[r] = cc - sgn * c1
     A = sp.csr_matrix((vals, (rows, cols)), shape=(N + nf, N + nf))
-    x = spla.spsolve(A.tocsc(), rhs)
+    return A, rhs, q
+
+
+def solve_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc):
+    """One group.  kappa, planck, E_prev: [cells]; F_prev: [faces] normal
+    flux of the previous step (x component on x-faces, y on y-faces);
+    f_cell: [3][cells] and f_face: [3][faces] Eddington tensor entries
+    (xx, xy, yy); bc: [nb][3] = (C, Phi^-, J^-) per boundary face.
+    Returns (E_cell [cells], E_face [faces], F_face [faces])."""
+    A, rhs, q = assemble_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc)
+    N = q.N
+    nf = n_faces(nx, ny)
+    lo, hi, _ = face_cells(nx, ny)
+    # Each equation is divided by its largest coefficient before the direct
+    # solve.  The solution is unchanged, but in optically thick cells the
+    # balance rows (of order c kappa_t) would otherwise dwarf the face rows
+    # (of order c / (kappa_t h)) and leave the solve with few correct digits.
+    scale = 1.0 / abs(A).max(axis=1).toarray().ravel()
+    x = spla.spsolve((sp.diags(scale) @ A).tocsc(), scale * rhs)
     E_cell, E_face = x[:N], x[N:]
     F_face = np.zeros(nf)
     for f in range(nf):

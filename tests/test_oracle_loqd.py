@@ -12,6 +12,9 @@ multigroup low-order equations, eq. (4), for one backward-Euler step.
 * Every cell balances with the returned fluxes, both cells next to a face
   give it the same flux, and the sources equal the outflow over the
   boundary (conservation).
+* With opacities up to 1e8 per cm the solution equals a dense solve of the
+  system with the cell unknowns eliminated by hand (full accuracy in
+  optically thick cells).
 * Planted mistakes (cross-term sign, cell tensor on the face, previous-step
   flux dropped, boundary-condition sign) fail the pins."""
 import math
@@ -275,6 +278,38 @@ def test_discrete_conservation():
     # and the boundary condition holds
     C, Pm, Jm = bc.T
     assert np.allclose(sgn * ff[nint:], C * (c * ef[nint:] - Pm) - Jm, rtol=1e-10, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# accuracy with optically thick cells
+# ---------------------------------------------------------------------------
+
+def test_thick_cells_keep_full_accuracy():
+    """Opacities from 0.1 to 1e8 per cm (the Fleck-Cummings law at 1 eV gives
+    such values in the lowest groups): the oracle's solution equals a dense
+    solve of the system with the cell unknowns eliminated by hand (each cell
+    equation holds only E_i and its own faces), to 1e-12 normwise.  An
+    unscaled direct solve of the full system is off by about 1e-3 here."""
+    import scipy.sparse.linalg as spla
+    args = list(_random_case(nx=12, ny=9, lx=1.2, ly=0.9, seed=8))
+    rng = np.random.default_rng(8)
+    args[6] = 10.0 ** rng.uniform(-1, 8, 12 * 9)
+    args[5] = 3.0
+    args[4] = 299.792458
+    e, ef, ff = loqd.solve_group(*args)
+    A, b, q = loqd.assemble_group(*args)
+    N = q.N
+    Ad = A.toarray()
+    assert np.count_nonzero(Ad[:N, :N] - np.diag(np.diag(Ad[:N, :N]))) == 0
+    dc = np.diag(Ad[:N, :N])
+    S = Ad[N:, N:] - Ad[N:, :N] @ (Ad[:N, N:] / dc[:, None])
+    xf = np.linalg.solve(S, b[N:] - Ad[N:, :N] @ (b[:N] / dc))
+    xc = (b[:N] - Ad[:N, N:] @ xf) / dc
+    ref = np.concatenate([xc, xf])
+    got = np.concatenate([e, ef])
+    assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
+    plain = spla.spsolve(A.tocsc(), b)
+    assert np.max(np.abs(plain - ref)) > 1e3 * np.max(np.abs(got - ref))   # the scaling matters here
 
 
 # ---------------------------------------------------------------------------
