@@ -307,6 +307,61 @@ lc_status lc_grey_closures_dims(int32_t cells, int32_t G, const double* E, const
                                 const double* kappa, const double* planck, double* out, void* stream);
 
 /*
+ * Multigroup low-order quasidiffusion (LOQD) equations, eq. (4), for one
+ * backward-Euler time step on the material grid, closed by the Eddington
+ * tensors of the transport sweep (cells: eq. (7), (15); faces: eq. (16))
+ * and its half-range boundary factors.  Time-discrete, with
+ * kappa_t = kappa + 1/(c dt):
+ *   c kappa_t E + div F = 4 pi kappa B + E^{n-1}/dt,
+ *   kappa_t F + c div(f E) = F^{n-1}/(c dt).
+ * The paper cites its second-order finite-volume scheme without printing
+ * it; the scheme here: unknowns are the cell averages E_i and the face
+ * averages E_f of every group; the balance is integrated over each cell;
+ * the first moment over each half cell next to a face, with kappa_t F taken
+ * at the face, the cell tensor times E_i at the centre, the face tensor
+ * times E_f on the face and the cell's transverse face averages for the
+ * mixed term; an interior face has one normal flux; a boundary face closes
+ * with n.F = C (c E_f - Phi^-) - J^- (C, Phi^-, J^- from the boundary
+ * factors).  Faces are numbered as for lc_face_moments (interior x-faces,
+ * then interior y-faces), followed by the boundary faces in their own order
+ * (nf = (nx-1) ny + nx (ny-1) + 2 (nx + ny)); normal fluxes are the x
+ * component on x-faces and the y component on y-faces.
+ *
+ * lc_loqd_create -- solver handle for an nx x ny grid on [0,lx] x [0,ly]
+ * and G groups; holds the face structure and the solver's workspace
+ * (about (22 G + 11) nf + (6 G + 4) nx ny doubles).  Errors: LC_ERR_ARG,
+ * LC_ERR_ALLOC, LC_ERR_HIP.
+ *
+ * lc_loqd_solve -- one step for every group.  Inputs (device, float64):
+ * kappa, planck, E_prev [G][cells]; F_prev [G][nf]; f_cell [cells][4][G]
+ * (the layout lc_moments writes); f_face [interior faces][4][G] (the layout
+ * lc_face_moments writes; may be NULL on a grid without interior faces);
+ * bnd [G][nb][8] (the layout lc_moments writes: C in column 4, Phi^- in 2,
+ * J^- in 3, the face tensor in 5-7).  Outputs: E_cell [G][cells], E_face
+ * [G][nf], F_face [G][nf].  The cell unknowns are eliminated exactly (the
+ * mixed terms cancel in each cell balance, so a cell row holds its own four
+ * faces only) and the face system of every group is solved by BiCGSTAB
+ * with a Jacobi preconditioner, all groups at once, to a relative residual
+ * rtol of the face system (its true residual is checked at the end, up to
+ * three restarts); inner products are fixed-order reductions, so results
+ * are deterministic.  iters (host, may be NULL) receives the iterations
+ * run; resid (host [G], may be NULL) each group's final relative residual.
+ * Synchronises `stream` (convergence checks), so it cannot be captured in a
+ * graph.  Errors: LC_ERR_ARG (NULL inputs or outputs, c or c_dt not finite
+ * or <= 0, rtol outside (0, 1), max_iter < 1), LC_ERR_STATE (invalid
+ * handle), LC_ERR_UNSUPPORTED (some group above rtol after max_iter
+ * iterations; the outputs then hold the last iterate), LC_ERR_HIP.
+ */
+typedef struct lc_loqd_s* lc_loqd_t;
+lc_status lc_loqd_create(int32_t nx, int32_t ny, double lx, double ly, int32_t G, lc_loqd_t* out);
+lc_status lc_loqd_free(lc_loqd_t loqd);
+lc_status lc_loqd_solve(lc_loqd_t loqd, double c, double c_dt, const double* kappa, const double* planck,
+                        const double* E_prev, const double* F_prev, const double* f_cell,
+                        const double* f_face, const double* bnd, double* E_cell, double* E_face,
+                        double* F_face, double rtol, int32_t max_iter, int32_t* iters, double* resid,
+                        void* stream);
+
+/*
  * lc_step -- n_steps backward-Euler time steps (sweep, then moments) with the
  * state ping-ponging between state_a and state_b: step t reads the state
  * written by step t-1 (step 0 reads state_a); after an odd number of steps

@@ -75,6 +75,10 @@ _SIGS = {
     "lc_state_export": ([_vp, _vp, _vp, _vp], C.c_int),
     "lc_sweep": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_sweep_noalloc": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "lc_loqd_create": ([_i32, _i32, _d, _d, _i32, C.POINTER(_vp)], C.c_int),
+    "lc_loqd_free": ([_vp], C.c_int),
+    "lc_loqd_solve": ([_vp, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i32, _vp, _vp, _vp],
+                      C.c_int),
     "lc_moments": ([_vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_step": ([_vp, _i32, _vp, _vp, _i64, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_grey_closures": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp], C.c_int),
@@ -433,3 +437,45 @@ def lc_batch_profile_read(batch: Batch):
     _check(_lib.lc_batch_profile_read(batch.handle, out))
     return tuple(out)
 
+
+
+class Loqd:
+    """Owning wrapper of an ``lc_loqd_t`` handle (multigroup LOQD solver of
+    an nx x ny grid for G groups)."""
+
+    def __init__(self, nx, ny, lx, ly, G):
+        h = C.c_void_p()
+        _check(_lib.lc_loqd_create(int(nx), int(ny), float(lx), float(ly), int(G), C.byref(h)))
+        self.handle = h
+        self.nx, self.ny, self.G = int(nx), int(ny), int(G)
+        self.cells = self.nx * self.ny
+        self.n_interior = (self.nx - 1) * self.ny + self.nx * (self.ny - 1)
+        self.nb = 2 * (self.nx + self.ny)
+        self.nf = self.n_interior + self.nb
+
+    def free(self):
+        if self.handle:
+            _check(_lib.lc_loqd_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def lc_loqd_solve(h: Loqd, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bnd, E_cell, E_face, F_face,
+                  rtol=1e-13, max_iter=20000, stream=None):
+    """Returns (iterations, per-group relative residuals)."""
+    G, N, nf = h.G, h.cells, h.nf
+    it = C.c_int32(0)
+    res = np.zeros(G)
+    _check(_lib.lc_loqd_solve(h.handle, float(c), float(c_dt), _dev(kappa, G * N, name="kappa"),
+                              _dev(planck, G * N, name="planck"), _dev(E_prev, G * N, name="E_prev"),
+                              _dev(F_prev, G * nf, name="F_prev"), _dev(f_cell, 4 * G * N, name="f_cell"),
+                              _dev(f_face, 4 * G * h.n_interior, name="f_face", optional=h.n_interior == 0),
+                              _dev(bnd, 8 * G * h.nb, name="bnd"), _dev(E_cell, G * N, name="E_cell"),
+                              _dev(E_face, G * nf, name="E_face"), _dev(F_face, G * nf, name="F_face"),
+                              float(rtol), int(max_iter), C.byref(it), res.ctypes.data, _stream(stream)))
+    return int(it.value), res

@@ -1,0 +1,227 @@
+"""GPU: the multigroup LOQD solve (lc_loqd_solve, eq. (4) for one
+backward-Euler step) against the oracle's sparse direct solve of the same
+finite-volume scheme (oracle/loqd.py), on the same inputs.
+
+The GPU solves the face system by BiCGSTAB to a relative residual of 1e-13
+and the oracle solves it directly, so the two differ by the iteration's
+error, bounded by the system's condition number times the residual (about
+1e4 x 1e-13 on these grids).  Comparisons are normwise per group --
+max |x - x_ref| / max |x_ref| over the cells, the faces and the face fluxes --
+at 1e-9.  Cases: random coefficients (several groups, ragged grids, more
+than one reduction block), the smooth manufactured solution of the oracle's
+convergence pin, an optically thin worst case, closures from the oracle's
+own transport solve on the 16 x 16 workload fed to both, and the whole chain
+on the GPU (sweep with face intensities, moments, LOQD) against the whole
+chain in the oracle."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import faces as OF, loqd as OL, moments as OM, rays as OR, solve as OSV, sweep as OS
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-9
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lcmod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_11998_amd import driver, lc
+    return lc, driver
+
+
+def _gpu_layouts(nx, ny, f_cell, f_face, bc):
+    """Oracle-side closures -> the library's layouts: f_cell [G][3][cells] ->
+    [cells][4][G]; interior f_face [G][3][faces] -> [interior][4][G]; boundary
+    tensors and (C, Phi^-, J^-) -> bnd [G][nb][8]."""
+    G, _, N = f_cell.shape
+    nint = OL.n_interior(nx, ny)
+    nb = 2 * (nx + ny)
+    fc = np.full((N, 4, G), 1.0 / 3.0)
+    fc[:, :3, :] = f_cell.transpose(2, 1, 0)
+    ff = np.full((max(nint, 1), 4, G), 1.0 / 3.0)
+    ff[:nint, :3, :] = f_face[:, :, :nint].transpose(2, 1, 0)
+    bnd = np.zeros((G, nb, 8))
+    bnd[:, :, 4] = bc[:, :, 0]
+    bnd[:, :, 2] = bc[:, :, 1]
+    bnd[:, :, 3] = bc[:, :, 2]
+    bnd[:, :, 5:8] = f_face[:, :, nint:].transpose(0, 2, 1)
+    return fc, ff, bnd
+
+
+def _gpu_solve(lc, nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc, rtol=1e-13,
+               max_iter=20000):
+    import torch
+    G = kappa.shape[0]
+    fc, ff, bnd = _gpu_layouts(nx, ny, f_cell, f_face, bc)
+    h = lc.Loqd(nx, ny, lx, ly, G)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    Ec = torch.zeros(G * h.cells, dtype=torch.float64, device="cuda")
+    Ef = torch.zeros(G * h.nf, dtype=torch.float64, device="cuda")
+    Ff = torch.zeros(G * h.nf, dtype=torch.float64, device="cuda")
+    it, res = lc.lc_loqd_solve(h, c, c_dt, d(kappa), d(planck), d(E_prev), d(F_prev), d(fc), d(ff), d(bnd),
+                               Ec, Ef, Ff, rtol=rtol, max_iter=max_iter)
+    out = (Ec.cpu().numpy().reshape(G, -1), Ef.cpu().numpy().reshape(G, -1), Ff.cpu().numpy().reshape(G, -1))
+    return out, it, res
+
+
+def _compare(got, ref, what):
+    worst = 0.0
+    for name, a, b in zip(("E_cell", "E_face", "F_face"), got, ref):
+        for g in range(a.shape[0]):
+            scale = np.max(np.abs(b[g]))
+            if scale == 0.0:
+                assert np.max(np.abs(a[g])) == 0.0
+                continue
+            worst = max(worst, float(np.max(np.abs(a[g] - b[g])) / scale))
+    _say(f"  {what}: worst normwise difference {worst:.2e}")
+    assert worst <= TOL
+    return worst
+
+
+def _random_groups(nx, ny, lx, ly, G, seed, thin=False):
+    rng = np.random.default_rng(seed)
+    N, nf = nx * ny, OL.n_faces(nx, ny)
+    nb = 2 * (nx + ny)
+    c, c_dt = 299.792458, 3.0
+    scale = 10.0 ** rng.uniform(-3, 3, G)[:, None]
+    kappa = np.zeros((G, N)) if thin else 10.0 ** rng.uniform(-2, 3, (G, N))
+    planck = rng.uniform(0, 1, (G, N)) * scale
+    E_prev = rng.uniform(0, 1, (G, N)) * scale * 4 * math.pi / c
+    F_prev = rng.uniform(-0.3, 0.3, (G, nf)) * scale
+
+    def tensors(n):
+        a = rng.uniform(0.15, 0.6, (G, n))
+        dd = rng.uniform(0.15, 0.6, (G, n))
+        b = rng.uniform(-0.5, 0.5, (G, n)) * np.sqrt(a * dd)
+        return np.stack([a, b, dd], axis=1)
+    bc = np.stack([rng.uniform(0.3, 0.7, (G, nb)), rng.uniform(0, 1, (G, nb)) * scale,
+                   rng.uniform(0, 0.5, (G, nb)) * scale], axis=2)
+    return (nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, tensors(N), tensors(nf), bc)
+
+
+@pytest.mark.parametrize("shape", [(7, 5, 1.4, 0.7, 3), (33, 20, 3.3, 1.0, 5), (1, 6, 0.2, 1.2, 2), (9, 1, 0.9, 0.1, 2)])
+def test_loqd_random_coefficients(lcmod, shape):
+    lc, _ = lcmod
+    nx, ny, lx, ly, G = shape
+    args = _random_groups(nx, ny, lx, ly, G, seed=nx * 31 + ny)
+    _say(f"case loqd random {nx}x{ny} G={G}")
+    ref = OL.solve(*args)
+    got, it, res = _gpu_solve(lc, *args)
+    _say(f"  {it} iterations, residuals {np.max(res):.1e}")
+    _compare(got, ref, "random")
+
+
+def test_loqd_thin_worst_case(lcmod):
+    """kappa = 0 (only 1/(c dt) attenuates): the most diffusive system."""
+    lc, _ = lcmod
+    args = _random_groups(48, 40, 6.0, 5.0, 2, seed=5, thin=True)
+    _say("case loqd thin 48x40 G=2")
+    ref = OL.solve(*args)
+    got, it, res = _gpu_solve(lc, *args)
+    _say(f"  {it} iterations, residuals {np.max(res):.1e}")
+    _compare(got, ref, "thin")
+
+
+def test_loqd_manufactured_solution(lcmod):
+    lc, _ = lcmod
+    from tests.test_oracle_loqd import _manufactured_case
+    args, exact, _ = _manufactured_case(32)
+    nx, ny, lx, ly, c, c_dt, kap, planck, E_prev, F_prev, f_cell, f_face, bc = args
+    stack = (nx, ny, lx, ly, c, c_dt, kap[None], planck[None], E_prev[None], F_prev[None], f_cell[None],
+             f_face[None], bc[None])
+    _say("case loqd manufactured 32x32")
+    ref = OL.solve(*stack)
+    got, it, res = _gpu_solve(lc, *stack)
+    _compare(got, ref, "manufactured")
+    # and the GPU solution approximates the exact one to the scheme's accuracy
+    assert np.sqrt(np.mean((got[0][0] - exact[0]) ** 2)) < 1e-4
+
+
+def _oracle_transport_closures(prob):
+    """Cell, interior-face and boundary closures of one step of the oracle's
+    transport solve (with the upwind-face intensities of the sweep)."""
+    g = OR.build(prob.nx, prob.ny, prob.lx, prob.ly, prob.phi, prob.h_moc)
+    st = OS.initial_state(g, prob.n_pol, prob.state0)
+    pts = np.zeros_like(st)
+    st, exits = OS.sweep(g, prob.mu, prob.kappa[0], prob.planck[0], prob.c_dt, st, prob.I_in, points=pts)
+    E, F, f = OM.cell_moments(g, prob.phi, prob.mu, prob.omega, st, W.C_LIGHT)
+    bnd = OM.boundary_factors(g, prob.phi, prob.mu, prob.omega, exits, prob.I_in)
+    Ef, Ff, ff = OF.face_moments(g, prob.phi, prob.mu, prob.omega, pts, W.C_LIGHT)
+    return E, f, ff, bnd
+
+
+def _loqd_inputs(prob):
+    c = W.C_LIGHT
+    G, N = prob.G, prob.cells
+    nf = OL.n_faces(prob.nx, prob.ny)
+    E_prev = 4 * math.pi * prob.state0 / c                 # E^{n-1} of the isotropic initial intensity
+    return c, prob.c_dt, prob.kappa[0], prob.planck[0], E_prev, np.zeros((G, nf))
+
+
+def test_loqd_with_oracle_transport_closures(lcmod):
+    lc, _ = lcmod
+    prob = W.config(0)
+    _say("case loqd on oracle transport closures, 16x16 G=4")
+    E_tr, f, ff, bnd = _oracle_transport_closures(prob)
+    f_cell, f_face, bc = OL.closures_from_transport(prob.nx, prob.ny, f, ff, bnd)
+    c, c_dt, kap, pla, E_prev, F_prev = _loqd_inputs(prob)
+    args = (prob.nx, prob.ny, prob.lx, prob.ly, c, c_dt, kap, pla, E_prev, F_prev, f_cell, f_face, bc)
+    ref = OL.solve(*args)
+    got, it, res = _gpu_solve(lc, *args)
+    _compare(got, ref, "oracle closures")
+    # the low-order solution is consistent with the transport's energy density
+    gE = got[0].sum(0)
+    tE = E_tr.sum(0)
+    _say(f"  grey E: LOQD vs transport max relative difference {np.max(np.abs(gE - tE) / tE):.2e}")
+
+
+def test_loqd_whole_chain_on_gpu(lcmod):
+    """Sweep storing face intensities, cell and face moments, boundary factors
+    and the LOQD solve all in the library, from the problem's inputs only,
+    against the same chain in the oracle."""
+    import torch
+    lc, driver = lcmod
+    prob = W.config(0)
+    _say("case loqd whole chain 16x16 G=4")
+    s = driver.Solver(prob, prec=lc.LC_F64)
+    s.enable_faces()
+    s.reset()
+    s.step_faces(1)
+    G, N = prob.G, prob.cells
+    h = lc.Loqd(prob.nx, prob.ny, prob.lx, prob.ly, G)
+    c, c_dt, kap, pla, E_prev, F_prev = _loqd_inputs(prob)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+    Ec = torch.zeros(G * N, dtype=torch.float64, device="cuda")
+    Ef = torch.zeros(G * h.nf, dtype=torch.float64, device="cuda")
+    Ff = torch.zeros(G * h.nf, dtype=torch.float64, device="cuda")
+    lc.lc_loqd_solve(h, c, c_dt, s.kappa[0].reshape(-1), s.planck[0].reshape(-1), d(E_prev), d(F_prev), s.f,
+                     s.ff, s.bnd, Ec, Ef, Ff)
+    got = (Ec.cpu().numpy().reshape(G, -1), Ef.cpu().numpy().reshape(G, -1), Ff.cpu().numpy().reshape(G, -1))
+    _, f, ff, bnd = _oracle_transport_closures(prob)
+    f_cell, f_face, bc = OL.closures_from_transport(prob.nx, prob.ny, f, ff, bnd)
+    ref = OL.solve(prob.nx, prob.ny, prob.lx, prob.ly, c, c_dt, kap, pla, E_prev, F_prev, f_cell, f_face, bc)
+    _compare(got, ref, "whole chain")
+
+
+def test_loqd_is_deterministic_and_reports_non_convergence(lcmod):
+    lc, _ = lcmod
+    args = _random_groups(20, 16, 2.0, 1.6, 3, seed=9)
+    a, _, _ = _gpu_solve(lc, *args)
+    b, _, _ = _gpu_solve(lc, *args)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    with pytest.raises(lc.LcError) as e:
+        _gpu_solve(lc, *args, rtol=1e-15, max_iter=1)
+    assert e.value.status == lc.LC_ERR_UNSUPPORTED
