@@ -175,6 +175,19 @@ lc_status lc_state_fill(lc_plan_t plan, const double* field, void* state, void* 
 lc_status lc_state_export(lc_plan_t plan, const void* state, double* out, void* stream);
 
 /*
+ * lc_state_import -- the inverse of lc_state_export: fill a state buffer
+ * from finite float64 values in the canonical order [n_segments][2][n_pol][G]
+ * (resuming a run from an exported state, or moving a state between
+ * precisions).  LC_F64 plans store the values as they are; LC_F32 plans
+ * take each group's power-of-two scale from its largest magnitude and store
+ * the exactly rescaled values rounded to float32.  Uses the plan's
+ * group-maximum workspace, so order it with the plan's sweeps on one stream.
+ * Errors: LC_ERR_ARG (NULL), LC_ERR_UNSUPPORTED (more than 2^31 x 1024
+ * value rows), LC_ERR_HIP.
+ */
+lc_status lc_state_import(lc_plan_t plan, const double* in, void* state, void* stream);
+
+/*
  * lc_sweep -- one backward-Euler transport sweep, eq. (10)-(13), over every
  * characteristic, direction and group:
  *   kappa_t = kappa + 1/(c dt),  Q = kappa B + I_bar^{n-1}/(c dt),
@@ -386,7 +399,8 @@ lc_status lc_step(lc_plan_t plan, int32_t n_steps, const double* kappa, const do
  * in flight ahead of the arithmetic, 1, 2, 4, 8 or 16 (16: LC_F32 plans with
  * n_pol <= 4 only); moments_entries: entries of each (cell,
  * azimuth pair) list whose loads go through the moment kernel's pipeline, 1 to
- * 4 (longer lists finish in a plain loop).  Setting the tuning drops the plan's captured graphs.
+ * 4 (longer lists finish in a plain loop).  Setting the tuning synchronises the
+ * device and drops the plan's captured graphs.
  * Errors: LC_ERR_ARG for a null tuning or a value outside those sets (the
  * plan keeps its previous tuning).
  */
@@ -404,8 +418,8 @@ lc_status lc_plan_get_tuning(lc_plan_t plan, lc_tuning_t* tuning);
  * problems are served better by the caches that way; capped = 0: residency
  * is set by the kernel's registers alone, which shortens the tail of small
  * problems.  Results are bit-identical either way.  Batches keep the cap.
- * Drops the plan's captured graphs.  Errors: LC_ERR_ARG for a value other
- * than 0 or 1.
+ * Synchronises the device and drops the plan's captured graphs.  Errors:
+ * LC_ERR_ARG for a value other than 0 or 1.
  */
 lc_status lc_plan_set_sweep_residency(lc_plan_t plan, int32_t capped);
 

@@ -325,6 +325,13 @@ lc_status lc_state_export(lc_plan_t plan, const void* state, double* out, void* 
     return launch_state_export(pl, state, out, static_cast<hipStream_t>(stream));
 }
 
+lc_status lc_state_import(lc_plan_t plan, const double* in, void* state, void* stream) {
+    Plan* pl = as_plan(plan);
+    LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
+    LC_ARG(state && in, "in and state must not be NULL");
+    return launch_state_import(pl, in, state, static_cast<hipStream_t>(stream));
+}
+
 lc_status lc_sweep(lc_plan_t plan, const double* kappa, const double* planck, double c_dt,
                    const void* state_prev, void* state_new, const double* I_in, double* I_exit,
                    void* stream) {
@@ -459,6 +466,7 @@ lc_status lc_plan_set_tuning(lc_plan_t plan, const lc_tuning_t* t) {
     LC_ARG(t->sweep_unroll != 16 || (pl->prec == LC_F32 && pl->rays->n_pol <= kMaxPolUnroll16),
            "sweep_unroll 16 needs LC_F32 and n_pol <= %d", kMaxPolUnroll16);
     LC_ARG(t->moments_entries >= 1 && t->moments_entries <= 4, "moments_entries must be 1, 2, 3 or 4");
+    LC_HIP(hipDeviceSynchronize());   // no captured step of the plan is still running
     pl->sweep_unroll = t->sweep_unroll;
     pl->moments_entries = t->moments_entries;
     for (auto& g : pl->graphs)
@@ -476,6 +484,7 @@ lc_status lc_plan_set_sweep_residency(lc_plan_t plan, int32_t capped) {
         lc_status rc = sweep_lds_bytes(&lds);
         if (rc) return rc;
     }
+    LC_HIP(hipDeviceSynchronize());   // no captured step of the plan is still running
     pl->sweep_lds = lds;
     for (auto& g : pl->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -488,10 +497,10 @@ lc_status lc_plan_set_split(lc_plan_t plan, int32_t chunk_steps) {
     LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
     LC_ARG(chunk_steps >= 0 && chunk_steps % kSplitUnroll == 0 && chunk_steps <= (1 << 24),
            "chunk_steps must be 0 or a positive multiple of %d up to 2^24", kSplitUnroll);
+    LC_HIP(hipDeviceSynchronize());   // no sweep in flight still reads the old records
     for (auto& g : pl->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     pl->graphs.clear();
-    LC_HIP(hipDeviceSynchronize());   // no sweep in flight still reads the old records
     return plan_set_split(pl, chunk_steps);
 }
 

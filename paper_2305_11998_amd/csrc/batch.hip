@@ -54,7 +54,9 @@ struct Batch {
     std::vector<GraphEntry> graphs;
     hipStream_t capture = nullptr;
     hipStream_t side = nullptr;         // captured side branch (boundary factors, next prologue)
+    hipStream_t side_mom = nullptr;     // captured branch of the moments
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    hipEvent_t ev_mom[2] = {nullptr, nullptr};   // end of the moments of steps of either parity
     bool profile = false;               // eager steps with events around each phase
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[3];   // prologue, sweep, moments
 };
@@ -90,17 +92,24 @@ lc_status ev_end(Batch* b, int k, hipStream_t st) {
     return LC_OK;
 }
 
-// Enqueue n_steps time steps of every problem on st, one phase after the
-// other (with the phase timers when profiling).  Running the polar groups
-// on streams of their own was measured slower: their kernels contend for the
-// same caches and bandwidth rather than filling each other's tails.
+// Enqueue n_steps time steps of every problem on st.  Running the polar
+// groups on streams of their own was measured slower: their kernels contend
+// for the same caches and bandwidth rather than filling each other's tails.
 //
-// In a captured graph (no profiling) the work that does not feed the moments
-// runs on a side branch beside them, joined before the next step's sweep:
-// the boundary factors of step t (they need only the exit intensities) and
-// the prologue of step t + 1 (queue counters, source maxima, coefficient
-// table and the scale of the state that step t consumed -- nothing the
-// moments of step t read).
+// Eager (profiling): one phase after the other, with the phase timers.
+//
+// Captured graph: the sweeps stay on the main branch; after the sweep of step
+// t two branches fork from it:
+//   - the boundary factors of step t (they need only the exit intensities)
+//     and the prologue of step t + 1 (queue counters, source maxima,
+//     coefficient table, and the scale in the header of the state buffer
+//     that step t + 1 writes), joined before the sweep of step t + 1;
+//   - the moments of step t, which read the state of step t -- the sweep of
+//     step t + 1 only reads it too, so the two run side by side.
+// The sweep of step t + 2 and the prologue of step t + 2 write the buffer
+// (values and header) the moments of step t read, so both wait for them;
+// the moments of consecutive steps keep their order on their branch (they
+// write the same outputs).
 lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
     const size_t sb = sweep_args_bytes(), mb = mom_args_bytes();
     const bool branch = !b->profile;
@@ -113,36 +122,52 @@ lc_status enqueue_steps(Batch* b, int n_steps, hipStream_t st) {
         if (rc == LC_OK) rc = ev_end(b, 0, s);
         return rc;
     };
+    auto moments = [&](int t, hipStream_t s) {
+        lc_status rc = ev_begin(b, 2, s);
+        for (size_t c = 0; c < b->cls.size() && rc == LC_OK; ++c)
+            rc = launch_moments_batch(b->prec, b->cls[c].pm, b->cls[c].ent,
+                                      static_cast<char*>(b->d_mom_args) + (t & 1) * b->n * mb,
+                                      b->cls[c].d_mom_items, b->cls[c].n_mom_items, s);
+        if (rc == LC_OK) rc = ev_end(b, 2, s);
+        return rc;
+    };
+    auto wait = [&](hipStream_t s, hipEvent_t e) {
+        return hipStreamWaitEvent(s, e, 0) == hipSuccess ? LC_OK : LC_ERR_HIP;
+    };
+    auto record = [&](hipEvent_t e, hipStream_t s) {
+        return hipEventRecord(e, s) == hipSuccess ? LC_OK : LC_ERR_HIP;
+    };
     lc_status rc = LC_OK;
     for (int t = 0; t < n_steps && rc == LC_OK; ++t) {
         const int parity = t & 1;
         if (t == 0 || !branch) rc = prologue(t, st);  // later steps: on the previous step's branch
+        if (rc == LC_OK && branch && t >= 2) rc = wait(st, b->ev_mom[parity]);   // moments of step t - 2
         if (rc == LC_OK) rc = ev_begin(b, 1, st);
         for (size_t c = 0; c < b->cls.size() && rc == LC_OK; ++c)
             rc = launch_sweep_batch(b->prec, b->cls[c].pm, b->cls[c].unroll, b->cls[c].full, b->cls[c].sweep_lds,
                                     b->cls[c].sweep_grid, static_cast<char*>(b->d_sweep_args) + parity * b->n * sb,
                                     b->cls[c].d_sweep_items, b->cls[c].d_sweep_qb, b->d_counters + 8 * c, st);
         if (rc == LC_OK) rc = ev_end(b, 1, st);
-        const bool side = branch && (b->bnd_blocks > 0 || t + 1 < n_steps);
+        if (!branch) {
+            if (rc == LC_OK) rc = moments(t, st);
+            if (rc == LC_OK && b->bnd_blocks > 0) rc = launch_boundary_batch(b->d_bnd_args, b->n, b->bnd_blocks, st);
+            continue;
+        }
+        const bool side = b->bnd_blocks > 0 || t + 1 < n_steps;
+        if (rc == LC_OK) rc = record(b->ev_fork, st);
         if (rc == LC_OK && side) {
-            if (hipEventRecord(b->ev_fork, st) != hipSuccess || hipStreamWaitEvent(b->side, b->ev_fork, 0) != hipSuccess)
-                rc = LC_ERR_HIP;
+            rc = wait(b->side, b->ev_fork);
             if (rc == LC_OK && b->bnd_blocks > 0) rc = launch_boundary_batch(b->d_bnd_args, b->n, b->bnd_blocks, b->side);
+            if (rc == LC_OK && t + 1 < n_steps && t >= 1) rc = wait(b->side, b->ev_mom[parity ^ 1]);   // step t - 1
             if (rc == LC_OK && t + 1 < n_steps) rc = prologue(t + 1, b->side);
-            if (rc == LC_OK && hipEventRecord(b->ev_join, b->side) != hipSuccess) rc = LC_ERR_HIP;
+            if (rc == LC_OK) rc = record(b->ev_join, b->side);
         }
-        if (rc == LC_OK) {                            // every step forms its moments
-            rc = ev_begin(b, 2, st);
-            for (size_t c = 0; c < b->cls.size() && rc == LC_OK; ++c)
-                rc = launch_moments_batch(b->prec, b->cls[c].pm, b->cls[c].ent,
-                                          static_cast<char*>(b->d_mom_args) + parity * b->n * mb,
-                                          b->cls[c].d_mom_items, b->cls[c].n_mom_items, st);
-            if (rc == LC_OK) rc = ev_end(b, 2, st);
-            if (rc == LC_OK && !branch && b->bnd_blocks > 0)
-                rc = launch_boundary_batch(b->d_bnd_args, b->n, b->bnd_blocks, st);
-            if (rc == LC_OK && side && hipStreamWaitEvent(st, b->ev_join, 0) != hipSuccess) rc = LC_ERR_HIP;
-        }
+        if (rc == LC_OK) rc = wait(b->side_mom, b->ev_fork);
+        if (rc == LC_OK) rc = moments(t, b->side_mom);
+        if (rc == LC_OK) rc = record(b->ev_mom[parity], b->side_mom);
+        if (rc == LC_OK && side) rc = wait(st, b->ev_join);
     }
+    if (rc == LC_OK && branch && n_steps > 0) rc = wait(st, b->ev_mom[(n_steps - 1) & 1]);   // join the moments
     return rc;
 }
 
@@ -158,6 +183,9 @@ void free_batch(Batch* b) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (b->capture) (void)hipStreamDestroy(b->capture);
     if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->side_mom) (void)hipStreamDestroy(b->side_mom);
+    for (hipEvent_t e : b->ev_mom)
+        if (e) (void)hipEventDestroy(e);
     if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
     if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     for (void* p : {b->d_sweep_args, b->d_coef_args, b->d_mom_args, b->d_bnd_args,
@@ -207,6 +235,8 @@ lc_status build_moment_args(Batch* b, double c) {
         rc = upload(&b->d_bnd_args, hb.data(), hb.size());
         if (rc) return rc;
     } else {
+        // a step launched earlier (on any stream) may still read the records
+        LC_HIP(hipDeviceSynchronize());
         LC_HIP(hipMemcpy(b->d_mom_args, b->h_mom.data(), b->h_mom.size(), hipMemcpyHostToDevice));
         LC_HIP(hipMemcpy(b->d_bnd_args, hb.data(), hb.size(), hipMemcpyHostToDevice));
     }
@@ -362,6 +392,9 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
     if (rc == LC_OK) {
         hipError_t e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->side_mom, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_mom[0], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_mom[1], hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming);
         if (e != hipSuccess) {

@@ -201,6 +201,7 @@ lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, cons
                          double c, double* E, double* F, double* f, double* bnd, hipStream_t st);
 lc_status launch_state_fill(Plan* pl, const double* field, void* state, hipStream_t st);
 lc_status launch_state_export(Plan* pl, const void* state, double* out, hipStream_t st);
+lc_status launch_state_import(Plan* pl, const double* in, void* state, hipStream_t st);
 lc_status build_geometry(Rays* r, hipStream_t st);
 lc_status plan_init_sweep(Plan* pl);
 lc_status plan_set_split(Plan* pl, int len);

@@ -95,6 +95,49 @@ __global__ void k_export(SlotArgs A, const T* __restrict__ in, const int* __rest
     });
 }
 
+template <typename T>
+__global__ void k_import(SlotArgs A, const double* __restrict__ in, const int* __restrict__ e, T* out) {
+    for_slots(A, [&](int64_t slot, int j, int d, int g, int p) {
+        double v = 0.0;
+        if (j >= 0) {
+            v = in[(((int64_t)j * 2 + d) * A.P + p) * A.G + g];
+            if (sizeof(T) == 4) v = ldexp(v, -e[g]);
+        }
+        out[slot] = (T)v;
+    });
+}
+
+// Per-group largest magnitude of canonical values [rows][G] (rows =
+// segments x 2 x polar angles): block maxima in LDS, then integer atomics
+// on the bit patterns of the non-negative doubles (order-independent).
+__global__ void k_canon_max(const double* __restrict__ in, int64_t rows, int G, int64_t rows_per_block,
+                            unsigned long long* gmax) {
+    extern __shared__ unsigned long long sm[];
+    for (int g = threadIdx.x; g < G; g += blockDim.x) sm[g] = 0ull;
+    __syncthreads();
+    const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r1 = r0 + rows_per_block < rows ? r0 + rows_per_block : rows;
+    for (int64_t i = r0 * G + threadIdx.x; i < r1 * G; i += blockDim.x) {
+        const double v = fabs(in[i]);
+        atomicMax(&sm[i % G], (unsigned long long)__double_as_longlong(v));
+    }
+    __syncthreads();
+    for (int g = threadIdx.x; g < G; g += blockDim.x)
+        if (sm[g]) atomicMax(&gmax[g], sm[g]);
+}
+
+__global__ void k_scale_from_max(const unsigned long long* gmax, int G, int* e) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= G) return;
+    const double m = __longlong_as_double((long long)gmax[g]);
+    e[g] = (m > 0.0 && isfinite(m)) ? ilogb(m) + 1 : 0;
+}
+
+__global__ void k_zero_u64s(unsigned long long* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
+
 __global__ void k_zero_int(int* p, int n) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
@@ -136,6 +179,34 @@ lc_status launch_state_fill(Plan* pl, const double* field, void* state, hipStrea
         double* v = static_cast<double*>(state_values(pl, state));
         hipLaunchKernelGGL(k_zero_int, dim3((G + kBlock - 1) / kBlock), dim3(kBlock), 0, st, e, G);
         hipLaunchKernelGGL(k_fill<double>, dim3(nb), dim3(kBlock), 0, st, A, field, e, v);
+    }
+    LC_HIP(hipGetLastError());
+    return LC_OK;
+}
+
+lc_status launch_state_import(Plan* pl, const double* in, void* state, hipStream_t st) {
+    Rays* r = pl->rays;
+    const int G = pl->G;
+    int* e = static_cast<int*>(state);
+    const SlotArgs A = slot_args(pl);
+    const unsigned nb = (unsigned)(2 * pl->n_bun);
+    const unsigned gb = (unsigned)((G + kBlock - 1) / kBlock);
+    if (pl->prec == LC_F32) {
+        const int64_t rows = r->n_seg * 2 * r->n_pol;
+        const int64_t rpb = 1024;
+        const int64_t blocks = (rows + rpb - 1) / rpb;
+        LC_CHECK(blocks < INT32_MAX, LC_ERR_UNSUPPORTED, "state too large to import");
+        hipLaunchKernelGGL(k_zero_u64s, dim3(gb), dim3(kBlock), 0, st, pl->d_gmax, G);
+        if (blocks > 0)
+            hipLaunchKernelGGL(k_canon_max, dim3((unsigned)blocks), dim3(kBlock), (size_t)G * sizeof(unsigned long long),
+                               st, in, rows, G, rpb, pl->d_gmax);
+        hipLaunchKernelGGL(k_scale_from_max, dim3(gb), dim3(kBlock), 0, st, pl->d_gmax, G, e);
+        hipLaunchKernelGGL(k_import<float>, dim3(nb), dim3(kBlock), 0, st, A, in, e,
+                           static_cast<float*>(state_values(pl, state)));
+    } else {
+        hipLaunchKernelGGL(k_zero_int, dim3(gb), dim3(kBlock), 0, st, e, G);
+        hipLaunchKernelGGL(k_import<double>, dim3(nb), dim3(kBlock), 0, st, A, in, e,
+                           static_cast<double*>(state_values(pl, state)));
     }
     LC_HIP(hipGetLastError());
     return LC_OK;

@@ -73,6 +73,7 @@ _SIGS = {
     "lc_state_bytes": ([_vp], C.c_size_t),
     "lc_state_fill": ([_vp, _vp, _vp, _vp], C.c_int),
     "lc_state_export": ([_vp, _vp, _vp, _vp], C.c_int),
+    "lc_state_import": ([_vp, _vp, _vp, _vp], C.c_int),
     "lc_sweep": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_sweep_noalloc": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_loqd_create": ([_i32, _i32, _d, _d, _i32, C.POINTER(_vp)], C.c_int),
@@ -250,6 +251,11 @@ def lc_state_fill(plan: Plan, field, state, stream=None):
 def lc_state_export(plan: Plan, state, out, stream=None):
     _check(_lib.lc_state_export(plan.handle, _bytes(state, plan.state_bytes, "state"),
                                 _dev(out, plan.n_state, name="out"), _stream(stream)))
+
+
+def lc_state_import(plan: Plan, src, state, stream=None):
+    _check(_lib.lc_state_import(plan.handle, _dev(src, plan.n_state, name="src"),
+                                _bytes(state, plan.state_bytes, "state"), _stream(stream)))
 
 
 def lc_sweep(plan: Plan, kappa, planck, c_dt, state_prev, state_new, I_in, I_exit=None, stream=None):
