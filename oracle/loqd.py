@@ -88,15 +88,22 @@ def face_cells(nx, ny):
     return lo, hi, is_x
 
 
-class _Group:
-    """Per-group data of one solve (plain attribute bag)."""
+SIDES = ("L", "R", "B", "T")
 
-    def __init__(self, nx, ny, lx, ly, c, c_dt, kappa, F_prev, f_cell, f_face):
+
+class _Group:
+    """Per-group data of one solve (plain attribute bag).  k_side and
+    eta_side ([cells][4], sides L, R, B, T) are the coefficients of the
+    flux and of the face energy density in the half-cell relations; the
+    multigroup equations have k = kappa_t of the cell and eta = 0."""
+
+    def __init__(self, nx, ny, lx, ly, c, c_dt, k_side, eta_side, F_prev, f_cell, f_face):
         self.nx, self.ny = nx, ny
         self.hx, self.hy = lx / nx, ly / ny
         self.N = nx * ny
         self.c, self.c_dt = c, c_dt
-        self.kt = kappa + 1.0 / c_dt
+        self.k_side = k_side
+        self.eta_side = eta_side
         self.F_prev = F_prev
         self.fxx, self.fxy, self.fyy = f_cell
         self.gxx, self.gxy, self.gyy = f_face
@@ -105,26 +112,33 @@ class _Group:
 
 def half_cell_flux(q, i, face):
     """The first-moment relation of cell i on the half of the cell next to one
-    of its faces, solved for that face's normal flux:
-    F_face = sum coef * x[col] + const, with columns 0..N-1 the cell
-    unknowns and N + f the face unknowns.  Returns ([(col, coef)], const)."""
+    of its faces,
+        k (h/2) F_face = -c ((f E)_high - (f E)_low) - c h/(2 h_t) (mixed term)
+                         - (h/2) eta E_face + (h/2) F^{n-1}_face / (c dt),
+    solved for that face's normal flux: F_face = sum coef * x[col] + const,
+    with columns 0..N-1 the cell unknowns and N + f the face unknowns.
+    Returns ([(col, coef)], const)."""
     c, N = q.c, q.N
     L, R, B, T = q.cf[i]
+    side = (L, R, B, T).index(face)
     if face in (L, R):
-        a = q.kt[i] * q.hx / 2.0
+        h = q.hx
+        a = q.k_side[i, side] * h / 2.0
         cross = [(N + T, -c * q.hx / (2 * q.hy) * q.gxy[T] / a), (N + B, c * q.hx / (2 * q.hy) * q.gxy[B] / a)]
         if face == R:
             terms = [(N + R, -c * q.gxx[R] / a), (i, c * q.fxx[i] / a)]
         else:
             terms = [(i, -c * q.fxx[i] / a), (N + L, c * q.gxx[L] / a)]
-        return terms + cross, (q.hx / 2.0) * q.F_prev[face] / q.c_dt / a
-    a = q.kt[i] * q.hy / 2.0
-    cross = [(N + R, -c * q.hy / (2 * q.hx) * q.gxy[R] / a), (N + L, c * q.hy / (2 * q.hx) * q.gxy[L] / a)]
-    if face == T:
-        terms = [(N + T, -c * q.gyy[T] / a), (i, c * q.fyy[i] / a)]
     else:
-        terms = [(i, -c * q.fyy[i] / a), (N + B, c * q.gyy[B] / a)]
-    return terms + cross, (q.hy / 2.0) * q.F_prev[face] / q.c_dt / a
+        h = q.hy
+        a = q.k_side[i, side] * h / 2.0
+        cross = [(N + R, -c * q.hy / (2 * q.hx) * q.gxy[R] / a), (N + L, c * q.hy / (2 * q.hx) * q.gxy[L] / a)]
+        if face == T:
+            terms = [(N + T, -c * q.gyy[T] / a), (i, c * q.fyy[i] / a)]
+        else:
+            terms = [(i, -c * q.fyy[i] / a), (N + B, c * q.gyy[B] / a)]
+    eta = [(N + face, -(h / 2.0) * q.eta_side[i, side] / a)] if q.eta_side[i, side] != 0.0 else []
+    return terms + cross + eta, (h / 2.0) * q.F_prev[face] / q.c_dt / a
 
 
 def boundary_condition(C, Phi_in, J_in, c):
@@ -132,10 +146,13 @@ def boundary_condition(C, Phi_in, J_in, c):
     return C * c, -C * Phi_in - J_in
 
 
-def assemble_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc):
-    """The linear system of one group: (A [n][n] sparse, rhs [n], per-group
-    data), n = cells + faces, cell unknowns first."""
-    q = _Group(nx, ny, lx, ly, c, c_dt, kappa, F_prev, f_cell, f_face)
+def assemble_general(nx, ny, lx, ly, c, c_dt, sigma, source, k_side, eta_side, F_prev, f_cell, f_face, bc):
+    """The linear system of one group of the low-order scheme in general
+    form: cell balances sigma_i E_i + div F = source_i, half-cell relations
+    with side coefficients k_side and eta_side, one flux per interior face,
+    boundary condition from bc.  Returns (A [n][n] sparse, rhs [n], data),
+    n = cells + faces, cell unknowns first."""
+    q = _Group(nx, ny, lx, ly, c, c_dt, k_side, eta_side, F_prev, f_cell, f_face)
     N = q.N
     nf = n_faces(nx, ny)
     nint = n_interior(nx, ny)
@@ -147,11 +164,11 @@ def assemble_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cel
         for col, v in terms:
             rows.append(r); cols.append(col); vals.append(scale * v)
 
-    # cell balances: c kappa_t E_i + (F_R - F_L)/hx + (F_T - F_B)/hy = source
+    # cell balances: sigma_i E_i + (F_R - F_L)/hx + (F_T - F_B)/hy = source_i
     for i in range(N):
         L, R, B, T = q.cf[i]
-        add(i, [(i, c * q.kt[i])], 1.0)
-        rhs[i] = 4.0 * np.pi * kappa[i] * planck[i] + c * E_prev[i] / c_dt
+        add(i, [(i, sigma[i])], 1.0)
+        rhs[i] = source[i]
         for face, sgn, h in ((R, 1.0, q.hx), (L, -1.0, q.hx), (T, 1.0, q.hy), (B, -1.0, q.hy)):
             terms, const = half_cell_flux(q, i, face)
             add(i, terms, sgn / h)
@@ -178,20 +195,33 @@ def assemble_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cel
     return A, rhs, q
 
 
-def solve_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc):
-    """One group.  kappa, planck, E_prev: [cells]; F_prev: [faces] normal
-    flux of the previous step (x component on x-faces, y on y-faces);
-    f_cell: [3][cells] and f_face: [3][faces] Eddington tensor entries
-    (xx, xy, yy); bc: [nb][3] = (C, Phi^-, J^-) per boundary face.
-    Returns (E_cell [cells], E_face [faces], F_face [faces])."""
-    A, rhs, q = assemble_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc)
+def multigroup_coefficients(c, c_dt, kappa, planck, E_prev):
+    """sigma, source, k_side, eta_side of one group of eq. (4):
+    sigma = c kappa_t, source = 4 pi kappa B + E^{n-1}/dt, k = kappa_t on
+    every side, eta = 0."""
+    kt = kappa + 1.0 / c_dt
+    sigma = c * kt
+    source = 4.0 * np.pi * kappa * planck + c * E_prev / c_dt
+    k_side = np.repeat(kt[:, None], 4, axis=1)
+    return sigma, source, k_side, np.zeros_like(k_side)
+
+
+def assemble_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc):
+    """The linear system of one group of eq. (4)."""
+    sigma, source, k_side, eta_side = multigroup_coefficients(c, c_dt, kappa, planck, E_prev)
+    return assemble_general(nx, ny, lx, ly, c, c_dt, sigma, source, k_side, eta_side, F_prev, f_cell, f_face, bc)
+
+
+def solve_assembled(nx, ny, A, rhs, q):
+    """Direct solve of an assembled system, then the face fluxes.
+
+    Each equation is divided by its largest coefficient before the direct
+    solve.  The solution is unchanged, but in optically thick cells the
+    balance rows (of order c kappa_t) would otherwise dwarf the face rows
+    (of order c / (kappa_t h)) and leave the solve with few correct digits."""
     N = q.N
     nf = n_faces(nx, ny)
     lo, hi, _ = face_cells(nx, ny)
-    # Each equation is divided by its largest coefficient before the direct
-    # solve.  The solution is unchanged, but in optically thick cells the
-    # balance rows (of order c kappa_t) would otherwise dwarf the face rows
-    # (of order c / (kappa_t h)) and leave the solve with few correct digits.
     scale = 1.0 / abs(A).max(axis=1).toarray().ravel()
     x = spla.spsolve((sp.diags(scale) @ A).tocsc(), scale * rhs)
     E_cell, E_face = x[:N], x[N:]
@@ -201,6 +231,23 @@ def solve_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, 
         terms, const = half_cell_flux(q, i, f)
         F_face[f] = sum(v * x[col] for col, v in terms) + const
     return E_cell, E_face, F_face
+
+
+def solve_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc):
+    """One group of eq. (4).  kappa, planck, E_prev: [cells]; F_prev: [faces]
+    normal flux of the previous step (x component on x-faces, y on y-faces);
+    f_cell: [3][cells] and f_face: [3][faces] Eddington tensor entries
+    (xx, xy, yy); bc: [nb][3] = (C, Phi^-, J^-) per boundary face.
+    Returns (E_cell [cells], E_face [faces], F_face [faces])."""
+    A, rhs, q = assemble_group(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc)
+    return solve_assembled(nx, ny, A, rhs, q)
+
+
+def solve_general(nx, ny, lx, ly, c, c_dt, sigma, source, k_side, eta_side, F_prev, f_cell, f_face, bc):
+    """One group of the scheme in general form (see assemble_general)."""
+    A, rhs, q = assemble_general(nx, ny, lx, ly, c, c_dt, sigma, source, k_side, eta_side, F_prev, f_cell,
+                                 f_face, bc)
+    return solve_assembled(nx, ny, A, rhs, q)
 
 
 def solve(nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc):
@@ -224,3 +271,85 @@ def closures_from_transport(nx, ny, E_cellmajor_f, face_f, bnd):
     f_face = np.concatenate([face_f[:, [0, 1, 2], :], bnd[:, :, 5:8].transpose(0, 2, 1)], axis=2)
     bc = bnd[:, :, [4, 2, 3]]
     return f_cell, f_face, bc
+
+
+# ---------------------------------------------------------------------------
+# effective grey low-order equations, eq. (5)
+# ---------------------------------------------------------------------------
+
+def grey_coefficients(nx, ny, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc, E_cell, E_face,
+                      F_face):
+    """Coefficients of the effective grey equations, eq. (5), in the general
+    form of the scheme, from a multigroup solution of eq. (4) on the same
+    grid (its cell and face energy densities and face fluxes).
+
+    The paper makes the grey scheme algebraically consistent with the
+    multigroup one.  Reading: the spectrum averages of eq. (8)-(9) are taken
+    where the scheme uses them --
+      cell balance: <kappa>_E and <kappa>_B of the cell (with a_R T^4 read
+        as (4 pi / c) sum_g B_g), so sigma E = sum_g c kappa_t,g E_g;
+      half-cell relation of cell i at face f: K_R = sum_g kappa_g,i |F_g,f| /
+        sum_g |F_g,f| (the normal flux component of the face) and
+        eta = sum_g (kappa_g,i - K_R) F_g,f / E_f with the face's grey E, so
+        K_R F_f + eta E_f = sum_g kappa_g,i F_g,f;
+      Eddington tensor: <f>_E of the cell with cell energies, of the face
+        with face energies;
+      boundary: C = sum_g C_g E_g,f / E_f and the incoming part
+        J^- = sum_g (C_g Phi^-_g + J^-_g) (Phi^- = 0), the sum of the group
+        conditions.
+    Summed over the groups the multigroup equations then are the grey ones,
+    so the grey solution is the sum of the group solutions.  Zero (not
+    negative: the scheme is not positivity preserving) denominators: <kappa>_E -> <kappa>_B -> the mean of kappa_g; K_R ->
+    <kappa>_E; eta = 0; <f> = 1/3 on the diagonal; C -> mean of C_g.
+
+    Inputs as for solve() plus E_cell [G][cells], E_face [G][faces],
+    F_face [G][faces].  Returns a dict with sigma, source [cells], k_side,
+    eta_side [cells][4], F_prev [faces], f_cell [3][cells], f_face
+    [3][faces], bc [nb][3], E_prev [cells]."""
+    G, N = kappa.shape
+    nf = n_faces(nx, ny)
+    nint = n_interior(nx, ny)
+    cf = cell_faces(nx, ny)
+    E = E_cell.sum(0)
+    Ef = E_face.sum(0)
+    mean_k = kappa.mean(0)
+    sB = planck.sum(0)
+    kB_num = (kappa * planck).sum(0)
+    kE_num = (kappa * E_cell).sum(0)
+    kB = np.where(sB != 0, kB_num / np.where(sB != 0, sB, 1.0), np.nan)
+    kE = np.where(E != 0, kE_num / np.where(E != 0, E, 1.0), np.where(np.isnan(kB), mean_k, kB))
+    kB = np.where(np.isnan(kB), kE, kB)
+    sigma = c * (kE + 1.0 / c_dt)
+    source = 4.0 * np.pi * kB * sB + c * E_prev.sum(0) / c_dt
+    k_side = np.zeros((N, 4))
+    eta_side = np.zeros((N, 4))
+    for i in range(N):
+        for s in range(4):
+            f = cf[i, s]
+            Fg = F_face[:, f]
+            aF = np.abs(Fg).sum()
+            K = (kappa[:, i] * np.abs(Fg)).sum() / aF if aF > 0 else kE[i]
+            k_side[i, s] = K + 1.0 / c_dt
+            eta_side[i, s] = ((kappa[:, i] - K) * Fg).sum() / Ef[f] if Ef[f] != 0 else 0.0
+
+    def spectrum_tensor(ft, Eg, Et):
+        out = np.empty((3, Eg.shape[1]))
+        for q, dflt in zip(range(3), (1 / 3, 0.0, 1 / 3)):
+            num = (ft[:, q, :] * Eg).sum(0)
+            out[q] = np.where(Et != 0, num / np.where(Et != 0, Et, 1.0), dflt)
+        return out
+    f_cell_g = spectrum_tensor(f_cell, E_cell, E)
+    f_face_g = spectrum_tensor(f_face, E_face, Ef)
+    Eb = E_face[:, nint:]
+    Ebt = Eb.sum(0)
+    C = np.where(Ebt != 0, (bc[:, :, 0] * Eb).sum(0) / np.where(Ebt != 0, Ebt, 1.0), bc[:, :, 0].mean(0))
+    Jm = (bc[:, :, 0] * bc[:, :, 1] + bc[:, :, 2]).sum(0)
+    bc_g = np.stack([C, np.zeros_like(C), Jm], axis=1)
+    return dict(sigma=sigma, source=source, k_side=k_side, eta_side=eta_side, F_prev=F_prev.sum(0),
+                f_cell=f_cell_g, f_face=f_face_g, bc=bc_g, E_prev=E_prev.sum(0))
+
+
+def solve_grey(nx, ny, lx, ly, c, c_dt, coef):
+    """The grey equations with the coefficients of grey_coefficients()."""
+    return solve_general(nx, ny, lx, ly, c, c_dt, coef["sigma"], coef["source"], coef["k_side"],
+                         coef["eta_side"], coef["F_prev"], coef["f_cell"], coef["f_face"], coef["bc"])

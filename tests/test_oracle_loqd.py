@@ -262,7 +262,8 @@ def test_discrete_conservation():
     div = (ff[R] - ff[L]) / hx + (ff[T] - ff[B]) / hy
     assert np.allclose(c * kt * e + div, src, rtol=1e-11, atol=1e-12 * np.max(src))
     # the other cell next to each interior face gives the same flux
-    q = loqd._Group(nx, ny, lx, ly, c, c_dt, kap, F_prev, f_cell, f_face)
+    _, _, k_side, eta_side = loqd.multigroup_coefficients(c, c_dt, kap, planck, E_prev)
+    q = loqd._Group(nx, ny, lx, ly, c, c_dt, k_side, eta_side, F_prev, f_cell, f_face)
     x = np.concatenate([e, ef])
     lo, hi, _ = loqd.face_cells(nx, ny)
     for fidx in range(loqd.n_interior(nx, ny)):
@@ -358,3 +359,83 @@ def test_planted_boundary_mistake_is_caught(monkeypatch):
     monkeypatch.setattr(loqd, "boundary_condition", lambda C, Pm, Jm, c: (C * c, -C * Pm + Jm))
     with pytest.raises(AssertionError):
         test_linear_field_is_reproduced_exactly()
+
+
+# ---------------------------------------------------------------------------
+# effective grey equations, eq. (5): consistency with the multigroup scheme
+# ---------------------------------------------------------------------------
+
+def _multigroup_case(G=4, nx=9, ny=7, lx=1.8, ly=1.4, seed=21):
+    rng = np.random.default_rng(seed)
+    N, nf = nx * ny, loqd.n_faces(nx, ny)
+    nb = 2 * (nx + ny)
+    c, c_dt = 299.792458, 0.6
+    kappa = 10.0 ** rng.uniform(-1, 4, (G, N))
+    planck = rng.uniform(0, 1, (G, N)) * 10.0 ** rng.uniform(-3, 0, (G, 1))
+    E_prev = rng.uniform(0, 1, (G, N)) * 4 * math.pi / c * 10.0 ** rng.uniform(-3, 0, (G, 1))
+    F_prev = rng.uniform(-0.3, 0.3, (G, nf))
+
+    def tensors(n):
+        a = rng.uniform(0.15, 0.6, (G, n))
+        dd = rng.uniform(0.15, 0.6, (G, n))
+        b = rng.uniform(-0.5, 0.5, (G, n)) * np.sqrt(a * dd)
+        return np.stack([a, b, dd], axis=1)
+    bc = np.stack([rng.uniform(0.3, 0.7, (G, nb)), rng.uniform(0, 1, (G, nb)), rng.uniform(0, 0.5, (G, nb))], axis=2)
+    return (nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, tensors(N), tensors(nf), bc)
+
+
+@pytest.mark.parametrize("seed", [21, 22])
+def test_grey_solution_is_the_sum_of_the_group_solutions(seed):
+    """With closures from the multigroup solution the grey scheme, eq. (5),
+    reproduces sum_g E_g in cells and on faces and sum_g F_g on faces (the
+    paper's algebraic consistency of the two schemes)."""
+    args = _multigroup_case(seed=seed)
+    nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc = args
+    Ec, Ef, Ff = loqd.solve(*args)
+    coef = loqd.grey_coefficients(nx, ny, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc, Ec, Ef, Ff)
+    e, ef, ff = loqd.solve_grey(nx, ny, lx, ly, c, c_dt, coef)
+    for got, want in ((e, Ec.sum(0)), (ef, Ef.sum(0)), (ff, Ff.sum(0))):
+        assert np.max(np.abs(got - want)) <= 1e-10 * np.max(np.abs(want))
+
+
+def test_grey_closures_special_cases_and_a_face_by_hand():
+    """Group-independent opacity: K_R = kappa and eta = 0 on every side.  A
+    two-group face worked by hand: kappa = (1, 3), F = (2, -1), E_f = 4:
+    K_R = (1*2 + 3*1)/3 = 5/3, eta = ((1 - 5/3) 2 + (3 - 5/3)(-1)) / 4 = -2/3."""
+    args = list(_multigroup_case(G=3, seed=5))
+    nx, ny = args[0], args[1]
+    args[6] = np.repeat(args[6][:1], 3, axis=0)               # the same opacity in every group
+    Ec, Ef, Ff = loqd.solve(*args)
+    coef = loqd.grey_coefficients(nx, ny, args[4], args[5], args[6], args[7], args[8], args[9], args[10],
+                                  args[11], args[12], Ec, Ef, Ff)
+    assert np.allclose(coef["k_side"], (args[6][0] + 1 / args[5])[:, None], rtol=1e-13)
+    assert np.max(np.abs(coef["eta_side"])) <= 1e-12 * np.max(args[6]) * np.max(np.abs(Ff)) / np.min(np.abs(Ef.sum(0)))
+    # the hand-worked face: a 1 x 1 grid, two groups, face L of the cell
+    nf = loqd.n_faces(1, 1)
+    kap = np.array([[1.0], [3.0]])
+    Fface = np.zeros((2, nf)); Fface[:, 0] = (2.0, -1.0)
+    Eface = np.ones((2, nf)); Eface[:, 0] = (1.5, 2.5)
+    coef = loqd.grey_coefficients(1, 1, 1.0, 1.0, kap, np.ones((2, 1)), np.zeros((2, 1)), np.zeros((2, nf)),
+                                  np.full((2, 3, 1), 1 / 3), np.full((2, 3, nf), 1 / 3), np.full((2, 4, 3), 0.5),
+                                  np.ones((2, 1)), Eface, Fface)
+    assert math.isclose(coef["k_side"][0, 0], 5 / 3 + 1.0, rel_tol=1e-14)
+    assert math.isclose(coef["eta_side"][0, 0], -2 / 3, rel_tol=1e-14)
+
+
+def _eta_on_cell_energy(nx, ny, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc, E_cell, E_face,
+                        F_face):
+    # mistake: eta formed with the cell's grey E instead of the face's
+    coef = _orig_grey(nx, ny, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc, E_cell, E_face, F_face)
+    cf = loqd.cell_faces(nx, ny)
+    Ef, E = E_face.sum(0), E_cell.sum(0)
+    coef["eta_side"] = coef["eta_side"] * Ef[cf] / E[:, None]
+    return coef
+
+
+_orig_grey = loqd.grey_coefficients
+
+
+def test_planted_grey_mistake_is_caught(monkeypatch):
+    monkeypatch.setattr(loqd, "grey_coefficients", _eta_on_cell_energy)
+    with pytest.raises(AssertionError):
+        test_grey_solution_is_the_sum_of_the_group_solutions(21)
