@@ -320,7 +320,7 @@ lc_status lc_grey_closures_dims(int32_t cells, int32_t G, const double* E, const
                                 const double* kappa, const double* planck, double* out, void* stream);
 
 /*
- * Multigroup low-order quasidiffusion (LOQD) equations, eq. (4), for one
+ * Low-order quasidiffusion (LOQD) equations.  Multigroup, eq. (4), for one
  * backward-Euler time step on the material grid, closed by the Eddington
  * tensors of the transport sweep (cells: eq. (7), (15); faces: eq. (16))
  * and its half-range boundary factors.  Time-discrete, with
@@ -373,6 +373,61 @@ lc_status lc_loqd_solve(lc_loqd_t loqd, double c, double c_dt, const double* kap
                         const double* f_face, const double* bnd, double* E_cell, double* E_face,
                         double* F_face, double rtol, int32_t max_iter, int32_t* iters, double* resid,
                         void* stream);
+
+/*
+ * The same scheme in general form, for the effective grey equations of
+ * eq. (5) (and any system of this shape): per group (G of the handle),
+ *   sigma_i E_i + (F_R - F_L)/hx + (F_T - F_B)/hy = source_i,
+ *   k (h/2) F_f = -c ((f E)_high - (f E)_low) - c h/(2 h_t) (mixed term)
+ *                 - (h/2) eta E_f + (h/2) F^{n-1}_f / (c dt)
+ * on each half cell, with k and eta given per cell and side.  Eq. (4) is
+ * sigma = c kappa_t, source = 4 pi kappa B + c E^{n-1}/(c dt), k = kappa_t,
+ * eta = 0.
+ *
+ * lc_loqd_solve_general -- inputs (device, float64): sigma, source
+ * [G][cells]; k_side, eta_side [G][4][cells] (sides L, R, B, T of each
+ * cell); F_prev [G][nf]; f_cell [G][3][cells] and f_face [G][3][nf]
+ * (xx, xy, yy); bc [G][nb][3] (C, Phi^-, J^-).  Outputs, solver, iters,
+ * resid, synchronisation and errors as lc_loqd_solve.
+ *
+ * lc_loqd_grey_coefficients -- the grey equations' coefficients (G = 1
+ * arrays of the general form, and E^{n-1} = sum_g E^{n-1}_g) from a
+ * multigroup solution on the handle's grid (the handle's G groups): the
+ * multigroup inputs of lc_loqd_solve and its outputs E_cell, E_face,
+ * F_face.  Paper: eq. (5) closed by the spectrum averages of eq. (8)-(9),
+ * taken where the scheme uses them so that the two schemes are
+ * algebraically consistent (summed over the groups, the multigroup
+ * equations are the grey ones, and the grey solution is the sum of the
+ * group solutions):
+ *   sigma = c (<kappa>_E + 1/(c dt)), source = 4 pi <kappa>_B sum_g B_g +
+ *     c E^{n-1}/(c dt) (a_R T^4 read as (4 pi / c) sum_g B_g) per cell;
+ *   per cell side: K_R = sum_g kappa_g |F_g,f| / sum_g |F_g,f| (normal face
+ *     fluxes), k = K_R + 1/(c dt), eta = sum_g (kappa_g - K_R) F_g,f / E_f
+ *     with the face's grey E;
+ *   <f>_E of cells with cell energies, of faces with face energies;
+ *   boundary: C = sum_g C_g E_g,f / E_f, Phi^- = 0,
+ *     J^- = sum_g (C_g Phi^-_g + J^-_g).
+ * Zero denominators: <kappa>_E -> <kappa>_B -> mean kappa_g; K_R ->
+ * <kappa>_E; eta = 0; <f> = 1/3 on the diagonal; C -> mean C_g.  Sums over
+ * the groups run in a fixed order.  Outputs (device, float64): sigma,
+ * source, E_prev_grey [cells]; k_side, eta_side [4][cells]; F_prev_grey
+ * [nf]; f_cell_grey [3][cells]; f_face_grey [3][nf]; bc_grey [nb][3].
+ * Allocates and synchronises nothing.  Errors: LC_ERR_ARG (NULL, c or c_dt
+ * not finite or <= 0), LC_ERR_STATE, LC_ERR_HIP.
+ */
+lc_status lc_loqd_solve_general(lc_loqd_t loqd, double c, double c_dt, const double* sigma,
+                                const double* source, const double* k_side, const double* eta_side,
+                                const double* F_prev, const double* f_cell, const double* f_face,
+                                const double* bc, double* E_cell, double* E_face, double* F_face,
+                                double rtol, int32_t max_iter, int32_t* iters, double* resid,
+                                void* stream);
+lc_status lc_loqd_grey_coefficients(lc_loqd_t loqd, double c, double c_dt, const double* kappa,
+                                    const double* planck, const double* E_prev, const double* F_prev,
+                                    const double* f_cell, const double* f_face, const double* bnd,
+                                    const double* E_cell, const double* E_face, const double* F_face,
+                                    double* sigma, double* source, double* k_side, double* eta_side,
+                                    double* F_prev_grey, double* f_cell_grey, double* f_face_grey,
+                                    double* bc_grey, double* E_prev_grey, void* stream);
 
 /*
  * lc_step -- n_steps backward-Euler time steps (sweep, then moments) with the

@@ -1,29 +1,35 @@
-// Multigroup low-order quasidiffusion (LOQD) equations, eq. (4), for one
-// backward-Euler step on the material grid, closed by the transport sweep's
-// Eddington tensors (cells: eq. (7), (15); faces: eq. (16)) and the
-// half-range boundary factors.
+// Low-order quasidiffusion (LOQD) equations of the multilevel method for one
+// backward-Euler step on the material grid: the multigroup equations,
+// eq. (4), closed by the transport sweep's Eddington tensors (cells:
+// eq. (7), (15); faces: eq. (16)) and half-range boundary factors, and the
+// effective grey equations, eq. (5), closed by spectrum averages of the
+// multigroup solution, eq. (8)-(9).
 //
 // Discretisation (the paper cites a second-order finite-volume scheme
 // without printing it; this is the reading the library implements): cell
-// and face averages of E per group; the balance (4a) integrated over each
-// cell; the first moment (4b) integrated over each half cell next to a face
-// (kappa_t F taken at the face, the cell tensor times E_i at the centre, the
-// face tensor times E_f on the face, the cell's transverse face averages for
-// the mixed term); one normal flux per interior face; the QD boundary
-// condition n.F = C (c E_f - Phi^-) - J^- on boundary faces.
+// and face averages of E per group; the balance integrated over each cell,
+//   sigma_i E_i + (F_R - F_L)/hx + (F_T - F_B)/hy = source_i;
+// the first moment integrated over each half cell next to a face,
+//   k (h/2) F_f = -c ((f E)_high - (f E)_low) - c h/(2 h_t) (mixed term)
+//                 - (h/2) eta E_f + (h/2) F^{n-1}_f / (c dt),
+// with the cell tensor times E_i at the centre, the face tensor times E_f
+// on the face and the cell's transverse face averages for the mixed term;
+// one normal flux per interior face; n.F = C (c E_f - Phi^-) - J^- on the
+// boundary.  Eq. (4): sigma = c kappa_t, source = 4 pi kappa B +
+// E^{n-1}/dt, k = kappa_t, eta = 0 (kappa_t = kappa + 1/(c dt)).  Eq. (5):
+// sigma = c (<kappa>_E + 1/(c dt)), source = 4 pi <kappa>_B sum_g B_g +
+// E^{n-1}/dt, k = K_R + 1/(c dt) and eta per (cell, face), so that the
+// multigroup equations summed over the groups are the grey ones.
 //
-// Solution: in the balance of cell i the mixed terms of its two opposite
-// faces cancel, so the cell row couples E_i only to the cell's own four
-// faces and E_i is eliminated exactly:
-//   E_i = (b_i - sum_k a_ik E_k) / d_i.
-// What remains is a system in the face unknowns alone (at most 7 entries a
-// row: the face and the other faces of its one or two cells), solved for all
+// Solution: a cell's balance couples E_i only to the cell's own four faces,
+// so E_i is eliminated exactly:  E_i = (b_i - sum_k a_ik E_k) / d_i.  What
+// remains is a system in the face unknowns alone (at most 7 entries a row:
+// the face and the other faces of its one or two cells), solved for all
 // groups at once by BiCGSTAB with a Jacobi preconditioner.  Every inner
 // product is a fixed-order reduction (no atomics), so results are
 // deterministic.  Then E_i and the face fluxes follow from the cell rows and
 // the half-cell relations.
 #include <cmath>
-#include <cstring>
 #include <vector>
 
 #include "lc_internal.hpp"
@@ -46,7 +52,16 @@ struct Loqd {
     int* d_lo = nullptr;              // [nf] cell below / left of the face, -1 outside
     int* d_hi = nullptr;              // [nf] cell above / right, -1 outside
     int* d_col = nullptr;             // [kSlots][nf] face columns of each face row (padding: the row itself)
-    // per solve, per group
+    // coefficients in general form, filled from multigroup inputs by lc_loqd_solve
+    double* d_sigma = nullptr;        // [G][N]
+    double* d_src = nullptr;          // [G][N]
+    double* d_ks = nullptr;           // [G][4][N] k per side L, R, B, T
+    double* d_es = nullptr;           // [G][4][N] eta per side
+    double* d_fc = nullptr;           // [G][3][N] cell tensors xx, xy, yy
+    double* d_ff = nullptr;           // [G][3][nf] face tensors
+    double* d_bc3 = nullptr;          // [G][nb][3] C, Phi^-, J^-
+    double* d_fp = nullptr;           // [G][nf] previous normal fluxes
+    // elimination and face system
     double* d_dc = nullptr;           // [G][N] cell diagonal
     double* d_ac = nullptr;           // [G][4][N] cell-row coefficients of the faces L, R, B, T
     double* d_bc = nullptr;           // [G][N] cell right-hand side
@@ -80,43 +95,67 @@ struct Geo {
     const int* col;
 };
 
-// Face tensor entry q (0 xx, 1 xy, 2 yy) of face f for group g: interior
-// faces from the face moments [nint][4][G], boundary faces from the
-// boundary factors [G][nb][8] (columns 5, 6, 7).
-__device__ inline double face_tensor(const Geo& Q, const double* ff, const double* bnd, int g, int f, int q) {
-    if (f < Q.nint) return ff[((size_t)f * 4 + q) * Q.G + g];
-    const int b = f - Q.nint;
-    const int nb = Q.nf - Q.nint;
-    return bnd[((size_t)g * nb + b) * 8 + 5 + q];
+// The coefficients of one group in general form (device pointers).
+struct Gen {
+    const double* sigma;   // [G][N]
+    const double* src;     // [G][N]
+    const double* ks;      // [G][4][N]
+    const double* es;      // [G][4][N]
+    const double* fc;      // [G][3][N]
+    const double* ff;      // [G][3][nf]
+    const double* bc3;     // [G][nb][3]
+    const double* fp;      // [G][nf]
+};
+
+// One half-cell relation of cell `cell` at its side s (0 L, 1 R, 2 B, 3 T),
+// solved for the side's normal flux: F = u E_cell + sum_k w[k] E_face(k) + k0,
+// with the four face coefficients w indexed by side.
+struct Rel {
+    double u, w[4], k0;
+};
+
+__device__ inline Rel side_relation(const Geo& Q, const Gen& C, int g, int cell, int s) {
+    const int f = Q.cface[(size_t)s * Q.N + cell];
+    const bool xs = s < 2;
+    const bool high = (s == 1 || s == 3);
+    const double hn = xs ? Q.hx : Q.hy, ht = xs ? Q.hy : Q.hx;
+    const size_t gc = (size_t)g * 4 * Q.N + (size_t)s * Q.N + cell;
+    const double a = C.ks[gc] * hn / 2.0;
+    const double eta = C.es[gc];
+    const double fnn = C.fc[((size_t)g * 3 + (xs ? 0 : 2)) * Q.N + cell];
+    const double gnn = C.ff[((size_t)g * 3 + (xs ? 0 : 2)) * Q.nf + f];
+    const int hiT = xs ? 3 : 1, loT = xs ? 2 : 0;       // transverse sides: T, B or R, L
+    const int fhi = Q.cface[(size_t)hiT * Q.N + cell], flo = Q.cface[(size_t)loT * Q.N + cell];
+    const double x = Q.c * hn / (2.0 * ht) / a;
+    Rel r;
+    r.w[0] = r.w[1] = r.w[2] = r.w[3] = 0.0;
+    r.u = (high ? Q.c : -Q.c) * fnn / a;
+    r.w[s] += (high ? -Q.c : Q.c) * gnn / a - (hn / 2.0) * eta / a;
+    r.w[hiT] -= x * C.ff[((size_t)g * 3 + 1) * Q.nf + fhi];
+    r.w[loT] += x * C.ff[((size_t)g * 3 + 1) * Q.nf + flo];
+    r.k0 = (hn / 2.0) * C.fp[(size_t)g * Q.nf + f] / (Q.c_dt * a);
+    return r;
 }
 
-// Cell rows: d_i, a_ik and b_i of
-//   c kt E_i + (F_R - F_L)/hx + (F_T - F_B)/hy = 4 pi kappa B + c E_prev / c_dt
+// Cell rows: d_i, a_ik and b_i of sigma_i E_i + (F_R - F_L)/hx + (F_T - F_B)/hy = source_i
 // after the half-cell relations are put in for the four fluxes.
-__global__ void k_loqd_cells(Geo Q, const double* __restrict__ kappa, const double* __restrict__ planck,
-                             const double* __restrict__ E_prev, const double* __restrict__ F_prev,
-                             const double* __restrict__ fc, const double* __restrict__ ff,
-                             const double* __restrict__ bnd, double* dc, double* ac, double* bcv) {
+__global__ void k_loqd_cells(Geo Q, Gen C, double* dc, double* ac, double* bcv) {
     const int g = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= Q.N) return;
     const size_t gi = (size_t)g * Q.N + i;
-    const double kap = kappa[gi];
-    const double kt = kap + 1.0 / Q.c_dt;
-    const double fxx = fc[((size_t)i * 4 + 0) * Q.G + g];
-    const double fyy = fc[((size_t)i * 4 + 2) * Q.G + g];
-    const int L = Q.cface[i], R = Q.cface[Q.N + i], B = Q.cface[2 * Q.N + i], T = Q.cface[3 * Q.N + i];
-    const double ex = 2.0 * Q.c / (kt * Q.hx * Q.hx);
-    const double ey = 2.0 * Q.c / (kt * Q.hy * Q.hy);
-    dc[gi] = Q.c * kt + 2.0 * ex * fxx + 2.0 * ey * fyy;
+    double d = C.sigma[gi], w[4] = {0.0, 0.0, 0.0, 0.0}, rhs = C.src[gi];
+    for (int s = 0; s < 4; ++s) {
+        const double sg = (s == 1 || s == 3 ? 1.0 : -1.0) / (s < 2 ? Q.hx : Q.hy);
+        const Rel r = side_relation(Q, C, g, i, s);
+        d += sg * r.u;
+        for (int k = 0; k < 4; ++k) w[k] += sg * r.w[k];
+        rhs -= sg * r.k0;
+    }
+    dc[gi] = d;
     const size_t a0 = (size_t)g * 4 * Q.N + i;
-    ac[a0] = -ex * face_tensor(Q, ff, bnd, g, L, 0);
-    ac[a0 + Q.N] = -ex * face_tensor(Q, ff, bnd, g, R, 0);
-    ac[a0 + 2 * (size_t)Q.N] = -ey * face_tensor(Q, ff, bnd, g, B, 2);
-    ac[a0 + 3 * (size_t)Q.N] = -ey * face_tensor(Q, ff, bnd, g, T, 2);
-    const double* Fp = F_prev + (size_t)g * Q.nf;
-    bcv[gi] = 4.0 * kPi * kap * planck[gi] + Q.c * E_prev[gi] / Q.c_dt -
-              (Fp[R] - Fp[L]) / (kt * Q.hx * Q.c_dt) - (Fp[T] - Fp[B]) / (kt * Q.hy * Q.c_dt);
+    for (int k = 0; k < 4; ++k) ac[a0 + (size_t)k * Q.N] = w[k];
+    bcv[gi] = rhs;
 }
 
 // Add v to the slot of column col in a face row (cols: the row's columns).
@@ -133,11 +172,8 @@ __device__ inline void put(double* row, const int* cols, int col, double v) {
 // an interior face so states that both cells give one flux), minus
 // C c E_f on a boundary face, with every cell unknown replaced by its
 // cell row.
-__global__ void k_loqd_faces(Geo Q, const double* __restrict__ kappa, const double* __restrict__ F_prev,
-                             const double* __restrict__ fc, const double* __restrict__ ff,
-                             const double* __restrict__ bnd, const double* __restrict__ dc,
-                             const double* __restrict__ ac, const double* __restrict__ bcv, double* val,
-                             double* dinv, double* b) {
+__global__ void k_loqd_faces(Geo Q, Gen C, const double* __restrict__ dc, const double* __restrict__ ac,
+                             const double* __restrict__ bcv, double* val, double* dinv, double* b) {
     const int g = blockIdx.y;
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= Q.nf) return;
@@ -148,44 +184,27 @@ __global__ void k_loqd_faces(Geo Q, const double* __restrict__ kappa, const doub
         row[s] = 0.0;
     }
     double rhs = 0.0;
-    const double Fp = F_prev[(size_t)g * Q.nf + f];
     for (int side = 0; side < 2; ++side) {
         const int cell = side == 0 ? Q.lo[f] : Q.hi[f];
         if (cell < 0) continue;
         const double sg = side == 0 ? 1.0 : -1.0;
-        const int L = Q.cface[cell], R = Q.cface[Q.N + cell], B = Q.cface[2 * Q.N + cell],
-                  T = Q.cface[3 * Q.N + cell];
-        const bool xf = (f == L || f == R);
-        const double hn = xf ? Q.hx : Q.hy, ht = xf ? Q.hy : Q.hx;
-        const double kt = kappa[(size_t)g * Q.N + cell] + 1.0 / Q.c_dt;
-        const double a = kt * hn / 2.0;
-        const double fnn = fc[((size_t)cell * 4 + (xf ? 0 : 2)) * Q.G + g];
-        const double gnn = face_tensor(Q, ff, bnd, g, f, xf ? 0 : 2);
-        const int hiT = xf ? T : R, loT = xf ? B : L;
-        const double x = Q.c * hn / (2.0 * ht) / a;
-        // sigma F^(cell)_f = (c fnn E_cell - c gnn E_f) / a
-        //                    - sigma x (gxy_hiT E_hiT - gxy_loT E_loT) + sigma (hn/2) Fp / (c_dt a)
-        put(row, cols, f, -Q.c * gnn / a);
-        put(row, cols, hiT, -sg * x * face_tensor(Q, ff, bnd, g, hiT, 1));
-        put(row, cols, loT, sg * x * face_tensor(Q, ff, bnd, g, loT, 1));
-        rhs -= sg * (hn / 2.0) * Fp / (Q.c_dt * a);
+        int s = 0;
+        while (Q.cface[(size_t)s * Q.N + cell] != f) ++s;   // the face's side of this cell
+        const Rel r = side_relation(Q, C, g, cell, s);
+        for (int k = 0; k < 4; ++k) put(row, cols, Q.cface[(size_t)k * Q.N + cell], sg * r.w[k]);
+        rhs -= sg * r.k0;
         // E_cell = (b_cell - sum_k a_k E_k) / d_cell
-        const double beta = Q.c * fnn / a;
+        const double beta = sg * r.u;
         const size_t gi = (size_t)g * Q.N + cell;
         const double d = dc[gi];
         const size_t a0 = (size_t)g * 4 * Q.N + cell;
-        put(row, cols, L, -beta * ac[a0] / d);
-        put(row, cols, R, -beta * ac[a0 + Q.N] / d);
-        put(row, cols, B, -beta * ac[a0 + 2 * (size_t)Q.N] / d);
-        put(row, cols, T, -beta * ac[a0 + 3 * (size_t)Q.N] / d);
+        for (int k = 0; k < 4; ++k) put(row, cols, Q.cface[(size_t)k * Q.N + cell], -beta * ac[a0 + (size_t)k * Q.N] / d);
         rhs -= beta * bcv[gi] / d;
     }
     if (Q.lo[f] < 0 || Q.hi[f] < 0) {                    // n.F = C (c E_f - Phi^-) - J^-
-        const int nb = Q.nf - Q.nint;
-        const double* bb = bnd + ((size_t)g * nb + (f - Q.nint)) * 8;
-        const double C = bb[4], Pm = bb[2], Jm = bb[3];
-        put(row, cols, f, -C * Q.c);
-        rhs += -C * Pm - Jm;
+        const double* bb = C.bc3 + ((size_t)g * (Q.nf - Q.nint) + (f - Q.nint)) * 3;
+        put(row, cols, f, -bb[0] * Q.c);
+        rhs += -bb[0] * bb[1] - bb[2];
     }
     for (int s = 0; s < kSlots; ++s) val[((size_t)g * kSlots + s) * Q.nf + f] = row[s];
     dinv[(size_t)g * Q.nf + f] = 1.0 / row[0];           // slot 0 is the face itself
@@ -350,12 +369,10 @@ __global__ void k_bi_x(Geo Q, Vecs V, const double* sc, const int* flag, double*
     block_sum2(a, b, part + ((size_t)g * nblk + blockIdx.x) * 2);
 }
 
-// Cell values and face fluxes from the face solution.
-__global__ void k_loqd_back(Geo Q, const double* __restrict__ kappa, const double* __restrict__ F_prev,
-                            const double* __restrict__ fc, const double* __restrict__ ff,
-                            const double* __restrict__ bnd, const double* __restrict__ dc,
-                            const double* __restrict__ ac, const double* __restrict__ bcv,
-                            const double* __restrict__ xf, double* E_cell, double* E_face, double* F_face) {
+// Cell values from the face solution.
+__global__ void k_loqd_back(Geo Q, const double* __restrict__ dc, const double* __restrict__ ac,
+                            const double* __restrict__ bcv, const double* __restrict__ xf, double* E_cell,
+                            double* E_face) {
     const int g = blockIdx.y;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const double* X = xf + (size_t)g * Q.nf;
@@ -369,32 +386,143 @@ __global__ void k_loqd_back(Geo Q, const double* __restrict__ kappa, const doubl
     }
 }
 
-__global__ void k_loqd_flux(Geo Q, const double* __restrict__ kappa, const double* __restrict__ F_prev,
-                            const double* __restrict__ fc, const double* __restrict__ ff,
-                            const double* __restrict__ bnd, const double* __restrict__ E_cell,
-                            const double* __restrict__ E_face, double* F_face) {
+// Face fluxes from the half-cell relation of the cell below / left of the
+// face (above / right on the domain's low boundaries).
+__global__ void k_loqd_flux(Geo Q, Gen C, const double* __restrict__ E_cell, const double* __restrict__ E_face,
+                            double* F_face) {
     const int g = blockIdx.y;
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= Q.nf) return;
-    // the half-cell relation of the cell below / left of the face (above /
-    // right on the domain's low boundaries)
-    const bool low_side = Q.lo[f] >= 0;
-    const int cell = low_side ? Q.lo[f] : Q.hi[f];
-    const int L = Q.cface[cell], R = Q.cface[Q.N + cell], B = Q.cface[2 * Q.N + cell], T = Q.cface[3 * Q.N + cell];
-    const bool xf = (f == L || f == R);
-    const double hn = xf ? Q.hx : Q.hy, ht = xf ? Q.hy : Q.hx;
-    const double kt = kappa[(size_t)g * Q.N + cell] + 1.0 / Q.c_dt;
-    const double a = kt * hn / 2.0;
-    const double fnn = fc[((size_t)cell * 4 + (xf ? 0 : 2)) * Q.G + g];
-    const double gnn = face_tensor(Q, ff, bnd, g, f, xf ? 0 : 2);
-    const int hiT = xf ? T : R, loT = xf ? B : L;
+    const int cell = Q.lo[f] >= 0 ? Q.lo[f] : Q.hi[f];
+    int s = 0;
+    while (Q.cface[(size_t)s * Q.N + cell] != f) ++s;
+    const Rel r = side_relation(Q, C, g, cell, s);
     const double* Ef = E_face + (size_t)g * Q.nf;
-    const double Ec = E_cell[(size_t)g * Q.N + cell];
-    const double cross = Q.c * hn / (2.0 * ht) *
-                         (face_tensor(Q, ff, bnd, g, hiT, 1) * Ef[hiT] - face_tensor(Q, ff, bnd, g, loT, 1) * Ef[loT]);
-    const double Fp = F_prev[(size_t)g * Q.nf + f];
-    const double grad = low_side ? (Q.c * gnn * Ef[f] - Q.c * fnn * Ec) : (Q.c * fnn * Ec - Q.c * gnn * Ef[f]);
-    F_face[(size_t)g * Q.nf + f] = (-grad - cross + hn / 2.0 * Fp / Q.c_dt) / a;
+    double F = r.u * E_cell[(size_t)g * Q.N + cell] + r.k0;
+    for (int k = 0; k < 4; ++k) F += r.w[k] * Ef[Q.cface[(size_t)k * Q.N + cell]];
+    F_face[(size_t)g * Q.nf + f] = F;
+}
+
+// Multigroup inputs (eq. (4)) in general form.
+__global__ void k_loqd_prep_cells(Geo Q, const double* __restrict__ kappa, const double* __restrict__ planck,
+                                  const double* __restrict__ E_prev, const double* __restrict__ f_cell, double* sigma,
+                                  double* src, double* ks, double* es, double* fc) {
+    const int g = blockIdx.y;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Q.N) return;
+    const size_t gi = (size_t)g * Q.N + i;
+    const double kap = kappa[gi];
+    const double kt = kap + 1.0 / Q.c_dt;
+    sigma[gi] = Q.c * kt;
+    src[gi] = 4.0 * kPi * kap * planck[gi] + Q.c * E_prev[gi] / Q.c_dt;
+    for (int s = 0; s < 4; ++s) {
+        ks[(size_t)g * 4 * Q.N + (size_t)s * Q.N + i] = kt;
+        es[(size_t)g * 4 * Q.N + (size_t)s * Q.N + i] = 0.0;
+    }
+    for (int q = 0; q < 3; ++q) fc[((size_t)g * 3 + q) * Q.N + i] = f_cell[((size_t)i * 4 + q) * Q.G + g];
+}
+
+__global__ void k_loqd_prep_faces(Geo Q, const double* __restrict__ F_prev, const double* __restrict__ f_face,
+                                  const double* __restrict__ bnd, double* ff, double* bc3, double* fp) {
+    const int g = blockIdx.y;
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= Q.nf) return;
+    const int nb = Q.nf - Q.nint;
+    for (int q = 0; q < 3; ++q)
+        ff[((size_t)g * 3 + q) * Q.nf + f] = f < Q.nint ? f_face[((size_t)f * 4 + q) * Q.G + g]
+                                                        : bnd[((size_t)g * nb + (f - Q.nint)) * 8 + 5 + q];
+    fp[(size_t)g * Q.nf + f] = F_prev[(size_t)g * Q.nf + f];
+    if (f >= Q.nint) {
+        const double* bb = bnd + ((size_t)g * nb + (f - Q.nint)) * 8;
+        double* o = bc3 + ((size_t)g * nb + (f - Q.nint)) * 3;
+        o[0] = bb[4];
+        o[1] = bb[2];
+        o[2] = bb[3];
+    }
+}
+
+// Grey coefficients (eq. (5) in general form) from a multigroup solution:
+// per cell the energy-weighted and Planck-weighted opacities, per cell side
+// K_R from the normal face fluxes and eta, and the cell's spectrum-averaged
+// tensor; fixed-order sums over the groups.
+__global__ void k_grey_cells(Geo Q, const double* __restrict__ kappa, const double* __restrict__ planck,
+                             const double* __restrict__ E_prev, const double* __restrict__ f_cell,
+                             const double* __restrict__ E_cell, const double* __restrict__ E_face,
+                             const double* __restrict__ F_face, double* sigma, double* src, double* ks, double* es,
+                             double* fc, double* Ep) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Q.N) return;
+    const int G = Q.G;
+    double E = 0.0, kE = 0.0, sB = 0.0, kB = 0.0, sk = 0.0, ep = 0.0, t[3] = {0.0, 0.0, 0.0};
+    for (int g = 0; g < G; ++g) {
+        const size_t gi = (size_t)g * Q.N + i;
+        const double e = E_cell[gi], k = kappa[gi], b = planck[gi];
+        E += e;
+        kE += k * e;
+        sB += b;
+        kB += k * b;
+        sk += k;
+        ep += E_prev[gi];
+        for (int q = 0; q < 3; ++q) t[q] += f_cell[((size_t)i * 4 + q) * G + g] * e;
+    }
+    const double mean_k = sk / G;
+    double avgB = sB != 0.0 ? kB / sB : NAN;
+    const double avgE = E != 0.0 ? kE / E : (std::isnan(avgB) ? mean_k : avgB);
+    if (std::isnan(avgB)) avgB = avgE;
+    sigma[i] = Q.c * (avgE + 1.0 / Q.c_dt);
+    src[i] = 4.0 * kPi * avgB * sB + Q.c * ep / Q.c_dt;
+    Ep[i] = ep;
+    fc[i] = E != 0.0 ? t[0] / E : 1.0 / 3.0;
+    fc[Q.N + i] = E != 0.0 ? t[1] / E : 0.0;
+    fc[2 * (size_t)Q.N + i] = E != 0.0 ? t[2] / E : 1.0 / 3.0;
+    for (int s = 0; s < 4; ++s) {
+        const int f = Q.cface[(size_t)s * Q.N + i];
+        double aF = 0.0, kaF = 0.0, Ef = 0.0;
+        for (int g = 0; g < G; ++g) {
+            const double F = F_face[(size_t)g * Q.nf + f];
+            aF += fabs(F);
+            kaF += kappa[(size_t)g * Q.N + i] * fabs(F);
+            Ef += E_face[(size_t)g * Q.nf + f];
+        }
+        const double K = aF != 0.0 ? kaF / aF : avgE;
+        double num = 0.0;
+        for (int g = 0; g < G; ++g) num += (kappa[(size_t)g * Q.N + i] - K) * F_face[(size_t)g * Q.nf + f];
+        ks[(size_t)s * Q.N + i] = K + 1.0 / Q.c_dt;
+        es[(size_t)s * Q.N + i] = Ef != 0.0 ? num / Ef : 0.0;
+    }
+}
+
+__global__ void k_grey_faces(Geo Q, const double* __restrict__ F_prev, const double* __restrict__ f_face,
+                             const double* __restrict__ bnd, const double* __restrict__ E_face, double* ff,
+                             double* bc3, double* fp) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= Q.nf) return;
+    const int G = Q.G, nb = Q.nf - Q.nint;
+    double Ef = 0.0, t[3] = {0.0, 0.0, 0.0}, p = 0.0, cE = 0.0, cs = 0.0, jm = 0.0;
+    for (int g = 0; g < G; ++g) {
+        const double e = E_face[(size_t)g * Q.nf + f];
+        Ef += e;
+        p += F_prev[(size_t)g * Q.nf + f];
+        for (int q = 0; q < 3; ++q)
+            t[q] += (f < Q.nint ? f_face[((size_t)f * 4 + q) * G + g]
+                                : bnd[((size_t)g * nb + (f - Q.nint)) * 8 + 5 + q]) * e;
+        if (f >= Q.nint) {
+            const double* bb = bnd + ((size_t)g * nb + (f - Q.nint)) * 8;
+            cE += bb[4] * e;
+            cs += bb[4];
+            jm += bb[4] * bb[2] + bb[3];
+        }
+    }
+    ff[f] = Ef != 0.0 ? t[0] / Ef : 1.0 / 3.0;
+    ff[Q.nf + f] = Ef != 0.0 ? t[1] / Ef : 0.0;
+    ff[2 * (size_t)Q.nf + f] = Ef != 0.0 ? t[2] / Ef : 1.0 / 3.0;
+    fp[f] = p;
+    if (f >= Q.nint) {
+        double* o = bc3 + (size_t)(f - Q.nint) * 3;
+        o[0] = Ef != 0.0 ? cE / Ef : cs / G;
+        o[1] = 0.0;
+        o[2] = jm;
+    }
 }
 
 }  // namespace
@@ -417,111 +545,20 @@ lc_status upload(Loqd* q, T** dst, const std::vector<T>& src) {
     return LC_OK;
 }
 
-}  // namespace
-}  // namespace lc
-
-using namespace lc;
-
-extern "C" {
-
-lc_status lc_loqd_create(int32_t nx, int32_t ny, double lx, double ly, int32_t G, lc_loqd_t* out) {
-    LC_ARG(out, "out must not be NULL");
-    *out = nullptr;
-    LC_ARG(nx >= 1 && ny >= 1, "nx and ny must be >= 1");
-    LC_ARG(std::isfinite(lx) && lx > 0.0 && std::isfinite(ly) && ly > 0.0, "lx, ly must be finite and > 0");
-    LC_ARG(G >= 1 && G <= 65535, "G must be in 1..65535");
-    Loqd* q = new Loqd();
-    q->nx = nx; q->ny = ny; q->G = G; q->lx = lx; q->ly = ly; q->hx = lx / nx; q->hy = ly / ny;
-    q->N = nx * ny;
-    q->nint = (nx - 1) * ny + nx * (ny - 1);
-    q->nb = 2 * (nx + ny);
-    q->nf = q->nint + q->nb;
-    q->nblk = (q->nf + kLoqdBlock - 1) / kLoqdBlock;
-    const int N = q->N, nf = q->nf, nint = q->nint;
-    // faces of each cell (L, R, B, T) and the cells of each face
-    std::vector<int> cface(4 * (size_t)N), lo(nf, -1), hi(nf, -1);
-    for (int iy = 0; iy < ny; ++iy)
-        for (int ix = 0; ix < nx; ++ix) {
-            const int i = iy * nx + ix;
-            const int L = ix > 0 ? iy * (nx - 1) + ix - 1 : nint + iy;
-            const int R = ix < nx - 1 ? iy * (nx - 1) + ix : nint + ny + iy;
-            const int B = iy > 0 ? (nx - 1) * ny + (iy - 1) * nx + ix : nint + 2 * ny + ix;
-            const int T = iy < ny - 1 ? (nx - 1) * ny + iy * nx + ix : nint + 2 * ny + nx + ix;
-            cface[i] = L; cface[N + i] = R; cface[2 * (size_t)N + i] = B; cface[3 * (size_t)N + i] = T;
-            hi[L] = i; lo[R] = i; hi[B] = i; lo[T] = i;
-        }
-    // columns of each face row: the face, then the other faces of its cells
-    std::vector<int> col((size_t)kSlots * nf);
-    for (int f = 0; f < nf; ++f) {
-        int c[kSlots], n = 0;
-        c[n++] = f;
-        for (int cell : {lo[f], hi[f]}) {
-            if (cell < 0) continue;
-            for (int k = 0; k < 4; ++k) {
-                const int e = cface[(size_t)k * N + cell];
-                bool seen = false;
-                for (int s = 0; s < n; ++s) seen |= c[s] == e;
-                if (!seen && n < kSlots) c[n++] = e;
-            }
-        }
-        for (int s = n; s < kSlots; ++s) c[s] = f;           // padding: zero entries on the row itself
-        for (int s = 0; s < kSlots; ++s) col[(size_t)s * nf + f] = c[s];
-    }
-    lc_status rc = upload(q, &q->d_cface, cface);
-    if (!rc) rc = upload(q, &q->d_lo, lo);
-    if (!rc) rc = upload(q, &q->d_hi, hi);
-    if (!rc) rc = upload(q, &q->d_col, col);
-    const size_t GN = (size_t)G * N, GF = (size_t)G * nf;
-    if (!rc) rc = dalloc(q->owned, &q->d_dc, GN);
-    if (!rc) rc = dalloc(q->owned, &q->d_ac, 4 * GN);
-    if (!rc) rc = dalloc(q->owned, &q->d_bc, GN);
-    if (!rc) rc = dalloc(q->owned, &q->d_val, (size_t)kSlots * GF);
-    if (!rc) rc = dalloc(q->owned, &q->d_dinv, GF);
-    if (!rc) rc = dalloc(q->owned, &q->d_b, GF);
-    if (!rc) rc = dalloc(q->owned, &q->d_vec, 8 * GF);
-    if (!rc) rc = dalloc(q->owned, &q->d_sh, GF);
-    if (!rc) rc = dalloc(q->owned, &q->d_part, (size_t)G * q->nblk * 2);
-    if (!rc) rc = dalloc(q->owned, &q->d_sc, (size_t)G * kScal);
-    if (!rc) rc = dalloc(q->owned, &q->d_flag, (size_t)G);
-    if (rc) {
-        free_loqd(q);
-        return rc;
-    }
-    q->magic = kLoqdMagic;
-    *out = reinterpret_cast<lc_loqd_t>(q);
-    return LC_OK;
+Geo geo(const Loqd* q, double c, double c_dt, int G) {
+    return Geo{q->nx, q->ny, q->N, q->nint, q->nf, G, q->hx, q->hy, c, c_dt, q->d_cface, q->d_lo, q->d_hi, q->d_col};
 }
 
-lc_status lc_loqd_free(lc_loqd_t h) {
-    if (!h) return LC_OK;
-    Loqd* q = as_loqd(h);
-    LC_CHECK(q, LC_ERR_STATE, "invalid LOQD handle");
-    free_loqd(q);
-    return LC_OK;
-}
-
-lc_status lc_loqd_solve(lc_loqd_t h, double c, double c_dt, const double* kappa, const double* planck,
-                        const double* E_prev, const double* F_prev, const double* f_cell, const double* f_face,
-                        const double* bnd, double* E_cell, double* E_face, double* F_face, double rtol,
-                        int32_t max_iter, int32_t* iters, double* resid, void* stream) {
-    Loqd* q = as_loqd(h);
-    LC_CHECK(q, LC_ERR_STATE, "invalid LOQD handle");
-    LC_ARG(kappa && planck && E_prev && F_prev && f_cell && bnd && E_cell && E_face && F_face,
-           "inputs and outputs must not be NULL");
-    LC_ARG(f_face || q->nint == 0, "f_face must not be NULL when the grid has interior faces");
-    LC_ARG(std::isfinite(c) && c > 0.0 && std::isfinite(c_dt) && c_dt > 0.0, "c and c_dt must be finite and > 0");
-    LC_ARG(std::isfinite(rtol) && rtol > 0.0 && rtol < 1.0, "rtol must be in (0, 1)");
-    LC_ARG(max_iter >= 1, "max_iter must be >= 1");
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const int G = q->G, nf = q->nf, nblk = q->nblk;
-    Geo Q{q->nx, q->ny, q->N, q->nint, nf, G, q->hx, q->hy, c, c_dt, q->d_cface, q->d_lo, q->d_hi, q->d_col};
+// Assemble and solve the general-form system of every group; outputs E_cell
+// [G][N], E_face [G][nf], F_face [G][nf].
+lc_status solve_general(Loqd* q, const Geo& Q, const Gen& Cg, double* E_cell, double* E_face, double* F_face,
+                        double rtol, int max_iter, int32_t* iters, double* resid, hipStream_t st) {
+    const int G = Q.G, nf = q->nf, nblk = q->nblk;
     const dim3 blk(kLoqdBlock);
     const dim3 gc((q->N + kLoqdBlock - 1) / kLoqdBlock, G), gf(nblk, G);
     const dim3 gmax((std::max(q->N, nf) + kLoqdBlock - 1) / kLoqdBlock, G);
-    hipLaunchKernelGGL(k_loqd_cells, gc, blk, 0, st, Q, kappa, planck, E_prev, F_prev, f_cell, f_face, bnd, q->d_dc,
-                       q->d_ac, q->d_bc);
-    hipLaunchKernelGGL(k_loqd_faces, gf, blk, 0, st, Q, kappa, F_prev, f_cell, f_face, bnd, q->d_dc, q->d_ac,
-                       q->d_bc, q->d_val, q->d_dinv, q->d_b);
+    hipLaunchKernelGGL(k_loqd_cells, gc, blk, 0, st, Q, Cg, q->d_dc, q->d_ac, q->d_bc);
+    hipLaunchKernelGGL(k_loqd_faces, gf, blk, 0, st, Q, Cg, q->d_dc, q->d_ac, q->d_bc, q->d_val, q->d_dinv, q->d_b);
     LC_HIP(hipGetLastError());
     const size_t GF = (size_t)G * nf;
     Vecs V{q->d_vec, q->d_vec + GF, q->d_vec + 2 * GF, q->d_vec + 3 * GF, q->d_vec + 4 * GF, q->d_vec + 5 * GF,
@@ -595,9 +632,8 @@ lc_status lc_loqd_solve(lc_loqd_t h, double c, double c_dt, const double* kappa,
         if (!again) break;
     }
     LC_HIP(hipMemcpyAsync(hsc.data(), q->d_sc, hsc.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    hipLaunchKernelGGL(k_loqd_back, gmax, blk, 0, st, Q, kappa, F_prev, f_cell, f_face, bnd, q->d_dc, q->d_ac,
-                       q->d_bc, V.x, E_cell, E_face, F_face);
-    hipLaunchKernelGGL(k_loqd_flux, gf, blk, 0, st, Q, kappa, F_prev, f_cell, f_face, bnd, E_cell, E_face, F_face);
+    hipLaunchKernelGGL(k_loqd_back, gmax, blk, 0, st, Q, q->d_dc, q->d_ac, q->d_bc, V.x, E_cell, E_face);
+    hipLaunchKernelGGL(k_loqd_flux, gf, blk, 0, st, Q, Cg, E_cell, E_face, F_face);
     LC_HIP(hipGetLastError());
     LC_HIP(hipStreamSynchronize(st));
     if (iters) *iters = it;
@@ -610,6 +646,165 @@ lc_status lc_loqd_solve(lc_loqd_t h, double c, double c_dt, const double* kappa,
         ok &= rel <= rtol;
     }
     LC_CHECK(ok, LC_ERR_UNSUPPORTED, "LOQD solve did not reach rtol %.3g within %d iterations", rtol, max_iter);
+    return LC_OK;
+}
+
+}  // namespace
+}  // namespace lc
+
+using namespace lc;
+
+extern "C" {
+
+lc_status lc_loqd_create(int32_t nx, int32_t ny, double lx, double ly, int32_t G, lc_loqd_t* out) {
+    LC_ARG(out, "out must not be NULL");
+    *out = nullptr;
+    LC_ARG(nx >= 1 && ny >= 1, "nx and ny must be >= 1");
+    LC_ARG(std::isfinite(lx) && lx > 0.0 && std::isfinite(ly) && ly > 0.0, "lx, ly must be finite and > 0");
+    LC_ARG(G >= 1 && G <= 65535, "G must be in 1..65535");
+    Loqd* q = new Loqd();
+    q->nx = nx; q->ny = ny; q->G = G; q->lx = lx; q->ly = ly; q->hx = lx / nx; q->hy = ly / ny;
+    q->N = nx * ny;
+    q->nint = (nx - 1) * ny + nx * (ny - 1);
+    q->nb = 2 * (nx + ny);
+    q->nf = q->nint + q->nb;
+    q->nblk = (q->nf + kLoqdBlock - 1) / kLoqdBlock;
+    const int N = q->N, nf = q->nf, nint = q->nint;
+    // faces of each cell (L, R, B, T) and the cells of each face
+    std::vector<int> cface(4 * (size_t)N), lo(nf, -1), hi(nf, -1);
+    for (int iy = 0; iy < ny; ++iy)
+        for (int ix = 0; ix < nx; ++ix) {
+            const int i = iy * nx + ix;
+            const int L = ix > 0 ? iy * (nx - 1) + ix - 1 : nint + iy;
+            const int R = ix < nx - 1 ? iy * (nx - 1) + ix : nint + ny + iy;
+            const int B = iy > 0 ? (nx - 1) * ny + (iy - 1) * nx + ix : nint + 2 * ny + ix;
+            const int T = iy < ny - 1 ? (nx - 1) * ny + iy * nx + ix : nint + 2 * ny + nx + ix;
+            cface[i] = L; cface[N + i] = R; cface[2 * (size_t)N + i] = B; cface[3 * (size_t)N + i] = T;
+            hi[L] = i; lo[R] = i; hi[B] = i; lo[T] = i;
+        }
+    // columns of each face row: the face, then the other faces of its cells
+    std::vector<int> col((size_t)kSlots * nf);
+    for (int f = 0; f < nf; ++f) {
+        int c[kSlots], n = 0;
+        c[n++] = f;
+        for (int cell : {lo[f], hi[f]}) {
+            if (cell < 0) continue;
+            for (int k = 0; k < 4; ++k) {
+                const int e = cface[(size_t)k * N + cell];
+                bool seen = false;
+                for (int s = 0; s < n; ++s) seen |= c[s] == e;
+                if (!seen && n < kSlots) c[n++] = e;
+            }
+        }
+        for (int s = n; s < kSlots; ++s) c[s] = f;           // padding: zero entries on the row itself
+        for (int s = 0; s < kSlots; ++s) col[(size_t)s * nf + f] = c[s];
+    }
+    lc_status rc = upload(q, &q->d_cface, cface);
+    if (!rc) rc = upload(q, &q->d_lo, lo);
+    if (!rc) rc = upload(q, &q->d_hi, hi);
+    if (!rc) rc = upload(q, &q->d_col, col);
+    const size_t GN = (size_t)G * N, GF = (size_t)G * nf;
+    if (!rc) rc = dalloc(q->owned, &q->d_sigma, GN);
+    if (!rc) rc = dalloc(q->owned, &q->d_src, GN);
+    if (!rc) rc = dalloc(q->owned, &q->d_ks, 4 * GN);
+    if (!rc) rc = dalloc(q->owned, &q->d_es, 4 * GN);
+    if (!rc) rc = dalloc(q->owned, &q->d_fc, 3 * GN);
+    if (!rc) rc = dalloc(q->owned, &q->d_ff, 3 * GF);
+    if (!rc) rc = dalloc(q->owned, &q->d_bc3, 3 * (size_t)G * q->nb);
+    if (!rc) rc = dalloc(q->owned, &q->d_fp, GF);
+    if (!rc) rc = dalloc(q->owned, &q->d_dc, GN);
+    if (!rc) rc = dalloc(q->owned, &q->d_ac, 4 * GN);
+    if (!rc) rc = dalloc(q->owned, &q->d_bc, GN);
+    if (!rc) rc = dalloc(q->owned, &q->d_val, (size_t)kSlots * GF);
+    if (!rc) rc = dalloc(q->owned, &q->d_dinv, GF);
+    if (!rc) rc = dalloc(q->owned, &q->d_b, GF);
+    if (!rc) rc = dalloc(q->owned, &q->d_vec, 8 * GF);
+    if (!rc) rc = dalloc(q->owned, &q->d_sh, GF);
+    if (!rc) rc = dalloc(q->owned, &q->d_part, (size_t)G * q->nblk * 2);
+    if (!rc) rc = dalloc(q->owned, &q->d_sc, (size_t)G * kScal);
+    if (!rc) rc = dalloc(q->owned, &q->d_flag, (size_t)G);
+    if (rc) {
+        free_loqd(q);
+        return rc;
+    }
+    q->magic = kLoqdMagic;
+    *out = reinterpret_cast<lc_loqd_t>(q);
+    return LC_OK;
+}
+
+lc_status lc_loqd_free(lc_loqd_t h) {
+    if (!h) return LC_OK;
+    Loqd* q = as_loqd(h);
+    LC_CHECK(q, LC_ERR_STATE, "invalid LOQD handle");
+    free_loqd(q);
+    return LC_OK;
+}
+
+lc_status lc_loqd_solve(lc_loqd_t h, double c, double c_dt, const double* kappa, const double* planck,
+                        const double* E_prev, const double* F_prev, const double* f_cell, const double* f_face,
+                        const double* bnd, double* E_cell, double* E_face, double* F_face, double rtol,
+                        int32_t max_iter, int32_t* iters, double* resid, void* stream) {
+    Loqd* q = as_loqd(h);
+    LC_CHECK(q, LC_ERR_STATE, "invalid LOQD handle");
+    LC_ARG(kappa && planck && E_prev && F_prev && f_cell && bnd && E_cell && E_face && F_face,
+           "inputs and outputs must not be NULL");
+    LC_ARG(f_face || q->nint == 0, "f_face must not be NULL when the grid has interior faces");
+    LC_ARG(std::isfinite(c) && c > 0.0 && std::isfinite(c_dt) && c_dt > 0.0, "c and c_dt must be finite and > 0");
+    LC_ARG(std::isfinite(rtol) && rtol > 0.0 && rtol < 1.0, "rtol must be in (0, 1)");
+    LC_ARG(max_iter >= 1, "max_iter must be >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Geo Q = geo(q, c, c_dt, q->G);
+    const dim3 blk(kLoqdBlock);
+    hipLaunchKernelGGL(k_loqd_prep_cells, dim3((q->N + kLoqdBlock - 1) / kLoqdBlock, q->G), blk, 0, st, Q, kappa,
+                       planck, E_prev, f_cell, q->d_sigma, q->d_src, q->d_ks, q->d_es, q->d_fc);
+    hipLaunchKernelGGL(k_loqd_prep_faces, dim3(q->nblk, q->G), blk, 0, st, Q, F_prev, f_face, bnd, q->d_ff,
+                       q->d_bc3, q->d_fp);
+    LC_HIP(hipGetLastError());
+    const Gen Cg{q->d_sigma, q->d_src, q->d_ks, q->d_es, q->d_fc, q->d_ff, q->d_bc3, q->d_fp};
+    return solve_general(q, Q, Cg, E_cell, E_face, F_face, rtol, max_iter, iters, resid, st);
+}
+
+lc_status lc_loqd_solve_general(lc_loqd_t h, double c, double c_dt, const double* sigma, const double* source,
+                                const double* k_side, const double* eta_side, const double* F_prev,
+                                const double* f_cell, const double* f_face, const double* bc, double* E_cell,
+                                double* E_face, double* F_face, double rtol, int32_t max_iter, int32_t* iters,
+                                double* resid, void* stream) {
+    Loqd* q = as_loqd(h);
+    LC_CHECK(q, LC_ERR_STATE, "invalid LOQD handle");
+    LC_ARG(sigma && source && k_side && eta_side && F_prev && f_cell && f_face && bc && E_cell && E_face && F_face,
+           "inputs and outputs must not be NULL");
+    LC_ARG(std::isfinite(c) && c > 0.0 && std::isfinite(c_dt) && c_dt > 0.0, "c and c_dt must be finite and > 0");
+    LC_ARG(std::isfinite(rtol) && rtol > 0.0 && rtol < 1.0, "rtol must be in (0, 1)");
+    LC_ARG(max_iter >= 1, "max_iter must be >= 1");
+    const Geo Q = geo(q, c, c_dt, q->G);
+    const Gen Cg{sigma, source, k_side, eta_side, f_cell, f_face, bc, F_prev};
+    return solve_general(q, Q, Cg, E_cell, E_face, F_face, rtol, max_iter, iters, resid,
+                         static_cast<hipStream_t>(stream));
+}
+
+lc_status lc_loqd_grey_coefficients(lc_loqd_t h, double c, double c_dt, const double* kappa, const double* planck,
+                                    const double* E_prev, const double* F_prev, const double* f_cell,
+                                    const double* f_face, const double* bnd, const double* E_cell,
+                                    const double* E_face, const double* F_face, double* sigma, double* source,
+                                    double* k_side, double* eta_side, double* F_prev_grey, double* f_cell_grey,
+                                    double* f_face_grey, double* bc_grey, double* E_prev_grey, void* stream) {
+    Loqd* q = as_loqd(h);
+    LC_CHECK(q, LC_ERR_STATE, "invalid LOQD handle");
+    LC_ARG(kappa && planck && E_prev && F_prev && f_cell && bnd && E_cell && E_face && F_face,
+           "multigroup inputs must not be NULL");
+    LC_ARG(f_face || q->nint == 0, "f_face must not be NULL when the grid has interior faces");
+    LC_ARG(sigma && source && k_side && eta_side && F_prev_grey && f_cell_grey && f_face_grey && bc_grey &&
+               E_prev_grey,
+           "outputs must not be NULL");
+    LC_ARG(std::isfinite(c) && c > 0.0 && std::isfinite(c_dt) && c_dt > 0.0, "c and c_dt must be finite and > 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const Geo Q = geo(q, c, c_dt, q->G);
+    const dim3 blk(kLoqdBlock);
+    hipLaunchKernelGGL(k_grey_cells, dim3((q->N + kLoqdBlock - 1) / kLoqdBlock), blk, 0, st, Q, kappa, planck, E_prev,
+                       f_cell, E_cell, E_face, F_face, sigma, source, k_side, eta_side, f_cell_grey, E_prev_grey);
+    hipLaunchKernelGGL(k_grey_faces, dim3(q->nblk), blk, 0, st, Q, F_prev, f_face, bnd, E_face, f_face_grey, bc_grey,
+                       F_prev_grey);
+    LC_HIP(hipGetLastError());
     return LC_OK;
 }
 

@@ -78,6 +78,9 @@ _SIGS = {
     "lc_sweep_noalloc": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_loqd_create": ([_i32, _i32, _d, _d, _i32, C.POINTER(_vp)], C.c_int),
     "lc_loqd_free": ([_vp], C.c_int),
+    "lc_loqd_solve_general": ([_vp, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i32, _vp,
+                               _vp, _vp], C.c_int),
+    "lc_loqd_grey_coefficients": ([_vp, _d, _d] + [_vp] * 19, C.c_int),
     "lc_loqd_solve": ([_vp, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i32, _vp, _vp, _vp],
                       C.c_int),
     "lc_moments": ([_vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
@@ -485,3 +488,38 @@ def lc_loqd_solve(h: Loqd, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_fac
                               _dev(E_face, G * nf, name="E_face"), _dev(F_face, G * nf, name="F_face"),
                               float(rtol), int(max_iter), C.byref(it), res.ctypes.data, _stream(stream)))
     return int(it.value), res
+
+
+def lc_loqd_solve_general(h: Loqd, c, c_dt, sigma, source, k_side, eta_side, F_prev, f_cell, f_face, bc, E_cell,
+                          E_face, F_face, rtol=1e-13, max_iter=20000, stream=None):
+    """General form (the handle's G groups).  Returns (iterations, residuals)."""
+    G, N, nf = h.G, h.cells, h.nf
+    it = C.c_int32(0)
+    res = np.zeros(G)
+    _check(_lib.lc_loqd_solve_general(h.handle, float(c), float(c_dt), _dev(sigma, G * N, name="sigma"),
+                                      _dev(source, G * N, name="source"), _dev(k_side, 4 * G * N, name="k_side"),
+                                      _dev(eta_side, 4 * G * N, name="eta_side"), _dev(F_prev, G * nf, name="F_prev"),
+                                      _dev(f_cell, 3 * G * N, name="f_cell"), _dev(f_face, 3 * G * nf, name="f_face"),
+                                      _dev(bc, 3 * G * h.nb, name="bc"), _dev(E_cell, G * N, name="E_cell"),
+                                      _dev(E_face, G * nf, name="E_face"), _dev(F_face, G * nf, name="F_face"),
+                                      float(rtol), int(max_iter), C.byref(it), res.ctypes.data, _stream(stream)))
+    return int(it.value), res
+
+
+def lc_loqd_grey_coefficients(h: Loqd, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bnd, E_cell, E_face,
+                              F_face, out, stream=None):
+    """out: dict of device tensors sigma, source, E_prev [cells]; k_side,
+    eta_side [4 cells]; F_prev [nf]; f_cell [3 cells]; f_face [3 nf];
+    bc [3 nb] (the grey coefficients are written there)."""
+    G, N, nf = h.G, h.cells, h.nf
+    _check(_lib.lc_loqd_grey_coefficients(
+        h.handle, float(c), float(c_dt), _dev(kappa, G * N, name="kappa"), _dev(planck, G * N, name="planck"),
+        _dev(E_prev, G * N, name="E_prev"), _dev(F_prev, G * nf, name="F_prev"),
+        _dev(f_cell, 4 * G * N, name="f_cell"),
+        _dev(f_face, 4 * G * h.n_interior, name="f_face", optional=h.n_interior == 0),
+        _dev(bnd, 8 * G * h.nb, name="bnd"), _dev(E_cell, G * N, name="E_cell"), _dev(E_face, G * nf, name="E_face"),
+        _dev(F_face, G * nf, name="F_face"), _dev(out["sigma"], N, name="sigma"), _dev(out["source"], N, name="source"),
+        _dev(out["k_side"], 4 * N, name="k_side"), _dev(out["eta_side"], 4 * N, name="eta_side"),
+        _dev(out["F_prev"], nf, name="F_prev out"), _dev(out["f_cell"], 3 * N, name="f_cell out"),
+        _dev(out["f_face"], 3 * nf, name="f_face out"), _dev(out["bc"], 3 * h.nb, name="bc out"),
+        _dev(out["E_prev"], N, name="E_prev out"), _stream(stream)))

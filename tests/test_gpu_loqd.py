@@ -225,3 +225,134 @@ def test_loqd_is_deterministic_and_reports_non_convergence(lcmod):
     with pytest.raises(lc.LcError) as e:
         _gpu_solve(lc, *args, rtol=1e-15, max_iter=1)
     assert e.value.status == lc.LC_ERR_UNSUPPORTED
+
+
+# ---------------------------------------------------------------------------
+# general form and the effective grey equations, eq. (5)
+# ---------------------------------------------------------------------------
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def _gpu_general(lc, nx, ny, lx, ly, c, c_dt, sigma, source, k_side, eta_side, F_prev, f_cell, f_face, bc):
+    """Arrays with a leading group axis, oracle layouts (k_side [G][cells][4])."""
+    import torch
+    G = sigma.shape[0]
+    h = lc.Loqd(nx, ny, lx, ly, G)
+    Ec = torch.zeros(G * h.cells, dtype=torch.float64, device="cuda")
+    Ef = torch.zeros(G * h.nf, dtype=torch.float64, device="cuda")
+    Ff = torch.zeros(G * h.nf, dtype=torch.float64, device="cuda")
+    it, res = lc.lc_loqd_solve_general(h, c, c_dt, _dev(sigma), _dev(source), _dev(k_side.transpose(0, 2, 1)),
+                                       _dev(eta_side.transpose(0, 2, 1)), _dev(F_prev), _dev(f_cell), _dev(f_face),
+                                       _dev(bc), Ec, Ef, Ff)
+    return (Ec.cpu().numpy().reshape(G, -1), Ef.cpu().numpy().reshape(G, -1), Ff.cpu().numpy().reshape(G, -1))
+
+
+def test_loqd_general_form(lcmod):
+    """Side-dependent k and non-zero eta (the shape of the grey equations)."""
+    lc, _ = lcmod
+    rng = np.random.default_rng(12)
+    nx, ny, lx, ly, G = 17, 11, 1.7, 1.1, 2
+    N, nf, nb = nx * ny, OL.n_faces(nx, ny), 2 * (nx + ny)
+    c, c_dt = 299.792458, 0.6
+    sigma = c * 10.0 ** rng.uniform(0, 2, (G, N))
+    source = rng.uniform(0, 100, (G, N))
+    k_side = 10.0 ** rng.uniform(0, 2, (G, N, 4))
+    eta_side = rng.uniform(-0.5, 0.5, (G, N, 4)) * k_side
+    F_prev = rng.uniform(-0.3, 0.3, (G, nf))
+
+    def tensors(n):
+        a = rng.uniform(0.15, 0.6, (G, n)); dd = rng.uniform(0.15, 0.6, (G, n))
+        return np.stack([a, rng.uniform(-0.5, 0.5, (G, n)) * np.sqrt(a * dd), dd], axis=1)
+    fc, ff = tensors(N), tensors(nf)
+    bc = np.stack([rng.uniform(0.3, 0.7, (G, nb)), rng.uniform(0, 1, (G, nb)), rng.uniform(0, 0.5, (G, nb))], axis=2)
+    _say("case loqd general form 17x11 G=2")
+    got = _gpu_general(lc, nx, ny, lx, ly, c, c_dt, sigma, source, k_side, eta_side, F_prev, fc, ff, bc)
+    ref = [np.stack(x) for x in zip(*[OL.solve_general(nx, ny, lx, ly, c, c_dt, sigma[g], source[g], k_side[g],
+                                                       eta_side[g], F_prev[g], fc[g], ff[g], bc[g])
+                                      for g in range(G)])]
+    _compare(got, ref, "general form")
+
+
+def _gpu_grey_coefficients(lc, nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc, sol):
+    """The library's grey coefficients from a multigroup solution `sol`
+    (E_cell, E_face, F_face [G][...]), returned in the oracle's layouts."""
+    import torch
+    G = kappa.shape[0]
+    h = lc.Loqd(nx, ny, lx, ly, G)
+    fc, ff, bnd = _gpu_layouts(nx, ny, f_cell, f_face, bc)
+    N, nf, nb = h.cells, h.nf, h.nb
+    z = lambda n: torch.zeros(n, dtype=torch.float64, device="cuda")
+    out = dict(sigma=z(N), source=z(N), E_prev=z(N), k_side=z(4 * N), eta_side=z(4 * N), F_prev=z(nf),
+               f_cell=z(3 * N), f_face=z(3 * nf), bc=z(3 * nb))
+    lc.lc_loqd_grey_coefficients(h, c, c_dt, _dev(kappa), _dev(planck), _dev(E_prev), _dev(F_prev), _dev(fc),
+                                 _dev(ff), _dev(bnd), _dev(sol[0]), _dev(sol[1]), _dev(sol[2]), out)
+    o = {k: v.cpu().numpy() for k, v in out.items()}
+    return dict(sigma=o["sigma"], source=o["source"], E_prev=o["E_prev"], k_side=o["k_side"].reshape(4, N).T,
+                eta_side=o["eta_side"].reshape(4, N).T, F_prev=o["F_prev"], f_cell=o["f_cell"].reshape(3, N),
+                f_face=o["f_face"].reshape(3, nf), bc=o["bc"].reshape(nb, 3))
+
+
+def test_grey_coefficients_and_solve_match_the_oracle(lcmod):
+    """From one multigroup solution (the oracle's), the library's grey
+    coefficients equal the oracle's, and the grey solves agree."""
+    lc, _ = lcmod
+    from tests.test_oracle_loqd import _multigroup_case
+    args = _multigroup_case(G=5, nx=14, ny=9, lx=2.8, ly=1.8, seed=31)
+    nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc = args
+    _say("case grey coefficients 14x9 G=5")
+    sol = OL.solve(*args)
+    ref = OL.grey_coefficients(nx, ny, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc, *sol)
+    got = _gpu_grey_coefficients(lc, *args, sol)
+    for k in ref:
+        scale = np.max(np.abs(ref[k])) or 1.0
+        d = np.max(np.abs(got[k] - ref[k])) / scale
+        assert d <= 1e-13, (k, d)
+    g1 = lambda a: a[None]
+    gs = _gpu_general(lc, nx, ny, lx, ly, c, c_dt, g1(got["sigma"]), g1(got["source"]), g1(got["k_side"]),
+                      g1(got["eta_side"]), g1(got["F_prev"]), g1(got["f_cell"]), g1(got["f_face"]), g1(got["bc"]))
+    rs = OL.solve_grey(nx, ny, lx, ly, c, c_dt, ref)
+    _compare(gs, [g1(x) for x in rs], "grey solve")
+
+
+def test_grey_equals_the_sum_of_the_groups_on_the_gpu(lcmod):
+    """The whole low-order chain in the library -- multigroup solve, grey
+    coefficients, grey solve -- on closures of the transport sweep of the
+    16 x 16 workload (sweep, moments and face moments in the library too):
+    the grey solution is the sum of the group solutions (1e-9 normwise), and
+    agrees with the same chain in the oracle."""
+    import torch
+    lc, driver = lcmod
+    prob = W.config(0)
+    _say("case grey chain 16x16 G=4")
+    s = driver.Solver(prob, prec=lc.LC_F64)
+    s.enable_faces()
+    s.reset()
+    s.step_faces(1)
+    G, N = prob.G, prob.cells
+    c, c_dt, kap, pla, E_prev, F_prev = _loqd_inputs(prob)
+    h = lc.Loqd(prob.nx, prob.ny, prob.lx, prob.ly, G)
+    z = lambda n: torch.zeros(n, dtype=torch.float64, device="cuda")
+    Ec, Ef, Ff = z(G * N), z(G * h.nf), z(G * h.nf)
+    kd, pd, epd, fpd = s.kappa[0].reshape(-1), s.planck[0].reshape(-1), _dev(E_prev), _dev(F_prev)
+    lc.lc_loqd_solve(h, c, c_dt, kd, pd, epd, fpd, s.f, s.ff, s.bnd, Ec, Ef, Ff)
+    out = dict(sigma=z(N), source=z(N), E_prev=z(N), k_side=z(4 * N), eta_side=z(4 * N), F_prev=z(h.nf),
+               f_cell=z(3 * N), f_face=z(3 * h.nf), bc=z(3 * h.nb))
+    lc.lc_loqd_grey_coefficients(h, c, c_dt, kd, pd, epd, fpd, s.f, s.ff, s.bnd, Ec, Ef, Ff, out)
+    hg = lc.Loqd(prob.nx, prob.ny, prob.lx, prob.ly, 1)
+    gE, gEf, gF = z(N), z(hg.nf), z(hg.nf)
+    lc.lc_loqd_solve_general(hg, c, c_dt, out["sigma"], out["source"], out["k_side"], out["eta_side"],
+                             out["F_prev"], out["f_cell"], out["f_face"], out["bc"], gE, gEf, gF)
+    grey = (gE.cpu().numpy()[None], gEf.cpu().numpy()[None], gF.cpu().numpy()[None])
+    summed = tuple(x.cpu().numpy().reshape(G, -1).sum(0)[None] for x in (Ec, Ef, Ff))
+    _compare(grey, summed, "grey vs sum of groups (library)")
+    # the oracle's chain
+    _, f, ff, bnd = _oracle_transport_closures(prob)
+    f_cell, f_face, bc = OL.closures_from_transport(prob.nx, prob.ny, f, ff, bnd)
+    oargs = (prob.nx, prob.ny, prob.lx, prob.ly, c, c_dt, kap, pla, E_prev, F_prev, f_cell, f_face, bc)
+    osol = OL.solve(*oargs)
+    ocoef = OL.grey_coefficients(prob.nx, prob.ny, c, c_dt, kap, pla, E_prev, F_prev, f_cell, f_face, bc, *osol)
+    oref = OL.solve_grey(prob.nx, prob.ny, prob.lx, prob.ly, c, c_dt, ocoef)
+    _compare(grey, tuple(x[None] for x in oref), "grey chain vs oracle")
