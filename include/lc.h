@@ -411,7 +411,9 @@ lc_status lc_loqd_solve(lc_loqd_t loqd, double c, double c_dt, const double* kap
  * <kappa>_E; eta = 0; <f> = 1/3 on the diagonal; C -> mean C_g.  Sums over
  * the groups run in a fixed order.  Outputs (device, float64): sigma,
  * source, E_prev_grey [cells]; k_side, eta_side [4][cells]; F_prev_grey
- * [nf]; f_cell_grey [3][cells]; f_face_grey [3][nf]; bc_grey [nb][3].
+ * [nf]; f_cell_grey [3][cells]; f_face_grey [3][nf]; bc_grey [nb][3];
+ * kappa_E, kappa_B [cells] (<kappa>_E and <kappa>_B, the inputs of
+ * lc_loqd_grey_meb; either may be NULL).
  * Allocates and synchronises nothing.  Errors: LC_ERR_ARG (NULL, c or c_dt
  * not finite or <= 0), LC_ERR_STATE, LC_ERR_HIP.
  */
@@ -427,7 +429,47 @@ lc_status lc_loqd_grey_coefficients(lc_loqd_t loqd, double c, double c_dt, const
                                     const double* E_cell, const double* E_face, const double* F_face,
                                     double* sigma, double* source, double* k_side, double* eta_side,
                                     double* F_prev_grey, double* f_cell_grey, double* f_face_grey,
-                                    double* bc_grey, double* E_prev_grey, void* stream);
+                                    double* bc_grey, double* E_prev_grey, double* kappa_E,
+                                    double* kappa_B, void* stream);
+
+/*
+ * lc_loqd_grey_meb -- the effective grey problem of one backward-Euler step:
+ * the grey equations, eq. (5), coupled to the grey material energy balance,
+ * eq. (6), with material energy eps = c_v T (the paper's test material),
+ *   c_v (T - T^{n-1}) / dt = c <kappa>_E E - c <kappa>_B a_R T^4,
+ *   c (<kappa>_E + 1/(c dt)) E + div F = c <kappa>_B a_R T^4 + E^{n-1}/dt,
+ * with the spectrum averages and the other grey coefficients held fixed
+ * (the outputs of lc_loqd_grey_coefficients).  Newton iteration on T:
+ * a_R T^4 is linearised about the iterate T_k, the energy balance then gives
+ * T = alpha + beta E per cell, the grey equations with the resulting
+ * absorption and source are solved as lc_loqd_solve_general does, and T is
+ * updated, until max over cells of |T_{k+1} - T_k| / |T_{k+1}| <= newton_tol.
+ * The handle's G is the number of independent grey problems (normally 1);
+ * every array carries a leading [G] axis over the layouts of
+ * lc_loqd_solve_general: kappa_E, kappa_B, E_prev, T_prev [G][cells];
+ * k_side, eta_side [G][4][cells]; F_prev [G][nf]; f_cell [G][3][cells];
+ * f_face [G][3][nf]; bc [G][nb][3] (device, float64).  T [G][cells]
+ * (device, in/out): the first iterate on entry (T_prev is the usual
+ * choice), the converged temperature on return.  Outputs E_cell [G][cells],
+ * E_face, F_face [G][nf] as lc_loqd_solve_general.  c_v (energy per volume
+ * and temperature) and a_R > 0 in the units of E and T.  Each inner solve
+ * runs to rtol within max_iter iterations; newton_iters (may be NULL)
+ * receives the Newton iterations, iters (may be NULL) the BiCGSTAB
+ * iterations summed over them, resid (may be NULL, [G]) the last inner
+ * solve's relative residuals.  Uses the handle's coefficient buffers
+ * (sigma, source) and synchronises the stream every iteration.  Errors:
+ * LC_ERR_ARG (NULL, c, c_dt, c_v or a_R not finite or <= 0, newton_tol < 0,
+ * max_newton or max_iter < 1, rtol outside (0, 1)), LC_ERR_STATE,
+ * LC_ERR_UNSUPPORTED (an inner solve or the Newton iteration did not
+ * converge; the outputs then hold the last iterate), LC_ERR_HIP.
+ */
+lc_status lc_loqd_grey_meb(lc_loqd_t loqd, double c, double c_dt, const double* kappa_E,
+                           const double* kappa_B, const double* E_prev, const double* k_side,
+                           const double* eta_side, const double* F_prev, const double* f_cell,
+                           const double* f_face, const double* bc, const double* T_prev, double c_v,
+                           double a_R, double* T, double* E_cell, double* E_face, double* F_face,
+                           double newton_tol, int32_t max_newton, double rtol, int32_t max_iter,
+                           int32_t* newton_iters, int32_t* iters, double* resid, void* stream);
 
 /*
  * lc_step -- n_steps backward-Euler time steps (sweep, then moments) with the

@@ -305,7 +305,7 @@ def grey_coefficients(nx, ny, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_
     Inputs as for solve() plus E_cell [G][cells], E_face [G][faces],
     F_face [G][faces].  Returns a dict with sigma, source [cells], k_side,
     eta_side [cells][4], F_prev [faces], f_cell [3][cells], f_face
-    [3][faces], bc [nb][3], E_prev [cells]."""
+    [3][faces], bc [nb][3], E_prev [cells], kappa_E and kappa_B [cells]."""
     G, N = kappa.shape
     nf = n_faces(nx, ny)
     nint = n_interior(nx, ny)
@@ -346,10 +346,46 @@ def grey_coefficients(nx, ny, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_
     Jm = (bc[:, :, 0] * bc[:, :, 1] + bc[:, :, 2]).sum(0)
     bc_g = np.stack([C, np.zeros_like(C), Jm], axis=1)
     return dict(sigma=sigma, source=source, k_side=k_side, eta_side=eta_side, F_prev=F_prev.sum(0),
-                f_cell=f_cell_g, f_face=f_face_g, bc=bc_g, E_prev=E_prev.sum(0))
+                f_cell=f_cell_g, f_face=f_face_g, bc=bc_g, E_prev=E_prev.sum(0), kappa_E=kE, kappa_B=kB)
 
 
 def solve_grey(nx, ny, lx, ly, c, c_dt, coef):
     """The grey equations with the coefficients of grey_coefficients()."""
     return solve_general(nx, ny, lx, ly, c, c_dt, coef["sigma"], coef["source"], coef["k_side"],
                          coef["eta_side"], coef["F_prev"], coef["f_cell"], coef["f_face"], coef["bc"])
+
+
+
+def solve_grey_meb(nx, ny, lx, ly, c, c_dt, coef, T_prev, c_v, a_R, T_start=None, tol=1e-13, max_newton=50):
+    """The effective grey problem: eq. (5) coupled to the grey energy
+    balance, eq. (6), with material energy eps = c_v T, over one
+    backward-Euler step:
+        c_v (T - T^{n-1}) / dt = c <kappa>_E E - c <kappa>_B a_R T^4,
+        c (<kappa>_E + 1/(c dt)) E + div F = c <kappa>_B a_R T^4 + E^{n-1}/dt,
+    with the spectrum averages and the rest of the grey coefficients held
+    fixed (coef from grey_coefficients).  Newton iteration on T: a_R T^4 is
+    linearised about the iterate T_k, the energy balance then gives
+    T = alpha + beta E in every cell, which turns the emission into an
+    absorption and a source of the grey equations; each iteration solves
+    them and updates T, until max |T_{k+1} - T_k| / T_{k+1} <= tol.
+    Returns (T, E_cell, E_face, F_face, iterations)."""
+    kE, kB = coef["kappa_E"], coef["kappa_B"]
+    cv_dt = c_v * c / c_dt                       # c_v / dt
+    T = np.array(T_prev if T_start is None else T_start, dtype=np.float64)
+    base = c * coef["E_prev"] / c_dt
+    for it in range(1, max_newton + 1):
+        A = a_R * T ** 4
+        D = 4.0 * a_R * T ** 3
+        den = cv_dt + c * kB * D
+        beta = c * kE / den
+        alpha = (cv_dt * T_prev - c * kB * (A - D * T)) / den
+        sigma = c * (kE + 1.0 / c_dt) - c * kB * D * beta
+        source = base + c * kB * (A + D * (alpha - T))
+        Ec, Ef, Ff = solve_general(nx, ny, lx, ly, c, c_dt, sigma, source, coef["k_side"], coef["eta_side"],
+                                   coef["F_prev"], coef["f_cell"], coef["f_face"], coef["bc"])
+        T_new = alpha + beta * Ec
+        change = np.max(np.abs(T_new - T) / np.abs(T_new))
+        T = T_new
+        if change <= tol:
+            break
+    return T, Ec, Ef, Ff, it

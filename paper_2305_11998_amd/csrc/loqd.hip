@@ -21,6 +21,14 @@
 // E^{n-1}/dt, k = K_R + 1/(c dt) and eta per (cell, face), so that the
 // multigroup equations summed over the groups are the grey ones.
 //
+// The effective grey problem couples eq. (5) to the grey energy balance,
+// eq. (6), with eps = c_v T: per backward-Euler step
+//   c_v (T - T^{n-1})/dt = c <kappa>_E E - c <kappa>_B a_R T^4,
+// solved by Newton iteration on T with the spectrum averages held fixed.
+// Linearising a_R T^4 about the iterate T_k turns the energy balance into
+// T = alpha + beta E per cell, which enters the grey balance as an extra
+// absorption and source; each iteration is one general-form solve.
+//
 // Solution: a cell's balance couples E_i only to the cell's own four faces,
 // so E_i is eliminated exactly:  E_i = (b_i - sum_k a_ik E_k) / d_i.  What
 // remains is a system in the face unknowns alone (at most 7 entries a row:
@@ -449,7 +457,7 @@ __global__ void k_grey_cells(Geo Q, const double* __restrict__ kappa, const doub
                              const double* __restrict__ E_prev, const double* __restrict__ f_cell,
                              const double* __restrict__ E_cell, const double* __restrict__ E_face,
                              const double* __restrict__ F_face, double* sigma, double* src, double* ks, double* es,
-                             double* fc, double* Ep) {
+                             double* fc, double* Ep, double* kEo, double* kBo) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= Q.N) return;
     const int G = Q.G;
@@ -471,6 +479,8 @@ __global__ void k_grey_cells(Geo Q, const double* __restrict__ kappa, const doub
     if (std::isnan(avgB)) avgB = avgE;
     sigma[i] = Q.c * (avgE + 1.0 / Q.c_dt);
     src[i] = 4.0 * kPi * avgB * sB + Q.c * ep / Q.c_dt;
+    if (kEo) kEo[i] = avgE;
+    if (kBo) kBo[i] = avgB;
     Ep[i] = ep;
     fc[i] = E != 0.0 ? t[0] / E : 1.0 / 3.0;
     fc[Q.N + i] = E != 0.0 ? t[1] / E : 0.0;
@@ -523,6 +533,73 @@ __global__ void k_grey_faces(Geo Q, const double* __restrict__ F_prev, const dou
         o[1] = 0.0;
         o[2] = jm;
     }
+}
+
+// Grey energy balance, eq. (6) with eps = c_v T (inputs of one Newton
+// iteration; arrays [G][N], one independent grey problem per group index).
+struct Meb {
+    const double* kE;      // <kappa>_E
+    const double* kB;      // <kappa>_B
+    const double* Ep;      // E^{n-1}
+    const double* Tp;      // T^{n-1}
+    double cv_dt;          // c_v / dt
+    double a;              // a_R
+};
+
+// alpha, beta of T = alpha + beta E from the energy balance with a_R T^4
+// linearised about T_k: a_R T^4 ~ A + D (T - T_k), A = a_R T_k^4,
+// D = 4 a_R T_k^3.
+struct MebLin {
+    double A, D, alpha, beta;
+};
+
+__device__ inline MebLin meb_lin(const Geo& Q, const Meb& M, size_t gi, double Tk) {
+    MebLin l;
+    const double T2 = Tk * Tk;
+    l.A = M.a * T2 * T2;
+    l.D = 4.0 * M.a * T2 * Tk;
+    const double ckB = Q.c * M.kB[gi];
+    const double den = M.cv_dt + ckB * l.D;
+    l.beta = Q.c * M.kE[gi] / den;
+    l.alpha = (M.cv_dt * M.Tp[gi] - ckB * (l.A - l.D * Tk)) / den;
+    return l;
+}
+
+// Grey balance of one Newton iteration: the emission c <kappa>_B a_R T^4
+// with T = alpha + beta E moves c <kappa>_B D beta E to the left-hand side.
+__global__ void k_meb_linearise(Geo Q, Meb M, const double* __restrict__ T, double* sigma, double* src) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= Q.N) return;
+    const size_t gi = (size_t)blockIdx.y * Q.N + i;
+    const double Tk = T[gi];
+    const MebLin l = meb_lin(Q, M, gi, Tk);
+    const double ckB = Q.c * M.kB[gi];
+    sigma[gi] = Q.c * (M.kE[gi] + 1.0 / Q.c_dt) - ckB * l.D * l.beta;
+    src[gi] = Q.c * M.Ep[gi] / Q.c_dt + ckB * (l.A + l.D * (l.alpha - Tk));
+}
+
+// T_{k+1} = alpha + beta E in place; per block the largest relative change
+// |T_{k+1} - T_k| / |T_{k+1}| (infinity where it is not finite).
+__global__ void k_meb_update(Geo Q, Meb M, double* T, const double* __restrict__ E, double* part, int nblk) {
+    __shared__ double sm[kLoqdBlock];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double ch = 0.0;
+    if (i < Q.N) {
+        const size_t gi = (size_t)blockIdx.y * Q.N + i;
+        const double Tk = T[gi];
+        const MebLin l = meb_lin(Q, M, gi, Tk);
+        const double Tn = l.alpha + l.beta * E[gi];
+        T[gi] = Tn;
+        ch = fabs(Tn - Tk) / fabs(Tn);
+        if (!std::isfinite(ch)) ch = INFINITY;
+    }
+    sm[threadIdx.x] = ch;
+    __syncthreads();
+    for (int w = kLoqdBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(size_t)blockIdx.y * nblk + blockIdx.x] = sm[0];
 }
 
 }  // namespace
@@ -787,7 +864,8 @@ lc_status lc_loqd_grey_coefficients(lc_loqd_t h, double c, double c_dt, const do
                                     const double* f_face, const double* bnd, const double* E_cell,
                                     const double* E_face, const double* F_face, double* sigma, double* source,
                                     double* k_side, double* eta_side, double* F_prev_grey, double* f_cell_grey,
-                                    double* f_face_grey, double* bc_grey, double* E_prev_grey, void* stream) {
+                                    double* f_face_grey, double* bc_grey, double* E_prev_grey, double* kappa_E,
+                                    double* kappa_B, void* stream) {
     Loqd* q = as_loqd(h);
     LC_CHECK(q, LC_ERR_STATE, "invalid LOQD handle");
     LC_ARG(kappa && planck && E_prev && F_prev && f_cell && bnd && E_cell && E_face && F_face,
@@ -801,10 +879,67 @@ lc_status lc_loqd_grey_coefficients(lc_loqd_t h, double c, double c_dt, const do
     const Geo Q = geo(q, c, c_dt, q->G);
     const dim3 blk(kLoqdBlock);
     hipLaunchKernelGGL(k_grey_cells, dim3((q->N + kLoqdBlock - 1) / kLoqdBlock), blk, 0, st, Q, kappa, planck, E_prev,
-                       f_cell, E_cell, E_face, F_face, sigma, source, k_side, eta_side, f_cell_grey, E_prev_grey);
+                       f_cell, E_cell, E_face, F_face, sigma, source, k_side, eta_side, f_cell_grey, E_prev_grey,
+                       kappa_E, kappa_B);
     hipLaunchKernelGGL(k_grey_faces, dim3(q->nblk), blk, 0, st, Q, F_prev, f_face, bnd, E_face, f_face_grey, bc_grey,
                        F_prev_grey);
     LC_HIP(hipGetLastError());
+    return LC_OK;
+}
+
+lc_status lc_loqd_grey_meb(lc_loqd_t h, double c, double c_dt, const double* kappa_E, const double* kappa_B,
+                           const double* E_prev, const double* k_side, const double* eta_side, const double* F_prev,
+                           const double* f_cell, const double* f_face, const double* bc, const double* T_prev,
+                           double c_v, double a_R, double* T, double* E_cell, double* E_face, double* F_face,
+                           double newton_tol, int32_t max_newton, double rtol, int32_t max_iter,
+                           int32_t* newton_iters, int32_t* iters, double* resid, void* stream) {
+    Loqd* q = as_loqd(h);
+    LC_CHECK(q, LC_ERR_STATE, "invalid LOQD handle");
+    LC_ARG(kappa_E && kappa_B && E_prev && k_side && eta_side && F_prev && f_cell && f_face && bc && T_prev && T &&
+               E_cell && E_face && F_face,
+           "inputs and outputs must not be NULL");
+    LC_ARG(std::isfinite(c) && c > 0.0 && std::isfinite(c_dt) && c_dt > 0.0, "c and c_dt must be finite and > 0");
+    LC_ARG(std::isfinite(c_v) && c_v > 0.0 && std::isfinite(a_R) && a_R > 0.0, "c_v and a_R must be finite and > 0");
+    LC_ARG(std::isfinite(newton_tol) && newton_tol >= 0.0, "newton_tol must be finite and >= 0");
+    LC_ARG(max_newton >= 1, "max_newton must be >= 1");
+    LC_ARG(std::isfinite(rtol) && rtol > 0.0 && rtol < 1.0, "rtol must be in (0, 1)");
+    LC_ARG(max_iter >= 1, "max_iter must be >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int G = q->G;
+    const Geo Q = geo(q, c, c_dt, G);
+    const Meb M{kappa_E, kappa_B, E_prev, T_prev, c_v * c / c_dt, a_R};
+    const Gen Cg{q->d_sigma, q->d_src, k_side, eta_side, f_cell, f_face, bc, F_prev};
+    const int nblkc = (q->N + kLoqdBlock - 1) / kLoqdBlock;      // <= q->nblk: the partials fit d_part
+    const dim3 gc(nblkc, G), blk(kLoqdBlock);
+    std::vector<double> part((size_t)G * nblkc);
+    int total = 0, k = 0;
+    double change = INFINITY;
+    std::vector<double> res(G, 0.0);
+    while (k < max_newton && !(change <= newton_tol)) {
+        ++k;
+        hipLaunchKernelGGL(k_meb_linearise, gc, blk, 0, st, Q, M, T, q->d_sigma, q->d_src);
+        LC_HIP(hipGetLastError());
+        int32_t it = 0;
+        lc_status rc = solve_general(q, Q, Cg, E_cell, E_face, F_face, rtol, max_iter, &it, res.data(), st);
+        total += it;
+        if (rc) {
+            if (iters) *iters = total;
+            if (newton_iters) *newton_iters = k;
+            return rc;
+        }
+        hipLaunchKernelGGL(k_meb_update, gc, blk, 0, st, Q, M, T, E_cell, q->d_part, nblkc);
+        LC_HIP(hipGetLastError());
+        LC_HIP(hipMemcpyAsync(part.data(), q->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        LC_HIP(hipStreamSynchronize(st));
+        change = 0.0;
+        for (double v : part) change = std::max(change, v);
+    }
+    if (iters) *iters = total;
+    if (newton_iters) *newton_iters = k;
+    if (resid)
+        for (int g = 0; g < G; ++g) resid[g] = res[g];
+    LC_CHECK(change <= newton_tol, LC_ERR_UNSUPPORTED,
+             "grey energy balance: Newton change %.3g above %.3g after %d iterations", change, newton_tol, k);
     return LC_OK;
 }
 

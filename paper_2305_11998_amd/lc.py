@@ -80,7 +80,9 @@ _SIGS = {
     "lc_loqd_free": ([_vp], C.c_int),
     "lc_loqd_solve_general": ([_vp, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i32, _vp,
                                _vp, _vp], C.c_int),
-    "lc_loqd_grey_coefficients": ([_vp, _d, _d] + [_vp] * 19, C.c_int),
+    "lc_loqd_grey_coefficients": ([_vp, _d, _d] + [_vp] * 21, C.c_int),
+    "lc_loqd_grey_meb": ([_vp, _d, _d] + [_vp] * 10 + [_d, _d] + [_vp] * 4 + [_d, _i32, _d, _i32, _vp, _vp, _vp, _vp],
+                         C.c_int),
     "lc_loqd_solve": ([_vp, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i32, _vp, _vp, _vp],
                       C.c_int),
     "lc_moments": ([_vp, _vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
@@ -510,7 +512,8 @@ def lc_loqd_grey_coefficients(h: Loqd, c, c_dt, kappa, planck, E_prev, F_prev, f
                               F_face, out, stream=None):
     """out: dict of device tensors sigma, source, E_prev [cells]; k_side,
     eta_side [4 cells]; F_prev [nf]; f_cell [3 cells]; f_face [3 nf];
-    bc [3 nb] (the grey coefficients are written there)."""
+    bc [3 nb]; optionally kappa_E, kappa_B [cells] (the grey coefficients
+    are written there)."""
     G, N, nf = h.G, h.cells, h.nf
     _check(_lib.lc_loqd_grey_coefficients(
         h.handle, float(c), float(c_dt), _dev(kappa, G * N, name="kappa"), _dev(planck, G * N, name="planck"),
@@ -522,4 +525,26 @@ def lc_loqd_grey_coefficients(h: Loqd, c, c_dt, kappa, planck, E_prev, F_prev, f
         _dev(out["k_side"], 4 * N, name="k_side"), _dev(out["eta_side"], 4 * N, name="eta_side"),
         _dev(out["F_prev"], nf, name="F_prev out"), _dev(out["f_cell"], 3 * N, name="f_cell out"),
         _dev(out["f_face"], 3 * nf, name="f_face out"), _dev(out["bc"], 3 * h.nb, name="bc out"),
-        _dev(out["E_prev"], N, name="E_prev out"), _stream(stream)))
+        _dev(out["E_prev"], N, name="E_prev out"), _dev(out.get("kappa_E"), N, name="kappa_E", optional=True),
+        _dev(out.get("kappa_B"), N, name="kappa_B", optional=True), _stream(stream)))
+
+
+def lc_loqd_grey_meb(h: Loqd, c, c_dt, kappa_E, kappa_B, E_prev, k_side, eta_side, F_prev, f_cell, f_face, bc,
+                     T_prev, c_v, a_R, T, E_cell, E_face, F_face, newton_tol=1e-10, max_newton=50, rtol=1e-13,
+                     max_iter=20000, stream=None):
+    """The grey problem with the energy balance (the handle's G independent
+    problems).  T is the first iterate on entry and the result on return.
+    Returns (Newton iterations, BiCGSTAB iterations, last residuals)."""
+    G, N, nf = h.G, h.cells, h.nf
+    nit, it = C.c_int32(0), C.c_int32(0)
+    res = np.zeros(G)
+    _check(_lib.lc_loqd_grey_meb(
+        h.handle, float(c), float(c_dt), _dev(kappa_E, G * N, name="kappa_E"), _dev(kappa_B, G * N, name="kappa_B"),
+        _dev(E_prev, G * N, name="E_prev"), _dev(k_side, 4 * G * N, name="k_side"),
+        _dev(eta_side, 4 * G * N, name="eta_side"), _dev(F_prev, G * nf, name="F_prev"),
+        _dev(f_cell, 3 * G * N, name="f_cell"), _dev(f_face, 3 * G * nf, name="f_face"),
+        _dev(bc, 3 * G * h.nb, name="bc"), _dev(T_prev, G * N, name="T_prev"), float(c_v), float(a_R),
+        _dev(T, G * N, name="T"), _dev(E_cell, G * N, name="E_cell"), _dev(E_face, G * nf, name="E_face"),
+        _dev(F_face, G * nf, name="F_face"), float(newton_tol), int(max_newton), float(rtol), int(max_iter),
+        C.byref(nit), C.byref(it), res.ctypes.data, _stream(stream)))
+    return int(nit.value), int(it.value), res

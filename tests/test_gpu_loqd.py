@@ -77,8 +77,10 @@ def _gpu_solve(lc, nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cel
 
 
 def _compare(got, ref, what):
+    assert len(got) == len(ref)
+    names = ("E_cell", "E_face", "F_face") if len(got) == 3 else ("T", "E_cell", "E_face", "F_face")
     worst = 0.0
-    for name, a, b in zip(("E_cell", "E_face", "F_face"), got, ref):
+    for name, a, b in zip(names, got, ref, strict=True):
         for g in range(a.shape[0]):
             scale = np.max(np.abs(b[g]))
             if scale == 0.0:
@@ -286,13 +288,14 @@ def _gpu_grey_coefficients(lc, nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F
     N, nf, nb = h.cells, h.nf, h.nb
     z = lambda n: torch.zeros(n, dtype=torch.float64, device="cuda")
     out = dict(sigma=z(N), source=z(N), E_prev=z(N), k_side=z(4 * N), eta_side=z(4 * N), F_prev=z(nf),
-               f_cell=z(3 * N), f_face=z(3 * nf), bc=z(3 * nb))
+               f_cell=z(3 * N), f_face=z(3 * nf), bc=z(3 * nb), kappa_E=z(N), kappa_B=z(N))
     lc.lc_loqd_grey_coefficients(h, c, c_dt, _dev(kappa), _dev(planck), _dev(E_prev), _dev(F_prev), _dev(fc),
                                  _dev(ff), _dev(bnd), _dev(sol[0]), _dev(sol[1]), _dev(sol[2]), out)
     o = {k: v.cpu().numpy() for k, v in out.items()}
     return dict(sigma=o["sigma"], source=o["source"], E_prev=o["E_prev"], k_side=o["k_side"].reshape(4, N).T,
                 eta_side=o["eta_side"].reshape(4, N).T, F_prev=o["F_prev"], f_cell=o["f_cell"].reshape(3, N),
-                f_face=o["f_face"].reshape(3, nf), bc=o["bc"].reshape(nb, 3))
+                f_face=o["f_face"].reshape(3, nf), bc=o["bc"].reshape(nb, 3), kappa_E=o["kappa_E"],
+                kappa_B=o["kappa_B"])
 
 
 def test_grey_coefficients_and_solve_match_the_oracle(lcmod):
@@ -356,3 +359,122 @@ def test_grey_equals_the_sum_of_the_groups_on_the_gpu(lcmod):
     ocoef = OL.grey_coefficients(prob.nx, prob.ny, c, c_dt, kap, pla, E_prev, F_prev, f_cell, f_face, bc, *osol)
     oref = OL.solve_grey(prob.nx, prob.ny, prob.lx, prob.ly, c, c_dt, ocoef)
     _compare(grey, tuple(x[None] for x in oref), "grey chain vs oracle")
+
+
+# ---------------------------------------------------------------------------
+# the grey problem with the energy balance, eq. (5)-(6)
+# ---------------------------------------------------------------------------
+
+def _gpu_meb(lc, geo, coefs, T_prev, c_v, a_R, newton_tol=1e-11, max_newton=50):
+    """lc_loqd_grey_meb over independent grey problems (one per entry of
+    coefs, oracle layouts), T starting at T_prev.  Returns (T, E_cell,
+    E_face, F_face) [problems][...] and the Newton iterations."""
+    import torch
+    nx, ny, lx, ly, c, c_dt = geo
+    G = len(coefs)
+    h = lc.Loqd(nx, ny, lx, ly, G)
+    st = lambda key, f=(lambda a: a): _dev(np.stack([f(cf[key]) for cf in coefs]))
+    z = lambda n: torch.zeros(n, dtype=torch.float64, device="cuda")
+    T = _dev(np.stack(T_prev))
+    Ec, Ef, Ff = z(G * h.cells), z(G * h.nf), z(G * h.nf)
+    nit, it, res = lc.lc_loqd_grey_meb(h, c, c_dt, st("kappa_E"), st("kappa_B"), st("E_prev"),
+                                       st("k_side", lambda a: a.T), st("eta_side", lambda a: a.T), st("F_prev"),
+                                       st("f_cell"), st("f_face"), st("bc"), _dev(np.stack(T_prev)), c_v, a_R, T,
+                                       Ec, Ef, Ff, newton_tol=newton_tol, max_newton=max_newton)
+    out = tuple(x.cpu().numpy().reshape(G, -1) for x in (T, Ec, Ef, Ff))
+    return out, nit
+
+
+def test_grey_meb_matches_the_oracle(lcmod):
+    """Grey coefficients of a multigroup solution on a 33 x 20 grid (several
+    reduction blocks, ragged tail), T^{n-1} in [0.05, 0.8] keV: T, E and F
+    of the library's Newton iteration against the oracle's, 1e-9 normwise,
+    and energy conserved by the library's solution."""
+    lc, _ = lcmod
+    from tests.test_oracle_loqd import A_R, C_V, _grey_meb_case, energy_defects
+    geo, coef, Ts = _grey_meb_case(seed=51, nx=33, ny=20, lx=3.3, ly=2.0)
+    _say("case grey energy balance 33x20")
+    ref = OL.solve_grey_meb(*geo, coef, Ts, C_V, A_R, tol=1e-12)
+    got, nit = _gpu_meb(lc, geo, [coef], [Ts], C_V, A_R)
+    _say(f"  Newton iterations: library {nit}, oracle {ref[4]}")
+    assert abs(nit - ref[4]) <= 1
+    _compare(got, tuple(x[None] for x in ref[:4]), "grey energy balance")
+    gained, inflow, meb = energy_defects(geo, coef, Ts, got[0][0], got[1][0], got[3][0], C_V, A_R)
+    _say(f"  energy gained {gained:.6e} vs boundary inflow {inflow:.6e}; energy-balance residual {meb:.1e}")
+    assert math.isclose(gained, inflow, rel_tol=1e-8) and meb <= 1e-9
+
+
+def test_grey_meb_independent_problems(lcmod):
+    """Three problems in one handle (G = 3), one of them starting far from
+    its solution, each against its own oracle solve."""
+    lc, _ = lcmod
+    from tests.test_oracle_loqd import A_R, C_V, _grey_meb_case
+    cases = [_grey_meb_case(seed=s, nx=14, ny=9, lx=1.4, ly=0.9) for s in (61, 62, 63)]
+    geo = cases[0][0]
+    coefs = [cs[1] for cs in cases]
+    T_prev = [cs[2] for cs in cases]
+    T_prev[2] = np.full_like(T_prev[2], 0.001)           # cold matter under the inflow
+    _say("case grey energy balance 14x9, three problems")
+    got, nit = _gpu_meb(lc, geo, coefs, T_prev, C_V, A_R)
+    for g in range(3):
+        ref = OL.solve_grey_meb(*geo, coefs[g], T_prev[g], C_V, A_R, tol=1e-12)
+        _compare(tuple(x[g:g + 1] for x in got), tuple(x[None] for x in ref[:4]), f"problem {g}")
+
+
+def test_grey_meb_whole_chain(lcmod):
+    """Transport sweep, moments, multigroup LOQD, grey coefficients and the
+    grey problem with the energy balance all in the library on the 16 x 16
+    workload (c_v = 0.5917 a_R keV^-3 material), against the same chain in
+    the oracle; the library's result conserves energy."""
+    import torch
+    lc, driver = lcmod
+    from tests.test_oracle_loqd import A_R, C_V, energy_defects
+    prob = W.config(0)
+    _say("case grey energy balance whole chain 16x16 G=4")
+    s = driver.Solver(prob, prec=lc.LC_F64)
+    s.enable_faces()
+    s.reset()
+    s.step_faces(1)
+    G, N = prob.G, prob.cells
+    c, c_dt, kap, pla, E_prev, F_prev = _loqd_inputs(prob)
+    h = lc.Loqd(prob.nx, prob.ny, prob.lx, prob.ly, G)
+    z = lambda n: torch.zeros(n, dtype=torch.float64, device="cuda")
+    Ec, Ef, Ff = z(G * N), z(G * h.nf), z(G * h.nf)
+    kd, pd, epd, fpd = s.kappa[0].reshape(-1), s.planck[0].reshape(-1), _dev(E_prev), _dev(F_prev)
+    lc.lc_loqd_solve(h, c, c_dt, kd, pd, epd, fpd, s.f, s.ff, s.bnd, Ec, Ef, Ff)
+    out = dict(sigma=z(N), source=z(N), E_prev=z(N), k_side=z(4 * N), eta_side=z(4 * N), F_prev=z(h.nf),
+               f_cell=z(3 * N), f_face=z(3 * h.nf), bc=z(3 * h.nb), kappa_E=z(N), kappa_B=z(N))
+    lc.lc_loqd_grey_coefficients(h, c, c_dt, kd, pd, epd, fpd, s.f, s.ff, s.bnd, Ec, Ef, Ff, out)
+    hg = lc.Loqd(prob.nx, prob.ny, prob.lx, prob.ly, 1)
+    Ts = np.asarray(prob.T[0], dtype=np.float64)
+    T = _dev(Ts)
+    gE, gEf, gF = z(N), z(hg.nf), z(hg.nf)
+    nit, _, _ = lc.lc_loqd_grey_meb(hg, c, c_dt, out["kappa_E"], out["kappa_B"], out["E_prev"], out["k_side"],
+                                    out["eta_side"], out["F_prev"], out["f_cell"], out["f_face"], out["bc"],
+                                    _dev(Ts), C_V, A_R, T, gE, gEf, gF, newton_tol=1e-11)
+    got = tuple(x.cpu().numpy()[None] for x in (T, gE, gEf, gF))
+    # the oracle's chain
+    _, f, ff, bnd = _oracle_transport_closures(prob)
+    f_cell, f_face, bc = OL.closures_from_transport(prob.nx, prob.ny, f, ff, bnd)
+    osol = OL.solve(prob.nx, prob.ny, prob.lx, prob.ly, c, c_dt, kap, pla, E_prev, F_prev, f_cell, f_face, bc)
+    ocoef = OL.grey_coefficients(prob.nx, prob.ny, c, c_dt, kap, pla, E_prev, F_prev, f_cell, f_face, bc, *osol)
+    geo = (prob.nx, prob.ny, prob.lx, prob.ly, c, c_dt)
+    ref = OL.solve_grey_meb(*geo, ocoef, Ts, C_V, A_R, tol=1e-12)
+    _say(f"  Newton iterations: library {nit}, oracle {ref[4]}")
+    _compare(got, tuple(x[None] for x in ref[:4]), "grey energy balance chain")
+    gained, inflow, meb = energy_defects(geo, ocoef, Ts, got[0][0], got[1][0], got[3][0], C_V, A_R)
+    _say(f"  energy gained {gained:.6e} vs boundary inflow {inflow:.6e}; energy-balance residual {meb:.1e}")
+    assert math.isclose(gained, inflow, rel_tol=1e-8) and meb <= 1e-9
+
+
+def test_grey_meb_is_deterministic_and_reports_non_convergence(lcmod):
+    lc, _ = lcmod
+    from tests.test_oracle_loqd import A_R, C_V, _grey_meb_case
+    geo, coef, Ts = _grey_meb_case(seed=71, nx=12, ny=7, lx=1.2, ly=0.7)
+    a, _ = _gpu_meb(lc, geo, [coef], [Ts], C_V, A_R)
+    b, _ = _gpu_meb(lc, geo, [coef], [Ts], C_V, A_R)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    with pytest.raises(lc.LcError) as e:
+        _gpu_meb(lc, geo, [coef], [Ts], C_V, A_R, newton_tol=0.0, max_newton=1)
+    assert e.value.status == lc.LC_ERR_UNSUPPORTED

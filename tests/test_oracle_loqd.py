@@ -439,3 +439,112 @@ def test_planted_grey_mistake_is_caught(monkeypatch):
     monkeypatch.setattr(loqd, "grey_coefficients", _eta_on_cell_energy)
     with pytest.raises(AssertionError):
         test_grey_solution_is_the_sum_of_the_group_solutions(21)
+
+
+# ---------------------------------------------------------------------------
+# effective grey problem with the energy balance, eq. (5)-(6)
+# ---------------------------------------------------------------------------
+
+A_R = W.A_RAD
+C_V = 0.5917 * A_R          # eps = c_v T with c_v = 0.5917 a_R (1 keV)^3
+
+
+def _grey_meb_case(seed=41, nx=10, ny=8, lx=1.0, ly=0.8):
+    """Grey coefficients from a multigroup solution of physically shaped
+    data (Fleck-Cummings opacity and group Planck functions of a random
+    temperature field, inflow at x = 0)."""
+    rng = np.random.default_rng(seed)
+    Ts = rng.uniform(0.05, 0.8, nx * ny)
+    p = W.make_problem(nx, ny, lx, ly, 8, 2, 5, 0.001, 20.0, 0.05, 0.6, [Ts], name="meb")
+    c = W.C_LIGHT
+    nf = loqd.n_faces(nx, ny)
+    E_prev = 4 * math.pi * p.planck[0] / c
+    F_prev = np.zeros((p.G, nf))
+    G, N = p.G, nx * ny
+    f_cell = np.zeros((G, 3, N)); f_cell[:, 0] = f_cell[:, 2] = 1 / 3
+    f_face = np.zeros((G, 3, nf)); f_face[:, 0] = f_face[:, 2] = 1 / 3
+    nb = 2 * (nx + ny)
+    bc = np.zeros((G, nb, 3)); bc[:, :, 0] = 0.5
+    bc[:, :ny, 1] = 2 * math.pi * W.group_planck(p.edges, np.array([1.0]))[:, 0][:, None]   # x = 0: Phi^-
+    bc[:, :ny, 2] = 0.5 * bc[:, :ny, 1]                                                     # J^- = Phi^-/2
+    args = (nx, ny, lx, ly, c, p.c_dt, p.kappa[0], p.planck[0], E_prev, F_prev, f_cell, f_face, bc)
+    sol = loqd.solve(*args)
+    coef = loqd.grey_coefficients(nx, ny, c, p.c_dt, p.kappa[0], p.planck[0], E_prev, F_prev, f_cell, f_face, bc,
+                                  *sol)
+    return (nx, ny, lx, ly, c, p.c_dt), coef, Ts
+
+
+def energy_defects(geo, coef, T_prev, T, E, F, c_v, a_R):
+    """(energy gained by matter and radiation over the step, energy that
+    crossed the boundary in it, the largest cell residual of the energy
+    balance relative to c_v T / dt) of a solution of the grey problem."""
+    nx, ny, lx, ly, c, c_dt = geo
+    dt = c_dt / c
+    hx, hy = lx / nx, ly / ny
+    gained = np.sum(c_v * (T - T_prev) + (E - coef["E_prev"])) * hx * hy
+    nint = loqd.n_interior(nx, ny)
+    sgn = np.concatenate([-np.ones(ny), np.ones(ny), -np.ones(nx), np.ones(nx)])
+    lens = np.concatenate([np.full(ny, hy), np.full(ny, hy), np.full(nx, hx), np.full(nx, hx)])
+    inflow = -dt * np.sum(sgn * F[nint:] * lens)
+    meb = c_v * (T - T_prev) / dt - (c * coef["kappa_E"] * E - c * coef["kappa_B"] * a_R * T ** 4)
+    return gained, inflow, np.max(np.abs(meb)) / np.max(np.abs(c_v * T / dt))
+
+
+def test_grey_energy_balance_conserves_energy():
+    """Summed over the cells, the change of material plus radiation energy
+    over the step equals the energy that crosses the boundary (discrete
+    balance and energy balance add up exactly once Newton has converged)."""
+    geo, coef, Ts = _grey_meb_case()
+    nx, ny, lx, ly, c, c_dt = geo
+    T, E, Ef, F, it = loqd.solve_grey_meb(*geo, coef, Ts, C_V, A_R)
+    assert it < 20
+    gained, inflow, meb = energy_defects(geo, coef, Ts, T, E, F, C_V, A_R)
+    assert math.isclose(gained, inflow, rel_tol=1e-9, abs_tol=1e-12 * np.sum(C_V * T) * geo[2] * geo[3] / Ts.size)
+    # and the energy balance of every cell holds with the converged T
+    assert meb <= 1e-9
+
+
+def test_grey_energy_balance_keeps_equilibrium():
+    """Uniform temperature, radiation in equilibrium with it, and an
+    isotropic equilibrium boundary: nothing changes."""
+    nx, ny, lx, ly = 6, 5, 1.2, 1.0
+    c, c_dt, Teq = W.C_LIGHT, 0.6, 0.37
+    N, nf, nb = nx * ny, loqd.n_faces(nx, ny), 2 * (nx + ny)
+    Eeq = A_R * Teq ** 4
+    kap = np.linspace(0.5, 20.0, N)
+    coef = dict(kappa_E=kap, kappa_B=kap, E_prev=np.full(N, Eeq), k_side=np.repeat((kap + 1 / c_dt)[:, None], 4, 1),
+                eta_side=np.zeros((N, 4)), F_prev=np.zeros(nf), f_cell=np.array([np.full(N, 1 / 3), np.zeros(N),
+                                                                                  np.full(N, 1 / 3)]),
+                f_face=np.array([np.full(nf, 1 / 3), np.zeros(nf), np.full(nf, 1 / 3)]),
+                bc=np.stack([np.full(nb, 0.5), np.full(nb, c * Eeq / 2), np.full(nb, c * Eeq / 4)], axis=1))
+    T, E, Ef, F, it = loqd.solve_grey_meb(nx, ny, lx, ly, c, c_dt, coef, np.full(N, Teq), C_V, A_R)
+    assert np.allclose(T, Teq, rtol=1e-13) and np.allclose(E, Eeq, rtol=1e-12) and np.allclose(Ef, Eeq, rtol=1e-12)
+    assert np.max(np.abs(F)) <= 1e-12 * c * Eeq
+
+
+def test_grey_energy_balance_with_infinite_heat_capacity():
+    """c_v -> infinity: the temperature cannot move, and E is the solution
+    of the grey equations with the emission of the fixed temperature."""
+    geo, coef, Ts = _grey_meb_case(seed=43)
+    nx, ny, lx, ly, c, c_dt = geo
+    T, E, Ef, F, it = loqd.solve_grey_meb(*geo, coef, Ts, 1e30, A_R)
+    assert np.allclose(T, Ts, rtol=1e-12)
+    source = c * coef["E_prev"] / c_dt + c * coef["kappa_B"] * A_R * Ts ** 4
+    e, ef, ff = loqd.solve_general(nx, ny, lx, ly, c, c_dt, coef["sigma"], source, coef["k_side"],
+                                   coef["eta_side"], coef["F_prev"], coef["f_cell"], coef["f_face"], coef["bc"])
+    assert np.allclose(E, e, rtol=1e-10) and np.allclose(F, ff, rtol=1e-9, atol=1e-12 * np.max(np.abs(ff)))
+
+
+def test_newton_converges_quadratically():
+    geo, coef, Ts = _grey_meb_case(seed=44)
+    changes = []
+    T = Ts.copy()
+    for k in range(1, 7):
+        Tk, *_ = loqd.solve_grey_meb(*geo, coef, Ts, C_V, A_R, T_start=Ts, max_newton=k, tol=0.0)
+        changes.append(np.max(np.abs(Tk - T) / np.abs(Tk)))
+        T = Tk
+    # successive changes fall quadratically once in the basin (a Newton
+    # step with a wrong derivative falls only linearly)
+    for a, b in zip(changes[1:4], changes[2:5]):
+        assert b <= 4 * a * a
+    assert changes[5] < 1e-14
