@@ -17,7 +17,14 @@ of long characteristics:
                  segment-average intensities;
 * ``moments`` -- eq. (7), (14)-(16): area-weighted cell averages, the angular
                  moments E, F and the Eddington tensor, plus boundary factors;
-* ``solve``   -- the time loop with prescribed material data.
+* ``solve``   -- the time loop with prescribed material data;
+* ``faces``, ``closures`` -- face-average Eddington tensors (eq. (16)) and
+                 the grey spectrum averages of eq. (8)-(9);
+* ``loqd``    -- the multigroup and effective grey low-order equations,
+                 eq. (4)-(6), in a finite-volume reading;
+* ``material``, ``mlqd`` -- the Fleck-Cummings material and one time step
+                 of the multilevel method (transport, multigroup and grey
+                 levels, iterated).
 
 Parity pins (tests/test_oracle_*.py) tie every function to what the paper and
 the mathematics fix; the functions with no such pin say "parity unpinned" in

@@ -35,7 +35,7 @@ __all__ = [
     "group_edges", "group_midpoints", "fc_opacity", "planck_integral_0x",
     "group_planck", "boundary_faces", "inflow_left_planck",
     "t_field_iid", "t_field_gaussians", "t_field_front", "make_problem",
-    "config", "batch_problems",
+    "config", "batch_problems", "FcMlqd", "open_group_edges", "fc_mlqd",
 ]
 
 
@@ -120,8 +120,11 @@ def _planck_series(x: np.ndarray) -> np.ndarray:
 def _planck_tail(x: np.ndarray) -> np.ndarray:
     # int_x^inf t^3/(e^t - 1) dt = sum_n e^(-n x) (x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4)
     out = np.zeros_like(x)
+    fin = np.isfinite(x)
+    xf = np.where(fin, x, 0.0)
     for n in range(1, 26):
-        out += np.exp(-n * x) * (x ** 3 / n + 3 * x ** 2 / n ** 2 + 6 * x / n ** 3 + 6 / n ** 4)
+        out += np.where(fin, np.exp(-n * xf) * (xf ** 3 / n + 3 * xf ** 2 / n ** 2 + 6 * xf / n ** 3 + 6 / n ** 4),
+                        0.0)
     return out
 
 
@@ -379,3 +382,87 @@ def batch_problems(n_problems=64, steps=5, seed=SEED0 + 3, only=None):
         out.append(make_problem(N, N, L, L, n_az, n_pol, G, 0.001, 30.0,
                                 L / N / 2, 3.0, [T] * steps, name=f"b{j}"))
     return out
+
+
+# ---------------------------------------------------------------------------
+# the Fleck-Cummings problem of the multilevel method's time steps
+# ---------------------------------------------------------------------------
+
+def open_group_edges(G: int, nu_lo: float, nu_hi: float) -> np.ndarray:
+    """G + 1 edges covering the whole spectrum: 0, then G - 1 log-spaced
+    edges from nu_lo to nu_hi, then infinity (so that the group Planck
+    functions sum to a_R c T^4 / 4 pi exactly)."""
+    e = np.empty(G + 1)
+    e[0] = 0.0
+    e[1:G] = group_edges(G - 2, nu_lo, nu_hi) if G > 2 else [nu_lo]
+    e[G] = math.inf
+    return e
+
+
+@dataclass
+class FcMlqd:
+    """The Fleck-Cummings problem as the multilevel method's time steps take
+    it: a 6 x 6 cm slab of cells h_mat wide, opacity 27/nu^3 (1 - e^(-nu/T))
+    at the representative frequencies nu, eps = c_v T with
+    c_v = 0.5917 a_R keV^-3, T^0 = 1 eV, the Planckian of T_in = 1 keV
+    entering at x = 0, vacuum elsewhere."""
+    nx: int
+    ny: int
+    lx: float
+    ly: float
+    phi: np.ndarray
+    mu: np.ndarray
+    omega: np.ndarray
+    edges: np.ndarray          # [G + 1] keV, 0 and inf at the ends
+    nu: np.ndarray             # [G] representative frequencies of the opacity
+    h_moc: float
+    c_dt: float
+    c_v: float
+    T0: float
+    T_in: float
+    I_in: np.ndarray           # [nb][M][G]
+    state0: np.ndarray         # [G][cells]: B_g(T^0)
+    name: str = ""
+
+    @property
+    def G(self):
+        return len(self.nu)
+
+    @property
+    def cells(self):
+        return self.nx * self.ny
+
+    @property
+    def n_pol(self):
+        return len(self.mu)
+
+    @property
+    def kappa0(self):
+        return fc_opacity(self.nu, np.full(self.cells, self.T0))
+
+    @property
+    def planck0(self):
+        return self.state0
+
+
+def fc_mlqd(h_mat: float, h_moc: float, n_az: int = 36, n_pol: int = 4, G: int = 17, nu_lo: float = 0.01,
+            nu_hi: float = 20.0, dt_ns: float = 0.02, L: float = 6.0, name: str = "") -> FcMlqd:
+    """Representative frequencies: arithmetic midpoints of the finite groups,
+    half the upper edge for [0, nu_lo], the lower edge for [nu_hi, inf).
+    Default 36 x 4 = 144 directions and 17 groups, the paper's counts, and
+    Delta t = 0.02 ns."""
+    n = int(round(L / h_mat))
+    if n < 1 or abs(n * h_mat - L) > 1e-9 * L:
+        raise ValueError("h_mat must divide the 6 cm slab")
+    phi, mu, omega = product_quadrature(n_az, n_pol)
+    edges = open_group_edges(G, nu_lo, nu_hi)
+    nu = np.empty(G)
+    nu[0] = 0.5 * edges[1]
+    nu[1:G - 1] = 0.5 * (edges[1:G - 1] + edges[2:G])
+    nu[G - 1] = edges[G - 1]
+    T0, T_in = 0.001, 1.0
+    c_dt = C_LIGHT * dt_ns * 0.1          # 1 shake = 10 ns
+    I_in = inflow_left_planck(n, n, phi, mu, edges, T_in)
+    s0 = np.repeat(group_planck(edges, np.array([T0])), n * n, axis=1)
+    return FcMlqd(n, n, L, L, phi, mu, omega, edges, nu, h_moc, c_dt, 0.5917 * A_RAD, T0, T_in, I_in, s0,
+                  name or f"fc_{n}x{n}")
