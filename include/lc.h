@@ -472,6 +472,81 @@ lc_status lc_loqd_grey_meb(lc_loqd_t loqd, double c, double c_dt, const double* 
                            int32_t* newton_iters, int32_t* iters, double* resid, void* stream);
 
 /*
+ * lc_loqd_set_warm_start -- with enable != 0, every later solve on the
+ * handle (lc_loqd_solve, lc_loqd_solve_general and each Newton iteration
+ * of lc_loqd_grey_meb) starts BiCGSTAB from the current contents of its
+ * E_face output (which must then hold finite values) instead of zero; the
+ * solution is the same within rtol, reached in fewer iterations when the
+ * system changed little since the last solve.  Errors: LC_ERR_STATE.
+ */
+lc_status lc_loqd_set_warm_start(lc_loqd_t loqd, int32_t enable);
+
+/*
+ * Multilevel quasidiffusion (MLQD) time steps on the Fleck-Cummings test
+ * material of the paper's results section: opacity 27/nu^3 (1 - e^(-nu/T))
+ * at each group's representative frequency nu_g, material energy
+ * eps = c_v T.  One step composes the paper's three levels:
+ *   1. the transport sweep (eq. (10)-(13)) from the state of step n-1 with
+ *      kappa_g, B_g of the current temperature, giving the cell and face
+ *      Eddington tensors and the boundary factors;
+ *   2. the multigroup LOQD equations, eq. (4), closed by them;
+ *   3. the effective grey problem, eq. (5)-(6), closed by the spectrum
+ *      averages of eq. (8)-(9),
+ * iterated: an outer (transport) iteration s forms the closures with the
+ * material of T^(s); inner (low-order) iterations, closures fixed,
+ * evaluate kappa_g, B_g at the newest temperature and solve 2. then 3. for
+ * the next, until max_i |T_new - T| / T_new <= eps or max_inner
+ * iterations; the step ends when, between transport sweeps, the
+ * temperature changes by at most eps (relative, every cell) and the grey
+ * cell energy by at most eps (max |dE| / max |E|).  T^(0) = T^{n-1}.
+ * B_g(T) = (a_R c T^4 / 4 pi)(15/pi^4) int over [nu_{g-1}/T, nu_g/T] of
+ * x^3/(e^x - 1) dx (per steradian, the 4 pi kappa B of eq. (4a)).
+ *
+ * lc_mlqd_create -- for a plan (its grid, quadrature, characteristic grid
+ * and G; interior-face lists are enabled on it, as lc_plan_enable_faces):
+ * nu [G] (host, keV, > 0) the opacity frequencies; edges [G + 1] (host,
+ * keV, increasing, edges[0] >= 0, only edges[G] may be +infinity: with 0
+ * and infinity the groups sum to a_R c T^4 / 4 pi); c, c_v, a_R > 0 in the
+ * units of the rest (c_v: energy per volume and temperature).  Allocates
+ * the step's work buffers (a state-sized buffer for the face crossings,
+ * the closures, two LOQD handles with warm starts, the grey coefficients)
+ * and synchronises the device.  Errors: LC_ERR_ARG, LC_ERR_STATE,
+ * LC_ERR_ALLOC, LC_ERR_HIP.
+ *
+ * lc_mlqd_material -- kappa_g(T), B_g(T) [G][cells] (device, float64) for
+ * T [cells] (device, > 0), as the step evaluates them.  Allocates and
+ * synchronises nothing.
+ *
+ * lc_mlqd_step -- one time step of c_dt (> 0).  Inputs (device): the
+ * transport state of step n-1 (state_prev; state_new receives the last
+ * sweep's, distinct buffers of lc_state_bytes), I_in [nb][M][G] as for
+ * lc_sweep, T_prev [cells], E_prev [G][cells] and F_prev [G][nf] (the
+ * multigroup low-order solution of step n-1; face numbering of
+ * lc_loqd_solve).  Outputs (device, float64): T [cells]; the multigroup
+ * E_cell [G][cells], E_face, F_face [G][nf] of the last inner iteration
+ * (the next step's E_prev and F_prev: use other buffers); E_grey [cells]
+ * (may be NULL) the grey cell energy.  outer_iters, inner_iters (total),
+ * changes [2] (the last dT, dE) may be NULL.  Inner solves: BiCGSTAB to
+ * rtol 1e-13, Newton to max(min(eps, 1e-11), 1e-13).  eps much below 1e-12
+ * may not be reachable in float64.  Synchronises the stream many times.
+ * Errors: LC_ERR_ARG (NULL, aliased states, c_dt or eps not finite or
+ * <= 0, max_outer or max_inner < 1), LC_ERR_STATE, LC_ERR_UNSUPPORTED (an
+ * inner solve failed, or the step did not converge within max_outer
+ * transport iterations: the outputs then hold the last iterates),
+ * LC_ERR_HIP.
+ */
+typedef struct lc_mlqd_s* lc_mlqd_t;
+lc_status lc_mlqd_create(lc_plan_t plan, const double* nu, const double* edges, double c, double c_v,
+                         double a_R, lc_mlqd_t* out);
+lc_status lc_mlqd_free(lc_mlqd_t mlqd);
+lc_status lc_mlqd_material(lc_mlqd_t mlqd, const double* T, double* kappa, double* planck, void* stream);
+lc_status lc_mlqd_step(lc_mlqd_t mlqd, double c_dt, const void* state_prev, void* state_new,
+                       const double* I_in, const double* T_prev, const double* E_prev,
+                       const double* F_prev, double* T, double* E_cell, double* E_face, double* F_face,
+                       double* E_grey, double eps, int32_t max_outer, int32_t max_inner,
+                       int32_t* outer_iters, int32_t* inner_iters, double* changes, void* stream);
+
+/*
  * lc_step -- n_steps backward-Euler time steps (sweep, then moments) with the
  * state ping-ponging between state_a and state_b: step t reads the state
  * written by step t-1 (step 0 reads state_a); after an odd number of steps

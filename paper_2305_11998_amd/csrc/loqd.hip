@@ -81,6 +81,7 @@ struct Loqd {
     double* d_part = nullptr;         // [G][nblk][2] block partial sums
     double* d_sc = nullptr;           // [G][kScal] per-group scalars
     int* d_flag = nullptr;            // [G] 1 = iterating
+    bool warm = false;                // BiCGSTAB starts from the E_face output's contents
     std::vector<void*> owned;
 };
 
@@ -648,7 +649,9 @@ lc_status solve_general(Loqd* q, const Geo& Q, const Gen& Cg, double* E_cell, do
     };
     lc_status rc = set_flags(flag);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_bi_init, gf, blk, 0, st, Q, q->d_val, q->d_b, V, q->d_flag, q->d_part, nblk, 0);
+    if (q->warm) LC_HIP(hipMemcpyAsync(V.x, E_face, GF * sizeof(double), hipMemcpyDeviceToDevice, st));
+    hipLaunchKernelGGL(k_bi_init, gf, blk, 0, st, Q, q->d_val, q->d_b, V, q->d_flag, q->d_part, nblk,
+                       q->warm ? 1 : 0);
     hipLaunchKernelGGL(k_bi_scalars, dim3(G), blk, 0, st, q->d_part, nblk, q->d_sc, q->d_flag, 0, rtol);
     LC_HIP(hipGetLastError());
     // (Re)start the groups selected by sel: r = b - A x, rh = r, p = v = 0;
@@ -806,6 +809,13 @@ lc_status lc_loqd_create(int32_t nx, int32_t ny, double lx, double ly, int32_t G
     }
     q->magic = kLoqdMagic;
     *out = reinterpret_cast<lc_loqd_t>(q);
+    return LC_OK;
+}
+
+lc_status lc_loqd_set_warm_start(lc_loqd_t h, int32_t enable) {
+    Loqd* q = as_loqd(h);
+    LC_CHECK(q, LC_ERR_STATE, "invalid LOQD handle");
+    q->warm = enable != 0;
     return LC_OK;
 }
 

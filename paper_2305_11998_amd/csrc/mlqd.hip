@@ -1,0 +1,386 @@
+// One backward-Euler time step of the multilevel quasidiffusion (MLQD)
+// method on the Fleck-Cummings test material: the transport equation by
+// long characteristics (eq. (10)-(13)) closes the multigroup LOQD equations
+// (eq. (4)) through the cell and face Eddington tensors and the boundary
+// factors; their solution closes the effective grey problem (eq. (5)-(6),
+// averages of eq. (8)-(9)), whose temperature feeds the opacities and
+// Planck functions of the next iteration.
+//
+// Iterations (T^(0) = T^{n-1}): an outer (transport) iteration sweeps from
+// the state of step n-1 with kappa_g, B_g of T^(s) and forms the closures;
+// inner (low-order) iterations then, with those closures fixed, evaluate
+// kappa_g, B_g at the newest temperature, solve the multigroup equations,
+// form the grey coefficients and solve the grey problem for the next
+// temperature, until it changes by at most eps (relative, every cell).  The
+// outer iteration ends when the temperature and the grey cell energy
+// change by at most eps between transport sweeps.
+//
+// Material: kappa_g(T) = 27/nu_g^3 (1 - e^(-nu_g/T)) at each group's
+// representative frequency, B_g(T) = (a_R c T^4 / 4 pi)(15/pi^4) times the
+// integral of x^3/(e^x - 1) over the group's [nu_{g-1}/T, nu_g/T]: a
+// Bernoulli series below x = 2, the exponential tail series
+// sum_n e^(-n x)(x^3/n + 3x^2/n^2 + 6x/n^3 + 6/n^4) above, so that no
+// difference of large integrals is formed in the Wien tail.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "lc_internal.hpp"
+
+namespace lc {
+
+constexpr uint32_t kMlqdMagic = 0x4c434d51u;   // "LCMQ"
+constexpr int kMlqdBlock = 256;
+constexpr int kBern = 41;                      // series terms k = 0 .. 40
+constexpr double kMPi = 3.14159265358979323846;
+
+struct Mlqd {
+    uint32_t magic = 0;
+    lc_plan_t plan = nullptr;
+    Plan* pl = nullptr;
+    int G = 0, N = 0, nint = 0, nf = 0, nb = 0, nblk = 0;
+    double c = 0, c_v = 0, a_R = 0, pref = 0;
+    size_t state_bytes = 0;
+    lc_loqd_t mg = nullptr, grey = nullptr;
+    double* d_nu = nullptr;       // [G]
+    double* d_edges = nullptr;    // [G + 1]
+    double* d_bern = nullptr;     // [kBern] B_k / k!
+    double* d_kappa = nullptr;    // [G][N]
+    double* d_planck = nullptr;   // [G][N]
+    void* d_points = nullptr;     // a state-sized buffer
+    double* d_exit = nullptr;     // [n_rays][2][n_pol][G]
+    double* d_f = nullptr;        // [N][4][G]
+    double* d_bnd = nullptr;      // [G][nb][8]
+    double* d_ff = nullptr;       // [nint][4][G]
+    // grey coefficients
+    double *d_sigma = nullptr, *d_src = nullptr, *d_ep = nullptr, *d_kE = nullptr, *d_kB = nullptr;
+    double *d_ks = nullptr, *d_es = nullptr, *d_fp = nullptr, *d_fc = nullptr, *d_ffg = nullptr, *d_bc = nullptr;
+    // grey solution and temperature iterates
+    double *d_Eg = nullptr, *d_Egf = nullptr, *d_Fgf = nullptr, *d_Eg_old = nullptr;
+    double *d_Ts = nullptr, *d_Tl = nullptr, *d_Tn = nullptr;
+    double* d_part = nullptr;     // [nblk][2] block maxima
+    std::vector<void*> owned;
+};
+
+inline Mlqd* as_mlqd(lc_mlqd_t h) {
+    Mlqd* p = reinterpret_cast<Mlqd*>(h);
+    return (p && p->magic == kMlqdMagic) ? p : nullptr;
+}
+
+namespace {
+
+// int_0^x t^3/(e^t - 1) dt = sum_k b_k x^(k+3)/(k+3), b_k = B_k/k!, x < 2
+__device__ double planck_series(double x, const double* __restrict__ b) {
+    double s = 0.0, xp = x * x * x;
+    for (int k = 0; k < kBern; ++k) {
+        s += b[k] * xp / (k + 3);
+        xp *= x;
+    }
+    return s;
+}
+
+// int_x^inf t^3/(e^t - 1) dt, x >= 2 (0 at infinity); smallest terms first
+__device__ double planck_tail(double x) {
+    if (!std::isfinite(x)) return 0.0;
+    const double x2 = x * x, x3 = x2 * x;
+    double s = 0.0;
+    for (int n = 25; n >= 1; --n) {
+        const double dn = n;
+        s += exp(-dn * x) * (x3 / dn + 3.0 * x2 / (dn * dn) + 6.0 * x / (dn * dn * dn) + 6.0 / (dn * dn * dn * dn));
+    }
+    return s;
+}
+
+__device__ double group_integral(double x1, double x2, const double* b) {
+    const double total = kMPi * kMPi * kMPi * kMPi / 15.0;
+    if (x1 >= 2.0) return planck_tail(x1) - planck_tail(x2);
+    if (x2 < 2.0) return planck_series(x2, b) - planck_series(x1, b);
+    return (total - planck_tail(x2)) - planck_series(x1, b);
+}
+
+__global__ void k_fc_material(int G, int N, const double* __restrict__ nu, const double* __restrict__ edges,
+                              const double* __restrict__ bern, double pref, const double* __restrict__ T,
+                              double* kappa, double* planck) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int g = blockIdx.y;
+    if (i >= N || g >= G) return;
+    const double t = T[i], v = nu[g];
+    const size_t gi = (size_t)g * N + i;
+    kappa[gi] = 27.0 / (v * v * v) * -expm1(-v / t);
+    const double t2 = t * t;
+    planck[gi] = pref * t2 * t2 * group_integral(edges[g] / t, edges[g + 1] / t, bern);
+}
+
+// Per block: rel = 1: max |a - b| / |a|; rel = 0: max |a - b| and max |a|.
+// Not finite -> infinity.
+__global__ void k_change(int n, const double* __restrict__ a, const double* __restrict__ b, int rel, double* part) {
+    __shared__ double s0[kMlqdBlock], s1[kMlqdBlock];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double d = 0.0, m = 0.0;
+    if (i < n) {
+        const double x = a[i], y = b[i];
+        d = rel ? fabs(x - y) / fabs(x) : fabs(x - y);
+        m = fabs(x);
+        if (!std::isfinite(d)) d = INFINITY;
+    }
+    s0[threadIdx.x] = d;
+    s1[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kMlqdBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s0[threadIdx.x] = fmax(s0[threadIdx.x], s0[threadIdx.x + w]);
+            s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s0[0];
+        part[2 * blockIdx.x + 1] = s1[0];
+    }
+}
+
+// B_k / k! for k = 0..40 (B_1 = -1/2): b_1 = -1/2, b_odd = 0 beyond,
+// b_2m = (-1)^(m+1) 2 zeta(2m) / (2 pi)^(2m).
+std::vector<double> bernoulli_over_factorial() {
+    std::vector<double> b(kBern, 0.0);
+    b[0] = 1.0;
+    b[1] = -0.5;
+    const double two_pi = 2.0 * kMPi;
+    for (int m = 1; 2 * m < kBern; ++m) {
+        double zeta;
+        if (m == 1) {
+            zeta = kMPi * kMPi / 6.0;
+        } else if (m == 2) {
+            zeta = kMPi * kMPi * kMPi * kMPi / 90.0;
+        } else {
+            zeta = 0.0;                               // tail below 2000^(1-2m)/(2m-1) < 1e-16
+            for (int n = 2000; n >= 1; --n) zeta += std::pow((double)n, -2.0 * m);
+        }
+        b[2 * m] = (m % 2 ? 2.0 : -2.0) * zeta / std::pow(two_pi, 2.0 * m);
+    }
+    return b;
+}
+
+void free_mlqd(Mlqd* h) {
+    if (!h) return;
+    for (void* p : h->owned) (void)hipFree(p);
+    h->owned.clear();
+    if (h->mg) (void)lc_loqd_free(h->mg);
+    if (h->grey) (void)lc_loqd_free(h->grey);
+    h->magic = 0;
+    delete h;
+}
+
+lc_status material(Mlqd* h, const double* T, double* kappa, double* planck, hipStream_t st) {
+    const dim3 grid((h->N + kMlqdBlock - 1) / kMlqdBlock, h->G);
+    hipLaunchKernelGGL(k_fc_material, grid, dim3(kMlqdBlock), 0, st, h->G, h->N, h->d_nu, h->d_edges, h->d_bern,
+                       h->pref, T, kappa, planck);
+    LC_HIP(hipGetLastError());
+    return LC_OK;
+}
+
+// Largest change between a and b (see k_change); out[0] the change, out[1]
+// max |a|.  Synchronises the stream.
+lc_status change(Mlqd* h, const double* a, const double* b, int rel, double out[2], hipStream_t st) {
+    hipLaunchKernelGGL(k_change, dim3(h->nblk), dim3(kMlqdBlock), 0, st, h->N, a, b, rel, h->d_part);
+    LC_HIP(hipGetLastError());
+    std::vector<double> part(2 * (size_t)h->nblk);
+    LC_HIP(hipMemcpyAsync(part.data(), h->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    LC_HIP(hipStreamSynchronize(st));
+    out[0] = out[1] = 0.0;
+    for (int k = 0; k < h->nblk; ++k) {
+        out[0] = std::max(out[0], part[2 * k]);
+        out[1] = std::max(out[1], part[2 * k + 1]);
+    }
+    return LC_OK;
+}
+
+}  // namespace
+}  // namespace lc
+
+using namespace lc;
+
+extern "C" {
+
+lc_status lc_mlqd_create(lc_plan_t plan, const double* nu, const double* edges, double c, double c_v, double a_R,
+                         lc_mlqd_t* out) {
+    LC_ARG(out, "out must not be NULL");
+    *out = nullptr;
+    Plan* pl = as_plan(plan);
+    LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
+    LC_ARG(nu && edges, "nu and edges must not be NULL");
+    LC_ARG(std::isfinite(c) && c > 0.0 && std::isfinite(c_v) && c_v > 0.0 && std::isfinite(a_R) && a_R > 0.0,
+           "c, c_v and a_R must be finite and > 0");
+    const int G = pl->G;
+    for (int g = 0; g < G; ++g) LC_ARG(std::isfinite(nu[g]) && nu[g] > 0.0, "nu[%d] must be finite and > 0", g);
+    LC_ARG(edges[0] >= 0.0 && std::isfinite(edges[0]), "edges[0] must be finite and >= 0");
+    for (int g = 0; g < G; ++g)
+        LC_ARG(edges[g + 1] > edges[g] && (std::isfinite(edges[g + 1]) || g == G - 1),
+               "edges must increase; only the last may be infinite");
+    Rays* r = pl->rays;
+    Mlqd* h = new Mlqd();
+    h->plan = plan;
+    h->pl = pl;
+    h->G = G;
+    h->N = r->cells;
+    h->nint = (r->nx - 1) * r->ny + r->nx * (r->ny - 1);
+    h->nb = 2 * (r->nx + r->ny);
+    h->nf = h->nint + h->nb;
+    h->nblk = (h->N + kMlqdBlock - 1) / kMlqdBlock;
+    h->c = c;
+    h->c_v = c_v;
+    h->a_R = a_R;
+    h->pref = a_R * c / (4.0 * kMPi) * 15.0 / (kMPi * kMPi * kMPi * kMPi);
+    h->state_bytes = lc_state_bytes(plan);
+    const int N = h->N, nf = h->nf, nb = h->nb;
+    auto fail = [&](lc_status rc) {
+        free_mlqd(h);
+        return rc;
+    };
+    lc_status rc = lc_plan_enable_faces(plan, nullptr);
+    if (!rc) rc = lc_loqd_create(r->nx, r->ny, r->lx, r->ly, G, &h->mg);
+    if (!rc) rc = lc_loqd_create(r->nx, r->ny, r->lx, r->ly, 1, &h->grey);
+    if (rc) return fail(rc);
+    (void)lc_loqd_set_warm_start(h->mg, 1);
+    (void)lc_loqd_set_warm_start(h->grey, 1);
+    const size_t GN = (size_t)G * N;
+    std::vector<double> bern = bernoulli_over_factorial();
+    rc = dalloc(h->owned, &h->d_nu, (size_t)G);
+    if (!rc) rc = dalloc(h->owned, &h->d_edges, (size_t)G + 1);
+    if (!rc) rc = dalloc(h->owned, &h->d_bern, (size_t)kBern);
+    if (!rc) rc = dalloc(h->owned, &h->d_kappa, GN);
+    if (!rc) rc = dalloc(h->owned, &h->d_planck, GN);
+    if (!rc) rc = dalloc(h->owned, reinterpret_cast<unsigned char**>(&h->d_points), h->state_bytes);
+    if (!rc) rc = dalloc(h->owned, &h->d_exit, (size_t)r->n_rays * 2 * r->n_pol * G);
+    if (!rc) rc = dalloc(h->owned, &h->d_f, 4 * GN);
+    if (!rc) rc = dalloc(h->owned, &h->d_bnd, (size_t)G * nb * 8);
+    if (!rc) rc = dalloc(h->owned, &h->d_ff, 4 * (size_t)G * std::max(h->nint, 1));
+    for (double** p : {&h->d_sigma, &h->d_src, &h->d_ep, &h->d_kE, &h->d_kB, &h->d_Eg, &h->d_Eg_old, &h->d_Ts,
+                       &h->d_Tl, &h->d_Tn})
+        if (!rc) rc = dalloc(h->owned, p, (size_t)N);
+    if (!rc) rc = dalloc(h->owned, &h->d_ks, 4 * (size_t)N);
+    if (!rc) rc = dalloc(h->owned, &h->d_es, 4 * (size_t)N);
+    if (!rc) rc = dalloc(h->owned, &h->d_fc, 3 * (size_t)N);
+    if (!rc) rc = dalloc(h->owned, &h->d_fp, (size_t)nf);
+    if (!rc) rc = dalloc(h->owned, &h->d_ffg, 3 * (size_t)nf);
+    if (!rc) rc = dalloc(h->owned, &h->d_bc, 3 * (size_t)nb);
+    if (!rc) rc = dalloc(h->owned, &h->d_Egf, (size_t)nf);
+    if (!rc) rc = dalloc(h->owned, &h->d_Fgf, (size_t)nf);
+    if (!rc) rc = dalloc(h->owned, &h->d_part, 2 * (size_t)h->nblk);
+    if (rc) return fail(rc);
+    if (hipMemcpy(h->d_nu, nu, G * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_edges, edges, (G + 1) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(h->d_bern, bern.data(), kBern * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(h->d_Egf, 0, nf * sizeof(double)) != hipSuccess) {
+        set_error("HIP error uploading the material tables");
+        return fail(LC_ERR_HIP);
+    }
+    h->magic = kMlqdMagic;
+    *out = reinterpret_cast<lc_mlqd_t>(h);
+    return LC_OK;
+}
+
+lc_status lc_mlqd_free(lc_mlqd_t handle) {
+    if (!handle) return LC_OK;
+    Mlqd* h = as_mlqd(handle);
+    LC_CHECK(h, LC_ERR_STATE, "invalid MLQD handle");
+    free_mlqd(h);
+    return LC_OK;
+}
+
+lc_status lc_mlqd_material(lc_mlqd_t handle, const double* T, double* kappa, double* planck, void* stream) {
+    Mlqd* h = as_mlqd(handle);
+    LC_CHECK(h, LC_ERR_STATE, "invalid MLQD handle");
+    LC_ARG(T && kappa && planck, "T, kappa and planck must not be NULL");
+    return material(h, T, kappa, planck, static_cast<hipStream_t>(stream));
+}
+
+lc_status lc_mlqd_step(lc_mlqd_t handle, double c_dt, const void* state_prev, void* state_new, const double* I_in,
+                       const double* T_prev, const double* E_prev, const double* F_prev, double* T, double* E_cell,
+                       double* E_face, double* F_face, double* E_grey, double eps, int32_t max_outer,
+                       int32_t max_inner, int32_t* outer_iters, int32_t* inner_iters, double* changes, void* stream) {
+    Mlqd* h = as_mlqd(handle);
+    LC_CHECK(h, LC_ERR_STATE, "invalid MLQD handle");
+    LC_ARG(state_prev && state_new && I_in && T_prev && E_prev && F_prev && T && E_cell && E_face && F_face,
+           "inputs and outputs must not be NULL");
+    LC_ARG(state_prev != state_new, "state_prev and state_new must be distinct buffers");
+    LC_ARG(std::isfinite(c_dt) && c_dt > 0.0, "c_dt must be finite and > 0");
+    LC_ARG(std::isfinite(eps) && eps > 0.0, "eps must be finite and > 0");
+    LC_ARG(max_outer >= 1 && max_inner >= 1, "max_outer and max_inner must be >= 1");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int G = h->G, N = h->N, nf = h->nf;
+    const double c = h->c;
+    const double rtol = 1e-13;
+    const int max_iter = 20000;
+    const double newton_tol = std::max(std::min(eps, 1e-11), 1e-13);
+    const size_t bytesN = N * sizeof(double);
+    LC_HIP(hipMemcpyAsync(h->d_Ts, T_prev, bytesN, hipMemcpyDeviceToDevice, st));
+    LC_HIP(hipMemsetAsync(E_face, 0, (size_t)G * nf * sizeof(double), st));   // first multigroup solve: cold start
+    int s = 0, inner = 0;
+    double dT = INFINITY, dE = INFINITY;
+    lc_status rc = LC_OK;
+    auto report = [&]() {
+        if (outer_iters) *outer_iters = s;
+        if (inner_iters) *inner_iters = inner;
+        if (changes) {
+            changes[0] = dT;
+            changes[1] = dE;
+        }
+    };
+    while (s < max_outer) {
+        ++s;
+        // transport with the material of T^(s), closures
+        rc = material(h, h->d_Ts, h->d_kappa, h->d_planck, st);
+        if (!rc) rc = lc_sweep_points(h->plan, h->d_kappa, h->d_planck, c_dt, state_prev, state_new, I_in, h->d_exit,
+                                      h->d_points, st);
+        if (!rc) rc = lc_moments(h->plan, state_new, h->d_exit, I_in, c, nullptr, nullptr, h->d_f, h->d_bnd, st);
+        if (!rc && h->nint > 0)
+            rc = lc_face_moments(h->plan, h->d_points, state_new, c, nullptr, nullptr, h->d_ff, st);
+        if (rc) break;
+        // inner low-order iterations with these closures
+        LC_HIP(hipMemcpyAsync(h->d_Tl, h->d_Ts, bytesN, hipMemcpyDeviceToDevice, st));
+        for (int l = 0; l < max_inner; ++l) {
+            ++inner;
+            rc = material(h, h->d_Tl, h->d_kappa, h->d_planck, st);
+            if (!rc) rc = lc_loqd_solve(h->mg, c, c_dt, h->d_kappa, h->d_planck, E_prev, F_prev, h->d_f, h->d_ff,
+                                        h->d_bnd, E_cell, E_face, F_face, rtol, max_iter, nullptr, nullptr, st);
+            if (!rc) rc = lc_loqd_grey_coefficients(h->mg, c, c_dt, h->d_kappa, h->d_planck, E_prev, F_prev, h->d_f,
+                                                    h->d_ff, h->d_bnd, E_cell, E_face, F_face, h->d_sigma, h->d_src,
+                                                    h->d_ks, h->d_es, h->d_fp, h->d_fc, h->d_ffg, h->d_bc, h->d_ep,
+                                                    h->d_kE, h->d_kB, st);
+            if (rc) break;
+            LC_HIP(hipMemcpyAsync(h->d_Tn, h->d_Tl, bytesN, hipMemcpyDeviceToDevice, st));
+            rc = lc_loqd_grey_meb(h->grey, c, c_dt, h->d_kE, h->d_kB, h->d_ep, h->d_ks, h->d_es, h->d_fp, h->d_fc,
+                                  h->d_ffg, h->d_bc, T_prev, h->c_v, h->a_R, h->d_Tn, h->d_Eg, h->d_Egf, h->d_Fgf,
+                                  newton_tol, 100, rtol, max_iter, nullptr, nullptr, nullptr, st);
+            if (rc) break;
+            double ch[2];
+            rc = change(h, h->d_Tn, h->d_Tl, 1, ch, st);
+            if (rc) break;
+            std::swap(h->d_Tl, h->d_Tn);
+            if (ch[0] <= eps) break;
+        }
+        if (rc) break;
+        double ct[2], ce[2];
+        rc = change(h, h->d_Tl, h->d_Ts, 1, ct, st);
+        if (!rc) rc = change(h, h->d_Eg, h->d_Eg_old, 0, ce, st);
+        if (rc) break;
+        dT = ct[0];
+        dE = s == 1 ? INFINITY : (ce[1] > 0.0 ? ce[0] / ce[1] : 0.0);
+        std::swap(h->d_Ts, h->d_Tl);
+        LC_HIP(hipMemcpyAsync(h->d_Eg_old, h->d_Eg, bytesN, hipMemcpyDeviceToDevice, st));
+        if (dT <= eps && dE <= eps) break;
+    }
+    if (!rc) {
+        LC_HIP(hipMemcpyAsync(T, h->d_Ts, bytesN, hipMemcpyDeviceToDevice, st));
+        if (E_grey) LC_HIP(hipMemcpyAsync(E_grey, h->d_Eg, bytesN, hipMemcpyDeviceToDevice, st));
+        LC_HIP(hipStreamSynchronize(st));
+    }
+    report();
+    if (rc) return rc;
+    LC_CHECK(dT <= eps && dE <= eps, LC_ERR_UNSUPPORTED,
+             "MLQD step: changes %.3g (T) and %.3g (E) above %.3g after %d transport iterations", dT, dE, eps, s);
+    return LC_OK;
+}
+
+}  // extern "C"

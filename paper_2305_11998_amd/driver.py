@@ -277,3 +277,64 @@ class BatchSolver:
     def updates_per_step(self):
         return sum(s.updates_per_step() for s in self.solvers)
 
+
+
+class MlqdSolver:
+    """Time steps of the multilevel method (lc_mlqd_step) on a
+    Fleck-Cummings problem (workloads.fc_mlqd): the transport state, the
+    temperature and the multigroup low-order solution ping-pong between two
+    buffers; history records (outer, inner, (dT, dE)) per step."""
+
+    def __init__(self, prob, prec=lc.LC_F64, rays=None, eps=1e-12, max_outer=60, max_inner=1000):
+        from workloads import A_RAD, C_LIGHT
+        self.prob = prob
+        self.c = C_LIGHT
+        self.eps, self.max_outer, self.max_inner = eps, max_outer, max_inner
+        self.rays = rays if rays is not None else lc.lc_build_rays(
+            prob.nx, prob.ny, prob.lx, prob.ly, prob.phi, prob.mu, prob.omega, prob.h_moc)
+        self.plan = lc.Plan(self.rays, prob.G, prec)
+        self.h = lc.Mlqd(self.plan, prob.nu, prob.edges, C_LIGHT, prob.c_v, A_RAD)
+        G, N, nf = prob.G, prob.cells, self.h.nf
+        z = lambda n: torch.zeros(n, dtype=torch.float64, device="cuda")
+        self.I_in = _dev(prob.I_in)
+        self.state0 = _dev(prob.state0)
+        self.state = [self.plan.new_state(), self.plan.new_state()]
+        self.T = [z(N), z(N)]
+        self.E = [z(G * N), z(G * N)]
+        self.Ef = [z(G * nf), z(G * nf)]
+        self.F = [z(G * nf), z(G * nf)]
+        self.E_grey = z(N)
+        self.cur = 0
+        self.history = []
+
+    def reset(self):
+        p = self.prob
+        lc.lc_state_fill(self.plan, self.state0, self.state[0])
+        self.T[0].fill_(p.T0)
+        self.E[0].copy_(4.0 * np.pi * self.state0.reshape(-1) / self.c)
+        self.F[0].zero_()
+        self.cur = 0
+        self.history = []
+
+    def step(self, n=1):
+        p = self.prob
+        for _ in range(n):
+            a, b = self.cur, 1 - self.cur
+            r = lc.lc_mlqd_step(self.h, p.c_dt, self.state[a], self.state[b], self.I_in, self.T[a], self.E[a],
+                                self.F[a], self.T[b], self.E[b], self.Ef[b], self.F[b], self.E_grey, eps=self.eps,
+                                max_outer=self.max_outer, max_inner=self.max_inner)
+            self.history.append(r)
+            self.cur = b
+
+    def solution(self):
+        G, N, nf = self.prob.G, self.prob.cells, self.h.nf
+        k = self.cur
+        return dict(T=self.T[k].cpu().numpy(), E_cell=self.E[k].cpu().numpy().reshape(G, N),
+                    E_face=self.Ef[k].cpu().numpy().reshape(G, nf), F_face=self.F[k].cpu().numpy().reshape(G, nf),
+                    E_grey=self.E_grey.cpu().numpy())
+
+    def state_canonical(self):
+        out = torch.empty(self.plan.n_state, dtype=torch.float64, device="cuda")
+        lc.lc_state_export(self.plan, self.state[self.cur], out)
+        r = self.rays
+        return out.cpu().numpy().reshape(r.n_segments, 2, r.n_pol, self.prob.G)

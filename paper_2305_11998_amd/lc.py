@@ -78,6 +78,11 @@ _SIGS = {
     "lc_sweep_noalloc": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_loqd_create": ([_i32, _i32, _d, _d, _i32, C.POINTER(_vp)], C.c_int),
     "lc_loqd_free": ([_vp], C.c_int),
+    "lc_loqd_set_warm_start": ([_vp, _i32], C.c_int),
+    "lc_mlqd_create": ([_vp, _vp, _vp, _d, _d, _d, C.POINTER(_vp)], C.c_int),
+    "lc_mlqd_free": ([_vp], C.c_int),
+    "lc_mlqd_material": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
+    "lc_mlqd_step": ([_vp, _d] + [_vp] * 11 + [_d, _i32, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "lc_loqd_solve_general": ([_vp, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i32, _vp,
                                _vp, _vp], C.c_int),
     "lc_loqd_grey_coefficients": ([_vp, _d, _d] + [_vp] * 21, C.c_int),
@@ -548,3 +553,64 @@ def lc_loqd_grey_meb(h: Loqd, c, c_dt, kappa_E, kappa_B, E_prev, k_side, eta_sid
         _dev(F_face, G * nf, name="F_face"), float(newton_tol), int(max_newton), float(rtol), int(max_iter),
         C.byref(nit), C.byref(it), res.ctypes.data, _stream(stream)))
     return int(nit.value), int(it.value), res
+
+
+
+def lc_loqd_set_warm_start(h: Loqd, enable=True):
+    _check(_lib.lc_loqd_set_warm_start(h.handle, int(bool(enable))))
+
+
+class Mlqd:
+    """Owning wrapper of an ``lc_mlqd_t`` handle: multilevel time steps on
+    the Fleck-Cummings material for a plan (kept alive here)."""
+
+    def __init__(self, plan: Plan, nu, edges, c, c_v, a_R):
+        nu = np.ascontiguousarray(nu, dtype=np.float64)
+        edges = np.ascontiguousarray(edges, dtype=np.float64)
+        if nu.size != plan.G or edges.size != plan.G + 1:
+            raise ValueError("nu needs G values and edges G + 1")
+        h = C.c_void_p()
+        _check(_lib.lc_mlqd_create(plan.handle, nu.ctypes.data, edges.ctypes.data, float(c), float(c_v), float(a_R),
+                                   C.byref(h)))
+        self.handle = h
+        self.plan = plan
+        self.G = plan.G
+        r = plan.rays
+        self.cells = r.cells
+        self.n_interior = (r.nx - 1) * r.ny + r.nx * (r.ny - 1)
+        self.nb = 2 * (r.nx + r.ny)
+        self.nf = self.n_interior + self.nb
+
+    def free(self):
+        if self.handle:
+            _check(_lib.lc_mlqd_free(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def lc_mlqd_material(h: Mlqd, T, kappa, planck, stream=None):
+    G, N = h.G, h.cells
+    _check(_lib.lc_mlqd_material(h.handle, _dev(T, N, name="T"), _dev(kappa, G * N, name="kappa"),
+                                 _dev(planck, G * N, name="planck"), _stream(stream)))
+
+
+def lc_mlqd_step(h: Mlqd, c_dt, state_prev, state_new, I_in, T_prev, E_prev, F_prev, T, E_cell, E_face, F_face,
+                 E_grey=None, eps=1e-12, max_outer=60, max_inner=1000, stream=None):
+    """Returns (outer iterations, inner iterations, (dT, dE))."""
+    G, N, nf = h.G, h.cells, h.nf
+    nbytes = h.plan.state_bytes
+    so, si = C.c_int32(0), C.c_int32(0)
+    ch = np.zeros(2)
+    _check(_lib.lc_mlqd_step(
+        h.handle, float(c_dt), _bytes(state_prev, nbytes, "state_prev"), _bytes(state_new, nbytes, "state_new"),
+        _dev(I_in, h.plan.n_in, name="I_in"), _dev(T_prev, N, name="T_prev"), _dev(E_prev, G * N, name="E_prev"),
+        _dev(F_prev, G * nf, name="F_prev"), _dev(T, N, name="T"), _dev(E_cell, G * N, name="E_cell"),
+        _dev(E_face, G * nf, name="E_face"), _dev(F_face, G * nf, name="F_face"),
+        _dev(E_grey, N, name="E_grey", optional=True), float(eps), int(max_outer), int(max_inner), C.byref(so),
+        C.byref(si), ch.ctypes.data, _stream(stream)))
+    return int(so.value), int(si.value), (float(ch[0]), float(ch[1]))

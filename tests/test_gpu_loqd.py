@@ -478,3 +478,26 @@ def test_grey_meb_is_deterministic_and_reports_non_convergence(lcmod):
     with pytest.raises(lc.LcError) as e:
         _gpu_meb(lc, geo, [coef], [Ts], C_V, A_R, newton_tol=0.0, max_newton=1)
     assert e.value.status == lc.LC_ERR_UNSUPPORTED
+
+
+def test_loqd_warm_start(lcmod):
+    """A second solve started from the first's solution: the same result
+    within rtol, in fewer iterations."""
+    import torch
+    lc, _ = lcmod
+    args = _random_groups(33, 20, 3.3, 1.0, 5, seed=21)
+    nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc = args
+    G = kappa.shape[0]
+    fc, ff, bnd = _gpu_layouts(nx, ny, f_cell, f_face, bc)
+    h = lc.Loqd(nx, ny, lx, ly, G)
+    z = lambda n: torch.zeros(n, dtype=torch.float64, device="cuda")
+    Ec, Ef, Ff = z(G * h.cells), z(G * h.nf), z(G * h.nf)
+    ins = [_dev(a) for a in (kappa, planck, E_prev, F_prev, fc, ff, bnd)]
+    it0, _ = lc.lc_loqd_solve(h, c, c_dt, *ins, Ec, Ef, Ff)
+    cold = (Ec.cpu().numpy().reshape(G, -1), Ef.cpu().numpy().reshape(G, -1), Ff.cpu().numpy().reshape(G, -1))
+    lc.lc_loqd_set_warm_start(h, True)
+    it1, res = lc.lc_loqd_solve(h, c, c_dt, *ins, Ec, Ef, Ff)
+    warm = (Ec.cpu().numpy().reshape(G, -1), Ef.cpu().numpy().reshape(G, -1), Ff.cpu().numpy().reshape(G, -1))
+    _say(f"case loqd warm start: iterations cold {it0}, warm {it1}")
+    assert it1 < it0 and np.all(res <= 1e-13)
+    _compare(warm, cold, "warm vs cold")
