@@ -539,13 +539,127 @@ def main_refinement(args):
           flush=True)
 
 
+def _fc_energy_defect(prob, prev, got, C):
+    """Relative mismatch between the energy a step gains (matter plus
+    radiation, summed over the cells) and the energy that crossed the
+    boundary in it (from the multigroup face fluxes)."""
+    import numpy as np
+    nx, ny = prob.nx, prob.ny
+    hx, hy = prob.lx / nx, prob.ly / ny
+    nint = (nx - 1) * ny + nx * (ny - 1)
+    gained = np.sum(prob.c_v * (got["T"] - prev["T"]) + (got["E_cell"] - prev["E_cell"]).sum(0)) * hx * hy
+    sgn = np.concatenate([-np.ones(ny), np.ones(ny), -np.ones(nx), np.ones(nx)])
+    lens = np.concatenate([np.full(ny, hy), np.full(ny, hy), np.full(nx, hx), np.full(nx, hx)])
+    inflow = -(prob.c_dt / C) * np.sum(sgn * got["F_face"].sum(0)[nint:] * lens)
+    return abs(gained - inflow) / abs(inflow)
+
+
+def _oracle_mlqd_sample():
+    """The oracle's multilevel step (unchanged) on a small Fleck-Cummings
+    case: 4 x 4 cells of 1.5 cm, 4 groups, 8 x 2 directions, h_moc 0.3 cm,
+    one step from T^0 at eps 1e-10.  Returns seconds per step."""
+    import warnings
+    import numpy as np
+    import workloads as W
+    from oracle import mlqd, rays, sweep
+    p = W.fc_mlqd(1.5, 0.3, 8, 2, 4, nu_lo=0.3, nu_hi=30.0)
+    g = rays.build(p.nx, p.ny, p.lx, p.ly, p.phi, p.h_moc)
+    st = sweep.initial_state(g, p.n_pol, p.state0)
+    E0, F0 = mlqd.initial_low_order(p, W.C_LIGHT)
+    t = time.time()
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        r = mlqd.outer_step(g, p, st, np.full(p.cells, p.T0), E0, F0, W.C_LIGHT, W.A_RAD, eps=1e-10)
+    return time.time() - t, r["outer"], r["inner"]
+
+
+def main_fc_mlqd(args):
+    """Multilevel (MLQD) time steps on the Fleck-Cummings problem at the
+    paper's counts: 6 x 6 cm, 17 groups, 144 directions (36 x 4), Delta t =
+    0.02 ns, eps = c_v T with c_v = 0.5917 a_R, 1 keV Planckian entering at
+    x = 0, T^0 = 1 eV; for each h_mat of --h-mat, --steps time steps at the
+    characteristic spacing --h-moc and tolerance --eps.  Per step: transport
+    (outer) and low-order (inner) iterations, time, and the energy-balance
+    mismatch; per grid the kernel-time share of the transport sweep (plan
+    events).  One JSON line per grid, then a summary line."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2305_11998_amd import driver, lc
+    grids = []
+    for h_mat in args.h_mat:
+        prob = W.fc_mlqd(h_mat, args.h_moc, 36, 4, 17, nu_lo=0.3, nu_hi=30.0)
+        t0 = time.time()
+        s = driver.MlqdSolver(prob, eps=args.eps, max_outer=200, max_inner=2000)
+        build_s = time.time() - t0
+        lc.lc_plan_profile(s.plan, True)
+        s.reset()
+        prev = dict(T=np.full(prob.cells, prob.T0), E_cell=4 * np.pi * prob.state0 / W.C_LIGHT)
+        rows, total_ms = [], 0.0
+        for n in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            s.step(1)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            total_ms += ms
+            got = s.solution()
+            outer, inner, ch = s.history[-1]
+            rows.append({"step": n + 1, "outer": outer, "inner": inner, "ms": round(ms, 3),
+                         "T_max": float(got["T"].max()), "energy_defect": _fc_energy_defect(prob, prev, got, W.C_LIGHT)})
+            prev = got
+            _say(f"h_mat {h_mat}: step {n + 1} outer {outer} inner {inner} {ms:.1f} ms T_max {got['T'].max():.4f}")
+        prof = lc.lc_plan_profile_read(s.plan)
+        r = s.rays
+        sweeps = sum(x["outer"] for x in rows)
+        upd = r.n_segments * 2 * r.n_pol * prob.G
+        line = {"workload": "fc_mlqd", "h_mat": h_mat, "cells": prob.cells, "h_moc": args.h_moc,
+                "characteristics": int(r.n_rays), "segments": int(r.n_segments), "groups": prob.G,
+                "directions": len(prob.omega), "eps": args.eps, "steps": args.steps, "build_s": round(build_s, 2),
+                "ms_per_step": total_ms / args.steps, "mean_outer": sweeps / args.steps,
+                "mean_inner": sum(x["inner"] for x in rows) / args.steps,
+                "sweep_ms_total": prof[0] if prof else None, "sweep_launches": prof[1] if prof else None,
+                "moments_ms_total": prof[2] if prof else None,
+                "updates_per_sweep": int(upd), "max_energy_defect": max(x["energy_defect"] for x in rows),
+                "per_step": rows}
+        if prof and prof[1]:
+            # float64 sweep with face points: the previous state read, the new
+            # state and the entering intensities written, 8 bytes each per update
+            line["sweep_achieved_GBs"] = 24.0 * upd * prof[1] / (prof[0] * 1e-3) / 1e9
+            line["sweep_frac_of_hbm"] = line["sweep_achieved_GBs"] / 8000.0
+            line["sweep_share_of_step"] = prof[0] / total_ms
+        print(json.dumps(line), flush=True)
+        grids.append(line)
+        del s
+        torch.cuda.empty_cache()
+    main = grids[0]
+    out = {"metric": "fc_mlqd_time_steps_per_s", "value": 1000.0 / main["ms_per_step"], "unit": "steps/s",
+           "n_gpus": 1, "steps": args.steps, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+           "vs_baseline": None,
+           "config": {"workload": f"multilevel time steps, Fleck-Cummings, {main['cells']} cells (h_mat "
+                                  f"{main['h_mat']} cm), 17 groups, 144 directions, h_moc {args.h_moc} cm, "
+                                  f"eps {args.eps}"},
+           "mean_transport_iterations": main["mean_outer"], "mean_low_order_iterations": main["mean_inner"]}
+    if not args.no_cpu_baseline:
+        sec, outer, inner = _oracle_mlqd_sample()
+        out["cpu_baseline"] = {"value": 1.0 / sec, "unit": "steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"one step of a 4x4-cell, 4-group, 16-direction Fleck-Cummings case "
+                                         f"(h_moc 0.3 cm, eps 1e-10): {sec:.2f} s, {outer} transport and {inner} "
+                                         f"low-order iterations; a far smaller problem than the timed one"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=("batch", "single", "refinement", "split"), default="batch",
+    ap.add_argument("--workload", choices=("batch", "single", "refinement", "split", "fc_mlqd"), default="batch",
                     help="batch: the 64-problem batched form (default); single: one problem of --config; "
                          "refinement: characteristic-grid refinement study; split: whole vs split sweep "
-                         "on few-lane problems")
+                         "on few-lane problems; fc_mlqd: multilevel time steps on Fleck-Cummings")
+    ap.add_argument("--h-mat", type=float, nargs="+", default=[0.6], help="--workload fc_mlqd: material cell widths")
+    ap.add_argument("--h-moc", type=float, default=0.01, help="--workload fc_mlqd: characteristic spacing")
+    ap.add_argument("--eps", type=float, default=1e-12, help="--workload fc_mlqd: iteration tolerance")
     ap.add_argument("--config", type=int, default=2, help="workload index for --workload single (0, 1, 2 or 4)")
     ap.add_argument("--case", type=int, default=None, help="--workload split: run only this case (0, 1 or 2)")
     ap.add_argument("--steps", type=int, default=10)
@@ -581,6 +695,9 @@ def main():
         return main_split(args)
     if args.workload == "refinement":
         main_refinement(args)
+        return
+    if args.workload == "fc_mlqd":
+        main_fc_mlqd(args)
         return
     if args.workload == "single":
         main_single(args)

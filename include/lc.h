@@ -494,9 +494,12 @@ lc_status lc_loqd_set_warm_start(lc_loqd_t loqd, int32_t enable);
  *      averages of eq. (8)-(9),
  * iterated: an outer (transport) iteration s forms the closures with the
  * material of T^(s); inner (low-order) iterations, closures fixed,
- * evaluate kappa_g, B_g at the newest temperature and solve 2. then 3. for
- * the next, until max_i |T_new - T| / T_new <= eps or max_inner
- * iterations; the step ends when, between transport sweeps, the
+ * evaluate kappa_g, B_g at the temperature T and solve 2. then 3. for
+ * Phi(T), until max_i |Phi(T)_i - T_i| / Phi(T)_i <= eps or max_inner
+ * passes, the next T from Anderson mixing of the last passes on log T
+ * (depth set by lc_mlqd_set_acceleration, default 3; it changes the
+ * iteration's speed, not its fixed point); the step ends when, between
+ * transport sweeps, the
  * temperature changes by at most eps (relative, every cell) and the grey
  * cell energy by at most eps (max |dE| / max |E|).  T^(0) = T^{n-1}.
  * B_g(T) = (a_R c T^4 / 4 pi)(15/pi^4) int over [nu_{g-1}/T, nu_g/T] of
@@ -512,6 +515,9 @@ lc_status lc_loqd_set_warm_start(lc_loqd_t loqd, int32_t enable);
  * the closures, two LOQD handles with warm starts, the grey coefficients)
  * and synchronises the device.  Errors: LC_ERR_ARG, LC_ERR_STATE,
  * LC_ERR_ALLOC, LC_ERR_HIP.
+ *
+ * lc_mlqd_set_acceleration -- Anderson depth of the inner iteration,
+ * 0 (plain fixed-point passes) to 8.  Errors: LC_ERR_ARG, LC_ERR_STATE.
  *
  * lc_mlqd_material -- kappa_g(T), B_g(T) [G][cells] (device, float64) for
  * T [cells] (device, > 0), as the step evaluates them.  Allocates and
@@ -539,6 +545,7 @@ typedef struct lc_mlqd_s* lc_mlqd_t;
 lc_status lc_mlqd_create(lc_plan_t plan, const double* nu, const double* edges, double c, double c_v,
                          double a_R, lc_mlqd_t* out);
 lc_status lc_mlqd_free(lc_mlqd_t mlqd);
+lc_status lc_mlqd_set_acceleration(lc_mlqd_t mlqd, int32_t depth);
 lc_status lc_mlqd_material(lc_mlqd_t mlqd, const double* T, double* kappa, double* planck, void* stream);
 lc_status lc_mlqd_step(lc_mlqd_t mlqd, double c_dt, const void* state_prev, void* state_new,
                        const double* I_in, const double* T_prev, const double* E_prev,

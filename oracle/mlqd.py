@@ -33,12 +33,22 @@ import numpy as np
 from . import faces, loqd, material, moments, sweep
 
 
-def low_order(prob, T_start, T_prev, E_prev, F_prev, f_cell, f_face, bc, c, a_R, eps, max_inner):
-    """Inner iterations with fixed closures.  Returns (T, multigroup
-    (E_cell, E_face, F_face), grey E, iterations, last change)."""
+def low_order(prob, T_start, T_prev, E_prev, F_prev, f_cell, f_face, bc, c, a_R, eps, max_inner, depth=3):
+    """Inner iterations with fixed closures: the fixed point T = Phi(T) of
+    one pass (material of T, multigroup solve, grey coefficients, grey
+    problem), with Anderson mixing of depth `depth` (0: plain iteration) on
+    x = log T: with the map g(x) = log Phi(e^x) and residual r = g(x) - x,
+    the next x is g(x) - dG gamma, gamma minimising |r - dF gamma| over
+    the last `depth` differences dF of residuals and dG of map values.  The
+    iteration stops when max_i |Phi(T)_i - T_i| / Phi(T)_i <= eps.  Returns
+    (Phi(T) of the last pass, its multigroup (E_cell, E_face, F_face), its
+    grey E, passes, last change)."""
     nx, ny, lx, ly = prob.nx, prob.ny, prob.lx, prob.ly
-    T = np.array(T_start, dtype=np.float64)
+    x = np.log(np.asarray(T_start, dtype=np.float64))
+    dF, dG = [], []
+    r_prev = g_prev = None
     for l in range(1, max_inner + 1):
+        T = np.exp(x)
         kappa = material.fc_opacity(prob.nu, T)
         planck = material.group_planck(prob.edges, T, a_R, c)
         mg = loqd.solve(nx, ny, lx, ly, c, prob.c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc)
@@ -46,13 +56,25 @@ def low_order(prob, T_start, T_prev, E_prev, F_prev, f_cell, f_face, bc, c, a_R,
         T_new, E, _, _, _ = loqd.solve_grey_meb(nx, ny, lx, ly, c, prob.c_dt, coef, T_prev, prob.c_v, a_R,
                                                 T_start=T, tol=min(eps, 1e-13))
         change = float(np.max(np.abs(T_new - T) / np.abs(T_new)))
-        T = T_new
         if change <= eps:
             break
-    return T, mg, E, l, change
+        g = np.log(T_new)
+        r = g - x
+        if r_prev is not None and depth > 0:
+            dF.append(r - r_prev)
+            dG.append(g - g_prev)
+            del dF[:-depth], dG[:-depth]
+        r_prev, g_prev = r, g
+        if dF:
+            gamma = np.linalg.lstsq(np.column_stack(dF), r, rcond=None)[0]
+            x = g - np.column_stack(dG) @ gamma
+        else:
+            x = g
+    return T_new, mg, E, l, change
 
 
-def outer_step(grid, prob, state_prev, T_prev, E_prev, F_prev, c, a_R, eps=1e-12, max_outer=60, max_inner=1000):
+def outer_step(grid, prob, state_prev, T_prev, E_prev, F_prev, c, a_R, eps=1e-12, max_outer=60, max_inner=1000,
+               depth=3):
     """prob: an object with nx, ny, lx, ly, phi, mu, omega, edges, nu,
     c_dt, c_v, I_in (the Fleck-Cummings builder's fields).  state_prev is the
     transport state of step n-1, T_prev [cells], E_prev [G][cells], F_prev
@@ -72,7 +94,8 @@ def outer_step(grid, prob, state_prev, T_prev, E_prev, F_prev, c, a_R, eps=1e-12
         bnd = moments.boundary_factors(grid, prob.phi, prob.mu, prob.omega, exits, prob.I_in)
         _, _, ff = faces.face_moments(grid, prob.phi, prob.mu, prob.omega, points, c)
         f_cell, f_face, bc = loqd.closures_from_transport(nx, ny, f, ff, bnd)
-        T_new, mg, E, l, _ = low_order(prob, T, T_prev, E_prev, F_prev, f_cell, f_face, bc, c, a_R, eps, max_inner)
+        T_new, mg, E, l, _ = low_order(prob, T, T_prev, E_prev, F_prev, f_cell, f_face, bc, c, a_R, eps, max_inner,
+                                       depth)
         inner += l
         dT = float(np.max(np.abs(T_new - T) / np.abs(T_new)))
         dE = np.inf if E_old is None else float(np.max(np.abs(E - E_old)) / np.max(np.abs(E)))

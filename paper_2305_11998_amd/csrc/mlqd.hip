@@ -10,10 +10,14 @@
 // the state of step n-1 with kappa_g, B_g of T^(s) and forms the closures;
 // inner (low-order) iterations then, with those closures fixed, evaluate
 // kappa_g, B_g at the newest temperature, solve the multigroup equations,
-// form the grey coefficients and solve the grey problem for the next
-// temperature, until it changes by at most eps (relative, every cell).  The
-// outer iteration ends when the temperature and the grey cell energy
-// change by at most eps between transport sweeps.
+// form the grey coefficients and solve the grey problem: one pass T ->
+// Phi(T), until Phi(T) differs from T by at most eps (relative, every cell).
+// The next inner iterate comes from Anderson mixing of the last passes on
+// x = log T (g(x) = log Phi(e^x), r = g(x) - x; x <- g - dG gamma with gamma
+// minimising |r - dF gamma| over the last `depth` differences of residuals
+// dF and of map values dG); the mixing changes only the speed, not the
+// fixed point.  The outer iteration ends when the temperature and the grey
+// cell energy change by at most eps between transport sweeps.
 //
 // Material: kappa_g(T) = 27/nu_g^3 (1 - e^(-nu_g/T)) at each group's
 // representative frequency, B_g(T) = (a_R c T^4 / 4 pi)(15/pi^4) times the
@@ -32,6 +36,8 @@ namespace lc {
 constexpr uint32_t kMlqdMagic = 0x4c434d51u;   // "LCMQ"
 constexpr int kMlqdBlock = 256;
 constexpr int kBern = 41;                      // series terms k = 0 .. 40
+constexpr int kMaxDepth = 8;                   // Anderson history
+constexpr int kMaxDots = kMaxDepth * (kMaxDepth + 1) / 2 + kMaxDepth;
 constexpr double kMPi = 3.14159265358979323846;
 
 struct Mlqd {
@@ -59,6 +65,11 @@ struct Mlqd {
     double *d_Eg = nullptr, *d_Egf = nullptr, *d_Fgf = nullptr, *d_Eg_old = nullptr;
     double *d_Ts = nullptr, *d_Tl = nullptr, *d_Tn = nullptr;
     double* d_part = nullptr;     // [nblk][2] block maxima
+    // Anderson mixing of the inner iteration on x = log T
+    int depth = 3;
+    double *d_x = nullptr, *d_gx = nullptr, *d_rprev = nullptr, *d_gprev = nullptr;   // [N]
+    double *d_dF = nullptr, *d_dG = nullptr;  // [kMaxDepth][N]
+    double* d_dots = nullptr;                 // [nblk][kMaxDots] block partial sums
     std::vector<void*> owned;
 };
 
@@ -139,6 +150,71 @@ __global__ void k_change(int n, const double* __restrict__ a, const double* __re
     }
 }
 
+__global__ void k_log(int n, const double* __restrict__ T, double* x) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = log(T[i]);
+}
+
+__global__ void k_exp(int n, const double* __restrict__ x, double* T) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) T[i] = exp(x[i]);
+}
+
+// After a pass: g = log Phi, r = g - x; with a previous pass, the history
+// column `slot` takes dF = r - r_prev, dG = g - g_prev; then r_prev = r,
+// g_prev = g.
+__global__ void k_aa_update(int n, const double* __restrict__ Tn, const double* __restrict__ x, double* gx,
+                            double* rprev, double* gprev, double* dF, double* dG, int have_prev) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double g = log(Tn[i]), r = g - x[i];
+    if (have_prev) {
+        dF[i] = r - rprev[i];
+        dG[i] = g - gprev[i];
+    }
+    gx[i] = g;
+    rprev[i] = r;
+    gprev[i] = g;
+}
+
+// Block partial sums of dF_a . dF_b (a <= b < h, row-major upper triangle)
+// then dF_a . r (a < h); r = rprev (the newest residual).
+__global__ void k_aa_dots(int n, int h, const double* __restrict__ dF, const double* __restrict__ r, double* part) {
+    __shared__ double sm[kMlqdBlock];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nd = h * (h + 1) / 2 + h;
+    int a = 0, b = 0;
+    for (int d = 0; d < nd; ++d) {
+        const double* u = dF + (size_t)a * n;
+        const double* v = d < h * (h + 1) / 2 ? dF + (size_t)b * n : r;
+        sm[threadIdx.x] = i < n ? u[i] * v[i] : 0.0;
+        __syncthreads();
+        for (int w = kMlqdBlock / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) sm[threadIdx.x] += sm[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(size_t)blockIdx.x * kMaxDots + d] = sm[0];
+        __syncthreads();
+        if (d < h * (h + 1) / 2) {            // next pair of the triangle, then a = 0.. for dF . r
+            if (++b == h) b = ++a;
+            if (a == h) a = 0;
+        } else {
+            ++a;
+        }
+    }
+}
+
+// x = g - sum_k gamma_k dG_k
+__global__ void k_aa_mix(int n, int h, const double* __restrict__ gx, const double* __restrict__ dG, double g0,
+                         double g1, double g2, double g3, double g4, double g5, double g6, double g7, double* x) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double gam[kMaxDepth] = {g0, g1, g2, g3, g4, g5, g6, g7};
+    double v = gx[i];
+    for (int k = 0; k < h; ++k) v -= gam[k] * dG[(size_t)k * n + i];
+    x[i] = v;
+}
+
 // B_k / k! for k = 0..40 (B_1 = -1/2): b_1 = -1/2, b_odd = 0 beyond,
 // b_2m = (-1)^(m+1) 2 zeta(2m) / (2 pi)^(2m).
 std::vector<double> bernoulli_over_factorial() {
@@ -191,6 +267,51 @@ lc_status change(Mlqd* h, const double* a, const double* b, int rel, double out[
     for (int k = 0; k < h->nblk; ++k) {
         out[0] = std::max(out[0], part[2 * k]);
         out[1] = std::max(out[1], part[2 * k + 1]);
+    }
+    return LC_OK;
+}
+
+// Anderson coefficients: gamma minimising |r - dF gamma| from the normal
+// equations (dF^T dF) gamma = dF^T r, by Gaussian elimination with partial
+// pivoting.  False when the history is numerically rank-deficient.
+lc_status aa_gamma(Mlqd* h, int hcols, double* gamma, bool* ok, hipStream_t st) {
+    const int nd = hcols * (hcols + 1) / 2 + hcols;
+    hipLaunchKernelGGL(k_aa_dots, dim3(h->nblk), dim3(kMlqdBlock), 0, st, h->N, hcols, h->d_dF, h->d_rprev,
+                       h->d_dots);
+    LC_HIP(hipGetLastError());
+    std::vector<double> part((size_t)h->nblk * kMaxDots);
+    LC_HIP(hipMemcpyAsync(part.data(), h->d_dots, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    LC_HIP(hipStreamSynchronize(st));
+    std::vector<double> dots(nd, 0.0);
+    for (int k = 0; k < h->nblk; ++k)
+        for (int d = 0; d < nd; ++d) dots[d] += part[(size_t)k * kMaxDots + d];
+    double A[kMaxDepth][kMaxDepth + 1];
+    int d = 0;
+    for (int a = 0; a < hcols; ++a)
+        for (int b = a; b < hcols; ++b, ++d) A[a][b] = A[b][a] = dots[d];
+    for (int a = 0; a < hcols; ++a) A[a][hcols] = dots[d + a];
+    double dmax = 0.0;
+    for (int a = 0; a < hcols; ++a) dmax = std::max(dmax, A[a][a]);
+    *ok = dmax > 0.0 && std::isfinite(dmax);
+    for (int col = 0; col < hcols && *ok; ++col) {
+        int piv = col;
+        for (int r2 = col + 1; r2 < hcols; ++r2)
+            if (fabs(A[r2][col]) > fabs(A[piv][col])) piv = r2;
+        if (fabs(A[piv][col]) <= 1e-13 * dmax) {
+            *ok = false;
+            break;
+        }
+        for (int k = 0; k <= hcols; ++k) std::swap(A[col][k], A[piv][k]);
+        for (int r2 = col + 1; r2 < hcols; ++r2) {
+            const double m = A[r2][col] / A[col][col];
+            for (int k = col; k <= hcols; ++k) A[r2][k] -= m * A[col][k];
+        }
+    }
+    for (int a = hcols - 1; a >= 0 && *ok; --a) {
+        double v = A[a][hcols];
+        for (int k = a + 1; k < hcols; ++k) v -= A[a][k] * gamma[k];
+        gamma[a] = v / A[a][a];
+        *ok = std::isfinite(gamma[a]);
     }
     return LC_OK;
 }
@@ -267,6 +388,11 @@ lc_status lc_mlqd_create(lc_plan_t plan, const double* nu, const double* edges, 
     if (!rc) rc = dalloc(h->owned, &h->d_Egf, (size_t)nf);
     if (!rc) rc = dalloc(h->owned, &h->d_Fgf, (size_t)nf);
     if (!rc) rc = dalloc(h->owned, &h->d_part, 2 * (size_t)h->nblk);
+    for (double** p : {&h->d_x, &h->d_gx, &h->d_rprev, &h->d_gprev})
+        if (!rc) rc = dalloc(h->owned, p, (size_t)N);
+    if (!rc) rc = dalloc(h->owned, &h->d_dF, (size_t)kMaxDepth * N);
+    if (!rc) rc = dalloc(h->owned, &h->d_dG, (size_t)kMaxDepth * N);
+    if (!rc) rc = dalloc(h->owned, &h->d_dots, (size_t)h->nblk * kMaxDots);
     if (rc) return fail(rc);
     if (hipMemcpy(h->d_nu, nu, G * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->d_edges, edges, (G + 1) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -285,6 +411,14 @@ lc_status lc_mlqd_free(lc_mlqd_t handle) {
     Mlqd* h = as_mlqd(handle);
     LC_CHECK(h, LC_ERR_STATE, "invalid MLQD handle");
     free_mlqd(h);
+    return LC_OK;
+}
+
+lc_status lc_mlqd_set_acceleration(lc_mlqd_t handle, int32_t depth) {
+    Mlqd* h = as_mlqd(handle);
+    LC_CHECK(h, LC_ERR_STATE, "invalid MLQD handle");
+    LC_ARG(depth >= 0 && depth <= kMaxDepth, "depth must be in 0..%d", kMaxDepth);
+    h->depth = depth;
     return LC_OK;
 }
 
@@ -337,10 +471,14 @@ lc_status lc_mlqd_step(lc_mlqd_t handle, double c_dt, const void* state_prev, vo
         if (!rc && h->nint > 0)
             rc = lc_face_moments(h->plan, h->d_points, state_new, c, nullptr, nullptr, h->d_ff, st);
         if (rc) break;
-        // inner low-order iterations with these closures
-        LC_HIP(hipMemcpyAsync(h->d_Tl, h->d_Ts, bytesN, hipMemcpyDeviceToDevice, st));
+        // inner low-order iterations with these closures (Anderson mixing on log T)
+        const dim3 gN(h->nblk), bN(kMlqdBlock);
+        hipLaunchKernelGGL(k_log, gN, bN, 0, st, N, h->d_Ts, h->d_x);
+        int hcols = 0, slot = 0;
+        bool have_prev = false;
         for (int l = 0; l < max_inner; ++l) {
             ++inner;
+            hipLaunchKernelGGL(k_exp, gN, bN, 0, st, N, h->d_x, h->d_Tl);
             rc = material(h, h->d_Tl, h->d_kappa, h->d_planck, st);
             if (!rc) rc = lc_loqd_solve(h->mg, c, c_dt, h->d_kappa, h->d_planck, E_prev, F_prev, h->d_f, h->d_ff,
                                         h->d_bnd, E_cell, E_face, F_face, rtol, max_iter, nullptr, nullptr, st);
@@ -356,10 +494,33 @@ lc_status lc_mlqd_step(lc_mlqd_t handle, double c_dt, const void* state_prev, vo
             if (rc) break;
             double ch[2];
             rc = change(h, h->d_Tn, h->d_Tl, 1, ch, st);
-            if (rc) break;
-            std::swap(h->d_Tl, h->d_Tn);
-            if (ch[0] <= eps) break;
+            if (rc || ch[0] <= eps) break;
+            const bool push = have_prev && h->depth > 0;
+            hipLaunchKernelGGL(k_aa_update, gN, bN, 0, st, N, h->d_Tn, h->d_x, h->d_gx, h->d_rprev, h->d_gprev,
+                               h->d_dF + (size_t)slot * N, h->d_dG + (size_t)slot * N, push ? 1 : 0);
+            LC_HIP(hipGetLastError());
+            if (push) {
+                hcols = std::min(hcols + 1, h->depth);
+                slot = (slot + 1) % h->depth;
+            }
+            have_prev = true;
+            double gamma[kMaxDepth] = {0, 0, 0, 0, 0, 0, 0, 0};
+            bool ok = false;
+            if (hcols > 0) {
+                rc = aa_gamma(h, hcols, gamma, &ok, st);
+                if (rc) break;
+            }
+            if (ok) {
+                hipLaunchKernelGGL(k_aa_mix, gN, bN, 0, st, N, hcols, h->d_gx, h->d_dG, gamma[0], gamma[1], gamma[2],
+                                   gamma[3], gamma[4], gamma[5], gamma[6], gamma[7], h->d_x);
+            } else {
+                LC_HIP(hipMemcpyAsync(h->d_x, h->d_gx, bytesN, hipMemcpyDeviceToDevice, st));
+                hcols = 0;                    // a rank-deficient history starts again
+                slot = 0;
+            }
+            LC_HIP(hipGetLastError());
         }
+        std::swap(h->d_Tl, h->d_Tn);          // T^(s+1): the last pass's Phi
         if (rc) break;
         double ct[2], ce[2];
         rc = change(h, h->d_Tl, h->d_Ts, 1, ct, st);

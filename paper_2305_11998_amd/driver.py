@@ -285,7 +285,7 @@ class MlqdSolver:
     temperature and the multigroup low-order solution ping-pong between two
     buffers; history records (outer, inner, (dT, dE)) per step."""
 
-    def __init__(self, prob, prec=lc.LC_F64, rays=None, eps=1e-12, max_outer=60, max_inner=1000):
+    def __init__(self, prob, prec=lc.LC_F64, rays=None, eps=1e-12, max_outer=60, max_inner=1000, depth=3):
         from workloads import A_RAD, C_LIGHT
         self.prob = prob
         self.c = C_LIGHT
@@ -294,6 +294,7 @@ class MlqdSolver:
             prob.nx, prob.ny, prob.lx, prob.ly, prob.phi, prob.mu, prob.omega, prob.h_moc)
         self.plan = lc.Plan(self.rays, prob.G, prec)
         self.h = lc.Mlqd(self.plan, prob.nu, prob.edges, C_LIGHT, prob.c_v, A_RAD)
+        lc.lc_mlqd_set_acceleration(self.h, depth)
         G, N, nf = prob.G, prob.cells, self.h.nf
         z = lambda n: torch.zeros(n, dtype=torch.float64, device="cuda")
         self.I_in = _dev(prob.I_in)

@@ -81,6 +81,7 @@ _SIGS = {
     "lc_loqd_set_warm_start": ([_vp, _i32], C.c_int),
     "lc_mlqd_create": ([_vp, _vp, _vp, _d, _d, _d, C.POINTER(_vp)], C.c_int),
     "lc_mlqd_free": ([_vp], C.c_int),
+    "lc_mlqd_set_acceleration": ([_vp, _i32], C.c_int),
     "lc_mlqd_material": ([_vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_mlqd_step": ([_vp, _d] + [_vp] * 11 + [_d, _i32, _i32, _vp, _vp, _vp, _vp], C.c_int),
     "lc_loqd_solve_general": ([_vp, _d, _d, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _d, _i32, _vp,
@@ -591,6 +592,10 @@ class Mlqd:
             self.free()
         except Exception:
             pass
+
+
+def lc_mlqd_set_acceleration(h: Mlqd, depth):
+    _check(_lib.lc_mlqd_set_acceleration(h.handle, int(depth)))
 
 
 def lc_mlqd_material(h: Mlqd, T, kappa, planck, stream=None):

@@ -188,3 +188,22 @@ def test_mlqd_reports_non_convergence(lcmod):
     with pytest.raises(lc.LcError) as e:
         s.step(1)
     assert e.value.status == lc.LC_ERR_UNSUPPORTED
+
+
+def test_mlqd_acceleration_keeps_the_fixed_point(lcmod):
+    """Plain inner passes (depth 0) and Anderson mixing (depth 3) reach the
+    same step result within the iteration tolerance, the mixing in fewer
+    passes."""
+    lc, driver = lcmod
+    p = _fc()
+    _say("case fc mlqd 6x6: plain vs accelerated inner iterations, 2 steps")
+    out = {}
+    for depth in (0, 3):
+        s = driver.MlqdSolver(p, eps=1e-11, depth=depth)
+        s.reset()
+        s.step(2)
+        out[depth] = (s.solution(), sum(h[1] for h in s.history))
+    a, b = out[0][0], out[3][0]
+    e = max(_normwise(a[k], b[k]) for k in ("T", "E_cell", "E_face", "F_face"))
+    _say(f"  inner passes: plain {out[0][1]}, accelerated {out[3][1]}; difference {e:.2e}")
+    assert out[3][1] < out[0][1] and e <= TOL
