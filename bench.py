@@ -573,74 +573,114 @@ def _oracle_mlqd_sample():
     return time.time() - t, r["outer"], r["inner"]
 
 
+def _restrict(y, n):
+    """Cell averages of an n x n field on the n/2 x n/2 grid (cell i = iy n + ix)."""
+    a = y.reshape(n, n)
+    return 0.25 * (a[0::2, 0::2] + a[1::2, 0::2] + a[0::2, 1::2] + a[1::2, 1::2]).ravel()
+
+
+def _refinement_rows(runs, key, L=6.0):
+    """||Delta y_h|| = ||y_h - y_{2h}||_L2 over the slab at the last step (the
+    finer solution restricted to the coarser grid by cell averages when the
+    material grids differ), rho = ||Delta y_{2h}|| / ||Delta y_h|| and the
+    relative difference ||Delta y_h|| / ||y_h||, for T and the grey E."""
+    import numpy as np
+    rows = []
+    for prev, cur in zip(runs, runs[1:]):
+        row = {"h_mat": cur["h_mat"], "h_moc": cur["h_moc"]}
+        for name in ("T", "E"):
+            yf, yc = cur[name], prev[name]
+            n = int(round(np.sqrt(yf.size)))
+            if yf.size != yc.size:
+                yf = _restrict(yf, n)
+                n //= 2
+            h2 = (L / n) ** 2
+            d = float(np.sqrt(np.sum((yf - yc) ** 2) * h2))
+            row[f"d{name}"] = d
+            row[f"d{name}_rel"] = d / float(np.sqrt(np.sum(yf ** 2) * h2))
+            if rows and rows[-1].get(f"d{name}"):
+                row[f"rho_{name}"] = rows[-1][f"d{name}"] / d if d > 0 else None
+        rows.append(row)
+    return rows
+
+
 def main_fc_mlqd(args):
     """Multilevel (MLQD) time steps on the Fleck-Cummings problem at the
     paper's counts: 6 x 6 cm, 17 groups, 144 directions (36 x 4), Delta t =
     0.02 ns, eps = c_v T with c_v = 0.5917 a_R, 1 keV Planckian entering at
-    x = 0, T^0 = 1 eV; for each h_mat of --h-mat, --steps time steps at the
-    characteristic spacing --h-moc and tolerance --eps.  Per step: transport
-    (outer) and low-order (inner) iterations, time, and the energy-balance
-    mismatch; per grid the kernel-time share of the transport sweep (plan
-    events).  One JSON line per grid, then a summary line."""
+    x = 0, T^0 = 1 eV; for each h_mat of --h-mat and h_moc of --h-moc,
+    --steps time steps at tolerance --eps (uniform characteristics, or the
+    paper's vertex-avoiding grid with --tubes).  Per step: transport (outer)
+    and low-order (inner) iterations, time, and the energy-balance mismatch;
+    per run the kernel-time share of the transport sweep (plan events).
+    With several h_mat (one h_moc) or several h_moc (one h_mat), the
+    refinement norms of the last step's T and grey E follow.  One JSON line
+    per run, then a summary line."""
     import numpy as np
     import torch
     import workloads as W
     from paper_2305_11998_amd import driver, lc
-    grids = []
+    mode = lc.LC_RAYS_TUBES if args.tubes else lc.LC_RAYS_UNIFORM
+    runs = []
     for h_mat in args.h_mat:
-        prob = W.fc_mlqd(h_mat, args.h_moc, 36, 4, 17, nu_lo=0.3, nu_hi=30.0)
-        t0 = time.time()
-        s = driver.MlqdSolver(prob, eps=args.eps, max_outer=200, max_inner=2000)
-        build_s = time.time() - t0
-        lc.lc_plan_profile(s.plan, True)
-        s.reset()
-        prev = dict(T=np.full(prob.cells, prob.T0), E_cell=4 * np.pi * prob.state0 / W.C_LIGHT)
-        rows, total_ms = [], 0.0
-        for n in range(args.steps):
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            s.step(1)
-            e1.record()
-            torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1)
-            total_ms += ms
-            got = s.solution()
-            outer, inner, ch = s.history[-1]
-            rows.append({"step": n + 1, "outer": outer, "inner": inner, "ms": round(ms, 3),
-                         "T_max": float(got["T"].max()), "energy_defect": _fc_energy_defect(prob, prev, got, W.C_LIGHT)})
-            prev = got
-            _say(f"h_mat {h_mat}: step {n + 1} outer {outer} inner {inner} {ms:.1f} ms T_max {got['T'].max():.4f}")
-        prof = lc.lc_plan_profile_read(s.plan)
-        r = s.rays
-        sweeps = sum(x["outer"] for x in rows)
-        upd = r.n_segments * 2 * r.n_pol * prob.G
-        line = {"workload": "fc_mlqd", "h_mat": h_mat, "cells": prob.cells, "h_moc": args.h_moc,
-                "characteristics": int(r.n_rays), "segments": int(r.n_segments), "groups": prob.G,
-                "directions": len(prob.omega), "eps": args.eps, "steps": args.steps, "build_s": round(build_s, 2),
-                "ms_per_step": total_ms / args.steps, "mean_outer": sweeps / args.steps,
-                "mean_inner": sum(x["inner"] for x in rows) / args.steps,
-                "sweep_ms_total": prof[0] if prof else None, "sweep_launches": prof[1] if prof else None,
-                "moments_ms_total": prof[2] if prof else None,
-                "updates_per_sweep": int(upd), "max_energy_defect": max(x["energy_defect"] for x in rows),
-                "per_step": rows}
-        if prof and prof[1]:
-            # float64 sweep with face points: the previous state read, the new
-            # state and the entering intensities written, 8 bytes each per update
-            line["sweep_achieved_GBs"] = 24.0 * upd * prof[1] / (prof[0] * 1e-3) / 1e9
-            line["sweep_frac_of_hbm"] = line["sweep_achieved_GBs"] / 8000.0
-            line["sweep_share_of_step"] = prof[0] / total_ms
-        print(json.dumps(line), flush=True)
-        grids.append(line)
-        del s
-        torch.cuda.empty_cache()
-    main = grids[0]
+        for h_moc in args.h_moc:
+            prob = W.fc_mlqd(h_mat, h_moc, 36, 4, 17, nu_lo=0.3, nu_hi=30.0)
+            t0 = time.time()
+            rays = lc.lc_build_rays(prob.nx, prob.ny, prob.lx, prob.ly, prob.phi, prob.mu, prob.omega, h_moc, mode)
+            s = driver.MlqdSolver(prob, rays=rays, eps=args.eps, max_outer=200, max_inner=2000)
+            build_s = time.time() - t0
+            lc.lc_plan_profile(s.plan, True)
+            s.reset()
+            prev = dict(T=np.full(prob.cells, prob.T0), E_cell=4 * np.pi * prob.state0 / W.C_LIGHT)
+            rows, total_ms = [], 0.0
+            for n in range(args.steps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                s.step(1)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+                total_ms += ms
+                got = s.solution()
+                outer, inner, ch = s.history[-1]
+                rows.append({"step": n + 1, "outer": outer, "inner": inner, "ms": round(ms, 3),
+                             "T_max": float(got["T"].max()),
+                             "energy_defect": _fc_energy_defect(prob, prev, got, W.C_LIGHT)})
+                prev = got
+                _say(f"h_mat {h_mat} h_moc {h_moc}: step {n + 1} outer {outer} inner {inner} {ms:.1f} ms "
+                     f"T_max {got['T'].max():.4f}")
+            prof = lc.lc_plan_profile_read(s.plan)
+            r = s.rays
+            upd = r.n_segments * 2 * r.n_pol * prob.G
+            line = {"workload": "fc_mlqd", "h_mat": h_mat, "cells": prob.cells, "h_moc": h_moc,
+                    "grid": "tubes" if args.tubes else "uniform", "characteristics": int(r.n_rays),
+                    "segments": int(r.n_segments), "groups": prob.G, "directions": len(prob.omega), "eps": args.eps,
+                    "steps": args.steps, "build_s": round(build_s, 2), "ms_per_step": total_ms / args.steps,
+                    "mean_outer": sum(x["outer"] for x in rows) / args.steps,
+                    "mean_inner": sum(x["inner"] for x in rows) / args.steps,
+                    "sweep_ms_total": prof[0] if prof else None, "sweep_launches": prof[1] if prof else None,
+                    "moments_ms_total": prof[2] if prof else None, "updates_per_sweep": int(upd),
+                    "max_energy_defect": max(x["energy_defect"] for x in rows), "per_step": rows}
+            if prof and prof[1]:
+                # float64 sweep with face points: the previous state read, the new
+                # state and the entering intensities written, 8 bytes each per update
+                line["sweep_achieved_GBs"] = 24.0 * upd * prof[1] / (prof[0] * 1e-3) / 1e9
+                line["sweep_frac_of_hbm"] = line["sweep_achieved_GBs"] / 8000.0
+                line["sweep_share_of_step"] = prof[0] / total_ms
+            print(json.dumps(line), flush=True)
+            runs.append(dict(line, T=prev["T"], E=prev["E_grey"]))
+            del s
+            torch.cuda.empty_cache()
+    main = runs[0]
     out = {"metric": "fc_mlqd_time_steps_per_s", "value": 1000.0 / main["ms_per_step"], "unit": "steps/s",
            "n_gpus": 1, "steps": args.steps, "higher_is_better": True, "dtype": "f64", "data": "synthetic",
            "vs_baseline": None,
            "config": {"workload": f"multilevel time steps, Fleck-Cummings, {main['cells']} cells (h_mat "
-                                  f"{main['h_mat']} cm), 17 groups, 144 directions, h_moc {args.h_moc} cm, "
-                                  f"eps {args.eps}"},
+                                  f"{main['h_mat']} cm), 17 groups, 144 directions, h_moc {main['h_moc']} cm "
+                                  f"({main['grid']}), eps {args.eps}"},
            "mean_transport_iterations": main["mean_outer"], "mean_low_order_iterations": main["mean_inner"]}
+    if len(runs) > 1 and (len(args.h_mat) == 1 or len(args.h_moc) == 1):
+        out["refinement"] = _refinement_rows(runs, "h_mat" if len(args.h_moc) == 1 else "h_moc")
     if not args.no_cpu_baseline:
         sec, outer, inner = _oracle_mlqd_sample()
         out["cpu_baseline"] = {"value": 1.0 / sec, "unit": "steps/s", "cores": 1, "kind": "oracle",
@@ -658,7 +698,8 @@ def main():
                          "refinement: characteristic-grid refinement study; split: whole vs split sweep "
                          "on few-lane problems; fc_mlqd: multilevel time steps on Fleck-Cummings")
     ap.add_argument("--h-mat", type=float, nargs="+", default=[0.6], help="--workload fc_mlqd: material cell widths")
-    ap.add_argument("--h-moc", type=float, default=0.01, help="--workload fc_mlqd: characteristic spacing")
+    ap.add_argument("--h-moc", type=float, nargs="+", default=[0.01], help="--workload fc_mlqd: characteristic spacings")
+    ap.add_argument("--tubes", action="store_true", help="--workload fc_mlqd: the paper's vertex-avoiding grid")
     ap.add_argument("--eps", type=float, default=1e-12, help="--workload fc_mlqd: iteration tolerance")
     ap.add_argument("--config", type=int, default=2, help="workload index for --workload single (0, 1, 2 or 4)")
     ap.add_argument("--case", type=int, default=None, help="--workload split: run only this case (0, 1 or 2)")

@@ -482,6 +482,17 @@ lc_status lc_loqd_grey_meb(lc_loqd_t loqd, double c, double c_dt, const double* 
 lc_status lc_loqd_set_warm_start(lc_loqd_t loqd, int32_t enable);
 
 /*
+ * lc_loqd_set_solver -- how the handle's BiCGSTAB runs: 0 (default) by
+ * size, 1 one workgroup per group running the whole iteration in one
+ * launch (the default for face systems up to 16384 faces: no host round
+ * trips), 2 grids of blocks per vector operation with the host testing
+ * convergence every 8 iterations (the default above that).  The two
+ * iterate alike and differ only in the order of their sums, so their
+ * solutions agree within rtol.  Errors: LC_ERR_ARG, LC_ERR_STATE.
+ */
+lc_status lc_loqd_set_solver(lc_loqd_t loqd, int32_t mode);
+
+/*
  * Multilevel quasidiffusion (MLQD) time steps on the Fleck-Cummings test
  * material of the paper's results section: opacity 27/nu^3 (1 - e^(-nu/T))
  * at each group's representative frequency nu_g, material energy

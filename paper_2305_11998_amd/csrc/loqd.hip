@@ -33,10 +33,14 @@
 // so E_i is eliminated exactly:  E_i = (b_i - sum_k a_ik E_k) / d_i.  What
 // remains is a system in the face unknowns alone (at most 7 entries a row:
 // the face and the other faces of its one or two cells), solved for all
-// groups at once by BiCGSTAB with a Jacobi preconditioner.  Every inner
+// groups at once by BiCGSTAB with a Jacobi preconditioner: for small
+// systems by one workgroup per group that runs the whole iteration in one
+// launch, for large ones by grids of blocks per vector operation with the
+// host checking convergence every 8 iterations.  Every inner
 // product is a fixed-order reduction (no atomics), so results are
 // deterministic.  Then E_i and the face fluxes follow from the cell rows and
 // the half-cell relations.
+#include <algorithm>
 #include <cmath>
 #include <vector>
 
@@ -82,8 +86,16 @@ struct Loqd {
     double* d_sc = nullptr;           // [G][kScal] per-group scalars
     int* d_flag = nullptr;            // [G] 1 = iterating
     bool warm = false;                // BiCGSTAB starts from the E_face output's contents
+    int solver = 0;                   // 0 by size, 1 one workgroup per group, 2 many blocks per group
+    int* d_iters = nullptr;           // [G] iterations (one-workgroup solver)
+    double* d_resid = nullptr;        // [G] final relative residuals (one-workgroup solver)
     std::vector<void*> owned;
 };
+
+// Face systems up to this size are solved by one workgroup per group: the
+// whole iteration in one launch, reductions in LDS, no host round trips.
+constexpr int kSmallFaces = 16384;
+constexpr int kWG = 512;
 
 // per-group scalars
 enum { S_RHO = 0, S_ALPHA, S_OMEGA, S_BETA, S_BNORM, S_RNORM, S_TS, S_TT, S_RV, kScal };
@@ -379,6 +391,162 @@ __global__ void k_bi_x(Geo Q, Vecs V, const double* sc, const int* flag, double*
 }
 
 // Cell values from the face solution.
+// One workgroup per group: Jacobi-preconditioned BiCGSTAB on the face system
+// of group blockIdx.x, the same iteration as the many-block kernels above
+// (restart from the current x on breakdown, true-residual check when the
+// recursive residual reaches rtol, at most 3 of them).  Every scalar comes
+// from a fixed-order LDS reduction that all threads read, so the control
+// flow is uniform over the workgroup.  x starts from zero, or from its
+// contents with warm != 0.  iters[g], resid[g]: iterations and the final
+// relative residual (as the many-block path reports it).
+__device__ inline void wg_sum2(double& a, double& b, double* sa, double* sb) {
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int w = kWG / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sa[threadIdx.x] += sa[threadIdx.x + w];
+            sb[threadIdx.x] += sb[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    a = sa[0];
+    b = sb[0];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restrict__ val, const double* __restrict__ bv,
+                                                     const double* __restrict__ dinv, Vecs V, int warm, double rtol,
+                                                     int max_iter, int* iters, double* resid) {
+    __shared__ double sa[kWG], sb[kWG];
+    const int g = blockIdx.x, nf = Q.nf, tid = threadIdx.x;
+    const size_t o = (size_t)g * nf;
+    double *x = V.x + o, *r = V.r + o, *rh = V.rh + o, *p = V.p + o, *v = V.v + o;
+    double *s = V.s + o, *t = V.t + o, *ph = V.ph + o, *sh = V.sh + o;
+    const double* b = bv + o;
+    const double* di = dinv + o;
+    if (!warm)
+        for (int f = tid; f < nf; f += kWG) x[f] = 0.0;
+    __syncthreads();
+    // r = b - A x, rh = r, p = v = 0; returns (r, r) and (b, b)
+    auto restart = [&](double& rr, double& bb) {
+        rr = 0.0;
+        bb = 0.0;
+        for (int f = tid; f < nf; f += kWG) {
+            const double e = b[f] - spmv_row(Q, val, V.x, g, f);
+            r[f] = e;
+            rh[f] = e;
+            p[f] = 0.0;
+            v[f] = 0.0;
+            rr += e * e;
+            bb += b[f] * b[f];
+        }
+        wg_sum2(rr, bb, sa, sb);
+    };
+    double rr, bb;
+    restart(rr, bb);
+    const double bnorm = sqrt(bb);
+    if (bnorm == 0.0)                                 // b = 0: x = 0
+        for (int f = tid; f < nf; f += kWG) x[f] = 0.0;
+    double rho = rr, alpha = 1.0, omega = 1.0, beta = 0.0, rnorm = bnorm == 0.0 ? 0.0 : sqrt(rr);
+    int it = 0, checks = 0;
+    bool done = bnorm == 0.0 || rnorm <= rtol * bnorm;
+    while (bnorm > 0.0) {
+        if (done) {                                   // true residual
+            if (checks >= 3) break;
+            ++checks;
+            restart(rr, bb);
+            rnorm = sqrt(rr);
+            rho = rr;
+            alpha = omega = 1.0;
+            beta = 0.0;
+            if (rnorm <= rtol * bnorm) break;
+            done = false;
+        }
+        if (it >= max_iter) break;
+        ++it;
+        for (int f = tid; f < nf; f += kWG) {
+            const double pv = r[f] + beta * (p[f] - omega * v[f]);
+            p[f] = pv;
+            ph[f] = di[f] * pv;
+        }
+        __syncthreads();
+        double a = 0.0, c = 0.0;
+        for (int f = tid; f < nf; f += kWG) {
+            const double vv = spmv_row(Q, val, V.ph, g, f);
+            v[f] = vv;
+            a += rh[f] * vv;
+        }
+        wg_sum2(a, c, sa, sb);
+        if (a == 0.0 || !std::isfinite(a)) {          // breakdown: restart from x
+            restart(rr, bb);
+            rho = rr;
+            alpha = omega = 1.0;
+            beta = 0.0;
+            rnorm = sqrt(rr);
+            done = rnorm <= rtol * bnorm;
+            continue;
+        }
+        alpha = rho / a;
+        for (int f = tid; f < nf; f += kWG) {
+            const double sv = r[f] - alpha * v[f];
+            s[f] = sv;
+            sh[f] = di[f] * sv;
+        }
+        __syncthreads();
+        a = 0.0;
+        c = 0.0;
+        for (int f = tid; f < nf; f += kWG) {
+            const double tv = spmv_row(Q, val, V.sh, g, f);
+            t[f] = tv;
+            a += tv * s[f];
+            c += tv * tv;
+        }
+        wg_sum2(a, c, sa, sb);
+        omega = c > 0.0 ? a / c : 0.0;
+        a = 0.0;
+        c = 0.0;
+        for (int f = tid; f < nf; f += kWG) {
+            x[f] += alpha * ph[f] + omega * sh[f];
+            const double rv = s[f] - omega * t[f];
+            r[f] = rv;
+            a += rh[f] * rv;
+            c += rv * rv;
+        }
+        wg_sum2(a, c, sa, sb);
+        rnorm = sqrt(c);
+        if (rnorm <= rtol * bnorm) {
+            done = true;
+        } else if (a == 0.0 || omega == 0.0 || !std::isfinite(a)) {
+            restart(rr, bb);
+            rho = rr;
+            alpha = omega = 1.0;
+            beta = 0.0;
+            rnorm = sqrt(rr);
+            done = rnorm <= rtol * bnorm;
+        } else {
+            beta = (a / rho) * (alpha / omega);
+            rho = a;
+        }
+    }
+    // As the many-block path: the residual of the last test -- the true one
+    // after a passed check, the recursive one once the three checks are
+    // spent -- and the true one when the iterations ran out.
+    if (!done && bnorm > 0.0 && it >= max_iter) {
+        double e2 = 0.0, unused = 0.0;
+        for (int f = tid; f < nf; f += kWG) {
+            const double e = b[f] - spmv_row(Q, val, V.x, g, f);
+            e2 += e * e;
+        }
+        wg_sum2(e2, unused, sa, sb);
+        rnorm = sqrt(e2);
+    }
+    if (tid == 0) {
+        iters[g] = it;
+        resid[g] = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+    }
+}
+
 __global__ void k_loqd_back(Geo Q, const double* __restrict__ dc, const double* __restrict__ ac,
                             const double* __restrict__ bcv, const double* __restrict__ xf, double* E_cell,
                             double* E_face) {
@@ -641,6 +809,31 @@ lc_status solve_general(Loqd* q, const Geo& Q, const Gen& Cg, double* E_cell, do
     const size_t GF = (size_t)G * nf;
     Vecs V{q->d_vec, q->d_vec + GF, q->d_vec + 2 * GF, q->d_vec + 3 * GF, q->d_vec + 4 * GF, q->d_vec + 5 * GF,
            q->d_vec + 6 * GF, q->d_vec + 7 * GF, q->d_sh};
+    if (q->solver == 1 || (q->solver == 0 && nf <= kSmallFaces)) {
+        if (q->warm) LC_HIP(hipMemcpyAsync(V.x, E_face, GF * sizeof(double), hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(k_bicg_group, dim3(G), dim3(kWG), 0, st, Q, q->d_val, q->d_b, q->d_dinv, V, q->warm ? 1 : 0,
+                           rtol, max_iter, q->d_iters, q->d_resid);
+        hipLaunchKernelGGL(k_loqd_back, gmax, blk, 0, st, Q, q->d_dc, q->d_ac, q->d_bc, V.x, E_cell, E_face);
+        hipLaunchKernelGGL(k_loqd_flux, gf, blk, 0, st, Q, Cg, E_cell, E_face, F_face);
+        LC_HIP(hipGetLastError());
+        std::vector<int> hit(G);
+        std::vector<double> hres(G);
+        LC_HIP(hipMemcpyAsync(hit.data(), q->d_iters, G * sizeof(int), hipMemcpyDeviceToHost, st));
+        LC_HIP(hipMemcpyAsync(hres.data(), q->d_resid, G * sizeof(double), hipMemcpyDeviceToHost, st));
+        LC_HIP(hipStreamSynchronize(st));
+        int most = 0;
+        double worst = 0.0;
+        for (int g = 0; g < G; ++g) {
+            most = std::max(most, hit[g]);
+            if (resid) resid[g] = hres[g];
+            worst = std::max(worst, std::isfinite(hres[g]) ? hres[g] : INFINITY);
+        }
+        if (iters) *iters = most;
+        LC_CHECK(worst <= rtol, LC_ERR_UNSUPPORTED,
+                 "LOQD solve did not reach rtol %.3g: residual %.3g after %d iterations (limit %d)", rtol, worst, most,
+                 max_iter);
+        return LC_OK;
+    }
     std::vector<int> flag(G, 1), hflag(G, 1);
     std::vector<double> hsc((size_t)G * kScal);
     auto set_flags = [&](const std::vector<int>& fl) -> lc_status {
@@ -803,12 +996,22 @@ lc_status lc_loqd_create(int32_t nx, int32_t ny, double lx, double ly, int32_t G
     if (!rc) rc = dalloc(q->owned, &q->d_part, (size_t)G * q->nblk * 2);
     if (!rc) rc = dalloc(q->owned, &q->d_sc, (size_t)G * kScal);
     if (!rc) rc = dalloc(q->owned, &q->d_flag, (size_t)G);
+    if (!rc) rc = dalloc(q->owned, &q->d_iters, (size_t)G);
+    if (!rc) rc = dalloc(q->owned, &q->d_resid, (size_t)G);
     if (rc) {
         free_loqd(q);
         return rc;
     }
     q->magic = kLoqdMagic;
     *out = reinterpret_cast<lc_loqd_t>(q);
+    return LC_OK;
+}
+
+lc_status lc_loqd_set_solver(lc_loqd_t h, int32_t mode) {
+    Loqd* q = as_loqd(h);
+    LC_CHECK(q, LC_ERR_STATE, "invalid LOQD handle");
+    LC_ARG(mode >= 0 && mode <= 2, "mode must be 0, 1 or 2");
+    q->solver = mode;
     return LC_OK;
 }
 

@@ -79,6 +79,7 @@ _SIGS = {
     "lc_loqd_create": ([_i32, _i32, _d, _d, _i32, C.POINTER(_vp)], C.c_int),
     "lc_loqd_free": ([_vp], C.c_int),
     "lc_loqd_set_warm_start": ([_vp, _i32], C.c_int),
+    "lc_loqd_set_solver": ([_vp, _i32], C.c_int),
     "lc_mlqd_create": ([_vp, _vp, _vp, _d, _d, _d, C.POINTER(_vp)], C.c_int),
     "lc_mlqd_free": ([_vp], C.c_int),
     "lc_mlqd_set_acceleration": ([_vp, _i32], C.c_int),
@@ -555,6 +556,11 @@ def lc_loqd_grey_meb(h: Loqd, c, c_dt, kappa_E, kappa_B, E_prev, k_side, eta_sid
         C.byref(nit), C.byref(it), res.ctypes.data, _stream(stream)))
     return int(nit.value), int(it.value), res
 
+
+
+def lc_loqd_set_solver(h: Loqd, mode):
+    """0 by size, 1 one workgroup per group, 2 many blocks per group."""
+    _check(_lib.lc_loqd_set_solver(h.handle, int(mode)))
 
 
 def lc_loqd_set_warm_start(h: Loqd, enable=True):

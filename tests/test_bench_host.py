@@ -70,3 +70,22 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(os.path.dirname(bench.__file__), "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU only" in r.stderr
+
+
+def test_refinement_norms_of_the_multilevel_study():
+    """bench's refinement rows: cell-average restriction of the finer grid,
+    area-weighted L2 differences and their ratios."""
+    import numpy as np
+    import bench
+    n = 8
+    x = (np.arange(n) + 0.5) / n
+    fine = np.add.outer(x, x).ravel()                        # linear: restriction is exact
+    xc = (np.arange(n // 2) + 0.5) / (n // 2)
+    assert np.allclose(bench._restrict(fine, n), np.add.outer(xc, xc).ravel())
+    runs = [dict(h_mat=3.0, h_moc=0.1, T=np.full(4, 1.0), E=np.full(4, 2.0)),
+            dict(h_mat=1.5, h_moc=0.1, T=np.full(16, 1.2), E=np.full(16, 2.0)),
+            dict(h_mat=0.75, h_moc=0.1, T=np.full(64, 1.3), E=np.full(64, 2.5))]
+    rows = bench._refinement_rows(runs, "h_mat")
+    assert np.isclose(rows[0]["dT"], 0.2 * 6.0) and np.isclose(rows[1]["dT"], 0.1 * 6.0)
+    assert np.isclose(rows[1]["rho_T"], 2.0) and np.isclose(rows[0]["dT_rel"], 0.2 / 1.2)
+    assert rows[0]["dE"] == 0.0 and "rho_E" not in rows[1] and np.isclose(rows[1]["dE"], 0.5 * 6.0)

@@ -61,11 +61,12 @@ def _gpu_layouts(nx, ny, f_cell, f_face, bc):
 
 
 def _gpu_solve(lc, nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bc, rtol=1e-13,
-               max_iter=20000):
+               max_iter=20000, solver=0):
     import torch
     G = kappa.shape[0]
     fc, ff, bnd = _gpu_layouts(nx, ny, f_cell, f_face, bc)
     h = lc.Loqd(nx, ny, lx, ly, G)
+    lc.lc_loqd_set_solver(h, solver)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
     Ec = torch.zeros(G * h.cells, dtype=torch.float64, device="cuda")
     Ef = torch.zeros(G * h.nf, dtype=torch.float64, device="cuda")
@@ -113,14 +114,15 @@ def _random_groups(nx, ny, lx, ly, G, seed, thin=False):
     return (nx, ny, lx, ly, c, c_dt, kappa, planck, E_prev, F_prev, tensors(N), tensors(nf), bc)
 
 
+@pytest.mark.parametrize("solver", [1, 2])
 @pytest.mark.parametrize("shape", [(7, 5, 1.4, 0.7, 3), (33, 20, 3.3, 1.0, 5), (1, 6, 0.2, 1.2, 2), (9, 1, 0.9, 0.1, 2)])
-def test_loqd_random_coefficients(lcmod, shape):
+def test_loqd_random_coefficients(lcmod, shape, solver):
     lc, _ = lcmod
     nx, ny, lx, ly, G = shape
     args = _random_groups(nx, ny, lx, ly, G, seed=nx * 31 + ny)
-    _say(f"case loqd random {nx}x{ny} G={G}")
+    _say(f"case loqd random {nx}x{ny} G={G} solver {solver}")
     ref = OL.solve(*args)
-    got, it, res = _gpu_solve(lc, *args)
+    got, it, res = _gpu_solve(lc, *args, solver=solver)
     _say(f"  {it} iterations, residuals {np.max(res):.1e}")
     _compare(got, ref, "random")
 
@@ -501,3 +503,17 @@ def test_loqd_warm_start(lcmod):
     _say(f"case loqd warm start: iterations cold {it0}, warm {it1}")
     assert it1 < it0 and np.all(res <= 1e-13)
     _compare(warm, cold, "warm vs cold")
+
+
+
+def test_loqd_large_system_takes_the_block_path(lcmod):
+    """A face system above the one-workgroup size (95 x 90 cells, 17,285
+    faces) through the automatic choice, against the oracle."""
+    lc, _ = lcmod
+    args = _random_groups(95, 90, 6.0, 5.7, 1, seed=95)
+    _say("case loqd random 95x90 G=1 (automatic: block path)")
+    assert OL.n_faces(95, 90) > 16384
+    ref = OL.solve(*args)
+    got, it, res = _gpu_solve(lc, *args)
+    _say(f"  {it} iterations, residuals {np.max(res):.1e}")
+    _compare(got, ref, "large")
