@@ -108,6 +108,24 @@ int32_t lc_version(void);
 const char* lc_last_error(void);
 
 /*
+ * Process-wide settings for testing and debugging.
+ *
+ * lc_set_alloc_limit -- every later device allocation of the library larger
+ * than `bytes` fails (0: no limit, the default) as if the device were out of
+ * memory: the call that needed it returns LC_ERR_ALLOC and frees whatever it
+ * had allocated, so that error paths can be exercised on any GPU.
+ *
+ * lc_set_validation -- with enable != 0, lc_sweep, lc_sweep_points,
+ * lc_sweep_noalloc and lc_step first check kappa, planck (all the steps'
+ * values for lc_step) and I_in on the device for values that are not finite
+ * or are negative, and return LC_ERR_ARG naming the array and the first such
+ * index; this synchronises the stream.  Off by default (the checks cost a
+ * pass over the inputs).  The batched calls are not checked.
+ */
+lc_status lc_set_alloc_limit(uint64_t bytes);
+lc_status lc_set_validation(int32_t enable);
+
+/*
  * lc_build_rays -- characteristic grid for every azimuth pair.
  * Paper: characteristic coordinates and segment lengths (section on the
  * method of long characteristics), segment area eq. (14), the construction of
@@ -665,6 +683,12 @@ lc_status lc_plan_profile_read(lc_plan_t plan, double* out);
  * moments, and the outputs hold those of the last step.  The incoming
  * intensities I_in are the same for every step of a call (their float32
  * scale maxima are taken at its first step); they may change between calls.
+ * A call whose c differs from the previous call's rewrites the moment and
+ * boundary argument records, and first synchronises the device (a step
+ * launched earlier may still read them); calls with an unchanged c do not
+ * synchronise.  The captured step graph runs the moments of step t on a
+ * second stream beside the sweep of step t + 1 and joins it before the call
+ * returns its work to the caller's stream.
  * All problems must share one precision.  I_exit is required.  Errors of
  * lc_batch_create:
  * LC_ERR_ARG (no problems; a problem without kappa, planck, states, I_in or

@@ -2,6 +2,7 @@
 // graph-captured time step.  Every entry point checks its arguments before any
 // HIP call and reports failures as status codes.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstring>
@@ -50,6 +51,7 @@ void free_plan(Plan* pl) {
     if (pl->capture) (void)hipStreamDestroy(pl->capture);
     if (pl->d_coef) (void)hipFree(pl->d_coef);
     if (pl->d_gmax) (void)hipFree(pl->d_gmax);
+    if (pl->d_check) (void)hipFree(pl->d_check);
     if (pl->d_bun_off) (void)hipFree(pl->d_bun_off);
     if (pl->d_bun_len) (void)hipFree(pl->d_bun_len);
     if (pl->d_bun_base) (void)hipFree(pl->d_bun_base);
@@ -63,7 +65,55 @@ void free_plan(Plan* pl) {
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
+std::atomic<uint64_t> g_alloc_cap{0};
+std::atomic<int> g_validate{0};
+
+// Smallest index i < n with a[i] not finite or negative (atomicMin over the
+// index: the same answer however the threads are scheduled).
+__global__ void k_first_invalid(const double* __restrict__ a, int64_t n, unsigned long long* first) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const double v = a[i];
+        if (!(std::isfinite(v) && v >= 0.0)) atomicMin(first, (unsigned long long)i);
+    }
+}
+
 }  // namespace
+
+hipError_t lc_malloc(void** p, size_t bytes) {
+    const uint64_t cap = g_alloc_cap.load();
+    if (cap && bytes > cap) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+bool validation_on() { return g_validate.load() != 0; }
+
+lc_status validate_inputs(Plan* pl, const double* kappa, const double* planck, int64_t n_mat, const double* I_in,
+                          hipStream_t st) {
+    const Rays* r = pl->rays;
+    const struct {
+        const double* a;
+        int64_t n;
+        const char* name;
+    } arrays[3] = {{kappa, n_mat, "kappa"},
+                   {planck, n_mat, "planck"},
+                   {I_in, (int64_t)r->nb * r->n_az * r->n_pol * pl->G, "I_in"}};
+    for (const auto& x : arrays) {
+        const unsigned long long none = ~0ull;
+        LC_HIP(hipMemcpyAsync(pl->d_check, &none, sizeof(none), hipMemcpyHostToDevice, st));
+        const int64_t blocks = std::min<int64_t>((x.n + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_first_invalid, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, st, x.a, x.n,
+                           pl->d_check);
+        LC_HIP(hipGetLastError());
+        unsigned long long first = none;
+        LC_HIP(hipMemcpyAsync(&first, pl->d_check, sizeof(first), hipMemcpyDeviceToHost, st));
+        LC_HIP(hipStreamSynchronize(st));
+        LC_ARG(first == none, "%s[%llu] is not finite or is negative", x.name, first);
+    }
+    return LC_OK;
+}
 
 lc_status prof_begin(Plan* pl, std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, hipStream_t st) {
     if (!pl->profile || pl->capturing) return LC_OK;
@@ -91,6 +141,16 @@ lc_status prof_end(Plan* pl, std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, 
 using namespace lc;
 
 extern "C" {
+
+lc_status lc_set_alloc_limit(uint64_t bytes) {
+    g_alloc_cap.store(bytes);
+    return LC_OK;
+}
+
+lc_status lc_set_validation(int32_t enable) {
+    g_validate.store(enable != 0);
+    return LC_OK;
+}
 
 int32_t lc_version(void) { return 1 * 10000 + 4 * 100 + 0; }
 
@@ -266,12 +326,13 @@ lc_status lc_plan_create(lc_rays_t rays, int32_t G, int32_t prec, lc_plan_t* out
     if (rc == LC_OK) {
         const size_t coef_bytes = (size_t)r->cells * G * (prec == LC_F32 ? 8 : 16);
         const size_t nbun = (size_t)pl->n_bun;
-        e = hipMalloc(&pl->d_coef, coef_bytes);
+        e = lc_malloc(&pl->d_coef, coef_bytes);
         if (e == hipSuccess)
-            e = hipMalloc(reinterpret_cast<void**>(&pl->d_gmax), 2 * (size_t)G * sizeof(unsigned long long));
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_off), pl->bun_off.size() * sizeof(int));
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_len), std::max<size_t>(nbun, 1) * sizeof(int));
-        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_base), std::max<size_t>(nbun, 1) * sizeof(int64_t));
+            e = lc_malloc(reinterpret_cast<void**>(&pl->d_gmax), 2 * (size_t)G * sizeof(unsigned long long));
+        if (e == hipSuccess) e = lc_malloc(reinterpret_cast<void**>(&pl->d_check), sizeof(unsigned long long));
+        if (e == hipSuccess) e = lc_malloc(reinterpret_cast<void**>(&pl->d_bun_off), pl->bun_off.size() * sizeof(int));
+        if (e == hipSuccess) e = lc_malloc(reinterpret_cast<void**>(&pl->d_bun_len), std::max<size_t>(nbun, 1) * sizeof(int));
+        if (e == hipSuccess) e = lc_malloc(reinterpret_cast<void**>(&pl->d_bun_base), std::max<size_t>(nbun, 1) * sizeof(int64_t));
         if (e == hipSuccess)
             e = hipMemcpy(pl->d_bun_off, pl->bun_off.data(), pl->bun_off.size() * sizeof(int), hipMemcpyHostToDevice);
         if (e == hipSuccess)
@@ -341,6 +402,11 @@ lc_status lc_sweep(lc_plan_t plan, const double* kappa, const double* planck, do
            "kappa, planck, states and I_in must not be NULL");
     LC_ARG(state_prev != state_new, "state_prev and state_new must be distinct buffers");
     LC_ARG(finite_pos(c_dt), "c_dt must be finite and > 0");
+    if (validation_on()) {
+        lc_status rc = validate_inputs(pl, kappa, planck, (int64_t)pl->G * pl->rays->cells, I_in,
+                                       static_cast<hipStream_t>(stream));
+        if (rc) return rc;
+    }
     return launch_sweep(pl, kappa, planck, c_dt, state_prev, state_new, I_in, I_exit,
                         static_cast<hipStream_t>(stream));
 }
@@ -371,6 +437,11 @@ lc_status lc_sweep_points(lc_plan_t plan, const double* kappa, const double* pla
     LC_ARG(state_prev != state_new && points != state_prev && points != state_new,
            "state_prev, state_new and points must be distinct buffers");
     LC_ARG(finite_pos(c_dt), "c_dt must be finite and > 0");
+    if (validation_on()) {
+        lc_status rc = validate_inputs(pl, kappa, planck, (int64_t)pl->G * pl->rays->cells, I_in,
+                                       static_cast<hipStream_t>(stream));
+        if (rc) return rc;
+    }
     return launch_sweep(pl, kappa, planck, c_dt, state_prev, state_new, I_in, I_exit,
                         static_cast<hipStream_t>(stream), points);
 }
@@ -412,6 +483,12 @@ lc_status lc_step(lc_plan_t plan, int32_t n_steps, const double* kappa, const do
     LC_ARG(finite_pos(c_dt) && finite_pos(c), "c_dt and c must be finite and > 0");
     LC_ARG(!bnd || I_exit, "boundary factors need I_exit");
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (validation_on()) {
+        lc_status rc = validate_inputs(pl, kappa, planck,
+                                       (int64_t)(n_steps - 1) * material_stride + (int64_t)pl->G * pl->rays->cells,
+                                       I_in, st);
+        if (rc) return rc;
+    }
     uint64_t cdt_bits, c_bits;
     std::memcpy(&cdt_bits, &c_dt, 8);
     std::memcpy(&c_bits, &c, 8);

@@ -200,7 +200,7 @@ void free_batch(Batch* b) {
 }
 
 lc_status upload(void** dst, const void* src, size_t bytes) {
-    hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 1));
+    hipError_t e = lc_malloc(dst, std::max<size_t>(bytes, 1));
     if (e != hipSuccess) {
         (void)hipGetLastError();
         set_error("hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
@@ -285,7 +285,7 @@ lc_status lc_batch_create(int32_t n_problems, const lc_problem_t* problems, lc_b
     }
     {
         hipError_t e =
-            hipMalloc(reinterpret_cast<void**>(&b->d_gmax), 2 * (size_t)b->n_gmax * sizeof(unsigned long long));
+            lc_malloc(reinterpret_cast<void**>(&b->d_gmax), 2 * (size_t)b->n_gmax * sizeof(unsigned long long));
         if (e != hipSuccess) {
             (void)hipGetLastError();
             set_error("hipMalloc of the batch maxima failed: %s", hipGetErrorString(e));

@@ -14,6 +14,11 @@ namespace lc {
 
 void set_error(const char* fmt, ...);
 
+// Every device allocation of the library goes through lc_malloc, which
+// refuses (hipErrorOutOfMemory, nothing allocated) any request above the
+// process-wide cap set by lc_set_alloc_limit (0: no cap).
+hipError_t lc_malloc(void** p, size_t bytes);
+
 #define LC_HIP(expr)                                                          \
     do {                                                                      \
         hipError_t lc_e_ = (expr);                                            \
@@ -119,6 +124,7 @@ struct Plan {
     size_t value_bytes = 0;
     void* d_coef = nullptr;           // [cells][G] {kappa_t, kappa B / kappa_t}
     unsigned long long* d_gmax = nullptr;  // [2][G] per-group maxima of |B| and of |I_in| (float32 scale)
+    unsigned long long* d_check = nullptr; // first invalid input index (validation mode)
     int sweep_unroll = 0;             // steps whose loads are issued together (1, 2, 4, 8 or 16)
     int moments_entries = 0;          // C(i, m) entries per list in the moment pipeline (1..4)
     // State layout: the lanes (k, g) of pair a, g fastest, are cut into
@@ -155,6 +161,13 @@ struct Plan {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_sweep, ev_mom;
 };
 
+// Validation mode (lc_set_validation): when on, the sweep entry points check
+// kappa and planck (n_mat values each) and I_in for values that are not
+// finite or are negative before any launch; LC_ERR_ARG names the first.
+bool validation_on();
+lc_status validate_inputs(Plan* pl, const double* kappa, const double* planck, int64_t n_mat, const double* I_in,
+                          hipStream_t st);
+
 // Event pair around one kernel launch when the plan records timings.
 lc_status prof_begin(Plan* pl, std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, hipStream_t st);
 lc_status prof_end(Plan* pl, std::vector<std::pair<hipEvent_t, hipEvent_t>>& v, hipStream_t st);
@@ -173,7 +186,7 @@ template <typename T>
 lc_status dalloc(std::vector<void*>& owned, T** out, size_t n) {
     void* p = nullptr;
     size_t bytes = n ? n * sizeof(T) : sizeof(T);
-    hipError_t e = hipMalloc(&p, bytes);
+    hipError_t e = lc_malloc(&p, bytes);
     if (e != hipSuccess) {
         set_error("hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
         (void)hipGetLastError();

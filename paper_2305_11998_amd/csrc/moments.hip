@@ -481,7 +481,7 @@ lc_status plan_init_moments(Plan* pl) {
     {
         std::vector<unsigned> rec(std::max<size_t>((size_t)pl->n_bun, 1), 0u);
         for (int64_t B = 0; B < pl->n_bun; ++B) rec[B] = (unsigned)(pl->bun_base_h[B] / r->n_pol);
-        hipError_t e = hipMalloc(reinterpret_cast<void**>(&pl->d_bun_rec), rec.size() * sizeof(unsigned));
+        hipError_t e = lc_malloc(reinterpret_cast<void**>(&pl->d_bun_rec), rec.size() * sizeof(unsigned));
         if (e == hipSuccess) e = hipMemcpy(pl->d_bun_rec, rec.data(), rec.size() * sizeof(unsigned), hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -489,7 +489,7 @@ lc_status plan_init_moments(Plan* pl) {
             return LC_ERR_ALLOC;
         }
     }
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&pl->d_ent_off),
+    hipError_t e = lc_malloc(reinterpret_cast<void**>(&pl->d_ent_off),
                              std::max<size_t>((size_t)r->n_seg, 1) * 4 * sizeof(unsigned));
     if (e != hipSuccess) {
         (void)hipGetLastError();
@@ -520,7 +520,7 @@ lc_status plan_enable_faces(Plan* pl, hipStream_t st) {
     }
     if (pl->d_fent_off) return LC_OK;
     const int64_t n_keys = n_interior_faces(r) * r->n_pairs;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(&pl->d_fent_off),
+    hipError_t e = lc_malloc(reinterpret_cast<void**>(&pl->d_fent_off),
                              std::max<size_t>((size_t)r->n_fent, 1) * 4 * sizeof(unsigned));
     if (e != hipSuccess) {
         (void)hipGetLastError();

@@ -74,6 +74,11 @@ lc_status lc_sweep_noalloc(lc_plan_t plan, const double* kappa, const double* pl
     void* base = nullptr;
     lc_status rc = scratch_of(&base);
     if (rc) return rc;
+    if (validation_on()) {                       // the plan's check slot: allocated with the plan
+        rc = validate_inputs(pl, kappa, planck, (int64_t)pl->G * pl->rays->cells, I_in,
+                             static_cast<hipStream_t>(stream));
+        if (rc) return rc;
+    }
     SweepScratch ws;
     ws.coef = base;
     ws.gmax = reinterpret_cast<unsigned long long*>(static_cast<char*>(base) + coef_table_bytes(pl));

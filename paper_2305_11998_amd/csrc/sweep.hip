@@ -844,7 +844,7 @@ lc_status plan_set_split(Plan* pl, int len) {
     lc_status rc = LC_OK;
     auto put = [&](void** dst, const void* src, size_t bytes) {
         if (rc != LC_OK) return;
-        if (hipMalloc(dst, bytes) != hipSuccess) {
+        if (lc_malloc(dst, bytes) != hipSuccess) {
             (void)hipGetLastError();
             *dst = nullptr;
             set_error("hipMalloc of %zu bytes for the split sweep failed", bytes);

@@ -76,6 +76,8 @@ _SIGS = {
     "lc_state_import": ([_vp, _vp, _vp, _vp], C.c_int),
     "lc_sweep": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
     "lc_sweep_noalloc": ([_vp, _vp, _vp, _d, _vp, _vp, _vp, _vp, _vp], C.c_int),
+    "lc_set_alloc_limit": ([C.c_uint64], C.c_int),
+    "lc_set_validation": ([_i32], C.c_int),
     "lc_loqd_create": ([_i32, _i32, _d, _d, _i32, C.POINTER(_vp)], C.c_int),
     "lc_loqd_free": ([_vp], C.c_int),
     "lc_loqd_set_warm_start": ([_vp, _i32], C.c_int),
@@ -556,6 +558,16 @@ def lc_loqd_grey_meb(h: Loqd, c, c_dt, kappa_E, kappa_B, E_prev, k_side, eta_sid
         C.byref(nit), C.byref(it), res.ctypes.data, _stream(stream)))
     return int(nit.value), int(it.value), res
 
+
+
+def lc_set_alloc_limit(nbytes):
+    """Device allocations of the library above nbytes fail with LC_ERR_ALLOC (0: no limit)."""
+    _check(_lib.lc_set_alloc_limit(int(nbytes)))
+
+
+def lc_set_validation(enable):
+    """Check material and boundary inputs for non-finite or negative values before sweeps."""
+    _check(_lib.lc_set_validation(int(bool(enable))))
 
 
 def lc_loqd_set_solver(h: Loqd, mode):
