@@ -53,9 +53,9 @@ def test_validation_rejects_bad_inputs(lcmod):
         assert torch.equal(s.state[1], ref)
         for name, arr, idx, val in (("kappa", kap, 77, float("nan")), ("planck", pla, 5, -1.0),
                                     ("I_in", s.I_in, 123, float("inf"))):
-            bad = arr.clone()
+            bad = arr.clone().reshape(-1)
             bad[idx] = val
-            args = {"kappa": kap, "planck": pla, "I_in": s.I_in}
+            args = {"kappa": kap, "planck": pla, "I_in": s.I_in.reshape(-1)}
             args[name] = bad
             with pytest.raises(lc.LcError) as e:
                 _sweep(lc, s, args["kappa"], args["planck"], args["I_in"])
