@@ -395,30 +395,38 @@ __global__ void k_bi_x(Geo Q, Vecs V, const double* sc, const int* flag, double*
 // of group blockIdx.x, the same iteration as the many-block kernels above
 // (restart from the current x on breakdown, true-residual check when the
 // recursive residual reaches rtol, at most 3 of them).  Every scalar comes
-// from a fixed-order LDS reduction that all threads read, so the control
-// flow is uniform over the workgroup.  x starts from zero, or from its
+// from a fixed-order reduction that all threads read, so the control flow
+// is uniform over the workgroup.  x starts from zero, or from its
 // contents with warm != 0.  iters[g], resid[g]: iterations and the final
 // relative residual (as the many-block path reports it).
+// Within each wavefront a butterfly over the 64 lanes (lane 0's sum, whose
+// order is fixed, is the one kept), then the wavefronts' partials added in
+// wavefront order by every thread: two barriers a reduction.
 __device__ inline void wg_sum2(double& a, double& b, double* sa, double* sb) {
-    sa[threadIdx.x] = a;
-    sb[threadIdx.x] = b;
-    __syncthreads();
-    for (int w = kWG / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            sa[threadIdx.x] += sa[threadIdx.x + w];
-            sb[threadIdx.x] += sb[threadIdx.x + w];
-        }
-        __syncthreads();
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
     }
-    a = sa[0];
-    b = sb[0];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sa[w] = a;
+        sb[w] = b;
+    }
+    __syncthreads();
+    double ta = 0.0, tb = 0.0;
+    for (int k = 0; k < kWG / 64; ++k) {
+        ta += sa[k];
+        tb += sb[k];
+    }
+    a = ta;
+    b = tb;
     __syncthreads();
 }
 
 __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restrict__ val, const double* __restrict__ bv,
                                                      const double* __restrict__ dinv, Vecs V, int warm, double rtol,
                                                      int max_iter, int* iters, double* resid) {
-    __shared__ double sa[kWG], sb[kWG];
+    __shared__ double sa[kWG / 64], sb[kWG / 64];
     const int g = blockIdx.x, nf = Q.nf, tid = threadIdx.x;
     const size_t o = (size_t)g * nf;
     double *x = V.x + o, *r = V.r + o, *rh = V.rh + o, *p = V.p + o, *v = V.v + o;
