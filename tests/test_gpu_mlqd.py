@@ -73,8 +73,8 @@ def test_material_matches_the_oracle(lcmod):
     assert np.all(pla[~big] <= 1e-199 * rb.sum(0)[None, :].repeat(G, 0)[~big])
 
 
-def _oracle_steps(p, steps, eps):
-    g = OR.build(p.nx, p.ny, p.lx, p.ly, p.phi, p.h_moc)
+def _oracle_steps(p, steps, eps, mode=OR.UNIFORM):
+    g = OR.build(p.nx, p.ny, p.lx, p.ly, p.phi, p.h_moc, mode=mode)
     st = OS.initial_state(g, p.n_pol, p.state0)
     E0, F0 = OMQ.initial_low_order(p, C)
     T = np.full(p.cells, p.T0)
@@ -210,3 +210,29 @@ def test_mlqd_acceleration_keeps_the_fixed_point(lcmod):
     e = max(_normwise(a[k], b[k]) for k in ("T", "E_cell", "E_face", "F_face"))
     _say(f"  inner passes: plain {out[0][1]}, accelerated {out[3][1]}; difference {e:.2e}")
     assert out[3][1] < out[0][1] and e <= TOL
+
+
+
+def test_mlqd_steps_match_the_oracle_on_the_papers_grid(lcmod):
+    """The vertex-avoiding, width-halving characteristic grid (the paper's
+    construction), 5 x 5 cells of 1.2 cm, h_moc = 0.15 cm: two steps against
+    the oracle's, as on the equally spaced grid."""
+    lc, driver = lcmod
+    p = _fc(h_mat=1.2, h_moc=0.15, G=5)
+    eps = 1e-10
+    _say(f"case fc mlqd {p.nx}x{p.ny} G={p.G} tube grid, 2 steps, eps {eps}")
+    ref = _oracle_steps(p, 2, eps, mode=OR.TUBES)
+    rays = lc.lc_build_rays(p.nx, p.ny, p.lx, p.ly, p.phi, p.mu, p.omega, p.h_moc, lc.LC_RAYS_TUBES)
+    s = driver.MlqdSolver(p, rays=rays, eps=eps)
+    s.reset()
+    for n in range(2):
+        s.step(1)
+        got = s.solution()
+        r = ref[n]
+        outer, inner, ch = s.history[-1]
+        e = dict(T=_normwise(got["T"], r["T"]), E_cell=_normwise(got["E_cell"], r["E_cell"]),
+                 F_face=_normwise(got["F_face"], r["F_face"]), state=err_rel(s.state_canonical(), r["state"]))
+        _say(f"  step {n}: outer {outer} (oracle {r['outer']}), inner {inner} (oracle {r['inner']}); "
+             + " ".join(f"{k} {v:.2e}" for k, v in e.items()))
+        assert abs(outer - r["outer"]) <= 1
+        assert max(e.values()) <= TOL

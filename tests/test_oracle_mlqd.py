@@ -144,3 +144,46 @@ def test_mlqd_temperature_satisfies_its_energy_balance(fc_step):
         lhs = p.c_v * (T - Tp) / (p.c_dt / C)
         scale = np.max((4 * math.pi * kap * B).sum(0))
         assert np.max(np.abs(lhs - rhs)) <= 1e-8 * scale
+
+
+def _small_step(monkeypatch=None, max_outer=60, max_inner=1000):
+    p = _small_fc()
+    g, st, T0, E0, F0 = _start(p)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        r = mlqd.outer_step(g, p, st, T0, E0, F0, C, A_R, eps=1e-11, max_outer=max_outer, max_inner=max_inner)
+    return p, (T0, E0), r
+
+
+def _defects(p, prev, r):
+    T0, E0 = prev
+    hx, hy = p.lx / p.nx, p.ly / p.ny
+    gained = np.sum(p.c_v * (r["T"] - T0) + (r["E_cell"] - E0).sum(0)) * hx * hy
+    inflow = _boundary_inflow(p, r["F_face"])
+    kap = material.fc_opacity(p.nu, r["T"])
+    B = material.group_planck(p.edges, r["T"], A_R, C)
+    rhs = (C * kap * r["E_cell"] - 4 * math.pi * kap * B).sum(0)
+    lhs = p.c_v * (r["T"] - T0) / (p.c_dt / C)
+    meb = np.max(np.abs(lhs - rhs)) / np.max((4 * math.pi * kap * B).sum(0))
+    return abs(gained - inflow) / abs(inflow), meb
+
+
+def test_planted_mistakes_in_the_step_are_caught(monkeypatch):
+    """The pins of the step fail for plausible mistakes in its composition:
+    the grey problem given the current temperature instead of T^{n-1}, and
+    a multigroup solve that sees a slightly different opacity than the grey
+    coefficients."""
+    p, prev, r = _small_step()
+    good = _defects(p, prev, r)
+    assert good[0] <= 1e-8 and good[1] <= 1e-8
+    real_low = mlqd.low_order
+    monkeypatch.setattr(mlqd, "low_order", lambda prob, T_start, T_prev, *a, **k: real_low(prob, T_start, T_start,
+                                                                                          *a, **k))
+    p, prev, r = _small_step(max_outer=8, max_inner=60)
+    assert max(_defects(p, prev, r)) > 1e-6
+    monkeypatch.setattr(mlqd, "low_order", real_low)
+    real_solve = loqd.solve
+    monkeypatch.setattr(loqd, "solve", lambda nx, ny, lx, ly, c, c_dt, kappa, *a: real_solve(nx, ny, lx, ly, c, c_dt,
+                                                                                          kappa * (1 + 1e-6), *a))
+    p, prev, r = _small_step(max_outer=20, max_inner=200)
+    assert _defects(p, prev, r)[1] > 1e-8
