@@ -373,10 +373,15 @@ lc_status lc_grey_closures_dims(int32_t cells, int32_t G, const double* E, const
  * mixed terms cancel in each cell balance, so a cell row holds its own four
  * faces only) and the face system of every group is solved by BiCGSTAB
  * with a Jacobi preconditioner, all groups at once, to a relative residual
- * rtol of the face system (its true residual is checked at the end, up to
- * three restarts); inner products are fixed-order reductions, so results
- * are deterministic.  iters (host, may be NULL) receives the iterations
- * run; resid (host [G], may be NULL) each group's final relative residual.
+ * rtol of the face system (its true residual is checked when the recursive
+ * one reaches rtol, up to three times); inner products are fixed-order
+ * reductions, so results are deterministic.  Face systems of up to 16384
+ * faces run the whole iteration in one launch, one workgroup per group;
+ * larger ones one launch per vector operation (lc_loqd_set_solver chooses
+ * explicitly).  The iteration starts from zero, or from E_face's contents
+ * after lc_loqd_set_warm_start.  iters (host, may be NULL) receives the
+ * iterations run (the most of any group); resid (host [G], may be NULL)
+ * each group's final relative residual.
  * Synchronises `stream` (convergence checks), so it cannot be captured in a
  * graph.  Errors: LC_ERR_ARG (NULL inputs or outputs, c or c_dt not finite
  * or <= 0, rtol outside (0, 1), max_iter < 1), LC_ERR_STATE (invalid
