@@ -397,7 +397,8 @@ lc_status lc_mlqd_create(lc_plan_t plan, const double* nu, const double* edges, 
     if (hipMemcpy(h->d_nu, nu, G * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->d_edges, edges, (G + 1) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->d_bern, bern.data(), kBern * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemset(h->d_Egf, 0, nf * sizeof(double)) != hipSuccess) {
+        hipMemset(h->d_Egf, 0, nf * sizeof(double)) != hipSuccess ||
+        hipMemset(h->d_Eg_old, 0, N * sizeof(double)) != hipSuccess) {
         set_error("HIP error uploading the material tables");
         return fail(LC_ERR_HIP);
     }
