@@ -604,6 +604,41 @@ def _refinement_rows(runs, key, L=6.0):
     return rows
 
 
+def _mlqd_leg(steps=5, h_mat=0.3, h_moc=0.01):
+    """A short run of the multilevel time step (the --workload fc_mlqd leg)
+    for the default bench line: `steps` steps from T^0 on the 20 x 20
+    Fleck-Cummings grid, 17 groups, 144 directions."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2305_11998_amd import driver
+    prob = W.fc_mlqd(h_mat, h_moc, 36, 4, 17, nu_lo=0.3, nu_hi=30.0)
+    s = driver.MlqdSolver(prob, eps=1e-12, max_outer=200, max_inner=2000)
+    s.reset()
+    prev = dict(T=np.full(prob.cells, prob.T0), E_cell=4 * np.pi * prob.state0 / W.C_LIGHT)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    defect = 0.0
+    total = 0.0
+    for _ in range(steps):
+        e0.record()
+        s.step(1)
+        e1.record()
+        torch.cuda.synchronize()
+        total += e0.elapsed_time(e1)
+        got = s.solution()
+        defect = max(defect, _fc_energy_defect(prob, prev, got, W.C_LIGHT))
+        prev = got
+    _say(f"multilevel steps: {total / steps:.1f} ms per step")
+    return {"metric": "fc_mlqd_time_steps_per_s", "value": 1000.0 * steps / total, "unit": "steps/s",
+            "ms_per_step": total / steps, "steps": steps,
+            "mean_transport_iterations": sum(h[0] for h in s.history) / steps,
+            "mean_low_order_iterations": sum(h[1] for h in s.history) / steps, "max_energy_defect": defect,
+            "dtype": "f64",
+            "workload": f"multilevel time steps from T^0, Fleck-Cummings, {prob.nx}x{prob.ny} cells (h_mat {h_mat} cm), "
+                        f"17 groups, 144 directions, h_moc {h_moc} cm, eps 1e-12"}
+
+
 def main_fc_mlqd(args):
     """Multilevel (MLQD) time steps on the Fleck-Cummings problem at the
     paper's counts: 6 x 6 cm, 17 groups, 144 directions (36 x 4), Delta t =
@@ -710,6 +745,7 @@ def main():
                     help="steps over which the float32 moments are compared with float64 ones")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--no-mlqd", action="store_true", help="leave the short multilevel-step leg out of the default line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 4 GiB buffer three times (scales the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -823,6 +859,8 @@ def main():
                      "step_algorithmic_bytes": step_alg, "step_achieved": step_achieved,
                      "step_frac": step_achieved / HBM_PEAK_GBS},
     }
+    if not args.no_mlqd:
+        out["fc_mlqd"] = _mlqd_leg()
     if not args.no_cpu_baseline:
         _say("cpu baseline (oracle sample)")
         big = max(range(len(probs)), key=lambda j: probs[j].cells * probs[j].G * probs[j].M)
