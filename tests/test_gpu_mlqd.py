@@ -7,11 +7,12 @@ to 1e-14 relative, group Planck functions (series and tails in the
 library, adaptive quadrature in the oracle) to 1e-11 relative wherever B_g
 is above 1e-200 of the group sum.  A time step is an iteration to a
 fixed point that both sides stop once the temperature changes by at most
-eps = 1e-10 between iterations; with contraction factors up to about 0.8
-(the inner low-order iterations) each side sits within about 4 eps of the
-fixed point, and the inner solves add 1e-13 times the condition number.
-T, E and F (normwise per group) and the transport state are compared at
-1e-8."""
+eps = 1e-11 between iterations; with contraction factors up to about 0.8
+each side sits within a few eps of the fixed point in T, and the
+intensities of groups in the Wien tail of a cold cell move by (nu/T) dT/T,
+up to a few hundred times more; the low-order solves add their residual
+(1e-13 at the end) times the condition number.  T, E and F (normwise per
+group) and the transport state are compared at 1e-8."""
 import math
 import sys
 import warnings
@@ -96,7 +97,7 @@ def _normwise(a, b):
 def test_mlqd_steps_match_the_oracle(lcmod):
     lc, driver = lcmod
     p = _fc()
-    eps = 1e-10
+    eps = 1e-11
     _say(f"case fc mlqd {p.nx}x{p.ny} G={p.G} M={len(p.omega)}, 2 steps, eps {eps}")
     ref = _oracle_steps(p, 2, eps)
     s = driver.MlqdSolver(p, eps=eps)
@@ -219,7 +220,7 @@ def test_mlqd_steps_match_the_oracle_on_the_papers_grid(lcmod):
     the oracle's, as on the equally spaced grid."""
     lc, driver = lcmod
     p = _fc(h_mat=1.2, h_moc=0.15, G=5)
-    eps = 1e-10
+    eps = 1e-11
     _say(f"case fc mlqd {p.nx}x{p.ny} G={p.G} tube grid, 2 steps, eps {eps}")
     ref = _oracle_steps(p, 2, eps, mode=OR.TUBES)
     rays = lc.lc_build_rays(p.nx, p.ny, p.lx, p.ly, p.phi, p.mu, p.omega, p.h_moc, lc.LC_RAYS_TUBES)
