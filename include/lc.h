@@ -507,9 +507,10 @@ lc_status lc_loqd_set_warm_start(lc_loqd_t loqd, int32_t enable);
 /*
  * lc_loqd_set_solver -- how the handle's BiCGSTAB runs: 0 (default) by
  * size, 1 one workgroup per group running the whole iteration in one
- * launch (the default for face systems up to 16384 faces: no host round
- * trips), 2 grids of blocks per vector operation with the host testing
- * convergence every 8 iterations (the default above that).  The two
+ * launch (face systems up to 16384 faces, the default there: no host round
+ * trips; larger systems run as 2), 2 grids of blocks per vector operation
+ * with the host testing convergence every 8 iterations (the default above
+ * 16384 faces).  The two
  * iterate alike and differ only in the order of their sums, so their
  * solutions agree within rtol.  Errors: LC_ERR_ARG, LC_ERR_STATE.
  */

@@ -423,9 +423,17 @@ __device__ inline void wg_sum2(double& a, double& b, double* sa, double* sb) {
     __syncthreads();
 }
 
+// R: a bound on the rows each thread owns (nf <= R kWG).  With R <= 8
+// (nf <= 4096, 32 KB) the vector a product gathers from is also kept in LDS
+// (ph, sh, or x for a residual), so the gathers are LDS reads (19 instead
+// of 24 us an iteration at 3,280 faces; unrolling the row loops, which
+// spills registers, made it slower).
+template <int R>
 __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restrict__ val, const double* __restrict__ bv,
                                                      const double* __restrict__ dinv, Vecs V, int warm, double rtol,
                                                      int max_iter, int* iters, double* resid) {
+    constexpr bool kLds = R <= 8;
+    extern __shared__ double gsv[];                   // [nf] the gathered vector (kLds)
     __shared__ double sa[kWG / 64], sb[kWG / 64];
     const int g = blockIdx.x, nf = Q.nf, tid = threadIdx.x;
     const size_t o = (size_t)g * nf;
@@ -433,29 +441,51 @@ __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restr
     double *s = V.s + o, *t = V.t + o, *ph = V.ph + o, *sh = V.sh + o;
     const double* b = bv + o;
     const double* di = dinv + o;
-    if (!warm)
-        for (int f = tid; f < nf; f += kWG) x[f] = 0.0;
+    auto rows = [&](auto fn) {
+#pragma unroll 1
+        for (int j = 0; j < R; ++j) {
+            const int f = tid + j * kWG;
+            if (f < nf) fn(f);
+        }
+    };
+    // row f of A times u (u: this group's vector; read from LDS when staged)
+    auto prod = [&](const double* u, int f) -> double {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            const int cidx = Q.col[(size_t)k * nf + f];
+            const double a = val[((size_t)g * kSlots + k) * nf + f];
+            acc += a * (kLds ? gsv[cidx] : u[cidx]);
+        }
+        return acc;
+    };
+    // make u readable by the products of every thread
+    auto stage = [&](const double* u) {
+        if constexpr (kLds) rows([&](int f) { gsv[f] = u[f]; });
+        __syncthreads();
+    };
+    if (!warm) rows([&](int f) { x[f] = 0.0; });
     __syncthreads();
     // r = b - A x, rh = r, p = v = 0; returns (r, r) and (b, b)
     auto restart = [&](double& rr, double& bb) {
+        stage(x);
         rr = 0.0;
         bb = 0.0;
-        for (int f = tid; f < nf; f += kWG) {
-            const double e = b[f] - spmv_row(Q, val, V.x, g, f);
+        rows([&](int f) {
+            const double e = b[f] - prod(x, f);
             r[f] = e;
             rh[f] = e;
             p[f] = 0.0;
             v[f] = 0.0;
             rr += e * e;
             bb += b[f] * b[f];
-        }
+        });
         wg_sum2(rr, bb, sa, sb);
     };
     double rr, bb;
     restart(rr, bb);
     const double bnorm = sqrt(bb);
-    if (bnorm == 0.0)                                 // b = 0: x = 0
-        for (int f = tid; f < nf; f += kWG) x[f] = 0.0;
+    if (bnorm == 0.0) rows([&](int f) { x[f] = 0.0; });   // b = 0: x = 0
     double rho = rr, alpha = 1.0, omega = 1.0, beta = 0.0, rnorm = bnorm == 0.0 ? 0.0 : sqrt(rr);
     int it = 0, checks = 0;
     bool done = bnorm == 0.0 || rnorm <= rtol * bnorm;
@@ -473,18 +503,20 @@ __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restr
         }
         if (it >= max_iter) break;
         ++it;
-        for (int f = tid; f < nf; f += kWG) {
+        rows([&](int f) {
             const double pv = r[f] + beta * (p[f] - omega * v[f]);
+            const double q = di[f] * pv;
             p[f] = pv;
-            ph[f] = di[f] * pv;
-        }
+            ph[f] = q;
+            if constexpr (kLds) gsv[f] = q;
+        });
         __syncthreads();
         double a = 0.0, c = 0.0;
-        for (int f = tid; f < nf; f += kWG) {
-            const double vv = spmv_row(Q, val, V.ph, g, f);
+        rows([&](int f) {
+            const double vv = prod(ph, f);
             v[f] = vv;
             a += rh[f] * vv;
-        }
+        });
         wg_sum2(a, c, sa, sb);
         if (a == 0.0 || !std::isfinite(a)) {          // breakdown: restart from x
             restart(rr, bb);
@@ -496,31 +528,33 @@ __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restr
             continue;
         }
         alpha = rho / a;
-        for (int f = tid; f < nf; f += kWG) {
+        rows([&](int f) {
             const double sv = r[f] - alpha * v[f];
+            const double q = di[f] * sv;
             s[f] = sv;
-            sh[f] = di[f] * sv;
-        }
+            sh[f] = q;
+            if constexpr (kLds) gsv[f] = q;
+        });
         __syncthreads();
         a = 0.0;
         c = 0.0;
-        for (int f = tid; f < nf; f += kWG) {
-            const double tv = spmv_row(Q, val, V.sh, g, f);
+        rows([&](int f) {
+            const double tv = prod(sh, f);
             t[f] = tv;
             a += tv * s[f];
             c += tv * tv;
-        }
+        });
         wg_sum2(a, c, sa, sb);
         omega = c > 0.0 ? a / c : 0.0;
         a = 0.0;
         c = 0.0;
-        for (int f = tid; f < nf; f += kWG) {
+        rows([&](int f) {
             x[f] += alpha * ph[f] + omega * sh[f];
             const double rv = s[f] - omega * t[f];
             r[f] = rv;
             a += rh[f] * rv;
             c += rv * rv;
-        }
+        });
         wg_sum2(a, c, sa, sb);
         rnorm = sqrt(c);
         if (rnorm <= rtol * bnorm) {
@@ -541,11 +575,12 @@ __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restr
     // after a passed check, the recursive one once the three checks are
     // spent -- and the true one when the iterations ran out.
     if (!done && bnorm > 0.0 && it >= max_iter) {
+        stage(x);
         double e2 = 0.0, unused = 0.0;
-        for (int f = tid; f < nf; f += kWG) {
-            const double e = b[f] - spmv_row(Q, val, V.x, g, f);
+        rows([&](int f) {
+            const double e = b[f] - prod(x, f);
             e2 += e * e;
-        }
+        });
         wg_sum2(e2, unused, sa, sb);
         rnorm = sqrt(e2);
     }
@@ -817,10 +852,23 @@ lc_status solve_general(Loqd* q, const Geo& Q, const Gen& Cg, double* E_cell, do
     const size_t GF = (size_t)G * nf;
     Vecs V{q->d_vec, q->d_vec + GF, q->d_vec + 2 * GF, q->d_vec + 3 * GF, q->d_vec + 4 * GF, q->d_vec + 5 * GF,
            q->d_vec + 6 * GF, q->d_vec + 7 * GF, q->d_sh};
-    if (q->solver == 1 || (q->solver == 0 && nf <= kSmallFaces)) {
+    if (q->solver != 2 && nf <= kSmallFaces) {
         if (q->warm) LC_HIP(hipMemcpyAsync(V.x, E_face, GF * sizeof(double), hipMemcpyDeviceToDevice, st));
-        hipLaunchKernelGGL(k_bicg_group, dim3(G), dim3(kWG), 0, st, Q, q->d_val, q->d_b, q->d_dinv, V, q->warm ? 1 : 0,
-                           rtol, max_iter, q->d_iters, q->d_resid);
+        {
+            const int rows_per_thread = (nf + kWG - 1) / kWG;
+            const size_t lds = rows_per_thread <= 8 ? (size_t)nf * sizeof(double) : 0;
+            const int wv = q->warm ? 1 : 0;
+            auto go = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3(G), dim3(kWG), lds, st, Q, q->d_val, q->d_b, q->d_dinv, V, wv, rtol,
+                                   max_iter, q->d_iters, q->d_resid);
+            };
+            if (rows_per_thread <= 1) go(k_bicg_group<1>);
+            else if (rows_per_thread <= 2) go(k_bicg_group<2>);
+            else if (rows_per_thread <= 4) go(k_bicg_group<4>);
+            else if (rows_per_thread <= 8) go(k_bicg_group<8>);
+            else if (rows_per_thread <= 16) go(k_bicg_group<16>);
+            else go(k_bicg_group<32>);
+        }
         hipLaunchKernelGGL(k_loqd_back, gmax, blk, 0, st, Q, q->d_dc, q->d_ac, q->d_bc, V.x, E_cell, E_face);
         hipLaunchKernelGGL(k_loqd_flux, gf, blk, 0, st, Q, Cg, E_cell, E_face, F_face);
         LC_HIP(hipGetLastError());
