@@ -540,8 +540,10 @@ lc_status lc_loqd_set_solver(lc_loqd_t loqd, int32_t mode);
  * B_g(T) = (a_R c T^4 / 4 pi)(15/pi^4) int over [nu_{g-1}/T, nu_g/T] of
  * x^3/(e^x - 1) dx (per steradian, the 4 pi kappa B of eq. (4a)).
  *
- * lc_mlqd_create -- for a plan (its grid, quadrature, characteristic grid
- * and G; interior-face lists are enabled on it, as lc_plan_enable_faces):
+ * lc_mlqd_create -- for a float64 plan (its grid, quadrature,
+ * characteristic grid and G; interior-face lists are enabled on it, as
+ * lc_plan_enable_faces; a float32 plan is refused with LC_ERR_UNSUPPORTED,
+ * since the iterations converge far below the float32 sweep's rounding):
  * nu [G] (host, keV, > 0) the opacity frequencies; edges [G + 1] (host,
  * keV, increasing, edges[0] >= 0, only edges[G] may be +infinity: with 0
  * and infinity the groups sum to a_R c T^4 / 4 pi); c, c_v, a_R > 0 in the

@@ -329,6 +329,9 @@ lc_status lc_mlqd_create(lc_plan_t plan, const double* nu, const double* edges, 
     *out = nullptr;
     Plan* pl = as_plan(plan);
     LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
+    LC_CHECK(pl->prec == LC_F64, LC_ERR_UNSUPPORTED,
+             "the multilevel step needs a float64 plan: its iterations converge to tolerances far below the float32 "
+             "sweep's rounding");
     LC_ARG(nu && edges, "nu and edges must not be NULL");
     LC_ARG(std::isfinite(c) && c > 0.0 && std::isfinite(c_v) && c_v > 0.0 && std::isfinite(a_R) && a_R > 0.0,
            "c, c_v and a_R must be finite and > 0");

@@ -184,13 +184,16 @@ def test_mlqd_steps_conserve_energy_at_the_papers_counts(lcmod, h_mat, h_moc):
         prev = got
 
 
-def test_mlqd_reports_non_convergence(lcmod):
+def test_mlqd_reports_non_convergence_and_refuses_float32(lcmod):
     lc, driver = lcmod
     p = _fc(h_mat=1.5, h_moc=0.3, G=4)
     s = driver.MlqdSolver(p, eps=1e-12, max_outer=1)
     s.reset()
     with pytest.raises(lc.LcError) as e:
         s.step(1)
+    assert e.value.status == lc.LC_ERR_UNSUPPORTED
+    with pytest.raises(lc.LcError) as e:
+        driver.MlqdSolver(p, prec=lc.LC_F32)
     assert e.value.status == lc.LC_ERR_UNSUPPORTED
 
 
