@@ -569,9 +569,13 @@ lc_status lc_loqd_set_solver(lc_loqd_t loqd, int32_t mode);
  * E_cell [G][cells], E_face, F_face [G][nf] of the last inner iteration
  * (the next step's E_prev and F_prev: use other buffers); E_grey [cells]
  * (may be NULL) the grey cell energy.  outer_iters, inner_iters (total),
- * changes [2] (the last dT, dE) may be NULL.  Inner solves: BiCGSTAB to
- * rtol 1e-13, Newton to max(min(eps, 1e-11), 1e-13).  eps much below 1e-12
- * may not be reachable in float64.  Synchronises the stream many times.
+ * changes [2] (the last dT, dE) may be NULL.  Inner solves: BiCGSTAB to a
+ * relative residual of 1e-3 times the last change, within [1e-13, 1e-8]
+ * (the pass that ends the inner iteration at 1e-13), Newton to
+ * max(min(eps, 1e-11), 1e-13).  eps much below 1e-12 may not be reachable in
+ * float64.  The low-order solves of a step start cold and there are no
+ * floating-point atomics, so a step's results depend on its arguments alone
+ * (the same bits on every call).  Synchronises the stream many times.
  * Errors: LC_ERR_ARG (NULL, aliased states, c_dt or eps not finite or
  * <= 0, max_outer or max_inner < 1), LC_ERR_STATE, LC_ERR_UNSUPPORTED (an
  * inner solve failed, or the step did not converge within max_outer
@@ -661,6 +665,34 @@ lc_status lc_plan_set_sweep_residency(lc_plan_t plan, int32_t capped);
  * split turned off); LC_ERR_HIP.
  */
 lc_status lc_plan_set_split(lc_plan_t plan, int32_t chunk_steps);
+
+/*
+ * Gathers split over azimuth pairs, for plans whose (cell, group) lanes are
+ * too few to fill the device while every C(i, m) list is long (a fine
+ * characteristic grid over a coarse material grid, as in the refinement
+ * studies of the numerical-results section).  The moments of eq. (7),
+ * (14)-(16) sum, per (cell or interior face, group), the direction averages
+ * of every azimuth pair; split, one lane per (pair, cell, group) sums its
+ * pair's list and stores the pair's seven partial sums, and a second launch
+ * adds them in pair order.  The boundary factors split the same way, one
+ * lane per ((pair, traversal), boundary face, group) summing the exit
+ * intensities, the combining launch forming the factors.  Both forms add the
+ * same terms in the same order, so results are bit-identical either way.
+ * mode: 1 splits the cell and face gathers and the boundary factors, 0 runs
+ * them whole, -1 (the default at lc_plan_create) chooses per gather: the
+ * moments split when the plan's tiles hold fewer than 2048 wavefronts and
+ * the lists average at least 8 entries, the boundary factors when
+ * nb * G < 131072 and at least 8 characteristics per (face, pair) exit.  A
+ * split plan holds a device buffer of n_pairs * 7 * (its largest gather
+ * grid's lanes) values of its precision, or 2 n_pairs (n_pol + 1) nb G
+ * doubles if larger.  Batched steps always run whole gathers.
+ * lc_plan_get_moment_split returns the forms in use (bit 0: moments, bit 1:
+ * boundary factors).  Setting synchronises the device and drops the plan's
+ * captured graphs.  Errors: LC_ERR_ARG for a mode outside -1..1;
+ * LC_ERR_ALLOC (the plan is then left with whole gathers); LC_ERR_HIP.
+ */
+lc_status lc_plan_set_moment_split(lc_plan_t plan, int32_t mode);
+lc_status lc_plan_get_moment_split(lc_plan_t plan, int32_t* mode);
 
 /*
  * Kernel timers (tracing).  lc_plan_profile(plan, 1) makes every following

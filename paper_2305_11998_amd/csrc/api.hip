@@ -58,6 +58,7 @@ void free_plan(Plan* pl) {
     if (pl->d_ent_off) (void)hipFree(pl->d_ent_off);
     if (pl->d_fent_off) (void)hipFree(pl->d_fent_off);
     if (pl->d_bun_rec) (void)hipFree(pl->d_bun_rec);
+    if (pl->d_mom_part) (void)hipFree(pl->d_mom_part);
     plan_free_split(pl);
     pl->magic = 0;
     delete pl;
@@ -579,6 +580,25 @@ lc_status lc_plan_set_split(lc_plan_t plan, int32_t chunk_steps) {
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     pl->graphs.clear();
     return plan_set_split(pl, chunk_steps);
+}
+
+lc_status lc_plan_set_moment_split(lc_plan_t plan, int32_t mode) {
+    Plan* pl = as_plan(plan);
+    LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
+    LC_ARG(mode >= -1 && mode <= 1, "mode must be -1 (automatic), 0 (whole) or 1 (split)");
+    LC_HIP(hipDeviceSynchronize());   // no captured step of the plan is still running
+    for (auto& g : pl->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    pl->graphs.clear();
+    return plan_set_moment_split(pl, mode);
+}
+
+lc_status lc_plan_get_moment_split(lc_plan_t plan, int32_t* mode) {
+    Plan* pl = as_plan(plan);
+    LC_CHECK(pl, LC_ERR_STATE, "invalid plan handle");
+    LC_ARG(mode, "mode is NULL");
+    *mode = pl->mom_split;
+    return LC_OK;
 }
 
 lc_status lc_plan_get_tuning(lc_plan_t plan, lc_tuning_t* t) {

@@ -144,6 +144,12 @@ struct Plan {
     unsigned* d_fent_off = nullptr;   // [n_fent][4] the same for the interior-face crossings (on request)
     unsigned* d_bun_rec = nullptr;    // [n_bun] first lane record of each bundle
     int tile_w = 1, tile_h = 1;       // cell tile of the moments kernel
+    // gathers split over azimuth pairs (lc_plan_set_moment_split): bit 0 the
+    // cell and face moments, bit 1 the boundary factors; per-pair partial
+    // sums in d_mom_part, combined in pair order by a second kernel
+    int mom_split = 0;
+    void* d_mom_part = nullptr;
+    size_t mom_part_bytes = 0;
     int64_t sweep_blocks = 0;         // blocks of one sweep launch
     size_t sweep_lds = 0;             // LDS reserved per sweep block (caps the blocks per CU)
     // split sweep (lc_plan_set_split): traversals cut into chunks of
@@ -220,6 +226,7 @@ lc_status plan_init_sweep(Plan* pl);
 lc_status plan_set_split(Plan* pl, int len);
 void plan_free_split(Plan* pl);
 lc_status plan_init_moments(Plan* pl);
+lc_status plan_set_moment_split(Plan* pl, int mode);
 lc_status plan_enable_faces(Plan* pl, hipStream_t st);
 lc_status launch_face_moments(Plan* pl, const void* point, const void* state, double c, double* E, double* F,
                               double* f, hipStream_t st);

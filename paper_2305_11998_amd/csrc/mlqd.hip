@@ -459,7 +459,11 @@ lc_status lc_mlqd_step(lc_mlqd_t handle, double c_dt, const void* state_prev, vo
     double level = 1.0;
     const size_t bytesN = N * sizeof(double);
     LC_HIP(hipMemcpyAsync(h->d_Ts, T_prev, bytesN, hipMemcpyDeviceToDevice, st));
-    LC_HIP(hipMemsetAsync(E_face, 0, (size_t)G * nf * sizeof(double), st));   // first multigroup solve: cold start
+    // The first multigroup and grey solves of a step start cold, so a step's
+    // result depends on its arguments alone, not on the steps the handle ran
+    // before; later passes start from the previous pass's solution.
+    LC_HIP(hipMemsetAsync(E_face, 0, (size_t)G * nf * sizeof(double), st));
+    LC_HIP(hipMemsetAsync(h->d_Egf, 0, (size_t)nf * sizeof(double), st));
     int s = 0, inner = 0;
     double dT = INFINITY, dE = INFINITY;
     lc_status rc = LC_OK;

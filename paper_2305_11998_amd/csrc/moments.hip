@@ -130,6 +130,62 @@ __device__ __forceinline__ void load_entry(gptr<const T> st, size_t o, int P, T 
     }
 }
 
+// Cell and group of lane tid of a tile of tw x th cells (false for the
+// lanes past the tile's cells or the grid's edge).
+__device__ __forceinline__ bool tile_lane(const MomArgs& A, int64_t tile, int tid, int& cell, int& g) {
+    const int cl = tid / A.G;
+    g = tid - cl * A.G;
+    if (cl >= A.tw * A.th) return false;
+    const int cx = (int)(tile % A.tiles_x) * A.tw + cl % A.tw;
+    const int cy = (int)(tile / A.tiles_x) * A.th + cl / A.tw;
+    if (cx >= A.nx || cy >= A.ny) return false;
+    cell = cy * A.nx + cx;
+    return true;
+}
+
+// One pair's contribution to the seven angular moments from the
+// direction-averaged intensities I_{i,m} of both traversals.
+template <typename T, int PM>
+__device__ __forceinline__ void pair_moments(const MomArgs& A, int a, const T (&Iim)[2][PM], T (&part)[7]) {
+    const int P = A.P;
+#pragma unroll
+    for (int c = 0; c < 7; ++c) part[c] = (T)0;
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int p = 0; p < PM; ++p) {
+            if (p >= P) continue;
+            const gptr<const double> dw = as_global(A.dirw + (((size_t)a * 2 + d) * P + p) * kDirW);
+#pragma unroll
+            for (int c = 0; c < 7; ++c) part[c] += (T)dw[c] * Iim[d][p];
+        }
+}
+
+// E, F and the Eddington tensor of lane (cell, g) from its seven sums.
+template <typename T>
+__device__ __forceinline__ void moments_store(const MomArgs& A, int cell, int g, const Acc<T> (&acc)[7]) {
+    const int G = A.G;
+    double sc = 1.0;
+    if (sizeof(T) == 4) sc = ldexp(1.0, as_global(A.e)[g]);
+    const double Phi = acc[0].value() * sc;
+    const size_t o = (size_t)cell * G + g;
+    if (A.E) as_global_w(A.E)[o] = Phi * A.inv_c;
+    if (A.F) {
+        const gptr<double> F = as_global_w(A.F);
+        F[((size_t)cell * 2 + 0) * G + g] = acc[1].value() * sc;
+        F[((size_t)cell * 2 + 1) * G + g] = acc[2].value() * sc;
+    }
+    if (A.f) {
+        const gptr<double> f = as_global_w(A.f);
+        const bool z = Phi == 0.0;
+        const double inv = z ? 0.0 : 1.0 / Phi;
+        f[((size_t)cell * 4 + 0) * G + g] = z ? 1.0 / 3 : acc[3].value() * sc * inv;
+        f[((size_t)cell * 4 + 1) * G + g] = z ? 0.0 : acc[4].value() * sc * inv;
+        f[((size_t)cell * 4 + 2) * G + g] = z ? 1.0 / 3 : acc[5].value() * sc * inv;
+        f[((size_t)cell * 4 + 3) * G + g] = z ? 1.0 / 3 : acc[6].value() * sc * inv;
+    }
+}
+
 // Lane (cell, g) of a tile of tw x th cells.  For each azimuth
 // pair the lane gathers the segment averages of the characteristics crossing
 // its cell (the C(i, m) list, in (k, s) order) with the area weights, giving
@@ -148,15 +204,9 @@ __device__ __forceinline__ void load_entry(gptr<const T> st, size_t o, int P, T 
 // The sums run in list order whatever K is.  PM bounds the polar count.
 template <typename T, int PM, int K>
 __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int tid) {
-    const int G = A.G;
     const int P = A.P;
-    const int cl = tid / G;
-    const int g = tid - cl * G;
-    if (cl >= A.tw * A.th) return;
-    const int cx = (int)(tile % A.tiles_x) * A.tw + cl % A.tw;
-    const int cy = (int)(tile / A.tiles_x) * A.th + cl / A.tw;
-    if (cx >= A.nx || cy >= A.ny) return;
-    const int cell = cy * A.nx + cx;
+    int cell, g;
+    if (!tile_lane(A, tile, tid, cell, g)) return;
     const int np = A.n_pairs;
     const gptr<const T> st = as_global(static_cast<const T*>(A.state));
     const gptr<const T> cw = as_global(static_cast<const T*>(A.csr_w));
@@ -203,17 +253,7 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
                 for (int p = 0; p < PM; ++p) Iim[d][p] += t.w * y[d][p];
         }
         T part[7];
-#pragma unroll
-        for (int c = 0; c < 7; ++c) part[c] = (T)0;
-#pragma unroll
-        for (int d = 0; d < 2; ++d)
-#pragma unroll
-            for (int p = 0; p < PM; ++p) {
-                if (p >= P) continue;
-                const gptr<const double> dw = as_global(A.dirw + (((size_t)a * 2 + d) * P + p) * kDirW);
-#pragma unroll
-                for (int c = 0; c < 7; ++c) part[c] += (T)dw[c] * Iim[d][p];
-            }
+        pair_moments<T, PM>(A, a, Iim, part);
 #pragma unroll
         for (int c = 0; c < 7; ++c) acc[c].add(part[c]);
 #pragma unroll
@@ -222,25 +262,87 @@ __device__ __forceinline__ void moments_tile(const MomArgs& A, int64_t tile, int
         b1 = b2;
         b2 = b3;
     }
-    double sc = 1.0;
-    if (sizeof(T) == 4) sc = ldexp(1.0, as_global(A.e)[g]);
-    const double Phi = acc[0].value() * sc;
-    const size_t o = (size_t)cell * G + g;
-    if (A.E) as_global_w(A.E)[o] = Phi * A.inv_c;
-    if (A.F) {
-        const gptr<double> F = as_global_w(A.F);
-        F[((size_t)cell * 2 + 0) * G + g] = acc[1].value() * sc;
-        F[((size_t)cell * 2 + 1) * G + g] = acc[2].value() * sc;
+    moments_store<T>(A, cell, g, acc);
+}
+
+// Split form, for plans whose (cell, g) lanes are too few to fill the device
+// while each list is long (fine characteristic grids on coarse material
+// grids): one lane per (pair, cell, g) sums that pair's list -- U entries'
+// loads in flight at a time, added in list order -- and stores the pair's
+// seven partial sums; a second kernel adds them in pair order.  The terms
+// and their order are those of moments_tile (a padding entry adds w = 0), so
+// both forms give the same bits.
+template <typename T, int PM>
+__device__ __forceinline__ void pair_list(const MomArgs& A, int cell, int g, int a, T (&Iim)[2][PM]) {
+    constexpr int U = PM <= 2 ? 8 : 4;
+    const int P = A.P;
+    const gptr<const T> st = as_global(static_cast<const T*>(A.state));
+    const gptr<const T> cw = as_global(static_cast<const T*>(A.csr_w));
+    const gptr<const unsigned> eo = as_global(A.ent_off);
+    const gptr<const int> co = as_global(A.csr_off + (size_t)cell * A.n_pairs + a);
+    const int b0 = co[0], b1 = co[1];
+#pragma unroll
+    for (int d = 0; d < 2; ++d)
+#pragma unroll
+        for (int p = 0; p < PM; ++p) Iim[d][p] = (T)0;
+    for (int e = b0; e < b1; e += U) {
+        Slot<T> s[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) s[u] = load_slot(eo, cw, e + u, e + u < b1, g, A);
+        T x[U][2][PM];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            load_entry<T, PM>(st, (size_t)s[u].r0 * P, P, x[u][0]);
+            load_entry<T, PM>(st, (size_t)s[u].r1 * P, P, x[u][1]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int d = 0; d < 2; ++d)
+#pragma unroll
+                for (int p = 0; p < PM; ++p) Iim[d][p] += s[u].w * x[u][d][p];
     }
-    if (A.f) {
-        const gptr<double> f = as_global_w(A.f);
-        const bool z = Phi == 0.0;
-        const double inv = z ? 0.0 : 1.0 / Phi;
-        f[((size_t)cell * 4 + 0) * G + g] = z ? 1.0 / 3 : acc[3].value() * sc * inv;
-        f[((size_t)cell * 4 + 1) * G + g] = z ? 0.0 : acc[4].value() * sc * inv;
-        f[((size_t)cell * 4 + 2) * G + g] = z ? 1.0 / 3 : acc[5].value() * sc * inv;
-        f[((size_t)cell * 4 + 3) * G + g] = z ? 1.0 / 3 : acc[6].value() * sc * inv;
-    }
+}
+
+// Partial sums [pair][7][lane] over the tile lanes (n_tiles * wpt * 64 of
+// them); work items (pair, wavefront of a tile), pair-major, so each XCD
+// streams the state of a few pairs.
+template <typename T, int PM>
+__global__ __launch_bounds__(kMomWaves * kWave) void k_moments_pairs(MomArgs A, T* __restrict__ part) {
+    const int64_t waves = A.n_tiles * A.wpt;
+    const int64_t lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int64_t wi = lb * kMomWaves + (threadIdx.x >> 6);
+    if (wi >= waves * A.n_pairs) return;
+    const int a = (int)(wi / waves);
+    const int64_t wv = wi - (int64_t)a * waves;
+    const int64_t tile = wv / A.wpt;
+    const int tid = (int)(wv - tile * A.wpt) * kWave + (threadIdx.x & (kWave - 1));
+    int cell, g;
+    if (!tile_lane(A, tile, tid, cell, g)) return;
+    T Iim[2][PM];
+    pair_list<T, PM>(A, cell, g, a, Iim);
+    T pt[7];
+    pair_moments<T, PM>(A, a, Iim, pt);
+    const int64_t n_lanes = waves * kWave;
+    const gptr<T> o = as_global_w(part) + (size_t)a * 7 * n_lanes + wv * kWave + (threadIdx.x & (kWave - 1));
+#pragma unroll
+    for (int c = 0; c < 7; ++c) o[(size_t)c * n_lanes] = pt[c];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_moments_combine(MomArgs A, const T* __restrict__ part) {
+    const int64_t n_lanes = A.n_tiles * A.wpt * kWave;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= n_lanes) return;
+    const int64_t tile = t / ((int64_t)A.wpt * kWave);
+    int cell, g;
+    if (!tile_lane(A, tile, (int)(t - tile * A.wpt * kWave), cell, g)) return;
+    Acc<T> acc[7];
+    const gptr<const T> p = as_global(part) + t;
+    for (int a = 0; a < A.n_pairs; ++a)
+#pragma unroll
+        for (int c = 0; c < 7; ++c) acc[c].add(p[((size_t)a * 7 + c) * n_lanes]);
+    moments_store<T>(A, cell, g, acc);
 }
 
 // Work unit: one wavefront of a tile, i.e. 64 consecutive (cell, g) lanes of
@@ -333,95 +435,169 @@ struct BndArgs {
 // direction is the width-weighted mean exit intensity of the characteristics
 // leaving through b; incoming directions take I_in.  One pass over the exit
 // characteristics of each (pair, traversal) accumulates every polar angle.
-__device__ __forceinline__ void boundary_lane(const BndArgs& A, int lane) {
-    const int G = A.G;
-    if (lane >= A.nb * G) return;
-    const int b = lane / G;
-    const int g = lane - b * G;
+struct BndSums {
+    double Pp = 0, Jp = 0, Pm = 0, Jm = 0, S = 0, Sxx = 0, Sxy = 0, Syy = 0, wo = 0, wodn = 0;
+};
+
+// Width-weighted sums of the exit intensities of characteristics [k0, k1)
+// leaving through the face in traversal d, every polar angle, two
+// characteristics' loads in flight.
+__device__ __forceinline__ void bnd_exit_sums(const BndArgs& A, int g, int d, int k0, int k1,
+                                              double (&acc)[kMaxPol], double& wsum) {
     const int P = A.P;
+    const int G = A.G;
+    const gptr<const double> width = as_global(A.width);
+    const gptr<const double> I_exit = as_global(A.I_exit);
+    wsum = 0.0;
+#pragma unroll
+    for (int p = 0; p < kMaxPol; ++p) acc[p] = 0.0;
+    for (int k = k0; k < k1; k += 2) {
+        const bool two = k + 1 < k1;
+        const double w0 = width[k];
+        const double w1 = two ? width[k + 1] : 0.0;
+        const gptr<const double> ie0 = I_exit + (size_t)(2 * k + d) * P * G + g;
+        const gptr<const double> ie1 = ie0 + (size_t)2 * P * G;
+        double x0[kMaxPol], x1[kMaxPol];
+#pragma unroll
+        for (int p = 0; p < kMaxPol; ++p) {
+            x0[p] = p < P ? ie0[(size_t)p * G] : 0.0;
+            x1[p] = p < P && two ? ie1[(size_t)p * G] : 0.0;
+        }
+        wsum += w0;
+#pragma unroll
+        for (int p = 0; p < kMaxPol; ++p)
+            if (p < P) acc[p] += w0 * x0[p];
+        if (two) {
+            wsum += w1;
+#pragma unroll
+            for (int p = 0; p < kMaxPol; ++p)
+                if (p < P) acc[p] += w1 * x1[p];
+        }
+    }
+}
+
+// Adds the directions of one (pair, traversal) to the face's sums: outgoing
+// ones (the face has exit characteristics) from the exit means, incoming ones
+// from I_in.
+__device__ __forceinline__ void bnd_add(const BndArgs& A, int b, int g, int a, int d, bool out,
+                                        const double (&acc)[kMaxPol], double wsum, BndSums& s) {
+    const int P = A.P;
+    const int G = A.G;
     const int M = A.n_az * P;
     double nxv = 0, nyv = 0;
     if (b < A.ny) nxv = -1;
     else if (b < 2 * A.ny) nxv = 1;
     else if (b < 2 * A.ny + A.nx) nyv = -1;
     else nyv = 1;
-    double Pp = 0, Jp = 0, Pm = 0, Jm = 0, S = 0, Sxx = 0, Sxy = 0, Syy = 0, wo = 0, wodn = 0;
-    const gptr<const double> width = as_global(A.width);
-    const gptr<const double> I_exit = as_global(A.I_exit);
     const gptr<const double> I_in = as_global(A.I_in);
+#pragma unroll
+    for (int p = 0; p < kMaxPol; ++p) {
+        if (p >= P) continue;
+        const gptr<const double> dw = as_global(A.dirw + ((size_t)(a * 2 + d) * P + p) * kDirW);
+        const double om = dw[0];
+        const double odn = dw[7] * nxv + dw[8] * nyv;
+        double I;
+        if (out) {
+            I = acc[p] / wsum;
+            s.Pp += om * I;
+            s.Jp += om * odn * I;
+            s.wo += om;
+            s.wodn += om * odn;
+        } else {
+            const int m = (a + d * (A.n_az >> 1)) * P + p;
+            I = I_in[((size_t)b * M + m) * G + g];
+            s.Pm += om * I;
+            s.Jm += om * fabs(odn) * I;
+        }
+        s.S += om * I;
+        s.Sxx += dw[3] * I;
+        s.Sxy += dw[4] * I;
+        s.Syy += dw[5] * I;
+    }
+}
+
+__device__ __forceinline__ void bnd_store(const BndArgs& A, int b, int g, const BndSums& s) {
+    const gptr<double> out = as_global_w(A.bnd + ((size_t)g * A.nb + b) * 8);
+    out[0] = s.Pp;
+    out[1] = s.Jp;
+    out[2] = s.Pm;
+    out[3] = s.Jm;
+    out[4] = s.Pp > 0.0 ? s.Jp / s.Pp : s.wodn / s.wo;
+    const bool z = s.S == 0.0;
+    out[5] = z ? 1.0 / 3 : s.Sxx / s.S;
+    out[6] = z ? 0.0 : s.Sxy / s.S;
+    out[7] = z ? 1.0 / 3 : s.Syy / s.S;
+}
+
+using I2 = int __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ void boundary_lane(const BndArgs& A, int lane) {
+    const int G = A.G;
+    if (lane >= A.nb * G) return;
+    const int b = lane / G;
+    const int g = lane - b * G;
+    BndSums s;
     // exit ranges of face b, one int2 per (pair, traversal); the next one is
     // loaded while the current one is summed
     const int nad = 2 * A.n_pairs;
-    using I2 = int __attribute__((ext_vector_type(2)));
     const gptr<const I2> bmv = (gptr<const I2>)as_global(A.bmap + (size_t)b * nad * 2);
     I2 nxt = bmv[0];
     for (int ad = 0; ad < nad; ++ad) {
-        const int a = ad >> 1, d = ad & 1;
         const int k0 = nxt.x, k1 = nxt.y;
         if (ad + 1 < nad) nxt = bmv[ad + 1];
         double wsum = 0.0;
         double acc[kMaxPol];
 #pragma unroll
         for (int p = 0; p < kMaxPol; ++p) acc[p] = 0.0;
-        if (k0 >= 0)
-            for (int k = k0; k < k1; k += 2) {        // two characteristics' loads in flight
-                const bool two = k + 1 < k1;
-                const double w0 = width[k];
-                const double w1 = two ? width[k + 1] : 0.0;
-                const gptr<const double> ie0 = I_exit + (size_t)(2 * k + d) * P * G + g;
-                const gptr<const double> ie1 = ie0 + (size_t)2 * P * G;
-                double x0[kMaxPol], x1[kMaxPol];
-#pragma unroll
-                for (int p = 0; p < kMaxPol; ++p) {
-                    x0[p] = p < P ? ie0[(size_t)p * G] : 0.0;
-                    x1[p] = p < P && two ? ie1[(size_t)p * G] : 0.0;
-                }
-                wsum += w0;
-#pragma unroll
-                for (int p = 0; p < kMaxPol; ++p)
-                    if (p < P) acc[p] += w0 * x0[p];
-                if (two) {
-                    wsum += w1;
-#pragma unroll
-                    for (int p = 0; p < kMaxPol; ++p)
-                        if (p < P) acc[p] += w1 * x1[p];
-                }
-            }
-#pragma unroll
-        for (int p = 0; p < kMaxPol; ++p) {
-            if (p >= P) continue;
-            const gptr<const double> dw = as_global(A.dirw + ((size_t)(a * 2 + d) * P + p) * kDirW);
-            const double om = dw[0];
-            const double odn = dw[7] * nxv + dw[8] * nyv;
-            double I;
-            if (k0 >= 0) {
-                I = acc[p] / wsum;
-                Pp += om * I;
-                Jp += om * odn * I;
-                wo += om;
-                wodn += om * odn;
-            } else {
-                const int m = (a + d * (A.n_az >> 1)) * P + p;
-                I = I_in[((size_t)b * M + m) * G + g];
-                Pm += om * I;
-                Jm += om * fabs(odn) * I;
-            }
-            S += om * I;
-            Sxx += dw[3] * I;
-            Sxy += dw[4] * I;
-            Syy += dw[5] * I;
-        }
+        if (k0 >= 0) bnd_exit_sums(A, g, ad & 1, k0, k1, acc, wsum);
+        bnd_add(A, b, g, ad >> 1, ad & 1, k0 >= 0, acc, wsum, s);
     }
-    const gptr<double> out = as_global_w(A.bnd + ((size_t)g * A.nb + b) * 8);
-    out[0] = Pp;
-    out[1] = Jp;
-    out[2] = Pm;
-    out[3] = Jm;
-    out[4] = Pp > 0.0 ? Jp / Pp : wodn / wo;
-    const bool z = S == 0.0;
-    out[5] = z ? 1.0 / 3 : Sxx / S;
-    out[6] = z ? 0.0 : Sxy / S;
-    out[7] = z ? 1.0 / 3 : Syy / S;
+    bnd_store(A, b, g, s);
+}
+
+// Split form of the boundary factors (few (face, g) lanes, many exit
+// characteristics per face): one lane per ((pair, traversal), face, g) stores
+// the exit sums {wsum, acc[p]} as [ad][1 + P][lane]; the combine kernel adds
+// the directions in (pair, traversal) order exactly as boundary_lane does.
+__global__ __launch_bounds__(kBlock) void k_boundary_parts(BndArgs A, double* __restrict__ part) {
+    const int64_t nl = (int64_t)A.nb * A.G;
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int nad = 2 * A.n_pairs;
+    if (t >= nl * nad) return;
+    const int ad = (int)(t / nl);
+    const int lane = (int)(t - ad * nl);
+    const int b = lane / A.G;
+    const int g = lane - b * A.G;
+    const I2 r = *(gptr<const I2>)as_global(A.bmap + ((size_t)b * nad + ad) * 2);
+    if (r.x < 0) return;
+    double wsum, acc[kMaxPol];
+    bnd_exit_sums(A, g, ad & 1, r.x, r.y, acc, wsum);
+    const gptr<double> o = as_global_w(part) + (size_t)ad * (1 + A.P) * nl + lane;
+    o[0] = wsum;
+#pragma unroll
+    for (int p = 0; p < kMaxPol; ++p)
+        if (p < A.P) o[(size_t)(1 + p) * nl] = acc[p];
+}
+
+__global__ __launch_bounds__(kBlock) void k_boundary_combine(BndArgs A, const double* __restrict__ part) {
+    const int64_t nl = (int64_t)A.nb * A.G;
+    const int lane = (int)((int64_t)blockIdx.x * kBlock + threadIdx.x);
+    if (lane >= nl) return;
+    const int b = lane / A.G;
+    const int g = lane - b * A.G;
+    const int nad = 2 * A.n_pairs;
+    const gptr<const I2> bmv = (gptr<const I2>)as_global(A.bmap + (size_t)b * nad * 2);
+    BndSums s;
+    for (int ad = 0; ad < nad; ++ad) {
+        const bool out = bmv[ad].x >= 0;
+        double wsum = 0.0, acc[kMaxPol];
+        const gptr<const double> q = as_global(part) + (size_t)ad * (1 + A.P) * nl + lane;
+#pragma unroll
+        for (int p = 0; p < kMaxPol; ++p) acc[p] = out && p < A.P ? q[(size_t)(1 + p) * nl] : 0.0;
+        if (out) wsum = q[0];
+        bnd_add(A, b, g, ad >> 1, ad & 1, out, acc, wsum, s);
+    }
+    bnd_store(A, b, g, s);
 }
 
 __global__ __launch_bounds__(kBlock) void k_boundary(BndArgs A) {
@@ -471,7 +647,117 @@ lc_status launch_cell_moments_p(int P, int ent, const MomArgs& A, hipStream_t st
     return LC_OK;
 }
 
+template <typename T, int PM>
+void launch_split_e(const MomArgs& A, void* part, hipStream_t st) {
+    const int64_t waves = A.n_tiles * A.wpt * A.n_pairs;
+    hipLaunchKernelGGL((k_moments_pairs<T, PM>), dim3((unsigned)((waves + kMomWaves - 1) / kMomWaves)),
+                       dim3(kMomWaves * kWave), 0, st, A, static_cast<T*>(part));
+    const int64_t lanes = A.n_tiles * A.wpt * kWave;
+    hipLaunchKernelGGL((k_moments_combine<T>), dim3((unsigned)((lanes + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       A, static_cast<const T*>(part));
+}
+
+template <typename T>
+lc_status launch_split_p(int P, const MomArgs& A, void* part, hipStream_t st) {
+    switch (P) {
+        case 1: launch_split_e<T, 1>(A, part, st); break;
+        case 2: launch_split_e<T, 2>(A, part, st); break;
+        case 3: launch_split_e<T, 3>(A, part, st); break;
+        case 4: launch_split_e<T, 4>(A, part, st); break;
+        case 5: launch_split_e<T, 5>(A, part, st); break;
+        case 6: launch_split_e<T, 6>(A, part, st); break;
+        case 7: launch_split_e<T, 7>(A, part, st); break;
+        case 8: launch_split_e<T, 8>(A, part, st); break;
+        default:
+            set_error("n_pol = %d not supported (1..8)", P);
+            return LC_ERR_UNSUPPORTED;
+    }
+    LC_HIP(hipGetLastError());
+    return LC_OK;
+}
+
+// Bytes of the split gather's partial sums for a grid of n_tiles x wpt
+// wavefronts: [pair][7][lane].
+size_t split_part_bytes(int64_t n_tiles, int wpt, int n_pairs, size_t el) {
+    return (size_t)n_pairs * 7 * (size_t)n_tiles * wpt * kWave * el;
+}
+
+// The cell-moment gather of one grid (cells or a family of interior faces),
+// whole or split over pairs as the plan says.
+lc_status launch_gather(Plan* pl, const MomArgs& A, hipStream_t st) {
+    const bool f32 = pl->prec == LC_F32;
+    const int P = pl->rays->n_pol;
+    if (pl->mom_split & 1) {
+        const size_t need = split_part_bytes(A.n_tiles, A.wpt, A.n_pairs, f32 ? 4 : 8);
+        LC_CHECK(need <= pl->mom_part_bytes, LC_ERR_STATE, "split gather: %zu bytes of partial sums needed, %zu held",
+                 need, pl->mom_part_bytes);
+        return f32 ? launch_split_p<float>(P, A, pl->d_mom_part, st) : launch_split_p<double>(P, A, pl->d_mom_part, st);
+    }
+    return f32 ? launch_cell_moments_p<float>(P, pl->moments_entries, A, st)
+               : launch_cell_moments_p<double>(P, pl->moments_entries, A, st);
+}
+
+// Tiles of an interior-face grid of fnx x fny faces: as for cells.
+void face_tiles(int G, int fnx, int fny, MomArgs& A) {
+    const int cells_max = std::max(1, kTileWaves * kWave / G);
+    A.tw = std::max(1, std::min({16, cells_max, fnx}));
+    A.th = std::max(1, std::min({16, cells_max / A.tw, fny}));
+    A.tiles_x = (fnx + A.tw - 1) / A.tw;
+    A.n_tiles = (int64_t)A.tiles_x * ((fny + A.th - 1) / A.th);
+    A.wpt = (A.tw * A.th * G + kWave - 1) / kWave;
+}
+
+constexpr int64_t kSplitMaxWaves = 2048;   // tile wavefronts (two per SIMD) below which a gather may split
+constexpr double kSplitMinList = 8.0;      // and its lists must hold this many entries on average
+
 }  // namespace
+
+lc_status plan_set_moment_split(Plan* pl, int mode) {
+    Rays* r = pl->rays;
+    int want = 0;
+    if (mode < 0) {
+        const int64_t waves = moment_tiles(pl) * moment_tile_waves(pl);
+        const double per_list = (double)r->n_seg / std::max(1.0, (double)r->cells * r->n_pairs);
+        if (r->n_pairs > 1 && waves < kSplitMaxWaves && per_list >= kSplitMinList) want |= 1;
+        const int64_t lanes = (int64_t)r->nb * pl->G;
+        const double per_face = (double)r->n_rays / std::max(1.0, (double)r->nb * r->n_pairs);
+        if (lanes < kSplitMaxWaves * kWave && per_face >= kSplitMinList) want |= 2;
+    } else if (mode > 0) {
+        want = 3;
+    }
+    const size_t el = pl->prec == LC_F32 ? 4 : 8;
+    size_t bytes = 0;
+    if (want & 1) {
+        bytes = split_part_bytes(moment_tiles(pl), moment_tile_waves(pl), r->n_pairs, el);
+        for (int part = 0; part < 2; ++part) {
+            const int fnx = part == 0 ? r->nx - 1 : r->nx;
+            const int fny = part == 0 ? r->ny : r->ny - 1;
+            if (fnx < 1 || fny < 1) continue;
+            MomArgs A{};
+            face_tiles(pl->G, fnx, fny, A);
+            bytes = std::max(bytes, split_part_bytes(A.n_tiles, A.wpt, r->n_pairs, el));
+        }
+    }
+    if (want & 2) bytes = std::max(bytes, (size_t)2 * r->n_pairs * (1 + r->n_pol) * (size_t)r->nb * pl->G * 8);
+    if (bytes > pl->mom_part_bytes) {
+        LC_HIP(hipDeviceSynchronize());   // no gather in flight still uses the old buffer
+        if (pl->d_mom_part) (void)hipFree(pl->d_mom_part);
+        pl->d_mom_part = nullptr;
+        pl->mom_part_bytes = 0;
+        pl->mom_split = 0;
+        hipError_t e = lc_malloc(&pl->d_mom_part, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            pl->d_mom_part = nullptr;
+            set_error("allocation of the split gathers' partial sums (%zu bytes) failed: %s", bytes,
+                      hipGetErrorString(e));
+            return LC_ERR_ALLOC;
+        }
+        pl->mom_part_bytes = bytes;
+    }
+    pl->mom_split = want;
+    return LC_OK;
+}
 
 lc_status plan_init_moments(Plan* pl) {
     Rays* r = pl->rays;
@@ -507,7 +793,7 @@ lc_status plan_init_moments(Plan* pl) {
     const int cells_max = std::max(1, kTileWaves * kWave / pl->G);
     pl->tile_w = std::max(1, std::min({16, cells_max, r->nx}));
     pl->tile_h = std::max(1, std::min({16, cells_max / pl->tile_w, r->ny}));
-    return LC_OK;
+    return plan_set_moment_split(pl, -1);
 }
 
 // Interior-face crossing lists of a plan: the geometry's lists (built once
@@ -566,20 +852,14 @@ lc_status launch_face_moments(Plan* pl, const void* point, const void* state, do
         A.nx = fnx;
         A.ny = fny;
         A.P = r->n_pol;
-        const int cells_max = std::max(1, kTileWaves * kWave / G);
-        A.tw = std::max(1, std::min({16, cells_max, fnx}));
-        A.th = std::max(1, std::min({16, cells_max / A.tw, fny}));
-        A.tiles_x = (fnx + A.tw - 1) / A.tw;
-        A.n_tiles = (int64_t)A.tiles_x * ((fny + A.th - 1) / A.th);
-        A.wpt = (A.tw * A.th * G + kWave - 1) / kWave;
+        face_tiles(G, fnx, fny, A);
         A.G = G;
         A.n_pairs = r->n_pairs;
         A.inv_c = 1.0 / c;
         A.E = E ? E + face0 * G : nullptr;
         A.F = F ? F + face0 * 2 * G : nullptr;
         A.f = f ? f + face0 * 4 * G : nullptr;
-        lc_status rc = f32 ? launch_cell_moments_p<float>(r->n_pol, pl->moments_entries, A, st)
-                           : launch_cell_moments_p<double>(r->n_pol, pl->moments_entries, A, st);
+        lc_status rc = launch_gather(pl, A, st);
         if (rc) return rc;
     }
     return LC_OK;
@@ -616,8 +896,7 @@ lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, cons
         A.f = f;
         lc_status rc = prof_begin(pl, pl->ev_mom, st);
         if (rc) return rc;
-        rc = f32 ? launch_cell_moments_p<float>(r->n_pol, pl->moments_entries, A, st)
-                 : launch_cell_moments_p<double>(r->n_pol, pl->moments_entries, A, st);
+        rc = launch_gather(pl, A, st);
         if (rc) return rc;
         rc = prof_end(pl, pl->ev_mom, st);
         if (rc) return rc;
@@ -638,7 +917,17 @@ lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, cons
         B.P = r->n_pol;
         B.bnd = bnd;
         const int lanes = r->nb * pl->G;
-        hipLaunchKernelGGL(k_boundary, dim3((lanes + kBlock - 1) / kBlock), dim3(kBlock), 0, st, B);
+        if (pl->mom_split & 2) {
+            const int64_t parts = (int64_t)lanes * 2 * r->n_pairs;
+            LC_CHECK(parts * (1 + r->n_pol) * 8 <= (int64_t)pl->mom_part_bytes, LC_ERR_STATE,
+                     "split boundary factors: partial-sum buffer too small");
+            hipLaunchKernelGGL(k_boundary_parts, dim3((unsigned)((parts + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                               B, static_cast<double*>(pl->d_mom_part));
+            hipLaunchKernelGGL(k_boundary_combine, dim3((lanes + kBlock - 1) / kBlock), dim3(kBlock), 0, st, B,
+                               static_cast<const double*>(pl->d_mom_part));
+        } else {
+            hipLaunchKernelGGL(k_boundary, dim3((lanes + kBlock - 1) / kBlock), dim3(kBlock), 0, st, B);
+        }
         LC_HIP(hipGetLastError());
     }
     return LC_OK;

@@ -104,6 +104,8 @@ _SIGS = {
     "lc_plan_set_tuning": ([_vp, C.POINTER(lc_tuning_t)], C.c_int),
     "lc_plan_get_tuning": ([_vp, C.POINTER(lc_tuning_t)], C.c_int),
     "lc_plan_set_split": ([_vp, _i32], C.c_int),
+    "lc_plan_set_moment_split": ([_vp, _i32], C.c_int),
+    "lc_plan_get_moment_split": ([_vp, _vp], C.c_int),
     "lc_plan_set_sweep_residency": ([_vp, _i32], C.c_int),
     "lc_plan_profile": ([_vp, _i32], C.c_int),
     "lc_plan_profile_read": ([_vp, _vp], C.c_int),
@@ -361,6 +363,16 @@ def lc_plan_set_sweep_residency(plan: Plan, capped: bool):
 
 def lc_plan_set_split(plan: Plan, chunk_steps: int):
     _check(_lib.lc_plan_set_split(plan.handle, int(chunk_steps)))
+
+
+def lc_plan_set_moment_split(plan: Plan, mode: int):
+    _check(_lib.lc_plan_set_moment_split(plan.handle, int(mode)))
+
+
+def lc_plan_get_moment_split(plan: Plan) -> int:
+    m = C.c_int32(0)
+    _check(_lib.lc_plan_get_moment_split(plan.handle, C.byref(m)))
+    return int(m.value)
 
 
 def lc_plan_get_tuning(plan: Plan):

@@ -217,6 +217,30 @@ def test_mlqd_acceleration_keeps_the_fixed_point(lcmod):
 
 
 
+def test_mlqd_steps_repeat_bit_for_bit(lcmod):
+    """A step's results depend on its arguments alone: the same steps run
+    again from reset() on the same handle, on a fresh handle, and with the
+    transport gathers whole instead of split over azimuth pairs give the same
+    bits and the same iteration counts."""
+    lc, driver = lcmod
+    p = _fc(h_mat=0.6, h_moc=0.02, G=6)
+    _say(f"case fc mlqd {p.nx}x{p.ny} G={p.G} h_moc {p.h_moc}: repeated steps")
+    runs = []
+    a = driver.MlqdSolver(p, eps=1e-11)
+    assert lc.lc_plan_get_moment_split(a.plan) == 3
+    b = driver.MlqdSolver(p, eps=1e-11)
+    lc.lc_plan_set_moment_split(b.plan, 0)
+    for s in (a, a, b):
+        s.reset()
+        s.step(2)
+        runs.append((s.solution(), [tuple(h[:2]) for h in s.history]))
+    for sol, hist in runs[1:]:
+        assert hist == runs[0][1]
+        for k in sol:
+            assert np.array_equal(sol[k], runs[0][0][k]), k
+    _say(f"  iterations {runs[0][1]}")
+
+
 def test_mlqd_steps_match_the_oracle_on_the_papers_grid(lcmod):
     """The vertex-avoiding, width-halving characteristic grid (the paper's
     construction), 5 x 5 cells of 1.2 cm, h_moc = 0.15 cm: two steps against

@@ -1,0 +1,126 @@
+"""GPU: gathers split over azimuth pairs (lc_plan_set_moment_split).
+
+The split cell moments, interior-face moments (eq. (7), (14)-(16)) and
+boundary factors must give the bits of the whole gathers -- both precisions,
+both grid constructions, polar counts 1 to 6, more groups than a bundle
+holds, grids one cell wide -- and match the oracle; the automatic choice
+splits only plans with few lanes and long lists."""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.parity_util import FLOOR, bnd_errors, err_E, err_F, err_f
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def lcmod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2305_11998_amd import driver, lc
+    return lc, driver
+
+
+def _problem(nx, ny, G, n_pol, h_moc, steps=2, seed=5, n_az=8):
+    rng = np.random.default_rng(seed)
+    Ts = [rng.uniform(0.01, 1.0, nx * ny) for _ in range(steps)]
+    return W.make_problem(nx, ny, nx * 0.1, ny * 0.1, n_az, n_pol, G, 0.001, 20.0, h_moc, 2.0, Ts, name="split")
+
+
+def _gathers(lc, s):
+    """Cell moments, boundary factors and interior-face moments of the
+    solver's current state, into fresh buffers (host copies)."""
+    import torch
+    z = lambda t: torch.zeros_like(t)
+    E, F, f, bnd = z(s.E), z(s.F), z(s.f), z(s.bnd)
+    Ef, Ff, ff = z(s.Ef), z(s.Ff), z(s.ff)
+    st = s.state[s.cur]
+    lc.lc_moments(s.plan, st, s.c, E, F, f, bnd, s.I_exit, s.I_in)
+    lc.lc_face_moments(s.plan, s.points, st, s.c, Ef, Ff, ff)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in dict(E=E, F=F, f=f, bnd=bnd, Ef=Ef, Ff=Ff, ff=ff).items()}
+
+
+@pytest.mark.parametrize("nx,ny,G,n_pol,mode,prec,h_moc", [
+    (6, 5, 17, 4, 0, 0, 0.004), (6, 5, 17, 4, 0, 1, 0.004),
+    (5, 7, 70, 2, 1, 0, 0.01), (5, 7, 70, 2, 1, 1, 0.01),
+    (7, 4, 3, 6, 0, 0, 0.005), (7, 4, 3, 6, 0, 1, 0.005),
+    (4, 4, 5, 1, 0, 0, 0.01), (1, 6, 4, 3, 0, 1, 0.01), (6, 1, 9, 2, 1, 0, 0.008)])
+def test_split_gathers_give_the_bits_of_whole_ones(lcmod, nx, ny, G, n_pol, mode, prec, h_moc):
+    lc, driver = lcmod
+    prob = _problem(nx, ny, G, n_pol, h_moc)
+    _say(f"split vs whole {nx}x{ny} G={G} P={n_pol} mode={mode} prec={prec} h_moc={h_moc}")
+    s = driver.Solver(prob, prec=prec, mode=mode)
+    s.enable_faces()
+    s.reset()
+    s.step_faces(prob.steps)
+    lc.lc_plan_set_moment_split(s.plan, 0)
+    assert lc.lc_plan_get_moment_split(s.plan) == 0
+    whole = _gathers(lc, s)
+    lc.lc_plan_set_moment_split(s.plan, 1)
+    assert lc.lc_plan_get_moment_split(s.plan) == 3
+    split = _gathers(lc, s)
+    again = _gathers(lc, s)
+    for k in whole:
+        assert np.array_equal(split[k], whole[k]), k
+        assert np.array_equal(again[k], split[k]), k
+    assert np.all(np.isfinite(whole["E"])) and whole["E"].max() > 0
+
+
+def test_automatic_choice(lcmod):
+    lc, driver = lcmod
+    # few lanes, long lists: both gathers split
+    fine = driver.Solver(_problem(6, 5, 17, 4, 0.002, steps=1), prec=0)
+    assert lc.lc_plan_get_moment_split(fine.plan) == 3
+    # short lists (spacing near the cell size): whole
+    coarse = driver.Solver(_problem(6, 5, 17, 4, 0.05, steps=1), prec=0)
+    assert lc.lc_plan_get_moment_split(coarse.plan) == 0
+    # many lanes (a 256^2 grid at spacing h/2): whole
+    big = W.config(2, steps=1)
+    s = driver.Solver(big, prec=lc.LC_F32)
+    assert lc.lc_plan_get_moment_split(s.plan) == 0
+    # back to automatic after a forced setting
+    lc.lc_plan_set_moment_split(fine.plan, 0)
+    lc.lc_plan_set_moment_split(fine.plan, -1)
+    assert lc.lc_plan_get_moment_split(fine.plan) == 3
+    with pytest.raises(lc.LcError):
+        lc.lc_plan_set_moment_split(fine.plan, 2)
+
+
+@pytest.mark.parametrize("prec,mode", [(0, 0), (1, 0), (0, 1)])
+def test_split_gathers_match_oracle(lcmod, prec, mode):
+    lc, driver = lcmod
+    from oracle import faces as OF, rays as R, solve as osolve, sweep as OS
+    prob = _problem(6, 5, 5, 3, 0.01, seed=9)
+    _say(f"split gathers vs oracle prec={prec} mode={mode}")
+    s = driver.Solver(prob, prec=prec, mode=mode)
+    lc.lc_plan_set_moment_split(s.plan, 1)
+    s.enable_faces()
+    s.reset()
+    s.step_faces(prob.steps)
+    got = s.moments()
+    gotf = s.face_moments()
+    ref = osolve.run(prob, mode=mode)["steps"][-1]
+    g = R.build(prob.nx, prob.ny, prob.lx, prob.ly, prob.phi, prob.h_moc, mode)
+    st = OS.initial_state(g, prob.n_pol, prob.state0)
+    pts = None
+    for t in range(prob.steps):
+        pts = np.zeros_like(st)
+        st, _ = OS.sweep(g, prob.mu, prob.kappa[t], prob.planck[t], prob.c_dt, st, prob.I_in, points=pts)
+    Ef, Ff, ff = OF.face_moments(g, prob.phi, prob.mu, prob.omega, pts, W.C_LIGHT)
+    c = W.C_LIGHT
+    tol = 1e-12 if prec == 0 else 1e-5
+    e = [err_E(got["E"], ref["E"]), err_F(got["F"], ref["F"], ref["E"], c), err_f(got["f"], ref["f"], ref["E"]),
+         err_E(gotf["E"], Ef), err_F(gotf["F"], Ff, Ef, c), err_f(gotf["f"], ff, Ef)]
+    eb, ebc = bnd_errors(got["bnd"], ref["bnd"], floor=0.0 if prec == 0 else FLOOR)
+    _say("  cells E %.2e F %.2e f %.2e faces E %.2e F %.2e f %.2e bnd %.2e / %.2e" % (*e, eb, ebc))
+    assert max(e) <= tol and eb <= tol and ebc <= tol
