@@ -423,17 +423,14 @@ __device__ inline void wg_sum2(double& a, double& b, double* sa, double* sb) {
     __syncthreads();
 }
 
-// R: a bound on the rows each thread owns (nf <= R kWG).  With R <= 8
-// (nf <= 4096, 32 KB) the vector a product gathers from is also kept in LDS
-// (ph, sh, or x for a residual), so the gathers are LDS reads (19 instead
-// of 24 us an iteration at 3,280 faces; unrolling the row loops, which
-// spills registers, made it slower).
+// R: a bound on the rows each thread owns (nf <= R kWG); this form serves
+// R = 16 and 32 (systems of 4097 to 16384 faces), with its vectors in
+// global memory (L2) and gathers from there; smaller systems take the
+// register form below.
 template <int R>
 __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restrict__ val, const double* __restrict__ bv,
                                                      const double* __restrict__ dinv, Vecs V, int warm, double rtol,
                                                      int max_iter, int* iters, double* resid) {
-    constexpr bool kLds = R <= 8;
-    extern __shared__ double gsv[];                   // [nf] the gathered vector (kLds)
     __shared__ double sa[kWG / 64], sb[kWG / 64];
     const int g = blockIdx.x, nf = Q.nf, tid = threadIdx.x;
     const size_t o = (size_t)g * nf;
@@ -448,22 +445,19 @@ __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restr
             if (f < nf) fn(f);
         }
     };
-    // row f of A times u (u: this group's vector; read from LDS when staged)
+    // row f of A times u (this group's vector)
     auto prod = [&](const double* u, int f) -> double {
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
             const int cidx = Q.col[(size_t)k * nf + f];
             const double a = val[((size_t)g * kSlots + k) * nf + f];
-            acc += a * (kLds ? gsv[cidx] : u[cidx]);
+            acc += a * u[cidx];
         }
         return acc;
     };
     // make u readable by the products of every thread
-    auto stage = [&](const double* u) {
-        if constexpr (kLds) rows([&](int f) { gsv[f] = u[f]; });
-        __syncthreads();
-    };
+    auto stage = [&](const double*) { __syncthreads(); };
     if (!warm) rows([&](int f) { x[f] = 0.0; });
     __syncthreads();
     // r = b - A x, rh = r, p = v = 0; returns (r, r) and (b, b)
@@ -508,7 +502,6 @@ __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restr
             const double q = di[f] * pv;
             p[f] = pv;
             ph[f] = q;
-            if constexpr (kLds) gsv[f] = q;
         });
         __syncthreads();
         double a = 0.0, c = 0.0;
@@ -533,7 +526,6 @@ __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restr
             const double q = di[f] * sv;
             s[f] = sv;
             sh[f] = q;
-            if constexpr (kLds) gsv[f] = q;
         });
         __syncthreads();
         a = 0.0;
@@ -583,6 +575,224 @@ __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restr
         });
         wg_sum2(e2, unused, sa, sb);
         rnorm = sqrt(e2);
+    }
+    if (tid == 0) {
+        iters[g] = it;
+        resid[g] = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+    }
+}
+
+// Register form for systems of up to R <= 8 rows a thread (nf <= 4096): the
+// iterate and the BiCGSTAB vectors of a thread's rows stay in registers,
+// the vector a product gathers from is staged in LDS, and only the matrix
+// (values and columns) is read from memory in an iteration.  The arithmetic
+// and the order of every sum are those of k_bicg_group, row by row; x is
+// read (warm != 0) and written in xv only at the ends.
+template <int R>
+__global__ __launch_bounds__(kWG) void k_bicg_reg(Geo Q, const double* __restrict__ val,
+                                                   const double* __restrict__ bv, const double* __restrict__ dinv,
+                                                   double* __restrict__ xv, int warm, double rtol, int max_iter,
+                                                   int* iters, double* resid) {
+    // With R <= 4 the compiler keeps the matrix rows of a thread in
+    // registers across iterations too.  With R = 8 neither they nor all the
+    // rows' product loads in flight fit beside the vectors: the products
+    // then run row by row (no unrolling) into LDS, from where each thread
+    // takes its own rows, and the matrix is read again in every product.
+    constexpr bool kRowLoop = R > 4;
+    extern __shared__ double gsv[];                   // [nf] the gathered vector; [nf] products (kRowLoop)
+    __shared__ double sa[kWG / 64], sb[kWG / 64];
+    const int g = blockIdx.x, nf = Q.nf, tid = threadIdx.x;
+    const size_t o = (size_t)g * nf;
+    const gptr<const double> vg = as_global(val + (size_t)g * kSlots * nf);
+    const gptr<const int> cg = as_global(Q.col);
+    const gptr<const double> b = as_global(bv + o);
+    double x[R], r[R], rh[R], p[R], v[R], s[R], t[R], di[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int f = tid + j * kWG;
+        const bool ok = f < nf;
+        di[j] = ok ? dinv[o + f] : 0.0;
+        x[j] = ok && warm ? xv[o + f] : 0.0;
+        r[j] = rh[j] = p[j] = v[j] = s[j] = t[j] = 0.0;
+    }
+    // row f of A times the staged vector
+    auto prod = [&](int f) -> double {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) {
+            const int cidx = cg[(size_t)k * nf + f];
+            const double a = vg[(size_t)k * nf + f];
+            acc += a * gsv[cidx];
+        }
+        return acc;
+    };
+    // y_j = (A u)_f for this thread's rows f; out-of-range rows untouched
+    auto spmv = [&](double (&y)[R]) {
+        if constexpr (kRowLoop) {
+            double* out = gsv + nf;
+#pragma unroll 1
+            for (int j = 0; j < R; ++j) {
+                const int f = tid + j * kWG;
+                if (f < nf) out[f] = prod(f);
+            }
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int f = tid + j * kWG;
+                if (f < nf) y[j] = out[f];
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+                const int f = tid + j * kWG;
+                if (f < nf) y[j] = prod(f);
+            }
+        }
+    };
+    auto stage = [&](const double (&u)[R]) {
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int f = tid + j * kWG;
+            if (f < nf) gsv[f] = u[j];
+        }
+        __syncthreads();
+    };
+    // r = b - A x, rh = r, p = v = 0; returns (r, r) and (b, b)
+    auto restart = [&](double& rr, double& bb) {
+        stage(x);
+        spmv(v);                                      // v is reset below
+        rr = 0.0;
+        bb = 0.0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int f = tid + j * kWG;
+            if (f < nf) {
+                const double bf = b[f];
+                const double e = bf - v[j];
+                r[j] = e;
+                rh[j] = e;
+                p[j] = 0.0;
+                v[j] = 0.0;
+                rr += e * e;
+                bb += bf * bf;
+            }
+        }
+        wg_sum2(rr, bb, sa, sb);
+    };
+    double rr, bb;
+    restart(rr, bb);
+    const double bnorm = sqrt(bb);
+    if (bnorm == 0.0)
+#pragma unroll
+        for (int j = 0; j < R; ++j) x[j] = 0.0;
+    double rho = rr, alpha = 1.0, omega = 1.0, beta = 0.0, rnorm = bnorm == 0.0 ? 0.0 : sqrt(rr);
+    int it = 0, checks = 0;
+    bool done = bnorm == 0.0 || rnorm <= rtol * bnorm;
+    while (bnorm > 0.0) {
+        if (done) {                                   // true residual
+            if (checks >= 3) break;
+            ++checks;
+            restart(rr, bb);
+            rnorm = sqrt(rr);
+            rho = rr;
+            alpha = omega = 1.0;
+            beta = 0.0;
+            if (rnorm <= rtol * bnorm) break;
+            done = false;
+        }
+        if (it >= max_iter) break;
+        ++it;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int f = tid + j * kWG;
+            p[j] = r[j] + beta * (p[j] - omega * v[j]);
+            if (f < nf) gsv[f] = di[j] * p[j];
+        }
+        __syncthreads();
+        double a = 0.0, c = 0.0;
+        spmv(v);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int f = tid + j * kWG;
+            if (f < nf) a += rh[j] * v[j];
+        }
+        wg_sum2(a, c, sa, sb);
+        if (a == 0.0 || !std::isfinite(a)) {          // breakdown: restart from x
+            restart(rr, bb);
+            rho = rr;
+            alpha = omega = 1.0;
+            beta = 0.0;
+            rnorm = sqrt(rr);
+            done = rnorm <= rtol * bnorm;
+            continue;
+        }
+        alpha = rho / a;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int f = tid + j * kWG;
+            s[j] = r[j] - alpha * v[j];
+            if (f < nf) gsv[f] = di[j] * s[j];
+        }
+        __syncthreads();
+        a = 0.0;
+        c = 0.0;
+        spmv(t);
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int f = tid + j * kWG;
+            if (f < nf) {
+                a += t[j] * s[j];
+                c += t[j] * t[j];
+            }
+        }
+        wg_sum2(a, c, sa, sb);
+        omega = c > 0.0 ? a / c : 0.0;
+        a = 0.0;
+        c = 0.0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int f = tid + j * kWG;
+            if (f < nf) {
+                x[j] += alpha * (di[j] * p[j]) + omega * (di[j] * s[j]);
+                r[j] = s[j] - omega * t[j];
+                a += rh[j] * r[j];
+                c += r[j] * r[j];
+            }
+        }
+        wg_sum2(a, c, sa, sb);
+        rnorm = sqrt(c);
+        if (rnorm <= rtol * bnorm) {
+            done = true;
+        } else if (a == 0.0 || omega == 0.0 || !std::isfinite(a)) {
+            restart(rr, bb);
+            rho = rr;
+            alpha = omega = 1.0;
+            beta = 0.0;
+            rnorm = sqrt(rr);
+            done = rnorm <= rtol * bnorm;
+        } else {
+            beta = (a / rho) * (alpha / omega);
+            rho = a;
+        }
+    }
+    if (!done && bnorm > 0.0 && it >= max_iter) {
+        stage(x);
+        spmv(t);
+        double e2 = 0.0, unused = 0.0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int f = tid + j * kWG;
+            if (f < nf) {
+                const double e = b[f] - t[j];
+                e2 += e * e;
+            }
+        }
+        wg_sum2(e2, unused, sa, sb);
+        rnorm = sqrt(e2);
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int f = tid + j * kWG;
+        if (f < nf) xv[o + f] = x[j];
     }
     if (tid == 0) {
         iters[g] = it;
@@ -856,18 +1066,22 @@ lc_status solve_general(Loqd* q, const Geo& Q, const Gen& Cg, double* E_cell, do
         if (q->warm) LC_HIP(hipMemcpyAsync(V.x, E_face, GF * sizeof(double), hipMemcpyDeviceToDevice, st));
         {
             const int rows_per_thread = (nf + kWG - 1) / kWG;
-            const size_t lds = rows_per_thread <= 8 ? (size_t)nf * sizeof(double) : 0;
+            const size_t lds = (size_t)nf * sizeof(double) * (rows_per_thread > 4 ? 2 : 1);
             const int wv = q->warm ? 1 : 0;
-            auto go = [&](auto kern) {
-                hipLaunchKernelGGL(kern, dim3(G), dim3(kWG), lds, st, Q, q->d_val, q->d_b, q->d_dinv, V, wv, rtol,
+            auto reg = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3(G), dim3(kWG), lds, st, Q, q->d_val, q->d_b, q->d_dinv, V.x, wv, rtol,
                                    max_iter, q->d_iters, q->d_resid);
             };
-            if (rows_per_thread <= 1) go(k_bicg_group<1>);
-            else if (rows_per_thread <= 2) go(k_bicg_group<2>);
-            else if (rows_per_thread <= 4) go(k_bicg_group<4>);
-            else if (rows_per_thread <= 8) go(k_bicg_group<8>);
-            else if (rows_per_thread <= 16) go(k_bicg_group<16>);
-            else go(k_bicg_group<32>);
+            auto glob = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3(G), dim3(kWG), 0, st, Q, q->d_val, q->d_b, q->d_dinv, V, wv, rtol,
+                                   max_iter, q->d_iters, q->d_resid);
+            };
+            if (rows_per_thread <= 1) reg(k_bicg_reg<1>);
+            else if (rows_per_thread <= 2) reg(k_bicg_reg<2>);
+            else if (rows_per_thread <= 4) reg(k_bicg_reg<4>);
+            else if (rows_per_thread <= 8) reg(k_bicg_reg<8>);
+            else if (rows_per_thread <= 16) glob(k_bicg_group<16>);
+            else glob(k_bicg_group<32>);
         }
         hipLaunchKernelGGL(k_loqd_back, gmax, blk, 0, st, Q, q->d_dc, q->d_ac, q->d_bc, V.x, E_cell, E_face);
         hipLaunchKernelGGL(k_loqd_flux, gf, blk, 0, st, Q, Cg, E_cell, E_face, F_face);
