@@ -884,6 +884,9 @@ __global__ void k_grey_cells(Geo Q, const double* __restrict__ kappa, const doub
     if (i >= Q.N) return;
     const int G = Q.G;
     double E = 0.0, kE = 0.0, sB = 0.0, kB = 0.0, sk = 0.0, ep = 0.0, t[3] = {0.0, 0.0, 0.0};
+    // the group loops are unrolled so that several groups' loads are in
+    // flight at once; the sums still run in group order
+#pragma unroll 4
     for (int g = 0; g < G; ++g) {
         const size_t gi = (size_t)g * Q.N + i;
         const double e = E_cell[gi], k = kappa[gi], b = planck[gi];
@@ -910,6 +913,7 @@ __global__ void k_grey_cells(Geo Q, const double* __restrict__ kappa, const doub
     for (int s = 0; s < 4; ++s) {
         const int f = Q.cface[(size_t)s * Q.N + i];
         double aF = 0.0, kaF = 0.0, Ef = 0.0;
+#pragma unroll 4
         for (int g = 0; g < G; ++g) {
             const double F = F_face[(size_t)g * Q.nf + f];
             aF += fabs(F);
@@ -918,6 +922,7 @@ __global__ void k_grey_cells(Geo Q, const double* __restrict__ kappa, const doub
         }
         const double K = aF != 0.0 ? kaF / aF : avgE;
         double num = 0.0;
+#pragma unroll 4
         for (int g = 0; g < G; ++g) num += (kappa[(size_t)g * Q.N + i] - K) * F_face[(size_t)g * Q.nf + f];
         ks[(size_t)s * Q.N + i] = K + 1.0 / Q.c_dt;
         es[(size_t)s * Q.N + i] = Ef != 0.0 ? num / Ef : 0.0;
@@ -931,6 +936,7 @@ __global__ void k_grey_faces(Geo Q, const double* __restrict__ F_prev, const dou
     if (f >= Q.nf) return;
     const int G = Q.G, nb = Q.nf - Q.nint;
     double Ef = 0.0, t[3] = {0.0, 0.0, 0.0}, p = 0.0, cE = 0.0, cs = 0.0, jm = 0.0;
+#pragma unroll 4
     for (int g = 0; g < G; ++g) {
         const double e = E_face[(size_t)g * Q.nf + f];
         Ef += e;
