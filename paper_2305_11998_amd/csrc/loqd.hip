@@ -45,6 +45,7 @@
 #include <vector>
 
 #include "lc_internal.hpp"
+#include "loqd_internal.hpp"
 
 namespace lc {
 
@@ -89,7 +90,17 @@ struct Loqd {
     int solver = 0;                   // 0 by size, 1 one workgroup per group, 2 many blocks per group
     int* d_iters = nullptr;           // [G] iterations (one-workgroup solver)
     double* d_resid = nullptr;        // [G] final relative residuals (one-workgroup solver)
+    // pinned host copies of the convergence report and of the Newton change
+    // partials, so that copies queued together need one wait
+    int* h_iters = nullptr;           // [G]
+    double* h_resid = nullptr;        // [G]
+    double* h_part = nullptr;         // [G * nblk]
+    // a one-workgroup solve whose report was queued but not yet checked
+    bool pending = false;
+    double pending_rtol = 0.0;
+    int pending_max_iter = 0;
     std::vector<void*> owned;
+    std::vector<void*> owned_host;
 };
 
 // Face systems up to this size are solved by one workgroup per group: the
@@ -806,7 +817,7 @@ __global__ void k_loqd_back(Geo Q, const double* __restrict__ dc, const double* 
     const int g = blockIdx.y;
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     const double* X = xf + (size_t)g * Q.nf;
-    if (t < Q.nf) E_face[(size_t)g * Q.nf + t] = X[t];
+    if (t < Q.nf && xf != E_face) E_face[(size_t)g * Q.nf + t] = X[t];   // the solver may have written E_face
     if (t < Q.N) {
         const size_t gi = (size_t)g * Q.N + t;
         const size_t a0 = (size_t)g * 4 * Q.N + t;
@@ -1038,8 +1049,26 @@ void free_loqd(Loqd* q) {
     if (!q) return;
     for (void* p : q->owned) (void)hipFree(p);
     q->owned.clear();
+    for (void* p : q->owned_host) (void)hipHostFree(p);
+    q->owned_host.clear();
     q->magic = 0;
     delete q;
+}
+
+// pinned host allocation owned by a vector of pointers
+template <typename T>
+lc_status halloc(std::vector<void*>& owned, T** out, size_t n) {
+    void* p = nullptr;
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("hipHostMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+        return LC_ERR_ALLOC;
+    }
+    owned.push_back(p);
+    *out = static_cast<T*>(p);
+    return LC_OK;
 }
 
 template <typename T>
@@ -1056,8 +1085,36 @@ Geo geo(const Loqd* q, double c, double c_dt, int G) {
 
 // Assemble and solve the general-form system of every group; outputs E_cell
 // [G][N], E_face [G][nf], F_face [G][nf].
+// Check the queued report of the last one-workgroup solve (the caller has
+// synchronised the stream since): iterations (the most of any group) and
+// residuals to iters / resid, LC_ERR_UNSUPPORTED if a group missed rtol.
+lc_status check_report(Loqd* q, int32_t* iters, double* resid) {
+    if (!q->pending) return LC_OK;
+    q->pending = false;
+    int most = 0;
+    double worst = 0.0;
+    for (int g = 0; g < q->G; ++g) {
+        most = std::max(most, q->h_iters[g]);
+        if (resid) resid[g] = q->h_resid[g];
+        worst = std::max(worst, std::isfinite(q->h_resid[g]) ? q->h_resid[g] : INFINITY);
+    }
+    if (iters) *iters = most;
+    LC_CHECK(worst <= q->pending_rtol, LC_ERR_UNSUPPORTED,
+             "LOQD solve did not reach rtol %.3g: residual %.3g after %d iterations (limit %d)", q->pending_rtol,
+             worst, most, q->pending_max_iter);
+    return LC_OK;
+}
+
+// With defer, a one-workgroup solve only queues the copies of its report:
+// the caller checks it with check_report after its next wait on the stream.
 lc_status solve_general(Loqd* q, const Geo& Q, const Gen& Cg, double* E_cell, double* E_face, double* F_face,
-                        double rtol, int max_iter, int32_t* iters, double* resid, hipStream_t st) {
+                        double rtol, int max_iter, int32_t* iters, double* resid, hipStream_t st,
+                        bool defer = false) {
+    if (q->pending) {                 // a deferred report not yet read
+        LC_HIP(hipStreamSynchronize(st));
+        lc_status rc = check_report(q, nullptr, nullptr);
+        if (rc) return rc;
+    }
     const int G = Q.G, nf = q->nf, nblk = q->nblk;
     const dim3 blk(kLoqdBlock);
     const dim3 gc((q->N + kLoqdBlock - 1) / kLoqdBlock, G), gf(nblk, G);
@@ -1069,13 +1126,16 @@ lc_status solve_general(Loqd* q, const Geo& Q, const Gen& Cg, double* E_cell, do
     Vecs V{q->d_vec, q->d_vec + GF, q->d_vec + 2 * GF, q->d_vec + 3 * GF, q->d_vec + 4 * GF, q->d_vec + 5 * GF,
            q->d_vec + 6 * GF, q->d_vec + 7 * GF, q->d_sh};
     if (q->solver != 2 && nf <= kSmallFaces) {
-        if (q->warm) LC_HIP(hipMemcpyAsync(V.x, E_face, GF * sizeof(double), hipMemcpyDeviceToDevice, st));
+        const int rows_per_thread = (nf + kWG - 1) / kWG;
+        // the register form starts from and writes E_face itself
+        double* xf = rows_per_thread <= 8 ? E_face : V.x;
+        if (q->warm && xf != E_face)
+            LC_HIP(hipMemcpyAsync(V.x, E_face, GF * sizeof(double), hipMemcpyDeviceToDevice, st));
         {
-            const int rows_per_thread = (nf + kWG - 1) / kWG;
             const size_t lds = (size_t)nf * sizeof(double) * (rows_per_thread > 4 ? 2 : 1);
             const int wv = q->warm ? 1 : 0;
             auto reg = [&](auto kern) {
-                hipLaunchKernelGGL(kern, dim3(G), dim3(kWG), lds, st, Q, q->d_val, q->d_b, q->d_dinv, V.x, wv, rtol,
+                hipLaunchKernelGGL(kern, dim3(G), dim3(kWG), lds, st, Q, q->d_val, q->d_b, q->d_dinv, xf, wv, rtol,
                                    max_iter, q->d_iters, q->d_resid);
             };
             auto glob = [&](auto kern) {
@@ -1089,26 +1149,17 @@ lc_status solve_general(Loqd* q, const Geo& Q, const Gen& Cg, double* E_cell, do
             else if (rows_per_thread <= 16) glob(k_bicg_group<16>);
             else glob(k_bicg_group<32>);
         }
-        hipLaunchKernelGGL(k_loqd_back, gmax, blk, 0, st, Q, q->d_dc, q->d_ac, q->d_bc, V.x, E_cell, E_face);
+        hipLaunchKernelGGL(k_loqd_back, gmax, blk, 0, st, Q, q->d_dc, q->d_ac, q->d_bc, xf, E_cell, E_face);
         hipLaunchKernelGGL(k_loqd_flux, gf, blk, 0, st, Q, Cg, E_cell, E_face, F_face);
         LC_HIP(hipGetLastError());
-        std::vector<int> hit(G);
-        std::vector<double> hres(G);
-        LC_HIP(hipMemcpyAsync(hit.data(), q->d_iters, G * sizeof(int), hipMemcpyDeviceToHost, st));
-        LC_HIP(hipMemcpyAsync(hres.data(), q->d_resid, G * sizeof(double), hipMemcpyDeviceToHost, st));
+        LC_HIP(hipMemcpyAsync(q->h_iters, q->d_iters, G * sizeof(int), hipMemcpyDeviceToHost, st));
+        LC_HIP(hipMemcpyAsync(q->h_resid, q->d_resid, G * sizeof(double), hipMemcpyDeviceToHost, st));
+        q->pending = true;
+        q->pending_rtol = rtol;
+        q->pending_max_iter = max_iter;
+        if (defer) return LC_OK;
         LC_HIP(hipStreamSynchronize(st));
-        int most = 0;
-        double worst = 0.0;
-        for (int g = 0; g < G; ++g) {
-            most = std::max(most, hit[g]);
-            if (resid) resid[g] = hres[g];
-            worst = std::max(worst, std::isfinite(hres[g]) ? hres[g] : INFINITY);
-        }
-        if (iters) *iters = most;
-        LC_CHECK(worst <= rtol, LC_ERR_UNSUPPORTED,
-                 "LOQD solve did not reach rtol %.3g: residual %.3g after %d iterations (limit %d)", rtol, worst, most,
-                 max_iter);
-        return LC_OK;
+        return check_report(q, iters, resid);
     }
     std::vector<int> flag(G, 1), hflag(G, 1);
     std::vector<double> hsc((size_t)G * kScal);
@@ -1274,6 +1325,9 @@ lc_status lc_loqd_create(int32_t nx, int32_t ny, double lx, double ly, int32_t G
     if (!rc) rc = dalloc(q->owned, &q->d_flag, (size_t)G);
     if (!rc) rc = dalloc(q->owned, &q->d_iters, (size_t)G);
     if (!rc) rc = dalloc(q->owned, &q->d_resid, (size_t)G);
+    if (!rc) rc = halloc(q->owned_host, &q->h_iters, (size_t)G);
+    if (!rc) rc = halloc(q->owned_host, &q->h_resid, (size_t)G);
+    if (!rc) rc = halloc(q->owned_host, &q->h_part, (size_t)G * q->nblk);
     if (rc) {
         free_loqd(q);
         return rc;
@@ -1310,6 +1364,24 @@ lc_status lc_loqd_solve(lc_loqd_t h, double c, double c_dt, const double* kappa,
                         const double* E_prev, const double* F_prev, const double* f_cell, const double* f_face,
                         const double* bnd, double* E_cell, double* E_face, double* F_face, double rtol,
                         int32_t max_iter, int32_t* iters, double* resid, void* stream) {
+    return lc::loqd_solve(h, c, c_dt, kappa, planck, E_prev, F_prev, f_cell, f_face, bnd, E_cell, E_face, F_face, rtol,
+                          max_iter, iters, resid, stream, false);
+}
+
+}  // extern "C"
+
+namespace lc {
+
+lc_status loqd_check_deferred(lc_loqd_t h, int32_t* iters) {
+    Loqd* q = as_loqd(h);
+    LC_CHECK(q, LC_ERR_STATE, "invalid LOQD handle");
+    return check_report(q, iters, nullptr);
+}
+
+lc_status loqd_solve(lc_loqd_t h, double c, double c_dt, const double* kappa, const double* planck,
+                     const double* E_prev, const double* F_prev, const double* f_cell, const double* f_face,
+                     const double* bnd, double* E_cell, double* E_face, double* F_face, double rtol,
+                     int32_t max_iter, int32_t* iters, double* resid, void* stream, bool defer) {
     Loqd* q = as_loqd(h);
     LC_CHECK(q, LC_ERR_STATE, "invalid LOQD handle");
     LC_ARG(kappa && planck && E_prev && F_prev && f_cell && bnd && E_cell && E_face && F_face,
@@ -1327,8 +1399,12 @@ lc_status lc_loqd_solve(lc_loqd_t h, double c, double c_dt, const double* kappa,
                        q->d_bc3, q->d_fp);
     LC_HIP(hipGetLastError());
     const Gen Cg{q->d_sigma, q->d_src, q->d_ks, q->d_es, q->d_fc, q->d_ff, q->d_bc3, q->d_fp};
-    return solve_general(q, Q, Cg, E_cell, E_face, F_face, rtol, max_iter, iters, resid, st);
+    return solve_general(q, Q, Cg, E_cell, E_face, F_face, rtol, max_iter, iters, resid, st, defer);
 }
+
+}  // namespace lc
+
+extern "C" {
 
 lc_status lc_loqd_solve_general(lc_loqd_t h, double c, double c_dt, const double* sigma, const double* source,
                                 const double* k_side, const double* eta_side, const double* F_prev,
@@ -1400,7 +1476,7 @@ lc_status lc_loqd_grey_meb(lc_loqd_t h, double c, double c_dt, const double* kap
     const Gen Cg{q->d_sigma, q->d_src, k_side, eta_side, f_cell, f_face, bc, F_prev};
     const int nblkc = (q->N + kLoqdBlock - 1) / kLoqdBlock;      // <= q->nblk: the partials fit d_part
     const dim3 gc(nblkc, G), blk(kLoqdBlock);
-    std::vector<double> part((size_t)G * nblkc);
+    const size_t n_part = (size_t)G * nblkc;
     int total = 0, k = 0;
     double change = INFINITY;
     std::vector<double> res(G, 0.0);
@@ -1409,19 +1485,23 @@ lc_status lc_loqd_grey_meb(lc_loqd_t h, double c, double c_dt, const double* kap
         hipLaunchKernelGGL(k_meb_linearise, gc, blk, 0, st, Q, M, T, q->d_sigma, q->d_src);
         LC_HIP(hipGetLastError());
         int32_t it = 0;
-        lc_status rc = solve_general(q, Q, Cg, E_cell, E_face, F_face, rtol, max_iter, &it, res.data(), st);
+        // the solve's report and the update's change partials: one wait
+        lc_status rc = solve_general(q, Q, Cg, E_cell, E_face, F_face, rtol, max_iter, &it, res.data(), st, true);
+        if (!rc) {
+            hipLaunchKernelGGL(k_meb_update, gc, blk, 0, st, Q, M, T, E_cell, q->d_part, nblkc);
+            LC_HIP(hipGetLastError());
+            LC_HIP(hipMemcpyAsync(q->h_part, q->d_part, n_part * sizeof(double), hipMemcpyDeviceToHost, st));
+            LC_HIP(hipStreamSynchronize(st));
+            rc = check_report(q, &it, res.data());
+        }
         total += it;
         if (rc) {
             if (iters) *iters = total;
             if (newton_iters) *newton_iters = k;
             return rc;
         }
-        hipLaunchKernelGGL(k_meb_update, gc, blk, 0, st, Q, M, T, E_cell, q->d_part, nblkc);
-        LC_HIP(hipGetLastError());
-        LC_HIP(hipMemcpyAsync(part.data(), q->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-        LC_HIP(hipStreamSynchronize(st));
         change = 0.0;
-        for (double v : part) change = std::max(change, v);
+        for (size_t j = 0; j < n_part; ++j) change = std::max(change, q->h_part[j]);
     }
     if (iters) *iters = total;
     if (newton_iters) *newton_iters = k;

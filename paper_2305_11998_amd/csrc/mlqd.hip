@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "lc_internal.hpp"
+#include "loqd_internal.hpp"
 
 namespace lc {
 
@@ -70,6 +71,7 @@ struct Mlqd {
     double *d_x = nullptr, *d_gx = nullptr, *d_rprev = nullptr, *d_gprev = nullptr;   // [N]
     double *d_dF = nullptr, *d_dG = nullptr;  // [kMaxDepth][N]
     double* d_dots = nullptr;                 // [nblk][kMaxDots] block partial sums
+    double* h_read = nullptr;                 // pinned host copy of d_part or d_dots
     std::vector<void*> owned;
 };
 
@@ -241,6 +243,8 @@ void free_mlqd(Mlqd* h) {
     if (!h) return;
     for (void* p : h->owned) (void)hipFree(p);
     h->owned.clear();
+    if (h->h_read) (void)hipHostFree(h->h_read);
+    h->h_read = nullptr;
     if (h->mg) (void)lc_loqd_free(h->mg);
     if (h->grey) (void)lc_loqd_free(h->grey);
     h->magic = 0;
@@ -260,8 +264,8 @@ lc_status material(Mlqd* h, const double* T, double* kappa, double* planck, hipS
 lc_status change(Mlqd* h, const double* a, const double* b, int rel, double out[2], hipStream_t st) {
     hipLaunchKernelGGL(k_change, dim3(h->nblk), dim3(kMlqdBlock), 0, st, h->N, a, b, rel, h->d_part);
     LC_HIP(hipGetLastError());
-    std::vector<double> part(2 * (size_t)h->nblk);
-    LC_HIP(hipMemcpyAsync(part.data(), h->d_part, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    const double* part = h->h_read;
+    LC_HIP(hipMemcpyAsync(h->h_read, h->d_part, 2 * (size_t)h->nblk * sizeof(double), hipMemcpyDeviceToHost, st));
     LC_HIP(hipStreamSynchronize(st));
     out[0] = out[1] = 0.0;
     for (int k = 0; k < h->nblk; ++k) {
@@ -279,8 +283,9 @@ lc_status aa_gamma(Mlqd* h, int hcols, double* gamma, bool* ok, hipStream_t st) 
     hipLaunchKernelGGL(k_aa_dots, dim3(h->nblk), dim3(kMlqdBlock), 0, st, h->N, hcols, h->d_dF, h->d_rprev,
                        h->d_dots);
     LC_HIP(hipGetLastError());
-    std::vector<double> part((size_t)h->nblk * kMaxDots);
-    LC_HIP(hipMemcpyAsync(part.data(), h->d_dots, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    const double* part = h->h_read;
+    LC_HIP(hipMemcpyAsync(h->h_read, h->d_dots, (size_t)h->nblk * kMaxDots * sizeof(double), hipMemcpyDeviceToHost,
+                          st));
     LC_HIP(hipStreamSynchronize(st));
     std::vector<double> dots(nd, 0.0);
     for (int k = 0; k < h->nblk; ++k)
@@ -396,6 +401,15 @@ lc_status lc_mlqd_create(lc_plan_t plan, const double* nu, const double* edges, 
     if (!rc) rc = dalloc(h->owned, &h->d_dF, (size_t)kMaxDepth * N);
     if (!rc) rc = dalloc(h->owned, &h->d_dG, (size_t)kMaxDepth * N);
     if (!rc) rc = dalloc(h->owned, &h->d_dots, (size_t)h->nblk * kMaxDots);
+    if (!rc) {
+        const size_t bytes = (size_t)h->nblk * std::max(2, kMaxDots) * sizeof(double);
+        if (hipHostMalloc(reinterpret_cast<void**>(&h->h_read), bytes, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            h->h_read = nullptr;
+            set_error("hipHostMalloc(%zu bytes) failed", bytes);
+            rc = LC_ERR_ALLOC;
+        }
+    }
     if (rc) return fail(rc);
     if (hipMemcpy(h->d_nu, nu, G * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(h->d_edges, edges, (G + 1) * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
@@ -496,8 +510,10 @@ lc_status lc_mlqd_step(lc_mlqd_t handle, double c_dt, const void* state_prev, vo
             const double ntol = std::max(newton_tol, 1e3 * rtol);
             hipLaunchKernelGGL(k_exp, gN, bN, 0, st, N, h->d_x, h->d_Tl);
             rc = material(h, h->d_Tl, h->d_kappa, h->d_planck, st);
-            if (!rc) rc = lc_loqd_solve(h->mg, c, c_dt, h->d_kappa, h->d_planck, E_prev, F_prev, h->d_f, h->d_ff,
-                                        h->d_bnd, E_cell, E_face, F_face, rtol, max_iter, nullptr, nullptr, st);
+            // the multigroup solve's report is checked after the grey
+            // problem's first wait on the stream
+            if (!rc) rc = loqd_solve(h->mg, c, c_dt, h->d_kappa, h->d_planck, E_prev, F_prev, h->d_f, h->d_ff,
+                                     h->d_bnd, E_cell, E_face, F_face, rtol, max_iter, nullptr, nullptr, st, true);
             if (!rc) rc = lc_loqd_grey_coefficients(h->mg, c, c_dt, h->d_kappa, h->d_planck, E_prev, F_prev, h->d_f,
                                                     h->d_ff, h->d_bnd, E_cell, E_face, F_face, h->d_sigma, h->d_src,
                                                     h->d_ks, h->d_es, h->d_fp, h->d_fc, h->d_ffg, h->d_bc, h->d_ep,
@@ -507,6 +523,7 @@ lc_status lc_mlqd_step(lc_mlqd_t handle, double c_dt, const void* state_prev, vo
             rc = lc_loqd_grey_meb(h->grey, c, c_dt, h->d_kE, h->d_kB, h->d_ep, h->d_ks, h->d_es, h->d_fp, h->d_fc,
                                   h->d_ffg, h->d_bc, T_prev, h->c_v, h->a_R, h->d_Tn, h->d_Eg, h->d_Egf, h->d_Fgf,
                                   ntol, 100, rtol, max_iter, nullptr, nullptr, nullptr, st);
+            if (!rc) rc = loqd_check_deferred(h->mg, nullptr);
             if (rc) break;
             double ch[2];
             rc = change(h, h->d_Tn, h->d_Tl, 1, ch, st);
