@@ -259,34 +259,51 @@ lc_status material(Mlqd* h, const double* T, double* kappa, double* planck, hipS
     return LC_OK;
 }
 
-// Largest change between a and b (see k_change); out[0] the change, out[1]
-// max |a|.  Synchronises the stream.
-lc_status change(Mlqd* h, const double* a, const double* b, int rel, double out[2], hipStream_t st) {
+// Largest change between a and b (see k_change), in two halves: the
+// partials are queued (kernel and a copy into the pinned buffer), then read
+// after the caller's wait on the stream; out[0] the change, out[1] max |a|.
+lc_status change_queue(Mlqd* h, const double* a, const double* b, int rel, hipStream_t st) {
     hipLaunchKernelGGL(k_change, dim3(h->nblk), dim3(kMlqdBlock), 0, st, h->N, a, b, rel, h->d_part);
     LC_HIP(hipGetLastError());
-    const double* part = h->h_read;
     LC_HIP(hipMemcpyAsync(h->h_read, h->d_part, 2 * (size_t)h->nblk * sizeof(double), hipMemcpyDeviceToHost, st));
-    LC_HIP(hipStreamSynchronize(st));
+    return LC_OK;
+}
+
+void change_read(const Mlqd* h, double out[2]) {
+    const double* part = h->h_read;
     out[0] = out[1] = 0.0;
     for (int k = 0; k < h->nblk; ++k) {
         out[0] = std::max(out[0], part[2 * k]);
         out[1] = std::max(out[1], part[2 * k + 1]);
     }
+}
+
+// Both halves with a wait between them.
+lc_status change(Mlqd* h, const double* a, const double* b, int rel, double out[2], hipStream_t st) {
+    lc_status rc = change_queue(h, a, b, rel, st);
+    if (rc) return rc;
+    LC_HIP(hipStreamSynchronize(st));
+    change_read(h, out);
     return LC_OK;
 }
 
 // Anderson coefficients: gamma minimising |r - dF gamma| from the normal
 // equations (dF^T dF) gamma = dF^T r, by Gaussian elimination with partial
-// pivoting.  False when the history is numerically rank-deficient.
-lc_status aa_gamma(Mlqd* h, int hcols, double* gamma, bool* ok, hipStream_t st) {
-    const int nd = hcols * (hcols + 1) / 2 + hcols;
+// pivoting.  False when the history is numerically rank-deficient.  Again
+// two halves: the Gram partials are queued into the pinned buffer (after the
+// change partials), and aa_gamma solves once the caller has waited.
+lc_status aa_queue(Mlqd* h, int hcols, hipStream_t st) {
     hipLaunchKernelGGL(k_aa_dots, dim3(h->nblk), dim3(kMlqdBlock), 0, st, h->N, hcols, h->d_dF, h->d_rprev,
                        h->d_dots);
     LC_HIP(hipGetLastError());
-    const double* part = h->h_read;
-    LC_HIP(hipMemcpyAsync(h->h_read, h->d_dots, (size_t)h->nblk * kMaxDots * sizeof(double), hipMemcpyDeviceToHost,
-                          st));
-    LC_HIP(hipStreamSynchronize(st));
+    LC_HIP(hipMemcpyAsync(h->h_read + 2 * (size_t)h->nblk, h->d_dots, (size_t)h->nblk * kMaxDots * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+    return LC_OK;
+}
+
+void aa_gamma(const Mlqd* h, int hcols, double* gamma, bool* ok) {
+    const int nd = hcols * (hcols + 1) / 2 + hcols;
+    const double* part = h->h_read + 2 * (size_t)h->nblk;
     std::vector<double> dots(nd, 0.0);
     for (int k = 0; k < h->nblk; ++k)
         for (int d = 0; d < nd; ++d) dots[d] += part[(size_t)k * kMaxDots + d];
@@ -318,7 +335,6 @@ lc_status aa_gamma(Mlqd* h, int hcols, double* gamma, bool* ok, hipStream_t st) 
         gamma[a] = v / A[a][a];
         *ok = std::isfinite(gamma[a]);
     }
-    return LC_OK;
 }
 
 }  // namespace
@@ -402,7 +418,7 @@ lc_status lc_mlqd_create(lc_plan_t plan, const double* nu, const double* edges, 
     if (!rc) rc = dalloc(h->owned, &h->d_dG, (size_t)kMaxDepth * N);
     if (!rc) rc = dalloc(h->owned, &h->d_dots, (size_t)h->nblk * kMaxDots);
     if (!rc) {
-        const size_t bytes = (size_t)h->nblk * std::max(2, kMaxDots) * sizeof(double);
+        const size_t bytes = (size_t)h->nblk * (2 + kMaxDots) * sizeof(double);
         if (hipHostMalloc(reinterpret_cast<void**>(&h->h_read), bytes, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             h->h_read = nullptr;
@@ -525,11 +541,13 @@ lc_status lc_mlqd_step(lc_mlqd_t handle, double c_dt, const void* state_prev, vo
                                   ntol, 100, rtol, max_iter, nullptr, nullptr, nullptr, st);
             if (!rc) rc = loqd_check_deferred(h->mg, nullptr);
             if (rc) break;
+            // the pass's change and the Anderson update with its Gram
+            // partials are queued together and read after one wait (when the
+            // pass ends the iteration, the update is simply not used: the
+            // next transport iteration starts a new history)
             double ch[2];
-            rc = change(h, h->d_Tn, h->d_Tl, 1, ch, st);
+            rc = change_queue(h, h->d_Tn, h->d_Tl, 1, st);
             if (rc) break;
-            level = ch[0];
-            if (ch[0] <= eps && rtol == rtol_min) break;
             const bool push = have_prev && h->depth > 0;
             hipLaunchKernelGGL(k_aa_update, gN, bN, 0, st, N, h->d_Tn, h->d_x, h->d_gx, h->d_rprev, h->d_gprev,
                                h->d_dF + (size_t)slot * N, h->d_dG + (size_t)slot * N, push ? 1 : 0);
@@ -539,12 +557,17 @@ lc_status lc_mlqd_step(lc_mlqd_t handle, double c_dt, const void* state_prev, vo
                 slot = (slot + 1) % h->depth;
             }
             have_prev = true;
-            double gamma[kMaxDepth] = {0, 0, 0, 0, 0, 0, 0, 0};
-            bool ok = false;
             if (hcols > 0) {
-                rc = aa_gamma(h, hcols, gamma, &ok, st);
+                rc = aa_queue(h, hcols, st);
                 if (rc) break;
             }
+            LC_HIP(hipStreamSynchronize(st));
+            change_read(h, ch);
+            level = ch[0];
+            if (ch[0] <= eps && rtol == rtol_min) break;
+            double gamma[kMaxDepth] = {0, 0, 0, 0, 0, 0, 0, 0};
+            bool ok = false;
+            if (hcols > 0) aa_gamma(h, hcols, gamma, &ok);
             if (ok) {
                 hipLaunchKernelGGL(k_aa_mix, gN, bN, 0, st, N, hcols, h->d_gx, h->d_dG, gamma[0], gamma[1], gamma[2],
                                    gamma[3], gamma[4], gamma[5], gamma[6], gamma[7], h->d_x);
