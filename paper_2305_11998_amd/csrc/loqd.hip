@@ -88,12 +88,10 @@ struct Loqd {
     int* d_flag = nullptr;            // [G] 1 = iterating
     bool warm = false;                // BiCGSTAB starts from the E_face output's contents
     int solver = 0;                   // 0 by size, 1 one workgroup per group, 2 many blocks per group
-    int* d_iters = nullptr;           // [G] iterations (one-workgroup solver)
-    double* d_resid = nullptr;        // [G] final relative residuals (one-workgroup solver)
+    double* d_report = nullptr;       // [2][G] final relative residuals, then iterations (one-workgroup solver)
     // pinned host copies of the convergence report and of the Newton change
     // partials, so that copies queued together need one wait
-    int* h_iters = nullptr;           // [G]
-    double* h_resid = nullptr;        // [G]
+    double* h_report = nullptr;       // [2][G]
     double* h_part = nullptr;         // [G * nblk]
     // a one-workgroup solve whose report was queued but not yet checked
     bool pending = false;
@@ -408,8 +406,8 @@ __global__ void k_bi_x(Geo Q, Vecs V, const double* sc, const int* flag, double*
 // recursive residual reaches rtol, at most 3 of them).  Every scalar comes
 // from a fixed-order reduction that all threads read, so the control flow
 // is uniform over the workgroup.  x starts from zero, or from its
-// contents with warm != 0.  iters[g], resid[g]: iterations and the final
-// relative residual (as the many-block path reports it).
+// contents with warm != 0.  report[g]: the final relative residual (as
+// the many-block path reports it); report[G + g]: the iterations.
 // Within each wavefront a butterfly over the 64 lanes (lane 0's sum, whose
 // order is fixed, is the one kept), then the wavefronts' partials added in
 // wavefront order by every thread: two barriers a reduction.
@@ -441,7 +439,7 @@ __device__ inline void wg_sum2(double& a, double& b, double* sa, double* sb) {
 template <int R>
 __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restrict__ val, const double* __restrict__ bv,
                                                      const double* __restrict__ dinv, Vecs V, int warm, double rtol,
-                                                     int max_iter, int* iters, double* resid) {
+                                                     int max_iter, double* report) {
     __shared__ double sa[kWG / 64], sb[kWG / 64];
     const int g = blockIdx.x, nf = Q.nf, tid = threadIdx.x;
     const size_t o = (size_t)g * nf;
@@ -588,8 +586,8 @@ __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restr
         rnorm = sqrt(e2);
     }
     if (tid == 0) {
-        iters[g] = it;
-        resid[g] = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+        report[g] = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+        report[gridDim.x + g] = it;
     }
 }
 
@@ -603,7 +601,7 @@ template <int R>
 __global__ __launch_bounds__(kWG) void k_bicg_reg(Geo Q, const double* __restrict__ val,
                                                    const double* __restrict__ bv, const double* __restrict__ dinv,
                                                    double* __restrict__ xv, int warm, double rtol, int max_iter,
-                                                   int* iters, double* resid) {
+                                                   double* report) {
     // With R <= 4 the compiler keeps the matrix rows of a thread in
     // registers across iterations too.  With R = 8 neither they nor all the
     // rows' product loads in flight fit beside the vectors: the products
@@ -806,8 +804,8 @@ __global__ __launch_bounds__(kWG) void k_bicg_reg(Geo Q, const double* __restric
         if (f < nf) xv[o + f] = x[j];
     }
     if (tid == 0) {
-        iters[g] = it;
-        resid[g] = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+        report[g] = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+        report[gridDim.x + g] = it;
     }
 }
 
@@ -845,12 +843,10 @@ __global__ void k_loqd_flux(Geo Q, Gen C, const double* __restrict__ E_cell, con
 }
 
 // Multigroup inputs (eq. (4)) in general form.
-__global__ void k_loqd_prep_cells(Geo Q, const double* __restrict__ kappa, const double* __restrict__ planck,
-                                  const double* __restrict__ E_prev, const double* __restrict__ f_cell, double* sigma,
-                                  double* src, double* ks, double* es, double* fc) {
-    const int g = blockIdx.y;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Q.N) return;
+__device__ inline void loqd_prep_cell(const Geo& Q, int g, int i, const double* __restrict__ kappa,
+                                      const double* __restrict__ planck, const double* __restrict__ E_prev,
+                                      const double* __restrict__ f_cell, double* sigma, double* src, double* ks,
+                                      double* es, double* fc) {
     const size_t gi = (size_t)g * Q.N + i;
     const double kap = kappa[gi];
     const double kt = kap + 1.0 / Q.c_dt;
@@ -863,11 +859,9 @@ __global__ void k_loqd_prep_cells(Geo Q, const double* __restrict__ kappa, const
     for (int q = 0; q < 3; ++q) fc[((size_t)g * 3 + q) * Q.N + i] = f_cell[((size_t)i * 4 + q) * Q.G + g];
 }
 
-__global__ void k_loqd_prep_faces(Geo Q, const double* __restrict__ F_prev, const double* __restrict__ f_face,
-                                  const double* __restrict__ bnd, double* ff, double* bc3, double* fp) {
-    const int g = blockIdx.y;
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= Q.nf) return;
+__device__ inline void loqd_prep_face(const Geo& Q, int g, int f, const double* __restrict__ F_prev,
+                                      const double* __restrict__ f_face, const double* __restrict__ bnd, double* ff,
+                                      double* bc3, double* fp) {
     const int nb = Q.nf - Q.nint;
     for (int q = 0; q < 3; ++q)
         ff[((size_t)g * 3 + q) * Q.nf + f] = f < Q.nint ? f_face[((size_t)f * 4 + q) * Q.G + g]
@@ -882,17 +876,28 @@ __global__ void k_loqd_prep_faces(Geo Q, const double* __restrict__ F_prev, cons
     }
 }
 
+// Both preparations in one launch: thread t takes cell t and face t.
+__global__ void k_loqd_prep(Geo Q, const double* __restrict__ kappa, const double* __restrict__ planck,
+                            const double* __restrict__ E_prev, const double* __restrict__ f_cell,
+                            const double* __restrict__ F_prev, const double* __restrict__ f_face,
+                            const double* __restrict__ bnd, double* sigma, double* src, double* ks, double* es,
+                            double* fc, double* ff, double* bc3, double* fp) {
+    const int g = blockIdx.y;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < Q.N) loqd_prep_cell(Q, g, t, kappa, planck, E_prev, f_cell, sigma, src, ks, es, fc);
+    if (t < Q.nf) loqd_prep_face(Q, g, t, F_prev, f_face, bnd, ff, bc3, fp);
+}
+
 // Grey coefficients (eq. (5) in general form) from a multigroup solution:
 // per cell the energy-weighted and Planck-weighted opacities, per cell side
 // K_R from the normal face fluxes and eta, and the cell's spectrum-averaged
 // tensor; fixed-order sums over the groups.
-__global__ void k_grey_cells(Geo Q, const double* __restrict__ kappa, const double* __restrict__ planck,
-                             const double* __restrict__ E_prev, const double* __restrict__ f_cell,
-                             const double* __restrict__ E_cell, const double* __restrict__ E_face,
-                             const double* __restrict__ F_face, double* sigma, double* src, double* ks, double* es,
-                             double* fc, double* Ep, double* kEo, double* kBo) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= Q.N) return;
+__device__ inline void grey_cell(const Geo& Q, int i, const double* __restrict__ kappa,
+                                 const double* __restrict__ planck, const double* __restrict__ E_prev,
+                                 const double* __restrict__ f_cell, const double* __restrict__ E_cell,
+                                 const double* __restrict__ E_face, const double* __restrict__ F_face, double* sigma,
+                                 double* src, double* ks, double* es, double* fc, double* Ep, double* kEo,
+                                 double* kBo) {
     const int G = Q.G;
     double E = 0.0, kE = 0.0, sB = 0.0, kB = 0.0, sk = 0.0, ep = 0.0, t[3] = {0.0, 0.0, 0.0};
     // the group loops are unrolled so that several groups' loads are in
@@ -940,11 +945,9 @@ __global__ void k_grey_cells(Geo Q, const double* __restrict__ kappa, const doub
     }
 }
 
-__global__ void k_grey_faces(Geo Q, const double* __restrict__ F_prev, const double* __restrict__ f_face,
-                             const double* __restrict__ bnd, const double* __restrict__ E_face, double* ff,
-                             double* bc3, double* fp) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= Q.nf) return;
+__device__ inline void grey_face(const Geo& Q, int f, const double* __restrict__ F_prev,
+                                 const double* __restrict__ f_face, const double* __restrict__ bnd,
+                                 const double* __restrict__ E_face, double* ff, double* bc3, double* fp) {
     const int G = Q.G, nb = Q.nf - Q.nint;
     double Ef = 0.0, t[3] = {0.0, 0.0, 0.0}, p = 0.0, cE = 0.0, cs = 0.0, jm = 0.0;
 #pragma unroll 4
@@ -972,6 +975,20 @@ __global__ void k_grey_faces(Geo Q, const double* __restrict__ F_prev, const dou
         o[1] = 0.0;
         o[2] = jm;
     }
+}
+
+// Both in one launch: thread t takes cell t and face t.
+__global__ void k_grey_coef(Geo Q, const double* __restrict__ kappa, const double* __restrict__ planck,
+                            const double* __restrict__ E_prev, const double* __restrict__ f_cell,
+                            const double* __restrict__ E_cell, const double* __restrict__ E_face,
+                            const double* __restrict__ F_face, const double* __restrict__ F_prev,
+                            const double* __restrict__ f_face, const double* __restrict__ bnd, double* sigma,
+                            double* src, double* ks, double* es, double* fc, double* Ep, double* kEo, double* kBo,
+                            double* ff, double* bc3, double* fp) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < Q.N) grey_cell(Q, t, kappa, planck, E_prev, f_cell, E_cell, E_face, F_face, sigma, src, ks, es, fc, Ep, kEo,
+                           kBo);
+    if (t < Q.nf) grey_face(Q, t, F_prev, f_face, bnd, E_face, ff, bc3, fp);
 }
 
 // Grey energy balance, eq. (6) with eps = c_v T (inputs of one Newton
@@ -1094,9 +1111,10 @@ lc_status check_report(Loqd* q, int32_t* iters, double* resid) {
     int most = 0;
     double worst = 0.0;
     for (int g = 0; g < q->G; ++g) {
-        most = std::max(most, q->h_iters[g]);
-        if (resid) resid[g] = q->h_resid[g];
-        worst = std::max(worst, std::isfinite(q->h_resid[g]) ? q->h_resid[g] : INFINITY);
+        const double rg = q->h_report[g];
+        most = std::max(most, (int)q->h_report[q->G + g]);
+        if (resid) resid[g] = rg;
+        worst = std::max(worst, std::isfinite(rg) ? rg : INFINITY);
     }
     if (iters) *iters = most;
     LC_CHECK(worst <= q->pending_rtol, LC_ERR_UNSUPPORTED,
@@ -1136,11 +1154,11 @@ lc_status solve_general(Loqd* q, const Geo& Q, const Gen& Cg, double* E_cell, do
             const int wv = q->warm ? 1 : 0;
             auto reg = [&](auto kern) {
                 hipLaunchKernelGGL(kern, dim3(G), dim3(kWG), lds, st, Q, q->d_val, q->d_b, q->d_dinv, xf, wv, rtol,
-                                   max_iter, q->d_iters, q->d_resid);
+                                   max_iter, q->d_report);
             };
             auto glob = [&](auto kern) {
                 hipLaunchKernelGGL(kern, dim3(G), dim3(kWG), 0, st, Q, q->d_val, q->d_b, q->d_dinv, V, wv, rtol,
-                                   max_iter, q->d_iters, q->d_resid);
+                                   max_iter, q->d_report);
             };
             if (rows_per_thread <= 1) reg(k_bicg_reg<1>);
             else if (rows_per_thread <= 2) reg(k_bicg_reg<2>);
@@ -1152,8 +1170,7 @@ lc_status solve_general(Loqd* q, const Geo& Q, const Gen& Cg, double* E_cell, do
         hipLaunchKernelGGL(k_loqd_back, gmax, blk, 0, st, Q, q->d_dc, q->d_ac, q->d_bc, xf, E_cell, E_face);
         hipLaunchKernelGGL(k_loqd_flux, gf, blk, 0, st, Q, Cg, E_cell, E_face, F_face);
         LC_HIP(hipGetLastError());
-        LC_HIP(hipMemcpyAsync(q->h_iters, q->d_iters, G * sizeof(int), hipMemcpyDeviceToHost, st));
-        LC_HIP(hipMemcpyAsync(q->h_resid, q->d_resid, G * sizeof(double), hipMemcpyDeviceToHost, st));
+        LC_HIP(hipMemcpyAsync(q->h_report, q->d_report, 2 * G * sizeof(double), hipMemcpyDeviceToHost, st));
         q->pending = true;
         q->pending_rtol = rtol;
         q->pending_max_iter = max_iter;
@@ -1323,10 +1340,8 @@ lc_status lc_loqd_create(int32_t nx, int32_t ny, double lx, double ly, int32_t G
     if (!rc) rc = dalloc(q->owned, &q->d_part, (size_t)G * q->nblk * 2);
     if (!rc) rc = dalloc(q->owned, &q->d_sc, (size_t)G * kScal);
     if (!rc) rc = dalloc(q->owned, &q->d_flag, (size_t)G);
-    if (!rc) rc = dalloc(q->owned, &q->d_iters, (size_t)G);
-    if (!rc) rc = dalloc(q->owned, &q->d_resid, (size_t)G);
-    if (!rc) rc = halloc(q->owned_host, &q->h_iters, (size_t)G);
-    if (!rc) rc = halloc(q->owned_host, &q->h_resid, (size_t)G);
+    if (!rc) rc = dalloc(q->owned, &q->d_report, 2 * (size_t)G);
+    if (!rc) rc = halloc(q->owned_host, &q->h_report, 2 * (size_t)G);
     if (!rc) rc = halloc(q->owned_host, &q->h_part, (size_t)G * q->nblk);
     if (rc) {
         free_loqd(q);
@@ -1393,10 +1408,9 @@ lc_status loqd_solve(lc_loqd_t h, double c, double c_dt, const double* kappa, co
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Geo Q = geo(q, c, c_dt, q->G);
     const dim3 blk(kLoqdBlock);
-    hipLaunchKernelGGL(k_loqd_prep_cells, dim3((q->N + kLoqdBlock - 1) / kLoqdBlock, q->G), blk, 0, st, Q, kappa,
-                       planck, E_prev, f_cell, q->d_sigma, q->d_src, q->d_ks, q->d_es, q->d_fc);
-    hipLaunchKernelGGL(k_loqd_prep_faces, dim3(q->nblk, q->G), blk, 0, st, Q, F_prev, f_face, bnd, q->d_ff,
-                       q->d_bc3, q->d_fp);
+    hipLaunchKernelGGL(k_loqd_prep, dim3((std::max(q->N, q->nf) + kLoqdBlock - 1) / kLoqdBlock, q->G), blk, 0, st, Q,
+                       kappa, planck, E_prev, f_cell, F_prev, f_face, bnd, q->d_sigma, q->d_src, q->d_ks, q->d_es,
+                       q->d_fc, q->d_ff, q->d_bc3, q->d_fp);
     LC_HIP(hipGetLastError());
     const Gen Cg{q->d_sigma, q->d_src, q->d_ks, q->d_es, q->d_fc, q->d_ff, q->d_bc3, q->d_fp};
     return solve_general(q, Q, Cg, E_cell, E_face, F_face, rtol, max_iter, iters, resid, st, defer);
@@ -1443,11 +1457,9 @@ lc_status lc_loqd_grey_coefficients(lc_loqd_t h, double c, double c_dt, const do
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Geo Q = geo(q, c, c_dt, q->G);
     const dim3 blk(kLoqdBlock);
-    hipLaunchKernelGGL(k_grey_cells, dim3((q->N + kLoqdBlock - 1) / kLoqdBlock), blk, 0, st, Q, kappa, planck, E_prev,
-                       f_cell, E_cell, E_face, F_face, sigma, source, k_side, eta_side, f_cell_grey, E_prev_grey,
-                       kappa_E, kappa_B);
-    hipLaunchKernelGGL(k_grey_faces, dim3(q->nblk), blk, 0, st, Q, F_prev, f_face, bnd, E_face, f_face_grey, bc_grey,
-                       F_prev_grey);
+    hipLaunchKernelGGL(k_grey_coef, dim3((std::max(q->N, q->nf) + kLoqdBlock - 1) / kLoqdBlock), blk, 0, st, Q, kappa,
+                       planck, E_prev, f_cell, E_cell, E_face, F_face, F_prev, f_face, bnd, sigma, source, k_side,
+                       eta_side, f_cell_grey, E_prev_grey, kappa_E, kappa_B, f_face_grey, bc_grey, F_prev_grey);
     LC_HIP(hipGetLastError());
     return LC_OK;
 }

@@ -157,26 +157,51 @@ __global__ void k_log(int n, const double* __restrict__ T, double* x) {
     if (i < n) x[i] = log(T[i]);
 }
 
-__global__ void k_exp(int n, const double* __restrict__ x, double* T) {
+// T = T2 = exp(x): the pass's temperature, and the Newton iterate that
+// starts from it.
+__global__ void k_exp(int n, const double* __restrict__ x, double* T, double* T2) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) T[i] = exp(x[i]);
+    if (i < n) T[i] = T2[i] = exp(x[i]);
 }
 
 // After a pass: g = log Phi, r = g - x; with a previous pass, the history
 // column `slot` takes dF = r - r_prev, dG = g - g_prev; then r_prev = r,
-// g_prev = g.
-__global__ void k_aa_update(int n, const double* __restrict__ Tn, const double* __restrict__ x, double* gx,
-                            double* rprev, double* gprev, double* dF, double* dG, int have_prev) {
+// g_prev = g.  Also the pass's change, as k_change with rel = 1 on
+// (Phi, T): per block max |Phi - T| / |Phi| and max |Phi|.
+__global__ void k_aa_update(int n, const double* __restrict__ Tn, const double* __restrict__ Tl,
+                            const double* __restrict__ x, double* gx, double* rprev, double* gprev, double* dF,
+                            double* dG, int have_prev, double* part) {
+    __shared__ double s0[kMlqdBlock], s1[kMlqdBlock];
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double g = log(Tn[i]), r = g - x[i];
-    if (have_prev) {
-        dF[i] = r - rprev[i];
-        dG[i] = g - gprev[i];
+    double d = 0.0, m = 0.0;
+    if (i < n) {
+        const double a = Tn[i];
+        const double g = log(a), r = g - x[i];
+        if (have_prev) {
+            dF[i] = r - rprev[i];
+            dG[i] = g - gprev[i];
+        }
+        gx[i] = g;
+        rprev[i] = r;
+        gprev[i] = g;
+        d = fabs(a - Tl[i]) / fabs(a);
+        m = fabs(a);
+        if (!std::isfinite(d)) d = INFINITY;
     }
-    gx[i] = g;
-    rprev[i] = r;
-    gprev[i] = g;
+    s0[threadIdx.x] = d;
+    s1[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = kMlqdBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            s0[threadIdx.x] = fmax(s0[threadIdx.x], s0[threadIdx.x + w]);
+            s1[threadIdx.x] = fmax(s1[threadIdx.x], s1[threadIdx.x + w]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = s0[0];
+        part[2 * blockIdx.x + 1] = s1[0];
+    }
 }
 
 // Block partial sums of dF_a . dF_b (a <= b < h, row-major upper triangle)
@@ -259,16 +284,8 @@ lc_status material(Mlqd* h, const double* T, double* kappa, double* planck, hipS
     return LC_OK;
 }
 
-// Largest change between a and b (see k_change), in two halves: the
-// partials are queued (kernel and a copy into the pinned buffer), then read
-// after the caller's wait on the stream; out[0] the change, out[1] max |a|.
-lc_status change_queue(Mlqd* h, const double* a, const double* b, int rel, hipStream_t st) {
-    hipLaunchKernelGGL(k_change, dim3(h->nblk), dim3(kMlqdBlock), 0, st, h->N, a, b, rel, h->d_part);
-    LC_HIP(hipGetLastError());
-    LC_HIP(hipMemcpyAsync(h->h_read, h->d_part, 2 * (size_t)h->nblk * sizeof(double), hipMemcpyDeviceToHost, st));
-    return LC_OK;
-}
-
+// Per-block partials of a change (k_change or k_aa_update), read from the
+// pinned buffer after the caller's wait: out[0] the change, out[1] max |a|.
 void change_read(const Mlqd* h, double out[2]) {
     const double* part = h->h_read;
     out[0] = out[1] = 0.0;
@@ -278,10 +295,11 @@ void change_read(const Mlqd* h, double out[2]) {
     }
 }
 
-// Both halves with a wait between them.
+// Largest change between a and b (see k_change).  Synchronises the stream.
 lc_status change(Mlqd* h, const double* a, const double* b, int rel, double out[2], hipStream_t st) {
-    lc_status rc = change_queue(h, a, b, rel, st);
-    if (rc) return rc;
+    hipLaunchKernelGGL(k_change, dim3(h->nblk), dim3(kMlqdBlock), 0, st, h->N, a, b, rel, h->d_part);
+    LC_HIP(hipGetLastError());
+    LC_HIP(hipMemcpyAsync(h->h_read, h->d_part, 2 * (size_t)h->nblk * sizeof(double), hipMemcpyDeviceToHost, st));
     LC_HIP(hipStreamSynchronize(st));
     change_read(h, out);
     return LC_OK;
@@ -289,17 +307,10 @@ lc_status change(Mlqd* h, const double* a, const double* b, int rel, double out[
 
 // Anderson coefficients: gamma minimising |r - dF gamma| from the normal
 // equations (dF^T dF) gamma = dF^T r, by Gaussian elimination with partial
-// pivoting.  False when the history is numerically rank-deficient.  Again
-// two halves: the Gram partials are queued into the pinned buffer (after the
-// change partials), and aa_gamma solves once the caller has waited.
-lc_status aa_queue(Mlqd* h, int hcols, hipStream_t st) {
-    hipLaunchKernelGGL(k_aa_dots, dim3(h->nblk), dim3(kMlqdBlock), 0, st, h->N, hcols, h->d_dF, h->d_rprev,
-                       h->d_dots);
-    LC_HIP(hipGetLastError());
-    LC_HIP(hipMemcpyAsync(h->h_read + 2 * (size_t)h->nblk, h->d_dots, (size_t)h->nblk * kMaxDots * sizeof(double),
-                          hipMemcpyDeviceToHost, st));
-    return LC_OK;
-}
+// pivoting.  False when the history is numerically rank-deficient.  The
+// Gram partials (d_dots, right after the change partials d_part on the
+// device and in the pinned buffer) are copied by the caller with the
+// change's, and aa_gamma solves once the caller has waited.
 
 void aa_gamma(const Mlqd* h, int hcols, double* gamma, bool* ok) {
     const int nd = hcols * (hcols + 1) / 2 + hcols;
@@ -411,12 +422,12 @@ lc_status lc_mlqd_create(lc_plan_t plan, const double* nu, const double* edges, 
     if (!rc) rc = dalloc(h->owned, &h->d_bc, 3 * (size_t)nb);
     if (!rc) rc = dalloc(h->owned, &h->d_Egf, (size_t)nf);
     if (!rc) rc = dalloc(h->owned, &h->d_Fgf, (size_t)nf);
-    if (!rc) rc = dalloc(h->owned, &h->d_part, 2 * (size_t)h->nblk);
+    if (!rc) rc = dalloc(h->owned, &h->d_part, (2 + (size_t)kMaxDots) * h->nblk);   // then d_dots
+    if (!rc) h->d_dots = h->d_part + 2 * (size_t)h->nblk;
     for (double** p : {&h->d_x, &h->d_gx, &h->d_rprev, &h->d_gprev})
         if (!rc) rc = dalloc(h->owned, p, (size_t)N);
     if (!rc) rc = dalloc(h->owned, &h->d_dF, (size_t)kMaxDepth * N);
     if (!rc) rc = dalloc(h->owned, &h->d_dG, (size_t)kMaxDepth * N);
-    if (!rc) rc = dalloc(h->owned, &h->d_dots, (size_t)h->nblk * kMaxDots);
     if (!rc) {
         const size_t bytes = (size_t)h->nblk * (2 + kMaxDots) * sizeof(double);
         if (hipHostMalloc(reinterpret_cast<void**>(&h->h_read), bytes, hipHostMallocDefault) != hipSuccess) {
@@ -524,7 +535,7 @@ lc_status lc_mlqd_step(lc_mlqd_t handle, double c_dt, const void* state_prev, vo
             ++inner;
             const double rtol = std::min(rtol_max, std::max(rtol_min, 1e-3 * level));
             const double ntol = std::max(newton_tol, 1e3 * rtol);
-            hipLaunchKernelGGL(k_exp, gN, bN, 0, st, N, h->d_x, h->d_Tl);
+            hipLaunchKernelGGL(k_exp, gN, bN, 0, st, N, h->d_x, h->d_Tl, h->d_Tn);
             rc = material(h, h->d_Tl, h->d_kappa, h->d_planck, st);
             // the multigroup solve's report is checked after the grey
             // problem's first wait on the stream
@@ -535,7 +546,6 @@ lc_status lc_mlqd_step(lc_mlqd_t handle, double c_dt, const void* state_prev, vo
                                                     h->d_ks, h->d_es, h->d_fp, h->d_fc, h->d_ffg, h->d_bc, h->d_ep,
                                                     h->d_kE, h->d_kB, st);
             if (rc) break;
-            LC_HIP(hipMemcpyAsync(h->d_Tn, h->d_Tl, bytesN, hipMemcpyDeviceToDevice, st));
             rc = lc_loqd_grey_meb(h->grey, c, c_dt, h->d_kE, h->d_kB, h->d_ep, h->d_ks, h->d_es, h->d_fp, h->d_fc,
                                   h->d_ffg, h->d_bc, T_prev, h->c_v, h->a_R, h->d_Tn, h->d_Eg, h->d_Egf, h->d_Fgf,
                                   ntol, 100, rtol, max_iter, nullptr, nullptr, nullptr, st);
@@ -546,21 +556,22 @@ lc_status lc_mlqd_step(lc_mlqd_t handle, double c_dt, const void* state_prev, vo
             // pass ends the iteration, the update is simply not used: the
             // next transport iteration starts a new history)
             double ch[2];
-            rc = change_queue(h, h->d_Tn, h->d_Tl, 1, st);
-            if (rc) break;
             const bool push = have_prev && h->depth > 0;
-            hipLaunchKernelGGL(k_aa_update, gN, bN, 0, st, N, h->d_Tn, h->d_x, h->d_gx, h->d_rprev, h->d_gprev,
-                               h->d_dF + (size_t)slot * N, h->d_dG + (size_t)slot * N, push ? 1 : 0);
-            LC_HIP(hipGetLastError());
+            hipLaunchKernelGGL(k_aa_update, gN, bN, 0, st, N, h->d_Tn, h->d_Tl, h->d_x, h->d_gx, h->d_rprev,
+                               h->d_gprev, h->d_dF + (size_t)slot * N, h->d_dG + (size_t)slot * N, push ? 1 : 0,
+                               h->d_part);
             if (push) {
                 hcols = std::min(hcols + 1, h->depth);
                 slot = (slot + 1) % h->depth;
             }
             have_prev = true;
+            size_t n_read = 2 * (size_t)h->nblk;
             if (hcols > 0) {
-                rc = aa_queue(h, hcols, st);
-                if (rc) break;
+                hipLaunchKernelGGL(k_aa_dots, gN, bN, 0, st, N, hcols, h->d_dF, h->d_rprev, h->d_dots);
+                n_read += (size_t)h->nblk * kMaxDots;
             }
+            LC_HIP(hipGetLastError());
+            LC_HIP(hipMemcpyAsync(h->h_read, h->d_part, n_read * sizeof(double), hipMemcpyDeviceToHost, st));
             LC_HIP(hipStreamSynchronize(st));
             change_read(h, ch);
             level = ch[0];

@@ -124,3 +124,22 @@ def test_split_gathers_match_oracle(lcmod, prec, mode):
     eb, ebc = bnd_errors(got["bnd"], ref["bnd"], floor=0.0 if prec == 0 else FLOOR)
     _say("  cells E %.2e F %.2e f %.2e faces E %.2e F %.2e f %.2e bnd %.2e / %.2e" % (*e, eb, ebc))
     assert max(e) <= tol and eb <= tol and ebc <= tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_split_gathers_in_captured_steps(lcmod, prec):
+    """lc_step captures the split gathers in its graph: replays equal the
+    eager sweeps and gathers bit for bit, and the whole gathers too."""
+    lc, driver = lcmod
+    prob = _problem(6, 5, 17, 4, 0.004, steps=3, seed=13)
+    _say(f"split gathers in lc_step graphs prec={prec}")
+    out = {}
+    for name, graph, mode in (("graph", True, 1), ("eager", False, 1), ("whole", True, 0)):
+        s = driver.Solver(prob, prec=prec)
+        lc.lc_plan_set_moment_split(s.plan, mode)
+        s.reset()
+        s.step(prob.steps, graph=graph)
+        out[name] = s.moments()
+    for k in out["graph"]:
+        assert np.array_equal(out["graph"][k], out["eager"][k]), k
+        assert np.array_equal(out["graph"][k], out["whole"][k]), k
