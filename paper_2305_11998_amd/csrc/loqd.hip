@@ -892,7 +892,19 @@ __global__ void k_loqd_prep(Geo Q, const double* __restrict__ kappa, const doubl
 // per cell the energy-weighted and Planck-weighted opacities, per cell side
 // K_R from the normal face fluxes and eta, and the cell's spectrum-averaged
 // tensor; fixed-order sums over the groups.
-__device__ inline void grey_cell(const Geo& Q, int i, const double* __restrict__ kappa,
+// Sum over the eight lanes of a cell in a fixed butterfly: every lane ends
+// with the same total.
+__device__ inline double sum8(double v) {
+    v += __shfl_xor(v, 4);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 1);
+    return v;
+}
+
+// Cell i's grey coefficients by its eight lanes (j = 0..7, consecutive in a
+// wavefront): lane j takes groups j, j + 8, ..., the partial sums meet in
+// sum8, and lane 0 writes.
+__device__ inline void grey_cell(const Geo& Q, int i, int j, const double* __restrict__ kappa,
                                  const double* __restrict__ planck, const double* __restrict__ E_prev,
                                  const double* __restrict__ f_cell, const double* __restrict__ E_cell,
                                  const double* __restrict__ E_face, const double* __restrict__ F_face, double* sigma,
@@ -900,10 +912,7 @@ __device__ inline void grey_cell(const Geo& Q, int i, const double* __restrict__
                                  double* kBo) {
     const int G = Q.G;
     double E = 0.0, kE = 0.0, sB = 0.0, kB = 0.0, sk = 0.0, ep = 0.0, t[3] = {0.0, 0.0, 0.0};
-    // the group loops are unrolled so that several groups' loads are in
-    // flight at once; the sums still run in group order
-#pragma unroll 4
-    for (int g = 0; g < G; ++g) {
+    for (int g = j; g < G; g += 8) {
         const size_t gi = (size_t)g * Q.N + i;
         const double e = E_cell[gi], k = kappa[gi], b = planck[gi];
         E += e;
@@ -914,34 +923,47 @@ __device__ inline void grey_cell(const Geo& Q, int i, const double* __restrict__
         ep += E_prev[gi];
         for (int q = 0; q < 3; ++q) t[q] += f_cell[((size_t)i * 4 + q) * G + g] * e;
     }
+    E = sum8(E);
+    kE = sum8(kE);
+    sB = sum8(sB);
+    kB = sum8(kB);
+    sk = sum8(sk);
+    ep = sum8(ep);
+    for (int q = 0; q < 3; ++q) t[q] = sum8(t[q]);
     const double mean_k = sk / G;
     double avgB = sB != 0.0 ? kB / sB : NAN;
     const double avgE = E != 0.0 ? kE / E : (std::isnan(avgB) ? mean_k : avgB);
     if (std::isnan(avgB)) avgB = avgE;
-    sigma[i] = Q.c * (avgE + 1.0 / Q.c_dt);
-    src[i] = 4.0 * kPi * avgB * sB + Q.c * ep / Q.c_dt;
-    if (kEo) kEo[i] = avgE;
-    if (kBo) kBo[i] = avgB;
-    Ep[i] = ep;
-    fc[i] = E != 0.0 ? t[0] / E : 1.0 / 3.0;
-    fc[Q.N + i] = E != 0.0 ? t[1] / E : 0.0;
-    fc[2 * (size_t)Q.N + i] = E != 0.0 ? t[2] / E : 1.0 / 3.0;
+    if (j == 0) {
+        sigma[i] = Q.c * (avgE + 1.0 / Q.c_dt);
+        src[i] = 4.0 * kPi * avgB * sB + Q.c * ep / Q.c_dt;
+        if (kEo) kEo[i] = avgE;
+        if (kBo) kBo[i] = avgB;
+        Ep[i] = ep;
+        fc[i] = E != 0.0 ? t[0] / E : 1.0 / 3.0;
+        fc[Q.N + i] = E != 0.0 ? t[1] / E : 0.0;
+        fc[2 * (size_t)Q.N + i] = E != 0.0 ? t[2] / E : 1.0 / 3.0;
+    }
     for (int s = 0; s < 4; ++s) {
         const int f = Q.cface[(size_t)s * Q.N + i];
         double aF = 0.0, kaF = 0.0, Ef = 0.0;
-#pragma unroll 4
-        for (int g = 0; g < G; ++g) {
+        for (int g = j; g < G; g += 8) {
             const double F = F_face[(size_t)g * Q.nf + f];
             aF += fabs(F);
             kaF += kappa[(size_t)g * Q.N + i] * fabs(F);
             Ef += E_face[(size_t)g * Q.nf + f];
         }
+        aF = sum8(aF);
+        kaF = sum8(kaF);
+        Ef = sum8(Ef);
         const double K = aF != 0.0 ? kaF / aF : avgE;
         double num = 0.0;
-#pragma unroll 4
-        for (int g = 0; g < G; ++g) num += (kappa[(size_t)g * Q.N + i] - K) * F_face[(size_t)g * Q.nf + f];
-        ks[(size_t)s * Q.N + i] = K + 1.0 / Q.c_dt;
-        es[(size_t)s * Q.N + i] = Ef != 0.0 ? num / Ef : 0.0;
+        for (int g = j; g < G; g += 8) num += (kappa[(size_t)g * Q.N + i] - K) * F_face[(size_t)g * Q.nf + f];
+        num = sum8(num);
+        if (j == 0) {
+            ks[(size_t)s * Q.N + i] = K + 1.0 / Q.c_dt;
+            es[(size_t)s * Q.N + i] = Ef != 0.0 ? num / Ef : 0.0;
+        }
     }
 }
 
@@ -977,7 +999,7 @@ __device__ inline void grey_face(const Geo& Q, int f, const double* __restrict__
     }
 }
 
-// Both in one launch: thread t takes cell t and face t.
+// Both in one launch: threads 8i .. 8i + 7 take cell i, thread t face t.
 __global__ void k_grey_coef(Geo Q, const double* __restrict__ kappa, const double* __restrict__ planck,
                             const double* __restrict__ E_prev, const double* __restrict__ f_cell,
                             const double* __restrict__ E_cell, const double* __restrict__ E_face,
@@ -986,8 +1008,9 @@ __global__ void k_grey_coef(Geo Q, const double* __restrict__ kappa, const doubl
                             double* src, double* ks, double* es, double* fc, double* Ep, double* kEo, double* kBo,
                             double* ff, double* bc3, double* fp) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < Q.N) grey_cell(Q, t, kappa, planck, E_prev, f_cell, E_cell, E_face, F_face, sigma, src, ks, es, fc, Ep, kEo,
-                           kBo);
+    if (t < 8 * Q.N)                  // whole groups of eight lanes
+        grey_cell(Q, t >> 3, t & 7, kappa, planck, E_prev, f_cell, E_cell, E_face, F_face, sigma, src, ks, es, fc, Ep,
+                  kEo, kBo);
     if (t < Q.nf) grey_face(Q, t, F_prev, f_face, bnd, E_face, ff, bc3, fp);
 }
 
@@ -1457,7 +1480,7 @@ lc_status lc_loqd_grey_coefficients(lc_loqd_t h, double c, double c_dt, const do
     hipStream_t st = static_cast<hipStream_t>(stream);
     const Geo Q = geo(q, c, c_dt, q->G);
     const dim3 blk(kLoqdBlock);
-    hipLaunchKernelGGL(k_grey_coef, dim3((std::max(q->N, q->nf) + kLoqdBlock - 1) / kLoqdBlock), blk, 0, st, Q, kappa,
+    hipLaunchKernelGGL(k_grey_coef, dim3((std::max(8 * q->N, q->nf) + kLoqdBlock - 1) / kLoqdBlock), blk, 0, st, Q, kappa,
                        planck, E_prev, f_cell, E_cell, E_face, F_face, F_prev, f_face, bnd, sigma, source, k_side,
                        eta_side, f_cell_grey, E_prev_grey, kappa_E, kappa_B, f_face_grey, bc_grey, F_prev_grey);
     LC_HIP(hipGetLastError());
