@@ -399,7 +399,6 @@ __global__ void k_bi_x(Geo Q, Vecs V, const double* sc, const int* flag, double*
     block_sum2(a, b, part + ((size_t)g * nblk + blockIdx.x) * 2);
 }
 
-// Cell values from the face solution.
 // One workgroup per group: Jacobi-preconditioned BiCGSTAB on the face system
 // of group blockIdx.x, the same iteration as the many-block kernels above
 // (restart from the current x on breakdown, true-residual check when the

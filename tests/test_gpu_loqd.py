@@ -506,6 +506,22 @@ def test_loqd_warm_start(lcmod):
 
 
 
+@pytest.mark.parametrize("nx,ny", [(50, 45), (70, 60)])
+def test_loqd_mid_size_one_workgroup_form(lcmod, nx, ny):
+    """Face systems of 4,595 and 8,530 faces: above the register form's
+    4096, below the one-workgroup limit -- the form that keeps its vectors
+    in global memory (16 and 32 rows a thread) -- against the oracle."""
+    lc, _ = lcmod
+    nf = OL.n_faces(nx, ny)
+    assert 4096 < nf <= 16384
+    args = _random_groups(nx, ny, nx * 0.1, ny * 0.1, 2, seed=nx + ny)
+    _say(f"case loqd random {nx}x{ny} G=2 ({nf} faces, one workgroup, vectors in global memory)")
+    ref = OL.solve(*args)
+    got, it, res = _gpu_solve(lc, *args)
+    _say(f"  {it} iterations, residuals {np.max(res):.1e}")
+    _compare(got, ref, "mid-size")
+
+
 def test_loqd_large_system_takes_the_block_path(lcmod):
     """A face system above the one-workgroup size (95 x 90 cells, 17,285
     faces) through the automatic choice, against the oracle."""
