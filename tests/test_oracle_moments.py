@@ -70,6 +70,63 @@ def test_single_direction_indicator_boundary():
                     assert np.allclose(bnd[b, 5:], ref, rtol=1e-12, atol=1e-15)
 
 
+def _linear_field_case(unweighted=False):
+    nx, ny, lx, ly = 4, 3, 1.0, 0.75
+    phi, mu, om = W.product_quadrature(8, 2)
+    g = rays.build(nx, ny, lx, ly, phi, 0.05, rays.TUBES)
+    if unweighted:                                       # planted mistake: plain mean of the exits
+        for pr in g.pairs:
+            pr.w = np.ones_like(pr.w)
+    return nx, ny, lx, ly, phi, mu, om, g
+
+
+def _linear_field_check(nx, ny, lx, ly, phi, mu, om, g):
+    """Largest relative deviation of Phi+, J+ and C from the closed form."""
+    n_pol, M, half = len(mu), len(om), len(phi) // 2
+    nb = 2 * (nx + ny)
+    normals = W.boundary_faces(nx, ny)
+    centres = rays.face_centres(nx, ny, lx, ly)
+    V0 = 10.0
+    slope = lambda m: 0.5 + 0.25 * m                     # a different field for every direction
+    exits = []
+    for a, pr in enumerate(g.pairs):
+        e = np.zeros((2, pr.K, n_pol, 1))
+        for d in (0, 1):
+            for p in range(n_pol):
+                e[d, :, p, 0] = V0 + slope((a + d * half) * n_pol + p) * pr.v
+        exits.append(e)
+    bnd = moments.boundary_factors(g, phi, mu, om, exits, np.zeros((nb, M, 1)))[0]
+    worst = 0.0
+    for b in range(nb):
+        Pp = Jp = 0.0
+        for a, pr in enumerate(g.pairs):
+            vb = -centres[b, 0] * pr.s + centres[b, 1] * pr.c
+            for d in (0, 1):
+                for p in range(n_pol):
+                    m = (a + d * half) * n_pol + p
+                    Om = _omega(phi, mu, a + d * half, p)
+                    odn = Om[0] * normals[b, 0] + Om[1] * normals[b, 1]
+                    if odn > 0:
+                        I = V0 + slope(m) * vb
+                        Pp += om[m] * I
+                        Jp += om[m] * odn * I
+        assert bnd[b, 2] == 0.0 and bnd[b, 3] == 0.0
+        worst = max(worst, abs(bnd[b, 0] / Pp - 1), abs(bnd[b, 1] / Jp - 1), abs(bnd[b, 4] / (Jp / Pp) - 1))
+    return worst
+
+
+def test_boundary_exit_means_of_a_linear_field_on_the_papers_grid():
+    """On the vertex-avoiding grid the characteristics leaving through a
+    boundary face tile the face's projection exactly, so an exit intensity
+    linear in the characteristic coordinate v = -x sin(phi) + y cos(phi) has
+    the width-weighted mean of its value at the face centre: Phi+, J+ and
+    C = J+/Phi+ then follow in closed form for a mix of directions whose
+    fields differ (reading R4/R5: width-weighted mean within a direction,
+    then the sum over directions).  A plain mean of the exits fails it."""
+    assert _linear_field_check(*_linear_field_case()) < 1e-12
+    assert _linear_field_check(*_linear_field_case(unweighted=True)) > 1e-6
+
+
 def _c_iso(n_az, mu_w):
     """Half-range factor for an isotropic intensity, closed form for the
     product set: (sum_p w_p sin zeta_p / sum_p w_p) x (mean of |cos| over the
