@@ -27,8 +27,12 @@ through b (Omega_m . n_b > 0), or the given incoming I_in[b, m] otherwise:
 If no characteristic leaves through b in direction m, the one whose exit
 point is nearest to the face centre is used (ties: lower k).  Where Phi (or
 Phi+) is zero, f = 1/3 on the diagonal and C = its isotropic value.
-The boundary factor C is named but not written out in the paper: parity
-unpinned beyond its isotropic value.
+The boundary factor C is named but not written out in the paper, so the
+definition above is a reading.  Its evaluation is pinned (the isotropic
+closed form, single-direction indicators, and a field linear in the
+characteristic coordinate on the vertex-avoiding grid, whose width-weighted
+exit means are the face-centre values); against the paper itself, which
+prints no value of C, parity is unpinned.
 """
 from __future__ import annotations
 
