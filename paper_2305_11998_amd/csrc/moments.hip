@@ -865,35 +865,61 @@ lc_status launch_face_moments(Plan* pl, const void* point, const void* state, do
     return LC_OK;
 }
 
+// Argument records of a plan's cell gather and boundary factors.
+static MomArgs cell_moment_args(Plan* pl, const void* state, double c, double* E, double* F, double* f) {
+    Rays* r = pl->rays;
+    const bool f32 = pl->prec == LC_F32;
+    MomArgs A{};
+    A.csr_off = r->d_csr_off;
+    A.ent_off = pl->d_ent_off;
+    A.bun_rec = pl->d_bun_rec;
+    A.half_rec = (unsigned)(pl->half_elems / r->n_pol);
+    A.multi = pl->G > kWave ? 1 : 0;
+    A.csr_w = f32 ? static_cast<const void*>(r->d_csr_w32) : static_cast<const void*>(r->d_csr_w);
+    A.dirw = r->d_dirw;
+    A.state = state_values(pl, state);
+    A.e = static_cast<const int*>(state);
+    A.nx = r->nx;
+    A.ny = r->ny;
+    A.P = r->n_pol;
+    A.tw = pl->tile_w;
+    A.th = pl->tile_h;
+    A.tiles_x = (r->nx + pl->tile_w - 1) / pl->tile_w;
+    A.n_tiles = moment_tiles(pl);
+    A.wpt = moment_tile_waves(pl);
+    A.G = pl->G;
+    A.n_pairs = r->n_pairs;
+    A.inv_c = 1.0 / c;
+    A.E = E;
+    A.F = F;
+    A.f = f;
+    return A;
+}
+
+static BndArgs boundary_args(Plan* pl, const double* I_exit, const double* I_in, double* bnd) {
+    Rays* r = pl->rays;
+    BndArgs B{};
+    B.bmap = r->d_bmap;
+    B.width = r->d_width;
+    B.dirw = r->d_dirw;
+    B.I_exit = I_exit;
+    B.I_in = I_in;
+    B.nx = r->nx;
+    B.ny = r->ny;
+    B.nb = r->nb;
+    B.G = pl->G;
+    B.n_pairs = r->n_pairs;
+    B.n_az = r->n_az;
+    B.P = r->n_pol;
+    B.bnd = bnd;
+    return B;
+}
+
 lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, const double* I_in,
                          double c, double* E, double* F, double* f, double* bnd, hipStream_t st) {
     Rays* r = pl->rays;
-    const bool f32 = pl->prec == LC_F32;
     if (E || F || f) {
-        MomArgs A{};
-        A.csr_off = r->d_csr_off;
-        A.ent_off = pl->d_ent_off;
-        A.bun_rec = pl->d_bun_rec;
-        A.half_rec = (unsigned)(pl->half_elems / r->n_pol);
-        A.multi = pl->G > kWave ? 1 : 0;
-        A.csr_w = f32 ? static_cast<const void*>(r->d_csr_w32) : static_cast<const void*>(r->d_csr_w);
-        A.dirw = r->d_dirw;
-        A.state = state_values(pl, state);
-        A.e = static_cast<const int*>(state);
-        A.nx = r->nx;
-        A.ny = r->ny;
-        A.P = r->n_pol;
-        A.tw = pl->tile_w;
-        A.th = pl->tile_h;
-        A.tiles_x = (r->nx + pl->tile_w - 1) / pl->tile_w;
-        A.n_tiles = moment_tiles(pl);
-        A.wpt = moment_tile_waves(pl);
-        A.G = pl->G;
-        A.n_pairs = r->n_pairs;
-        A.inv_c = 1.0 / c;
-        A.E = E;
-        A.F = F;
-        A.f = f;
+        const MomArgs A = cell_moment_args(pl, state, c, E, F, f);
         lc_status rc = prof_begin(pl, pl->ev_mom, st);
         if (rc) return rc;
         rc = launch_gather(pl, A, st);
@@ -902,20 +928,7 @@ lc_status launch_moments(Plan* pl, const void* state, const double* I_exit, cons
         if (rc) return rc;
     }
     if (bnd) {
-        BndArgs B{};
-        B.bmap = r->d_bmap;
-        B.width = r->d_width;
-        B.dirw = r->d_dirw;
-        B.I_exit = I_exit;
-        B.I_in = I_in;
-        B.nx = r->nx;
-        B.ny = r->ny;
-        B.nb = r->nb;
-        B.G = pl->G;
-        B.n_pairs = r->n_pairs;
-        B.n_az = r->n_az;
-        B.P = r->n_pol;
-        B.bnd = bnd;
+        const BndArgs B = boundary_args(pl, I_exit, I_in, bnd);
         const int lanes = r->nb * pl->G;
         if (pl->mom_split & 2) {
             const int64_t parts = (int64_t)lanes * 2 * r->n_pairs;
@@ -965,47 +978,9 @@ size_t bnd_args_bytes() { return sizeof(BndArgs); }
 void make_moment_args(Plan* pl, const void* state, const double* I_exit, const double* I_in, double c,
                       double* E, double* F, double* f, double* bnd, int64_t bnd_blk_off, void* mom_out,
                       void* bnd_out) {
-    Rays* r = pl->rays;
-    const bool f32 = pl->prec == LC_F32;
-    MomArgs A{};
-    A.csr_off = r->d_csr_off;
-    A.ent_off = pl->d_ent_off;
-    A.bun_rec = pl->d_bun_rec;
-    A.half_rec = (unsigned)(pl->half_elems / r->n_pol);
-    A.multi = pl->G > kWave ? 1 : 0;
-    A.csr_w = f32 ? static_cast<const void*>(r->d_csr_w32) : static_cast<const void*>(r->d_csr_w);
-    A.dirw = r->d_dirw;
-    A.state = state_values(pl, state);
-    A.e = static_cast<const int*>(state);
-    A.nx = r->nx;
-    A.ny = r->ny;
-    A.P = r->n_pol;
-    A.tw = pl->tile_w;
-    A.th = pl->tile_h;
-    A.tiles_x = (r->nx + pl->tile_w - 1) / pl->tile_w;
-    A.n_tiles = moment_tiles(pl);
-    A.wpt = moment_tile_waves(pl);
-    A.G = pl->G;
-    A.n_pairs = r->n_pairs;
-    A.inv_c = 1.0 / c;
-    A.E = E;
-    A.F = F;
-    A.f = f;
+    const MomArgs A = cell_moment_args(pl, state, c, E, F, f);
     std::memcpy(mom_out, &A, sizeof(A));
-    BndArgs B{};
-    B.bmap = r->d_bmap;
-    B.width = r->d_width;
-    B.dirw = r->d_dirw;
-    B.I_exit = I_exit;
-    B.I_in = I_in;
-    B.nx = r->nx;
-    B.ny = r->ny;
-    B.nb = r->nb;
-    B.G = pl->G;
-    B.n_pairs = r->n_pairs;
-    B.n_az = r->n_az;
-    B.P = r->n_pol;
-    B.bnd = bnd;
+    BndArgs B = boundary_args(pl, I_exit, I_in, bnd);
     B.blk_off = bnd_blk_off;
     std::memcpy(bnd_out, &B, sizeof(B));
 }
