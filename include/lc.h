@@ -682,7 +682,8 @@ lc_status lc_plan_set_split(lc_plan_t plan, int32_t chunk_steps);
  * them whole, -1 (the default at lc_plan_create) chooses per gather: the
  * moments split when the plan's tiles hold fewer than 2048 wavefronts and
  * the lists average at least 8 entries, the boundary factors when
- * nb * G < 131072 and at least 8 characteristics per (face, pair) exit.  A
+ * nb * G < 16384, or nb * G < 131072 and at least 8 characteristics per
+ * (face, pair) exit.  A
  * split plan holds a device buffer of n_pairs * 7 * (its largest gather
  * grid's lanes) values of its precision, or 2 n_pairs (n_pol + 1) nb G
  * doubles if larger.  Batched steps always run whole gathers.

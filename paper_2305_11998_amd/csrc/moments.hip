@@ -709,6 +709,7 @@ void face_tiles(int G, int fnx, int fny, MomArgs& A) {
 
 constexpr int64_t kSplitMaxWaves = 2048;   // tile wavefronts (two per SIMD) below which a gather may split
 constexpr double kSplitMinList = 8.0;      // and its lists must hold this many entries on average
+constexpr int64_t kSplitFewLanes = 16384;  // boundary lanes (under one wavefront per CU): split whatever the lists
 
 }  // namespace
 
@@ -721,7 +722,7 @@ lc_status plan_set_moment_split(Plan* pl, int mode) {
         if (r->n_pairs > 1 && waves < kSplitMaxWaves && per_list >= kSplitMinList) want |= 1;
         const int64_t lanes = (int64_t)r->nb * pl->G;
         const double per_face = (double)r->n_rays / std::max(1.0, (double)r->nb * r->n_pairs);
-        if (lanes < kSplitMaxWaves * kWave && per_face >= kSplitMinList) want |= 2;
+        if (lanes < kSplitFewLanes || (lanes < kSplitMaxWaves * kWave && per_face >= kSplitMinList)) want |= 2;
     } else if (mode > 0) {
         want = 3;
     }
