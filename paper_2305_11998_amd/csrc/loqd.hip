@@ -88,6 +88,7 @@ struct Loqd {
     int* d_flag = nullptr;            // [G] 1 = iterating
     bool warm = false;                // BiCGSTAB starts from the E_face output's contents
     int solver = 0;                   // 0 by size, 1 one workgroup per group, 2 many blocks per group
+    size_t lds_max = 0;               // LDS a workgroup may hold on this device (bytes)
     double* d_report = nullptr;       // [2][G] final relative residuals, then iterations (one-workgroup solver)
     // pinned host copies of the convergence report and of the Newton change
     // partials, so that copies queued together need one wait
@@ -407,14 +408,50 @@ __global__ void k_bi_x(Geo Q, Vecs V, const double* sc, const int* flag, double*
 // is uniform over the workgroup.  x starts from zero, or from its
 // contents with warm != 0.  report[g]: the final relative residual (as
 // the many-block path reports it); report[G + g]: the iterations.
-// Within each wavefront a butterfly over the 64 lanes (lane 0's sum, whose
-// order is fixed, is the one kept), then the wavefronts' partials added in
-// wavefront order by every thread: two barriers a reduction.
-__device__ inline void wg_sum2(double& a, double& b, double* sa, double* sb) {
-    for (int o = 32; o > 0; o >>= 1) {
-        a += __shfl_xor(a, o);
-        b += __shfl_xor(b, o);
-    }
+// A workgroup sum of two values, the same bits in every thread.  Within a
+// wavefront: pairs, quads, eights and sixteens by DPP lane moves (each step
+// adds two equal-order operands, so every lane of a 16-lane row ends with
+// the same bits), then the four rows added in row order from their first
+// lanes; then the wavefronts' partials added in wavefront order by every
+// thread.  Two LDS slots alternate between calls: a call writes its slot
+// only after the previous call's barrier, which no thread passes before
+// every thread has read that slot in the call before, so one barrier a
+// call suffices -- every thread makes the same sequence of calls.
+template <int Ctrl>
+__device__ __forceinline__ double dpp_move(double v) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, Ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), Ctrl, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, lane);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+    v += dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
+    v += dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+    v += dpp_move<0x141>(v);   // row_half_mirror: the other quad of the eight
+    v += dpp_move<0x140>(v);   // row_mirror: the other eight of the row
+    return ((read_lane(v, 0) + read_lane(v, 16)) + read_lane(v, 32)) + read_lane(v, 48);
+}
+
+struct WgRed {
+    double* slot;              // [2][2][kWG / 64] in LDS
+    int par;
+};
+
+__device__ inline void wg_sum2(double& a, double& b, WgRed& R) {
+    constexpr int W = kWG / 64;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    double* const sa = R.slot + R.par * 2 * W;
+    double* const sb = sa + W;
+    R.par ^= 1;
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         sa[w] = a;
@@ -422,13 +459,12 @@ __device__ inline void wg_sum2(double& a, double& b, double* sa, double* sb) {
     }
     __syncthreads();
     double ta = 0.0, tb = 0.0;
-    for (int k = 0; k < kWG / 64; ++k) {
+    for (int k = 0; k < W; ++k) {
         ta += sa[k];
         tb += sb[k];
     }
     a = ta;
     b = tb;
-    __syncthreads();
 }
 
 // R: a bound on the rows each thread owns (nf <= R kWG); this form serves
@@ -439,7 +475,8 @@ template <int R>
 __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restrict__ val, const double* __restrict__ bv,
                                                      const double* __restrict__ dinv, Vecs V, int warm, double rtol,
                                                      int max_iter, double* report) {
-    __shared__ double sa[kWG / 64], sb[kWG / 64];
+    __shared__ double red[4 * (kWG / 64)];
+    WgRed rd{red, 0};
     const int g = blockIdx.x, nf = Q.nf, tid = threadIdx.x;
     const size_t o = (size_t)g * nf;
     double *x = V.x + o, *r = V.r + o, *rh = V.rh + o, *p = V.p + o, *v = V.v + o;
@@ -482,7 +519,7 @@ __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restr
             rr += e * e;
             bb += b[f] * b[f];
         });
-        wg_sum2(rr, bb, sa, sb);
+        wg_sum2(rr, bb, rd);
     };
     double rr, bb;
     restart(rr, bb);
@@ -518,7 +555,7 @@ __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restr
             v[f] = vv;
             a += rh[f] * vv;
         });
-        wg_sum2(a, c, sa, sb);
+        wg_sum2(a, c, rd);
         if (a == 0.0 || !std::isfinite(a)) {          // breakdown: restart from x
             restart(rr, bb);
             rho = rr;
@@ -544,7 +581,7 @@ __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restr
             a += tv * s[f];
             c += tv * tv;
         });
-        wg_sum2(a, c, sa, sb);
+        wg_sum2(a, c, rd);
         omega = c > 0.0 ? a / c : 0.0;
         a = 0.0;
         c = 0.0;
@@ -555,7 +592,7 @@ __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restr
             a += rh[f] * rv;
             c += rv * rv;
         });
-        wg_sum2(a, c, sa, sb);
+        wg_sum2(a, c, rd);
         rnorm = sqrt(c);
         if (rnorm <= rtol * bnorm) {
             done = true;
@@ -581,7 +618,7 @@ __global__ __launch_bounds__(kWG) void k_bicg_group(Geo Q, const double* __restr
             const double e = b[f] - prod(x, f);
             e2 += e * e;
         });
-        wg_sum2(e2, unused, sa, sb);
+        wg_sum2(e2, unused, rd);
         rnorm = sqrt(e2);
     }
     if (tid == 0) {
@@ -607,31 +644,58 @@ __global__ __launch_bounds__(kWG) void k_bicg_reg(Geo Q, const double* __restric
     // then run row by row (no unrolling) into LDS, from where each thread
     // takes its own rows, and the matrix is read again in every product.
     constexpr bool kRowLoop = R > 4;
-    extern __shared__ double gsv[];                   // [nf] the gathered vector; [nf] products (kRowLoop)
-    __shared__ double sa[kWG / 64], sb[kWG / 64];
+    extern __shared__ double gsv[];                   // [nf] the gathered vector; [nf] products, r^, 1/diag (kRowLoop)
+    __shared__ double red[4 * (kWG / 64)];
+    WgRed rd{red, 0};
     const int g = blockIdx.x, nf = Q.nf, tid = threadIdx.x;
     const size_t o = (size_t)g * nf;
     const gptr<const double> vg = as_global(val + (size_t)g * kSlots * nf);
     const gptr<const int> cg = as_global(Q.col);
     const gptr<const double> b = as_global(bv + o);
-    double x[R], r[R], rh[R], p[R], v[R], s[R], t[R], di[R];
+    double x[R], r[R], p[R], v[R], s[R], t[R];
+    // r^ and the inverse diagonal: registers, or (kRowLoop) LDS slots
+    // [R kWG] each after the two [nf] vectors, one per (thread, row) and
+    // touched by that thread only
+    constexpr int RR = kRowLoop ? 1 : R;
+    double rh_r[RR], di_r[RR];
+    double* const rh_l = gsv + 2 * (size_t)nf;
+    double* const di_l = rh_l + R * kWG;
+    auto RH = [&](int j) -> double& {
+        if constexpr (kRowLoop) return rh_l[tid + j * kWG];
+        else return rh_r[j];
+    };
+    auto DI = [&](int j) -> double& {
+        if constexpr (kRowLoop) return di_l[tid + j * kWG];
+        else return di_r[j];
+    };
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int f = tid + j * kWG;
         const bool ok = f < nf;
-        di[j] = ok ? dinv[o + f] : 0.0;
+        DI(j) = ok ? dinv[o + f] : 0.0;
         x[j] = ok && warm ? xv[o + f] : 0.0;
-        r[j] = rh[j] = p[j] = v[j] = s[j] = t[j] = 0.0;
+        r[j] = RH(j) = p[j] = v[j] = s[j] = t[j] = 0.0;
     }
     // row f of A times the staged vector
     auto prod = [&](int f) -> double {
-        double acc = 0.0;
+        int ci[kSlots];
+        double av[kSlots];
 #pragma unroll
         for (int k = 0; k < kSlots; ++k) {
-            const int cidx = cg[(size_t)k * nf + f];
-            const double a = vg[(size_t)k * nf + f];
-            acc += a * gsv[cidx];
+            ci[k] = cg[(size_t)k * nf + f];
+            av[k] = vg[(size_t)k * nf + f];
         }
+        // all of the row's loads, then all of its gathers, in flight before
+        // the first use (left to itself the scheduler waits on each entry
+        // in turn)
+        if constexpr (kRowLoop) __builtin_amdgcn_sched_barrier(0);
+        double gv[kSlots];
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) gv[k] = gsv[ci[k]];
+        if constexpr (kRowLoop) __builtin_amdgcn_sched_barrier(0);
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < kSlots; ++k) acc += av[k] * gv[k];
         return acc;
     };
     // y_j = (A u)_f for this thread's rows f; out-of-range rows untouched
@@ -677,14 +741,14 @@ __global__ __launch_bounds__(kWG) void k_bicg_reg(Geo Q, const double* __restric
                 const double bf = b[f];
                 const double e = bf - v[j];
                 r[j] = e;
-                rh[j] = e;
+                RH(j) = e;
                 p[j] = 0.0;
                 v[j] = 0.0;
                 rr += e * e;
                 bb += bf * bf;
             }
         }
-        wg_sum2(rr, bb, sa, sb);
+        wg_sum2(rr, bb, rd);
     };
     double rr, bb;
     restart(rr, bb);
@@ -713,7 +777,7 @@ __global__ __launch_bounds__(kWG) void k_bicg_reg(Geo Q, const double* __restric
         for (int j = 0; j < R; ++j) {
             const int f = tid + j * kWG;
             p[j] = r[j] + beta * (p[j] - omega * v[j]);
-            if (f < nf) gsv[f] = di[j] * p[j];
+            if (f < nf) gsv[f] = DI(j) * p[j];
         }
         __syncthreads();
         double a = 0.0, c = 0.0;
@@ -721,9 +785,9 @@ __global__ __launch_bounds__(kWG) void k_bicg_reg(Geo Q, const double* __restric
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int f = tid + j * kWG;
-            if (f < nf) a += rh[j] * v[j];
+            if (f < nf) a += RH(j) * v[j];
         }
-        wg_sum2(a, c, sa, sb);
+        wg_sum2(a, c, rd);
         if (a == 0.0 || !std::isfinite(a)) {          // breakdown: restart from x
             restart(rr, bb);
             rho = rr;
@@ -738,7 +802,7 @@ __global__ __launch_bounds__(kWG) void k_bicg_reg(Geo Q, const double* __restric
         for (int j = 0; j < R; ++j) {
             const int f = tid + j * kWG;
             s[j] = r[j] - alpha * v[j];
-            if (f < nf) gsv[f] = di[j] * s[j];
+            if (f < nf) gsv[f] = DI(j) * s[j];
         }
         __syncthreads();
         a = 0.0;
@@ -752,7 +816,7 @@ __global__ __launch_bounds__(kWG) void k_bicg_reg(Geo Q, const double* __restric
                 c += t[j] * t[j];
             }
         }
-        wg_sum2(a, c, sa, sb);
+        wg_sum2(a, c, rd);
         omega = c > 0.0 ? a / c : 0.0;
         a = 0.0;
         c = 0.0;
@@ -760,13 +824,14 @@ __global__ __launch_bounds__(kWG) void k_bicg_reg(Geo Q, const double* __restric
         for (int j = 0; j < R; ++j) {
             const int f = tid + j * kWG;
             if (f < nf) {
-                x[j] += alpha * (di[j] * p[j]) + omega * (di[j] * s[j]);
+                const double d = DI(j);
+                x[j] += alpha * (d * p[j]) + omega * (d * s[j]);
                 r[j] = s[j] - omega * t[j];
-                a += rh[j] * r[j];
+                a += RH(j) * r[j];
                 c += r[j] * r[j];
             }
         }
-        wg_sum2(a, c, sa, sb);
+        wg_sum2(a, c, rd);
         rnorm = sqrt(c);
         if (rnorm <= rtol * bnorm) {
             done = true;
@@ -794,7 +859,7 @@ __global__ __launch_bounds__(kWG) void k_bicg_reg(Geo Q, const double* __restric
                 e2 += e * e;
             }
         }
-        wg_sum2(e2, unused, sa, sb);
+        wg_sum2(e2, unused, rd);
         rnorm = sqrt(e2);
     }
 #pragma unroll
@@ -1167,12 +1232,17 @@ lc_status solve_general(Loqd* q, const Geo& Q, const Gen& Cg, double* E_cell, do
            q->d_vec + 6 * GF, q->d_vec + 7 * GF, q->d_sh};
     if (q->solver != 2 && nf <= kSmallFaces) {
         const int rows_per_thread = (nf + kWG - 1) / kWG;
+        // R = 8: the products and the [8 kWG] slots of r^ and 1/diag in LDS
+        // too; where the device cannot give a workgroup that much, the
+        // global-vector form (same arithmetic) takes these sizes
+        const size_t lds = rows_per_thread > 4 ? (2 * (size_t)nf + 2 * 8 * kWG) * sizeof(double)
+                                               : (size_t)nf * sizeof(double);
+        const bool reg_form = rows_per_thread <= 4 || (rows_per_thread <= 8 && lds <= q->lds_max);
         // the register form starts from and writes E_face itself
-        double* xf = rows_per_thread <= 8 ? E_face : V.x;
+        double* xf = reg_form ? E_face : V.x;
         if (q->warm && xf != E_face)
             LC_HIP(hipMemcpyAsync(V.x, E_face, GF * sizeof(double), hipMemcpyDeviceToDevice, st));
         {
-            const size_t lds = (size_t)nf * sizeof(double) * (rows_per_thread > 4 ? 2 : 1);
             const int wv = q->warm ? 1 : 0;
             auto reg = [&](auto kern) {
                 hipLaunchKernelGGL(kern, dim3(G), dim3(kWG), lds, st, Q, q->d_val, q->d_b, q->d_dinv, xf, wv, rtol,
@@ -1185,7 +1255,7 @@ lc_status solve_general(Loqd* q, const Geo& Q, const Gen& Cg, double* E_cell, do
             if (rows_per_thread <= 1) reg(k_bicg_reg<1>);
             else if (rows_per_thread <= 2) reg(k_bicg_reg<2>);
             else if (rows_per_thread <= 4) reg(k_bicg_reg<4>);
-            else if (rows_per_thread <= 8) reg(k_bicg_reg<8>);
+            else if (reg_form) reg(k_bicg_reg<8>);
             else if (rows_per_thread <= 16) glob(k_bicg_group<16>);
             else glob(k_bicg_group<32>);
         }
@@ -1365,6 +1435,15 @@ lc_status lc_loqd_create(int32_t nx, int32_t ny, double lx, double ly, int32_t G
     if (!rc) rc = dalloc(q->owned, &q->d_report, 2 * (size_t)G);
     if (!rc) rc = halloc(q->owned_host, &q->h_report, 2 * (size_t)G);
     if (!rc) rc = halloc(q->owned_host, &q->h_part, (size_t)G * q->nblk);
+    if (!rc) {
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+            set_error("hipDeviceGetAttribute(MaxSharedMemoryPerBlock) failed");
+            rc = LC_ERR_HIP;
+        }
+        q->lds_max = (size_t)lds;
+    }
     if (rc) {
         free_loqd(q);
         return rc;
