@@ -400,14 +400,6 @@ __global__ void k_bi_x(Geo Q, Vecs V, const double* sc, const int* flag, double*
     block_sum2(a, b, part + ((size_t)g * nblk + blockIdx.x) * 2);
 }
 
-// One workgroup per group: Jacobi-preconditioned BiCGSTAB on the face system
-// of group blockIdx.x, the same iteration as the many-block kernels above
-// (restart from the current x on breakdown, true-residual check when the
-// recursive residual reaches rtol, at most 3 of them).  Every scalar comes
-// from a fixed-order reduction that all threads read, so the control flow
-// is uniform over the workgroup.  x starts from zero, or from its
-// contents with warm != 0.  report[g]: the final relative residual (as
-// the many-block path reports it); report[G + g]: the iterations.
 // A workgroup sum of two values, the same bits in every thread.  Within a
 // wavefront: pairs, quads, eights and sixteens by DPP lane moves (each step
 // adds two equal-order operands, so every lane of a 16-lane row ends with
@@ -467,6 +459,15 @@ __device__ inline void wg_sum2(double& a, double& b, WgRed& R) {
     b = tb;
 }
 
+// One workgroup per group: Jacobi-preconditioned BiCGSTAB on the face system
+// of group blockIdx.x, the same iteration as the many-block kernels above
+// (restart from the current x on breakdown, true-residual check when the
+// recursive residual reaches rtol, at most 3 of them).  Every scalar comes
+// from a fixed-order reduction that all threads read, so the control flow
+// is uniform over the workgroup.  x starts from zero, or from its
+// contents with warm != 0.  report[g]: the final relative residual (as
+// the many-block path reports it); report[G + g]: the iterations.
+//
 // R: a bound on the rows each thread owns (nf <= R kWG); this form serves
 // R = 16 and 32 (systems of 4097 to 16384 faces), with its vectors in
 // global memory (L2) and gathers from there; smaller systems take the
