@@ -522,6 +522,22 @@ def test_loqd_mid_size_one_workgroup_form(lcmod, nx, ny):
     _compare(got, ref, "mid-size")
 
 
+def test_loqd_register_form_at_its_largest(lcmod):
+    """45 x 44 cells, 4,049 faces: eight rows a thread, the register form's
+    largest systems, whose products, r^ and inverse diagonal take about
+    130 KB of LDS -- against the oracle."""
+    lc, _ = lcmod
+    nx, ny = 45, 44
+    nf = OL.n_faces(nx, ny)
+    assert 3584 < nf <= 4096
+    args = _random_groups(nx, ny, nx * 0.1, ny * 0.1, 2, seed=89)
+    _say(f"case loqd random {nx}x{ny} G=2 ({nf} faces, one workgroup, 8 rows a thread)")
+    ref = OL.solve(*args)
+    got, it, res = _gpu_solve(lc, *args)
+    _say(f"  {it} iterations, residuals {np.max(res):.1e}")
+    _compare(got, ref, "largest register form")
+
+
 def test_loqd_large_system_takes_the_block_path(lcmod):
     """A face system above the one-workgroup size (95 x 90 cells, 17,285
     faces) through the automatic choice, against the oracle."""
