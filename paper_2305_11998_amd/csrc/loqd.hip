@@ -639,11 +639,11 @@ __global__ __launch_bounds__(kWG) void k_bicg_reg(Geo Q, const double* __restric
                                                    const double* __restrict__ bv, const double* __restrict__ dinv,
                                                    double* __restrict__ xv, int warm, double rtol, int max_iter,
                                                    double* report) {
-    // With R <= 4 the compiler keeps the matrix rows of a thread in
-    // registers across iterations too.  With R = 8 neither they nor all the
-    // rows' product loads in flight fit beside the vectors: the products
-    // then run row by row (no unrolling) into LDS, from where each thread
-    // takes its own rows, and the matrix is read again in every product.
+    // With R <= 4 a product is unrolled over the thread's rows, all of
+    // their matrix loads in flight together.  With R = 8 those loads do not
+    // fit beside the vectors: the products then run row by row (no
+    // unrolling) into LDS, from where each thread takes its own rows.  In
+    // both, the matrix is read again (from L2) in every product.
     constexpr bool kRowLoop = R > 4;
     extern __shared__ double gsv[];                   // [nf] the gathered vector; [nf] products, r^, 1/diag (kRowLoop)
     __shared__ double red[4 * (kWG / 64)];
