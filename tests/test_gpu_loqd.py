@@ -552,24 +552,27 @@ def test_loqd_large_system_takes_the_block_path(lcmod):
 
 
 
-def test_loqd_at_the_study_size(lcmod):
+@pytest.mark.parametrize("nx", [40, 30])
+def test_loqd_at_the_study_size(lcmod, nx):
     """The multigroup solve at the size of the paper's finest material grid
-    (40 x 40 cells, 17 groups) with physically shaped data: the
-    Fleck-Cummings opacity and Planck functions of a temperature front,
-    closures of the random-tensor kind, against the oracle's direct solve."""
+    (40 x 40 cells, 17 groups; and 30 x 30, whose 1,860 faces take the
+    4-row register form) with physically shaped data: the Fleck-Cummings
+    opacity and Planck functions of a temperature front, closures of the
+    random-tensor kind, against the oracle's direct solve."""
     lc, _ = lcmod
     from oracle import material as OMAT
-    nx = ny = 40
+    ny = nx
+    h = 6.0 / nx
     rng = np.random.default_rng(404)
-    x = (np.arange(nx) + 0.5) * 0.15
+    x = (np.arange(nx) + 0.5) * h
     T = np.tile(np.where(x < 1.5, 0.8, 0.002) + 0.05 * rng.random(nx), ny)
-    p = W.fc_mlqd(0.15, 0.05, 8, 2, 17, nu_lo=0.3, nu_hi=30.0)
+    p = W.fc_mlqd(h, 0.05, 8, 2, 17, nu_lo=0.3, nu_hi=30.0)
     kappa = OMAT.fc_opacity(p.nu, T)
     planck = W.group_planck(p.edges, T)
     args = list(_random_groups(nx, ny, 6.0, 6.0, 17, seed=41))
     args[6], args[7] = kappa, planck
     args[8] = 4 * math.pi * planck / W.C_LIGHT
-    _say("case loqd 40x40 G=17 Fleck-Cummings material")
+    _say(f"case loqd {nx}x{ny} G=17 Fleck-Cummings material ({OL.n_faces(nx, ny)} faces)")
     ref = OL.solve(*args)
     got, it, res = _gpu_solve(lc, *args)
     _say(f"  {it} iterations, residuals {np.max(res):.1e}")
